@@ -1,0 +1,199 @@
+/*
+ * Oracle for the interval search problem and for the Direct-search build.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * CPU reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product library never links or calls it, and it shares no code, header or
+ * constant with the product.
+ *
+ * Paper: F. Cannizzo, "A Fast and Vectorizable Alternative to Binary Search
+ * in O(1) with Wide Applicability to Arrays of Floating Point Numbers".
+ *
+ * Contents
+ *   oracle_search_*   the result itself (Sec. 2, Formal Problem Statement):
+ *                     i with X_i <= z < X_{i+1}, computed with the classic
+ *                     binary search (Sec. 3.1, algorithm "Classic"), extended
+ *                     to out-of-domain z by i = #{k : X_k <= z} - 1.
+ *   oracle_brute_*    the same count written as a linear scan (tiny N only).
+ *   oracle_compute_hr_*  the choice of H and R (Sec. 4.4.3, algorithm
+ *                     ComputeHR), in the subtraction form of eq. (function)
+ *                     and in the FMA form of Sec. 4.9.
+ *   oracle_init_k_*   the index table K (Sec. 4, eq. (indexdef), filled right
+ *                     to left as in algorithm InitK).
+ *   oracle_direct_*   the Direct search (Sec. 4.2, algorithm Direct) on the
+ *                     oracle's own tables; used only to pin the build.
+ *
+ * Floating point: IEEE round-to-nearest-even, no contraction (the build file
+ * passes -ffp-contract=off), denormals preserved, explicit fma() only in the
+ * FMA form.  Comparisons are made in the array's own precision.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* status codes (numerically equal to the product's, by the interface, not by
+ * shared code) */
+#define OR_OK 0
+#define OR_ERR_ARG 1
+#define OR_ERR_NOT_SORTED 2
+#define OR_ERR_NONFINITE 3
+#define OR_ERR_INFEASIBLE 4
+
+/* forms of the grid map f */
+#define OR_FORM_SUB 0 /* f(x) = floor(m(H * m(x - X_0)))        eq. (function) */
+#define OR_FORM_FMA 1 /* f(x) = floor(fma(H, x, -W)), W = m(H X_0)  Sec. 4.9   */
+
+/* starting point of the H search */
+#define OR_HSTART_PHI 0  /* H = phi(Hbar), as the text of Sec. 4.4.3 prints  */
+#define OR_HSTART_HBAR 1 /* H = Hbar (reproduces the statistics of Table 101) */
+
+/* Q = 31: grid indices and outputs are signed 32-bit integers. */
+#define OR_TWO_POW_Q 2147483648.0
+
+/*
+ * The whole oracle is written once per precision through this macro; T is the
+ * element type, S the symbol suffix, and FLOOR/FMA/NEXTUP the libm functions
+ * of that precision.
+ */
+#define DEFINE_ORACLE(T, S, FLOOR, FMA, NEXTUP)                                  \
+                                                                                 \
+  /* Sec. 3.1, algorithm Classic: low = 0, high = N, halve until high-low=1. */ \
+  static int64_t classic_##S(const T* X, int64_t N, T z) {                       \
+    /* outside [X_0, X_N): the count #{k : X_k <= z} - 1 directly */             \
+    if (!(z >= X[0])) return -1; /* also NaN: no X_k <= NaN */                   \
+    if (z >= X[N]) return N;                                                     \
+    int64_t low = 0, high = N;                                                   \
+    while (high - low > 1) {                                                     \
+      int64_t mid = (low + high) / 2;                                            \
+      if (z < X[mid])                                                            \
+        high = mid;                                                              \
+      else                                                                       \
+        low = mid;                                                               \
+    }                                                                            \
+    return low;                                                                  \
+  }                                                                              \
+                                                                                 \
+  void oracle_search_##S(const T* X, int64_t N, const T* z, int64_t M,           \
+                         int32_t* out, int nthreads) {                           \
+    if (nthreads < 1) nthreads = 1;                                              \
+    _Pragma("omp parallel for schedule(static) num_threads(nthreads)")           \
+    for (int64_t k = 0; k < M; ++k) out[k] = (int32_t)classic_##S(X, N, z[k]);  \
+  }                                                                              \
+                                                                                 \
+  /* i = #{k : X_k <= z} - 1, by a linear scan: the definition itself. */       \
+  void oracle_brute_##S(const T* X, int64_t N, const T* z, int64_t M,            \
+                        int32_t* out) {                                          \
+    for (int64_t k = 0; k < M; ++k) {                                            \
+      int64_t c = 0;                                                             \
+      for (int64_t i = 0; i <= N; ++i) c += (X[i] <= z[k]) ? 1 : 0;              \
+      out[k] = (int32_t)(c - 1);                                                 \
+    }                                                                            \
+  }                                                                              \
+                                                                                 \
+  /* the grid map f of eq. (function) or of Sec. 4.9, before the floor */       \
+  static T grid_value_##S(int form, T H, T W, T X0, T x) {                       \
+    if (form == OR_FORM_FMA) return FMA(H, x, -W);                               \
+    T d = x - X0;                                                                \
+    return H * d;                                                                \
+  }                                                                              \
+                                                                                 \
+  /* Sec. 4.4.3, algorithm ComputeHR, with the readings listed in the design  \
+   * notes: Q = 31, the overflow test is floor(m(H D_N)) >= 2^Q, the growth     \
+   * term P is never reset, and after the pass over i = 1..N the whole pass is   \
+   * repeated until it changes nothing (so every pair is verified under the     \
+   * final H). */                                                                \
+  int oracle_compute_hr_##S(const T* X, int64_t N, int form, int hstart,        \
+                            T* H_out, T* W_out, int64_t* R_out,                  \
+                            int64_t* jmin_out, int64_t* n_updates_out) {         \
+    if (N < 1 || X == 0) return OR_ERR_ARG;                                      \
+    for (int64_t i = 0; i <= N; ++i)                                             \
+      if (!isfinite(X[i])) return OR_ERR_NONFINITE;                              \
+    for (int64_t i = 0; i < N; ++i)                                              \
+      if (!(X[i] < X[i + 1])) return OR_ERR_NOT_SORTED;                          \
+    const T X0 = X[0];                                                           \
+    /* eq. (distinguishable-exact): D_i = m(X_i - X_0) strictly increasing */    \
+    T g = INFINITY;                                                              \
+    for (int64_t i = 0; i < N; ++i) {                                            \
+      T Di = X[i] - X0, Dn = X[i + 1] - X0;                                      \
+      if (!(Di < Dn)) return OR_ERR_INFEASIBLE;                                  \
+      T gap = Dn - Di; /* m(D_{i+1} - D_i) */                                    \
+      if (gap < g) g = gap;                                                      \
+    }                                                                            \
+    /* eq. (minhnumeric): Hbar = m(1 / min gap) */                               \
+    T one = 1;                                                                   \
+    T Hbar = one / g;                                                            \
+    if (isinf(Hbar)) return OR_ERR_INFEASIBLE;                                   \
+    T H = (hstart == OR_HSTART_HBAR) ? Hbar : NEXTUP(Hbar, (T)INFINITY);         \
+    T W = (form == OR_FORM_FMA) ? H * X0 : 0;                                    \
+    if (FLOOR(grid_value_##S(form, H, W, X0, X[N])) >= (T)OR_TWO_POW_Q)          \
+      return OR_ERR_INFEASIBLE;                                                  \
+    T P = NEXTUP(H, (T)INFINITY) - H;                                            \
+    int64_t n_updates = 0;                                                       \
+    for (;;) {                                                                   \
+      int changed = 0;                                                           \
+      for (int64_t i = 1; i <= N; ++i) {                                         \
+        /* eq. (cond2): floor(f(X_{i-1})) < floor(f(X_i)) must hold */           \
+        while (FLOOR(grid_value_##S(form, H, W, X0, X[i - 1])) ==                \
+               FLOOR(grid_value_##S(form, H, W, X0, X[i]))) {                    \
+          H = H + P;                                                             \
+          if (form == OR_FORM_FMA) W = H * X0;                                   \
+          if (FLOOR(grid_value_##S(form, H, W, X0, X[N])) >= (T)OR_TWO_POW_Q)    \
+            return OR_ERR_INFEASIBLE;                                            \
+          P = P + P;                                                             \
+          ++n_updates;                                                           \
+          changed = 1;                                                           \
+        }                                                                        \
+      }                                                                          \
+      if (!changed) break;                                                       \
+    }                                                                            \
+    *H_out = H;                                                                  \
+    *W_out = W;                                                                  \
+    *R_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[N]));              \
+    *jmin_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[0]));           \
+    *n_updates_out = n_updates;                                                  \
+    return OR_OK;                                                                \
+  }                                                                              \
+                                                                                 \
+  /* eq. (indexdef): K_j = i for f(X_{i-1}) < j <= f(X_i), K_{f(X_0)} = 0,     \
+   * filled from the right as algorithm InitK does.  K has R - jmin + 1         \
+   * entries; K[j - jmin] holds K_j. */                                          \
+  int oracle_init_k_##S(const T* X, int64_t N, int form, T H, T W, int64_t jmin, \
+                        int64_t R, int32_t* K) {                                 \
+    const T X0 = X[0];                                                           \
+    int64_t b = R;                                                               \
+    for (int64_t i = N; i >= 0 && b >= jmin; --i) {                              \
+      int64_t t = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[i]));          \
+      while (b > t) { /* cells strictly after f(X_i) and up to f(X_{i+1}) */     \
+        K[b - jmin] = (int32_t)(i + 1);                                          \
+        --b;                                                                     \
+      }                                                                          \
+      if (b != t) return OR_ERR_INFEASIBLE; /* f not strictly increasing */      \
+      K[b - jmin] = (int32_t)i;                                                  \
+      --b;                                                                       \
+    }                                                                            \
+    return (b == jmin - 1) ? OR_OK : OR_ERR_INFEASIBLE;                          \
+  }                                                                              \
+                                                                                 \
+  /* Sec. 4.2, algorithm Direct: j = f(z), t = K_j, i = t - [z < X_t], with j  \
+   * clamped to [jmin, R] in the floating-point domain first (fmax(NaN, a) = a  \
+   * sends NaN to jmin), which leaves in-domain queries untouched and gives -1  \
+   * below X_0 and N at or above X_N. */                                         \
+  void oracle_direct_##S(const T* X, int64_t N, const int32_t* K, int form,     \
+                         T H, T W, int64_t jmin, int64_t R, const T* z,          \
+                         int64_t M, int32_t* out) {                              \
+    (void)N;                                                                     \
+    for (int64_t k = 0; k < M; ++k) {                                            \
+      T v = grid_value_##S(form, H, W, X[0], z[k]);                              \
+      if (!(v >= (T)jmin)) v = (T)jmin;                                          \
+      if (v > (T)R) v = (T)R;                                                    \
+      int64_t j = (int64_t)FLOOR(v);                                             \
+      int64_t t = K[j - jmin];                                                   \
+      /* [z >= X_t] is false for NaN, so NaN gives t - 1 = -1 */              \
+      out[k] = (int32_t)(t - 1 + (z[k] >= X[t] ? 1 : 0));                        \
+    }                                                                            \
+  }
+
+DEFINE_ORACLE(float, f32, floorf, fmaf, nextafterf)
+DEFINE_ORACLE(double, f64, floor, fma, nextafter)
