@@ -1,0 +1,212 @@
+"""Throughput benchmark of the Direct search on one MI355X.
+
+Workload: the N sweep in single and double precision (N in {16, 256, 4096,
+65536, 2^20, 2^21}; X built from cumulative U(0.5, 1.5) gaps scaled to [0, 1];
+M = 2^26 uniform queries per (N, dtype)).  One timed step searches every
+(N, dtype) case once with the Direct method (subtraction form), inputs already
+resident in HBM; the tables are built before timing, as the paper's harness
+sets each algorithm up before its clock starts (Sec. 6.1, algorithm TestHarness).
+
+Prints one JSON line: Gqueries/s over the step, the HBM-roofline fraction of
+the dominant search kernel (timed with HIP events on the launch stream), the
+CPU oracle timed on a bounded sample, and per-case figures for Direct,
+Direct-FMA and the branch-free binary search.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--cpu-sample", type=int, default=1 << 22, help="queries per case for the CPU oracle")
+    p.add_argument("--no-extras", action="store_true", help="skip the per-method comparison runs")
+    p.add_argument("--sizes", type=str, default="", help="comma-separated subset of N (testing)")
+    p.add_argument("--m", type=int, default=0, help="queries per case (default 2^26)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1 "
+                                   "(the queries shard with no exchange, see DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_1506_08620_amd as ds
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    M = args.m or W.SWEEP_M
+    sizes = [int(s) for s in args.sizes.split(",")] if args.sizes else list(W.SWEEP_N)
+    cases = []
+    for dt in (np.float32, np.float64):
+        for n in sizes:
+            X = W.sweep_array(n, dt)
+            x_d = torch.from_numpy(X).to(dev)
+            z_d = W.sweep_queries_torch(M, dt, dev)
+            out = torch.empty(M, dtype=torch.int32, device=dev)
+            t0 = time.perf_counter()
+            idx = ds.build(x_d)
+            torch.cuda.synchronize()
+            build_s = time.perf_counter() - t0
+            cases.append(dict(n=n, dt=dt, X=X, x=x_d, z=z_d, out=out, idx=idx, build_s=build_s))
+
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        for k, c in enumerate(cases):
+            if ev is not None:
+                ev[k][0].record(stream)
+            ds.search(c["idx"], c["z"], out=c["out"], stream=stream)
+            if ev is not None:
+                ev[k][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps between synchronisations
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # per-launch kernel times with HIP events on the launch stream (separate pass)
+    per = [[0.0, 0] for _ in cases]
+    for _ in range(args.steps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+        step(ev)
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(ev):
+            per[k][0] += a.elapsed_time(b)
+            per[k][1] += 1
+
+    total_q = M * len(cases) * args.steps
+    value = total_q / wall / 1e9
+    case_rows = []
+    groups = {}
+    for k, c in enumerate(cases):
+        ms = per[k][0] / per[k][1]
+        S = np.dtype(c["dt"]).itemsize
+        bytes_per_launch = M * (S + 4)
+        inf = c["idx"].info()
+        row = dict(N=c["n"], dtype="f32" if S == 4 else "f64", gq_s=round(M / ms / 1e6, 2),
+                   gbs=round(bytes_per_launch / ms / 1e6, 1), hbm_frac=round(bytes_per_launch / ms / 1e6 / HBM_PEAK_GBS, 4),
+                   kernel_ms=round(ms, 5), staged=bool(inf["staged"]), R=inf["R"],
+                   table_bytes=inf["table_bytes"], build_ns_per_elem=round(c["build_s"] * 1e9 / (c["n"] + 1), 2))
+        case_rows.append(row)
+        key = (row["dtype"], row["staged"])
+        g = groups.setdefault(key, [0.0, 0, 0])
+        g[0] += ms
+        g[1] += 1
+        g[2] += bytes_per_launch
+    dom_key = max(groups, key=lambda k: groups[k][0])
+    g = groups[dom_key]
+    avg_ms = g[0] / g[1]
+    avg_bytes = g[2] / g[1]
+    achieved = avg_bytes / avg_ms / 1e6
+    kernel_name = "direct_search_kernel<{},SUB,{}>".format("float" if dom_key[0] == "f32" else "double",
+                                                          "LDS" if dom_key[1] else "L2")
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel_name,
+                    launches_per_step=g[1], bytes_per_launch=int(avg_bytes), avg_launch_ms=round(avg_ms, 5))
+
+    # CPU oracle on a bounded sample of the same workload
+    cpu = None
+    parity = True
+    try:
+        import oracle
+
+        threads = len(os.sched_getaffinity(0))
+        sample = min(args.cpu_sample, M)
+        cpu_t = 0.0
+        for c in cases:
+            zs = c["z"][:sample].cpu().numpy()
+            t1 = time.perf_counter()
+            ref = oracle.search(c["X"], zs, nthreads=threads)
+            cpu_t += time.perf_counter() - t1
+            got = c["out"][:sample].cpu().numpy()
+            parity = parity and bool(np.array_equal(got, ref))
+        cpu = dict(value=round(sample * len(cases) / cpu_t / 1e9, 4), unit="Gqueries/s", cores=threads,
+                   kind="oracle", sample=f"first {sample} queries of each of the {len(cases)} (N, dtype) cases, "
+                                          f"classic binary search, {threads} OpenMP threads")
+    except Exception as e:  # the CPU leg must not hide the GPU figure
+        cpu = dict(value=None, unit="Gqueries/s", cores=0, kind="oracle", sample=f"failed: {e}")
+
+    extras = {}
+    if not args.no_extras:
+        extras = compare_methods(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
+
+    line = {
+        "metric": "Gqueries/s and %HBM peak: Direct vs learned vs binary search, FP32/FP64",
+        "value": round(value, 2),
+        "unit": "Gqueries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"direct-sweep: N in {sizes} x {{f32, f64}}, gaps U(0.5,1.5) scaled to [0,1], "
+                               f"M={M} uniform queries per case, subtraction form",
+                   "queries_per_step": M * len(cases)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sample_bit_exact": parity,
+        "cases": case_rows,
+        **extras,
+    }
+    print(json.dumps(line))
+
+
+def compare_methods(ds, cases, M, stream, reps):
+    """Direct-FMA and the branch-free binary search on the same inputs (not in the timed step)."""
+    import torch
+
+    res = {"direct_fma": [], "bsearch_leadbit": []}
+    for c in cases:
+        for key, kw in (("direct_fma", dict(form="fma")), ("bsearch_leadbit", dict(method="leadbit"))):
+            idx = ds.build(c["x"], **kw)
+            out = torch.empty_like(c["out"])
+            ds.search(idx, c["z"], out=out, stream=stream)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                ds.search(idx, c["z"], out=out, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            same = bool(torch.equal(out, c["out"]))
+            S = np.dtype(c["dt"]).itemsize
+            res[key].append(dict(N=c["n"], dtype="f32" if S == 4 else "f64", gq_s=round(M / ms / 1e6, 2),
+                                 hbm_frac=round(M * (S + 4) / ms / 1e6 / HBM_PEAK_GBS, 4), same_as_direct=same))
+            idx.destroy()
+            del out
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * ds.h -- C interface of the MI355X (gfx950) interval-search library.
+ *
+ * Problem (paper Sec. 2, Formal Problem Statement): given N+1 strictly
+ * increasing floating-point values X_0 < X_1 < ... < X_N and queries z, find
+ * for every z the index i in [0, N-1] with X_i <= z < X_{i+1}.
+ *
+ * Out-of-domain queries (the paper assumes z in [X_0, X_N) and is silent about
+ * the rest) return i = #{k : X_k <= z} - 1, that is -1 below X_0 and for NaN,
+ * and N at or above X_N.  Every method below returns exactly these values.
+ *
+ * Methods
+ *   Direct        (Sec. 4, algorithm Direct): a one-time build chooses a grid
+ *                 scale H (Sec. 4.4.3, algorithm ComputeHR) and an index table
+ *                 K of R+1 entries (Sec. 4, eq. (indexdef), algorithm InitK);
+ *                 a query costs j = floor(H (z - X_0)) (or the FMA form of
+ *                 Sec. 4.9, j = floor(fma(H, z, -W)) with W = H X_0), one
+ *                 gather t = K_j and one compare-and-fix against X_t.
+ *   Binary search (Sec. 3.2.1 padded leading-bit search, Sec. 3.3 offset
+ *                 search): branch-free O(log N) baselines.
+ *   Learned       a monotone CDF model (a small FP32 network routing to
+ *                 per-segment linear fits) whose recorded error bounds drive
+ *                 an exact bounded search; used where the Direct table would
+ *                 be too large.  Not from the paper.
+ *
+ * Conventions
+ *   - Every pointer named *_dev is a device pointer (hipMalloc'd memory or any
+ *     device-accessible allocation) on the current HIP device.
+ *   - Calls that take a hipStream_t enqueue their work on that stream; 0 is
+ *     the legacy default stream.
+ *   - All status codes are returned synchronously.  Nothing can fail on the
+ *     device after a call has returned DS_OK.
+ *   - Handles are immutable after ds_build: concurrent ds_search calls on one
+ *     handle from several streams are safe.
+ */
+#ifndef DS_H_
+#define DS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { DS_F32 = 0, DS_F64 = 1 } ds_dtype;
+
+typedef enum {
+  DS_OK = 0,
+  DS_ERR_ARG = 1,          /* bad argument: null pointer, N < 1, N too large, bad enum */
+  DS_ERR_NOT_SORTED = 2,   /* X not strictly increasing */
+  DS_ERR_NONFINITE = 3,    /* X holds NaN or +-inf */
+  DS_ERR_INFEASIBLE = 4,   /* no H exists (Sec. 4.4.2): the rounded offsets
+                              m(X_i - X_0) are not strictly increasing, 1/min gap
+                              overflows, or floor(m(H D_N)) >= 2^31 */
+  DS_ERR_TABLE_CAP = 5,    /* the Direct table would exceed the byte cap */
+  DS_ERR_OOM = 6,          /* device allocation failed */
+  DS_ERR_HIP = 7,          /* a HIP runtime call failed */
+  DS_ERR_UNSUPPORTED = 8   /* option combination not supported */
+} ds_status;
+
+typedef enum { DS_FORM_SUB = 0, DS_FORM_FMA = 1 } ds_form;
+
+/* starting value of H in ComputeHR: phi(Hbar), the next float above Hbar, as
+ * the text of Sec. 4.4.3 prints; or Hbar itself, the start under which the
+ * paper's table of H-update counts is reproduced. */
+typedef enum { DS_HSTART_PHI = 0, DS_HSTART_HBAR = 1 } ds_hstart;
+
+typedef enum {
+  DS_METHOD_DIRECT = 0,         /* Sec. 4.2, algorithm Direct */
+  DS_METHOD_BSEARCH_LEADBIT = 1,/* Sec. 3.2.1, padded leading-bit search */
+  DS_METHOD_BSEARCH_OFFSET = 2, /* Sec. 3.3, offset-based search */
+  DS_METHOD_LEARNED = 3,        /* learned monotone CDF + bounded search */
+  DS_METHOD_AUTO = 4            /* Direct when feasible and under the cap, else learned */
+} ds_method;
+
+typedef enum {
+  DS_FALLBACK_NONE = 0,    /* an infeasible Direct build returns its error */
+  DS_FALLBACK_BSEARCH = 1, /* ... is replaced by the leading-bit binary search */
+  DS_FALLBACK_LEARNED = 2  /* ... is replaced by the learned method */
+} ds_fallback;
+
+/* Build options.  Zero-initialise and set what you need; ds_build(NULL opts)
+ * uses: Direct, subtraction form, H starting at phi(Hbar), no fallback, table
+ * cap 4 GiB. */
+typedef struct ds_build_opts {
+  int32_t method;           /* ds_method */
+  int32_t form;             /* ds_form (Direct only) */
+  int32_t hstart;           /* ds_hstart (Direct only) */
+  int32_t fallback;         /* ds_fallback */
+  int64_t table_cap_bytes;  /* 0 = 4 GiB; the Direct table may not exceed it */
+  /* learned method; 0 = default */
+  int32_t learn_epochs;     /* passes over the (X_i, i) pairs (default 60) */
+  int32_t learn_segments;   /* number of linear segments (default 4096) */
+  float learn_rate;         /* Adam step size (default 2e-3) */
+  int32_t learn_batch;      /* training pairs per step (default 8192) */
+  uint64_t seed;            /* initialisation / sampling seed */
+} ds_build_opts;
+
+typedef struct ds_info_t {
+  int32_t method;           /* method actually used (ds_method) */
+  int32_t dtype;            /* ds_dtype */
+  int32_t form;             /* ds_form */
+  int32_t staged;           /* 1 when the search kernels keep the tables in LDS */
+  int64_t N;                /* number of intervals; X has N+1 values */
+  double H;                 /* grid scale (exactly the dtype value) */
+  double W;                 /* H X_0 rounded (FMA form), else 0 */
+  double X0;                /* X_0 */
+  int64_t R;                /* last grid index f(X_N) */
+  int64_t jmin;             /* first grid index f(X_0): 0, or -1 in the FMA form */
+  int64_t n_h_updates;      /* H increases made by ComputeHR */
+  int64_t table_bytes;      /* bytes of the Direct table (0 for other methods) */
+  int64_t model_bytes;      /* bytes of the learned model (0 for other methods) */
+  int64_t max_err;          /* learned: max position error over the keys */
+  double mean_log2_window;  /* learned: mean log2 of the bounded-search window */
+  int64_t x_bytes;          /* bytes of the device copy of X (with padding) */
+  double build_ms;          /* wall time of ds_build */
+} ds_info_t;
+
+typedef struct ds_index* ds_handle;
+
+/* Launch shape of the search kernels; ds_search picks one when none is set.
+ * Any setting gives identical results. */
+typedef struct ds_tune {
+  int32_t block;            /* threads per workgroup: 64..1024, multiple of 64; 0 = auto */
+  int32_t unroll;           /* 16-byte query vectors per thread per iteration: 1, 2 or 4; 0 = auto */
+  int32_t stage;            /* 0 = auto, 1 = tables in LDS, 2 = tables read through L2 */
+  int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */
+} ds_tune;
+
+/*
+ * ds_build: build a search index over X.
+ *   X_dev  device pointer to N+1 strictly increasing values of type dt.  The
+ *          values are copied into the handle; the caller may free X_dev once
+ *          ds_build returns.
+ *   N      number of intervals, 1 <= N <= 2^31 - 2.
+ *   opts   NULL for defaults.
+ *   s      stream for the build's kernels and copies.  ds_build synchronises
+ *          s before returning (ComputeHR needs a few device-to-host reads).
+ *   out    receives the handle on DS_OK; untouched otherwise.
+ * Errors: DS_ERR_ARG, DS_ERR_NOT_SORTED, DS_ERR_NONFINITE, DS_ERR_INFEASIBLE,
+ *   DS_ERR_TABLE_CAP (when fallback is NONE), DS_ERR_OOM, DS_ERR_HIP.
+ * Build steps: validation and minimum rounded gap (Sec. 4.4.2, eq.
+ *   (distinguishable-exact), eq. (minhnumeric)); H growth (Sec. 4.4.3,
+ *   algorithm ComputeHR) with every pair re-verified under the final H; R;
+ *   the table K (Sec. 4, eq. (indexdef)).
+ */
+ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opts* opts, hipStream_t s,
+                   ds_handle* out);
+
+/*
+ * ds_search: out_dev[k] = i for every query z_dev[k], k < M (the vectorial
+ * problem of Sec. 2).
+ *   z_dev    M values of the handle's dtype (device).
+ *   out_dev  M int32 (device); may not overlap z_dev.
+ *   M        >= 0; M = 0 is a no-op.
+ * Asynchronous on s, allocates nothing, may be captured in a HIP graph.
+ * Errors (synchronous): DS_ERR_ARG for a null handle/pointer with M > 0 or
+ *   M < 0; DS_ERR_HIP if the launch fails.
+ */
+ds_status ds_search(ds_handle h, const void* z_dev, int64_t M, int32_t* out_dev, hipStream_t s);
+
+/* ds_set_tune: fix the launch shape of later ds_search calls on h (NULL
+ * restores automatic choice).  Not thread-safe against concurrent searches on
+ * the same handle.  DS_ERR_ARG for values outside the ranges above, or stage=1
+ * when the tables do not fit in LDS. */
+ds_status ds_set_tune(ds_handle h, const ds_tune* t);
+
+/* ds_info: fills *info (host memory). */
+ds_status ds_info(ds_handle h, ds_info_t* info);
+
+/* ds_copy_table: copies the Direct table K (R - jmin + 1 int32 entries,
+ * entry e holds K_{jmin+e}) into dst_dev (device), synchronously on s.
+ * DS_ERR_ARG if capacity_entries is too small or the handle has no table. */
+ds_status ds_copy_table(ds_handle h, int32_t* dst_dev, int64_t capacity_entries, hipStream_t s);
+
+/* ds_destroy: frees every device allocation of h; h is invalid afterwards.
+ * The caller must make sure no search on h is still running. */
+ds_status ds_destroy(ds_handle h);
+
+/* ds_status_str: static English text for a status code. */
+const char* ds_status_str(ds_status st);
+
+/* ------------------------------------------------------------------------
+ * Batched ragged search: K independent arrays, each with its own queries,
+ * built and searched by a fixed sequence of kernels with no host
+ * synchronisation (capturable in a HIP graph).  Array k is
+ * X_packed[x_off[k] .. x_off[k+1]) (N_k = x_off[k+1] - x_off[k] - 1 intervals,
+ * N_k = -1 means an empty array) and its queries are
+ * z_packed[q_off[k] .. q_off[k+1]); out_packed[q] receives the index local to
+ * the query's array.  The Direct method is used per array whenever it is
+ * feasible and its table fits the workspace; every other array is searched by
+ * the leading-bit binary search.  Results are identical either way.
+ */
+typedef struct ds_batch_desc {
+  int32_t dtype;              /* ds_dtype */
+  int32_t num_arrays;         /* K >= 0 */
+  const int64_t* x_off_dev;   /* K+1 non-decreasing offsets, x_off[0] = 0 */
+  const void* X_dev;          /* packed arrays */
+  const int64_t* q_off_dev;   /* K+1 non-decreasing offsets, q_off[0] = 0 */
+  const void* z_dev;          /* packed queries */
+  int32_t* out_dev;           /* one int32 per query */
+  void* workspace_dev;        /* device scratch of workspace_bytes */
+  size_t workspace_bytes;     /* from ds_batch_workspace_bytes */
+  int64_t total_x;            /* x_off[K] (host copy of the last offset) */
+  int64_t total_q;            /* q_off[K] */
+  int32_t form;               /* ds_form */
+  int32_t tile;               /* queries per work item; 0 = auto */
+  int32_t block;              /* threads per workgroup; 0 = auto */
+  int32_t lds_bytes;          /* LDS staging budget per workgroup; 0 = auto, -1 = never stage */
+} ds_batch_desc;
+
+/* Bytes of workspace ds_search_batched needs for K arrays holding total_x
+ * values in all, with at most table_budget_entries Direct-table entries in all
+ * (arrays whose table does not fit the remaining budget use binary search). */
+size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries);
+
+/* Enqueue the batched build + search on s.  No host synchronisation, no
+ * allocation.  DS_ERR_ARG for inconsistent sizes or a workspace smaller than
+ * ds_batch_workspace_bytes(num_arrays, total_x, 0). */
+ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s);
+
+/* Per-array outcome of the last ds_search_batched on this workspace (device
+ * to host copy, synchronous on s): method_host[k] = ds_method used for array
+ * k (DS_METHOD_DIRECT or DS_METHOD_BSEARCH_LEADBIT), R_host[k] = its R (or -1). */
+ds_status ds_batch_report(const ds_batch_desc* d, int32_t* method_host, int64_t* R_host, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DS_H_ */

@@ -1,0 +1,483 @@
+// Build of the Direct-search index on the GPU, and the C entry points that
+// create, describe and destroy handles.
+//
+//   a) validation + minimum rounded gap  (Sec. 4.4.2, eq. (distinguishable-exact)
+//      and eq. (minhnumeric)): one pass over X, a block-min reduction and flag OR.
+//   b) H growth (Sec. 4.4.3, algorithm ComputeHR): the host owns the scalar
+//      recurrence; a parallel kernel finds the first pair i >= i_start whose
+//      grid cells coincide under the current H, so the host applies the growth
+//      steps in exactly the order of the sequential algorithm.  Passes repeat
+//      until one changes nothing, so every pair holds under the final H.
+//   c) the table K (Sec. 4, eq. (indexdef)): one workgroup per 256 consecutive
+//      X_i computes their cells, then fills the contiguous run of K entries
+//      that falls between its first and last cell, each entry found by a
+//      binary search over the workgroup's cells in LDS.
+#include <algorithm>
+#include <chrono>
+#include <limits>
+#include <new>
+
+#include "ds_internal.h"
+
+namespace ds {
+
+namespace {
+
+constexpr uint32_t kFlagNonFinite = 1u;
+constexpr uint32_t kFlagNotSorted = 2u;
+constexpr uint32_t kFlagOffsetsNotIncreasing = 4u;
+
+struct BuildScratch {
+  unsigned long long min_gap_bits;  // bits of the smallest m(D_{i+1} - D_i) (positive floats order as integers)
+  unsigned long long first_bad;     // smallest failing pair index of a verify pass
+  uint32_t flags;
+  uint32_t pad[3];
+};
+
+template <typename T>
+struct Bits;
+template <>
+struct Bits<float> {
+  using U = uint32_t;
+};
+template <>
+struct Bits<double> {
+  using U = uint64_t;
+};
+
+template <typename T>
+__device__ __forceinline__ unsigned long long to_bits(T v) {
+  typename Bits<T>::U u;
+  __builtin_memcpy(&u, &v, sizeof(T));
+  return static_cast<unsigned long long>(u);
+}
+
+template <typename T>
+T from_bits(unsigned long long b) {
+  typename Bits<T>::U u = static_cast<typename Bits<T>::U>(b);
+  T v;
+  std::memcpy(&v, &u, sizeof(T));
+  return v;
+}
+
+constexpr int kScanBlock = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(kScanBlock) mingap_kernel(const T* __restrict__ X, int64_t N,
+                                                            BuildScratch* __restrict__ scr) {
+  const T X0 = X[0];
+  T gmin = std::numeric_limits<T>::infinity();
+  uint32_t fl = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const T a = X[i], b = X[i + 1];
+    if (!std::isfinite(a) || !std::isfinite(b)) fl |= kFlagNonFinite;
+    if (!(a < b)) fl |= kFlagNotSorted;
+    const T da = a - X0, db = b - X0;  // D_i = m(X_i - X_0)
+    if (!(da < db)) fl |= kFlagOffsetsNotIncreasing;
+    const T g = db - da;               // m(D_{i+1} - D_i)
+    gmin = std::fmin(gmin, g);
+  }
+  __shared__ T smin[kScanBlock];
+  __shared__ uint32_t sfl[kScanBlock];
+  smin[threadIdx.x] = gmin;
+  sfl[threadIdx.x] = fl;
+  __syncthreads();
+  for (int w = kScanBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smin[threadIdx.x] = std::fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+      sfl[threadIdx.x] |= sfl[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (sfl[0]) atomicOr(&scr->flags, sfl[0]);
+    const T m = smin[0];
+    // only positive gaps matter; a non-positive one is reported through the flags
+    if (m > T(0)) atomicMin(&scr->min_gap_bits, to_bits<T>(m));
+  }
+}
+
+// smallest i in [i_start, N] with floor(f(X_{i-1})) == floor(f(X_i)), eq. (cond2)
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kScanBlock) verify_kernel(const T* __restrict__ X, int64_t N, int64_t i_start,
+                                                            T H, T W, T X0, BuildScratch* __restrict__ scr) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long first = ~0ull;
+  for (int64_t i = i_start + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= N; i += stride) {
+    const T a = grid_floor<T, FORM>(X[i - 1], H, W, X0);
+    const T b = grid_floor<T, FORM>(X[i], H, W, X0);
+    if (a == b) {
+      first = static_cast<unsigned long long>(i);
+      break;  // later i of this thread are larger
+    }
+  }
+  if (first != ~0ull) atomicMin(&scr->first_bad, first);
+}
+
+constexpr int kFillBlock = 256;
+
+// K_j = min{ i : f(X_i) >= j } for j in [jmin, R]; K[e] holds K_{jmin+e}.
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kFillBlock) fill_kernel(const T* __restrict__ X, int64_t N, T H, T W, T X0,
+                                                          int32_t jmin, int64_t nK, int32_t* __restrict__ K) {
+  __shared__ int32_t c[kFillBlock + 1];  // c[0] = f(X_{i0-1}) (jmin-1 for i0 = 0), c[1+t] = f(X_{i0+t})
+  const int64_t i0 = (int64_t)blockIdx.x * kFillBlock;
+  const int64_t i = i0 + threadIdx.x;
+  if (i <= N) c[1 + threadIdx.x] = static_cast<int32_t>(grid_floor<T, FORM>(X[i], H, W, X0));
+  if (threadIdx.x == 0)
+    c[0] = (i0 == 0) ? jmin - 1 : static_cast<int32_t>(grid_floor<T, FORM>(X[i0 - 1], H, W, X0));
+  __syncthreads();
+  const int nb = static_cast<int>(std::min<int64_t>(kFillBlock, N + 1 - i0));
+  const int64_t jlo = (int64_t)c[0] + 1, jhi = c[nb];
+  for (int64_t j = jlo + threadIdx.x; j <= jhi; j += kFillBlock) {
+    int lo = 1, hi = nb;  // smallest t in [1, nb] with c[t] >= j
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int64_t)c[mid] >= j)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const int64_t e = j - jmin;
+    if (e >= 0 && e < nK) K[e] = static_cast<int32_t>(i0 + lo - 1);  // always true when f is monotone
+  }
+}
+
+// leading-bit padding (Sec. 3.2.1): X_N repeated up to 2^p entries
+template <typename T>
+__global__ void pad_kernel(T* __restrict__ Xp, int64_t from, int64_t to, T value) {
+  const int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < to) Xp[i] = value;
+}
+
+int64_t grid_for(int64_t n, int block, int64_t cap) {
+  int64_t g = (n + block - 1) / block;
+  return std::max<int64_t>(1, std::min(g, cap));
+}
+
+template <typename T>
+T next_up(T x) {
+  return std::nextafter(x, std::numeric_limits<T>::infinity());
+}
+
+// The host half of ComputeHR for one form; see the file comment.
+template <typename T, int FORM>
+ds_status compute_hr(ds_index* h, const T* X, BuildScratch* scr, hipStream_t s, T X0, T XN, T g) {
+  const int64_t N = h->N;
+  const T one = T(1);
+  const T Hbar = one / g;  // eq. (minhnumeric), correctly rounded
+  if (std::isinf(Hbar)) return DS_ERR_INFEASIBLE;
+  T H = (h->hstart == DS_HSTART_HBAR) ? Hbar : next_up(Hbar);
+  T W = (FORM == DS_FORM_FMA) ? T(H * X0) : T(0);
+  auto overflow = [&](T Hc, T Wc) { return grid_floor<T, FORM>(XN, Hc, Wc, X0) >= T(kTwoPowQ); };
+  if (overflow(H, W)) return DS_ERR_INFEASIBLE;  // eq. (overflowexact)
+  T P = next_up(H) - H;
+  int64_t n_updates = 0;
+  const int64_t vgrid = std::min<int64_t>(grid_for(N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
+  for (;;) {
+    bool changed = false;
+    int64_t i_start = 1;
+    while (i_start <= N) {
+      const unsigned long long none = ~0ull;
+      DS_HIP_CHECK(hipMemcpyAsync(&scr->first_bad, &none, sizeof(none), hipMemcpyHostToDevice, s));
+      verify_kernel<T, FORM><<<dim3((unsigned)vgrid), dim3(kScanBlock), 0, s>>>(X, N, i_start, H, W, X0, scr);
+      DS_HIP_CHECK(hipGetLastError());
+      unsigned long long first = 0;
+      DS_HIP_CHECK(hipMemcpyAsync(&first, &scr->first_bad, sizeof(first), hipMemcpyDeviceToHost, s));
+      DS_HIP_CHECK(hipStreamSynchronize(s));
+      if (first == ~0ull) break;
+      const int64_t i = static_cast<int64_t>(first);
+      T pair[2];
+      DS_HIP_CHECK(hipMemcpyAsync(pair, X + (i - 1), 2 * sizeof(T), hipMemcpyDeviceToHost, s));
+      DS_HIP_CHECK(hipStreamSynchronize(s));
+      while (grid_floor<T, FORM>(pair[0], H, W, X0) == grid_floor<T, FORM>(pair[1], H, W, X0)) {
+        H = H + P;
+        if (FORM == DS_FORM_FMA) W = H * X0;
+        if (overflow(H, W)) return DS_ERR_INFEASIBLE;
+        P = P + P;
+        ++n_updates;
+        changed = true;
+      }
+      i_start = i + 1;
+    }
+    if (!changed) break;
+  }
+  h->H = H;
+  h->W = W;
+  h->X0 = X0;
+  h->R = static_cast<int64_t>(grid_floor<T, FORM>(XN, H, W, X0));
+  h->jmin = static_cast<int64_t>(grid_floor<T, FORM>(X0, H, W, X0));
+  h->n_updates = n_updates;
+  return DS_OK;
+}
+
+template <typename T, int FORM>
+ds_status fill_table(ds_index* h, hipStream_t s) {
+  const int64_t blocks = (h->N + 1 + kFillBlock - 1) / kFillBlock;
+  fill_kernel<T, FORM><<<dim3((unsigned)blocks), dim3(kFillBlock), 0, s>>>(
+      static_cast<const T*>(h->X), h->N, T(h->H), T(h->W), T(h->X0), static_cast<int32_t>(h->jmin), h->nK, h->K);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+template <typename T>
+ds_status build_direct(ds_index* h, const ds_build_opts& o, hipStream_t s) {
+  const T* X = static_cast<const T*>(h->X);
+  const int64_t N = h->N;
+  BuildScratch* scr = nullptr;
+  if (hipMalloc(&scr, sizeof(BuildScratch)) != hipSuccess) return DS_ERR_OOM;
+  struct Free {
+    BuildScratch* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{scr};
+  BuildScratch init{};
+  init.min_gap_bits = ~0ull;
+  init.first_bad = ~0ull;
+  DS_HIP_CHECK(hipMemcpyAsync(scr, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  const int64_t grid = std::min<int64_t>(grid_for(N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
+  mingap_kernel<T><<<dim3((unsigned)grid), dim3(kScanBlock), 0, s>>>(X, N, scr);
+  DS_HIP_CHECK(hipGetLastError());
+  BuildScratch got{};
+  T ends[2];
+  DS_HIP_CHECK(hipMemcpyAsync(&got, scr, sizeof(got), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipMemcpyAsync(&ends[0], X, sizeof(T), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipMemcpyAsync(&ends[1], X + N, sizeof(T), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  if (got.flags & kFlagNonFinite) return DS_ERR_NONFINITE;
+  if (got.flags & kFlagNotSorted) return DS_ERR_NOT_SORTED;
+  if (got.flags & kFlagOffsetsNotIncreasing) return DS_ERR_INFEASIBLE;
+  const T g = from_bits<T>(got.min_gap_bits);
+  ds_status st = (h->form == DS_FORM_FMA) ? compute_hr<T, DS_FORM_FMA>(h, X, scr, s, ends[0], ends[1], g)
+                                          : compute_hr<T, DS_FORM_SUB>(h, X, scr, s, ends[0], ends[1], g);
+  if (st != DS_OK) return st;
+  h->nK = h->R - h->jmin + 1;
+  const int64_t cap = o.table_cap_bytes > 0 ? o.table_cap_bytes : kDefaultTableCap;
+  if (h->nK * int64_t(sizeof(int32_t)) > cap) return DS_ERR_TABLE_CAP;
+  if (hipMalloc(&h->K, size_t(h->nK) * sizeof(int32_t)) != hipSuccess) {
+    h->K = nullptr;
+    return DS_ERR_OOM;
+  }
+  st = (h->form == DS_FORM_FMA) ? fill_table<T, DS_FORM_FMA>(h, s) : fill_table<T, DS_FORM_SUB>(h, s);
+  if (st != DS_OK) return st;
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  return DS_OK;
+}
+
+// Binary-search baselines keep X (offset search) or X padded with X_N up to
+// 2^p entries, p = 1 + floor(log2 N) (leading-bit search, Sec. 3.2.1).
+template <typename T>
+ds_status build_bsearch(ds_index* h, const void* X_dev, hipStream_t s) {
+  const int64_t N = h->N;
+  int p = 0;
+  while ((int64_t(1) << (p + 1)) <= N) ++p;  // p = floor(log2 N)
+  h->P = static_cast<int32_t>(int64_t(1) << p);
+  // offset search constants (Sec. 3.3): F = floor((N+1)/2), S = N+1-F, J = floor(log2(N+1))
+  h->F = static_cast<int32_t>((N + 1) / 2);
+  h->S = static_cast<int32_t>(N + 1 - h->F);
+  int j = 0;
+  while ((int64_t(1) << (j + 1)) <= N + 1) ++j;
+  h->J = j;
+  const int64_t n_store = (h->method == DS_METHOD_BSEARCH_LEADBIT) ? (int64_t(2) * h->P) : (N + 1);
+  if (hipMalloc(&h->X, size_t(n_store) * sizeof(T)) != hipSuccess) {
+    h->X = nullptr;
+    return DS_ERR_OOM;
+  }
+  h->nX = n_store;
+  DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if (n_store > N + 1) {
+    T xn;
+    DS_HIP_CHECK(hipMemcpyAsync(&xn, static_cast<const T*>(X_dev) + N, sizeof(T), hipMemcpyDeviceToHost, s));
+    DS_HIP_CHECK(hipStreamSynchronize(s));
+    const int64_t cnt = n_store - (N + 1);
+    pad_kernel<T><<<dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s>>>(static_cast<T*>(h->X), N + 1, n_store, xn);
+    DS_HIP_CHECK(hipGetLastError());
+  }
+  return DS_OK;
+}
+
+// the validation pass alone, for the binary-search methods
+template <typename T>
+ds_status validate_only(ds_index* h, const void* X_dev, hipStream_t s) {
+  BuildScratch* scr = nullptr;
+  if (hipMalloc(&scr, sizeof(BuildScratch)) != hipSuccess) return DS_ERR_OOM;
+  struct Free {
+    BuildScratch* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{scr};
+  BuildScratch init{};
+  init.min_gap_bits = ~0ull;
+  DS_HIP_CHECK(hipMemcpyAsync(scr, &init, sizeof(init), hipMemcpyHostToDevice, s));
+  const int64_t grid = std::min<int64_t>(grid_for(h->N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
+  mingap_kernel<T><<<dim3((unsigned)grid), dim3(kScanBlock), 0, s>>>(static_cast<const T*>(X_dev), h->N, scr);
+  DS_HIP_CHECK(hipGetLastError());
+  BuildScratch got{};
+  DS_HIP_CHECK(hipMemcpyAsync(&got, scr, sizeof(got), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  if (got.flags & kFlagNonFinite) return DS_ERR_NONFINITE;
+  if (got.flags & kFlagNotSorted) return DS_ERR_NOT_SORTED;
+  T x0;
+  DS_HIP_CHECK(hipMemcpy(&x0, X_dev, sizeof(T), hipMemcpyDeviceToHost));
+  h->X0 = x0;
+  return DS_OK;
+}
+
+void free_device(ds_index* h) {
+  if (h->X) (void)hipFree(h->X);
+  if (h->K) (void)hipFree(h->K);
+  h->X = nullptr;
+  h->K = nullptr;
+  learned_free(h);
+}
+
+template <typename T>
+ds_status build_typed(ds_index* h, const void* X_dev, const ds_build_opts& o, hipStream_t s) {
+  const int64_t N = h->N;
+  int method = o.method;
+  if (method == DS_METHOD_BSEARCH_LEADBIT || method == DS_METHOD_BSEARCH_OFFSET) {
+    ds_status st = validate_only<T>(h, X_dev, s);
+    if (st != DS_OK) return st;
+    h->method = method;
+    return build_bsearch<T>(h, X_dev, s);
+  }
+  if (method == DS_METHOD_LEARNED) {
+    h->method = DS_METHOD_LEARNED;
+    if (hipMalloc(&h->X, size_t(N + 1) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
+    h->nX = N + 1;
+    DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    ds_status st = validate_only<T>(h, h->X, s);
+    if (st != DS_OK) return st;
+    return learned_build(h, &o, s);
+  }
+  // Direct (or AUTO: Direct first)
+  h->method = DS_METHOD_DIRECT;
+  if (hipMalloc(&h->X, size_t(N + 1) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
+  h->nX = N + 1;
+  DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
+  ds_status st = build_direct<T>(h, o, s);
+  if (st == DS_OK) return DS_OK;
+  const bool can_fall = (st == DS_ERR_INFEASIBLE || st == DS_ERR_TABLE_CAP);
+  int fb = o.fallback;
+  if (method == DS_METHOD_AUTO && fb == DS_FALLBACK_NONE) fb = DS_FALLBACK_LEARNED;
+  if (!can_fall || fb == DS_FALLBACK_NONE) return st;
+  // fall back: drop the partial Direct state and build the replacement
+  if (h->K) (void)hipFree(h->K);
+  h->K = nullptr;
+  h->nK = 0;
+  h->H = h->W = 0;
+  h->R = h->jmin = 0;
+  if (fb == DS_FALLBACK_BSEARCH) {
+    (void)hipFree(h->X);
+    h->X = nullptr;
+    h->method = DS_METHOD_BSEARCH_LEADBIT;
+    return build_bsearch<T>(h, X_dev, s);
+  }
+  h->method = DS_METHOD_LEARNED;
+  return learned_build(h, &o, s);
+}
+
+}  // namespace
+
+int num_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+}  // namespace ds
+
+extern "C" {
+
+ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opts* opts, hipStream_t s,
+                   ds_handle* out) {
+  if (!X_dev || !out || N < 1 || N > int64_t(2147483646)) return DS_ERR_ARG;
+  if (dt != DS_F32 && dt != DS_F64) return DS_ERR_ARG;
+  ds_build_opts o{};
+  if (opts) o = *opts;
+  if (o.method < DS_METHOD_DIRECT || o.method > DS_METHOD_AUTO) return DS_ERR_ARG;
+  if (o.form != DS_FORM_SUB && o.form != DS_FORM_FMA) return DS_ERR_ARG;
+  if (o.hstart != DS_HSTART_PHI && o.hstart != DS_HSTART_HBAR) return DS_ERR_ARG;
+  if (o.fallback < DS_FALLBACK_NONE || o.fallback > DS_FALLBACK_LEARNED) return DS_ERR_ARG;
+  if (o.table_cap_bytes < 0) return DS_ERR_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  ds_index* h = new (std::nothrow) ds_index();
+  if (!h) return DS_ERR_OOM;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return DS_ERR_HIP;
+  }
+  h->dt = dt;
+  h->N = N;
+  h->form = o.form;
+  h->hstart = o.hstart;
+  ds_status st = (dt == DS_F32) ? ds::build_typed<float>(h, X_dev, o, s) : ds::build_typed<double>(h, X_dev, o, s);
+  if (st == DS_OK && hipStreamSynchronize(s) != hipSuccess) st = DS_ERR_HIP;
+  if (st != DS_OK) {
+    (void)hipStreamSynchronize(s);
+    ds::free_device(h);
+    delete h;
+    return st;
+  }
+  h->staged = ds::tables_fit_lds(h) ? 1 : 0;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  ds_info_t& in = h->info;
+  in.method = h->method;
+  in.dtype = h->dt;
+  in.form = h->form;
+  in.staged = h->staged;
+  in.N = h->N;
+  in.H = h->H;
+  in.W = h->W;
+  in.X0 = h->X0;
+  in.R = h->R;
+  in.jmin = h->jmin;
+  in.n_h_updates = h->n_updates;
+  in.table_bytes = h->nK * int64_t(sizeof(int32_t));
+  in.x_bytes = h->nX * int64_t(dt == DS_F32 ? 4 : 8);
+  in.build_ms = ms;
+  *out = h;
+  return DS_OK;
+}
+
+ds_status ds_info(ds_handle h, ds_info_t* info) {
+  if (!h || !info) return DS_ERR_ARG;
+  *info = h->info;
+  return DS_OK;
+}
+
+ds_status ds_copy_table(ds_handle h, int32_t* dst_dev, int64_t capacity_entries, hipStream_t s) {
+  if (!h || !dst_dev || !h->K || capacity_entries < h->nK) return DS_ERR_ARG;
+  DS_HIP_CHECK(hipMemcpyAsync(dst_dev, h->K, size_t(h->nK) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  return DS_OK;
+}
+
+ds_status ds_destroy(ds_handle h) {
+  if (!h) return DS_ERR_ARG;
+  ds::free_device(h);
+  delete h;
+  return DS_OK;
+}
+
+const char* ds_status_str(ds_status st) {
+  switch (st) {
+    case DS_OK: return "ok";
+    case DS_ERR_ARG: return "invalid argument";
+    case DS_ERR_NOT_SORTED: return "X is not strictly increasing";
+    case DS_ERR_NONFINITE: return "X holds a non-finite value";
+    case DS_ERR_INFEASIBLE: return "no feasible grid scale H for this X in this precision";
+    case DS_ERR_TABLE_CAP: return "the Direct table would exceed the byte cap";
+    case DS_ERR_OOM: return "device allocation failed";
+    case DS_ERR_HIP: return "HIP runtime error";
+    case DS_ERR_UNSUPPORTED: return "unsupported option";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

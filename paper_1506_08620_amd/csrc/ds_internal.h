@@ -1,0 +1,143 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "ds.h"
+
+namespace ds {
+
+constexpr int kLdsBytesPerCU = 160 * 1024;     // gfx950 LDS per compute unit (and per workgroup)
+constexpr int64_t kDefaultTableCap = int64_t(4) << 30;
+constexpr double kTwoPowQ = 2147483648.0;       // Q = 31: grid indices are int32
+
+#define DS_HIP_CHECK(expr)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      std::fprintf(stderr, "ds: %s failed: %s (%s:%d)\n", #expr, hipGetErrorString(e_), \
+                   __FILE__, __LINE__);                                                  \
+      return DS_ERR_HIP;                                                                 \
+    }                                                                                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// The grid map f of the Direct method, shared by build and search so that
+// both evaluate exactly the same floating-point expression.
+//   subtraction form (Sec. 4.1, eq. (function)):  v = m(H * m(x - X_0))
+//   FMA form (Sec. 4.9, eq. (fma)):               v = fma(H, x, -W), W = m(H X_0)
+// f(x) = floor(v).  No contraction is allowed in either form (the library is
+// built with -ffp-contract=off); the FMA form uses an explicit fma.
+template <typename T, int FORM>
+__host__ __device__ __forceinline__ T grid_value(T x, T H, T W, T X0) {
+  if constexpr (FORM == DS_FORM_FMA) {
+    return std::fma(H, x, -W);
+  } else {
+    T d = x - X0;
+    return H * d;
+  }
+}
+
+template <typename T, int FORM>
+__host__ __device__ __forceinline__ T grid_floor(T x, T H, T W, T X0) {
+  return std::floor(grid_value<T, FORM>(x, H, W, X0));
+}
+
+// Direct search of one query (Sec. 4.2, algorithm Direct) on tables that may
+// live in LDS or in global memory.  Kb points at K_0 (entry jmin is Kb[jmin]).
+// The clamp of v to [jmin, R] is done on the float: maxNum(NaN, jmin) = jmin,
+// so NaN and z < X_0 land on K_jmin = 0, z >= X_N lands on K_R = N, and the
+// float->int conversion is always defined.  The fix step is written
+// i = t - 1 + [z >= X_t]: equal to the paper's "t, minus one if z < X_t" for
+// every non-NaN z, and -1 for NaN.
+template <typename T, int FORM>
+__device__ __forceinline__ int32_t direct_one(T z, const T* __restrict__ X, const int32_t* __restrict__ Kb, T H,
+                                              T W, T X0, T vlo, T vhi) {
+  T v = grid_value<T, FORM>(z, H, W, X0);
+  v = std::fmin(std::fmax(v, vlo), vhi);
+  int32_t j;
+  if constexpr (FORM == DS_FORM_FMA) {
+    j = static_cast<int32_t>(std::floor(v));
+  } else {
+    j = static_cast<int32_t>(v);  // v >= 0 here, truncation is the floor
+  }
+  const int32_t t = Kb[j];
+  const T x = X[t];
+  return t - 1 + (z >= x ? 1 : 0);
+}
+
+template <typename T>
+struct DirectArgs {
+  const T* X;         // N+1 values (global)
+  const int32_t* K;   // R - jmin + 1 entries (global), K[0] = K_jmin
+  T H, W, X0;
+  T vlo, vhi;         // jmin and R as T (exact)
+  int32_t jmin;
+  int32_t nK;         // R - jmin + 1
+  int32_t nX;         // N + 1
+  int32_t pad_;
+  const T* z;
+  int32_t* out;
+  int64_t M;
+};
+
+template <typename T>
+struct BsearchArgs {
+  const T* X;         // padded X (leading-bit) or plain X (offset)
+  int32_t nX;         // entries of X as stored
+  int32_t N;
+  int32_t P;          // leading-bit: 2^floor(log2 N)
+  int32_t F, S, J;    // offset search constants
+  int32_t pad_;
+  const T* z;
+  int32_t* out;
+  int64_t M;
+};
+
+struct LearnedModel;  // defined in ds_learned.hip
+
+}  // namespace ds
+
+// The opaque handle behind ds_handle.
+struct ds_index {
+  int device = 0;
+  ds_dtype dt = DS_F32;
+  int32_t method = DS_METHOD_DIRECT;
+  int32_t form = DS_FORM_SUB;
+  int32_t hstart = DS_HSTART_PHI;
+  int64_t N = 0;
+  // Direct method parameters, exact values of the dtype
+  double H = 0, W = 0, X0 = 0;
+  int64_t R = 0, jmin = 0;
+  int64_t n_updates = 0;
+  // device memory
+  void* X = nullptr;            // N+1 values (Direct, offset, learned) or padded (leading-bit)
+  int64_t nX = 0;               // entries in X
+  int32_t* K = nullptr;         // Direct table
+  int64_t nK = 0;
+  // binary search constants
+  int32_t P = 0, F = 0, S = 0, J = 0;
+  // learned model (device), owned
+  ds::LearnedModel* learned = nullptr;
+  // launch shape
+  ds_tune tune{};
+  bool tune_set = false;
+  int32_t staged = 0;           // tables fit in LDS
+  ds_info_t info{};
+};
+
+namespace ds {
+// implemented in ds_search.hip
+ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);
+bool tables_fit_lds(const ds_index* h);
+// implemented in ds_learned.hip
+ds_status learned_build(ds_index* h, const ds_build_opts* o, hipStream_t s);
+ds_status learned_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);
+void learned_free(ds_index* h);
+int num_cus();
+}  // namespace ds

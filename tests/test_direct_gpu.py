@@ -1,0 +1,250 @@
+"""GPU parity of the single-array methods against the CPU oracle.
+
+Every index is compared element by element with the oracle's classic binary
+search; the Direct build's H, W, R, jmin and table K are compared bit for bit
+with the oracle's ComputeHR/InitK.  At the full sweep size (2^26 queries, the
+benchmark's launch configuration) outputs are sampled and the defining
+invariant X_i <= z < X_{i+1} is checked for every query on the device.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+FORMS = {"sub": oracle.FORM_SUB, "fma": oracle.FORM_FMA}
+
+
+@pytest.fixture(scope="module")
+def ds():
+    import paper_1506_08620_amd as mod
+
+    return mod
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _check_tables(idx, X, form, hstart=oracle.HSTART_PHI):
+    t = oracle.build_direct(X, FORMS[form], hstart)
+    assert t.status == oracle.OK
+    inf = idx.info()
+    assert inf["method_name"] == "direct"
+    assert inf["H"] == t.H and inf["W"] == t.W and inf["R"] == t.R and inf["jmin"] == t.jmin
+    assert inf["n_h_updates"] == t.n_updates
+    K = idx.table().cpu().numpy()
+    assert np.array_equal(K, t.K)
+    return t
+
+
+def _assert_same(got, ref, z=None):
+    if not np.array_equal(got, ref):
+        bad = np.flatnonzero(got != ref)
+        extra = f" z={z[bad[:4]]}" if z is not None else ""
+        raise AssertionError(f"{bad.size} of {ref.size} indices differ; first at {bad[:4]}: "
+                             f"got {got[bad[:4]]} want {ref[bad[:4]]}{extra}")
+
+
+@pytest.mark.parametrize("form", ["sub", "fma"])
+def test_plain_f32_1024_all_queries(ds, form):
+    c = W.plain_f32_1024()
+    z = np.concatenate([c.z_all, c.z_outside])
+    idx = ds.build(_dev(c.X), form=form)
+    _check_tables(idx, c.X, form)
+    got = ds.search(idx, _dev(z)).cpu().numpy()
+    _assert_same(got, oracle.search(c.X, z), z)
+    # adversarial families explicitly
+    n = c.N
+    assert np.array_equal(ds.search(idx, _dev(c.z_hits)).cpu().numpy(), np.arange(n))
+    assert np.array_equal(ds.search(idx, _dev(c.z_below)).cpu().numpy(), np.arange(n))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("n", W.SWEEP_N)
+@pytest.mark.parametrize("form", ["sub", "fma"])
+def test_sweep_tables_and_indices(ds, dtype, n, form):
+    X = W.sweep_array(n, dtype)
+    z = W.sweep_queries(1 << 20, dtype, stream=1)
+    z = np.concatenate([z, X[:-1], W.prev_float(X[1:], dtype)[: 1 << 16]])
+    idx = ds.build(_dev(X), form=form)
+    _check_tables(idx, X, form)
+    got = ds.search(idx, _dev(z)).cpu().numpy()
+    _assert_same(got, oracle.search(X, z), z)
+
+
+def _invariant_on_device(X_d, z_d, out_d):
+    """X_i <= z < X_{i+1} for every query (all queries in [X_0, X_N))."""
+    n = X_d.numel() - 1
+    assert int(out_d.min()) >= 0 and int(out_d.max()) <= n - 1
+    i = out_d.long()
+    lo = X_d[i]
+    hi = X_d[i + 1]
+    assert bool(torch.all(lo <= z_d)) and bool(torch.all(z_d < hi))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("n", W.SWEEP_N)
+def test_full_size_sweep_sampled(ds, dtype, n):
+    """M = 2^26 in the benchmark's launch shape: sampled oracle check + invariant everywhere."""
+    X = W.sweep_array(n, dtype)
+    X_d = _dev(X)
+    z_d = W.sweep_queries_torch(W.SWEEP_M, dtype, DEV)
+    idx = ds.build(X_d)
+    out = ds.search(idx, z_d)
+    torch.cuda.synchronize()
+    _invariant_on_device(X_d, z_d, out)
+    g = torch.Generator(device="cpu").manual_seed(n)
+    pos = torch.randint(0, W.SWEEP_M, (1 << 18,), generator=g).to(DEV)
+    zs = z_d[pos].cpu().numpy()
+    _assert_same(out[pos].cpu().numpy(), oracle.search(X, zs), zs)
+    del out, z_d
+
+
+@pytest.mark.parametrize("method", ["leadbit", "offset"])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 255, 256, 257, 4096, 65536, 1 << 20])
+def test_binary_search_baselines(ds, method, dtype, n):
+    rng = np.random.default_rng(n)
+    X = W.gap_array(n, dtype, rng, x0=-3.0)
+    z = np.concatenate([W.uniform_queries(X[0], X[-1], 200_000, dtype, rng), X, W.prev_float(X, dtype),
+                        np.nextafter(X, np.dtype(dtype).type(np.inf)),
+                        np.array([np.nan, np.inf, -np.inf, 0.0, -0.0], dtype)]).astype(dtype)
+    idx = ds.build(_dev(X), method=method)
+    assert idx.info()["method_name"] == method
+    got = ds.search(idx, _dev(z)).cpu().numpy()
+    _assert_same(got, oracle.search(X, z), z)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_every_launch_shape_gives_the_same_answer(ds, dtype):
+    for n in (256, 65536):
+        X = W.sweep_array(n, dtype)
+        z = W.sweep_queries((1 << 18) + 3, dtype, stream=2)
+        ref = oracle.search(X, z)
+        for method in ("direct", "leadbit"):
+            idx = ds.build(_dev(X), method=method)
+            z_d = _dev(z)
+            stages = (1, 2) if idx.info()["staged"] else (2,)
+            for stage in stages:
+                for block in (64, 256, 1024):
+                    for unroll in (1, 2, 4):
+                        for grid in (0, 1, 7):
+                            idx.set_tune(block=block, unroll=unroll, stage=stage, grid=grid)
+                            got = ds.search(idx, z_d).cpu().numpy()
+                            _assert_same(got, ref)
+            idx.clear_tune()
+
+
+@pytest.mark.parametrize("form", ["sub", "fma"])
+def test_ragged_and_unaligned_sizes(ds, form):
+    X = W.sweep_array(4096, np.float64)
+    idx = ds.build(_dev(X), form=form)
+    zall = W.sweep_queries(5000, np.float64, stream=3)
+    ref = oracle.search(X, zall)
+    z_d = _dev(zall)
+    for m in (0, 1, 2, 3, 4, 5, 7, 63, 64, 65, 1023, 4097):
+        for off in (0, 1, 3):
+            if off + m > zall.size:
+                continue
+            zz = z_d[off:off + m]
+            out = torch.empty(m + 1, dtype=torch.int32, device=DEV)[1:]  # misaligned output
+            got = ds.search(idx, zz.contiguous() if off == 0 else zz, out=out).cpu().numpy()
+            _assert_same(got, ref[off:off + m])
+
+
+def test_exhaustive_f32_domain_on_gpu(ds):
+    """Every f32 value in [X_0, X_N) for X inside 2^22 consecutive floats above 1.0."""
+    span = (np.array([1.0], np.float32).view(np.int32)[0] + np.arange(1 << 22, dtype=np.int32)).view(np.float32)
+    rng = np.random.default_rng(3)
+    pick = np.sort(rng.choice(span.size - 2, size=500, replace=False)) + 1
+    X = np.concatenate([[span[0]], span[pick], [span[-1]]]).astype(np.float32)
+    z = span[:-1]
+    ref = oracle.search(X, z)
+    for form in ("sub", "fma"):
+        idx = ds.build(_dev(X), form=form)
+        _check_tables(idx, X, form)
+        _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref)
+
+
+def test_fma_form_with_negative_first_cell(ds):
+    """Arrays at random offsets, where W = m(H X_0) can leave f(X_0) = -1."""
+    rng = np.random.default_rng(9)
+    seen = set()
+    for k in range(60):
+        X = W.gap_array(int(rng.integers(8, 3000)), np.float32, rng, x0=rng.uniform(-1e3, 1e3))
+        t = oracle.build_direct(X, oracle.FORM_FMA)
+        seen.add(t.jmin)
+        idx = ds.build(_dev(X), form="fma")
+        _check_tables(idx, X, "fma")
+        z = np.concatenate([W.uniform_queries(X[0], X[-1], 5000, np.float32, rng), X,
+                            W.prev_float(X, np.float32)])
+        _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), oracle.search(X, z), z)
+    assert -1 in seen and 0 in seen
+
+
+def test_h_growth_matches_oracle(ds):
+    """Start at Hbar so that ComputeHR must grow H now and then; H, updates and K match."""
+    rng = np.random.default_rng(2024)
+    grown = 0
+    for a in range(6000):
+        X = np.concatenate([[0.0], np.cumsum(rng.uniform(1.0, 5.0, 15))]).astype(np.float32)
+        t = oracle.compute_hr(X, hstart=oracle.HSTART_HBAR)
+        if t.n_updates == 0 and a % 200:
+            continue
+        grown += t.n_updates > 0
+        for form in ("sub", "fma"):
+            idx = ds.build(_dev(X), form=form, hstart="hbar")
+            _check_tables(idx, X, form, oracle.HSTART_HBAR)
+    assert grown > 0
+
+
+def test_errors_and_fallback(ds):
+    for case in ([-1e9, 0.0, 1.0], [0.0, 1.42e-45, 1.0]):  # Sec. 4.4
+        with pytest.raises(ds.DsError) as e:
+            ds.build(_dev(np.array(case, np.float32)))
+        assert e.value.status == ds.ERR_INFEASIBLE
+    with pytest.raises(ds.DsError) as e:
+        ds.build(_dev(np.array([0, 1, 1, 2], np.float32)))
+    assert e.value.status == ds.ERR_NOT_SORTED
+    with pytest.raises(ds.DsError) as e:
+        ds.build(_dev(np.array([0, 1, np.nan, 2], np.float64)))
+    assert e.value.status == ds.ERR_NONFINITE
+    X = W.sweep_array(65536, np.float32)
+    with pytest.raises(ds.DsError) as e:
+        ds.build(_dev(X), table_cap_bytes=1024)
+    assert e.value.status == ds.ERR_TABLE_CAP
+    idx = ds.build(_dev(X), table_cap_bytes=1024, fallback="bsearch")
+    assert idx.info()["method_name"] == "leadbit"
+    z = W.sweep_queries(100_000, np.float32)
+    _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), oracle.search(X, z))
+    idx = ds.build(_dev(np.array([-1e9, 0.0, 1.0], np.float32)), fallback="bsearch")
+    zz = np.array([-2e9, -1e9, -1.0, 0.0, 0.5, 1.0, 2.0], np.float32)
+    _assert_same(ds.search(idx, _dev(zz)).cpu().numpy(), oracle.search(np.array([-1e9, 0.0, 1.0], np.float32), zz))
+
+
+def test_graph_replay_matches_eager(ds):
+    X = W.sweep_array(4096, np.float32)
+    idx = ds.build(_dev(X))
+    z_d = W.sweep_queries_torch(1 << 22, np.float32, DEV)
+    eager = ds.search(idx, z_d).clone()
+    out = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ds.search(idx, z_d, out=out)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ds.search(idx, z_d, out=out)
+    for r in range(4):
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), r
+        ds.search(idx, z_d[: 1000])  # eager work between replays
