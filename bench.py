@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2"}
 
 
 def parse():
@@ -112,10 +113,10 @@ def main():
         inf = c["idx"].info()
         row = dict(N=c["n"], dtype="f32" if S == 4 else "f64", gq_s=round(M / ms / 1e6, 2),
                    gbs=round(bytes_per_launch / ms / 1e6, 1), hbm_frac=round(bytes_per_launch / ms / 1e6 / HBM_PEAK_GBS, 4),
-                   kernel_ms=round(ms, 5), staged=bool(inf["staged"]), R=inf["R"],
+                   kernel_ms=round(ms, 5), layout=STAGE_NAMES[inf["staged"]], R=inf["R"],
                    table_bytes=inf["table_bytes"], build_ns_per_elem=round(c["build_s"] * 1e9 / (c["n"] + 1), 2))
         case_rows.append(row)
-        key = (row["dtype"], row["staged"])
+        key = (row["dtype"], row["layout"])
         g = groups.setdefault(key, [0.0, 0, 0])
         g[0] += ms
         g[1] += 1
@@ -125,8 +126,7 @@ def main():
     avg_ms = g[0] / g[1]
     avg_bytes = g[2] / g[1]
     achieved = avg_bytes / avg_ms / 1e6
-    kernel_name = "direct_search_kernel<{},SUB,{}>".format("float" if dom_key[0] == "f32" else "double",
-                                                          "LDS" if dom_key[1] else "L2")
+    kernel_name = "direct_search_kernel<{},SUB,{}>".format("float" if dom_key[0] == "f32" else "double", dom_key[1])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel_name,
                     launches_per_step=g[1], bytes_per_launch=int(avg_bytes), avg_launch_ms=round(avg_ms, 5))
@@ -183,28 +183,45 @@ def main():
 
 
 def compare_methods(ds, cases, M, stream, reps):
-    """Direct-FMA and the branch-free binary search on the same inputs (not in the timed step)."""
+    """Other layouts, Direct-FMA and the branch-free binary search on the same inputs (not in the timed step)."""
     import torch
 
-    res = {"direct_fma": [], "bsearch_leadbit": []}
+    def timed(idx, c, out):
+        ds.search(idx, c["z"], out=out, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ds.search(idx, c["z"], out=out, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {"direct_layouts": [], "direct_fma": [], "bsearch_leadbit": []}
     for c in cases:
+        S = np.dtype(c["dt"]).itemsize
+        tag = dict(N=c["n"], dtype="f32" if S == 4 else "f64")
+        out = torch.empty_like(c["out"])
+        idx = ds.build(c["x"], layouts=("rankcode", "pairs"))
+        inf = idx.info()
+        lay = {}
+        for stage, name in STAGE_NAMES.items():
+            try:
+                idx.set_tune(stage=stage)
+            except ds.DsError:
+                continue
+            ms = timed(idx, c, out)
+            lay[name] = dict(gq_s=round(M / ms / 1e6, 2), same_as_direct=bool(torch.equal(out, c["out"])))
+        res["direct_layouts"].append(dict(**tag, layouts=lay, rankcode_bytes=inf["rankcode_bytes"],
+                                          pairs_bytes=inf["pairs_bytes"]))
+        idx.destroy()
         for key, kw in (("direct_fma", dict(form="fma")), ("bsearch_leadbit", dict(method="leadbit"))):
             idx = ds.build(c["x"], **kw)
-            out = torch.empty_like(c["out"])
-            ds.search(idx, c["z"], out=out, stream=stream)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
-                ds.search(idx, c["z"], out=out, stream=stream)
-            b.record(stream)
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / reps
-            same = bool(torch.equal(out, c["out"]))
-            S = np.dtype(c["dt"]).itemsize
-            res[key].append(dict(N=c["n"], dtype="f32" if S == 4 else "f64", gq_s=round(M / ms / 1e6, 2),
-                                 hbm_frac=round(M * (S + 4) / ms / 1e6 / HBM_PEAK_GBS, 4), same_as_direct=same))
+            ms = timed(idx, c, out)
+            res[key].append(dict(**tag, gq_s=round(M / ms / 1e6, 2),
+                                 hbm_frac=round(M * (S + 4) / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                 same_as_direct=bool(torch.equal(out, c["out"]))))
             idx.destroy()
-            del out
+        del out
     return res
 
 

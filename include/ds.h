@@ -97,13 +97,30 @@ typedef struct ds_build_opts {
   float learn_rate;         /* Adam step size (default 2e-3) */
   int32_t learn_batch;      /* training pairs per step (default 8192) */
   uint64_t seed;            /* initialisation / sampling seed */
+  int32_t extra_layouts;    /* Direct: also build these search layouts (bit mask of
+                               DS_LAYOUT_*), beyond the one the automatic choice uses */
+  int32_t reserved_;
 } ds_build_opts;
+
+/* Device layouts of the Direct tables (ds_tune.stage selects one):
+ *   PLAIN     K (int32 per grid cell) and X, as in Sec. 4.
+ *   RANKCODE  a bitmap of the grid cells that hold an X_i with a running count
+ *             per 64 cells (so K_j is a count plus a popcount), and one 16-bit
+ *             code per X_i: 15 bits of the position of X_i inside its cell and
+ *             one bit telling whether X_i is the first float of its code class.
+ *             The compare-and-fix is decided from the codes; only a tie on a
+ *             non-first element reads X_t.  About 2.4 bytes per element, so
+ *             N ~ 65536 fits in one workgroup's LDS.
+ *   PAIRS     the cache-friendly layout of Sec. 4.8: each cell stores the pair
+ *             (K_j, X_{K_j}), so a query makes one gather instead of two. */
+#define DS_LAYOUT_RANKCODE 1
+#define DS_LAYOUT_PAIRS 2
 
 typedef struct ds_info_t {
   int32_t method;           /* method actually used (ds_method) */
   int32_t dtype;            /* ds_dtype */
   int32_t form;             /* ds_form */
-  int32_t staged;           /* 1 when the search kernels keep the tables in LDS */
+  int32_t staged;           /* automatic search layout: ds_tune.stage value it selects */
   int64_t N;                /* number of intervals; X has N+1 values */
   double H;                 /* grid scale (exactly the dtype value) */
   double W;                 /* H X_0 rounded (FMA form), else 0 */
@@ -116,6 +133,8 @@ typedef struct ds_info_t {
   int64_t max_err;          /* learned: max position error over the keys */
   double mean_log2_window;  /* learned: mean log2 of the bounded-search window */
   int64_t x_bytes;          /* bytes of the device copy of X (with padding) */
+  int64_t rankcode_bytes;   /* bytes of the RANKCODE layout (0 if not built) */
+  int64_t pairs_bytes;      /* bytes of the PAIRS layout (0 if not built) */
   double build_ms;          /* wall time of ds_build */
 } ds_info_t;
 
@@ -126,7 +145,9 @@ typedef struct ds_index* ds_handle;
 typedef struct ds_tune {
   int32_t block;            /* threads per workgroup: 64..1024, multiple of 64; 0 = auto */
   int32_t unroll;           /* 16-byte query vectors per thread per iteration: 1, 2 or 4; 0 = auto */
-  int32_t stage;            /* 0 = auto, 1 = tables in LDS, 2 = tables read through L2 */
+  int32_t stage;            /* 0 = auto; Direct: 1 = PLAIN in LDS, 2 = PLAIN through L2,
+                               3 = RANKCODE in LDS, 4 = PAIRS through L2; binary
+                               search: 1 = X in LDS, 2 = X through L2 */
   int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */
 } ds_tune;
 
@@ -164,8 +185,8 @@ ds_status ds_search(ds_handle h, const void* z_dev, int64_t M, int32_t* out_dev,
 
 /* ds_set_tune: fix the launch shape of later ds_search calls on h (NULL
  * restores automatic choice).  Not thread-safe against concurrent searches on
- * the same handle.  DS_ERR_ARG for values outside the ranges above, or stage=1
- * when the tables do not fit in LDS. */
+ * the same handle.  DS_ERR_ARG for values outside the ranges above, or a stage
+ * whose layout is not built or does not fit in LDS. */
 ds_status ds_set_tune(ds_handle h, const ds_tune* t);
 
 /* ds_info: fills *info (host memory). */

@@ -30,6 +30,10 @@ FORM_SUB, FORM_FMA = 0, 1
 HSTART_PHI, HSTART_HBAR = 0, 1
 METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, METHOD_AUTO = range(5)
 FALLBACK_NONE, FALLBACK_BSEARCH, FALLBACK_LEARNED = range(3)
+LAYOUT_RANKCODE, LAYOUT_PAIRS = 1, 2
+# ds_tune.stage values of the Direct method
+STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2 = 1, 2, 3, 4
+_LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS}
 
 _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset": METHOD_BSEARCH_OFFSET,
             "learned": METHOD_LEARNED, "auto": METHOD_AUTO}
@@ -47,7 +51,8 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("form", ctypes.c_int32), ("hstart", ctypes.c_int32),
                 ("fallback", ctypes.c_int32), ("table_cap_bytes", ctypes.c_int64),
                 ("learn_epochs", ctypes.c_int32), ("learn_segments", ctypes.c_int32),
-                ("learn_rate", ctypes.c_float), ("learn_batch", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("learn_rate", ctypes.c_float), ("learn_batch", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("extra_layouts", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -56,7 +61,8 @@ class Info(ctypes.Structure):
                 ("W", ctypes.c_double), ("X0", ctypes.c_double), ("R", ctypes.c_int64),
                 ("jmin", ctypes.c_int64), ("n_h_updates", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("model_bytes", ctypes.c_int64), ("max_err", ctypes.c_int64),
-                ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
+                ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64),
+                ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
 
 
 class Tune(ctypes.Structure):
@@ -191,13 +197,18 @@ class Index:
 
 def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart: str = "phi",
           fallback: str = "none", table_cap_bytes: int = 0, learn_epochs: int = 0, learn_segments: int = 0,
-          learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, stream=None) -> Index:
-    """ds_build over the N+1 values of x (a strictly increasing GPU tensor)."""
+          learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), stream=None) -> Index:
+    """ds_build over the N+1 values of x (a strictly increasing GPU tensor).
+
+    layouts: extra Direct layouts to build besides the automatic one
+    ("rankcode", "pairs"), so that set_tune(stage=...) can select them.
+    """
     _check_device(x, "x")
     if x.dim() != 1 or x.numel() < 2:
         raise ValueError("x must be 1-D with at least two values")
     opts = BuildOpts(_METHODS[method], _FORMS[form], _HSTARTS[hstart], _FALLBACKS[fallback], int(table_cap_bytes),
-                     int(learn_epochs), int(learn_segments), float(learn_rate), int(learn_batch), int(seed))
+                     int(learn_epochs), int(learn_segments), float(learn_rate), int(learn_batch), int(seed),
+                     sum(_LAYOUTS[k] for k in set(layouts)), 0)
     h = ctypes.c_void_p()
     with torch.cuda.device(x.device):
         st = _lib.ds_build(x.data_ptr(), x.numel() - 1, _dtype_code(x), ctypes.byref(opts), _stream_handle(stream),

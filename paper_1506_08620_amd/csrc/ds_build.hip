@@ -144,6 +144,60 @@ __global__ void __launch_bounds__(kFillBlock) fill_kernel(const T* __restrict__ 
   }
 }
 
+// RANKCODE bitmap: one wave per 64 cells.  Cell e holds an X_i exactly when
+// K_{e+1} > K_e (K counts the X_i of earlier cells); the last cell holds X_N.
+__global__ void __launch_bounds__(256) rank_bits_kernel(const int32_t* __restrict__ K, int64_t nK, int64_t nW,
+                                                        uint64_t* __restrict__ bits, uint32_t* __restrict__ base) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= nW) return;  // uniform across the wave
+  const int64_t e = w * 64 + lane;
+  bool occupied = false;
+  if (e < nK - 1)
+    occupied = K[e + 1] != K[e];
+  else if (e == nK - 1)
+    occupied = true;
+  const uint64_t m = __ballot(occupied);
+  if (lane == 0) {
+    bits[w] = m;
+    base[w] = static_cast<uint32_t>(K[w * 64]);
+  }
+}
+
+// RANKCODE codes: 15-bit position of X_i in its cell, and a flag set when no
+// smaller float shares the cell and the position code of X_i.
+template <typename T, int FORM>
+__global__ void __launch_bounds__(256) rank_code_kernel(const T* __restrict__ X, int64_t N, int64_t n_alloc, T H,
+                                                        T W, T X0, uint16_t* __restrict__ code) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_alloc) return;
+  if (i > N) {
+    code[i] = 0;
+    return;
+  }
+  const T x = X[i];
+  const T v = grid_value<T, FORM>(x, H, W, X0);
+  const T jf = std::floor(v);
+  const T c = cell_code<T>(v, jf);
+  const T p = std::nextafter(x, -std::numeric_limits<T>::infinity());
+  const T vp = grid_value<T, FORM>(p, H, W, X0);
+  const T jp = std::floor(vp);
+  const T cp = cell_code<T>(vp, jp);
+  const int first = (jp == jf && cp == c) ? 0 : 1;
+  code[i] = static_cast<uint16_t>((static_cast<int>(c) << 1) | first);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) pairs_kernel(const T* __restrict__ X, const int32_t* __restrict__ K, int64_t nK,
+                                                    CachePair<T>* __restrict__ pairs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nK) return;
+  CachePair<T> p{};
+  p.t = K[e];
+  p.x = X[p.t];
+  pairs[e] = p;
+}
+
 // leading-bit padding (Sec. 3.2.1): X_N repeated up to 2^p entries
 template <typename T>
 __global__ void pad_kernel(T* __restrict__ Xp, int64_t from, int64_t to, T value) {
@@ -206,6 +260,7 @@ ds_status compute_hr(ds_index* h, const T* X, BuildScratch* scr, hipStream_t s, 
   h->H = H;
   h->W = W;
   h->X0 = X0;
+  h->XN = XN;
   h->R = static_cast<int64_t>(grid_floor<T, FORM>(XN, H, W, X0));
   h->jmin = static_cast<int64_t>(grid_floor<T, FORM>(X0, H, W, X0));
   h->n_updates = n_updates;
@@ -218,6 +273,58 @@ ds_status fill_table(ds_index* h, hipStream_t s) {
   fill_kernel<T, FORM><<<dim3((unsigned)blocks), dim3(kFillBlock), 0, s>>>(
       static_cast<const T*>(h->X), h->N, T(h->H), T(h->W), T(h->X0), static_cast<int32_t>(h->jmin), h->nK, h->K);
   DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+template <typename T, int FORM>
+ds_status build_rankcode(ds_index* h, hipStream_t s) {
+  const int64_t nW = (h->nK + 63) / 64;
+  const int64_t n_codes = ((h->N + 1) + 7) / 8 * 8;
+  h->rc_words = nW;
+  if (hipMalloc(&h->rc_bits, size_t(nW) * 8) != hipSuccess || hipMalloc(&h->rc_base, size_t(nW) * 4) != hipSuccess ||
+      hipMalloc(&h->rc_code, size_t(n_codes) * 2) != hipSuccess)
+    return DS_ERR_OOM;
+  rank_bits_kernel<<<dim3((unsigned)((nW * 64 + 255) / 256)), dim3(256), 0, s>>>(h->K, h->nK, nW, h->rc_bits,
+                                                                                    h->rc_base);
+  DS_HIP_CHECK(hipGetLastError());
+  rank_code_kernel<T, FORM><<<dim3((unsigned)((n_codes + 255) / 256)), dim3(256), 0, s>>>(
+      static_cast<const T*>(h->X), h->N, n_codes, T(h->H), T(h->W), T(h->X0), h->rc_code);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+template <typename T>
+ds_status build_pairs(ds_index* h, hipStream_t s) {
+  if (hipMalloc(&h->pairs, size_t(h->nK) * sizeof(CachePair<T>)) != hipSuccess) {
+    h->pairs = nullptr;
+    return DS_ERR_OOM;
+  }
+  pairs_kernel<T><<<dim3((unsigned)((h->nK + 255) / 256)), dim3(256), 0, s>>>(
+      static_cast<const T*>(h->X), h->K, h->nK, static_cast<CachePair<T>*>(h->pairs));
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+// Which layouts to build: the one the automatic launch will use (PLAIN in LDS
+// when it fits, else RANKCODE in LDS when it fits, else PAIRS through L2),
+// plus whatever the caller asked for.
+template <typename T>
+ds_status build_layouts(ds_index* h, const ds_build_opts& o, hipStream_t s) {
+  h->staged = tables_fit_lds(h) ? 1 : 0;
+  const int64_t nW = (h->nK + 63) / 64;
+  h->rc_words = nW;
+  const bool rc_fits = rankcode_lds_bytes(h) <= kLdsBytesPerCU;
+  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : 4);
+  const bool want_rc = (o.extra_layouts & DS_LAYOUT_RANKCODE) || h->auto_stage == 3;
+  const bool want_pairs = (o.extra_layouts & DS_LAYOUT_PAIRS) || h->auto_stage == 4;
+  if (want_rc) {
+    ds_status st = (h->form == DS_FORM_FMA) ? build_rankcode<T, DS_FORM_FMA>(h, s) : build_rankcode<T, DS_FORM_SUB>(h, s);
+    if (st != DS_OK) return st;
+  }
+  if (want_pairs) {
+    ds_status st = build_pairs<T>(h, s);
+    if (st != DS_OK) return st;
+  }
   return DS_OK;
 }
 
@@ -259,6 +366,8 @@ ds_status build_direct(ds_index* h, const ds_build_opts& o, hipStream_t s) {
     return DS_ERR_OOM;
   }
   st = (h->form == DS_FORM_FMA) ? fill_table<T, DS_FORM_FMA>(h, s) : fill_table<T, DS_FORM_SUB>(h, s);
+  if (st != DS_OK) return st;
+  st = build_layouts<T>(h, o, s);
   if (st != DS_OK) return st;
   DS_HIP_CHECK(hipStreamSynchronize(s));
   return DS_OK;
@@ -322,11 +431,23 @@ ds_status validate_only(ds_index* h, const void* X_dev, hipStream_t s) {
   return DS_OK;
 }
 
+void free_layouts(ds_index* h) {
+  if (h->rc_bits) (void)hipFree(h->rc_bits);
+  if (h->rc_base) (void)hipFree(h->rc_base);
+  if (h->rc_code) (void)hipFree(h->rc_code);
+  if (h->pairs) (void)hipFree(h->pairs);
+  h->rc_bits = nullptr;
+  h->rc_base = nullptr;
+  h->rc_code = nullptr;
+  h->pairs = nullptr;
+}
+
 void free_device(ds_index* h) {
   if (h->X) (void)hipFree(h->X);
   if (h->K) (void)hipFree(h->K);
   h->X = nullptr;
   h->K = nullptr;
+  free_layouts(h);
   learned_free(h);
 }
 
@@ -361,6 +482,7 @@ ds_status build_typed(ds_index* h, const void* X_dev, const ds_build_opts& o, hi
   if (method == DS_METHOD_AUTO && fb == DS_FALLBACK_NONE) fb = DS_FALLBACK_LEARNED;
   if (!can_fall || fb == DS_FALLBACK_NONE) return st;
   // fall back: drop the partial Direct state and build the replacement
+  free_layouts(h);
   if (h->K) (void)hipFree(h->K);
   h->K = nullptr;
   h->nK = 0;
@@ -424,13 +546,13 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
     delete h;
     return st;
   }
-  h->staged = ds::tables_fit_lds(h) ? 1 : 0;
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   ds_info_t& in = h->info;
   in.method = h->method;
   in.dtype = h->dt;
   in.form = h->form;
-  in.staged = h->staged;
+  in.staged = (h->method == DS_METHOD_DIRECT) ? h->auto_stage : (ds::tables_fit_lds(h) ? 1 : 2);
+  if (h->method != DS_METHOD_DIRECT) h->staged = ds::tables_fit_lds(h) ? 1 : 0;
   in.N = h->N;
   in.H = h->H;
   in.W = h->W;
@@ -440,6 +562,8 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   in.n_h_updates = h->n_updates;
   in.table_bytes = h->nK * int64_t(sizeof(int32_t));
   in.x_bytes = h->nX * int64_t(dt == DS_F32 ? 4 : 8);
+  in.rankcode_bytes = h->rc_code ? (h->rc_words * 12 + (h->N + 1) * 2) : 0;
+  in.pairs_bytes = h->pairs ? h->nK * int64_t(dt == DS_F32 ? 8 : 16) : 0;
   in.build_ms = ms;
   *out = h;
   return DS_OK;

@@ -71,16 +71,49 @@ __device__ __forceinline__ int32_t direct_one(T z, const T* __restrict__ X, cons
   return t - 1 + (z >= x ? 1 : 0);
 }
 
+// Position code of a value inside its grid cell: the fraction v - floor(v) in
+// units of 2^-15, capped at 2^15 - 1.  It is a non-decreasing function of v
+// within a cell, computed identically by the build and the search, so a
+// strict difference between the codes of z and of X_t orders z and X_t.
+template <typename T>
+__host__ __device__ __forceinline__ T cell_code(T v, T jf) {
+  return std::fmin(std::floor((v - jf) * T(32768)), T(32767));
+}
+
+// the cache-friendly pair of Sec. 4.8: (K_j, X_{K_j}) in one aligned load
+template <typename T>
+struct alignas(2 * sizeof(T)) CachePair;
+template <>
+struct alignas(8) CachePair<float> {
+  int32_t t;
+  float x;
+};
+template <>
+struct alignas(16) CachePair<double> {
+  int32_t t;
+  int32_t pad;
+  double x;
+};
+
 template <typename T>
 struct DirectArgs {
   const T* X;         // N+1 values (global)
   const int32_t* K;   // R - jmin + 1 entries (global), K[0] = K_jmin
   T H, W, X0;
   T vlo, vhi;         // jmin and R as T (exact)
+  T XN;               // X_N
   int32_t jmin;
   int32_t nK;         // R - jmin + 1
   int32_t nX;         // N + 1
+  int32_t N;
+  // RANKCODE layout
+  const uint64_t* rc_bits;   // nW words, bit b of word w: cell jmin + 64 w + b holds an X_i
+  const uint32_t* rc_base;   // nW counts: #{i : f(X_i) < jmin + 64 w}
+  const uint16_t* rc_code;   // N+1 codes (allocation padded to a multiple of 8)
+  int32_t nW;
   int32_t pad_;
+  // PAIRS layout
+  const CachePair<T>* pairs; // nK pairs, pairs[0] for cell jmin
   const T* z;
   int32_t* out;
   int64_t M;
@@ -112,7 +145,7 @@ struct ds_index {
   int32_t hstart = DS_HSTART_PHI;
   int64_t N = 0;
   // Direct method parameters, exact values of the dtype
-  double H = 0, W = 0, X0 = 0;
+  double H = 0, W = 0, X0 = 0, XN = 0;
   int64_t R = 0, jmin = 0;
   int64_t n_updates = 0;
   // device memory
@@ -120,6 +153,14 @@ struct ds_index {
   int64_t nX = 0;               // entries in X
   int32_t* K = nullptr;         // Direct table
   int64_t nK = 0;
+  // RANKCODE layout (see ds.h)
+  uint64_t* rc_bits = nullptr;
+  uint32_t* rc_base = nullptr;
+  uint16_t* rc_code = nullptr;
+  int64_t rc_words = 0;
+  // PAIRS layout
+  void* pairs = nullptr;
+  int32_t auto_stage = 2;       // layout the automatic launch uses
   // binary search constants
   int32_t P = 0, F = 0, S = 0, J = 0;
   // learned model (device), owned
@@ -127,7 +168,7 @@ struct ds_index {
   // launch shape
   ds_tune tune{};
   bool tune_set = false;
-  int32_t staged = 0;           // tables fit in LDS
+  int32_t staged = 0;           // the PLAIN tables fit in LDS
   ds_info_t info{};
 };
 
@@ -135,6 +176,7 @@ namespace ds {
 // implemented in ds_search.hip
 ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);
 bool tables_fit_lds(const ds_index* h);
+int64_t rankcode_lds_bytes(const ds_index* h);
 // implemented in ds_learned.hip
 ds_status learned_build(ds_index* h, const ds_build_opts* o, hipStream_t s);
 ds_status learned_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);

@@ -26,13 +26,23 @@ using ivec4 = int __attribute__((ext_vector_type(4)));
 
 __host__ __device__ constexpr int64_t round16(int64_t b) { return (b + 15) & ~int64_t(15); }
 
-// Copy n_bytes (multiple of 4) from global to LDS with 16-byte moves.
+// Copy n_bytes (multiple of 4) from global to LDS with 16-byte moves, four
+// loads in flight per lane before the stores.
 __device__ __forceinline__ void stage_bytes(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src,
                                             int64_t n_bytes) {
   const int64_t n16 = n_bytes >> 4;
   const int4* s4 = reinterpret_cast<const int4*>(src);
   int4* d4 = reinterpret_cast<int4*>(dst);
-  for (int64_t k = threadIdx.x; k < n16; k += blockDim.x) d4[k] = s4[k];
+  const int64_t B = blockDim.x;
+  int64_t k = threadIdx.x;
+  for (; k + 3 * B < n16; k += 4 * B) {
+    const int4 a = s4[k], b = s4[k + B], c = s4[k + 2 * B], d = s4[k + 3 * B];
+    d4[k] = a;
+    d4[k + B] = b;
+    d4[k + 2 * B] = c;
+    d4[k + 3 * B] = d;
+  }
+  for (; k < n16; k += B) d4[k] = s4[k];
   const int64_t rem = n_bytes - (n16 << 4);  // 0, 4, 8 or 12
   if ((int64_t)threadIdx.x < (rem >> 2)) {
     reinterpret_cast<int*>(dst + (n16 << 4))[threadIdx.x] = reinterpret_cast<const int*>(src + (n16 << 4))[threadIdx.x];
@@ -87,22 +97,103 @@ struct DirectOp {
   __device__ __forceinline__ int32_t operator()(T z) const { return direct_one<T, FORM>(z, X, Kb, H, W, X0, vlo, vhi); }
 };
 
-// STAGE 1: tables in LDS; STAGE 2: tables through L1/L2.
+// RANKCODE layout (see ds.h).  With e = f(z) - jmin, K_j is the running count
+// of the 64-cell word plus the popcount of the word's lower bits.  A cell
+// without an X_i gives i = K_j - 1 directly (every X_i before it is below z
+// and X_{K_j} is above it).  A cell holding X_t (t = K_j) compares the position
+// codes of z and X_t: a strict difference decides, equal codes decide when X_t
+// is the first float of its code class, and only the remaining case reads X_t.
+// The last two lines give -1 below X_0 (and for NaN) and N at or above X_N.
+template <typename T, int FORM>
+struct RankCodeOp {
+  const uint64_t* bits;
+  const uint32_t* base;
+  const uint16_t* code;
+  const T* Xg;  // X in global memory, for the rare undecided compare
+  T H, W, X0, vlo, vhi, XN;
+  int32_t jmin, N;
+  __device__ __forceinline__ int32_t operator()(T z) const {
+    const T v = grid_value<T, FORM>(z, H, W, X0);
+    const T jf = std::floor(std::fmin(std::fmax(v, vlo), vhi));
+    const int32_t e = static_cast<int32_t>(jf) - jmin;
+    const int32_t w = e >> 6;
+    const uint32_t b = static_cast<uint32_t>(e) & 63u;
+    const uint64_t word = bits[w];
+    const int32_t t = static_cast<int32_t>(base[w]) + __popcll(word & ((uint64_t(1) << b) - 1));
+    const bool occupied = (word >> b) & 1u;
+    const int32_t c = code[t];
+    const T cz = cell_code<T>(v, jf);
+    const T cx = static_cast<T>(c >> 1);
+    const bool first = c & 1;
+    int32_t i = t - 1;
+    if (occupied) {
+      if (cz > cx || (cz == cx && first)) {
+        i = t;
+      } else if (cz == cx) {
+        i = t - 1 + (z >= Xg[t] ? 1 : 0);
+      }
+    }
+    i = (z >= XN) ? N : i;
+    return (z >= X0) ? i : -1;
+  }
+};
+
+// PAIRS layout (Sec. 4.8, algorithm DirectCache): one aligned load gives
+// (K_j, X_{K_j}).
+template <typename T, int FORM>
+struct PairsOp {
+  const CachePair<T>* pb;  // points at the pair of cell 0
+  T H, W, X0, vlo, vhi;
+  __device__ __forceinline__ int32_t operator()(T z) const {
+    T v = grid_value<T, FORM>(z, H, W, X0);
+    v = std::fmin(std::fmax(v, vlo), vhi);
+    const int32_t j = (FORM == DS_FORM_FMA) ? static_cast<int32_t>(std::floor(v)) : static_cast<int32_t>(v);
+    const CachePair<T> p = pb[j];
+    return p.t - 1 + (z >= p.x ? 1 : 0);
+  }
+};
+
+__host__ __device__ constexpr int64_t rankcode_offsets(int64_t nW, int64_t n_code_bytes, int64_t* base_off,
+                                                       int64_t* code_off) {
+  *base_off = round16(nW * 8);
+  *code_off = *base_off + round16(nW * 4);
+  return *code_off + round16(n_code_bytes);
+}
+
+// STAGE 1: PLAIN in LDS; 2: PLAIN through L1/L2; 3: RANKCODE in LDS;
+// 4: PAIRS through L1/L2.
 template <typename T, int FORM, int STAGE, int U, bool VEC>
 __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const T* X = a.X;
-  const int32_t* K = a.K;
-  if constexpr (STAGE == 1) {
-    const int64_t xb = round16(int64_t(a.nX) * sizeof(T));
-    stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.X), int64_t(a.nX) * sizeof(T));
-    stage_bytes(smem + xb, reinterpret_cast<const unsigned char*>(a.K), int64_t(a.nK) * 4);
+  if constexpr (STAGE == 1 || STAGE == 2) {
+    const T* X = a.X;
+    const int32_t* K = a.K;
+    if constexpr (STAGE == 1) {
+      const int64_t xb = round16(int64_t(a.nX) * sizeof(T));
+      stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.X), int64_t(a.nX) * sizeof(T));
+      stage_bytes(smem + xb, reinterpret_cast<const unsigned char*>(a.K), int64_t(a.nK) * 4);
+      __syncthreads();
+      X = reinterpret_cast<const T*>(smem);
+      K = reinterpret_cast<const int32_t*>(smem + xb);
+    }
+    DirectOp<T, FORM> op{X, K - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
+    stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+  } else if constexpr (STAGE == 3) {
+    int64_t base_off = 0, code_off = 0;
+    const int64_t code_bytes = round16(int64_t(a.N + 1) * 2);
+    rankcode_offsets(a.nW, code_bytes, &base_off, &code_off);
+    stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.rc_bits), int64_t(a.nW) * 8);
+    stage_bytes(smem + base_off, reinterpret_cast<const unsigned char*>(a.rc_base), int64_t(a.nW) * 4);
+    stage_bytes(smem + code_off, reinterpret_cast<const unsigned char*>(a.rc_code), code_bytes);
     __syncthreads();
-    X = reinterpret_cast<const T*>(smem);
-    K = reinterpret_cast<const int32_t*>(smem + xb);
+    RankCodeOp<T, FORM> op{reinterpret_cast<const uint64_t*>(smem), reinterpret_cast<const uint32_t*>(smem + base_off),
+                           reinterpret_cast<const uint16_t*>(smem + code_off), a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN,
+                           a.jmin, a.N};
+    stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+  } else {
+    PairsOp<T, FORM> op{a.pairs - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
+    stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   }
-  DirectOp<T, FORM> op{X, K - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
-  stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
 }
 
 // Sec. 3.2.1: i = 0; for k = P, P/2, ..., 1: r = i|k; if z >= Xp_r then i = r.
@@ -163,8 +254,12 @@ __global__ void __launch_bounds__(1024) bsearch_kernel(BsearchArgs<T> a) {
   }
 }
 
-int64_t lds_bytes_needed(const ds_index* h) {
+int64_t lds_bytes_needed(const ds_index* h, int stage) {
   const int64_t s = (h->dt == DS_F32) ? 4 : 8;
+  if (h->method == DS_METHOD_DIRECT && stage == 3) {
+    int64_t b = 0, c = 0;
+    return rankcode_offsets(h->rc_words, round16((h->N + 1) * 2), &b, &c);
+  }
   if (h->method == DS_METHOD_DIRECT) return round16(h->nX * s) + h->nK * 4;
   if (h->method == DS_METHOD_BSEARCH_LEADBIT || h->method == DS_METHOD_BSEARCH_OFFSET) return round16(h->nX * s);
   return int64_t(1) << 40;
@@ -192,7 +287,13 @@ Shape pick_shape(const ds_index* h, int64_t M) {
   const ds_tune& t = h->tune;
   sh.block = (h->tune_set && t.block) ? t.block : 512;
   sh.unroll = (h->tune_set && t.unroll) ? t.unroll : 2;
-  sh.stage = (h->tune_set && t.stage) ? t.stage : (h->staged ? 1 : 2);
+  if (h->tune_set && t.stage) {
+    sh.stage = t.stage;
+  } else if (h->method == DS_METHOD_DIRECT) {
+    sh.stage = h->auto_stage;
+  } else {
+    sh.stage = h->staged ? 1 : 2;
+  }
   sh.grid = (h->tune_set && t.grid) ? t.grid : 0;
   (void)M;
   return sh;
@@ -225,12 +326,20 @@ ds_status dispatch_direct_u(const DirectArgs<T>& a, const Shape& sh, int lds, in
 template <typename T, int FORM>
 ds_status dispatch_direct(const DirectArgs<T>& a, const Shape& sh, bool vec, int lds, hipStream_t s) {
   const int64_t items = vec ? ((a.M >> 2) + sh.unroll - 1) / sh.unroll : a.M;
-  if (sh.stage == 1) {
-    return vec ? dispatch_direct_u<T, FORM, 1, true>(a, sh, lds, items, s)
-               : dispatch_direct_u<T, FORM, 1, false>(a, sh, lds, items, s);
+  switch (sh.stage) {
+    case 1:
+      return vec ? dispatch_direct_u<T, FORM, 1, true>(a, sh, lds, items, s)
+                 : dispatch_direct_u<T, FORM, 1, false>(a, sh, lds, items, s);
+    case 3:
+      return vec ? dispatch_direct_u<T, FORM, 3, true>(a, sh, lds, items, s)
+                 : dispatch_direct_u<T, FORM, 3, false>(a, sh, lds, items, s);
+    case 4:
+      return vec ? dispatch_direct_u<T, FORM, 4, true>(a, sh, 0, items, s)
+                 : dispatch_direct_u<T, FORM, 4, false>(a, sh, 0, items, s);
+    default:
+      return vec ? dispatch_direct_u<T, FORM, 2, true>(a, sh, 0, items, s)
+                 : dispatch_direct_u<T, FORM, 2, false>(a, sh, 0, items, s);
   }
-  return vec ? dispatch_direct_u<T, FORM, 2, true>(a, sh, 0, items, s)
-             : dispatch_direct_u<T, FORM, 2, false>(a, sh, 0, items, s);
 }
 
 template <typename T, int KIND, int STAGE, bool VEC>
@@ -254,11 +363,16 @@ ds_status dispatch_bs(const BsearchArgs<T>& a, const Shape& sh, bool vec, int ld
 }
 
 template <typename T>
+T X_N(const ds_index* h) {
+  return T(h->XN);
+}
+
+template <typename T>
 ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s) {
   const Shape sh = pick_shape(h, M);
   const bool vec = ((reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T))) == 0) &&
                    ((reinterpret_cast<uintptr_t>(out) % 16) == 0);
-  const int lds = (sh.stage == 1) ? static_cast<int>(lds_bytes_needed(h)) : 0;
+  const int lds = (sh.stage == 1 || sh.stage == 3) ? static_cast<int>(lds_bytes_needed(h, sh.stage)) : 0;
   if (h->method == DS_METHOD_DIRECT) {
     DirectArgs<T> a{};
     a.X = static_cast<const T*>(h->X);
@@ -271,6 +385,13 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
     a.jmin = static_cast<int32_t>(h->jmin);
     a.nK = static_cast<int32_t>(h->nK);
     a.nX = static_cast<int32_t>(h->nX);
+    a.N = static_cast<int32_t>(h->N);
+    a.XN = X_N<T>(h);
+    a.rc_bits = h->rc_bits;
+    a.rc_base = h->rc_base;
+    a.rc_code = h->rc_code;
+    a.nW = static_cast<int32_t>(h->rc_words);
+    a.pairs = static_cast<const CachePair<T>*>(h->pairs);
     a.z = static_cast<const T*>(z);
     a.out = out;
     a.M = M;
@@ -294,7 +415,8 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
 
 }  // namespace
 
-bool tables_fit_lds(const ds_index* h) { return lds_bytes_needed(h) <= kLdsBytesPerCU; }
+bool tables_fit_lds(const ds_index* h) { return lds_bytes_needed(h, 1) <= kLdsBytesPerCU; }
+int64_t rankcode_lds_bytes(const ds_index* h) { return lds_bytes_needed(h, 3); }
 
 ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s) {
   if (h->method == DS_METHOD_LEARNED) return learned_search(h, z, M, out, s);
@@ -324,8 +446,11 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   }
   if (t->block != 0 && (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)) return DS_ERR_ARG;
   if (t->unroll != 0 && t->unroll != 1 && t->unroll != 2 && t->unroll != 4) return DS_ERR_ARG;
-  if (t->stage < 0 || t->stage > 2) return DS_ERR_ARG;
+  if (t->stage < 0 || t->stage > 4) return DS_ERR_ARG;
   if (t->stage == 1 && !h->staged) return DS_ERR_ARG;
+  if (t->stage >= 3 && h->method != DS_METHOD_DIRECT) return DS_ERR_ARG;
+  if (t->stage == 3 && (!h->rc_code || ds::rankcode_lds_bytes(h) > ds::kLdsBytesPerCU)) return DS_ERR_ARG;
+  if (t->stage == 4 && !h->pairs) return DS_ERR_ARG;
   if (t->grid < 0) return DS_ERR_ARG;
   h->tune = *t;
   h->tune_set = true;

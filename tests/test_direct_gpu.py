@@ -68,13 +68,19 @@ def test_plain_f32_1024_all_queries(ds, form):
 @pytest.mark.parametrize("n", W.SWEEP_N)
 @pytest.mark.parametrize("form", ["sub", "fma"])
 def test_sweep_tables_and_indices(ds, dtype, n, form):
+    """Every layout the build can make, at every size of the sweep."""
     X = W.sweep_array(n, dtype)
     z = W.sweep_queries(1 << 20, dtype, stream=1)
-    z = np.concatenate([z, X[:-1], W.prev_float(X[1:], dtype)[: 1 << 16]])
-    idx = ds.build(_dev(X), form=form)
+    z = np.concatenate([z, X[:-1], W.prev_float(X[1:], dtype)[: 1 << 16], np.nextafter(X, np.dtype(dtype).type(2))])
+    idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs"))
     _check_tables(idx, X, form)
-    got = ds.search(idx, _dev(z)).cpu().numpy()
-    _assert_same(got, oracle.search(X, z), z)
+    ref = oracle.search(X, z)
+    z_d = _dev(z)
+    for stage in _stages(idx):
+        idx.set_tune(stage=stage)
+        _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
+    idx.clear_tune()
+    _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
 
 
 def _invariant_on_device(X_d, z_d, out_d):
@@ -120,6 +126,20 @@ def test_binary_search_baselines(ds, method, dtype, n):
     _assert_same(got, oracle.search(X, z), z)
 
 
+def _stages(idx):
+    inf = idx.info()
+    if inf["method_name"] != "direct":
+        return (1, 2) if inf["staged"] == 1 else (2,)
+    st = [2]
+    if inf["staged"] == 1:
+        st.append(1)
+    if inf["rankcode_bytes"] and inf["rankcode_bytes"] <= 160 * 1024 - 64:
+        st.append(3)
+    if inf["pairs_bytes"]:
+        st.append(4)
+    return tuple(sorted(st))
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_every_launch_shape_gives_the_same_answer(ds, dtype):
     for n in (256, 65536):
@@ -127,9 +147,11 @@ def test_every_launch_shape_gives_the_same_answer(ds, dtype):
         z = W.sweep_queries((1 << 18) + 3, dtype, stream=2)
         ref = oracle.search(X, z)
         for method in ("direct", "leadbit"):
-            idx = ds.build(_dev(X), method=method)
+            idx = ds.build(_dev(X), method=method, layouts=("rankcode", "pairs") if method == "direct" else ())
             z_d = _dev(z)
-            stages = (1, 2) if idx.info()["staged"] else (2,)
+            stages = _stages(idx)
+            if method == "direct":
+                assert 4 in stages and (3 in stages) == (n <= 65536)
             for stage in stages:
                 for block in (64, 256, 1024):
                     for unroll in (1, 2, 4):
@@ -165,10 +187,31 @@ def test_exhaustive_f32_domain_on_gpu(ds):
     X = np.concatenate([[span[0]], span[pick], [span[-1]]]).astype(np.float32)
     z = span[:-1]
     ref = oracle.search(X, z)
+    z_d = _dev(z)
     for form in ("sub", "fma"):
-        idx = ds.build(_dev(X), form=form)
+        idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs"))
         _check_tables(idx, X, form)
-        _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref)
+        for stage in _stages(idx):
+            idx.set_tune(stage=stage)
+            _assert_same(ds.search(idx, z_d).cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_dense_neighbourhoods_all_layouts(ds, dtype):
+    """All floats within 2^12 ulps of every X_i of a sweep array, through every layout."""
+    dt = np.dtype(dtype)
+    X = W.sweep_array(4096, dt)
+    it = np.int32 if dt == np.float32 else np.int64
+    offs = np.arange(-(1 << 12), 1 << 12, dtype=it)
+    z = (X.view(it)[:, None] + offs[None, :]).reshape(-1).view(dt)
+    z = z[np.isfinite(z)]
+    ref = oracle.search(X, z)
+    z_d = _dev(z)
+    for form in ("sub", "fma"):
+        idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs"))
+        for stage in _stages(idx):
+            idx.set_tune(stage=stage)
+            _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
 
 
 def test_fma_form_with_negative_first_cell(ds):
@@ -179,11 +222,16 @@ def test_fma_form_with_negative_first_cell(ds):
         X = W.gap_array(int(rng.integers(8, 3000)), np.float32, rng, x0=rng.uniform(-1e3, 1e3))
         t = oracle.build_direct(X, oracle.FORM_FMA)
         seen.add(t.jmin)
-        idx = ds.build(_dev(X), form="fma")
+        idx = ds.build(_dev(X), form="fma", layouts=("rankcode", "pairs"))
         _check_tables(idx, X, "fma")
         z = np.concatenate([W.uniform_queries(X[0], X[-1], 5000, np.float32, rng), X,
-                            W.prev_float(X, np.float32)])
-        _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), oracle.search(X, z), z)
+                            W.prev_float(X, np.float32), np.nextafter(X, np.float32(np.inf)),
+                            np.array([np.nan, -np.inf, np.inf], np.float32)])
+        ref = oracle.search(X, z)
+        z_d = _dev(z)
+        for stage in _stages(idx):
+            idx.set_tune(stage=stage)
+            _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
     assert -1 in seen and 0 in seen
 
 
