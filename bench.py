@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
-STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2"}
+STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2", 5: "RANKCODE-L2"}
 
 
 def parse():

@@ -146,7 +146,8 @@ typedef struct ds_tune {
   int32_t block;            /* threads per workgroup: 64..1024, multiple of 64; 0 = auto */
   int32_t unroll;           /* 16-byte query vectors per thread per iteration: 1, 2 or 4; 0 = auto */
   int32_t stage;            /* 0 = auto; Direct: 1 = PLAIN in LDS, 2 = PLAIN through L2,
-                               3 = RANKCODE in LDS, 4 = PAIRS through L2; binary
+                               3 = RANKCODE in LDS, 4 = PAIRS through L2,
+                               5 = RANKCODE through L2; binary
                                search: 1 = X in LDS, 2 = X through L2 */
   int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */
 } ds_tune;
@@ -188,6 +189,14 @@ ds_status ds_search(ds_handle h, const void* z_dev, int64_t M, int32_t* out_dev,
  * the same handle.  DS_ERR_ARG for values outside the ranges above, or a stage
  * whose layout is not built or does not fit in LDS. */
 ds_status ds_set_tune(ds_handle h, const ds_tune* t);
+
+/* ds_autotune: times every launch shape the handle supports (each built
+ * layout x block {256, 512, 1024} x vectors per lane {1, 2, 4}) on the first
+ * min(M, 2^24) queries of z_dev with HIP events on s, and keeps the fastest
+ * for later ds_search calls on h (as ds_set_tune would).  out_dev receives
+ * scratch results.  Synchronises s.  *best (may be NULL) receives the choice.
+ * Results of ds_search do not depend on the choice. */
+ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_dev, hipStream_t s, ds_tune* best);
 
 /* ds_info: fills *info (host memory). */
 ds_status ds_info(ds_handle h, ds_info_t* info);

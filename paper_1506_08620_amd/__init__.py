@@ -32,7 +32,7 @@ METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, ME
 FALLBACK_NONE, FALLBACK_BSEARCH, FALLBACK_LEARNED = range(3)
 LAYOUT_RANKCODE, LAYOUT_PAIRS = 1, 2
 # ds_tune.stage values of the Direct method
-STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2 = 1, 2, 3, 4
+STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2, STAGE_RANKCODE_L2 = 1, 2, 3, 4, 5
 _LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS}
 
 _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset": METHOD_BSEARCH_OFFSET,
@@ -43,7 +43,7 @@ _FALLBACKS = {"none": FALLBACK_NONE, "bsearch": FALLBACK_BSEARCH, "learned": FAL
 METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 
 # exported symbols of libds.so (every function ds.h declares)
-SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_info", "ds_copy_table", "ds_destroy", "ds_status_str",
+SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_autotune", "ds_info", "ds_copy_table", "ds_destroy", "ds_status_str",
            "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_report")
 
 
@@ -96,6 +96,8 @@ def _load_library():
     lib.ds_search.restype = i32
     lib.ds_set_tune.argtypes = [vp, ctypes.POINTER(Tune)]
     lib.ds_set_tune.restype = i32
+    lib.ds_autotune.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(Tune)]
+    lib.ds_autotune.restype = i32
     lib.ds_info.argtypes = [vp, ctypes.POINTER(Info)]
     lib.ds_info.restype = i32
     lib.ds_copy_table.argtypes = [vp, vp, i64, vp]
@@ -174,6 +176,18 @@ class Index:
         st = _lib.ds_set_tune(self._h, ctypes.byref(t))
         if st != OK:
             raise DsError(st, "ds_set_tune")
+
+    def autotune(self, z: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> dict:
+        """ds_autotune on queries z; returns the chosen launch shape."""
+        _check_device(z, "z")
+        if out is None:
+            out = torch.empty(z.numel(), dtype=torch.int32, device=z.device)
+        t = Tune()
+        st = _lib.ds_autotune(self._h, z.data_ptr(), z.numel(), out.data_ptr(), _stream_handle(stream),
+                              ctypes.byref(t))
+        if st != OK:
+            raise DsError(st, "ds_autotune")
+        return {name: getattr(t, name) for name, _ in Tune._fields_}
 
     def clear_tune(self):
         st = _lib.ds_set_tune(self._h, None)

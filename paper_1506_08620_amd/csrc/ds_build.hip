@@ -147,7 +147,8 @@ __global__ void __launch_bounds__(kFillBlock) fill_kernel(const T* __restrict__ 
 // RANKCODE bitmap: one wave per 64 cells.  Cell e holds an X_i exactly when
 // K_{e+1} > K_e (K counts the X_i of earlier cells); the last cell holds X_N.
 __global__ void __launch_bounds__(256) rank_bits_kernel(const int32_t* __restrict__ K, int64_t nK, int64_t nW,
-                                                        uint64_t* __restrict__ bits, uint32_t* __restrict__ base) {
+                                                        uint64_t* __restrict__ bits, uint32_t* __restrict__ base,
+                                                        RcWord* __restrict__ w16) {
   const int lane = threadIdx.x & 63;
   const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (w >= nW) return;  // uniform across the wave
@@ -159,8 +160,14 @@ __global__ void __launch_bounds__(256) rank_bits_kernel(const int32_t* __restric
     occupied = true;
   const uint64_t m = __ballot(occupied);
   if (lane == 0) {
+    const uint32_t b0 = static_cast<uint32_t>(K[w * 64]);
     bits[w] = m;
-    base[w] = static_cast<uint32_t>(K[w * 64]);
+    base[w] = b0;
+    RcWord rw;
+    rw.bits = m;
+    rw.base = b0;
+    rw.pad = 0;
+    w16[w] = rw;
   }
 }
 
@@ -282,10 +289,11 @@ ds_status build_rankcode(ds_index* h, hipStream_t s) {
   const int64_t n_codes = ((h->N + 1) + 7) / 8 * 8;
   h->rc_words = nW;
   if (hipMalloc(&h->rc_bits, size_t(nW) * 8) != hipSuccess || hipMalloc(&h->rc_base, size_t(nW) * 4) != hipSuccess ||
-      hipMalloc(&h->rc_code, size_t(n_codes) * 2) != hipSuccess)
+      hipMalloc(&h->rc_code, size_t(n_codes) * 2) != hipSuccess ||
+      hipMalloc(&h->rc_w16, size_t(nW) * sizeof(RcWord)) != hipSuccess)
     return DS_ERR_OOM;
   rank_bits_kernel<<<dim3((unsigned)((nW * 64 + 255) / 256)), dim3(256), 0, s>>>(h->K, h->nK, nW, h->rc_bits,
-                                                                                    h->rc_base);
+                                                                                    h->rc_base, h->rc_w16);
   DS_HIP_CHECK(hipGetLastError());
   rank_code_kernel<T, FORM><<<dim3((unsigned)((n_codes + 255) / 256)), dim3(256), 0, s>>>(
       static_cast<const T*>(h->X), h->N, n_codes, T(h->H), T(h->W), T(h->X0), h->rc_code);
@@ -306,16 +314,18 @@ ds_status build_pairs(ds_index* h, hipStream_t s) {
 }
 
 // Which layouts to build: the one the automatic launch will use (PLAIN in LDS
-// when it fits, else RANKCODE in LDS when it fits, else PAIRS through L2),
-// plus whatever the caller asked for.
+// when it fits, else RANKCODE in LDS when it fits, else RANKCODE through L2
+// while it fits one XCD's L2, else PAIRS through L2), plus whatever the caller
+// asked for.
 template <typename T>
 ds_status build_layouts(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   h->staged = tables_fit_lds(h) ? 1 : 0;
   const int64_t nW = (h->nK + 63) / 64;
   h->rc_words = nW;
   const bool rc_fits = rankcode_lds_bytes(h) <= kLdsBytesPerCU;
-  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : 4);
-  const bool want_rc = (o.extra_layouts & DS_LAYOUT_RANKCODE) || h->auto_stage == 3;
+  const int64_t rc_global_bytes = nW * int64_t(sizeof(RcWord)) + (h->N + 1) * 2;
+  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : (rc_global_bytes <= kL2BytesPerXcd ? 5 : 4));
+  const bool want_rc = (o.extra_layouts & DS_LAYOUT_RANKCODE) || h->auto_stage == 3 || h->auto_stage == 5;
   const bool want_pairs = (o.extra_layouts & DS_LAYOUT_PAIRS) || h->auto_stage == 4;
   if (want_rc) {
     ds_status st = (h->form == DS_FORM_FMA) ? build_rankcode<T, DS_FORM_FMA>(h, s) : build_rankcode<T, DS_FORM_SUB>(h, s);
@@ -435,6 +445,8 @@ void free_layouts(ds_index* h) {
   if (h->rc_bits) (void)hipFree(h->rc_bits);
   if (h->rc_base) (void)hipFree(h->rc_base);
   if (h->rc_code) (void)hipFree(h->rc_code);
+  if (h->rc_w16) (void)hipFree(h->rc_w16);
+  h->rc_w16 = nullptr;
   if (h->pairs) (void)hipFree(h->pairs);
   h->rc_bits = nullptr;
   h->rc_base = nullptr;

@@ -13,6 +13,7 @@
 namespace ds {
 
 constexpr int kLdsBytesPerCU = 160 * 1024;     // gfx950 LDS per compute unit (and per workgroup)
+constexpr int64_t kL2BytesPerXcd = int64_t(4) << 20;  // MI355X L2 per XCD
 constexpr int64_t kDefaultTableCap = int64_t(4) << 30;
 constexpr double kTwoPowQ = 2147483648.0;       // Q = 31: grid indices are int32
 
@@ -95,6 +96,14 @@ struct alignas(16) CachePair<double> {
   double x;
 };
 
+// one 64-cell word of the RANKCODE bitmap with its running count, for the
+// layout read through L2 (one 16-byte gather per query)
+struct alignas(16) RcWord {
+  uint64_t bits;
+  uint32_t base;
+  uint32_t pad;
+};
+
 template <typename T>
 struct DirectArgs {
   const T* X;         // N+1 values (global)
@@ -110,6 +119,7 @@ struct DirectArgs {
   const uint64_t* rc_bits;   // nW words, bit b of word w: cell jmin + 64 w + b holds an X_i
   const uint32_t* rc_base;   // nW counts: #{i : f(X_i) < jmin + 64 w}
   const uint16_t* rc_code;   // N+1 codes (allocation padded to a multiple of 8)
+  const RcWord* rc_w16;      // nW interleaved words (bits, base)
   int32_t nW;
   int32_t pad_;
   // PAIRS layout
@@ -157,6 +167,7 @@ struct ds_index {
   uint64_t* rc_bits = nullptr;
   uint32_t* rc_base = nullptr;
   uint16_t* rc_code = nullptr;
+  ds::RcWord* rc_w16 = nullptr;
   int64_t rc_words = 0;
   // PAIRS layout
   void* pairs = nullptr;

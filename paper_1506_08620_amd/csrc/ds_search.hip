@@ -104,10 +104,11 @@ struct DirectOp {
 // codes of z and X_t: a strict difference decides, equal codes decide when X_t
 // is the first float of its code class, and only the remaining case reads X_t.
 // The last two lines give -1 below X_0 (and for NaN) and N at or above X_N.
-template <typename T, int FORM>
+template <typename T, int FORM, bool INTERLEAVED>
 struct RankCodeOp {
   const uint64_t* bits;
   const uint32_t* base;
+  const RcWord* w16;  // INTERLEAVED: (bits, base) of a word in one 16-byte load
   const uint16_t* code;
   const T* Xg;  // X in global memory, for the rare undecided compare
   T H, W, X0, vlo, vhi, XN;
@@ -118,8 +119,17 @@ struct RankCodeOp {
     const int32_t e = static_cast<int32_t>(jf) - jmin;
     const int32_t w = e >> 6;
     const uint32_t b = static_cast<uint32_t>(e) & 63u;
-    const uint64_t word = bits[w];
-    const int32_t t = static_cast<int32_t>(base[w]) + __popcll(word & ((uint64_t(1) << b) - 1));
+    uint64_t word;
+    uint32_t wbase;
+    if constexpr (INTERLEAVED) {
+      const RcWord rw = w16[w];
+      word = rw.bits;
+      wbase = rw.base;
+    } else {
+      word = bits[w];
+      wbase = base[w];
+    }
+    const int32_t t = static_cast<int32_t>(wbase) + __popcll(word & ((uint64_t(1) << b) - 1));
     const bool occupied = (word >> b) & 1u;
     const int32_t c = code[t];
     const T cz = cell_code<T>(v, jf);
@@ -161,7 +171,7 @@ __host__ __device__ constexpr int64_t rankcode_offsets(int64_t nW, int64_t n_cod
 }
 
 // STAGE 1: PLAIN in LDS; 2: PLAIN through L1/L2; 3: RANKCODE in LDS;
-// 4: PAIRS through L1/L2.
+// 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2.
 template <typename T, int FORM, int STAGE, int U, bool VEC>
 __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -186,9 +196,15 @@ __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
     stage_bytes(smem + base_off, reinterpret_cast<const unsigned char*>(a.rc_base), int64_t(a.nW) * 4);
     stage_bytes(smem + code_off, reinterpret_cast<const unsigned char*>(a.rc_code), code_bytes);
     __syncthreads();
-    RankCodeOp<T, FORM> op{reinterpret_cast<const uint64_t*>(smem), reinterpret_cast<const uint32_t*>(smem + base_off),
-                           reinterpret_cast<const uint16_t*>(smem + code_off), a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN,
-                           a.jmin, a.N};
+    RankCodeOp<T, FORM, false> op{reinterpret_cast<const uint64_t*>(smem),
+                                  reinterpret_cast<const uint32_t*>(smem + base_off),
+                                  nullptr,
+                                  reinterpret_cast<const uint16_t*>(smem + code_off),
+                                  a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
+    stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+  } else if constexpr (STAGE == 5) {
+    RankCodeOp<T, FORM, true> op{nullptr, nullptr, a.rc_w16, a.rc_code, a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN,
+                                 a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else {
     PairsOp<T, FORM> op{a.pairs - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
@@ -282,11 +298,27 @@ int resident_blocks(KernelT kernel, int block, int lds) {
   return per_cu * num_cus();
 }
 
+// Default launch shape per layout and precision, from a sweep of block size
+// and vectors per lane on MI355X (2^26 queries of the N sweep).
+void default_shape(const ds_index* h, int stage, int* block, int* unroll) {
+  const bool f32 = h->dt == DS_F32;
+  switch (stage) {
+    case 1: *block = 256; *unroll = f32 ? 4 : 2; return;
+    case 3: {
+      const bool one_wg_per_cu = lds_bytes_needed(h, 3) > kLdsBytesPerCU / 2;
+      *block = 1024;
+      *unroll = (one_wg_per_cu && f32) ? 4 : 1;
+      return;
+    }
+    case 4: *block = f32 ? 256 : 1024; *unroll = f32 ? 4 : 1; return;
+    case 5: *block = 512; *unroll = 2; return;
+    default: *block = 512; *unroll = 2; return;
+  }
+}
+
 Shape pick_shape(const ds_index* h, int64_t M) {
   Shape sh{};
   const ds_tune& t = h->tune;
-  sh.block = (h->tune_set && t.block) ? t.block : 512;
-  sh.unroll = (h->tune_set && t.unroll) ? t.unroll : 2;
   if (h->tune_set && t.stage) {
     sh.stage = t.stage;
   } else if (h->method == DS_METHOD_DIRECT) {
@@ -294,6 +326,10 @@ Shape pick_shape(const ds_index* h, int64_t M) {
   } else {
     sh.stage = h->staged ? 1 : 2;
   }
+  int block = 512, unroll = 2;
+  if (h->method == DS_METHOD_DIRECT) default_shape(h, sh.stage, &block, &unroll);
+  sh.block = (h->tune_set && t.block) ? t.block : block;
+  sh.unroll = (h->tune_set && t.unroll) ? t.unroll : unroll;
   sh.grid = (h->tune_set && t.grid) ? t.grid : 0;
   (void)M;
   return sh;
@@ -336,6 +372,9 @@ ds_status dispatch_direct(const DirectArgs<T>& a, const Shape& sh, bool vec, int
     case 4:
       return vec ? dispatch_direct_u<T, FORM, 4, true>(a, sh, 0, items, s)
                  : dispatch_direct_u<T, FORM, 4, false>(a, sh, 0, items, s);
+    case 5:
+      return vec ? dispatch_direct_u<T, FORM, 5, true>(a, sh, 0, items, s)
+                 : dispatch_direct_u<T, FORM, 5, false>(a, sh, 0, items, s);
     default:
       return vec ? dispatch_direct_u<T, FORM, 2, true>(a, sh, 0, items, s)
                  : dispatch_direct_u<T, FORM, 2, false>(a, sh, 0, items, s);
@@ -390,6 +429,7 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
     a.rc_bits = h->rc_bits;
     a.rc_base = h->rc_base;
     a.rc_code = h->rc_code;
+    a.rc_w16 = h->rc_w16;
     a.nW = static_cast<int32_t>(h->rc_words);
     a.pairs = static_cast<const CachePair<T>*>(h->pairs);
     a.z = static_cast<const T*>(z);
@@ -437,6 +477,65 @@ ds_status ds_search(ds_handle h, const void* z_dev, int64_t M, int32_t* out_dev,
   return ds::launch_search(h, z_dev, M, out_dev, s);
 }
 
+ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_dev, hipStream_t s, ds_tune* best) {
+  if (!h || !z_dev || !out_dev || M <= 0) return DS_ERR_ARG;
+  if (h->method == DS_METHOD_LEARNED) return DS_ERR_UNSUPPORTED;
+  const int64_t m = std::min<int64_t>(M, int64_t(1) << 24);
+  int stages[5];
+  int n_stages = 0;
+  if (h->method == DS_METHOD_DIRECT) {
+    if (h->staged) stages[n_stages++] = 1;
+    if (h->rc_code && ds::rankcode_lds_bytes(h) <= ds::kLdsBytesPerCU) stages[n_stages++] = 3;
+    if (h->rc_w16) stages[n_stages++] = 5;
+    if (h->pairs) stages[n_stages++] = 4;
+    stages[n_stages++] = 2;
+  } else {
+    if (h->staged) stages[n_stages++] = 1;
+    stages[n_stages++] = 2;
+  }
+  const ds_tune saved = h->tune;
+  const bool saved_set = h->tune_set;
+  hipEvent_t e0, e1;
+  DS_HIP_CHECK(hipEventCreate(&e0));
+  DS_HIP_CHECK(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  ds_tune best_t{};
+  ds_status st = DS_OK;
+  const int blocks[3] = {256, 512, 1024};
+  const int unrolls[3] = {1, 2, 4};
+  for (int si = 0; si < n_stages && st == DS_OK; ++si) {
+    for (int bi = 0; bi < 3 && st == DS_OK; ++bi) {
+      for (int ui = 0; ui < 3 && st == DS_OK; ++ui) {
+        ds_tune cand{blocks[bi], unrolls[ui], stages[si], 0};
+        h->tune = cand;
+        h->tune_set = true;
+        st = ds::launch_search(h, z_dev, m, out_dev, s);  // warm-up
+        if (st != DS_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = DS_ERR_HIP; break; }
+        for (int r = 0; r < 3 && st == DS_OK; ++r) st = ds::launch_search(h, z_dev, m, out_dev, s);
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = DS_ERR_HIP; break; }
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = DS_ERR_HIP; break; }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_t = cand;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != DS_OK) {
+    h->tune = saved;
+    h->tune_set = saved_set;
+    return st;
+  }
+  h->tune = best_t;
+  h->tune_set = true;
+  if (best) *best = best_t;
+  return DS_OK;
+}
+
 ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   if (!h) return DS_ERR_ARG;
   if (!t) {
@@ -446,7 +545,8 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   }
   if (t->block != 0 && (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)) return DS_ERR_ARG;
   if (t->unroll != 0 && t->unroll != 1 && t->unroll != 2 && t->unroll != 4) return DS_ERR_ARG;
-  if (t->stage < 0 || t->stage > 4) return DS_ERR_ARG;
+  if (t->stage < 0 || t->stage > 5) return DS_ERR_ARG;
+  if (t->stage == 5 && !h->rc_w16) return DS_ERR_ARG;
   if (t->stage == 1 && !h->staged) return DS_ERR_ARG;
   if (t->stage >= 3 && h->method != DS_METHOD_DIRECT) return DS_ERR_ARG;
   if (t->stage == 3 && (!h->rc_code || ds::rankcode_lds_bytes(h) > ds::kLdsBytesPerCU)) return DS_ERR_ARG;

@@ -137,6 +137,8 @@ def _stages(idx):
         st.append(3)
     if inf["pairs_bytes"]:
         st.append(4)
+    if inf["rankcode_bytes"]:
+        st.append(5)
     return tuple(sorted(st))
 
 
@@ -151,7 +153,7 @@ def test_every_launch_shape_gives_the_same_answer(ds, dtype):
             z_d = _dev(z)
             stages = _stages(idx)
             if method == "direct":
-                assert 4 in stages and (3 in stages) == (n <= 65536)
+                assert 4 in stages and 5 in stages and (3 in stages) == (n <= 65536)
             for stage in stages:
                 for block in (64, 256, 1024):
                     for unroll in (1, 2, 4):
@@ -160,6 +162,20 @@ def test_every_launch_shape_gives_the_same_answer(ds, dtype):
                             got = ds.search(idx, z_d).cpu().numpy()
                             _assert_same(got, ref)
             idx.clear_tune()
+
+
+def test_autotune_keeps_results(ds):
+    for dt in (np.float32, np.float64):
+        for n in (16, 65536, 1 << 20):
+            X = W.sweep_array(n, dt)
+            z_d = W.sweep_queries_torch(1 << 21, dt, DEV, stream=5)
+            idx = ds.build(_dev(X), layouts=("rankcode", "pairs"))
+            ref = ds.search(idx, z_d).clone()
+            best = idx.autotune(z_d)
+            assert best["stage"] in _stages(idx)
+            assert torch.equal(ds.search(idx, z_d), ref)
+            zs = z_d[:100_000].cpu().numpy()
+            _assert_same(ref[:100_000].cpu().numpy(), oracle.search(X, zs))
 
 
 @pytest.mark.parametrize("form", ["sub", "fma"])
