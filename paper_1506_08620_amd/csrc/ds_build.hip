@@ -314,17 +314,16 @@ ds_status build_pairs(ds_index* h, hipStream_t s) {
 }
 
 // Which layouts to build: the one the automatic launch will use (PLAIN in LDS
-// when it fits, else RANKCODE in LDS when it fits, else RANKCODE through L2
-// while it fits one XCD's L2, else PAIRS through L2), plus whatever the caller
-// asked for.
+// when it fits, else RANKCODE in LDS when it fits, else RANKCODE through L2,
+// which measured about twice as fast as PAIRS through L2 at N = 2^20..2^21),
+// plus whatever the caller asked for.
 template <typename T>
 ds_status build_layouts(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   h->staged = tables_fit_lds(h) ? 1 : 0;
   const int64_t nW = (h->nK + 63) / 64;
   h->rc_words = nW;
   const bool rc_fits = rankcode_lds_bytes(h) <= kLdsBytesPerCU;
-  const int64_t rc_global_bytes = nW * int64_t(sizeof(RcWord)) + (h->N + 1) * 2;
-  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : (rc_global_bytes <= kL2BytesPerXcd ? 5 : 4));
+  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : 5);
   const bool want_rc = (o.extra_layouts & DS_LAYOUT_RANKCODE) || h->auto_stage == 3 || h->auto_stage == 5;
   const bool want_pairs = (o.extra_layouts & DS_LAYOUT_PAIRS) || h->auto_stage == 4;
   if (want_rc) {

@@ -131,7 +131,7 @@ struct RankCodeOp {
     }
     const int32_t t = static_cast<int32_t>(wbase) + __popcll(word & ((uint64_t(1) << b) - 1));
     const bool occupied = (word >> b) & 1u;
-    const int32_t c = code[t];
+    const int32_t c = occupied ? code[t] : 0;  // only occupied cells need the code
     const T cz = cell_code<T>(v, jf);
     const T cx = static_cast<T>(c >> 1);
     const bool first = c & 1;
