@@ -215,46 +215,58 @@ const char* ds_status_str(ds_status st);
 
 /* ------------------------------------------------------------------------
  * Batched ragged search: K independent arrays, each with its own queries,
- * built and searched by a fixed sequence of kernels with no host
- * synchronisation (capturable in a HIP graph).  Array k is
- * X_packed[x_off[k] .. x_off[k+1]) (N_k = x_off[k+1] - x_off[k] - 1 intervals,
- * N_k = -1 means an empty array) and its queries are
- * z_packed[q_off[k] .. q_off[k+1]); out_packed[q] receives the index local to
- * the query's array.  The Direct method is used per array whenever it is
- * feasible and its table fits the workspace; every other array is searched by
- * the leading-bit binary search.  Results are identical either way.
+ * built and searched by a fixed sequence of four kernels with no host
+ * synchronisation and no allocation (capturable in a HIP graph).  Array k is
+ * X_packed[x_off[k] .. x_off[k+1]) (N_k = x_off[k+1] - x_off[k] - 1 intervals)
+ * and its queries are z_packed[q_off[k] .. q_off[k+1]); out_packed[q]
+ * receives the index local to the query's array, with the out-of-domain
+ * values of ds_search.  Per array the Direct method (Sec. 4, built on the
+ * device with ComputeHR of Sec. 4.4.3, searched through the RANKCODE layout)
+ * is used whenever it is feasible and its table fits the workspace; every
+ * other array is searched with the offset binary search (Sec. 3.3).  Results
+ * are identical either way.  Special arrays: N_k = -1 (no value) gives -1 for
+ * all its queries; N_k = 0 (one value) gives -1 below X_0 and 0 otherwise; an
+ * array that is not strictly increasing or holds NaN/inf gives -2.
  */
 typedef struct ds_batch_desc {
   int32_t dtype;              /* ds_dtype */
   int32_t num_arrays;         /* K >= 0 */
-  const int64_t* x_off_dev;   /* K+1 non-decreasing offsets, x_off[0] = 0 */
-  const void* X_dev;          /* packed arrays */
-  const int64_t* q_off_dev;   /* K+1 non-decreasing offsets, q_off[0] = 0 */
-  const void* z_dev;          /* packed queries */
-  int32_t* out_dev;           /* one int32 per query */
-  void* workspace_dev;        /* device scratch of workspace_bytes */
-  size_t workspace_bytes;     /* from ds_batch_workspace_bytes */
-  int64_t total_x;            /* x_off[K] (host copy of the last offset) */
-  int64_t total_q;            /* q_off[K] */
+  const int64_t* x_off_dev;   /* K+1 non-decreasing offsets, x_off[0] = 0 (device) */
+  const void* X_dev;          /* packed arrays (device) */
+  const int64_t* q_off_dev;   /* K+1 non-decreasing offsets, q_off[0] = 0 (device) */
+  const void* z_dev;          /* packed queries (device) */
+  int32_t* out_dev;           /* one int32 per query (device) */
+  void* workspace_dev;        /* device scratch of workspace_bytes, 256-byte aligned */
+  size_t workspace_bytes;     /* at least ds_batch_workspace_bytes(K, total_x, 0) */
+  int64_t total_x;            /* x_off[K], as a host value */
+  int64_t total_q;            /* q_off[K], as a host value */
   int32_t form;               /* ds_form */
-  int32_t tile;               /* queries per work item; 0 = auto */
-  int32_t block;              /* threads per workgroup; 0 = auto */
-  int32_t lds_bytes;          /* LDS staging budget per workgroup; 0 = auto, -1 = never stage */
+  int32_t tile;               /* queries per work item; 0 = auto (2^19) */
+  int32_t block;              /* threads per search workgroup, 64..1024 step 64; 0 = auto (1024) */
+  int32_t lds_bytes;          /* LDS budget per search workgroup; 0 = auto (159 KiB), -1 = never stage */
+  int32_t qpt;                /* queries in flight per lane: 4, 8 or 16; 0 = auto (8) */
+  int32_t reserved_;
 } ds_batch_desc;
 
-/* Bytes of workspace ds_search_batched needs for K arrays holding total_x
- * values in all, with at most table_budget_entries Direct-table entries in all
- * (arrays whose table does not fit the remaining budget use binary search). */
+/* Bytes of workspace for K arrays holding total_x values in all, with room for
+ * table_budget_entries Direct grid cells in all (arrays whose table does not
+ * fit the remaining room use binary search).  0 on bad arguments. */
 size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries);
 
 /* Enqueue the batched build + search on s.  No host synchronisation, no
- * allocation.  DS_ERR_ARG for inconsistent sizes or a workspace smaller than
- * ds_batch_workspace_bytes(num_arrays, total_x, 0). */
+ * allocation; the workspace may be reused by the next call once this one has
+ * completed on s.  DS_ERR_ARG for null pointers with non-zero sizes, bad
+ * enums or launch fields, or a workspace smaller than
+ * ds_batch_workspace_bytes(num_arrays, total_x, 0).  The offsets themselves
+ * live on the device and are not checked: they must be consistent with
+ * total_x and total_q. */
 ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s);
 
-/* Per-array outcome of the last ds_search_batched on this workspace (device
- * to host copy, synchronous on s): method_host[k] = ds_method used for array
- * k (DS_METHOD_DIRECT or DS_METHOD_BSEARCH_LEADBIT), R_host[k] = its R (or -1). */
+/* Per-array outcome of the last ds_search_batched on this descriptor's
+ * workspace (a synchronous device-to-host copy on s): method_host[k] is
+ * DS_METHOD_DIRECT, DS_METHOD_BSEARCH_OFFSET, -1 (array not strictly
+ * increasing or not finite) or -2 (N_k <= 0); R_host[k] is the array's R for
+ * Direct, else -1.  Both are host arrays of K entries. */
 ds_status ds_batch_report(const ds_batch_desc* d, int32_t* method_host, int64_t* R_host, hipStream_t s);
 
 #ifdef __cplusplus

@@ -76,7 +76,8 @@ class BatchDesc(ctypes.Structure):
                 ("q_off_dev", ctypes.c_void_p), ("z_dev", ctypes.c_void_p), ("out_dev", ctypes.c_void_p),
                 ("workspace_dev", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("total_x", ctypes.c_int64), ("total_q", ctypes.c_int64), ("form", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("block", ctypes.c_int32), ("lds_bytes", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("block", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("qpt", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class DsError(RuntimeError):
@@ -275,7 +276,7 @@ class Batch:
 
     def __init__(self, x_off: torch.Tensor, X: torch.Tensor, q_off: torch.Tensor, z: torch.Tensor,
                  out: torch.Tensor | None = None, *, form: str = "sub", table_budget_entries: int | None = None,
-                 tile: int = 0, block: int = 0, lds_bytes: int = 0, total_x: int | None = None,
+                 tile: int = 0, block: int = 0, lds_bytes: int = 0, qpt: int = 0, total_x: int | None = None,
                  total_q: int | None = None):
         for t, n in ((x_off, "x_off"), (X, "X"), (q_off, "q_off"), (z, "z")):
             _check_device(t, n)
@@ -299,7 +300,7 @@ class Batch:
         self.out = out
         self.desc = BatchDesc(_dtype_code(X), k, x_off.data_ptr(), X.data_ptr(), q_off.data_ptr(), z.data_ptr(),
                               out.data_ptr(), self.workspace.data_ptr(), ws, self.total_x, self.total_q,
-                              _FORMS[form], int(tile), int(block), int(lds_bytes))
+                              _FORMS[form], int(tile), int(block), int(lds_bytes), int(qpt), 0)
         self.device = z.device
 
     def run(self, stream=None) -> torch.Tensor:
@@ -308,6 +309,9 @@ class Batch:
         if st != OK:
             raise DsError(st, "ds_search_batched")
         return self.out
+
+    def set_shape(self, tile: int = 0, block: int = 0, lds_bytes: int = 0, qpt: int = 0):
+        self.desc.tile, self.desc.block, self.desc.lds_bytes, self.desc.qpt = int(tile), int(block), int(lds_bytes), int(qpt)
 
     def report(self, stream=None):
         import numpy as np

@@ -1,10 +1,631 @@
-// Batched ragged build + search (placeholder until the batched kernels land).
-#include "ds_internal.h"
+// Batched ragged build + search: K independent arrays, each with its own
+// queries, handled by a fixed sequence of four kernels with no host
+// synchronisation and no allocation, so the whole sequence can be captured in
+// a HIP graph and replayed.
+//
+//   1. build_hr    one workgroup per array: validation, minimum rounded gap,
+//                  and ComputeHR (Sec. 4.4.3) run entirely on the device: the
+//                  workgroup finds the first pair whose cells coincide, one
+//                  lane applies the growth steps of the sequential algorithm,
+//                  and the scan resumes after that pair; passes repeat until
+//                  one changes nothing.
+//   2. plan        one workgroup: exclusive scans over the arrays of the table
+//                  words, codes and query tiles; arrays whose table would not
+//                  fit the workspace fall back to the offset binary search
+//                  (Sec. 3.3).  It also clears the tile queues.
+//   3. rankcode    one workgroup per Direct array: the RANKCODE layout (bitmap
+//                  of occupied cells, running counts, 16-bit position codes).
+//   4. search      persistent workgroups pull query tiles from one queue per
+//                  XCD (tiles of an array go to the XCD that took its first
+//                  chunk, so that XCD's L2 holds the array's tables); when the
+//                  array changes, the workgroup copies the array's tables into
+//                  LDS if they fit, else it reads them through L2.
+//
+// Every array's results are local indices with the same out-of-domain values
+// as ds_search; arrays with no value give -1, arrays with one value give -1 or
+// 0, and arrays that are not strictly increasing or hold a non-finite value
+// give -2 for all their queries.
+#include <algorithm>
+#include <limits>
+
+#include "ds_ops.h"
+
+namespace ds {
+
+namespace {
+
+constexpr int32_t kBmInvalid = -1;   // report value: X_k not strictly increasing or not finite
+constexpr int32_t kBmTrivial = -2;   // report value: N_k <= 0
+constexpr int kNumQueues = 8;        // one tile queue per XCD
+constexpr int kBuildBlock = 256;
+constexpr int kPlanBlock = 1024;
+constexpr int kMaxGrowthRounds = 4096;
+
+template <typename T>
+struct alignas(16) ArrMeta {
+  T H, W, X0, XN;
+  int64_t x_off;    // first value of the array in X_packed
+  int64_t q_off;    // first query
+  int64_t q_end;    // one past the last query
+  int64_t w_off;    // first RANKCODE word in the word pool
+  int64_t c_off;    // first code in the code pool
+  int64_t t_off;    // first tile of the array
+  int32_t N, R, jmin, nW;
+  int32_t method;   // DS_METHOD_DIRECT, DS_METHOD_BSEARCH_OFFSET, kBmInvalid, kBmTrivial
+  int32_t n_updates;
+  int32_t pad0, pad1;
+};
+
+struct PlanTotals {
+  int64_t total_tiles;
+  int64_t words_used;
+  uint32_t queue[kNumQueues];
+};
+
+struct WsLayout {
+  size_t meta, tile_off, totals, bits, base, codes, end;
+  int64_t words_budget;
+  int64_t codes_cap;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+WsLayout ws_layout(int32_t K, int64_t total_x, int64_t words_budget) {
+  WsLayout L{};
+  size_t off = 0;
+  L.meta = off;
+  off = align256(off + size_t(K) * sizeof(ArrMeta<double>));
+  L.tile_off = off;
+  off = align256(off + size_t(K + 1) * sizeof(int64_t));
+  L.totals = off;
+  off = align256(off + sizeof(PlanTotals));
+  L.codes_cap = total_x + int64_t(K) * 8 + 8;
+  L.codes = off;
+  off = align256(off + size_t(L.codes_cap) * 2);
+  L.words_budget = words_budget;
+  L.bits = off;
+  off = align256(off + size_t(words_budget) * 8);
+  L.base = off;
+  off = align256(off + size_t(words_budget) * 4);
+  L.end = off;
+  return L;
+}
+
+// largest words budget whose layout fits in a workspace of the given size
+int64_t words_budget_for(int32_t K, int64_t total_x, size_t bytes) {
+  const WsLayout L0 = ws_layout(K, total_x, 0);
+  if (bytes <= L0.end) return 0;
+  int64_t w = int64_t((bytes - L0.end) / 12);
+  while (w > 0 && ws_layout(K, total_x, w).end > bytes) w -= std::max<int64_t>(1, w / 64);
+  return std::max<int64_t>(0, w);
+}
+
+template <typename T>
+__device__ __forceinline__ T next_up_dev(T x) {
+  return std::nextafter(x, std::numeric_limits<T>::infinity());
+}
+
+// --------------------------------------------------------------------------
+// 1. per-array ComputeHR
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __restrict__ x_off,
+                                                               const int64_t* __restrict__ q_off,
+                                                               const T* __restrict__ Xp, ArrMeta<T>* __restrict__ meta) {
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ T s_min[kBuildBlock];
+  __shared__ uint32_t s_flags[kBuildBlock];
+  __shared__ int64_t s_first[kBuildBlock];
+  __shared__ T s_H, s_W;
+  __shared__ int s_state;  // 0 continue, 1 infeasible
+  const int64_t xo = x_off[k];
+  const int64_t n_vals = x_off[k + 1] - xo;
+  const int64_t N = n_vals - 1;
+  const T* X = Xp + xo;
+  ArrMeta<T> m{};
+  m.x_off = xo;
+  m.q_off = q_off[k];
+  m.q_end = q_off[k + 1];
+  m.N = static_cast<int32_t>(N);
+  if (N <= 0) {
+    if (tid == 0) {
+      m.method = kBmTrivial;
+      m.X0 = (N == 0) ? X[0] : T(0);
+      meta[k] = m;
+    }
+    return;
+  }
+  const T X0 = X[0];
+  const T XN = X[N];
+  // validation and minimum rounded gap (Sec. 4.4.2)
+  T gmin = std::numeric_limits<T>::infinity();
+  uint32_t fl = 0;
+  for (int64_t i = tid; i < N; i += kBuildBlock) {
+    const T a = X[i], b = X[i + 1];
+    if (!std::isfinite(a) || !std::isfinite(b)) fl |= 1u;
+    if (!(a < b)) fl |= 2u;
+    const T da = a - X0, db = b - X0;
+    if (!(da < db)) fl |= 4u;
+    gmin = std::fmin(gmin, db - da);
+  }
+  s_min[tid] = gmin;
+  s_flags[tid] = fl;
+  __syncthreads();
+  for (int w = kBuildBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      s_min[tid] = std::fmin(s_min[tid], s_min[tid + w]);
+      s_flags[tid] |= s_flags[tid + w];
+    }
+    __syncthreads();
+  }
+  const uint32_t flags = s_flags[0];
+  const T g = s_min[0];
+  m.X0 = X0;
+  m.XN = XN;
+  if (flags & 3u) {
+    if (tid == 0) {
+      m.method = kBmInvalid;
+      meta[k] = m;
+    }
+    return;
+  }
+  bool feasible = !(flags & 4u);
+  T H = 0, W = 0, P = 0;
+  int32_t n_updates = 0;
+  if (feasible) {
+    const T Hbar = T(1) / g;  // correctly rounded division
+    feasible = !std::isinf(Hbar);
+    H = next_up_dev(Hbar);
+    W = (FORM == DS_FORM_FMA) ? T(H * X0) : T(0);
+    feasible = feasible && grid_floor<T, FORM>(XN, H, W, X0) < T(kTwoPowQ);
+    P = next_up_dev(H) - H;
+  }
+  if (feasible) {
+    // growth passes (Sec. 4.4.3); every lane keeps H, W, P in step via LDS
+    if (tid == 0) {
+      s_H = H;
+      s_W = W;
+      s_state = 0;
+    }
+    __syncthreads();
+    int64_t i_start = 1;
+    bool changed = false;
+    for (int round = 0; round < kMaxGrowthRounds; ++round) {
+      H = s_H;
+      W = s_W;
+      int64_t first = N + 1;
+      for (int64_t i = i_start + tid; i <= N; i += kBuildBlock) {
+        if (grid_floor<T, FORM>(X[i - 1], H, W, X0) == grid_floor<T, FORM>(X[i], H, W, X0)) {
+          first = i;
+          break;
+        }
+      }
+      s_first[tid] = first;
+      __syncthreads();
+      for (int w = kBuildBlock / 2; w > 0; w >>= 1) {
+        if (tid < w) s_first[tid] = std::min(s_first[tid], s_first[tid + w]);
+        __syncthreads();
+      }
+      const int64_t bad = s_first[0];
+      __syncthreads();
+      if (bad > N) {
+        if (!changed) break;  // a whole pass without change: every pair holds
+        changed = false;
+        i_start = 1;
+        continue;
+      }
+      if (tid == 0) {
+        const T a = X[bad - 1], b = X[bad];
+        T h = s_H, ww = s_W;
+        int st = 0;
+        while (grid_floor<T, FORM>(a, h, ww, X0) == grid_floor<T, FORM>(b, h, ww, X0)) {
+          h = h + P;
+          if (FORM == DS_FORM_FMA) ww = h * X0;
+          if (!(grid_floor<T, FORM>(XN, h, ww, X0) < T(kTwoPowQ))) {
+            st = 1;
+            break;
+          }
+          P = P + P;
+          ++n_updates;
+        }
+        s_H = h;
+        s_W = ww;
+        s_state = st;
+      }
+      __syncthreads();
+      if (s_state) {
+        feasible = false;
+        break;
+      }
+      changed = true;
+      i_start = bad + 1;
+      if (round == kMaxGrowthRounds - 1) feasible = false;
+    }
+    H = s_H;
+    W = s_W;
+  }
+  if (tid == 0) {
+    if (feasible) {
+      m.H = H;
+      m.W = W;
+      m.R = static_cast<int32_t>(grid_floor<T, FORM>(XN, H, W, X0));
+      m.jmin = static_cast<int32_t>(grid_floor<T, FORM>(X0, H, W, X0));
+      const int64_t nK = int64_t(m.R) - m.jmin + 1;
+      const int64_t nW = (nK + 63) / 64;
+      m.nW = static_cast<int32_t>((nW + 3) / 4 * 4);  // keeps every array's words 16-byte aligned
+      m.method = DS_METHOD_DIRECT;
+      m.n_updates = n_updates;
+    } else {
+      m.method = DS_METHOD_BSEARCH_OFFSET;
+      m.R = -1;
+    }
+    meta[k] = m;
+  }
+}
+
+// --------------------------------------------------------------------------
+// 2. plan: scans over arrays (one workgroup)
+template <typename T>
+__global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict__ meta, int32_t K,
+                                                          int64_t* __restrict__ tile_off, PlanTotals* __restrict__ tot,
+                                                          int64_t words_budget, int64_t tile) {
+  __shared__ int64_t s_w[kPlanBlock], s_c[kPlanBlock], s_t[kPlanBlock];
+  __shared__ int64_t carry_w, carry_c, carry_t;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    carry_w = carry_c = carry_t = 0;
+  }
+  if (tid < kNumQueues) tot->queue[tid] = 0;
+  __syncthreads();
+  for (int32_t base = 0; base < K; base += kPlanBlock) {
+    const int32_t k = base + tid;
+    int64_t nw = 0, nc = 0, nt = 0;
+    if (k < K) {
+      const ArrMeta<T>& m = meta[k];
+      if (m.method == DS_METHOD_DIRECT) {
+        nw = m.nW;
+        nc = (int64_t(m.N) + 1 + 7) / 8 * 8;
+      }
+      nt = (m.q_end - m.q_off + tile - 1) / tile;
+    }
+    s_w[tid] = nw;
+    s_c[tid] = nc;
+    s_t[tid] = nt;
+    __syncthreads();
+    // inclusive Hillis-Steele scans
+    for (int d = 1; d < kPlanBlock; d <<= 1) {
+      int64_t aw = 0, ac = 0, at = 0;
+      if (tid >= d) {
+        aw = s_w[tid - d];
+        ac = s_c[tid - d];
+        at = s_t[tid - d];
+      }
+      __syncthreads();
+      s_w[tid] += aw;
+      s_c[tid] += ac;
+      s_t[tid] += at;
+      __syncthreads();
+    }
+    if (k < K) {
+      ArrMeta<T>& m = meta[k];
+      const int64_t w0 = carry_w + s_w[tid] - nw;
+      const int64_t c0 = carry_c + s_c[tid] - nc;
+      const int64_t t0 = carry_t + s_t[tid] - nt;
+      m.t_off = t0;
+      tile_off[k] = t0;
+      if (m.method == DS_METHOD_DIRECT) {
+        if (w0 + nw > words_budget) {
+          m.method = DS_METHOD_BSEARCH_OFFSET;  // table does not fit the workspace
+          m.w_off = 0;
+          m.c_off = 0;
+        } else {
+          m.w_off = w0;
+          m.c_off = c0;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == kPlanBlock - 1) {
+      carry_w += s_w[tid];
+      carry_c += s_c[tid];
+      carry_t += s_t[tid];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    tile_off[K] = carry_t;
+    tot->total_tiles = carry_t;
+    tot->words_used = carry_w;
+  }
+}
+
+// --------------------------------------------------------------------------
+// 3. per-array RANKCODE layout
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kBuildBlock) rankcode_kernel(const T* __restrict__ Xp, ArrMeta<T>* __restrict__ meta,
+                                                               unsigned long long* __restrict__ bits,
+                                                               uint32_t* __restrict__ base,
+                                                               uint16_t* __restrict__ codes, int64_t words_budget) {
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ArrMeta<T> m = meta[k];
+  if (m.method != DS_METHOD_DIRECT) return;
+  const T* X = Xp + m.x_off;
+  const int64_t N = m.N;
+  unsigned long long* wb = bits + m.w_off;
+  uint32_t* bb = base + m.w_off;
+  uint16_t* cb = codes + m.c_off;
+  const int64_t nK = int64_t(m.R) - m.jmin + 1;
+  const int64_t nWused = (nK + 63) / 64;
+  for (int64_t w = tid; w < m.nW; w += kBuildBlock) {
+    wb[w] = 0ull;
+    bb[w] = static_cast<uint32_t>(N + 1);  // padding words past the last cell
+  }
+  const int64_t n_codes = (N + 1 + 7) / 8 * 8;
+  for (int64_t i = N + 1 + tid; i < n_codes; i += kBuildBlock) cb[i] = 0;
+  __syncthreads();
+  for (int64_t i = tid; i <= N; i += kBuildBlock) {
+    const T x = X[i];
+    const T v = grid_value<T, FORM>(x, m.H, m.W, m.X0);
+    const T jf = std::floor(v);
+    const int64_t e = static_cast<int64_t>(jf) - m.jmin;
+    const int64_t eprev = (i == 0) ? -1 : static_cast<int64_t>(grid_floor<T, FORM>(X[i - 1], m.H, m.W, m.X0)) - m.jmin;
+    if (e >= 0 && e < nK) atomicOr(&wb[e >> 6], 1ull << (e & 63));
+    // running counts: words whose first cell lies in (e_{i-1}, e_i] start at i
+    for (int64_t w = (eprev + 1 + 63) / 64; w <= e / 64 && w < nWused; ++w) bb[w] = static_cast<uint32_t>(i);
+    const T c = cell_code<T>(v, jf);
+    const T p = std::nextafter(x, -std::numeric_limits<T>::infinity());
+    const T vp = grid_value<T, FORM>(p, m.H, m.W, m.X0);
+    const T jp = std::floor(vp);
+    const int first = (jp == jf && cell_code<T>(vp, jp) == c) ? 0 : 1;
+    cb[i] = static_cast<uint16_t>((static_cast<int>(c) << 1) | first);
+  }
+  (void)words_budget;
+}
+
+// --------------------------------------------------------------------------
+// 4. persistent search
+struct SearchShape {
+  int64_t tile;
+  int32_t lds_budget;  // bytes of dynamic LDS per workgroup (0: never stage)
+  int32_t chunk;       // tiles per queue chunk
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_values(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+template <typename T, int QPT, class Op>
+__device__ __forceinline__ void run_tile(const T* __restrict__ z, int32_t* __restrict__ out, int64_t q0, int64_t q1,
+                                         const Op& op) {
+  const int64_t B = blockDim.x;
+  int64_t q = q0 + threadIdx.x;
+  for (; q + (QPT - 1) * B < q1; q += QPT * B) {
+    T v[QPT];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) v[u] = __builtin_nontemporal_load(z + q + u * B);
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) __builtin_nontemporal_store(op(v[u]), out + q + u * B);
+  }
+  for (; q < q1; q += B) out[q] = op(z[q]);
+}
+
+template <typename T, int FORM, int QPT>
+__global__ void __launch_bounds__(1024) batch_search_kernel(const ArrMeta<T>* __restrict__ meta, int32_t K,
+                                                            const int64_t* __restrict__ tile_off,
+                                                            PlanTotals* __restrict__ tot, const T* __restrict__ Xp,
+                                                            const unsigned long long* __restrict__ bits,
+                                                            const uint32_t* __restrict__ base,
+                                                            const uint16_t* __restrict__ codes,
+                                                            const T* __restrict__ z, int32_t* __restrict__ out,
+                                                            SearchShape sh) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int64_t s_tile;
+  __shared__ int32_t s_k;
+  const int queue = blockIdx.x % kNumQueues;
+  const int64_t total = tot->total_tiles;
+  int32_t cur = -1;
+  bool staged = false;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int64_t li = atomicAdd(&tot->queue[queue], 1u);
+      const int64_t ch = sh.chunk;
+      const int64_t g = ((li / ch) * kNumQueues + queue) * ch + (li % ch);
+      int32_t k = -1;
+      if (g < total) {
+        // last array whose first tile is <= g
+        int32_t lo = 0, hi = K - 1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (tile_off[mid] <= g)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        k = lo;
+      }
+      s_tile = g;
+      s_k = k;
+    }
+    __syncthreads();
+    const int64_t g = s_tile;
+    const int32_t k = s_k;
+    __syncthreads();  // s_tile is rewritten in the next round
+    if (g >= total) break;
+    const ArrMeta<T>& m = meta[k];
+    const int64_t q0 = m.q_off + (g - m.t_off) * sh.tile;
+    const int64_t q1 = std::min(m.q_end, q0 + sh.tile);
+    const int64_t N = m.N;
+    if (m.method == DS_METHOD_DIRECT) {
+      const int64_t nW = m.nW;
+      const int64_t code_bytes = round16((N + 1) * 2);
+      const int64_t base_off = round16(nW * 8);
+      const int64_t code_off = base_off + round16(nW * 4);
+      const bool fits = code_off + code_bytes <= sh.lds_budget;
+      if (k != cur) {
+        if (fits) {
+          __syncthreads();
+          stage_bytes(smem, reinterpret_cast<const unsigned char*>(bits + m.w_off), nW * 8);
+          stage_bytes(smem + base_off, reinterpret_cast<const unsigned char*>(base + m.w_off), nW * 4);
+          stage_bytes(smem + code_off, reinterpret_cast<const unsigned char*>(codes + m.c_off), code_bytes);
+          __syncthreads();
+        }
+        cur = k;
+        staged = fits;
+      }
+      const T vlo = T(m.jmin), vhi = T(m.R);
+      if (staged) {
+        RankCodeOp<T, FORM, false> op{reinterpret_cast<const uint64_t*>(smem),
+                                      reinterpret_cast<const uint32_t*>(smem + base_off), nullptr,
+                                      reinterpret_cast<const uint16_t*>(smem + code_off), Xp + m.x_off, m.H, m.W,
+                                      m.X0, vlo, vhi, m.XN, m.jmin, m.N};
+        run_tile<T, QPT>(z, out, q0, q1, op);
+      } else {
+        RankCodeOp<T, FORM, false> op{reinterpret_cast<const uint64_t*>(bits + m.w_off), base + m.w_off, nullptr,
+                                      codes + m.c_off, Xp + m.x_off, m.H, m.W, m.X0, vlo, vhi, m.XN, m.jmin, m.N};
+        run_tile<T, QPT>(z, out, q0, q1, op);
+      }
+    } else if (m.method == DS_METHOD_BSEARCH_OFFSET) {
+      const bool fits = (N + 1) * int64_t(sizeof(T)) <= sh.lds_budget;
+      if (k != cur) {
+        if (fits) {
+          __syncthreads();
+          stage_values(reinterpret_cast<T*>(smem), Xp + m.x_off, N + 1);
+          __syncthreads();
+        }
+        cur = k;
+        staged = fits;
+      }
+      const int32_t F = static_cast<int32_t>((N + 1) / 2);
+      const int32_t S = static_cast<int32_t>(N + 1 - F);
+      int32_t J = 0;
+      while ((int64_t(1) << (J + 1)) <= N + 1) ++J;
+      OffsetOp<T> op{staged ? reinterpret_cast<const T*>(smem) : Xp + m.x_off, F, S, J};
+      run_tile<T, QPT>(z, out, q0, q1, op);
+    } else {
+      const int32_t fill = (m.method == kBmInvalid) ? -2 : -1;
+      const bool one = (m.method == kBmTrivial && N == 0);
+      const T x0 = m.X0;
+      for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) out[q] = (one && z[q] >= x0) ? 0 : fill;
+    }
+  }
+}
+
+template <typename T, int FORM, int QPT>
+ds_status launch_search_kernel(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws, const SearchShape& sh,
+                               int block, hipStream_t s) {
+  auto kern = batch_search_kernel<T, FORM, QPT>;
+  const int lds = sh.lds_budget;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  int grid = per_cu * num_cus();
+  grid = std::max(kNumQueues, grid / kNumQueues * kNumQueues);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, reinterpret_cast<const ArrMeta<T>*>(ws + L.meta),
+                     d->num_arrays, reinterpret_cast<const int64_t*>(ws + L.tile_off),
+                     reinterpret_cast<PlanTotals*>(ws + L.totals), static_cast<const T*>(d->X_dev),
+                     reinterpret_cast<const unsigned long long*>(ws + L.bits),
+                     reinterpret_cast<const uint32_t*>(ws + L.base), reinterpret_cast<const uint16_t*>(ws + L.codes),
+                     static_cast<const T*>(d->z_dev), d->out_dev, sh);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+template <typename T, int FORM>
+ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
+  const int32_t K = d->num_arrays;
+  unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
+  const int64_t wb = words_budget_for(K, d->total_x, d->workspace_bytes);
+  const WsLayout L = ws_layout(K, d->total_x, wb);
+  const int64_t tile = d->tile > 0 ? d->tile : (int64_t(1) << 19);
+  auto* meta = reinterpret_cast<ArrMeta<T>*>(ws + L.meta);
+  build_hr_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(d->x_off_dev, d->q_off_dev,
+                                                                  static_cast<const T*>(d->X_dev), meta);
+  DS_HIP_CHECK(hipGetLastError());
+  plan_kernel<T><<<dim3(1), dim3(kPlanBlock), 0, s>>>(meta, K, reinterpret_cast<int64_t*>(ws + L.tile_off),
+                                                       reinterpret_cast<PlanTotals*>(ws + L.totals), wb, tile);
+  DS_HIP_CHECK(hipGetLastError());
+  rankcode_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(
+      static_cast<const T*>(d->X_dev), meta, reinterpret_cast<unsigned long long*>(ws + L.bits),
+      reinterpret_cast<uint32_t*>(ws + L.base), reinterpret_cast<uint16_t*>(ws + L.codes), wb);
+  DS_HIP_CHECK(hipGetLastError());
+  if (d->total_q == 0) return DS_OK;
+  SearchShape sh{};
+  sh.tile = tile;
+  sh.lds_budget = d->lds_bytes < 0 ? 0 : (d->lds_bytes > 0 ? std::min(d->lds_bytes, kLdsBytesPerCU - 1024)
+                                                            : kLdsBytesPerCU - 1024);
+  sh.chunk = 4;
+  const int block = d->block > 0 ? d->block : 1024;
+  const int qpt = d->qpt > 0 ? d->qpt : 8;
+  switch (qpt) {
+    case 4: return launch_search_kernel<T, FORM, 4>(d, L, ws, sh, block, s);
+    case 16: return launch_search_kernel<T, FORM, 16>(d, L, ws, sh, block, s);
+    default: return launch_search_kernel<T, FORM, 8>(d, L, ws, sh, block, s);
+  }
+}
+
+}  // namespace
+
+}  // namespace ds
 
 extern "C" {
 
-size_t ds_batch_workspace_bytes(int32_t, int64_t, int64_t) { return 0; }
-ds_status ds_search_batched(const ds_batch_desc*, hipStream_t) { return DS_ERR_UNSUPPORTED; }
-ds_status ds_batch_report(const ds_batch_desc*, int32_t*, int64_t*, hipStream_t) { return DS_ERR_UNSUPPORTED; }
+size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries) {
+  if (num_arrays < 0 || total_x < 0 || table_budget_entries < 0) return 0;
+  // each array's words are rounded up to a multiple of 4, plus one partial word
+  const int64_t words = table_budget_entries > 0 ? table_budget_entries / 64 + int64_t(num_arrays) * 4 + 16 : 0;
+  return ds::ws_layout(num_arrays, total_x, words).end;
+}
+
+ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s) {
+  if (!d) return DS_ERR_ARG;
+  if (d->dtype != DS_F32 && d->dtype != DS_F64) return DS_ERR_ARG;
+  if (d->form != DS_FORM_SUB && d->form != DS_FORM_FMA) return DS_ERR_ARG;
+  if (d->num_arrays < 0 || d->total_x < 0 || d->total_q < 0) return DS_ERR_ARG;
+  if (d->num_arrays == 0) return DS_OK;
+  if (!d->x_off_dev || !d->q_off_dev || !d->workspace_dev) return DS_ERR_ARG;
+  if (d->total_x > 0 && !d->X_dev) return DS_ERR_ARG;
+  if (d->total_q > 0 && (!d->z_dev || !d->out_dev)) return DS_ERR_ARG;
+  if (d->block != 0 && (d->block < 64 || d->block > 1024 || d->block % 64)) return DS_ERR_ARG;
+  if (d->qpt != 0 && d->qpt != 4 && d->qpt != 8 && d->qpt != 16) return DS_ERR_ARG;
+  if (d->tile < 0) return DS_ERR_ARG;
+  if (d->workspace_bytes < ds_batch_workspace_bytes(d->num_arrays, d->total_x, 0)) return DS_ERR_ARG;
+  if (d->dtype == DS_F32)
+    return d->form == DS_FORM_FMA ? ds::run_batched<float, DS_FORM_FMA>(d, s) : ds::run_batched<float, DS_FORM_SUB>(d, s);
+  return d->form == DS_FORM_FMA ? ds::run_batched<double, DS_FORM_FMA>(d, s) : ds::run_batched<double, DS_FORM_SUB>(d, s);
+}
+
+ds_status ds_batch_report(const ds_batch_desc* d, int32_t* method_host, int64_t* R_host, hipStream_t s) {
+  if (!d || d->num_arrays < 0) return DS_ERR_ARG;
+  if (d->num_arrays == 0) return DS_OK;
+  if (!method_host || !R_host || !d->workspace_dev) return DS_ERR_ARG;
+  const int64_t wb = ds::words_budget_for(d->num_arrays, d->total_x, d->workspace_bytes);
+  const ds::WsLayout L = ds::ws_layout(d->num_arrays, d->total_x, wb);
+  const size_t msz = d->dtype == DS_F32 ? sizeof(ds::ArrMeta<float>) : sizeof(ds::ArrMeta<double>);
+  unsigned char* host = static_cast<unsigned char*>(std::malloc(msz * size_t(d->num_arrays)));
+  if (!host) return DS_ERR_OOM;
+  hipError_t e = hipMemcpyAsync(host, static_cast<unsigned char*>(d->workspace_dev) + L.meta,
+                                msz * size_t(d->num_arrays), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    std::free(host);
+    return DS_ERR_HIP;
+  }
+  for (int32_t k = 0; k < d->num_arrays; ++k) {
+    if (d->dtype == DS_F32) {
+      const auto* m = reinterpret_cast<const ds::ArrMeta<float>*>(host) + k;
+      method_host[k] = m->method;
+      R_host[k] = m->method == DS_METHOD_DIRECT ? m->R : -1;
+    } else {
+      const auto* m = reinterpret_cast<const ds::ArrMeta<double>*>(host) + k;
+      method_host[k] = m->method;
+      R_host[k] = m->method == DS_METHOD_DIRECT ? m->R : -1;
+    }
+  }
+  std::free(host);
+  return DS_OK;
+}
 
 }  // extern "C"

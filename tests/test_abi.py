@@ -67,3 +67,18 @@ def test_no_oracle_in_the_product():
                 assert "liboracle" not in text and "ds_oracle" not in text, f
     lib = open(LIB, "rb").read() if os.path.exists(LIB) else b""
     assert b"oracle_search" not in lib
+
+
+def test_batch_workspace_sizing_is_monotone():
+    lib = _lib()
+    lib.ds_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.ds_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+    base = lib.ds_batch_workspace_bytes(100, 10_000, 0)
+    assert base > 100 * 64
+    prev = base
+    for budget in (64, 1 << 10, 1 << 20, 1 << 30):
+        cur = lib.ds_batch_workspace_bytes(100, 10_000, budget)
+        assert cur >= prev + budget // 64 * 12 - 4096
+        prev = cur
+    assert lib.ds_batch_workspace_bytes(-1, 10, 0) == 0
+    assert lib.ds_batch_workspace_bytes(0, 0, 0) > 0

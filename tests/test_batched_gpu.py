@@ -1,0 +1,219 @@
+"""GPU parity of the batched ragged search against the CPU oracle.
+
+Each array's outputs are compared element by element with the oracle's classic
+binary search on that array; at the full size of the 10,000-array workload the
+outputs are sampled and the defining invariant is checked for every query on
+the device.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ds():
+    import paper_1506_08620_amd as mod
+
+    return mod
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _oracle_batch(x_off, X, q_off, z):
+    ref = np.empty(z.size, np.int32)
+    for k in range(x_off.size - 1):
+        xa = X[x_off[k]:x_off[k + 1]]
+        q0, q1 = q_off[k], q_off[k + 1]
+        if q1 == q0:
+            continue
+        if xa.size == 0:
+            ref[q0:q1] = -1
+        else:
+            ref[q0:q1] = oracle.search(xa, z[q0:q1])
+    return ref
+
+
+def _run(ds, b: W.Batch, **kw):
+    bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z), **kw)
+    out = bt.run().cpu().numpy()
+    return bt, out
+
+
+def _assert_same(got, ref):
+    if not np.array_equal(got, ref):
+        bad = np.flatnonzero(got != ref)
+        raise AssertionError(f"{bad.size} of {ref.size} differ; first at {bad[:5]}: got {got[bad[:5]]} "
+                             f"want {ref[bad[:5]]}")
+
+
+@pytest.mark.parametrize("form", ["sub", "fma"])
+def test_small_batch_f32(ds, form):
+    b = W.batched_f32(num_arrays=300, n_lo=8, n_hi=8192, q_per_n=16, seed=7)
+    bt, out = _run(ds, b, form=form)
+    _assert_same(out, _oracle_batch(b.x_off, b.X, b.q_off, b.z))
+    meth, R = bt.report()
+    assert np.all(meth == ds.METHOD_DIRECT)
+    # per-array R equals the oracle's ComputeHR
+    for k in range(0, 300, 37):
+        t = oracle.compute_hr(b.array(k), oracle.FORM_SUB if form == "sub" else oracle.FORM_FMA)
+        assert t.R == R[k]
+
+
+def test_batch_equals_single_array_search(ds):
+    b = W.batched_f32(num_arrays=40, n_lo=8, n_hi=65536, q_per_n=8, seed=8)
+    _, out = _run(ds, b)
+    for k in range(b.num_arrays):
+        idx = ds.build(_dev(b.array(k)))
+        single = ds.search(idx, _dev(b.queries(k))).cpu().numpy()
+        assert np.array_equal(out[b.q_off[k]:b.q_off[k + 1]], single), k
+
+
+def test_batch_f64_mixture_small(ds):
+    rng = np.random.default_rng(4)
+    arrays = [W.mixture_array(int(n), rng) for n in (100, 2000, 30000, 70000)]
+    X = np.concatenate(arrays)
+    x_off = np.concatenate([[0], np.cumsum([a.size for a in arrays])]).astype(np.int64)
+    zs = [W.mixture_queries(a, 50_000, rng) for a in arrays]
+    z = np.concatenate(zs)
+    q_off = np.concatenate([[0], np.cumsum([q.size for q in zs])]).astype(np.int64)
+    bt, out = _run(ds, W.Batch(np.dtype(np.float64), x_off, X, q_off, z))
+    _assert_same(out, _oracle_batch(x_off, X, q_off, z))
+    meth, _ = bt.report()
+    # clustered arrays are infeasible for Direct and fall back to binary search
+    assert set(meth.tolist()) <= {ds.METHOD_DIRECT, ds.METHOD_BSEARCH_OFFSET}
+
+
+def test_edge_arrays(ds):
+    f32 = np.float32
+    arrays = [
+        np.array([], f32),                       # N = -1: no value
+        np.array([5.0], f32),                    # N = 0: one value
+        np.array([0.0, 1.0], f32),               # N = 1
+        np.array([-1e9, 0.0, 1.0], f32),         # infeasible (Sec. 4.4): binary search
+        np.array([0.0, 1.42e-45, 1.0], f32),     # infeasible (overflow of 1/min gap)
+        np.array([0.0, 2.0, 1.0], f32),          # not sorted: -2
+        np.array([0.0, np.nan, 1.0], f32),       # not finite: -2
+        W.gap_array(1000, f32, np.random.default_rng(1), x0=-7.0),
+        W.gap_array(5, f32, np.random.default_rng(2)),   # no queries
+    ]
+    rng = np.random.default_rng(3)
+    zs = []
+    for k, a in enumerate(arrays):
+        if k == 8:
+            zs.append(np.array([], f32))
+            continue
+        lo, hi = (float(a[0]) - 2, float(a[-1]) + 2) if a.size else (-1, 1)
+        zz = rng.uniform(lo, hi, 3000).astype(f32)
+        extra = np.concatenate([a, W.prev_float(a, f32), np.array([np.nan, np.inf, -np.inf], f32)]) if a.size else \
+            np.array([0.0, np.nan], f32)
+        zs.append(np.concatenate([zz, extra[np.isfinite(extra) | np.isnan(extra) | np.isinf(extra)]]).astype(f32))
+    X = np.concatenate(arrays).astype(f32)
+    x_off = np.concatenate([[0], np.cumsum([a.size for a in arrays])]).astype(np.int64)
+    z = np.concatenate(zs).astype(f32)
+    q_off = np.concatenate([[0], np.cumsum([q.size for q in zs])]).astype(np.int64)
+    bt, out = _run(ds, W.Batch(np.dtype(f32), x_off, X, q_off, z))
+    meth, _ = bt.report()
+    assert meth.tolist() == [-2, -2, 0, 2, 2, -1, -1, 0, 0]
+    for k in range(len(arrays)):
+        got = out[q_off[k]:q_off[k + 1]]
+        if k in (5, 6):
+            assert np.all(got == -2)
+            continue
+        ref = _oracle_batch(x_off[k:k + 2] - x_off[k], arrays[k], q_off[k:k + 2] - q_off[k], zs[k])
+        _assert_same(got, ref)
+
+
+def test_no_table_room_uses_binary_search(ds):
+    b = W.batched_f32(num_arrays=50, n_lo=8, n_hi=20000, q_per_n=8, seed=9)
+    bt, out = _run(ds, b, table_budget_entries=0)
+    meth, _ = bt.report()
+    assert np.all(meth == ds.METHOD_BSEARCH_OFFSET)
+    _assert_same(out, _oracle_batch(b.x_off, b.X, b.q_off, b.z))
+    # partial room: a prefix of the arrays gets Direct
+    bt2, out2 = _run(ds, b, table_budget_entries=int(np.sum(np.diff(b.x_off))) // 2)
+    meth2, _ = bt2.report()
+    assert (meth2 == ds.METHOD_DIRECT).any() and (meth2 == ds.METHOD_BSEARCH_OFFSET).any()
+    _assert_same(out2, out)
+
+
+def test_every_launch_shape_gives_the_same_answer(ds):
+    b = W.batched_f32(num_arrays=120, n_lo=8, n_hi=65536, q_per_n=4, seed=10)
+    ref = _oracle_batch(b.x_off, b.X, b.q_off, b.z)
+    bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z))
+    for tile in (1000, 1 << 16, 1 << 19):
+        for block in (256, 1024):
+            for qpt in (4, 8, 16):
+                for lds in (0, -1, 40_000):
+                    bt.set_shape(tile=tile, block=block, lds_bytes=lds, qpt=qpt)
+                    out = bt.run().cpu().numpy()
+                    _assert_same(out, ref)
+
+
+def test_graph_capture_replays(ds):
+    b = W.batched_f32(num_arrays=200, n_lo=8, n_hi=65536, q_per_n=8, seed=11)
+    bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z))
+    eager = bt.run().clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bt.run()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run()
+    for r in range(4):
+        bt.out.fill_(-9)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bt.out, eager), r
+        bt.run()  # eager work between replays
+        torch.cuda.synchronize()
+    _assert_same(eager.cpu().numpy(), _oracle_batch(b.x_off, b.X, b.q_off, b.z))
+
+
+def test_full_size_batched_f32_sampled(ds):
+    """10,000 arrays, N_k log-uniform in [8, 65536], M_k = 64 N_k (about 4.5e9 queries)."""
+    b = W.batched_f32(with_queries=False)
+    total_q = int(b.q_off[-1])
+    assert total_q > 2**32  # int64 offsets are exercised
+    z = W.batched_queries_torch(b, DEV)
+    x_off_d, X_d, q_off_d = _dev(b.x_off), _dev(b.X), _dev(b.q_off)
+    bt = ds.Batch(x_off_d, X_d, q_off_d, z)
+    out = bt.run()
+    torch.cuda.synchronize()
+    meth, _ = bt.report()
+    assert np.all(meth == ds.METHOD_DIRECT)
+    # invariant X_i <= z < X_{i+1} for every query, array chunk by array chunk
+    for a in range(0, b.num_arrays, 500):
+        e = min(b.num_arrays, a + 500)
+        q0, q1 = int(b.q_off[a]), int(b.q_off[e])
+        counts = torch.from_numpy(np.diff(b.q_off[a:e + 1])).to(DEV)
+        base = torch.repeat_interleave(x_off_d[a:e], counts)
+        nk = torch.repeat_interleave(x_off_d[a + 1:e + 1] - x_off_d[a:e] - 1, counts)
+        i = out[q0:q1].long()
+        assert bool(torch.all((i >= 0) & (i < nk)))
+        zz = z[q0:q1]
+        assert bool(torch.all(X_d[base + i] <= zz)) and bool(torch.all(zz < X_d[base + i + 1]))
+        del counts, base, nk, i
+    # sampled oracle check
+    g = torch.Generator(device="cpu").manual_seed(12)
+    pos = torch.randint(0, total_q, (1 << 18,), generator=g).numpy()
+    pos.sort()
+    zs = z[torch.from_numpy(pos).to(DEV)].cpu().numpy()
+    got = out[torch.from_numpy(pos).to(DEV)].cpu().numpy()
+    ks = np.searchsorted(b.q_off, pos, side="right") - 1
+    ref = np.empty_like(got)
+    for k in np.unique(ks):
+        sel = ks == k
+        ref[sel] = oracle.search(b.array(k), zs[sel])
+    _assert_same(got, ref)

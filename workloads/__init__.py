@@ -307,3 +307,34 @@ def mixture_queries(X: np.ndarray, m: int, rng: np.random.Generator) -> np.ndarr
     z = np.concatenate([zu, zh, zb]).astype(X.dtype)
     rng.shuffle(z)
     return z
+
+
+def batched_queries_torch(batch: Batch, device, seed: int = SEED_BATCHED, chunk_arrays: int = 256):
+    """Uniform queries per array, z ~ U[X_0k, X_Nk), generated on the device with
+    torch's counter-based generator: z = X_0k + u (X_Nk - X_0k) in f64, rounded to the
+    batch dtype and kept below X_Nk.  Returns the packed query tensor."""
+    import torch
+
+    tdt = torch.float32 if batch.dtype == np.float32 else torch.float64
+    total = int(batch.q_off[-1])
+    z = torch.empty(total, dtype=tdt, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed & (2**63 - 1))
+    K = batch.num_arrays
+    lo_all = batch.X[batch.x_off[:-1]].astype(np.float64)
+    hi_all = batch.X[batch.x_off[1:] - 1].astype(np.float64)
+    hi_below = prev_float(batch.X[batch.x_off[1:] - 1], batch.dtype).astype(np.float64)
+    for a in range(0, K, chunk_arrays):
+        b = min(K, a + chunk_arrays)
+        q0, q1 = int(batch.q_off[a]), int(batch.q_off[b])
+        if q1 == q0:
+            continue
+        counts = torch.from_numpy(np.diff(batch.q_off[a:b + 1])).to(device)
+        lo = torch.repeat_interleave(torch.from_numpy(lo_all[a:b]).to(device), counts)
+        hi = torch.repeat_interleave(torch.from_numpy(hi_all[a:b]).to(device), counts)
+        top = torch.repeat_interleave(torch.from_numpy(hi_below[a:b]).to(device), counts)
+        u = torch.rand(q1 - q0, dtype=torch.float64, device=device, generator=g)
+        v = (lo + u * (hi - lo)).to(tdt)
+        z[q0:q1] = torch.minimum(torch.maximum(v, lo.to(tdt)), top.to(tdt))
+        del lo, hi, top, u, v
+    return z
