@@ -78,7 +78,7 @@ def test_batch_workspace_sizing_is_monotone():
     prev = base
     for budget in (64, 1 << 10, 1 << 20, 1 << 30):
         cur = lib.ds_batch_workspace_bytes(100, 10_000, budget)
-        assert cur >= prev + budget // 64 * 12 - 4096
+        assert cur >= prev and cur >= base + budget // 64 * 12
         prev = cur
     assert lib.ds_batch_workspace_bytes(-1, 10, 0) == 0
     assert lib.ds_batch_workspace_bytes(0, 0, 0) > 0
