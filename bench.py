@@ -38,6 +38,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true", help="skip the per-method comparison runs")
     p.add_argument("--sizes", type=str, default="", help="comma-separated subset of N (testing)")
     p.add_argument("--m", type=int, default=0, help="queries per case (default 2^26)")
+    p.add_argument("--batched", action="store_true", help="also time the 10,000-array batched workload")
     return p.parse_args()
 
 
@@ -156,6 +157,12 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = compare_methods(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
+    if args.batched:
+        for c in cases:  # free the sweep's buffers first
+            c["idx"].destroy()
+        cases.clear()
+        torch.cuda.empty_cache()
+        extras["batched_f32"] = bench_batched(ds, W, dev, stream, reps=3)
 
     line = {
         "metric": "Gqueries/s and %HBM peak: Direct vs learned vs binary search, FP32/FP64",
@@ -222,6 +229,35 @@ def compare_methods(ds, cases, M, stream, reps):
                                  same_as_direct=bool(torch.equal(out, c["out"]))))
             idx.destroy()
         del out
+    return res
+
+
+def bench_batched(ds, W, dev, stream, reps):
+    """10,000 f32 arrays, N_k log-uniform in [8, 65536], M_k = 64 N_k: one ds_search_batched
+    call (device build of every array + search), timed end to end with HIP events."""
+    import torch
+
+    b = W.batched_f32(with_queries=False)
+    z = W.batched_queries_torch(b, dev)
+    bt = ds.Batch(torch.from_numpy(b.x_off).to(dev), torch.from_numpy(b.X).to(dev),
+                  torch.from_numpy(b.q_off).to(dev), z)
+    shape = bt.autotune(stream)
+    torch.cuda.synchronize()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        bt.run(stream)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / reps
+    total_q = int(b.q_off[-1])
+    meth, _ = bt.report()
+    res = dict(arrays=b.num_arrays, total_x=int(b.x_off[-1]), total_q=total_q, ms_end_to_end=round(ms, 3),
+               gq_s_end_to_end=round(total_q / ms / 1e6, 2),
+               hbm_frac_streaming=round(total_q * 8 / ms / 1e6 / HBM_PEAK_GBS, 4),
+               direct_arrays=int((meth == ds.METHOD_DIRECT).sum()), autotuned_shape=shape)
+    del z, bt
+    torch.cuda.empty_cache()
     return res
 
 

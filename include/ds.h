@@ -262,6 +262,13 @@ size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t tab
  * total_x and total_q. */
 ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s);
 
+/* Autotuner of the batched launch: runs ds_search_batched once, then times
+ * the search phase (HIP events on s) for tile in {2^16 .. 2^20}, block in
+ * {512, 1024} and queries in flight per lane in {4, 8, 16}, and writes the
+ * fastest into d->tile, d->block and d->qpt.  Synchronises s.  out_dev holds
+ * valid results afterwards.  Same errors as ds_search_batched. */
+ds_status ds_batch_autotune(ds_batch_desc* d, hipStream_t s);
+
 /* Per-array outcome of the last ds_search_batched on this descriptor's
  * workspace (a synchronous device-to-host copy on s): method_host[k] is
  * DS_METHOD_DIRECT, DS_METHOD_BSEARCH_OFFSET, -1 (array not strictly

@@ -44,7 +44,7 @@ METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 
 # exported symbols of libds.so (every function ds.h declares)
 SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_autotune", "ds_info", "ds_copy_table", "ds_destroy", "ds_status_str",
-           "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_report")
+           "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_autotune", "ds_batch_report")
 
 
 class BuildOpts(ctypes.Structure):
@@ -111,6 +111,8 @@ def _load_library():
     lib.ds_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.ds_search_batched.argtypes = [ctypes.POINTER(BatchDesc), vp]
     lib.ds_search_batched.restype = i32
+    lib.ds_batch_autotune.argtypes = [ctypes.POINTER(BatchDesc), vp]
+    lib.ds_batch_autotune.restype = i32
     lib.ds_batch_report.argtypes = [ctypes.POINTER(BatchDesc), vp, vp, vp]
     lib.ds_batch_report.restype = i32
     return lib
@@ -309,6 +311,31 @@ class Batch:
         if st != OK:
             raise DsError(st, "ds_search_batched")
         return self.out
+
+    def autotune(self, stream=None, cache: str | None = None) -> dict:
+        """ds_batch_autotune; with cache (a JSON file path) the choice is stored under a key of
+        the device and the batch's sizes, and reused instead of re-timed."""
+        import json
+
+        key = f"{torch.cuda.get_device_name(self.device)}|{self.desc.dtype}|{self.desc.form}|" \
+              f"{self.num_arrays}|{self.total_x}|{self.total_q}"
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_shape(**table[key])
+                return table[key]
+        with torch.cuda.device(self.device):
+            st = _lib.ds_batch_autotune(ctypes.byref(self.desc), _stream_handle(stream))
+        if st != OK:
+            raise DsError(st, "ds_batch_autotune")
+        best = dict(tile=self.desc.tile, block=self.desc.block, lds_bytes=self.desc.lds_bytes, qpt=self.desc.qpt)
+        if cache:
+            table[key] = best
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return best
 
     def set_shape(self, tile: int = 0, block: int = 0, lds_bytes: int = 0, qpt: int = 0):
         self.desc.tile, self.desc.block, self.desc.lds_bytes, self.desc.qpt = int(tile), int(block), int(lds_bytes), int(qpt)

@@ -364,21 +364,43 @@ __global__ void __launch_bounds__(kBuildBlock) rankcode_kernel(const T* __restri
   const int64_t n_codes = (N + 1 + 7) / 8 * 8;
   for (int64_t i = N + 1 + tid; i < n_codes; i += kBuildBlock) cb[i] = 0;
   __syncthreads();
-  for (int64_t i = tid; i <= N; i += kBuildBlock) {
-    const T x = X[i];
-    const T v = grid_value<T, FORM>(x, m.H, m.W, m.X0);
-    const T jf = std::floor(v);
-    const int64_t e = static_cast<int64_t>(jf) - m.jmin;
-    const int64_t eprev = (i == 0) ? -1 : static_cast<int64_t>(grid_floor<T, FORM>(X[i - 1], m.H, m.W, m.X0)) - m.jmin;
-    if (e >= 0 && e < nK) atomicOr(&wb[e >> 6], 1ull << (e & 63));
-    // running counts: words whose first cell lies in (e_{i-1}, e_i] start at i
-    for (int64_t w = (eprev + 1 + 63) / 64; w <= e / 64 && w < nWused; ++w) bb[w] = static_cast<uint32_t>(i);
-    const T c = cell_code<T>(v, jf);
-    const T p = std::nextafter(x, -std::numeric_limits<T>::infinity());
-    const T vp = grid_value<T, FORM>(p, m.H, m.W, m.X0);
-    const T jp = std::floor(vp);
-    const int first = (jp == jf && cell_code<T>(vp, jp) == c) ? 0 : 1;
-    cb[i] = static_cast<uint16_t>((static_cast<int>(c) << 1) | first);
+  // Lanes of a wave hold consecutive i, so their cells (and words) are
+  // non-decreasing across the wave: a segmented OR over lanes that share a
+  // word leaves one atomic per word and wave instead of one per element.
+  const int lane = tid & 63;
+  for (int64_t i0 = 0; i0 <= N; i0 += kBuildBlock) {
+    const int64_t i = i0 + tid;
+    const bool valid = i <= N;
+    int64_t word = -1 - lane;  // distinct per invalid lane: never merges
+    unsigned long long bitv = 0;
+    if (valid) {
+      const T x = X[i];
+      const T v = grid_value<T, FORM>(x, m.H, m.W, m.X0);
+      const T jf = std::floor(v);
+      const int64_t e = static_cast<int64_t>(jf) - m.jmin;
+      const int64_t eprev =
+          (i == 0) ? -1 : static_cast<int64_t>(grid_floor<T, FORM>(X[i - 1], m.H, m.W, m.X0)) - m.jmin;
+      if (e >= 0 && e < nK) {
+        word = e >> 6;
+        bitv = 1ull << (e & 63);
+      }
+      // running counts: words whose first cell lies in (e_{i-1}, e_i] start at i
+      for (int64_t w = (eprev + 1 + 63) / 64; w <= e / 64 && w < nWused; ++w) bb[w] = static_cast<uint32_t>(i);
+      const T c = cell_code<T>(v, jf);
+      const T p = std::nextafter(x, -std::numeric_limits<T>::infinity());
+      const T vp = grid_value<T, FORM>(p, m.H, m.W, m.X0);
+      const T jp = std::floor(vp);
+      const int first = (jp == jf && cell_code<T>(vp, jp) == c) ? 0 : 1;
+      cb[i] = static_cast<uint16_t>((static_cast<int>(c) << 1) | first);
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned long long ob = __shfl_down(bitv, off, 64);
+      const long long ow = __shfl_down(static_cast<long long>(word), off, 64);
+      if (lane + off < 64 && ow == word) bitv |= ob;
+    }
+    const long long wprev = __shfl_up(static_cast<long long>(word), 1, 64);
+    const bool head = (lane == 0) || (wprev != word);
+    if (valid && head && bitv) atomicOr(&wb[word], bitv);
   }
   (void)words_budget;
 }
@@ -534,6 +556,86 @@ ds_status launch_search_kernel(const ds_batch_desc* d, const WsLayout& L, unsign
 }
 
 template <typename T, int FORM>
+ds_status launch_search_qpt(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws, const SearchShape& sh,
+                            int block, int qpt, hipStream_t s) {
+  switch (qpt) {
+    case 4: return launch_search_kernel<T, FORM, 4>(d, L, ws, sh, block, s);
+    case 16: return launch_search_kernel<T, FORM, 16>(d, L, ws, sh, block, s);
+    default: return launch_search_kernel<T, FORM, 8>(d, L, ws, sh, block, s);
+  }
+}
+
+SearchShape shape_of(const ds_batch_desc* d) {
+  SearchShape sh{};
+  sh.tile = d->tile > 0 ? d->tile : (int64_t(1) << 19);
+  sh.lds_budget = d->lds_bytes < 0 ? 0 : (d->lds_bytes > 0 ? std::min(d->lds_bytes, kLdsBytesPerCU - 1024)
+                                                            : kLdsBytesPerCU - 1024);
+  sh.chunk = 4;
+  return sh;
+}
+
+template <typename T>
+ds_status launch_plan(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws, int64_t tile, hipStream_t s) {
+  plan_kernel<T><<<dim3(1), dim3(kPlanBlock), 0, s>>>(reinterpret_cast<ArrMeta<T>*>(ws + L.meta), d->num_arrays,
+                                                       reinterpret_cast<int64_t*>(ws + L.tile_off),
+                                                       reinterpret_cast<PlanTotals*>(ws + L.totals), L.words_budget,
+                                                       tile);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+// Times the search phase for each launch shape on the arrays already built in
+// the workspace; keeps the fastest in *d.
+template <typename T, int FORM>
+ds_status autotune_batched(ds_batch_desc* d, hipStream_t s) {
+  unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
+  const WsLayout L = ws_layout(d->num_arrays, d->total_x, words_budget_for(d->num_arrays, d->total_x, d->workspace_bytes));
+  hipEvent_t e0, e1;
+  DS_HIP_CHECK(hipEventCreate(&e0));
+  DS_HIP_CHECK(hipEventCreate(&e1));
+  const int tiles[5] = {1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20};
+  const int blocks[2] = {512, 1024};
+  const int qpts[3] = {4, 8, 16};
+  float best = 1e30f;
+  ds_batch_desc bd = *d;
+  ds_status st = DS_OK;
+  for (int ti = 0; ti < 5 && st == DS_OK; ++ti) {
+    for (int bi = 0; bi < 2 && st == DS_OK; ++bi) {
+      for (int qi = 0; qi < 3 && st == DS_OK; ++qi) {
+        ds_batch_desc c = *d;
+        c.tile = tiles[ti];
+        c.block = blocks[bi];
+        c.qpt = qpts[qi];
+        const SearchShape sh = shape_of(&c);
+        float total = 0;
+        for (int r = 0; r < 2 && st == DS_OK; ++r) {
+          st = launch_plan<T>(&c, L, ws, sh.tile, s);  // re-plans the tiles and clears the queues
+          if (st != DS_OK) break;
+          if (hipEventRecord(e0, s) != hipSuccess) { st = DS_ERR_HIP; break; }
+          st = launch_search_qpt<T, FORM>(&c, L, ws, sh, c.block, c.qpt, s);
+          if (st != DS_OK) break;
+          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = DS_ERR_HIP; break; }
+          float ms = 0;
+          if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = DS_ERR_HIP; break; }
+          if (r > 0) total += ms;
+        }
+        if (st == DS_OK && total < best) {
+          best = total;
+          bd = c;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != DS_OK) return st;
+  d->tile = bd.tile;
+  d->block = bd.block;
+  d->qpt = bd.qpt;
+  return DS_OK;
+}
+
+template <typename T, int FORM>
 ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
   const int32_t K = d->num_arrays;
   unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
@@ -552,18 +654,10 @@ ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
       reinterpret_cast<uint32_t*>(ws + L.base), reinterpret_cast<uint16_t*>(ws + L.codes), wb);
   DS_HIP_CHECK(hipGetLastError());
   if (d->total_q == 0) return DS_OK;
-  SearchShape sh{};
-  sh.tile = tile;
-  sh.lds_budget = d->lds_bytes < 0 ? 0 : (d->lds_bytes > 0 ? std::min(d->lds_bytes, kLdsBytesPerCU - 1024)
-                                                            : kLdsBytesPerCU - 1024);
-  sh.chunk = 4;
+  const SearchShape sh = shape_of(d);
   const int block = d->block > 0 ? d->block : 1024;
   const int qpt = d->qpt > 0 ? d->qpt : 8;
-  switch (qpt) {
-    case 4: return launch_search_kernel<T, FORM, 4>(d, L, ws, sh, block, s);
-    case 16: return launch_search_kernel<T, FORM, 16>(d, L, ws, sh, block, s);
-    default: return launch_search_kernel<T, FORM, 8>(d, L, ws, sh, block, s);
-  }
+  return launch_search_qpt<T, FORM>(d, L, ws, sh, block, qpt, s);
 }
 
 }  // namespace
@@ -595,6 +689,17 @@ ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s) {
   if (d->dtype == DS_F32)
     return d->form == DS_FORM_FMA ? ds::run_batched<float, DS_FORM_FMA>(d, s) : ds::run_batched<float, DS_FORM_SUB>(d, s);
   return d->form == DS_FORM_FMA ? ds::run_batched<double, DS_FORM_FMA>(d, s) : ds::run_batched<double, DS_FORM_SUB>(d, s);
+}
+
+ds_status ds_batch_autotune(ds_batch_desc* d, hipStream_t s) {
+  ds_status st = ds_search_batched(d, s);  // builds every array into the workspace
+  if (st != DS_OK) return st;
+  if (d->num_arrays == 0 || d->total_q == 0) return DS_OK;
+  if (d->dtype == DS_F32)
+    return d->form == DS_FORM_FMA ? ds::autotune_batched<float, DS_FORM_FMA>(d, s)
+                                  : ds::autotune_batched<float, DS_FORM_SUB>(d, s);
+  return d->form == DS_FORM_FMA ? ds::autotune_batched<double, DS_FORM_FMA>(d, s)
+                                : ds::autotune_batched<double, DS_FORM_SUB>(d, s);
 }
 
 ds_status ds_batch_report(const ds_batch_desc* d, int32_t* method_host, int64_t* R_host, hipStream_t s) {

@@ -158,6 +158,19 @@ def test_every_launch_shape_gives_the_same_answer(ds):
                     _assert_same(out, ref)
 
 
+def test_autotune_keeps_results(ds, tmp_path):
+    b = W.batched_f32(num_arrays=150, n_lo=8, n_hi=65536, q_per_n=16, seed=13)
+    bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z))
+    ref = bt.run().cpu().numpy()
+    cache = str(tmp_path / "tune.json")
+    best = bt.autotune(cache=cache)
+    assert best["tile"] in (1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20) and best["qpt"] in (4, 8, 16)
+    assert np.array_equal(bt.run().cpu().numpy(), ref)
+    bt2 = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z))
+    assert bt2.autotune(cache=cache) == best  # served from the cache
+    _assert_same(ref, _oracle_batch(b.x_off, b.X, b.q_off, b.z))
+
+
 def test_graph_capture_replays(ds):
     b = W.batched_f32(num_arrays=200, n_lo=8, n_hi=65536, q_per_n=8, seed=11)
     bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z))
