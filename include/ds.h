@@ -92,7 +92,8 @@ typedef struct ds_build_opts {
   int32_t fallback;         /* ds_fallback */
   int64_t table_cap_bytes;  /* 0 = 4 GiB; the Direct table may not exceed it */
   /* learned method; 0 = default */
-  int32_t learn_epochs;     /* passes over the (X_i, i) pairs (default 60) */
+  int32_t learn_epochs;     /* passes over the (X_i, i) pairs (default 60); -1 = no
+                               network: route by the feature alone (the ablation) */
   int32_t learn_segments;   /* number of linear segments (default 4096) */
   float learn_rate;         /* Adam step size (default 2e-3) */
   int32_t learn_batch;      /* training pairs per step (default 8192) */
@@ -212,6 +213,32 @@ ds_status ds_destroy(ds_handle h);
 
 /* ds_status_str: static English text for a status code. */
 const char* ds_status_str(ds_status st);
+
+/* ------------------------------------------------------------------------
+ * The learned router's training and inference kernels, exposed for checking
+ * them against a reference (these callers and tooling need no handle).
+ * Parameters are 1153 floats: W1[32], b1[32], W2[32*32] (row j holds the
+ * weights into hidden unit j), b2[32], W3[32], b3; the network is
+ *   y = W3 . clamp(W2 clamp(W1 u + b1, 0, 1) + b2, 0, 1) + b3.
+ */
+
+/* Mean squared error of y(u_dev[k]) against t_dev[k] over k < batch and its
+ * gradient, by the training kernels (one sample per lane, per-workgroup sums
+ * added in a fixed order).  grad_dev: 1153 floats; loss_dev: 1 float or NULL.
+ * Synchronises s.  Allocates temporary device memory. */
+ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const float* t_dev, int32_t batch,
+                          float* grad_dev, float* loss_dev, hipStream_t s);
+
+/* y(u_dev[k]) for k < n by the search-time router (the 32x32 layer on the
+ * matrix cores).  Synchronises s.  Allocates temporary device memory. */
+ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_t n, float* y_dev, hipStream_t s);
+
+/* Trained parameters of a learned handle (params_host: capacity >= 1153
+ * floats, or NULL) and the number of queries so far that fell outside their
+ * recorded window and took the full binary search (fallbacks_host, or NULL).
+ * DS_ERR_ARG if h is not a learned handle.  Synchronises s. */
+ds_status ds_learned_model(ds_handle h, float* params_host, int32_t capacity, uint64_t* fallbacks_host,
+                           hipStream_t s);
 
 /* ------------------------------------------------------------------------
  * Batched ragged search: K independent arrays, each with its own queries,

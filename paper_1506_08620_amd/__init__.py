@@ -44,7 +44,9 @@ METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 
 # exported symbols of libds.so (every function ds.h declares)
 SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_autotune", "ds_info", "ds_copy_table", "ds_destroy", "ds_status_str",
-           "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_autotune", "ds_batch_report")
+           "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_autotune", "ds_batch_report",
+           "ds_learned_grad", "ds_learned_forward", "ds_learned_model")
+N_ROUTER_PARAMS = 1153
 
 
 class BuildOpts(ctypes.Structure):
@@ -111,6 +113,12 @@ def _load_library():
     lib.ds_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.ds_search_batched.argtypes = [ctypes.POINTER(BatchDesc), vp]
     lib.ds_search_batched.restype = i32
+    lib.ds_learned_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.ds_learned_grad.restype = i32
+    lib.ds_learned_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.ds_learned_forward.restype = i32
+    lib.ds_learned_model.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.ds_learned_model.restype = i32
     lib.ds_batch_autotune.argtypes = [ctypes.POINTER(BatchDesc), vp]
     lib.ds_batch_autotune.restype = i32
     lib.ds_batch_report.argtypes = [ctypes.POINTER(BatchDesc), vp, vp, vp]
@@ -192,6 +200,17 @@ class Index:
             raise DsError(st, "ds_autotune")
         return {name: getattr(t, name) for name, _ in Tune._fields_}
 
+    def learned_model(self, stream=None):
+        """(trained router parameters as a numpy float32 array, fallback count)."""
+        import numpy as np
+
+        p = np.empty(N_ROUTER_PARAMS, np.float32)
+        fb = ctypes.c_uint64()
+        st = _lib.ds_learned_model(self._h, p.ctypes.data, p.size, ctypes.byref(fb), _stream_handle(stream))
+        if st != OK:
+            raise DsError(st, "ds_learned_model")
+        return p, int(fb.value)
+
     def clear_tune(self):
         st = _lib.ds_set_tune(self._h, None)
         if st != OK:
@@ -265,6 +284,34 @@ def info(index: Index) -> dict:
 
 def destroy(index: Index):
     index.destroy()
+
+
+# ---- learned router kernels ----------------------------------------------------
+
+def learned_grad(params: torch.Tensor, u: torch.Tensor, t: torch.Tensor, stream=None):
+    """(loss, gradient) of the router's mean squared error by the GPU training kernels."""
+    for x, n in ((params, "params"), (u, "u"), (t, "t")):
+        _check_device(x, n)
+        if x.dtype != torch.float32:
+            raise TypeError(f"{n} must be float32")
+    g = torch.empty(N_ROUTER_PARAMS, dtype=torch.float32, device=params.device)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    st = _lib.ds_learned_grad(params.data_ptr(), u.data_ptr(), t.data_ptr(), u.numel(), g.data_ptr(),
+                              loss.data_ptr(), _stream_handle(stream))
+    if st != OK:
+        raise DsError(st, "ds_learned_grad")
+    return float(loss.item()), g
+
+
+def learned_forward(params: torch.Tensor, u: torch.Tensor, stream=None) -> torch.Tensor:
+    """y(u) by the search-time router kernel."""
+    _check_device(params, "params")
+    _check_device(u, "u")
+    y = torch.empty(u.numel(), dtype=torch.float32, device=u.device)
+    st = _lib.ds_learned_forward(params.data_ptr(), u.data_ptr(), u.numel(), y.data_ptr(), _stream_handle(stream))
+    if st != OK:
+        raise DsError(st, "ds_learned_forward")
+    return y
 
 
 # ---- batched ----------------------------------------------------------------

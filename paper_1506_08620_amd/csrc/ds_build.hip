@@ -576,6 +576,7 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   in.rankcode_bytes = h->rc_code ? (h->rc_words * 12 + (h->N + 1) * 2) : 0;
   in.pairs_bytes = h->pairs ? h->nK * int64_t(dt == DS_F32 ? 8 : 16) : 0;
   in.build_ms = ms;
+  ds::learned_fill_info(h, &in);
   *out = h;
   return DS_OK;
 }

@@ -192,5 +192,6 @@ int64_t rankcode_lds_bytes(const ds_index* h);
 ds_status learned_build(ds_index* h, const ds_build_opts* o, hipStream_t s);
 ds_status learned_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);
 void learned_free(ds_index* h);
+void learned_fill_info(const ds_index* h, ds_info_t* in);
 int num_cus();
 }  // namespace ds

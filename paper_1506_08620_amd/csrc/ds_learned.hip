@@ -1,15 +1,764 @@
-// Learned monotone CDF method (placeholder until the model kernels land).
-#include "ds_internal.h"
+// Learned replacement of the Direct table (not from the paper): a monotone CDF
+// model routes a query to one of S segments, a per-segment linear fit
+// predicts its index, recorded error bounds give a window, and a branch-free
+// binary search inside the window finds the index exactly.
+//
+// Exactness does not depend on the quality of the model:
+//   * the feature u(z) and the router y(u) are non-decreasing functions of z,
+//     evaluated by the same device code for the keys at build time and for
+//     the queries, so routing is monotone: if the keys X_a .. X_{b-1} route to
+//     segment s, every query routed to s has its index in [a-1, b-1];
+//   * the fit's prediction is non-decreasing in z too, so the key errors over
+//     [a-1, b] bound the query's index relative to the prediction;
+//   * every result is verified against X_i <= z < X_{i+1}; a failure (never
+//     expected) falls back to a full binary search and is counted.
+//
+// Network: u -> 32 -> 32 -> 1, hidden units clamp(x, 0, 1), weights kept
+// >= 0 (projected after every Adam step), so y(u) is monotone.  Training
+// minimises the mean squared error of y(u(X_i)) against i / N with
+// hand-written forward/backward kernels (one thread per sample, deterministic
+// per-workgroup partial gradients) and an Adam kernel.  At search time the
+// 32x32 layer runs on the matrix cores (v_mfma_f32_32x32x2f32), 32 queries
+// per wave and pass.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <random>
+#include <vector>
+
+#include "ds_ops.h"
 
 namespace ds {
 
-struct LearnedModel {};
+constexpr int kHid = 32;
+constexpr int kParams = 2 * kHid + kHid * kHid + kHid + kHid + 1;  // 1153
+constexpr int oW1 = 0, oB1 = 32, oW2 = 64, oB2 = 64 + 1024, oW3 = 64 + 1024 + 32, oB3 = 64 + 1024 + 64;
+constexpr int kTrainBlock = 256;
 
-ds_status learned_build(ds_index*, const ds_build_opts*, hipStream_t) { return DS_ERR_UNSUPPORTED; }
-ds_status learned_search(ds_index*, const void*, int64_t, int32_t*, hipStream_t) { return DS_ERR_UNSUPPORTED; }
+// per-segment fit: prediction p = a (z - zc) + b (relative to lo), window
+// [lo + floor(p) + dmin - 1, lo + floor(p) + dmax] clipped to [lo, hi]
+struct alignas(16) SegFit {
+  double zc;
+  float a, b;
+  int32_t dmin, dmax, lo, hi;
+};
+
+struct LearnedModel {
+  float* params = nullptr;      // kParams
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* partial = nullptr;     // per-workgroup gradients
+  float* loss_partial = nullptr;
+  float* feat = nullptr;        // u of every key
+  int32_t* route = nullptr;     // segment of every key
+  int32_t* first = nullptr;     // nseg + 1: first key of each segment
+  SegFit* segs = nullptr;
+  unsigned long long* fallbacks = nullptr;
+  int32_t nseg = 0;
+  int32_t identity = 0;         // ablation: y = u
+  double delta = 0, flo = 0, fscale = 0;
+  int64_t max_err = 0;
+  double mean_log2_window = 0;
+  double final_loss = 0;
+};
+
+namespace {
+
+using floatx16 = float __attribute__((ext_vector_type(16)));
+
+// Monotone feature of a query: the bit pattern of d = max(z - X_0, 0) + delta
+// read as an integer is a non-decreasing, roughly logarithmic function of d;
+// it is scaled to [0, 1] and rounded to f32.  Every step is non-decreasing.
+__host__ __device__ __forceinline__ float feature(double z, double X0, double delta, double flo, double fscale) {
+  double d = z - X0;
+  d = std::fmax(d, 0.0) + delta;
+  int64_t bits;
+  __builtin_memcpy(&bits, &d, 8);
+  const double f = (static_cast<double>(bits) - flo) * fscale;
+  return static_cast<float>(std::fmin(std::fmax(f, 0.0), 1.0));
+}
+
+__device__ __forceinline__ float clamp01(float x) { return std::fmin(std::fmax(x, 0.0f), 1.0f); }
+
+// Router weights held in registers by one lane.  Lane l works on query
+// q = l % 32 and on the hidden units k = 2 kk + l / 32 of layer 1; for the
+// 32x32 layer it supplies row j = l % 32 of W2 (A operand) and its own h1
+// values (B operand); the output tile D[j][q] lands in lane q + 32 ((j / 4) % 2),
+// register (j % 4) + 4 (j / 8).
+struct RouterRegs {
+  float w1[16], b1[16], w2[16], w3[16];
+  floatx16 b2;
+  float b3;
+};
+
+__device__ __forceinline__ int out_row(int r, int half) { return (r & 3) + 4 * half + 8 * (r >> 2); }
+
+__device__ void load_router(const float* __restrict__ p, RouterRegs& R) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int m = lane & 31;
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 2 * kk + half;
+    R.w1[kk] = p[oW1 + k];
+    R.b1[kk] = p[oB1 + k];
+    R.w2[kk] = p[oW2 + m * kHid + k];
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j = out_row(r, half);
+    R.b2[r] = p[oB2 + j];
+    R.w3[r] = p[oW3 + j];
+  }
+  R.b3 = p[oB3];
+}
+
+// y(u) for the query of lane l % 32; all 64 lanes must call it, and lanes l
+// and l ^ 32 must pass the same u.  Both lanes return the same y.
+__device__ __forceinline__ float router_y(float u, const RouterRegs& R) {
+  const int half = (threadIdx.x & 63) >> 5;
+  floatx16 acc = R.b2;
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const float h1 = clamp01(std::fma(R.w1[kk], u, R.b1[kk]));
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(R.w2[kk], h1, acc, 0, 0, 0);
+  }
+  float part = 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part = std::fma(R.w3[r], clamp01(acc[r]), part);
+  const float other = __shfl_xor(part, 32, 64);
+  (void)half;
+  return (part + other) + R.b3;  // a + b == b + a exactly, so both lanes agree
+}
+
+__device__ __forceinline__ int32_t segment_of(float y, int32_t nseg) {
+  const float s = std::floor(std::fmin(std::fmax(y * static_cast<float>(nseg), 0.0f), static_cast<float>(nseg - 1)));
+  return static_cast<int32_t>(s);
+}
+
+// Prediction of a segment's fit, as an index offset relative to seg.lo; the
+// same code serves the bound computation (keys) and the search (queries).
+template <typename T>
+__device__ __forceinline__ int32_t seg_predict(const SegFit& sg, T z) {
+  const float d = static_cast<float>(static_cast<double>(z) - sg.zc);
+  float p = std::fma(sg.a, d, sg.b);
+  p = std::fmin(std::fmax(p, -2.0f), static_cast<float>(sg.hi - sg.lo + 2));
+  return static_cast<int32_t>(std::floor(p));
+}
+
+// ---------------------------------------------------------------------------
+// build kernels
+
+template <typename T>
+__global__ void feature_kernel(const T* __restrict__ X, int64_t n, double X0, double delta, double flo, double fscale,
+                               float* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[i] = feature(static_cast<double>(X[i]), X0, delta, flo, fscale);
+}
+
+__device__ __forceinline__ uint32_t mix32(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return static_cast<uint32_t>(x);
+}
+
+// One training step, forward and backward, one sample per thread.  Sample j
+// of step `step` is key idx = mix(seed, step, j) mod n_keys (or, when idx_in
+// is given, idx_in[j] with its own target t_in[j] and feature u_in[j]).
+// Each workgroup writes its summed gradient to partial[blockIdx.x * kParams].
+__global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
+    const float* __restrict__ params, const float* __restrict__ feat, int64_t n_keys, uint64_t seed, int64_t step,
+    int32_t batch, const float* __restrict__ u_in, const float* __restrict__ t_in, float* __restrict__ partial,
+    float* __restrict__ loss_partial) {
+  __shared__ float sp[kParams];
+  __shared__ float s_da2[kTrainBlock][kHid + 1];
+  __shared__ float s_h1[kTrainBlock][kHid + 1];
+  __shared__ float s_small[kTrainBlock][4];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < kParams; k += kTrainBlock) sp[k] = params[k];
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * kTrainBlock + tid;
+  const bool valid = j < batch;
+  float u = 0.0f, t = 0.0f;
+  if (valid) {
+    if (u_in) {
+      u = u_in[j];
+      t = t_in[j];
+    } else {
+      const uint64_t key = seed * 0x9E3779B97F4A7C15ull + static_cast<uint64_t>(step) * 0x100000001B3ull +
+                           static_cast<uint64_t>(j);
+      const int64_t idx = static_cast<int64_t>(mix32(key) % static_cast<uint32_t>(n_keys));
+      u = feat[idx];
+      t = static_cast<float>(static_cast<double>(idx) / static_cast<double>(n_keys - 1));
+    }
+  }
+  // clamp(a) lies strictly inside (0, 1) exactly when a does, so the unit
+  // outputs alone give the derivative masks
+  float h1[kHid], h2[kHid];
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) h1[k] = clamp01(std::fma(sp[oW1 + k], u, sp[oB1 + k]));
+  float y = sp[oB3];
+  for (int jj = 0; jj < kHid; ++jj) {
+    float acc = sp[oB2 + jj];
+#pragma unroll
+    for (int k = 0; k < kHid; ++k) acc = std::fma(sp[oW2 + jj * kHid + k], h1[k], acc);
+    h2[jj] = clamp01(acc);
+    y = std::fma(sp[oW3 + jj], h2[jj], y);
+  }
+  const float inv_b = 1.0f / static_cast<float>(batch);
+  const float dy = valid ? 2.0f * (y - t) * inv_b : 0.0f;
+  const float l = valid ? (y - t) * (y - t) * inv_b : 0.0f;
+  // backward
+  float dh1[kHid];
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) dh1[k] = 0.0f;
+  for (int jj = 0; jj < kHid; ++jj) {
+    const float da2 = (h2[jj] > 0.0f && h2[jj] < 1.0f) ? dy * sp[oW3 + jj] : 0.0f;
+    s_da2[tid][jj] = da2;
+#pragma unroll
+    for (int k = 0; k < kHid; ++k) dh1[k] = std::fma(da2, sp[oW2 + jj * kHid + k], dh1[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) s_h1[tid][k] = h1[k];
+  // per-sample gradients of the small tensors: dW1, db1 (32 each), dW3 (32), db3 (1)
+  float* out = partial + (int64_t)blockIdx.x * kParams;
+  __shared__ float s_g1[kTrainBlock][kHid + 1];
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) s_g1[tid][k] = (h1[k] > 0.0f && h1[k] < 1.0f) ? dh1[k] : 0.0f;  // da1
+  __shared__ float s_h2[kTrainBlock][kHid + 1];
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) s_h2[tid][k] = h2[k];
+  s_small[tid][0] = dy;
+  s_small[tid][1] = u;
+  s_small[tid][2] = l;
+  __syncthreads();
+  // W2 gradient: G[jj][k] = sum_s da2[s][jj] h1[s][k]; 1024 outputs, 4 per thread
+  for (int o = tid; o < kHid * kHid; o += kTrainBlock) {
+    const int jj = o / kHid, k = o % kHid;
+    float g = 0.0f;
+    for (int s = 0; s < kTrainBlock; ++s) g = std::fma(s_da2[s][jj], s_h1[s][k], g);
+    out[oW2 + o] = g;
+  }
+  // the 129 + 32 small gradients, one thread each
+  if (tid < kHid) {
+    float gw1 = 0.0f, gb1 = 0.0f;
+    for (int s = 0; s < kTrainBlock; ++s) {
+      gw1 = std::fma(s_g1[s][tid], s_small[s][1], gw1);
+      gb1 += s_g1[s][tid];
+    }
+    out[oW1 + tid] = gw1;
+    out[oB1 + tid] = gb1;
+  } else if (tid < 2 * kHid) {
+    const int jj = tid - kHid;
+    float gb2 = 0.0f, gw3 = 0.0f;
+    for (int s = 0; s < kTrainBlock; ++s) {
+      gb2 += s_da2[s][jj];
+      gw3 = std::fma(s_small[s][0], s_h2[s][jj], gw3);
+    }
+    out[oB2 + jj] = gb2;
+    out[oW3 + jj] = gw3;
+  } else if (tid == 2 * kHid) {
+    float gb3 = 0.0f, ls = 0.0f;
+    for (int s = 0; s < kTrainBlock; ++s) {
+      gb3 += s_small[s][0];
+      ls += s_small[s][2];
+    }
+    out[oB3] = gb3;
+    loss_partial[blockIdx.x] = ls;
+  }
+}
+
+// Sums the per-workgroup gradients in a fixed order (deterministic), then,
+// unless grad_out is given, applies one Adam step and projects the weights
+// onto w >= 0.
+__global__ void __launch_bounds__(1024) adam_kernel(float* __restrict__ params, float* __restrict__ m,
+                                                    float* __restrict__ v, const float* __restrict__ partial,
+                                                    int32_t n_parts, float lr, float beta1, float beta2, float eps,
+                                                    int64_t t, float* __restrict__ grad_out) {
+  for (int k = threadIdx.x; k < kParams; k += blockDim.x) {
+    float g = 0.0f;
+    for (int b = 0; b < n_parts; ++b) g += partial[(int64_t)b * kParams + k];
+    if (grad_out) {
+      grad_out[k] = g;
+      continue;
+    }
+    const float mk = beta1 * m[k] + (1.0f - beta1) * g;
+    const float vk = beta2 * v[k] + (1.0f - beta2) * g * g;
+    m[k] = mk;
+    v[k] = vk;
+    const float bc1 = 1.0f - std::pow(beta1, static_cast<float>(t));
+    const float bc2 = 1.0f - std::pow(beta2, static_cast<float>(t));
+    float p = params[k] - lr * (mk / bc1) / (std::sqrt(vk / bc2) + eps);
+    const bool is_weight = (k < oB1) || (k >= oW2 && k < oB2) || (k >= oW3 && k < oB3);
+    if (is_weight) p = std::fmax(p, 0.0f);
+    params[k] = p;
+  }
+}
+
+__global__ void sum_kernel(const float* __restrict__ parts, int32_t n, float* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.0f;
+    for (int i = 0; i < n; ++i) s += parts[i];
+    *out = s;
+  }
+}
+
+// segment of every key through the search-time router (MFMA), 64 keys per wave
+__global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict__ params,
+                                                         const float* __restrict__ feat, int64_t n,
+                                                         int32_t nseg, int32_t identity, int32_t* __restrict__ route,
+                                                         float* __restrict__ y_out) {
+  RouterRegs R;
+  load_router(params, R);
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t i = wave * 64 + lane;
+  const float u_mine = i < n ? feat[i] : 1.0f;
+  const float u_other = __shfl_xor(u_mine, 32, 64);
+  float y;
+  if (identity) {
+    y = u_mine;
+  } else {
+    const float ya = router_y(half ? u_other : u_mine, R);
+    const float yb = router_y(half ? u_mine : u_other, R);
+    y = half ? yb : ya;
+  }
+  if (i < n) {
+    route[i] = segment_of(y, nseg);
+    if (y_out) y_out[i] = y;
+  }
+}
+
+// first[s] = #{i : route_i < s} for s in [0, nseg]
+__global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, int32_t nseg,
+                                 int32_t* __restrict__ first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  const int32_t prev = (i == 0) ? -1 : route[i - 1];
+  const int32_t cur = (i == n) ? nseg : route[i];
+  for (int32_t s = prev + 1; s <= cur; ++s) first[s] = static_cast<int32_t>(i);
+}
+
+// least-squares line of index against z for the keys of one segment (f64
+// sums over centred z), then the key errors over [lo, hi + 1]
+template <typename T>
+__global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, int64_t N,
+                                                      const int32_t* __restrict__ first, SegFit* __restrict__ segs) {
+  const int s = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t a = first[s], b = first[s + 1];  // keys [a, b)
+  const int64_t lo = std::max<int64_t>(0, std::min<int64_t>(a - 1, N - 1));
+  const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(b - 1, N - 1));
+  __shared__ double sd[5][256];
+  __shared__ int32_t si[2][256];
+  const int64_t c0 = (a < b) ? a : lo;
+  const double zc = static_cast<double>(X[c0]);
+  double n = 0, sz = 0, szz = 0, si_ = 0, siz = 0;
+  for (int64_t i = a + tid; i < b; i += 256) {
+    const double dz = static_cast<double>(X[i]) - zc;
+    const double di = static_cast<double>(i - lo);
+    n += 1;
+    sz += dz;
+    szz += dz * dz;
+    si_ += di;
+    siz += di * dz;
+  }
+  sd[0][tid] = n;
+  sd[1][tid] = sz;
+  sd[2][tid] = szz;
+  sd[3][tid] = si_;
+  sd[4][tid] = siz;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int q = 0; q < 5; ++q) sd[q][tid] += sd[q][tid + w];
+    __syncthreads();
+  }
+  __shared__ SegFit s_fit;
+  if (tid == 0) {
+    const double cn = sd[0][0], cz = sd[1][0], czz = sd[2][0], ci = sd[3][0], ciz = sd[4][0];
+    double slope = 0, icpt = 0;
+    if (cn >= 2) {
+      const double var = czz - cz * cz / cn;
+      const double cov = ciz - ci * cz / cn;
+      slope = (var > 0) ? cov / var : 0.0;
+      if (!(slope > 0)) slope = 0;  // monotone prediction
+      icpt = (ci - slope * cz) / cn;
+    } else if (cn == 1) {
+      icpt = ci;
+    }
+    SegFit f{};
+    f.zc = zc;
+    f.a = static_cast<float>(slope);
+    f.b = static_cast<float>(icpt);
+    f.lo = static_cast<int32_t>(lo);
+    f.hi = static_cast<int32_t>(hi);
+    s_fit = f;
+  }
+  __syncthreads();
+  const SegFit f = s_fit;
+  int32_t dmin = 1 << 30, dmax = -(1 << 30);
+  for (int64_t i = lo + tid; i <= hi + 1 && i <= N; i += 256) {
+    const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, X[i]);
+    dmin = std::min(dmin, d);
+    dmax = std::max(dmax, d);
+  }
+  si[0][tid] = dmin;
+  si[1][tid] = dmax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      si[0][tid] = std::min(si[0][tid], si[0][tid + w]);
+      si[1][tid] = std::max(si[1][tid], si[1][tid + w]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    SegFit g = f;
+    g.dmin = si[0][0];
+    g.dmax = si[1][0];
+    segs[s] = g;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// search
+
+template <typename T>
+struct LearnedArgs {
+  const T* X;
+  const float* params;
+  const SegFit* segs;
+  unsigned long long* fallbacks;
+  const T* z;
+  int32_t* out;
+  int64_t M;
+  double X0d, delta, flo, fscale;
+  T X0, XN;
+  int32_t N, nseg, identity, pad;
+};
+
+template <typename T>
+__device__ __forceinline__ int32_t finish_query(T z, float y, const LearnedArgs<T>& a, const SegFit* segs) {
+  const SegFit sg = segs[segment_of(y, a.nseg)];
+  const int32_t q = seg_predict<T>(sg, z);
+  // window [q + dmin - 1, q + dmax] relative to lo, kept inside [lo, hi]
+  int32_t L = std::min(std::max(sg.lo, sg.lo + q + sg.dmin - 1), sg.hi);
+  const int32_t U = std::min(std::max(L, sg.lo + q + sg.dmax), sg.hi);
+  int32_t n = U - L + 1;
+  // branch-free search of the largest i in [L, U] with X_i <= z
+  while (n > 1) {
+    const int32_t h = n >> 1;
+    const int32_t m = L + h;
+    const bool c = z >= a.X[m];
+    L = c ? m : L;
+    n = c ? n - h : h;
+  }
+  int32_t i = L;
+  const bool inside = (z >= a.X0) && (z < a.XN);
+  if (inside && !(a.X[i] <= z && z < a.X[i + 1])) {
+    // outside the recorded window: full search (counted; never expected)
+    atomicAdd(a.fallbacks, 1ull);
+    int32_t lo = 0, nn = a.N;
+    while (nn > 1) {
+      const int32_t h = nn >> 1;
+      const bool c = z >= a.X[lo + h];
+      lo = c ? lo + h : lo;
+      nn = c ? nn - h : h;
+    }
+    i = lo;
+  }
+  i = (z >= a.XN) ? a.N : i;
+  return (z >= a.X0) ? i : -1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.segs), int64_t(a.nseg) * sizeof(SegFit));
+  __syncthreads();
+  const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
+  RouterRegs R;
+  load_router(a.params, R);
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  for (int64_t base = wave * 64; base < a.M; base += waves * 64) {
+    const int64_t qi = base + lane;
+    const bool valid = qi < a.M;
+    const T z = valid ? __builtin_nontemporal_load(a.z + qi) : a.X0;
+    const float u_mine = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
+    float y;
+    if (a.identity) {
+      y = u_mine;
+    } else {
+      const float u_other = __shfl_xor(u_mine, 32, 64);
+      const float ya = router_y(half ? u_other : u_mine, R);
+      const float yb = router_y(half ? u_mine : u_other, R);
+      y = half ? yb : ya;
+    }
+    const int32_t i = finish_query<T>(z, y, a, segs);
+    if (valid) __builtin_nontemporal_store(i, a.out + qi);
+  }
+}
+
+template <typename T>
+ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s) {
+  LearnedModel* L = new (std::nothrow) LearnedModel();
+  if (!L) return DS_ERR_OOM;
+  h->learned = L;
+  const int64_t N = h->N;
+  const int64_t n = N + 1;
+  const T* X = static_cast<const T*>(h->X);
+  T ends[2];
+  DS_HIP_CHECK(hipMemcpyAsync(&ends[0], X, sizeof(T), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipMemcpyAsync(&ends[1], X + N, sizeof(T), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  h->X0 = ends[0];
+  h->XN = ends[1];
+  const double range = static_cast<double>(ends[1]) - static_cast<double>(ends[0]);
+  L->delta = std::max(range * 0x1p-40, 1e-300);
+  {
+    double d0 = L->delta, d1 = range + L->delta;
+    int64_t b0, b1;
+    std::memcpy(&b0, &d0, 8);
+    std::memcpy(&b1, &d1, 8);
+    L->flo = static_cast<double>(b0);
+    L->fscale = 1.0 / (static_cast<double>(b1) - L->flo);
+  }
+  const int32_t nseg = o->learn_segments > 0 ? o->learn_segments : 4096;
+  if (nseg < 1 || nseg > 8192) return DS_ERR_ARG;
+  L->nseg = nseg;
+  L->identity = (o->learn_epochs < 0) ? 1 : 0;
+  const int32_t batch = o->learn_batch > 0 ? o->learn_batch : 8192;
+  const int32_t epochs = o->learn_epochs > 0 ? o->learn_epochs : (o->learn_epochs == 0 ? 60 : 0);
+  const float lr = o->learn_rate > 0 ? o->learn_rate : 2e-3f;
+  const int32_t n_parts = (batch + kTrainBlock - 1) / kTrainBlock;
+  if (hipMalloc(&L->params, kParams * 4) != hipSuccess || hipMalloc(&L->adam_m, kParams * 4) != hipSuccess ||
+      hipMalloc(&L->adam_v, kParams * 4) != hipSuccess ||
+      hipMalloc(&L->partial, size_t(n_parts) * kParams * 4) != hipSuccess ||
+      hipMalloc(&L->loss_partial, size_t(n_parts) * 4 + 4) != hipSuccess ||
+      hipMalloc(&L->feat, size_t(n) * 4) != hipSuccess || hipMalloc(&L->route, size_t(n) * 4) != hipSuccess ||
+      hipMalloc(&L->first, size_t(nseg + 1) * 4) != hipSuccess ||
+      hipMalloc(&L->segs, size_t(nseg) * sizeof(SegFit)) != hipSuccess ||
+      hipMalloc(&L->fallbacks, 8) != hipSuccess)
+    return DS_ERR_OOM;
+  // initial weights: layer-1 ramps spread over [0, 1], layer 2 averaging them,
+  // output the mean of layer 2 (so y(u) starts as a smooth increasing curve)
+  std::vector<float> p0(kParams, 0.0f);
+  std::mt19937_64 rng(o->seed ^ 0x5EEDull);
+  std::uniform_real_distribution<float> U(0.0f, 1.0f);
+  for (int k = 0; k < kHid; ++k) {
+    const float c = (k + 0.5f) / kHid;
+    const float w = 4.0f + 4.0f * U(rng);
+    p0[oW1 + k] = w;
+    p0[oB1 + k] = 0.5f - w * c;
+  }
+  for (int j = 0; j < kHid; ++j) {
+    float sum = 0.0f;
+    for (int k = 0; k < kHid; ++k) {
+      const float w = (0.5f + U(rng)) / kHid;
+      p0[oW2 + j * kHid + k] = w;
+      sum += w;
+    }
+    p0[oB2 + j] = 0.5f - 0.5f * sum;
+    p0[oW3 + j] = 1.0f / kHid;
+  }
+  p0[oB3] = 0.0f;
+  DS_HIP_CHECK(hipMemcpyAsync(L->params, p0.data(), kParams * 4, hipMemcpyHostToDevice, s));
+  std::vector<float> zeros(kParams, 0.0f);
+  DS_HIP_CHECK(hipMemcpyAsync(L->adam_m, zeros.data(), kParams * 4, hipMemcpyHostToDevice, s));
+  DS_HIP_CHECK(hipMemcpyAsync(L->adam_v, zeros.data(), kParams * 4, hipMemcpyHostToDevice, s));
+  const unsigned long long zero = 0;
+  DS_HIP_CHECK(hipMemcpyAsync(L->fallbacks, &zero, 8, hipMemcpyHostToDevice, s));
+  feature_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, n, static_cast<double>(ends[0]),
+                                                                             L->delta, L->flo, L->fscale, L->feat);
+  DS_HIP_CHECK(hipGetLastError());
+  // training: epochs passes of n / batch steps, cosine-decayed step size
+  const int64_t steps = L->identity ? 0 : std::max<int64_t>(1, int64_t(epochs) * ((n + batch - 1) / batch));
+  for (int64_t st = 0; st < steps; ++st) {
+    train_step_kernel<<<dim3(n_parts), dim3(kTrainBlock), 0, s>>>(L->params, L->feat, n, o->seed, st, batch, nullptr,
+                                                                  nullptr, L->partial, L->loss_partial);
+    const float frac = static_cast<float>(st) / static_cast<float>(steps);
+    const float lr_t = lr * (0.05f + 0.95f * 0.5f * (1.0f + std::cos(3.14159265f * frac)));
+    adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(L->params, L->adam_m, L->adam_v, L->partial, n_parts, lr_t, 0.9f,
+                                               0.999f, 1e-8f, st + 1, nullptr);
+  }
+  DS_HIP_CHECK(hipGetLastError());
+  if (steps > 0) {
+    float* dloss = L->loss_partial + n_parts;
+    sum_kernel<<<1, 64, 0, s>>>(L->loss_partial, n_parts, dloss);
+    float fl = 0;
+    DS_HIP_CHECK(hipMemcpyAsync(&fl, dloss, 4, hipMemcpyDeviceToHost, s));
+    DS_HIP_CHECK(hipStreamSynchronize(s));
+    L->final_loss = fl;
+  }
+  // route the keys with the search-time router, then segments, fits and bounds
+  route_keys_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg, L->identity,
+                                                                            L->route, nullptr);
+  seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first);
+  seg_fit_kernel<T><<<dim3(nseg), dim3(256), 0, s>>>(X, N, L->first, L->segs);
+  DS_HIP_CHECK(hipGetLastError());
+  std::vector<SegFit> host(nseg);
+  DS_HIP_CHECK(hipMemcpyAsync(host.data(), L->segs, size_t(nseg) * sizeof(SegFit), hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> firsts(nseg + 1);
+  DS_HIP_CHECK(hipMemcpyAsync(firsts.data(), L->first, size_t(nseg + 1) * 4, hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  int64_t max_err = 0;
+  double wsum = 0, wcnt = 0;
+  for (int32_t k = 0; k < nseg; ++k) {
+    const SegFit& f = host[k];
+    max_err = std::max<int64_t>(max_err, std::max(std::abs(int64_t(f.dmin)), std::abs(int64_t(f.dmax))));
+    const int64_t width = std::min<int64_t>(int64_t(f.dmax) - f.dmin + 2, int64_t(f.hi) - f.lo + 1);
+    const double keys = std::max(1, firsts[k + 1] - firsts[k]);
+    wsum += keys * std::log2(static_cast<double>(std::max<int64_t>(1, width)));
+    wcnt += keys;
+  }
+  L->max_err = max_err;
+  L->mean_log2_window = wcnt > 0 ? wsum / wcnt : 0;
+  // training scratch is no longer needed
+  (void)hipFree(L->partial);
+  (void)hipFree(L->route);
+  (void)hipFree(L->first);
+  L->partial = nullptr;
+  L->route = nullptr;
+  L->first = nullptr;
+  h->info.model_bytes = int64_t(kParams) * 4 + int64_t(nseg) * int64_t(sizeof(SegFit));
+  return DS_OK;
+}
+
+template <typename T>
+ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s) {
+  LearnedModel* L = h->learned;
+  LearnedArgs<T> a{};
+  a.X = static_cast<const T*>(h->X);
+  a.params = L->params;
+  a.segs = L->segs;
+  a.fallbacks = L->fallbacks;
+  a.z = static_cast<const T*>(z);
+  a.out = out;
+  a.M = M;
+  a.X0d = h->X0;
+  a.delta = L->delta;
+  a.flo = L->flo;
+  a.fscale = L->fscale;
+  a.X0 = T(h->X0);
+  a.XN = T(h->XN);
+  a.N = static_cast<int32_t>(h->N);
+  a.nseg = L->nseg;
+  a.identity = L->identity;
+  const int lds = static_cast<int>(int64_t(L->nseg) * sizeof(SegFit));
+  auto kern = learned_search_kernel<T>;
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[sizeof(T) == 8]) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsBytesPerCU);
+    attr_set[sizeof(T) == 8] = true;
+  }
+  const int block = (h->tune_set && h->tune.block) ? h->tune.block : 512;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int64_t need = (M + block - 1) / block;
+  int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * num_cus())));
+  if (h->tune_set && h->tune.grid) grid = h->tune.grid;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+}  // namespace
+
+ds_status learned_build(ds_index* h, const ds_build_opts* o, hipStream_t s) {
+  return h->dt == DS_F32 ? learned_build_typed<float>(h, o, s) : learned_build_typed<double>(h, o, s);
+}
+
+ds_status learned_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s) {
+  if (!h->learned) return DS_ERR_ARG;
+  return h->dt == DS_F32 ? learned_search_typed<float>(h, z, M, out, s)
+                         : learned_search_typed<double>(h, z, M, out, s);
+}
+
 void learned_free(ds_index* h) {
-  delete h->learned;
+  LearnedModel* L = h->learned;
+  if (!L) return;
+  for (void* p : {static_cast<void*>(L->params), static_cast<void*>(L->adam_m), static_cast<void*>(L->adam_v),
+                  static_cast<void*>(L->partial), static_cast<void*>(L->loss_partial), static_cast<void*>(L->feat),
+                  static_cast<void*>(L->route), static_cast<void*>(L->first), static_cast<void*>(L->segs),
+                  static_cast<void*>(L->fallbacks)})
+    if (p) (void)hipFree(p);
+  delete L;
   h->learned = nullptr;
 }
 
+void learned_fill_info(const ds_index* h, ds_info_t* in) {
+  const LearnedModel* L = h->learned;
+  if (!L) return;
+  in->model_bytes = int64_t(kParams) * 4 + int64_t(L->nseg) * int64_t(sizeof(SegFit));
+  in->max_err = L->max_err;
+  in->mean_log2_window = L->mean_log2_window;
+}
+
 }  // namespace ds
+
+extern "C" {
+
+ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const float* t_dev, int32_t batch,
+                          float* grad_dev, float* loss_dev, hipStream_t s) {
+  if (!params_dev || !u_dev || !t_dev || !grad_dev || batch < 1) return DS_ERR_ARG;
+  const int32_t n_parts = (batch + ds::kTrainBlock - 1) / ds::kTrainBlock;
+  float* partial = nullptr;
+  float* lp = nullptr;
+  if (hipMalloc(&partial, size_t(n_parts) * ds::kParams * 4) != hipSuccess) return DS_ERR_OOM;
+  if (hipMalloc(&lp, size_t(n_parts) * 4) != hipSuccess) {
+    (void)hipFree(partial);
+    return DS_ERR_OOM;
+  }
+  ds::train_step_kernel<<<dim3(n_parts), dim3(ds::kTrainBlock), 0, s>>>(params_dev, nullptr, 1, 0, 0, batch, u_dev,
+                                                                        t_dev, partial, lp);
+  ds::adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(nullptr, nullptr, nullptr, partial, n_parts, 0, 0, 0, 0, 1,
+                                                 grad_dev);
+  if (loss_dev) ds::sum_kernel<<<1, 64, 0, s>>>(lp, n_parts, loss_dev);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(partial);
+  (void)hipFree(lp);
+  return e == hipSuccess ? DS_OK : DS_ERR_HIP;
+}
+
+ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_t n, float* y_dev, hipStream_t s) {
+  if (!params_dev || !u_dev || !y_dev || n < 0) return DS_ERR_ARG;
+  if (n == 0) return DS_OK;
+  int32_t* route = nullptr;
+  if (hipMalloc(&route, size_t(n) * 4) != hipSuccess) return DS_ERR_OOM;
+  ds::route_keys_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0, route,
+                                                                                y_dev);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(route);
+  return e == hipSuccess ? DS_OK : DS_ERR_HIP;
+}
+
+ds_status ds_learned_model(ds_handle h, float* params_host, int32_t capacity, uint64_t* fallbacks_host,
+                           hipStream_t s) {
+  if (!h || !h->learned) return DS_ERR_ARG;
+  ds::LearnedModel* L = h->learned;
+  if (params_host) {
+    if (capacity < ds::kParams) return DS_ERR_ARG;
+    DS_HIP_CHECK(hipMemcpyAsync(params_host, L->params, ds::kParams * 4, hipMemcpyDeviceToHost, s));
+  }
+  if (fallbacks_host) {
+    unsigned long long f = 0;
+    DS_HIP_CHECK(hipMemcpyAsync(&f, L->fallbacks, 8, hipMemcpyDeviceToHost, s));
+    DS_HIP_CHECK(hipStreamSynchronize(s));
+    *fallbacks_host = f;
+  }
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  return DS_OK;
+}
+
+}  // extern "C"

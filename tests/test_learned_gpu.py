@@ -1,0 +1,163 @@
+"""GPU checks of the learned CDF method: the training kernels' gradients and the
+search-time router against the fp64 reference, monotone routing, and exact
+indices against the oracle on clustered arrays (where Direct is infeasible)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ds():
+    import paper_1506_08620_amd as mod
+
+    return mod
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _params(rng):
+    p = np.empty(mlp.N_PARAMS)
+    w1 = rng.uniform(2, 6, 32)
+    c = rng.uniform(0.1, 0.9, 32)
+    p[0:32] = w1
+    p[32:64] = 0.5 - w1 * c
+    W2 = rng.uniform(0, 2.0 / 32, (32, 32))
+    p[64:1088] = W2.reshape(-1)
+    p[1088:1120] = 0.5 - 0.5 * W2.sum(1) + rng.uniform(-0.1, 0.1, 32)
+    p[1120:1152] = rng.uniform(0, 1.0 / 16, 32)
+    p[1152] = rng.uniform(-0.1, 0.1)
+    return p.astype(np.float32)
+
+
+def _assert_same(got, ref, z=None):
+    if not np.array_equal(got, ref):
+        bad = np.flatnonzero(got != ref)
+        raise AssertionError(f"{bad.size} of {ref.size} differ; first {bad[:4]}: got {got[bad[:4]]} "
+                             f"want {ref[bad[:4]]}" + (f" z={z[bad[:4]]}" if z is not None else ""))
+
+
+def test_training_gradients_match_fp64_reference(ds):
+    """GPU fp32 gradients vs CPU fp64 at fixed weights on a fixed batch: relative L2 <= 1e-3 per tensor."""
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        p = _params(rng)
+        u = rng.uniform(0, 1, 3000).astype(np.float32)
+        t = np.sort(rng.uniform(0, 1, 3000)).astype(np.float32)
+        loss_g, g = ds.learned_grad(_dev(p), _dev(u), _dev(t))
+        loss_c, gc = mlp.grad(p.astype(np.float64), u.astype(np.float64), t.astype(np.float64))
+        g = g.cpu().numpy().astype(np.float64)
+        assert abs(loss_g - loss_c) <= 1e-4 * max(loss_c, 1e-12)
+        for name, a, b in (("W1", 0, 32), ("b1", 32, 64), ("W2", 64, 1088), ("b2", 1088, 1120),
+                           ("W3", 1120, 1152), ("b3", 1152, 1153)):
+            ref = gc[a:b]
+            err = np.linalg.norm(g[a:b] - ref) / max(np.linalg.norm(ref), 1e-12)
+            assert err <= 1e-3, (trial, name, err)
+
+
+def test_search_router_matches_reference_and_is_monotone(ds):
+    rng = np.random.default_rng(6)
+    p = _params(rng)
+    u = np.sort(np.concatenate([rng.uniform(0, 1, 200_000), np.linspace(0, 1, 4097)])).astype(np.float32)
+    y = ds.learned_forward(_dev(p), _dev(u)).cpu().numpy()
+    yc, _ = mlp.forward(p.astype(np.float64), u.astype(np.float64))
+    # 32-term fp32 dot products of values in [0, 1]: errors of a few 1e-7, bounded well below 1e-4
+    assert np.max(np.abs(y - yc)) < 1e-4
+    assert np.all(np.diff(y) >= 0)  # exact: non-negative weights, monotone rounding
+
+
+def _clustered(n, dt, seed):
+    rng = np.random.default_rng(seed)
+    x = np.unique(np.exp(rng.normal(0, 2, n * 2)).astype(dt))[: n + 1]
+    return x
+
+
+def _queries(X, m, rng):
+    dt = X.dtype
+    zu = W.uniform_queries(X[0], X[-1], m, dt, rng)
+    k = rng.integers(0, X.size, m)
+    zc = (X[k].astype(np.float64) * (1 + rng.uniform(-1e-6, 1e-6, m))).astype(dt)
+    zc = np.clip(zc, X[0], W.prev_float(X[-1], dt))
+    extra = [X, W.prev_float(X, dt), np.nextafter(X, dt.type(np.inf)),
+             np.array([np.nan, np.inf, -np.inf, 0.0, -1.0, 1e30], dt)]
+    return np.concatenate([zu, zc, *extra]).astype(dt)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_learned_exact_on_clustered_arrays(ds, dt):
+    rng = np.random.default_rng(7)
+    for n, segs in ((50, 16), (3000, 256), (40_000, 4096)):
+        X = _clustered(n, dt, n)
+        z = _queries(X, 100_000, rng)
+        ref = oracle.search(X, z)
+        for epochs in (20, -1):  # trained router, and the ablation without network
+            idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=segs, seed=3)
+            inf = idx.info()
+            assert inf["method_name"] == "learned"
+            _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
+            _, fb = idx.learned_model()
+            assert fb == 0
+            assert inf["model_bytes"] == 1153 * 4 + segs * 32
+
+
+def test_uniform_gaps_give_tight_windows(ds):
+    """Closed form: X_i = i has a linear CDF, so every segment's fit is exact up to
+    rounding and every window holds at most three candidates."""
+    X = np.arange(0, 65537, dtype=np.float64)
+    idx = ds.build(_dev(X), method="learned", learn_epochs=-1, learn_segments=1024)
+    inf = idx.info()
+    assert inf["max_err"] <= 1
+    assert inf["mean_log2_window"] <= np.log2(3) + 1e-9
+    z = np.concatenate([np.random.default_rng(1).uniform(0, 65536, 100_000), X, W.prev_float(X, np.float64)])
+    _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), oracle.search(X, z))
+
+
+def test_auto_and_fallback_choose_learned_on_infeasible(ds):
+    X = _clustered(20_000, np.float64, 3)
+    assert oracle.compute_hr(X).status == oracle.ERR_INFEASIBLE
+    z = _queries(X, 50_000, np.random.default_rng(2))
+    ref = oracle.search(X, z)
+    for kw in (dict(method="auto"), dict(fallback="learned")):
+        idx = ds.build(_dev(X), learn_epochs=10, learn_segments=1024, **kw)
+        assert idx.info()["method_name"] == "learned"
+        _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref)
+    # auto keeps Direct where it is feasible
+    Xu = W.sweep_array(4096, np.float64)
+    assert ds.build(_dev(Xu), method="auto").info()["method_name"] == "direct"
+
+
+def test_network_gains_over_identity_router(ds):
+    """What the trained router buys: narrower windows than equal-width segments of the feature."""
+    X = W.clustered_array(1 << 17)
+    trained = ds.build(_dev(X), method="learned", learn_segments=1024, learn_epochs=30).info()
+    plain = ds.build(_dev(X), method="learned", learn_segments=1024, learn_epochs=-1).info()
+    assert trained["mean_log2_window"] < plain["mean_log2_window"]
+
+
+def test_full_size_clustered_f64_sampled(ds):
+    """N + 1 = 2^20 lognormal draws, M = 2^26 (half uniform, half X_k (1 + 1e-12 noise))."""
+    X = W.clustered_array()
+    assert oracle.compute_hr(X).status == oracle.ERR_INFEASIBLE  # Direct table explodes
+    z = W.clustered_queries(X, 1 << 26)
+    X_d, z_d = _dev(X), _dev(z)
+    idx = ds.build(X_d, method="learned")
+    out = ds.search(idx, z_d)
+    torch.cuda.synchronize()
+    i = out.long()
+    assert int(i.min()) >= 0 and int(i.max()) <= X.size - 2
+    assert bool(torch.all(X_d[i] <= z_d)) and bool(torch.all(z_d < X_d[i + 1]))
+    pos = np.random.default_rng(3).integers(0, z.size, 1 << 18)
+    _assert_same(out[torch.from_numpy(pos).to(DEV)].cpu().numpy(), oracle.search(X, z[pos]))
+    _, fb = idx.learned_model()
+    assert fb == 0
+    inf = idx.info()
+    assert inf["model_bytes"] < 200_000
