@@ -38,7 +38,8 @@ def parse():
     p.add_argument("--no-extras", action="store_true", help="skip the per-method comparison runs")
     p.add_argument("--sizes", type=str, default="", help="comma-separated subset of N (testing)")
     p.add_argument("--m", type=int, default=0, help="queries per case (default 2^26)")
-    p.add_argument("--batched", action="store_true", help="also time the 10,000-array batched workload")
+    p.add_argument("--no-batched", action="store_true", help="skip the 10,000-array batched workload")
+    p.add_argument("--no-learned", action="store_true", help="skip the learned method on the clustered array")
     return p.parse_args()
 
 
@@ -157,11 +158,14 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = compare_methods(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
-    if args.batched:
-        for c in cases:  # free the sweep's buffers first
-            c["idx"].destroy()
-        cases.clear()
-        torch.cuda.empty_cache()
+    direct_f64_2p20 = next((r["gq_s"] for r in case_rows if r["N"] == 1 << 20 and r["dtype"] == "f64"), None)
+    for c in cases:  # free the sweep's buffers first
+        c["idx"].destroy()
+    cases.clear()
+    torch.cuda.empty_cache()
+    if not args.no_learned:
+        extras["learned_f64_clustered"] = bench_learned(ds, W, dev, stream, reps=5, direct_ref=direct_f64_2p20)
+    if not args.no_batched:
         extras["batched_f32"] = bench_batched(ds, W, dev, stream, reps=3)
 
     line = {
@@ -229,6 +233,59 @@ def compare_methods(ds, cases, M, stream, reps):
                                  same_as_direct=bool(torch.equal(out, c["out"]))))
             idx.destroy()
         del out
+    return res
+
+
+def bench_learned(ds, W, dev, stream, reps, direct_ref):
+    """Clustered f64 array (N + 1 = 2^20 lognormal draws), 2^26 queries: the learned
+    method (trained router), its ablation without the network, and the leading-bit
+    binary search on the same inputs.  Direct is infeasible on this array."""
+    import torch
+
+    X = W.clustered_array()
+    z = W.clustered_queries(X, 1 << 26)
+    x_d = torch.from_numpy(X).to(dev)
+    z_d = torch.from_numpy(z).to(dev)
+    out = torch.empty(z.size, dtype=torch.int32, device=dev)
+    M = z.size
+    res = {"N": X.size - 1, "M": M, "direct_table_bytes_needed": None}
+    gaps = np.diff(X)
+    res["direct_table_bytes_needed"] = float(4.0 * (X[-1] - X[0]) / gaps.min())
+    ref_out = None
+    for name, kw in (("learned", dict(method="learned")), ("learned_no_network", dict(method="learned", learn_epochs=-1)),
+                     ("bsearch_leadbit", dict(method="leadbit"))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idx = ds.build(x_d, **kw)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        ds.search(idx, z_d, out=out, stream=stream)
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            ds.search(idx, z_d, out=out, stream=stream)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e) / reps
+        inf = idx.info()
+        row = dict(gq_s=round(M / ms / 1e6, 2), hbm_frac=round(M * 12 / ms / 1e6 / HBM_PEAK_GBS, 4),
+                   build_s=round(build_s, 3))
+        if name.startswith("learned"):
+            _, fb = idx.learned_model()
+            row.update(model_bytes=inf["model_bytes"], max_err=inf["max_err"],
+                       mean_log2_window=round(inf["mean_log2_window"], 3), fallbacks=fb)
+        if ref_out is None:
+            ref_out = out.clone()
+        else:
+            row["same_as_learned"] = bool(torch.equal(out, ref_out))
+        res[name] = row
+        idx.destroy()
+    if direct_ref:
+        res["direct_f64_n2p20_sweep_gq_s"] = direct_ref
+        res["learned_vs_direct"] = round(res["learned"]["gq_s"] / direct_ref, 3)
+    res["model_vs_direct_table"] = res["learned"]["model_bytes"] / res["direct_table_bytes_needed"]
+    del z_d, out, ref_out
+    torch.cuda.empty_cache()
     return res
 
 

@@ -123,6 +123,7 @@ def test_uniform_gaps_give_tight_windows(ds):
 
 def test_auto_and_fallback_choose_learned_on_infeasible(ds):
     X = _clustered(20_000, np.float64, 3)
+    X = np.unique(np.concatenate([X, [1.0, np.nextafter(1.0, 2.0)]]))  # one gap of 1 ulp: no feasible H
     assert oracle.compute_hr(X).status == oracle.ERR_INFEASIBLE
     z = _queries(X, 50_000, np.random.default_rng(2))
     ref = oracle.search(X, z)
