@@ -34,6 +34,7 @@ constexpr int kHid = 32;
 constexpr int kParams = 2 * kHid + kHid * kHid + kHid + kHid + 1;  // 1153
 constexpr int oW1 = 0, oB1 = 32, oW2 = 64, oB2 = 64 + 1024, oW3 = 64 + 1024 + 32, oB3 = 64 + 1024 + 64;
 constexpr int kTrainBlock = 256;
+constexpr int kScan = 16;  // windows up to this size are scanned, not bisected
 
 // per-segment fit: prediction p = a (z - zc) + b (relative to lo), window
 // [lo + floor(p) + dmin - 1, lo + floor(p) + dmax] clipped to [lo, hi]
@@ -115,20 +116,38 @@ __device__ void load_router(const float* __restrict__ p, RouterRegs& R) {
 
 // y(u) for the query of lane l % 32; all 64 lanes must call it, and lanes l
 // and l ^ 32 must pass the same u.  Both lanes return the same y.
+__device__ __forceinline__ float router_tail(const floatx16& acc, const RouterRegs& R) {
+  float part = 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part = std::fma(R.w3[r], clamp01(acc[r]), part);
+  const float other = __shfl_xor(part, 32, 64);
+  return (part + other) + R.b3;  // a + b == b + a exactly, so both lanes agree
+}
+
 __device__ __forceinline__ float router_y(float u, const RouterRegs& R) {
-  const int half = (threadIdx.x & 63) >> 5;
   floatx16 acc = R.b2;
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const float h1 = clamp01(std::fma(R.w1[kk], u, R.b1[kk]));
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(R.w2[kk], h1, acc, 0, 0, 0);
   }
-  float part = 0.0f;
+  return router_tail(acc, R);
+}
+
+// Two independent 32-query passes interleaved, so each matrix instruction has
+// the other chain's instruction to overlap with.  Each result is computed by
+// exactly the same operations as router_y.
+__device__ __forceinline__ void router_y2(float ua, float ub, const RouterRegs& R, float* ya, float* yb) {
+  floatx16 acc_a = R.b2, acc_b = R.b2;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) part = std::fma(R.w3[r], clamp01(acc[r]), part);
-  const float other = __shfl_xor(part, 32, 64);
-  (void)half;
-  return (part + other) + R.b3;  // a + b == b + a exactly, so both lanes agree
+  for (int kk = 0; kk < 16; ++kk) {
+    const float ha = clamp01(std::fma(R.w1[kk], ua, R.b1[kk]));
+    const float hb = clamp01(std::fma(R.w1[kk], ub, R.b1[kk]));
+    acc_a = __builtin_amdgcn_mfma_f32_32x32x2f32(R.w2[kk], ha, acc_a, 0, 0, 0);
+    acc_b = __builtin_amdgcn_mfma_f32_32x32x2f32(R.w2[kk], hb, acc_b, 0, 0, 0);
+  }
+  *ya = router_tail(acc_a, R);
+  *yb = router_tail(acc_b, R);
 }
 
 __device__ __forceinline__ int32_t segment_of(float y, int32_t nseg) {
@@ -323,8 +342,8 @@ __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict
   if (identity) {
     y = u_mine;
   } else {
-    const float ya = router_y(half ? u_other : u_mine, R);
-    const float yb = router_y(half ? u_mine : u_other, R);
+    float ya, yb;
+    router_y2(half ? u_other : u_mine, half ? u_mine : u_other, R, &ya, &yb);
     y = half ? yb : ya;
   }
   if (i < n) {
@@ -450,15 +469,20 @@ __device__ __forceinline__ int32_t finish_query(T z, float y, const LearnedArgs<
   int32_t L = std::min(std::max(sg.lo, sg.lo + q + sg.dmin - 1), sg.hi);
   const int32_t U = std::min(std::max(L, sg.lo + q + sg.dmax), sg.hi);
   int32_t n = U - L + 1;
-  // branch-free search of the largest i in [L, U] with X_i <= z
-  while (n > 1) {
+  // largest i in [L, U] with X_i <= z: halve the window until it holds at most
+  // kScan candidates, then count them in one pass over contiguous memory (the
+  // loads are independent, so they share one round trip and their cache lines)
+  while (n > kScan) {
     const int32_t h = n >> 1;
     const int32_t m = L + h;
     const bool c = z >= a.X[m];
     L = c ? m : L;
     n = c ? n - h : h;
   }
-  int32_t i = L;
+  int32_t cnt = 0;
+#pragma unroll
+  for (int k = 1; k < kScan; ++k) cnt += (k < n && a.X[L + k] <= z) ? 1 : 0;
+  int32_t i = L + cnt;
   const bool inside = (z >= a.X0) && (z < a.XN);
   if (inside && !(a.X[i] <= z && z < a.X[i + 1])) {
     // outside the recorded window: full search (counted; never expected)
@@ -498,8 +522,8 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
       y = u_mine;
     } else {
       const float u_other = __shfl_xor(u_mine, 32, 64);
-      const float ya = router_y(half ? u_other : u_mine, R);
-      const float yb = router_y(half ? u_mine : u_other, R);
+      float ya, yb;
+      router_y2(half ? u_other : u_mine, half ? u_mine : u_other, R, &ya, &yb);
       y = half ? yb : ya;
     }
     const int32_t i = finish_query<T>(z, y, a, segs);
@@ -660,7 +684,7 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
                               kLdsBytesPerCU);
     attr_set[sizeof(T) == 8] = true;
   }
-  const int block = (h->tune_set && h->tune.block) ? h->tune.block : 512;
+  const int block = (h->tune_set && h->tune.block) ? h->tune.block : 1024;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
   const int64_t need = (M + block - 1) / block;
