@@ -252,7 +252,9 @@ def bench_learned(ds, W, dev, stream, reps, direct_ref):
     gaps = np.diff(X)
     res["direct_table_bytes_needed"] = float(4.0 * (X[-1] - X[0]) / gaps.min())
     ref_out = None
-    for name, kw in (("learned", dict(method="learned")), ("learned_no_network", dict(method="learned", learn_epochs=-1)),
+    for name, kw in (("learned", dict(method="learned")),
+                     ("learned_fp16_router", dict(method="learned", learn_fp16_router=True)),
+                     ("learned_no_network", dict(method="learned", learn_epochs=-1)),
                      ("bsearch_leadbit", dict(method="leadbit"))):
         torch.cuda.synchronize()
         t0 = time.perf_counter()

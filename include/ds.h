@@ -100,8 +100,13 @@ typedef struct ds_build_opts {
   uint64_t seed;            /* initialisation / sampling seed */
   int32_t extra_layouts;    /* Direct: also build these search layouts (bit mask of
                                DS_LAYOUT_*), beyond the one the automatic choice uses */
-  int32_t reserved_;
+  int32_t learn_flags;      /* learned: bit mask of DS_LEARN_* */
 } ds_build_opts;
+
+/* learned: evaluate the router's 32x32 layer with FP16 inputs and FP32
+ * accumulation at search time (the model is trained and stored in FP32; the
+ * segments are built with the same FP16 router, so results stay exact) */
+#define DS_LEARN_FP16_ROUTER 1
 
 /* Device layouts of the Direct tables (ds_tune.stage selects one):
  *   PLAIN     K (int32 per grid cell) and X, as in Sec. 4.
@@ -230,8 +235,10 @@ ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const flo
                           float* grad_dev, float* loss_dev, hipStream_t s);
 
 /* y(u_dev[k]) for k < n by the search-time router (the 32x32 layer on the
- * matrix cores).  Synchronises s.  Allocates temporary device memory. */
-ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_t n, float* y_dev, hipStream_t s);
+ * matrix cores; fp16_router != 0 selects the FP16-input variant).
+ * Synchronises s.  Allocates temporary device memory. */
+ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_t n, int32_t fp16_router, float* y_dev,
+                             hipStream_t s);
 
 /* Trained parameters of a learned handle (params_host: capacity >= 1153
  * floats, or NULL) and the number of queries so far that fell outside their

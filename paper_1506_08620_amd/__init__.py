@@ -54,7 +54,7 @@ class BuildOpts(ctypes.Structure):
                 ("fallback", ctypes.c_int32), ("table_cap_bytes", ctypes.c_int64),
                 ("learn_epochs", ctypes.c_int32), ("learn_segments", ctypes.c_int32),
                 ("learn_rate", ctypes.c_float), ("learn_batch", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("extra_layouts", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("extra_layouts", ctypes.c_int32), ("learn_flags", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -115,7 +115,7 @@ def _load_library():
     lib.ds_search_batched.restype = i32
     lib.ds_learned_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     lib.ds_learned_grad.restype = i32
-    lib.ds_learned_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.ds_learned_forward.argtypes = [vp, vp, i64, i32, vp, vp]
     lib.ds_learned_forward.restype = i32
     lib.ds_learned_model.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_uint64), vp]
     lib.ds_learned_model.restype = i32
@@ -233,7 +233,8 @@ class Index:
 
 def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart: str = "phi",
           fallback: str = "none", table_cap_bytes: int = 0, learn_epochs: int = 0, learn_segments: int = 0,
-          learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), stream=None) -> Index:
+          learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), learn_fp16_router: bool = False,
+          stream=None) -> Index:
     """ds_build over the N+1 values of x (a strictly increasing GPU tensor).
 
     layouts: extra Direct layouts to build besides the automatic one
@@ -244,7 +245,7 @@ def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart:
         raise ValueError("x must be 1-D with at least two values")
     opts = BuildOpts(_METHODS[method], _FORMS[form], _HSTARTS[hstart], _FALLBACKS[fallback], int(table_cap_bytes),
                      int(learn_epochs), int(learn_segments), float(learn_rate), int(learn_batch), int(seed),
-                     sum(_LAYOUTS[k] for k in set(layouts)), 0)
+                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp16_router else 0)
     h = ctypes.c_void_p()
     with torch.cuda.device(x.device):
         st = _lib.ds_build(x.data_ptr(), x.numel() - 1, _dtype_code(x), ctypes.byref(opts), _stream_handle(stream),
@@ -303,12 +304,13 @@ def learned_grad(params: torch.Tensor, u: torch.Tensor, t: torch.Tensor, stream=
     return float(loss.item()), g
 
 
-def learned_forward(params: torch.Tensor, u: torch.Tensor, stream=None) -> torch.Tensor:
-    """y(u) by the search-time router kernel."""
+def learned_forward(params: torch.Tensor, u: torch.Tensor, fp16_router: bool = False, stream=None) -> torch.Tensor:
+    """y(u) by the search-time router kernel (FP32 or FP16-input 32x32 layer)."""
     _check_device(params, "params")
     _check_device(u, "u")
     y = torch.empty(u.numel(), dtype=torch.float32, device=u.device)
-    st = _lib.ds_learned_forward(params.data_ptr(), u.data_ptr(), u.numel(), y.data_ptr(), _stream_handle(stream))
+    st = _lib.ds_learned_forward(params.data_ptr(), u.data_ptr(), u.numel(), int(bool(fp16_router)), y.data_ptr(),
+                                 _stream_handle(stream))
     if st != OK:
         raise DsError(st, "ds_learned_forward")
     return y

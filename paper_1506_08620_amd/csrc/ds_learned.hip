@@ -24,6 +24,7 @@
 #include <chrono>
 #include <cmath>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 #include "ds_ops.h"
@@ -34,7 +35,6 @@ constexpr int kHid = 32;
 constexpr int kParams = 2 * kHid + kHid * kHid + kHid + kHid + 1;  // 1153
 constexpr int oW1 = 0, oB1 = 32, oW2 = 64, oB2 = 64 + 1024, oW3 = 64 + 1024 + 32, oB3 = 64 + 1024 + 64;
 constexpr int kTrainBlock = 256;
-constexpr int kScan = 16;  // windows up to this size are scanned, not bisected
 
 // per-segment fit: prediction p = a (z - zc) + b (relative to lo), window
 // [lo + floor(p) + dmin - 1, lo + floor(p) + dmax] clipped to [lo, hi]
@@ -57,6 +57,7 @@ struct LearnedModel {
   unsigned long long* fallbacks = nullptr;
   int32_t nseg = 0;
   int32_t identity = 0;         // ablation: y = u
+  int32_t f16 = 0;              // router's 32x32 layer with FP16 inputs
   double delta = 0, flo = 0, fscale = 0;
   int64_t max_err = 0;
   double mean_log2_window = 0;
@@ -148,6 +149,84 @@ __device__ __forceinline__ void router_y2(float ua, float ub, const RouterRegs& 
   }
   *ya = router_tail(acc_a, R);
   *yb = router_tail(acc_b, R);
+}
+
+// The same network with the 32x32 layer's inputs (h1 and W2) rounded to
+// FP16 and FP32 accumulation (v_mfma_f32_32x32x8f16, 4 instructions per pass
+// instead of 16).  Rounding is monotone and W2 stays >= 0, so this router is
+// monotone as well; it is a different (slightly coarser) function of u, and a
+// model built with it is searched with it.  Lane l supplies, for block kb,
+// the units k = 8 kb + 4 (l / 32) + c, c = 0..3.
+using half4 = _Float16 __attribute__((ext_vector_type(4)));
+
+struct RouterRegs16 {
+  float w1[16], b1[16], w3[16];
+  half4 w2[4];
+  floatx16 b2;
+  float b3;
+};
+
+__device__ void load_router16(const float* __restrict__ p, RouterRegs16& R) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int m = lane & 31;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = 8 * kb + 4 * half + c;
+      R.w1[4 * kb + c] = p[oW1 + k];
+      R.b1[4 * kb + c] = p[oB1 + k];
+      R.w2[kb][c] = static_cast<_Float16>(p[oW2 + m * kHid + k]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j = out_row(r, half);
+    R.b2[r] = p[oB2 + j];
+    R.w3[r] = p[oW3 + j];
+  }
+  R.b3 = p[oB3];
+}
+
+__device__ __forceinline__ float router_tail16(const floatx16& acc, const RouterRegs16& R) {
+  float part = 0.0f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part = std::fma(R.w3[r], clamp01(acc[r]), part);
+  const float other = __shfl_xor(part, 32, 64);
+  return (part + other) + R.b3;
+}
+
+__device__ __forceinline__ void router16_y2(float ua, float ub, const RouterRegs16& R, float* ya, float* yb) {
+  floatx16 acc_a = R.b2, acc_b = R.b2;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    half4 ha, hb;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ha[c] = static_cast<_Float16>(clamp01(std::fma(R.w1[4 * kb + c], ua, R.b1[4 * kb + c])));
+      hb[c] = static_cast<_Float16>(clamp01(std::fma(R.w1[4 * kb + c], ub, R.b1[4 * kb + c])));
+    }
+    acc_a = __builtin_amdgcn_mfma_f32_32x32x8f16(R.w2[kb], ha, acc_a, 0, 0, 0);
+    acc_b = __builtin_amdgcn_mfma_f32_32x32x8f16(R.w2[kb], hb, acc_b, 0, 0, 0);
+  }
+  *ya = router_tail16(acc_a, R);
+  *yb = router_tail16(acc_b, R);
+}
+
+// y for the query of this lane (lane l: query l of the 64-query group), with
+// the two 32-query passes of either router precision
+template <bool F16>
+__device__ __forceinline__ float route_pair(float u_mine, const void* regs) {
+  const int half = (threadIdx.x & 63) >> 5;
+  const float u_other = __shfl_xor(u_mine, 32, 64);
+  float ya, yb;
+  if constexpr (F16) {
+    router16_y2(half ? u_other : u_mine, half ? u_mine : u_other, *static_cast<const RouterRegs16*>(regs), &ya, &yb);
+  } else {
+    router_y2(half ? u_other : u_mine, half ? u_mine : u_other, *static_cast<const RouterRegs*>(regs), &ya, &yb);
+  }
+  return half ? yb : ya;
 }
 
 __device__ __forceinline__ int32_t segment_of(float y, int32_t nseg) {
@@ -326,26 +405,21 @@ __global__ void sum_kernel(const float* __restrict__ parts, int32_t n, float* __
 }
 
 // segment of every key through the search-time router (MFMA), 64 keys per wave
+template <bool F16>
 __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict__ params,
                                                          const float* __restrict__ feat, int64_t n,
                                                          int32_t nseg, int32_t identity, int32_t* __restrict__ route,
                                                          float* __restrict__ y_out) {
-  RouterRegs R;
-  load_router(params, R);
+  typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
+  if constexpr (F16)
+    load_router16(params, R);
+  else
+    load_router(params, R);
   const int lane = threadIdx.x & 63;
-  const int half = lane >> 5;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t i = wave * 64 + lane;
   const float u_mine = i < n ? feat[i] : 1.0f;
-  const float u_other = __shfl_xor(u_mine, 32, 64);
-  float y;
-  if (identity) {
-    y = u_mine;
-  } else {
-    float ya, yb;
-    router_y2(half ? u_other : u_mine, half ? u_mine : u_other, R, &ya, &yb);
-    y = half ? yb : ya;
-  }
+  const float y = identity ? u_mine : route_pair<F16>(u_mine, &R);
   if (i < n) {
     route[i] = segment_of(y, nseg);
     if (y_out) y_out[i] = y;
@@ -469,22 +543,23 @@ __device__ __forceinline__ int32_t finish_query(T z, float y, const LearnedArgs<
   int32_t L = std::min(std::max(sg.lo, sg.lo + q + sg.dmin - 1), sg.hi);
   const int32_t U = std::min(std::max(L, sg.lo + q + sg.dmax), sg.hi);
   int32_t n = U - L + 1;
-  // largest i in [L, U] with X_i <= z: halve the window until it holds at most
-  // kScan candidates, then count them in one pass over contiguous memory (the
-  // loads are independent, so they share one round trip and their cache lines)
-  while (n > kScan) {
+  // branch-free bisection for the largest i in [L, U] with X_i <= z.  Every
+  // accepted probe proves X_m <= z and every rejected one z < X_m, so at the
+  // end only a result at an end of the window has a side left unproven.
+  const int32_t L0 = L;
+  while (n > 1) {
     const int32_t h = n >> 1;
     const int32_t m = L + h;
     const bool c = z >= a.X[m];
     L = c ? m : L;
     n = c ? n - h : h;
   }
-  int32_t cnt = 0;
-#pragma unroll
-  for (int k = 1; k < kScan; ++k) cnt += (k < n && a.X[L + k] <= z) ? 1 : 0;
-  int32_t i = L + cnt;
+  int32_t i = L;
   const bool inside = (z >= a.X0) && (z < a.XN);
-  if (inside && !(a.X[i] <= z && z < a.X[i + 1])) {
+  bool ok = true;
+  if (inside && i == L0) ok = a.X[i] <= z;
+  if (inside && i == U) ok = ok && z < a.X[i + 1];
+  if (inside && !ok) {
     // outside the recorded window: full search (counted; never expected)
     atomicAdd(a.fallbacks, 1ull);
     int32_t lo = 0, nn = a.N;
@@ -500,16 +575,18 @@ __device__ __forceinline__ int32_t finish_query(T z, float y, const LearnedArgs<
   return (z >= a.X0) ? i : -1;
 }
 
-template <typename T>
+template <typename T, bool F16>
 __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.segs), int64_t(a.nseg) * sizeof(SegFit));
   __syncthreads();
   const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
-  RouterRegs R;
-  load_router(a.params, R);
+  typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
+  if constexpr (F16)
+    load_router16(a.params, R);
+  else
+    load_router(a.params, R);
   const int lane = threadIdx.x & 63;
-  const int half = lane >> 5;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   for (int64_t base = wave * 64; base < a.M; base += waves * 64) {
@@ -517,15 +594,7 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
     const bool valid = qi < a.M;
     const T z = valid ? __builtin_nontemporal_load(a.z + qi) : a.X0;
     const float u_mine = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
-    float y;
-    if (a.identity) {
-      y = u_mine;
-    } else {
-      const float u_other = __shfl_xor(u_mine, 32, 64);
-      float ya, yb;
-      router_y2(half ? u_other : u_mine, half ? u_mine : u_other, R, &ya, &yb);
-      y = half ? yb : ya;
-    }
+    const float y = a.identity ? u_mine : route_pair<F16>(u_mine, &R);
     const int32_t i = finish_query<T>(z, y, a, segs);
     if (valid) __builtin_nontemporal_store(i, a.out + qi);
   }
@@ -559,6 +628,7 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   if (nseg < 1 || nseg > 8192) return DS_ERR_ARG;
   L->nseg = nseg;
   L->identity = (o->learn_epochs < 0) ? 1 : 0;
+  L->f16 = (o->learn_flags & DS_LEARN_FP16_ROUTER) ? 1 : 0;
   const int32_t batch = o->learn_batch > 0 ? o->learn_batch : 8192;
   const int32_t epochs = o->learn_epochs > 0 ? o->learn_epochs : (o->learn_epochs == 0 ? 60 : 0);
   const float lr = o->learn_rate > 0 ? o->learn_rate : 2e-3f;
@@ -623,8 +693,12 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
     L->final_loss = fl;
   }
   // route the keys with the search-time router, then segments, fits and bounds
-  route_keys_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg, L->identity,
-                                                                            L->route, nullptr);
+  if (L->f16)
+    route_keys_kernel<true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
+                                                                                  L->identity, L->route, nullptr);
+  else
+    route_keys_kernel<false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
+                                                                                   L->identity, L->route, nullptr);
   seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first);
   seg_fit_kernel<T><<<dim3(nseg), dim3(256), 0, s>>>(X, N, L->first, L->segs);
   DS_HIP_CHECK(hipGetLastError());
@@ -677,13 +751,9 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   a.nseg = L->nseg;
   a.identity = L->identity;
   const int lds = static_cast<int>(int64_t(L->nseg) * sizeof(SegFit));
-  auto kern = learned_search_kernel<T>;
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[sizeof(T) == 8]) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kLdsBytesPerCU);
-    attr_set[sizeof(T) == 8] = true;
-  }
+  auto kern = L->f16 ? learned_search_kernel<T, true> : learned_search_kernel<T, false>;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytesPerCU);
   const int block = (h->tune_set && h->tune.block) ? h->tune.block : 1024;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
@@ -754,13 +824,18 @@ ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const flo
   return e == hipSuccess ? DS_OK : DS_ERR_HIP;
 }
 
-ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_t n, float* y_dev, hipStream_t s) {
+ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_t n, int32_t fp16_router, float* y_dev,
+                             hipStream_t s) {
   if (!params_dev || !u_dev || !y_dev || n < 0) return DS_ERR_ARG;
   if (n == 0) return DS_OK;
   int32_t* route = nullptr;
   if (hipMalloc(&route, size_t(n) * 4) != hipSuccess) return DS_ERR_OOM;
-  ds::route_keys_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0, route,
-                                                                                y_dev);
+  if (fp16_router)
+    ds::route_keys_kernel<true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0,
+                                                                                      route, y_dev);
+  else
+    ds::route_keys_kernel<false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0,
+                                                                                       route, y_dev);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(route);

@@ -73,6 +73,11 @@ def test_search_router_matches_reference_and_is_monotone(ds):
     # 32-term fp32 dot products of values in [0, 1]: errors of a few 1e-7, bounded well below 1e-4
     assert np.max(np.abs(y - yc)) < 1e-4
     assert np.all(np.diff(y) >= 0)  # exact: non-negative weights, monotone rounding
+    # FP16 inputs to the 32x32 layer: relative rounding 2^-11 of h1 and W2, so |y - y_ref| of a
+    # few 1e-3 at most for these weights; still exactly monotone
+    y16 = ds.learned_forward(_dev(p), _dev(u), fp16_router=True).cpu().numpy()
+    assert np.max(np.abs(y16 - yc)) < 5e-3
+    assert np.all(np.diff(y16) >= 0)
 
 
 def _clustered(n, dt, seed):
@@ -99,8 +104,9 @@ def test_learned_exact_on_clustered_arrays(ds, dt):
         X = _clustered(n, dt, n)
         z = _queries(X, 100_000, rng)
         ref = oracle.search(X, z)
-        for epochs in (20, -1):  # trained router, and the ablation without network
-            idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=segs, seed=3)
+        for epochs, f16 in ((20, False), (20, True), (-1, False)):  # trained router (FP32 / FP16 layer), no network
+            idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=segs, seed=3,
+                           learn_fp16_router=f16)
             inf = idx.info()
             assert inf["method_name"] == "learned"
             _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
@@ -152,6 +158,8 @@ def test_full_size_clustered_f64_sampled(ds):
     X_d, z_d = _dev(X), _dev(z)
     idx = ds.build(X_d, method="learned")
     out = ds.search(idx, z_d)
+    idx16 = ds.build(X_d, method="learned", learn_fp16_router=True)
+    assert torch.equal(ds.search(idx16, z_d), out)
     torch.cuda.synchronize()
     i = out.long()
     assert int(i.min()) >= 0 and int(i.max()) <= X.size - 2
