@@ -535,32 +535,49 @@ struct LearnedArgs {
   int32_t N, nseg, identity, pad;
 };
 
+// Window of candidate indices for z from its segment: [q + dmin - 1, q + dmax]
+// relative to lo, kept inside [lo, hi].
 template <typename T>
-__device__ __forceinline__ int32_t finish_query(T z, float y, const LearnedArgs<T>& a, const SegFit* segs) {
+__device__ __forceinline__ void query_window(T z, float y, const LearnedArgs<T>& a, const SegFit* segs, int32_t* L,
+                                             int32_t* U) {
   const SegFit sg = segs[segment_of(y, a.nseg)];
   const int32_t q = seg_predict<T>(sg, z);
-  // window [q + dmin - 1, q + dmax] relative to lo, kept inside [lo, hi]
-  int32_t L = std::min(std::max(sg.lo, sg.lo + q + sg.dmin - 1), sg.hi);
-  const int32_t U = std::min(std::max(L, sg.lo + q + sg.dmax), sg.hi);
-  int32_t n = U - L + 1;
-  // branch-free bisection for the largest i in [L, U] with X_i <= z.  Every
-  // accepted probe proves X_m <= z and every rejected one z < X_m, so at the
-  // end only a result at an end of the window has a side left unproven.
-  const int32_t L0 = L;
-  while (n > 1) {
+  *L = std::min(std::max(sg.lo, sg.lo + q + sg.dmin - 1), sg.hi);
+  *U = std::min(std::max(*L, sg.lo + q + sg.dmax), sg.hi);
+}
+
+// One round of a branch-free 4-way search for the largest i in [L, L+n-1]
+// with X_i <= z: three independent probes at the quarter points (one memory
+// round trip), or a bisection probe when n < 4.  Accepted probes prove
+// X_m <= z and rejected ones z < X_m.
+template <typename T>
+__device__ __forceinline__ void search_round(T z, const T* __restrict__ X, int32_t& L, int32_t& n) {
+  if (n >= 4) {
+    const int32_t q = n >> 2;
+    const int32_t c1 = z >= X[L + q] ? 1 : 0;
+    const int32_t c2 = z >= X[L + 2 * q] ? 1 : 0;
+    const int32_t c3 = z >= X[L + 3 * q] ? 1 : 0;
+    const int32_t c = c1 + c2 + c3;
+    L += c * q;
+    n = (c == 3) ? n - 3 * q : q;
+  } else if (n > 1) {
     const int32_t h = n >> 1;
-    const int32_t m = L + h;
-    const bool c = z >= a.X[m];
-    L = c ? m : L;
+    const bool c = z >= X[L + h];
+    L = c ? L + h : L;
     n = c ? n - h : h;
   }
-  int32_t i = L;
+}
+
+// Exact index of z from its window, with the out-of-domain conventions.  Only
+// a result at an end of the window has a side not proven by a probe; that side
+// is checked, and a failure (never expected) takes a full search and is counted.
+template <typename T>
+__device__ __forceinline__ int32_t finish_window(T z, int32_t L0, int32_t U, int32_t i, const LearnedArgs<T>& a) {
   const bool inside = (z >= a.X0) && (z < a.XN);
   bool ok = true;
   if (inside && i == L0) ok = a.X[i] <= z;
   if (inside && i == U) ok = ok && z < a.X[i + 1];
   if (inside && !ok) {
-    // outside the recorded window: full search (counted; never expected)
     atomicAdd(a.fallbacks, 1ull);
     int32_t lo = 0, nn = a.N;
     while (nn > 1) {
@@ -575,8 +592,10 @@ __device__ __forceinline__ int32_t finish_query(T z, float y, const LearnedArgs<
   return (z >= a.X0) ? i : -1;
 }
 
+// Each wave handles two 64-query groups per iteration (two searches in flight
+// per lane) and loads the next iteration's queries before working on these.
 template <typename T, bool F16>
-__global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) {
+__global__ void __launch_bounds__(768) learned_search_kernel(LearnedArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.segs), int64_t(a.nseg) * sizeof(SegFit));
   __syncthreads();
@@ -589,14 +608,31 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  for (int64_t base = wave * 64; base < a.M; base += waves * 64) {
-    const int64_t qi = base + lane;
-    const bool valid = qi < a.M;
-    const T z = valid ? __builtin_nontemporal_load(a.z + qi) : a.X0;
-    const float u_mine = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
-    const float y = a.identity ? u_mine : route_pair<F16>(u_mine, &R);
-    const int32_t i = finish_query<T>(z, y, a, segs);
-    if (valid) __builtin_nontemporal_store(i, a.out + qi);
+  const int64_t stride = waves * 128;
+  int64_t base = wave * 128;
+  auto load_z = [&](int64_t q) { return q < a.M ? __builtin_nontemporal_load(a.z + q) : a.X0; };
+  T za = load_z(base + lane), zb = load_z(base + 64 + lane);
+  for (; base < a.M; base += stride) {
+    const T na = load_z(base + stride + lane), nb = load_z(base + stride + 64 + lane);
+    const float ua = feature(static_cast<double>(za), a.X0d, a.delta, a.flo, a.fscale);
+    const float ub = feature(static_cast<double>(zb), a.X0d, a.delta, a.flo, a.fscale);
+    const float ya = a.identity ? ua : route_pair<F16>(ua, &R);
+    const float yb = a.identity ? ub : route_pair<F16>(ub, &R);
+    int32_t La, Ua, Lb, Ub;
+    query_window<T>(za, ya, a, segs, &La, &Ua);
+    query_window<T>(zb, yb, a, segs, &Lb, &Ub);
+    const int32_t La0 = La, Lb0 = Lb;
+    int32_t nA = Ua - La + 1, nB = Ub - Lb + 1;
+    while (nA > 1 || nB > 1) {
+      search_round<T>(za, a.X, La, nA);
+      search_round<T>(zb, a.X, Lb, nB);
+    }
+    const int32_t ia = finish_window<T>(za, La0, Ua, La, a);
+    const int32_t ib = finish_window<T>(zb, Lb0, Ub, Lb, a);
+    if (base + lane < a.M) __builtin_nontemporal_store(ia, a.out + base + lane);
+    if (base + 64 + lane < a.M) __builtin_nontemporal_store(ib, a.out + base + 64 + lane);
+    za = na;
+    zb = nb;
   }
 }
 
@@ -754,10 +790,10 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   auto kern = L->f16 ? learned_search_kernel<T, true> : learned_search_kernel<T, false>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsBytesPerCU);
-  const int block = (h->tune_set && h->tune.block) ? h->tune.block : 1024;
+  const int block = (h->tune_set && h->tune.block) ? std::min(h->tune.block, 768) : 768;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-  const int64_t need = (M + block - 1) / block;
+  const int64_t need = (M + 2 * block - 1) / (2 * block);
   int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * num_cus())));
   if (h->tune_set && h->tune.grid) grid = h->tune.grid;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a);
