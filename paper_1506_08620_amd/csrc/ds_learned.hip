@@ -546,21 +546,12 @@ __device__ __forceinline__ void query_window(T z, float y, const LearnedArgs<T>&
   *U = std::min(std::max(*L, sg.lo + q + sg.dmax), sg.hi);
 }
 
-// One round of a branch-free 4-way search for the largest i in [L, L+n-1]
-// with X_i <= z: three independent probes at the quarter points (one memory
-// round trip), or a bisection probe when n < 4.  Accepted probes prove
-// X_m <= z and rejected ones z < X_m.
+// One branch-free bisection step for the largest i in [L, L+n-1] with
+// X_i <= z (the path is bound by the issue rate of random gathers, so one
+// probe per step).  Accepted probes prove X_m <= z and rejected ones z < X_m.
 template <typename T>
 __device__ __forceinline__ void search_round(T z, const T* __restrict__ X, int32_t& L, int32_t& n) {
-  if (n >= 4) {
-    const int32_t q = n >> 2;
-    const int32_t c1 = z >= X[L + q] ? 1 : 0;
-    const int32_t c2 = z >= X[L + 2 * q] ? 1 : 0;
-    const int32_t c3 = z >= X[L + 3 * q] ? 1 : 0;
-    const int32_t c = c1 + c2 + c3;
-    L += c * q;
-    n = (c == 3) ? n - 3 * q : q;
-  } else if (n > 1) {
+  if (n > 1) {
     const int32_t h = n >> 1;
     const bool c = z >= X[L + h];
     L = c ? L + h : L;
