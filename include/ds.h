@@ -103,10 +103,12 @@ typedef struct ds_build_opts {
   int32_t learn_flags;      /* learned: bit mask of DS_LEARN_* */
 } ds_build_opts;
 
-/* learned: evaluate the router's 32x32 layer with FP16 inputs and FP32
- * accumulation at search time (the model is trained and stored in FP32; the
- * segments are built with the same FP16 router, so results stay exact) */
-#define DS_LEARN_FP16_ROUTER 1
+/* learned: the router is trained and stored in FP32.  By default the search
+ * (and the routing of the keys that defines the segments) evaluates its 32x32
+ * layer on the matrix cores with FP16 inputs and FP32 accumulation; this flag
+ * keeps FP32 inputs instead (4x the matrix-core time).  Either way routing is
+ * monotone and results are exact. */
+#define DS_LEARN_FP32_ROUTER 1
 
 /* Device layouts of the Direct tables (ds_tune.stage selects one):
  *   PLAIN     K (int32 per grid cell) and X, as in Sec. 4.

@@ -233,7 +233,7 @@ class Index:
 
 def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart: str = "phi",
           fallback: str = "none", table_cap_bytes: int = 0, learn_epochs: int = 0, learn_segments: int = 0,
-          learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), learn_fp16_router: bool = False,
+          learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), learn_fp32_router: bool = False,
           stream=None) -> Index:
     """ds_build over the N+1 values of x (a strictly increasing GPU tensor).
 
@@ -245,7 +245,7 @@ def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart:
         raise ValueError("x must be 1-D with at least two values")
     opts = BuildOpts(_METHODS[method], _FORMS[form], _HSTARTS[hstart], _FALLBACKS[fallback], int(table_cap_bytes),
                      int(learn_epochs), int(learn_segments), float(learn_rate), int(learn_batch), int(seed),
-                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp16_router else 0)
+                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp32_router else 0)
     h = ctypes.c_void_p()
     with torch.cuda.device(x.device):
         st = _lib.ds_build(x.data_ptr(), x.numel() - 1, _dtype_code(x), ctypes.byref(opts), _stream_handle(stream),

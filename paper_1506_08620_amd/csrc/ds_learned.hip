@@ -583,10 +583,10 @@ __device__ __forceinline__ int32_t finish_window(T z, int32_t L0, int32_t U, int
   return (z >= a.X0) ? i : -1;
 }
 
-// Each wave handles two 64-query groups per iteration (two searches in flight
-// per lane) and loads the next iteration's queries before working on these.
+// One 64-query group per wave and iteration; the next group's queries are
+// loaded before this group is worked on.
 template <typename T, bool F16>
-__global__ void __launch_bounds__(768) learned_search_kernel(LearnedArgs<T> a) {
+__global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.segs), int64_t(a.nseg) * sizeof(SegFit));
   __syncthreads();
@@ -599,31 +599,22 @@ __global__ void __launch_bounds__(768) learned_search_kernel(LearnedArgs<T> a) {
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t stride = waves * 128;
-  int64_t base = wave * 128;
+  const int64_t stride = waves * 64;
+  int64_t base = wave * 64;
   auto load_z = [&](int64_t q) { return q < a.M ? __builtin_nontemporal_load(a.z + q) : a.X0; };
-  T za = load_z(base + lane), zb = load_z(base + 64 + lane);
+  T z = load_z(base + lane);
   for (; base < a.M; base += stride) {
-    const T na = load_z(base + stride + lane), nb = load_z(base + stride + 64 + lane);
-    const float ua = feature(static_cast<double>(za), a.X0d, a.delta, a.flo, a.fscale);
-    const float ub = feature(static_cast<double>(zb), a.X0d, a.delta, a.flo, a.fscale);
-    const float ya = a.identity ? ua : route_pair<F16>(ua, &R);
-    const float yb = a.identity ? ub : route_pair<F16>(ub, &R);
-    int32_t La, Ua, Lb, Ub;
-    query_window<T>(za, ya, a, segs, &La, &Ua);
-    query_window<T>(zb, yb, a, segs, &Lb, &Ub);
-    const int32_t La0 = La, Lb0 = Lb;
-    int32_t nA = Ua - La + 1, nB = Ub - Lb + 1;
-    while (nA > 1 || nB > 1) {
-      search_round<T>(za, a.X, La, nA);
-      search_round<T>(zb, a.X, Lb, nB);
-    }
-    const int32_t ia = finish_window<T>(za, La0, Ua, La, a);
-    const int32_t ib = finish_window<T>(zb, Lb0, Ub, Lb, a);
-    if (base + lane < a.M) __builtin_nontemporal_store(ia, a.out + base + lane);
-    if (base + 64 + lane < a.M) __builtin_nontemporal_store(ib, a.out + base + 64 + lane);
-    za = na;
-    zb = nb;
+    const T z_next = load_z(base + stride + lane);
+    const float u = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
+    const float y = a.identity ? u : route_pair<F16>(u, &R);
+    int32_t L, U;
+    query_window<T>(z, y, a, segs, &L, &U);
+    const int32_t L0 = L;
+    int32_t n = U - L + 1;
+    while (n > 1) search_round<T>(z, a.X, L, n);
+    const int32_t i = finish_window<T>(z, L0, U, L, a);
+    if (base + lane < a.M) __builtin_nontemporal_store(i, a.out + base + lane);
+    z = z_next;
   }
 }
 
@@ -655,7 +646,7 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   if (nseg < 1 || nseg > 8192) return DS_ERR_ARG;
   L->nseg = nseg;
   L->identity = (o->learn_epochs < 0) ? 1 : 0;
-  L->f16 = (o->learn_flags & DS_LEARN_FP16_ROUTER) ? 1 : 0;
+  L->f16 = (o->learn_flags & DS_LEARN_FP32_ROUTER) ? 0 : 1;
   const int32_t batch = o->learn_batch > 0 ? o->learn_batch : 8192;
   const int32_t epochs = o->learn_epochs > 0 ? o->learn_epochs : (o->learn_epochs == 0 ? 60 : 0);
   const float lr = o->learn_rate > 0 ? o->learn_rate : 2e-3f;
@@ -781,10 +772,10 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   auto kern = L->f16 ? learned_search_kernel<T, true> : learned_search_kernel<T, false>;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                             kLdsBytesPerCU);
-  const int block = (h->tune_set && h->tune.block) ? std::min(h->tune.block, 768) : 768;
+  const int block = (h->tune_set && h->tune.block) ? h->tune.block : 1024;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-  const int64_t need = (M + 2 * block - 1) / (2 * block);
+  const int64_t need = (M + block - 1) / block;
   int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * num_cus())));
   if (h->tune_set && h->tune.grid) grid = h->tune.grid;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a);

@@ -104,9 +104,9 @@ def test_learned_exact_on_clustered_arrays(ds, dt):
         X = _clustered(n, dt, n)
         z = _queries(X, 100_000, rng)
         ref = oracle.search(X, z)
-        for epochs, f16 in ((20, False), (20, True), (-1, False)):  # trained router (FP32 / FP16 layer), no network
+        for epochs, f32 in ((20, False), (20, True), (-1, False)):  # trained router (FP16 / FP32 layer), no network
             idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=segs, seed=3,
-                           learn_fp16_router=f16)
+                           learn_fp32_router=f32)
             inf = idx.info()
             assert inf["method_name"] == "learned"
             _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
@@ -158,8 +158,8 @@ def test_full_size_clustered_f64_sampled(ds):
     X_d, z_d = _dev(X), _dev(z)
     idx = ds.build(X_d, method="learned")
     out = ds.search(idx, z_d)
-    idx16 = ds.build(X_d, method="learned", learn_fp16_router=True)
-    assert torch.equal(ds.search(idx16, z_d), out)
+    idx32 = ds.build(X_d, method="learned", learn_fp32_router=True)
+    assert torch.equal(ds.search(idx32, z_d), out)
     torch.cuda.synchronize()
     i = out.long()
     assert int(i.min()) >= 0 and int(i.max()) <= X.size - 2
