@@ -29,6 +29,37 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2", 5: "RANKCODE-L2"}
 
 
+def measured_traffic(dtype: str, ns, stage_name: str):
+    """HBM bytes per launch of the given sweep cases from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "direct_sweep_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1506_08620_amd", "csrc", "*"))) + [
+            os.path.join(ROOT, "include", "ds.h")]:
+        h.update(open(p, "rb").read())
+    vals, cases = {}, {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "case":
+            cases[(f[1], int(f[2]))] = (float(f[4]), float(f[6]))
+        else:
+            vals[f[0]] = f[1]
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    fs, ws = float(vals["fetch_scale"]), float(vals["write_scale"])
+    got = [cases[(dtype, n)] for n in ns if (dtype, n) in cases]
+    if not got or len(got) != len(ns):
+        return None
+    return sum((f * fs + w * ws) * 1024.0 for f, w in got) / len(got)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -40,6 +71,9 @@ def parse():
     p.add_argument("--m", type=int, default=0, help="queries per case (default 2^26)")
     p.add_argument("--no-batched", action="store_true", help="skip the 10,000-array batched workload")
     p.add_argument("--no-learned", action="store_true", help="skip the learned method on the clustered array")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="first run a plain device copy of 2^26 int32 (256 MiB read + 256 MiB written), the "
+                        "reference for scaling hardware traffic counters")
     return p.parse_args()
 
 
@@ -58,6 +92,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     M = args.m or W.SWEEP_M
     sizes = [int(s) for s in args.sizes.split(",")] if args.sizes else list(W.SWEEP_N)
     cases = []
@@ -119,19 +160,23 @@ def main():
                    table_bytes=inf["table_bytes"], build_ns_per_elem=round(c["build_s"] * 1e9 / (c["n"] + 1), 2))
         case_rows.append(row)
         key = (row["dtype"], row["layout"])
-        g = groups.setdefault(key, [0.0, 0, 0])
+        g = groups.setdefault(key, [0.0, 0, 0, []])
         g[0] += ms
         g[1] += 1
         g[2] += bytes_per_launch
+        g[3].append(c["n"])
     dom_key = max(groups, key=lambda k: groups[k][0])
     g = groups[dom_key]
     avg_ms = g[0] / g[1]
     avg_bytes = g[2] / g[1]
     achieved = avg_bytes / avg_ms / 1e6
     kernel_name = "direct_search_kernel<{},SUB,{}>".format("float" if dom_key[0] == "f32" else "double", dom_key[1])
+    traffic = measured_traffic(dom_key[0], g[3], dom_key[1])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=kernel_name,
-                    launches_per_step=g[1], bytes_per_launch=int(avg_bytes), avg_launch_ms=round(avg_ms, 5))
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None if traffic is None else int(traffic),
+                    kernel=kernel_name, cases=[f"{dom_key[0]} N={n}" for n in g[3]],
+                    launches_per_step=g[1], bytes_per_launch=int(avg_bytes), avg_launch_ms=round(avg_ms, 5),
+                    traffic_over_algorithmic=None if traffic is None else round(traffic / avg_bytes, 3))
 
     # CPU oracle on a bounded sample of the same workload
     cpu = None
