@@ -258,9 +258,11 @@ ds_status ds_learned_model(ds_handle h, float* params_host, int32_t capacity, ui
  * receives the index local to the query's array, with the out-of-domain
  * values of ds_search.  Per array the Direct method (Sec. 4, built on the
  * device with ComputeHR of Sec. 4.4.3, searched through the RANKCODE layout)
- * is used whenever it is feasible and its table fits the workspace; every
- * other array is searched with the offset binary search (Sec. 3.3).  Results
- * are identical either way.  Special arrays: N_k = -1 (no value) gives -1 for
+ * is used whenever it is feasible, its table is under direct_cap_bytes and it
+ * fits the workspace; every other array is searched with the learned method
+ * when learn_segments > 0 (a model per array, all trained together: each
+ * training step is one launch over all learned arrays) and with the offset
+ * binary search (Sec. 3.3) otherwise.  Results are identical either way.  Special arrays: N_k = -1 (no value) gives -1 for
  * all its queries; N_k = 0 (one value) gives -1 below X_0 and 0 otherwise; an
  * array that is not strictly increasing or holds NaN/inf gives -2.
  */
@@ -281,13 +283,21 @@ typedef struct ds_batch_desc {
   int32_t block;              /* threads per search workgroup, 64..1024 step 64; 0 = auto (1024) */
   int32_t lds_bytes;          /* LDS budget per search workgroup; 0 = auto (159 KiB), -1 = never stage */
   int32_t qpt;                /* queries in flight per lane: 4, 8 or 16; 0 = auto (8) */
+  int32_t learn_segments;     /* > 0: arrays where Direct is infeasible, over direct_cap_bytes or out of
+                                 table room use the learned method with this many segments per array
+                                 (the workspace must be sized with the same value); 0: binary search */
+  int32_t learn_steps;        /* learned: training steps (one batched launch each); 0 = 300 */
   int32_t reserved_;
+  int64_t direct_cap_bytes;   /* per-array cap on the Direct table (4 bytes per grid cell); 0 = none */
 } ds_batch_desc;
 
 /* Bytes of workspace for K arrays holding total_x values in all, with room for
  * table_budget_entries Direct grid cells in all (arrays whose table does not
- * fit the remaining room use binary search).  0 on bad arguments. */
-size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries);
+ * fit the remaining room use another method) and, when learn_segments > 0,
+ * for one learned model of that many segments per array.  0 on bad
+ * arguments. */
+size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries,
+                                int32_t learn_segments);
 
 /* Enqueue the batched build + search on s.  No host synchronisation, no
  * allocation; the workspace may be reused by the next call once this one has
@@ -307,10 +317,15 @@ ds_status ds_batch_autotune(ds_batch_desc* d, hipStream_t s);
 
 /* Per-array outcome of the last ds_search_batched on this descriptor's
  * workspace (a synchronous device-to-host copy on s): method_host[k] is
- * DS_METHOD_DIRECT, DS_METHOD_BSEARCH_OFFSET, -1 (array not strictly
+ * DS_METHOD_DIRECT, DS_METHOD_LEARNED, DS_METHOD_BSEARCH_OFFSET, -1 (array not strictly
  * increasing or not finite) or -2 (N_k <= 0); R_host[k] is the array's R for
  * Direct, else -1.  Both are host arrays of K entries. */
 ds_status ds_batch_report(const ds_batch_desc* d, int32_t* method_host, int64_t* R_host, hipStream_t s);
+
+/* Number of learned-method queries of the last ds_search_batched on this
+ * workspace that fell outside their recorded window and took the full binary
+ * search (expected 0).  Synchronous on s. */
+ds_status ds_batch_fallbacks(const ds_batch_desc* d, uint64_t* count_host, hipStream_t s);
 
 #ifdef __cplusplus
 }

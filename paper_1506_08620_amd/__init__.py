@@ -45,6 +45,7 @@ METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 # exported symbols of libds.so (every function ds.h declares)
 SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_autotune", "ds_info", "ds_copy_table", "ds_destroy", "ds_status_str",
            "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_autotune", "ds_batch_report",
+           "ds_batch_fallbacks",
            "ds_learned_grad", "ds_learned_forward", "ds_learned_model")
 N_ROUTER_PARAMS = 1153
 
@@ -79,7 +80,8 @@ class BatchDesc(ctypes.Structure):
                 ("workspace_dev", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("total_x", ctypes.c_int64), ("total_q", ctypes.c_int64), ("form", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("block", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("qpt", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("qpt", ctypes.c_int32), ("learn_segments", ctypes.c_int32), ("learn_steps", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32), ("direct_cap_bytes", ctypes.c_int64)]
 
 
 class DsError(RuntimeError):
@@ -109,7 +111,7 @@ def _load_library():
     lib.ds_destroy.restype = i32
     lib.ds_status_str.argtypes = [i32]
     lib.ds_status_str.restype = ctypes.c_char_p
-    lib.ds_batch_workspace_bytes.argtypes = [i32, i64, i64]
+    lib.ds_batch_workspace_bytes.argtypes = [i32, i64, i64, i32]
     lib.ds_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.ds_search_batched.argtypes = [ctypes.POINTER(BatchDesc), vp]
     lib.ds_search_batched.restype = i32
@@ -119,6 +121,8 @@ def _load_library():
     lib.ds_learned_forward.restype = i32
     lib.ds_learned_model.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_uint64), vp]
     lib.ds_learned_model.restype = i32
+    lib.ds_batch_fallbacks.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.ds_batch_fallbacks.restype = i32
     lib.ds_batch_autotune.argtypes = [ctypes.POINTER(BatchDesc), vp]
     lib.ds_batch_autotune.restype = i32
     lib.ds_batch_report.argtypes = [ctypes.POINTER(BatchDesc), vp, vp, vp]
@@ -318,8 +322,10 @@ def learned_forward(params: torch.Tensor, u: torch.Tensor, fp16_router: bool = F
 
 # ---- batched ----------------------------------------------------------------
 
-def batch_workspace_bytes(num_arrays: int, total_x: int, table_budget_entries: int = 0) -> int:
-    return int(_lib.ds_batch_workspace_bytes(int(num_arrays), int(total_x), int(table_budget_entries)))
+def batch_workspace_bytes(num_arrays: int, total_x: int, table_budget_entries: int = 0,
+                          learn_segments: int = 0) -> int:
+    return int(_lib.ds_batch_workspace_bytes(int(num_arrays), int(total_x), int(table_budget_entries),
+                                             int(learn_segments)))
 
 
 class Batch:
@@ -328,7 +334,8 @@ class Batch:
     def __init__(self, x_off: torch.Tensor, X: torch.Tensor, q_off: torch.Tensor, z: torch.Tensor,
                  out: torch.Tensor | None = None, *, form: str = "sub", table_budget_entries: int | None = None,
                  tile: int = 0, block: int = 0, lds_bytes: int = 0, qpt: int = 0, total_x: int | None = None,
-                 total_q: int | None = None):
+                 total_q: int | None = None, learn_segments: int = 0, learn_steps: int = 0,
+                 direct_cap_bytes: int = 0):
         for t, n in ((x_off, "x_off"), (X, "X"), (q_off, "q_off"), (z, "z")):
             _check_device(t, n)
         if x_off.dtype != torch.int64 or q_off.dtype != torch.int64:
@@ -345,13 +352,14 @@ class Batch:
             out = torch.empty(self.total_q, dtype=torch.int32, device=z.device)
         if table_budget_entries is None:
             table_budget_entries = 8 * self.total_x + 64 * k
-        ws = batch_workspace_bytes(k, self.total_x, table_budget_entries)
+        ws = batch_workspace_bytes(k, self.total_x, table_budget_entries, learn_segments)
         self.workspace = torch.empty(max(ws, 1), dtype=torch.uint8, device=z.device)
         self.keep = (x_off, X, q_off, z, out)
         self.out = out
         self.desc = BatchDesc(_dtype_code(X), k, x_off.data_ptr(), X.data_ptr(), q_off.data_ptr(), z.data_ptr(),
                               out.data_ptr(), self.workspace.data_ptr(), ws, self.total_x, self.total_q,
-                              _FORMS[form], int(tile), int(block), int(lds_bytes), int(qpt), 0)
+                              _FORMS[form], int(tile), int(block), int(lds_bytes), int(qpt), int(learn_segments),
+                              int(learn_steps), 0, int(direct_cap_bytes))
         self.device = z.device
 
     def run(self, stream=None) -> torch.Tensor:
@@ -385,6 +393,13 @@ class Batch:
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)
         return best
+
+    def fallbacks(self, stream=None) -> int:
+        c = ctypes.c_uint64()
+        st = _lib.ds_batch_fallbacks(ctypes.byref(self.desc), ctypes.byref(c), _stream_handle(stream))
+        if st != OK:
+            raise DsError(st, "ds_batch_fallbacks")
+        return int(c.value)
 
     def set_shape(self, tile: int = 0, block: int = 0, lds_bytes: int = 0, qpt: int = 0):
         self.desc.tile, self.desc.block, self.desc.lds_bytes, self.desc.qpt = int(tile), int(block), int(lds_bytes), int(qpt)

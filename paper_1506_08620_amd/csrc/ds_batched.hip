@@ -28,75 +28,68 @@
 #include <algorithm>
 #include <limits>
 
+#include "ds_batched_internal.h"
 #include "ds_ops.h"
 
 namespace ds {
 
 namespace {
 
-constexpr int32_t kBmInvalid = -1;   // report value: X_k not strictly increasing or not finite
-constexpr int32_t kBmTrivial = -2;   // report value: N_k <= 0
-constexpr int kNumQueues = 8;        // one tile queue per XCD
 constexpr int kBuildBlock = 256;
 constexpr int kPlanBlock = 1024;
 constexpr int kMaxGrowthRounds = 4096;
 
-template <typename T>
-struct alignas(16) ArrMeta {
-  T H, W, X0, XN;
-  int64_t x_off;    // first value of the array in X_packed
-  int64_t q_off;    // first query
-  int64_t q_end;    // one past the last query
-  int64_t w_off;    // first RANKCODE word in the word pool
-  int64_t c_off;    // first code in the code pool
-  int64_t t_off;    // first tile of the array
-  int32_t N, R, jmin, nW;
-  int32_t method;   // DS_METHOD_DIRECT, DS_METHOD_BSEARCH_OFFSET, kBmInvalid, kBmTrivial
-  int32_t n_updates;
-  int32_t pad0, pad1;
-};
-
-struct PlanTotals {
-  int64_t total_tiles;
-  int64_t words_used;
-  uint32_t queue[kNumQueues];
-};
-
 struct WsLayout {
-  size_t meta, tile_off, totals, bits, base, codes, end;
+  size_t meta, tile_off, totals, codes, bits, base, end;
+  // learned region (present when nseg > 0)
+  size_t lmeta, params, adam_m, adam_v, partial, loss, segs, first, feat, route;
   int64_t words_budget;
   int64_t codes_cap;
+  int32_t nseg;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-WsLayout ws_layout(int32_t K, int64_t total_x, int64_t words_budget) {
+WsLayout ws_layout(int32_t K, int64_t total_x, int64_t words_budget, int32_t nseg) {
   WsLayout L{};
   size_t off = 0;
-  L.meta = off;
-  off = align256(off + size_t(K) * sizeof(ArrMeta<double>));
-  L.tile_off = off;
-  off = align256(off + size_t(K + 1) * sizeof(int64_t));
-  L.totals = off;
-  off = align256(off + sizeof(PlanTotals));
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  L.meta = take(size_t(K) * sizeof(ArrMeta<double>));
+  L.tile_off = take(size_t(K + 1) * sizeof(int64_t));
+  L.totals = take(sizeof(PlanTotals));
   L.codes_cap = total_x + int64_t(K) * 8 + 8;
-  L.codes = off;
-  off = align256(off + size_t(L.codes_cap) * 2);
+  L.codes = take(size_t(L.codes_cap) * 2);
+  L.nseg = nseg;
+  if (nseg > 0) {
+    const size_t P = size_t(kRouterParams) * 4;
+    L.lmeta = take(size_t(K) * sizeof(LearnMeta));
+    L.params = take(size_t(K) * P);
+    L.adam_m = take(size_t(K) * P);
+    L.adam_v = take(size_t(K) * P);
+    L.partial = take(size_t(K) * kBatchLearnParts * P);
+    L.loss = take(size_t(K) * kBatchLearnParts * 4);
+    L.segs = take(size_t(K) * size_t(nseg) * kSegFitBytes);
+    L.first = take(size_t(K) * size_t(nseg + 1) * 4);
+    L.feat = take(size_t(total_x) * 4);
+    L.route = take(size_t(total_x) * 4);
+  }
   L.words_budget = words_budget;
-  L.bits = off;
-  off = align256(off + size_t(words_budget) * 8);
-  L.base = off;
-  off = align256(off + size_t(words_budget) * 4);
+  L.bits = take(size_t(words_budget) * 8);
+  L.base = take(size_t(words_budget) * 4);
   L.end = off;
   return L;
 }
 
 // largest words budget whose layout fits in a workspace of the given size
-int64_t words_budget_for(int32_t K, int64_t total_x, size_t bytes) {
-  const WsLayout L0 = ws_layout(K, total_x, 0);
+int64_t words_budget_for(int32_t K, int64_t total_x, int32_t nseg, size_t bytes) {
+  const WsLayout L0 = ws_layout(K, total_x, 0, nseg);
   if (bytes <= L0.end) return 0;
   int64_t w = int64_t((bytes - L0.end) / 12);
-  while (w > 0 && ws_layout(K, total_x, w).end > bytes) w -= std::max<int64_t>(1, w / 64);
+  while (w > 0 && ws_layout(K, total_x, w, nseg).end > bytes) w -= std::max<int64_t>(1, w / 64);
   return std::max<int64_t>(0, w);
 }
 
@@ -268,14 +261,26 @@ __global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __
 template <typename T>
 __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict__ meta, int32_t K,
                                                           int64_t* __restrict__ tile_off, PlanTotals* __restrict__ tot,
-                                                          int64_t words_budget, int64_t tile) {
-  __shared__ int64_t s_w[kPlanBlock], s_c[kPlanBlock], s_t[kPlanBlock];
-  __shared__ int64_t carry_w, carry_c, carry_t;
+                                                          int64_t words_budget, int64_t tile, int32_t learn,
+                                                          int64_t direct_cap_cells, LearnMeta* __restrict__ lmeta) {
+  __shared__ int64_t s_w[kPlanBlock], s_c[kPlanBlock], s_t[kPlanBlock], s_l[kPlanBlock];
+  __shared__ int64_t carry_w, carry_c, carry_t, carry_l;
   const int tid = threadIdx.x;
   if (tid == 0) {
-    carry_w = carry_c = carry_t = 0;
+    carry_w = carry_c = carry_t = carry_l = 0;
   }
-  if (tid < kNumQueues) tot->queue[tid] = 0;
+  if (tid < kNumQueues) {
+    tot->queue[tid] = 0;
+    tot->lqueue[tid] = 0;
+  }
+  if (tid == 0) tot->fallbacks = 0;
+  // Direct over the per-array table cap is treated like an infeasible array
+  for (int32_t k = tid; k < K; k += kPlanBlock) {
+    ArrMeta<T>& m = meta[k];
+    if (m.method == DS_METHOD_DIRECT && direct_cap_cells > 0 && int64_t(m.R) - m.jmin + 1 > direct_cap_cells)
+      m.method = DS_METHOD_BSEARCH_OFFSET;
+    if (learn && m.method == DS_METHOD_BSEARCH_OFFSET) m.method = DS_METHOD_LEARNED;
+  }
   __syncthreads();
   for (int32_t base = 0; base < K; base += kPlanBlock) {
     const int32_t k = base + tid;
@@ -315,7 +320,8 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
       tile_off[k] = t0;
       if (m.method == DS_METHOD_DIRECT) {
         if (w0 + nw > words_budget) {
-          m.method = DS_METHOD_BSEARCH_OFFSET;  // table does not fit the workspace
+          // the table does not fit the workspace
+          m.method = learn ? DS_METHOD_LEARNED : DS_METHOD_BSEARCH_OFFSET;
           m.w_off = 0;
           m.c_off = 0;
         } else {
@@ -325,10 +331,42 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
       }
     }
     __syncthreads();
+    // learned arrays take consecutive model slots
+    const int64_t isl = (k < K && meta[k].method == DS_METHOD_LEARNED) ? 1 : 0;
+    s_l[tid] = isl;
+    __syncthreads();
+    for (int d = 1; d < kPlanBlock; d <<= 1) {
+      const int64_t a = tid >= d ? s_l[tid - d] : 0;
+      __syncthreads();
+      s_l[tid] += a;
+      __syncthreads();
+    }
+    if (isl) {
+      ArrMeta<T>& m = meta[k];
+      const int32_t slot = static_cast<int32_t>(carry_l + s_l[tid] - 1);
+      m.slot = slot;
+      LearnMeta lm{};
+      lm.X0 = static_cast<double>(m.X0);
+      lm.XN = static_cast<double>(m.XN);
+      const double range = lm.XN - lm.X0;
+      lm.delta = std::fmax(range * 0x1p-40, 1e-300);
+      const double d0 = lm.delta, d1 = range + lm.delta;
+      int64_t b0, b1;
+      __builtin_memcpy(&b0, &d0, 8);
+      __builtin_memcpy(&b1, &d1, 8);
+      lm.flo = static_cast<double>(b0);
+      lm.fscale = 1.0 / (static_cast<double>(b1) - lm.flo);
+      lm.x_off = m.x_off;
+      lm.N = m.N;
+      lm.k = k;
+      lmeta[slot] = lm;
+    }
+    __syncthreads();
     if (tid == kPlanBlock - 1) {
       carry_w += s_w[tid];
       carry_c += s_c[tid];
       carry_t += s_t[tid];
+      carry_l += s_l[tid];
     }
     __syncthreads();
   }
@@ -336,6 +374,7 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
     tile_off[K] = carry_t;
     tot->total_tiles = carry_t;
     tot->words_used = carry_w;
+    tot->n_learned = static_cast<int32_t>(carry_l);
   }
 }
 
@@ -508,6 +547,8 @@ __global__ void __launch_bounds__(1024) batch_search_kernel(const ArrMeta<T>* __
                                       codes + m.c_off, Xp + m.x_off, m.H, m.W, m.X0, vlo, vhi, m.XN, m.jmin, m.N};
         run_tile<T, QPT>(z, out, q0, q1, op);
       }
+    } else if (m.method == DS_METHOD_LEARNED) {
+      continue;  // searched by the learned kernel
     } else if (m.method == DS_METHOD_BSEARCH_OFFSET) {
       const bool fits = (N + 1) * int64_t(sizeof(T)) <= sh.lds_budget;
       if (k != cur) {
@@ -574,14 +615,48 @@ SearchShape shape_of(const ds_batch_desc* d) {
   return sh;
 }
 
+WsLayout layout_of(const ds_batch_desc* d) {
+  const int32_t nseg = d->learn_segments > 0 ? d->learn_segments : 0;
+  return ws_layout(d->num_arrays, d->total_x, words_budget_for(d->num_arrays, d->total_x, nseg, d->workspace_bytes),
+                   nseg);
+}
+
 template <typename T>
 ds_status launch_plan(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws, int64_t tile, hipStream_t s) {
-  plan_kernel<T><<<dim3(1), dim3(kPlanBlock), 0, s>>>(reinterpret_cast<ArrMeta<T>*>(ws + L.meta), d->num_arrays,
-                                                       reinterpret_cast<int64_t*>(ws + L.tile_off),
-                                                       reinterpret_cast<PlanTotals*>(ws + L.totals), L.words_budget,
-                                                       tile);
+  const int64_t cap_cells = d->direct_cap_bytes > 0 ? d->direct_cap_bytes / 4 : 0;
+  plan_kernel<T><<<dim3(1), dim3(kPlanBlock), 0, s>>>(
+      reinterpret_cast<ArrMeta<T>*>(ws + L.meta), d->num_arrays, reinterpret_cast<int64_t*>(ws + L.tile_off),
+      reinterpret_cast<PlanTotals*>(ws + L.totals), L.words_budget, tile, L.nseg > 0 ? 1 : 0, cap_cells,
+      L.nseg > 0 ? reinterpret_cast<LearnMeta*>(ws + L.lmeta) : nullptr);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
+}
+
+BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws) {
+  BatchLearned b{};
+  b.meta = ws + L.meta;
+  b.tile_off = reinterpret_cast<const int64_t*>(ws + L.tile_off);
+  b.tot = reinterpret_cast<PlanTotals*>(ws + L.totals);
+  b.K = d->num_arrays;
+  b.nseg = L.nseg;
+  b.steps = d->learn_steps > 0 ? d->learn_steps : 300;
+  b.fp32_router = 0;
+  b.seed = 0x1506ull;
+  b.tile = d->tile > 0 ? d->tile : (int64_t(1) << 19);
+  b.X = d->X_dev;
+  b.z = d->z_dev;
+  b.out = d->out_dev;
+  b.lmeta = reinterpret_cast<LearnMeta*>(ws + L.lmeta);
+  b.params = reinterpret_cast<float*>(ws + L.params);
+  b.adam_m = reinterpret_cast<float*>(ws + L.adam_m);
+  b.adam_v = reinterpret_cast<float*>(ws + L.adam_v);
+  b.partial = reinterpret_cast<float*>(ws + L.partial);
+  b.loss = reinterpret_cast<float*>(ws + L.loss);
+  b.segs = ws + L.segs;
+  b.first = reinterpret_cast<int32_t*>(ws + L.first);
+  b.feat = reinterpret_cast<float*>(ws + L.feat);
+  b.route = reinterpret_cast<int32_t*>(ws + L.route);
+  return b;
 }
 
 // Times the search phase for each launch shape on the arrays already built in
@@ -589,7 +664,7 @@ ds_status launch_plan(const ds_batch_desc* d, const WsLayout& L, unsigned char* 
 template <typename T, int FORM>
 ds_status autotune_batched(ds_batch_desc* d, hipStream_t s) {
   unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
-  const WsLayout L = ws_layout(d->num_arrays, d->total_x, words_budget_for(d->num_arrays, d->total_x, d->workspace_bytes));
+  const WsLayout L = layout_of(d);
   hipEvent_t e0, e1;
   DS_HIP_CHECK(hipEventCreate(&e0));
   DS_HIP_CHECK(hipEventCreate(&e1));
@@ -639,25 +714,30 @@ template <typename T, int FORM>
 ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
   const int32_t K = d->num_arrays;
   unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
-  const int64_t wb = words_budget_for(K, d->total_x, d->workspace_bytes);
-  const WsLayout L = ws_layout(K, d->total_x, wb);
+  const WsLayout L = layout_of(d);
+  const int64_t wb = L.words_budget;
   const int64_t tile = d->tile > 0 ? d->tile : (int64_t(1) << 19);
   auto* meta = reinterpret_cast<ArrMeta<T>*>(ws + L.meta);
   build_hr_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(d->x_off_dev, d->q_off_dev,
                                                                   static_cast<const T*>(d->X_dev), meta);
   DS_HIP_CHECK(hipGetLastError());
-  plan_kernel<T><<<dim3(1), dim3(kPlanBlock), 0, s>>>(meta, K, reinterpret_cast<int64_t*>(ws + L.tile_off),
-                                                       reinterpret_cast<PlanTotals*>(ws + L.totals), wb, tile);
-  DS_HIP_CHECK(hipGetLastError());
+  ds_status st = launch_plan<T>(d, L, ws, tile, s);
+  if (st != DS_OK) return st;
   rankcode_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(
       static_cast<const T*>(d->X_dev), meta, reinterpret_cast<unsigned long long*>(ws + L.bits),
       reinterpret_cast<uint32_t*>(ws + L.base), reinterpret_cast<uint16_t*>(ws + L.codes), wb);
   DS_HIP_CHECK(hipGetLastError());
+  if (L.nseg > 0) {
+    st = batched_learned_build(learned_of(d, L, ws), d->dtype, s);
+    if (st != DS_OK) return st;
+  }
   if (d->total_q == 0) return DS_OK;
   const SearchShape sh = shape_of(d);
   const int block = d->block > 0 ? d->block : 1024;
   const int qpt = d->qpt > 0 ? d->qpt : 8;
-  return launch_search_qpt<T, FORM>(d, L, ws, sh, block, qpt, s);
+  st = launch_search_qpt<T, FORM>(d, L, ws, sh, block, qpt, s);
+  if (st != DS_OK || L.nseg == 0) return st;
+  return batched_learned_search(learned_of(d, L, ws), d->dtype, s);
 }
 
 }  // namespace
@@ -666,11 +746,13 @@ ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
 
 extern "C" {
 
-size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries) {
-  if (num_arrays < 0 || total_x < 0 || table_budget_entries < 0) return 0;
+size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries,
+                                int32_t learn_segments) {
+  if (num_arrays < 0 || total_x < 0 || table_budget_entries < 0 || learn_segments < 0 || learn_segments > 8192)
+    return 0;
   // each array's words are rounded up to a multiple of 4, plus one partial word
   const int64_t words = table_budget_entries > 0 ? table_budget_entries / 64 + int64_t(num_arrays) * 4 + 16 : 0;
-  return ds::ws_layout(num_arrays, total_x, words).end;
+  return ds::ws_layout(num_arrays, total_x, words, learn_segments).end;
 }
 
 ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s) {
@@ -685,7 +767,10 @@ ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s) {
   if (d->block != 0 && (d->block < 64 || d->block > 1024 || d->block % 64)) return DS_ERR_ARG;
   if (d->qpt != 0 && d->qpt != 4 && d->qpt != 8 && d->qpt != 16) return DS_ERR_ARG;
   if (d->tile < 0) return DS_ERR_ARG;
-  if (d->workspace_bytes < ds_batch_workspace_bytes(d->num_arrays, d->total_x, 0)) return DS_ERR_ARG;
+  if (d->learn_segments < 0 || d->learn_segments > 8192 || d->learn_steps < 0 || d->direct_cap_bytes < 0)
+    return DS_ERR_ARG;
+  if (d->workspace_bytes < ds_batch_workspace_bytes(d->num_arrays, d->total_x, 0, d->learn_segments))
+    return DS_ERR_ARG;
   if (d->dtype == DS_F32)
     return d->form == DS_FORM_FMA ? ds::run_batched<float, DS_FORM_FMA>(d, s) : ds::run_batched<float, DS_FORM_SUB>(d, s);
   return d->form == DS_FORM_FMA ? ds::run_batched<double, DS_FORM_FMA>(d, s) : ds::run_batched<double, DS_FORM_SUB>(d, s);
@@ -702,12 +787,23 @@ ds_status ds_batch_autotune(ds_batch_desc* d, hipStream_t s) {
                                 : ds::autotune_batched<double, DS_FORM_SUB>(d, s);
 }
 
+ds_status ds_batch_fallbacks(const ds_batch_desc* d, uint64_t* count_host, hipStream_t s) {
+  if (!d || !count_host || !d->workspace_dev || d->num_arrays < 0) return DS_ERR_ARG;
+  const ds::WsLayout L = ds::layout_of(d);
+  const auto* tot = reinterpret_cast<const ds::PlanTotals*>(static_cast<const unsigned char*>(d->workspace_dev) +
+                                                             L.totals);
+  unsigned long long v = 0;
+  DS_HIP_CHECK(hipMemcpyAsync(&v, &tot->fallbacks, sizeof(v), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  *count_host = v;
+  return DS_OK;
+}
+
 ds_status ds_batch_report(const ds_batch_desc* d, int32_t* method_host, int64_t* R_host, hipStream_t s) {
   if (!d || d->num_arrays < 0) return DS_ERR_ARG;
   if (d->num_arrays == 0) return DS_OK;
   if (!method_host || !R_host || !d->workspace_dev) return DS_ERR_ARG;
-  const int64_t wb = ds::words_budget_for(d->num_arrays, d->total_x, d->workspace_bytes);
-  const ds::WsLayout L = ds::ws_layout(d->num_arrays, d->total_x, wb);
+  const ds::WsLayout L = ds::layout_of(d);
   const size_t msz = d->dtype == DS_F32 ? sizeof(ds::ArrMeta<float>) : sizeof(ds::ArrMeta<double>);
   unsigned char* host = static_cast<unsigned char*>(std::malloc(msz * size_t(d->num_arrays)));
   if (!host) return DS_ERR_OOM;

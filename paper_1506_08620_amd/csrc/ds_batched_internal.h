@@ -1,0 +1,81 @@
+// Declarations shared by the batched path (ds_batched.hip) and the batched
+// learned method (ds_learned.hip).
+#pragma once
+
+#include "ds_internal.h"
+
+namespace ds {
+
+constexpr int32_t kBmInvalid = -1;   // report value: X_k not strictly increasing or not finite
+constexpr int32_t kBmTrivial = -2;   // report value: N_k <= 0
+constexpr int kNumQueues = 8;        // one tile queue per XCD
+constexpr int kRouterParams = 1153;  // 1 -> 32 -> 32 -> 1 router
+constexpr int kSegFitBytes = 32;
+constexpr int kBatchLearnSamples = 4096;  // training samples per array and step
+constexpr int kBatchLearnParts = kBatchLearnSamples / 256;
+
+template <typename T>
+struct alignas(16) ArrMeta {
+  T H, W, X0, XN;
+  int64_t x_off;    // first value of the array in X_packed
+  int64_t q_off;    // first query
+  int64_t q_end;    // one past the last query
+  int64_t w_off;    // first RANKCODE word in the word pool
+  int64_t c_off;    // first code in the code pool
+  int64_t t_off;    // first tile of the array
+  int32_t N, R, jmin, nW;
+  int32_t method;   // DS_METHOD_DIRECT, _BSEARCH_OFFSET, _LEARNED, kBmInvalid, kBmTrivial
+  int32_t n_updates;
+  int32_t slot;     // learned: index of the array's model
+  int32_t pad;
+};
+
+struct PlanTotals {
+  int64_t total_tiles;
+  int64_t words_used;
+  uint32_t queue[kNumQueues];   // Direct / binary-search tiles
+  uint32_t lqueue[kNumQueues];  // learned tiles
+  int32_t n_learned;
+  int32_t pad;
+  unsigned long long fallbacks;  // learned queries that left their window
+};
+
+// per learned array: the feature's constants and where its keys are
+struct alignas(16) LearnMeta {
+  double X0, XN, delta, flo, fscale;
+  int64_t x_off;
+  int32_t N;
+  int32_t k;   // array index
+};
+
+// device pointers of the batched learned method inside the workspace
+struct BatchLearned {
+  const void* meta;        // ArrMeta<T>[K]
+  const int64_t* tile_off;
+  PlanTotals* tot;
+  int32_t K;
+  int32_t nseg;
+  int32_t steps;
+  int32_t fp32_router;
+  uint64_t seed;
+  int64_t tile;
+  const void* X;
+  const void* z;
+  int32_t* out;
+  LearnMeta* lmeta;        // [K] (first n_learned used)
+  float* params;           // [K][kRouterParams]
+  float* adam_m;
+  float* adam_v;
+  float* partial;          // [K][kBatchLearnParts][kRouterParams]
+  float* loss;             // [K][kBatchLearnParts]
+  void* segs;              // [K][nseg] segment fits
+  int32_t* first;          // [K][nseg + 1]
+  float* feat;             // [total_x]
+  int32_t* route;          // [total_x]
+};
+
+// implemented in ds_learned.hip
+ds_status batched_learned_build(const BatchLearned& b, int dtype, hipStream_t s);
+ds_status batched_learned_search(const BatchLearned& b, int dtype, hipStream_t s);
+
+}  // namespace ds

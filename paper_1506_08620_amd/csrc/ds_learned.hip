@@ -27,12 +27,14 @@
 #include <type_traits>
 #include <vector>
 
+#include "ds_batched_internal.h"
 #include "ds_ops.h"
 
 namespace ds {
 
 constexpr int kHid = 32;
 constexpr int kParams = 2 * kHid + kHid * kHid + kHid + kHid + 1;  // 1153
+static_assert(kParams == kRouterParams, "router parameter count");
 constexpr int oW1 = 0, oB1 = 32, oW2 = 64, oB2 = 64 + 1024, oW3 = 64 + 1024 + 32, oB3 = 64 + 1024 + 64;
 constexpr int kTrainBlock = 256;
 
@@ -43,6 +45,7 @@ struct alignas(16) SegFit {
   float a, b;
   int32_t dmin, dmax, lo, hi;
 };
+static_assert(sizeof(SegFit) == kSegFitBytes, "segment record size");
 
 struct LearnedModel {
   float* params = nullptr;      // kParams
@@ -247,11 +250,27 @@ __device__ __forceinline__ int32_t seg_predict(const SegFit& sg, T z) {
 // ---------------------------------------------------------------------------
 // build kernels
 
+// Kernels below serve one array, or, when lm is given, every learned array of
+// a batch at once: blockIdx.y (blockIdx.x for the Adam step) selects the
+// model slot, and lm[slot] gives the array's keys and feature constants.
 template <typename T>
 __global__ void feature_kernel(const T* __restrict__ X, int64_t n, double X0, double delta, double flo, double fscale,
-                               float* __restrict__ u) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) u[i] = feature(static_cast<double>(X[i]), X0, delta, flo, fscale);
+                               float* __restrict__ u, const LearnMeta* __restrict__ lm,
+                               const PlanTotals* __restrict__ tot) {
+  if (lm) {
+    const int slot = blockIdx.y;
+    if (slot >= tot->n_learned) return;
+    const LearnMeta L = lm[slot];
+    X += L.x_off;
+    u += L.x_off;
+    n = L.N + 1;
+    X0 = L.X0;
+    delta = L.delta;
+    flo = L.flo;
+    fscale = L.fscale;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    u[i] = feature(static_cast<double>(X[i]), X0, delta, flo, fscale);
 }
 
 __device__ __forceinline__ uint32_t mix32(uint64_t x) {
@@ -270,7 +289,18 @@ __device__ __forceinline__ uint32_t mix32(uint64_t x) {
 __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
     const float* __restrict__ params, const float* __restrict__ feat, int64_t n_keys, uint64_t seed, int64_t step,
     int32_t batch, const float* __restrict__ u_in, const float* __restrict__ t_in, float* __restrict__ partial,
-    float* __restrict__ loss_partial) {
+    float* __restrict__ loss_partial, const LearnMeta* __restrict__ lm, const PlanTotals* __restrict__ tot) {
+  if (lm) {
+    const int slot = blockIdx.y;
+    if (slot >= tot->n_learned) return;
+    const LearnMeta L = lm[slot];
+    params += (int64_t)slot * kParams;
+    feat += L.x_off;
+    n_keys = L.N + 1;
+    seed += 0x632BE59BD9B4E019ull * static_cast<uint64_t>(slot + 1);
+    partial += (int64_t)slot * gridDim.x * kParams;
+    loss_partial += (int64_t)slot * gridDim.x;
+  }
   __shared__ float sp[kParams];
   __shared__ float s_da2[kTrainBlock][kHid + 1];
   __shared__ float s_h1[kTrainBlock][kHid + 1];
@@ -375,7 +405,16 @@ __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
 __global__ void __launch_bounds__(1024) adam_kernel(float* __restrict__ params, float* __restrict__ m,
                                                     float* __restrict__ v, const float* __restrict__ partial,
                                                     int32_t n_parts, float lr, float beta1, float beta2, float eps,
-                                                    int64_t t, float* __restrict__ grad_out) {
+                                                    int64_t t, float* __restrict__ grad_out,
+                                                    const PlanTotals* __restrict__ tot) {
+  if (tot) {
+    const int slot = blockIdx.x;
+    if (slot >= tot->n_learned) return;
+    params += (int64_t)slot * kParams;
+    m += (int64_t)slot * kParams;
+    v += (int64_t)slot * kParams;
+    partial += (int64_t)slot * n_parts * kParams;
+  }
   for (int k = threadIdx.x; k < kParams; k += blockDim.x) {
     float g = 0.0f;
     for (int b = 0; b < n_parts; ++b) g += partial[(int64_t)b * kParams + k];
@@ -409,38 +448,70 @@ template <bool F16>
 __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict__ params,
                                                          const float* __restrict__ feat, int64_t n,
                                                          int32_t nseg, int32_t identity, int32_t* __restrict__ route,
-                                                         float* __restrict__ y_out) {
+                                                         float* __restrict__ y_out, const LearnMeta* __restrict__ lm,
+                                                         const PlanTotals* __restrict__ tot) {
+  if (lm) {
+    const int slot = blockIdx.y;
+    if (slot >= tot->n_learned) return;
+    const LearnMeta L = lm[slot];
+    params += (int64_t)slot * kParams;
+    feat += L.x_off;
+    route += L.x_off;
+    n = L.N + 1;
+  }
   typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
   if constexpr (F16)
     load_router16(params, R);
   else
     load_router(params, R);
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t i = wave * 64 + lane;
-  const float u_mine = i < n ? feat[i] : 1.0f;
-  const float y = identity ? u_mine : route_pair<F16>(u_mine, &R);
-  if (i < n) {
-    route[i] = segment_of(y, nseg);
-    if (y_out) y_out[i] = y;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wave * 64 < n; wave += waves) {
+    const int64_t i = wave * 64 + lane;
+    const float u_mine = i < n ? feat[i] : 1.0f;
+    const float y = identity ? u_mine : route_pair<F16>(u_mine, &R);
+    if (i < n) {
+      route[i] = segment_of(y, nseg);
+      if (y_out) y_out[i] = y;
+    }
   }
 }
 
 // first[s] = #{i : route_i < s} for s in [0, nseg]
 __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, int32_t nseg,
-                                 int32_t* __restrict__ first) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n) return;
-  const int32_t prev = (i == 0) ? -1 : route[i - 1];
-  const int32_t cur = (i == n) ? nseg : route[i];
-  for (int32_t s = prev + 1; s <= cur; ++s) first[s] = static_cast<int32_t>(i);
+                                 int32_t* __restrict__ first, const LearnMeta* __restrict__ lm,
+                                 const PlanTotals* __restrict__ tot) {
+  if (lm) {
+    const int slot = blockIdx.y;
+    if (slot >= tot->n_learned) return;
+    const LearnMeta L = lm[slot];
+    route += L.x_off;
+    first += (int64_t)slot * (nseg + 1);
+    n = L.N + 1;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t prev = (i == 0) ? -1 : route[i - 1];
+    const int32_t cur = (i == n) ? nseg : route[i];
+    for (int32_t s = prev + 1; s <= cur; ++s) first[s] = static_cast<int32_t>(i);
+  }
 }
 
 // least-squares line of index against z for the keys of one segment (f64
 // sums over centred z), then the key errors over [lo, hi + 1]
 template <typename T>
 __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, int64_t N,
-                                                      const int32_t* __restrict__ first, SegFit* __restrict__ segs) {
+                                                      const int32_t* __restrict__ first, SegFit* __restrict__ segs,
+                                                      const LearnMeta* __restrict__ lm,
+                                                      const PlanTotals* __restrict__ tot) {
+  if (lm) {
+    const int slot = blockIdx.y;
+    if (slot >= tot->n_learned) return;
+    const LearnMeta L = lm[slot];
+    X += L.x_off;
+    N = L.N;
+    first += (int64_t)slot * (gridDim.x + 1);
+    segs += (int64_t)slot * gridDim.x;
+  }
   const int s = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t a = first[s], b = first[s + 1];  // keys [a, b)
@@ -689,17 +760,19 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   const unsigned long long zero = 0;
   DS_HIP_CHECK(hipMemcpyAsync(L->fallbacks, &zero, 8, hipMemcpyHostToDevice, s));
   feature_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, n, static_cast<double>(ends[0]),
-                                                                             L->delta, L->flo, L->fscale, L->feat);
+                                                                             L->delta, L->flo, L->fscale, L->feat,
+                                                                             nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
   // training: epochs passes of n / batch steps, cosine-decayed step size
   const int64_t steps = L->identity ? 0 : std::max<int64_t>(1, int64_t(epochs) * ((n + batch - 1) / batch));
   for (int64_t st = 0; st < steps; ++st) {
     train_step_kernel<<<dim3(n_parts), dim3(kTrainBlock), 0, s>>>(L->params, L->feat, n, o->seed, st, batch, nullptr,
-                                                                  nullptr, L->partial, L->loss_partial);
+                                                                  nullptr, L->partial, L->loss_partial, nullptr,
+                                                                  nullptr);
     const float frac = static_cast<float>(st) / static_cast<float>(steps);
     const float lr_t = lr * (0.05f + 0.95f * 0.5f * (1.0f + std::cos(3.14159265f * frac)));
     adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(L->params, L->adam_m, L->adam_v, L->partial, n_parts, lr_t, 0.9f,
-                                               0.999f, 1e-8f, st + 1, nullptr);
+                                               0.999f, 1e-8f, st + 1, nullptr, nullptr);
   }
   DS_HIP_CHECK(hipGetLastError());
   if (steps > 0) {
@@ -713,12 +786,14 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   // route the keys with the search-time router, then segments, fits and bounds
   if (L->f16)
     route_keys_kernel<true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
-                                                                                  L->identity, L->route, nullptr);
+                                                                                  L->identity, L->route, nullptr, nullptr, nullptr);
   else
     route_keys_kernel<false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
-                                                                                   L->identity, L->route, nullptr);
-  seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first);
-  seg_fit_kernel<T><<<dim3(nseg), dim3(256), 0, s>>>(X, N, L->first, L->segs);
+                                                                                   L->identity, L->route, nullptr,
+                                                                                   nullptr, nullptr);
+  seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first,
+                                                                                nullptr, nullptr);
+  seg_fit_kernel<T><<<dim3(nseg), dim3(256), 0, s>>>(X, N, L->first, L->segs, nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
   std::vector<SegFit> host(nseg);
   DS_HIP_CHECK(hipMemcpyAsync(host.data(), L->segs, size_t(nseg) * sizeof(SegFit), hipMemcpyDeviceToHost, s));
@@ -807,6 +882,185 @@ void learned_free(ds_index* h) {
   h->learned = nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// batched learned method: every learned array of a batch has its own model
+// slot; all slots are initialised, trained (one launch per step for all of
+// them), routed and fitted together, then searched by a persistent kernel
+// that pulls the learned arrays' query tiles.
+
+namespace {
+
+__device__ __forceinline__ float unit_hash(uint64_t seed, uint64_t a, uint64_t b) {
+  return static_cast<float>(mix32(seed * 0x9E3779B97F4A7C15ull + a * 0xBF58476D1CE4E5B9ull + b) >> 8) *
+         (1.0f / 16777216.0f);
+}
+
+// the same starting point as the single-array build: layer-1 ramps spread over
+// [0, 1], layer 2 averaging them, the output averaging layer 2
+__global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ params, float* __restrict__ m,
+                                                         float* __restrict__ v, const PlanTotals* __restrict__ tot,
+                                                         uint64_t seed) {
+  const int slot = blockIdx.x;
+  if (slot >= tot->n_learned) return;
+  float* p = params + (int64_t)slot * kParams;
+  const int t = threadIdx.x;
+  if (t < kHid) {
+    const float w = 4.0f + 4.0f * unit_hash(seed, slot, t);
+    p[oW1 + t] = w;
+    p[oB1 + t] = 0.5f - w * (t + 0.5f) / kHid;
+    float sum = 0.0f;
+    for (int k = 0; k < kHid; ++k) {
+      const float w2 = (0.5f + unit_hash(seed, slot, 1000 + t * kHid + k)) / kHid;
+      p[oW2 + t * kHid + k] = w2;
+      sum += w2;
+    }
+    p[oB2 + t] = 0.5f - 0.5f * sum;
+    p[oW3 + t] = 1.0f / kHid;
+  }
+  if (t == 0) p[oB3] = 0.0f;
+  for (int k = t; k < kParams; k += blockDim.x) {
+    m[(int64_t)slot * kParams + k] = 0.0f;
+    v[(int64_t)slot * kParams + k] = 0.0f;
+  }
+}
+
+template <typename T, bool F16>
+__global__ void __launch_bounds__(1024) batch_learned_search_kernel(BatchLearned b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int64_t s_tile;
+  __shared__ int32_t s_k;
+  const ArrMeta<T>* meta = static_cast<const ArrMeta<T>*>(b.meta);
+  const int queue = blockIdx.x % kNumQueues;
+  const int64_t total = b.tot->total_tiles;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
+  int32_t cur = -1;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int64_t li = atomicAdd(&b.tot->lqueue[queue], 1u);
+      const int64_t ch = 4;
+      const int64_t g = ((li / ch) * kNumQueues + queue) * ch + (li % ch);
+      int32_t k = -1;
+      if (g < total) {
+        int32_t lo = 0, hi = b.K - 1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi + 1) >> 1;
+          if (b.tile_off[mid] <= g)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        k = lo;
+      }
+      s_tile = g;
+      s_k = k;
+    }
+    __syncthreads();
+    const int64_t g = s_tile;
+    const int32_t k = s_k;
+    __syncthreads();
+    if (g >= total) break;
+    const ArrMeta<T>& m = meta[k];
+    if (m.method != DS_METHOD_LEARNED) continue;
+    const int32_t slot = m.slot;
+    if (slot != cur) {
+      stage_bytes(smem, static_cast<const unsigned char*>(b.segs) + (int64_t)slot * b.nseg * kSegFitBytes,
+                  int64_t(b.nseg) * kSegFitBytes);
+      __syncthreads();
+      if constexpr (F16)
+        load_router16(b.params + (int64_t)slot * kParams, R);
+      else
+        load_router(b.params + (int64_t)slot * kParams, R);
+      cur = slot;
+    }
+    const LearnMeta lm = b.lmeta[slot];
+    LearnedArgs<T> a{};
+    a.X = static_cast<const T*>(b.X) + m.x_off;
+    a.fallbacks = &b.tot->fallbacks;
+    a.X0 = m.X0;
+    a.XN = m.XN;
+    a.N = m.N;
+    a.nseg = b.nseg;
+    const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
+    const int64_t q0 = m.q_off + (g - m.t_off) * b.tile;
+    const int64_t q1 = std::min(m.q_end, q0 + b.tile);
+    const T* z = static_cast<const T*>(b.z);
+    for (int64_t base = q0 + int64_t(wave) * 64; base < q1; base += int64_t(nwaves) * 64) {
+      const int64_t q = base + lane;
+      const T zq = q < q1 ? z[q] : a.X0;
+      const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
+      const float y = route_pair<F16>(u, &R);
+      int32_t L, U;
+      query_window<T>(zq, y, a, segs, &L, &U);
+      const int32_t L0 = L;
+      int32_t n = U - L + 1;
+      while (n > 1) search_round<T>(zq, a.X, L, n);
+      const int32_t i = finish_window<T>(zq, L0, U, L, a);
+      if (q < q1) b.out[q] = i;
+    }
+    __syncthreads();  // every wave is done with this array's tables before they may change
+  }
+}
+
+template <typename T>
+ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
+  const int K = b.K;
+  init_params_kernel<<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, b.tot, b.seed);
+  feature_kernel<T><<<dim3(64, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, 0, 0, 0, 0, b.feat, b.lmeta,
+                                                       b.tot);
+  DS_HIP_CHECK(hipGetLastError());
+  const float lr = 2e-3f;
+  for (int st = 0; st < b.steps; ++st) {
+    train_step_kernel<<<dim3(kBatchLearnParts, K), dim3(kTrainBlock), 0, s>>>(
+        b.params, b.feat, 0, b.seed, st, kBatchLearnSamples, nullptr, nullptr, b.partial, b.loss, b.lmeta, b.tot);
+    const float frac = static_cast<float>(st) / static_cast<float>(b.steps);
+    const float lr_t = lr * (0.05f + 0.95f * 0.5f * (1.0f + std::cos(3.14159265f * frac)));
+    adam_kernel<<<dim3(K), dim3(1024), 0, s>>>(b.params, b.adam_m, b.adam_v, b.partial, kBatchLearnParts, lr_t, 0.9f,
+                                               0.999f, 1e-8f, st + 1, nullptr, b.tot);
+  }
+  DS_HIP_CHECK(hipGetLastError());
+  if (b.fp32_router)
+    route_keys_kernel<false><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, 0, b.nseg, 0, b.route, nullptr,
+                                                               b.lmeta, b.tot);
+  else
+    route_keys_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, 0, b.nseg, 0, b.route, nullptr,
+                                                              b.lmeta, b.tot);
+  seg_first_kernel<<<dim3(64, K), dim3(256), 0, s>>>(b.route, 0, b.nseg, b.first, b.lmeta, b.tot);
+  seg_fit_kernel<T><<<dim3(b.nseg, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, b.first,
+                                                            static_cast<SegFit*>(b.segs), b.lmeta, b.tot);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+template <typename T>
+ds_status batched_learned_search_typed(const BatchLearned& b, hipStream_t s) {
+  auto kern = b.fp32_router ? batch_learned_search_kernel<T, false> : batch_learned_search_kernel<T, true>;
+  const int lds = b.nseg * kSegFitBytes;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytesPerCU);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 1024, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  int grid = per_cu * num_cus();
+  grid = std::max(kNumQueues, grid / kNumQueues * kNumQueues);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, s, b);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
+}  // namespace
+
+ds_status batched_learned_build(const BatchLearned& b, int dtype, hipStream_t s) {
+  if (b.nseg < 1 || b.nseg * kSegFitBytes > kLdsBytesPerCU) return DS_ERR_ARG;
+  return dtype == DS_F32 ? batched_learned_build_typed<float>(b, s) : batched_learned_build_typed<double>(b, s);
+}
+
+ds_status batched_learned_search(const BatchLearned& b, int dtype, hipStream_t s) {
+  return dtype == DS_F32 ? batched_learned_search_typed<float>(b, s) : batched_learned_search_typed<double>(b, s);
+}
+
+
 void learned_fill_info(const ds_index* h, ds_info_t* in) {
   const LearnedModel* L = h->learned;
   if (!L) return;
@@ -831,9 +1085,9 @@ ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const flo
     return DS_ERR_OOM;
   }
   ds::train_step_kernel<<<dim3(n_parts), dim3(ds::kTrainBlock), 0, s>>>(params_dev, nullptr, 1, 0, 0, batch, u_dev,
-                                                                        t_dev, partial, lp);
+                                                                        t_dev, partial, lp, nullptr, nullptr);
   ds::adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(nullptr, nullptr, nullptr, partial, n_parts, 0, 0, 0, 0, 1,
-                                                 grad_dev);
+                                                 grad_dev, nullptr);
   if (loss_dev) ds::sum_kernel<<<1, 64, 0, s>>>(lp, n_parts, loss_dev);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -850,10 +1104,10 @@ ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_
   if (hipMalloc(&route, size_t(n) * 4) != hipSuccess) return DS_ERR_OOM;
   if (fp16_router)
     ds::route_keys_kernel<true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0,
-                                                                                      route, y_dev);
+                                                                                      route, y_dev, nullptr, nullptr);
   else
     ds::route_keys_kernel<false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0,
-                                                                                       route, y_dev);
+                                                                                       route, y_dev, nullptr, nullptr);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(route);

@@ -72,13 +72,14 @@ def test_no_oracle_in_the_product():
 def test_batch_workspace_sizing_is_monotone():
     lib = _lib()
     lib.ds_batch_workspace_bytes.restype = ctypes.c_size_t
-    lib.ds_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
-    base = lib.ds_batch_workspace_bytes(100, 10_000, 0)
+    lib.ds_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+    base = lib.ds_batch_workspace_bytes(100, 10_000, 0, 0)
     assert base > 100 * 64
     prev = base
     for budget in (64, 1 << 10, 1 << 20, 1 << 30):
-        cur = lib.ds_batch_workspace_bytes(100, 10_000, budget)
+        cur = lib.ds_batch_workspace_bytes(100, 10_000, budget, 0)
         assert cur >= prev and cur >= base + budget // 64 * 12
         prev = cur
-    assert lib.ds_batch_workspace_bytes(-1, 10, 0) == 0
-    assert lib.ds_batch_workspace_bytes(0, 0, 0) > 0
+    assert lib.ds_batch_workspace_bytes(-1, 10, 0, 0) == 0
+    assert lib.ds_batch_workspace_bytes(0, 0, 0, 0) > 0
+    assert lib.ds_batch_workspace_bytes(100, 10_000, 0, 4096) > base + 100 * 4096 * 32

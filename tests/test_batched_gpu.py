@@ -230,3 +230,76 @@ def test_full_size_batched_f32_sampled(ds):
         sel = ks == k
         ref[sel] = oracle.search(b.array(k), zs[sel])
     _assert_same(got, ref)
+
+
+def _mixture_batch(ns, m_each, seed):
+    rng = np.random.default_rng(seed)
+    arrays = [W.mixture_array(int(n), rng) for n in ns]
+    X = np.concatenate(arrays)
+    x_off = np.concatenate([[0], np.cumsum([a.size for a in arrays])]).astype(np.int64)
+    zs = [W.mixture_queries(a, m_each, rng) for a in arrays]
+    z = np.concatenate(zs)
+    q_off = np.concatenate([[0], np.cumsum([q.size for q in zs])]).astype(np.int64)
+    return W.Batch(np.dtype(np.float64), x_off, X, q_off, z)
+
+
+def test_batched_learned_mixture_exact(ds):
+    b = _mixture_batch((300, 2000, 9000, 40000, 70000, 5), 60_000, 21)
+    bt, out = _run(ds, b, learn_segments=1024, learn_steps=60)
+    meth, _ = bt.report()
+    assert (meth == ds.METHOD_LEARNED).any()
+    assert set(meth.tolist()) <= {ds.METHOD_DIRECT, ds.METHOD_LEARNED}
+    _assert_same(out, _oracle_batch(b.x_off, b.X, b.q_off, b.z))
+    assert bt.fallbacks() == 0
+    # forcing every array off Direct with a tiny per-array cap keeps the results
+    bt2, out2 = _run(ds, b, learn_segments=512, learn_steps=20, direct_cap_bytes=64)
+    meth2, _ = bt2.report()
+    assert np.all((meth2 == ds.METHOD_LEARNED))
+    _assert_same(out2, out)
+    assert bt2.fallbacks() == 0
+
+
+def test_batched_learned_f32_and_shapes(ds):
+    b = W.batched_f32(num_arrays=30, n_lo=8, n_hi=30000, q_per_n=8, seed=22)
+    ref = _oracle_batch(b.x_off, b.X, b.q_off, b.z)
+    bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z), learn_segments=256, learn_steps=10,
+                  direct_cap_bytes=4 * 4096)
+    for tile in (1000, 1 << 16):
+        bt.set_shape(tile=tile)
+        _assert_same(bt.run().cpu().numpy(), ref)
+    meth, _ = bt.report()
+    assert (meth == ds.METHOD_LEARNED).any() and (meth == ds.METHOD_DIRECT).any()
+
+
+def test_full_size_batched_learned_f64_sampled(ds):
+    """256 mixture arrays, N_k log-uniform in [2^14, 2^20], 2^28 queries (70 % uniform, 20 % hits,
+    10 % nextafter(X_i, -inf)); Direct where its table fits under 64 MB, the learned method elsewhere."""
+    b = W.batched_mixture(with_queries=False)
+    z = W.batched_mixture_queries_torch(b, DEV)
+    x_off_d, X_d, q_off_d = _dev(b.x_off), _dev(b.X), _dev(b.q_off)
+    bt = ds.Batch(x_off_d, X_d, q_off_d, z, learn_segments=4096, direct_cap_bytes=64 << 20)
+    out = bt.run()
+    torch.cuda.synchronize()
+    meth, _ = bt.report()
+    assert set(meth.tolist()) <= {ds.METHOD_DIRECT, ds.METHOD_LEARNED}
+    assert bt.fallbacks() == 0
+    for a in range(0, b.num_arrays, 32):
+        e = min(b.num_arrays, a + 32)
+        q0, q1 = int(b.q_off[a]), int(b.q_off[e])
+        counts = torch.from_numpy(np.diff(b.q_off[a:e + 1])).to(DEV)
+        base = torch.repeat_interleave(x_off_d[a:e], counts)
+        nk = torch.repeat_interleave(x_off_d[a + 1:e + 1] - x_off_d[a:e] - 1, counts)
+        i = out[q0:q1].long()
+        assert bool(torch.all((i >= 0) & (i < nk)))
+        zz = z[q0:q1]
+        assert bool(torch.all(X_d[base + i] <= zz)) and bool(torch.all(zz < X_d[base + i + 1]))
+        del counts, base, nk, i
+    pos = np.sort(np.random.default_rng(14).integers(0, int(b.q_off[-1]), 1 << 18))
+    zs = z[torch.from_numpy(pos).to(DEV)].cpu().numpy()
+    got = out[torch.from_numpy(pos).to(DEV)].cpu().numpy()
+    ks = np.searchsorted(b.q_off, pos, side="right") - 1
+    ref = np.empty_like(got)
+    for k in np.unique(ks):
+        sel = ks == k
+        ref[sel] = oracle.search(b.array(k), zs[sel])
+    _assert_same(got, ref)

@@ -338,3 +338,38 @@ def batched_queries_torch(batch: Batch, device, seed: int = SEED_BATCHED, chunk_
         z[q0:q1] = torch.minimum(torch.maximum(v, lo.to(tdt)), top.to(tdt))
         del lo, hi, top, u, v
     return z
+
+
+def batched_mixture_queries_torch(batch: Batch, device, seed: int = SEED_MIXTURE, chunk_arrays: int = 16):
+    """Device-side queries of the mixture workload: per array 70 % uniform in [X_0, X_N),
+    20 % exact hits X_i (i < N), 10 % nextafter(X_i, -inf) (i >= 1), shuffled within the array."""
+    import torch
+
+    tdt = torch.float32 if batch.dtype == np.float32 else torch.float64
+    total = int(batch.q_off[-1])
+    z = torch.empty(total, dtype=tdt, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed & (2**63 - 1))
+    X_d = torch.from_numpy(batch.X).to(device)
+    for k in range(batch.num_arrays):
+        q0, q1 = int(batch.q_off[k]), int(batch.q_off[k + 1])
+        m = q1 - q0
+        if m == 0:
+            continue
+        x0, x1 = int(batch.x_off[k]), int(batch.x_off[k + 1])
+        n = x1 - x0 - 1
+        mu = int(round(0.7 * m))
+        mh = int(round(0.2 * m))
+        mb = m - mu - mh
+        lo, hi = float(batch.X[x0]), float(batch.X[x1 - 1])
+        u = torch.rand(mu, dtype=torch.float64, device=device, generator=g)
+        zu = (lo + u * (hi - lo)).to(tdt)
+        top = torch.nextafter(X_d[x1 - 1:x1], torch.tensor([-np.inf], dtype=tdt, device=device))
+        zu = torch.minimum(torch.maximum(zu, X_d[x0:x0 + 1]), top)
+        ih = torch.randint(0, n, (mh,), device=device, generator=g) + x0
+        ib = torch.randint(1, n + 1, (mb,), device=device, generator=g) + x0
+        zb = torch.nextafter(X_d[ib], torch.full((mb,), -np.inf, dtype=tdt, device=device))
+        zz = torch.cat([zu, X_d[ih], zb])
+        perm = torch.randperm(m, device=device, generator=g)
+        z[q0:q1] = zz[perm]
+    return z
