@@ -845,8 +845,9 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   a.identity = L->identity;
   const int lds = static_cast<int>(int64_t(L->nseg) * sizeof(SegFit));
   auto kern = L->f16 ? learned_search_kernel<T, true> : learned_search_kernel<T, false>;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsBytesPerCU);
+  if (lds > 64 * 1024)
+    DS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     lds));
   const int block = (h->tune_set && h->tune.block) ? h->tune.block : 1024;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
@@ -1038,8 +1039,9 @@ template <typename T>
 ds_status batched_learned_search_typed(const BatchLearned& b, hipStream_t s) {
   auto kern = b.fp32_router ? batch_learned_search_kernel<T, false> : batch_learned_search_kernel<T, true>;
   const int lds = b.nseg * kSegFitBytes;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsBytesPerCU);
+  if (lds > 64 * 1024)
+    DS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     lds));
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 1024, lds) != hipSuccess || per_cu < 1) per_cu = 1;
   int grid = per_cu * num_cus();
