@@ -212,6 +212,7 @@ def main():
         extras["learned_f64_clustered"] = bench_learned(ds, W, dev, stream, reps=5, direct_ref=direct_f64_2p20)
     if not args.no_batched:
         extras["batched_f32"] = bench_batched(ds, W, dev, stream, reps=3)
+        extras["batched_learned_f64_mixture"] = bench_batched_learned(ds, W, dev, stream, reps=2)
 
     line = {
         "metric": "Gqueries/s and %HBM peak: Direct vs learned vs binary search, FP32/FP64",
@@ -360,6 +361,38 @@ def bench_batched(ds, W, dev, stream, reps):
                gq_s_end_to_end=round(total_q / ms / 1e6, 2),
                hbm_frac_streaming=round(total_q * 8 / ms / 1e6 / HBM_PEAK_GBS, 4),
                direct_arrays=int((meth == ds.METHOD_DIRECT).sum()), autotuned_shape=shape)
+    del z, bt
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_batched_learned(ds, W, dev, stream, reps):
+    """256 f64 mixture arrays (N_k log-uniform in [2^14, 2^20]), 2^28 queries: one
+    ds_search_batched call = device build of every array, training of the learned
+    arrays' models (all together), routing, fits and search; Direct where its table
+    fits under 64 MB.  Timed end to end with HIP events."""
+    import torch
+
+    b = W.batched_mixture(with_queries=False)
+    z = W.batched_mixture_queries_torch(b, dev)
+    bt = ds.Batch(torch.from_numpy(b.x_off).to(dev), torch.from_numpy(b.X).to(dev),
+                  torch.from_numpy(b.q_off).to(dev), z, learn_segments=4096, direct_cap_bytes=64 << 20)
+    bt.run(stream)
+    torch.cuda.synchronize()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        bt.run(stream)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / reps
+    total_q = int(b.q_off[-1])
+    meth, _ = bt.report()
+    res = dict(arrays=b.num_arrays, total_x=int(b.x_off[-1]), total_q=total_q, ms_end_to_end=round(ms, 3),
+               gq_s_end_to_end=round(total_q / ms / 1e6, 2),
+               direct_arrays=int((meth == ds.METHOD_DIRECT).sum()),
+               learned_arrays=int((meth == ds.METHOD_LEARNED).sum()), fallbacks=bt.fallbacks(),
+               note="end to end includes the device build and 300 training steps of every learned model")
     del z, bt
     torch.cuda.empty_cache()
     return res

@@ -351,42 +351,43 @@ __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
   }
 #pragma unroll
   for (int k = 0; k < kHid; ++k) s_h1[tid][k] = h1[k];
-  // per-sample gradients of the small tensors: dW1, db1 (32 each), dW3 (32), db3 (1)
   float* out = partial + (int64_t)blockIdx.x * kParams;
-  __shared__ float s_g1[kTrainBlock][kHid + 1];
-#pragma unroll
-  for (int k = 0; k < kHid; ++k) s_g1[tid][k] = (h1[k] > 0.0f && h1[k] < 1.0f) ? dh1[k] : 0.0f;  // da1
-  __shared__ float s_h2[kTrainBlock][kHid + 1];
-#pragma unroll
-  for (int k = 0; k < kHid; ++k) s_h2[tid][k] = h2[k];
-  s_small[tid][0] = dy;
-  s_small[tid][1] = u;
-  s_small[tid][2] = l;
   __syncthreads();
-  // W2 gradient: G[jj][k] = sum_s da2[s][jj] h1[s][k]; 1024 outputs, 4 per thread
+  // phase 1 (LDS holds da2 and h1 of every sample):
+  // dW2[jj][k] = sum_s da2[s][jj] h1[s][k] (1024 outputs, 4 per thread), db2
   for (int o = tid; o < kHid * kHid; o += kTrainBlock) {
     const int jj = o / kHid, k = o % kHid;
     float g = 0.0f;
     for (int s = 0; s < kTrainBlock; ++s) g = std::fma(s_da2[s][jj], s_h1[s][k], g);
     out[oW2 + o] = g;
   }
-  // the 129 + 32 small gradients, one thread each
+  if (tid < kHid) {
+    float gb2 = 0.0f;
+    for (int s = 0; s < kTrainBlock; ++s) gb2 += s_da2[s][tid];
+    out[oB2 + tid] = gb2;
+  }
+  __syncthreads();
+  // phase 2 (the same LDS now holds da1 and h2): dW1, db1, dW3, db3 and the loss
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) s_da2[tid][k] = (h1[k] > 0.0f && h1[k] < 1.0f) ? dh1[k] : 0.0f;  // da1
+#pragma unroll
+  for (int k = 0; k < kHid; ++k) s_h1[tid][k] = h2[k];
+  s_small[tid][0] = dy;
+  s_small[tid][1] = u;
+  s_small[tid][2] = l;
+  __syncthreads();
   if (tid < kHid) {
     float gw1 = 0.0f, gb1 = 0.0f;
     for (int s = 0; s < kTrainBlock; ++s) {
-      gw1 = std::fma(s_g1[s][tid], s_small[s][1], gw1);
-      gb1 += s_g1[s][tid];
+      gw1 = std::fma(s_da2[s][tid], s_small[s][1], gw1);
+      gb1 += s_da2[s][tid];
     }
     out[oW1 + tid] = gw1;
     out[oB1 + tid] = gb1;
   } else if (tid < 2 * kHid) {
     const int jj = tid - kHid;
-    float gb2 = 0.0f, gw3 = 0.0f;
-    for (int s = 0; s < kTrainBlock; ++s) {
-      gb2 += s_da2[s][jj];
-      gw3 = std::fma(s_small[s][0], s_h2[s][jj], gw3);
-    }
-    out[oB2 + jj] = gb2;
+    float gw3 = 0.0f;
+    for (int s = 0; s < kTrainBlock; ++s) gw3 = std::fma(s_small[s][0], s_h1[s][jj], gw3);
     out[oW3 + jj] = gw3;
   } else if (tid == 2 * kHid) {
     float gb3 = 0.0f, ls = 0.0f;
@@ -925,8 +926,10 @@ __global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ par
   }
 }
 
+constexpr int kBatchLearnedBlock = 768;  // 170 registers per lane: the search state fits without spills
+
 template <typename T, bool F16>
-__global__ void __launch_bounds__(1024) batch_learned_search_kernel(BatchLearned b) {
+__global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kernel(BatchLearned b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int64_t s_tile;
   __shared__ int32_t s_k;
@@ -990,7 +993,7 @@ __global__ void __launch_bounds__(1024) batch_learned_search_kernel(BatchLearned
     const T* z = static_cast<const T*>(b.z);
     for (int64_t base = q0 + int64_t(wave) * 64; base < q1; base += int64_t(nwaves) * 64) {
       const int64_t q = base + lane;
-      const T zq = q < q1 ? z[q] : a.X0;
+      const T zq = q < q1 ? __builtin_nontemporal_load(z + q) : a.X0;
       const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
       const float y = route_pair<F16>(u, &R);
       int32_t L, U;
@@ -999,7 +1002,7 @@ __global__ void __launch_bounds__(1024) batch_learned_search_kernel(BatchLearned
       int32_t n = U - L + 1;
       while (n > 1) search_round<T>(zq, a.X, L, n);
       const int32_t i = finish_window<T>(zq, L0, U, L, a);
-      if (q < q1) b.out[q] = i;
+      if (q < q1) __builtin_nontemporal_store(i, b.out + q);
     }
     __syncthreads();  // every wave is done with this array's tables before they may change
   }
@@ -1043,10 +1046,11 @@ ds_status batched_learned_search_typed(const BatchLearned& b, hipStream_t s) {
     DS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      lds));
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 1024, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchLearnedBlock, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
   int grid = per_cu * num_cus();
   grid = std::max(kNumQueues, grid / kNumQueues * kNumQueues);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(1024), lds, s, b);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBatchLearnedBlock), lds, s, b);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }
