@@ -608,7 +608,7 @@ ds_status launch_search_qpt(const ds_batch_desc* d, const WsLayout& L, unsigned 
 
 SearchShape shape_of(const ds_batch_desc* d) {
   SearchShape sh{};
-  sh.tile = d->tile > 0 ? d->tile : (int64_t(1) << 19);
+  sh.tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
   sh.lds_budget = d->lds_bytes < 0 ? 0 : (d->lds_bytes > 0 ? std::min(d->lds_bytes, kLdsBytesPerCU - 1024)
                                                             : kLdsBytesPerCU - 1024);
   sh.chunk = 4;
@@ -642,7 +642,7 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.steps = d->learn_steps > 0 ? d->learn_steps : 300;
   b.fp32_router = 0;
   b.seed = 0x1506ull;
-  b.tile = d->tile > 0 ? d->tile : (int64_t(1) << 19);
+  b.tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
   b.X = d->X_dev;
   b.z = d->z_dev;
   b.out = d->out_dev;
@@ -716,7 +716,7 @@ ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
   unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
   const WsLayout L = layout_of(d);
   const int64_t wb = L.words_budget;
-  const int64_t tile = d->tile > 0 ? d->tile : (int64_t(1) << 19);
+  const int64_t tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
   auto* meta = reinterpret_cast<ArrMeta<T>*>(ws + L.meta);
   build_hr_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(d->x_off_dev, d->q_off_dev,
                                                                   static_cast<const T*>(d->X_dev), meta);

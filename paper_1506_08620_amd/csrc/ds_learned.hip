@@ -991,9 +991,13 @@ __global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kerne
     const int64_t q0 = m.q_off + (g - m.t_off) * b.tile;
     const int64_t q1 = std::min(m.q_end, q0 + b.tile);
     const T* z = static_cast<const T*>(b.z);
-    for (int64_t base = q0 + int64_t(wave) * 64; base < q1; base += int64_t(nwaves) * 64) {
+    const int64_t step = int64_t(nwaves) * 64;
+    int64_t base = q0 + int64_t(wave) * 64;
+    T zq = (base + lane < q1) ? __builtin_nontemporal_load(z + base + lane) : a.X0;
+    for (; base < q1; base += step) {
       const int64_t q = base + lane;
-      const T zq = q < q1 ? __builtin_nontemporal_load(z + q) : a.X0;
+      const int64_t qn = q + step;
+      const T z_next = qn < q1 ? __builtin_nontemporal_load(z + qn) : a.X0;
       const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
       const float y = route_pair<F16>(u, &R);
       int32_t L, U;
@@ -1003,6 +1007,7 @@ __global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kerne
       while (n > 1) search_round<T>(zq, a.X, L, n);
       const int32_t i = finish_window<T>(zq, L0, U, L, a);
       if (q < q1) __builtin_nontemporal_store(i, b.out + q);
+      zq = z_next;
     }
     __syncthreads();  // every wave is done with this array's tables before they may change
   }
