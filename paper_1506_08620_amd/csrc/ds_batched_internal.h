@@ -11,7 +11,7 @@ constexpr int32_t kBmTrivial = -2;   // report value: N_k <= 0
 constexpr int kNumQueues = 8;        // one tile queue per XCD
 constexpr int kRouterParams = 1153;  // 1 -> 32 -> 32 -> 1 router
 constexpr int kSegFitBytes = 32;
-constexpr int kBatchLearnSamples = 4096;  // training samples per array and step
+constexpr int kBatchLearnSamples = 2048;  // training samples per array and step
 constexpr int kBatchLearnParts = kBatchLearnSamples / 256;
 
 template <typename T>
