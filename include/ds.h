@@ -118,7 +118,10 @@ typedef struct ds_build_opts {
  *             one bit telling whether X_i is the first float of its code class.
  *             The compare-and-fix is decided from the codes; only a tie on a
  *             non-first element reads X_t.  About 2.4 bytes per element, so
- *             N ~ 65536 fits in one workgroup's LDS.
+ *             N ~ 65536 fits in one workgroup's LDS.  Read through L2
+ *             (stage 5), the word and its count are interleaved in 16
+ *             bytes and the codes have 8 bits (7 of position), so the
+ *             layout of N = 2^21 still fits one XCD's 4 MB L2.
  *   PAIRS     the cache-friendly layout of Sec. 4.8: each cell stores the pair
  *             (K_j, X_{K_j}), so a query makes one gather instead of two. */
 #define DS_LAYOUT_RANKCODE 1

@@ -194,6 +194,27 @@ __global__ void __launch_bounds__(256) rank_code_kernel(const T* __restrict__ X,
   code[i] = static_cast<uint16_t>((static_cast<int>(c) << 1) | first);
 }
 
+// the same codes with 7 bits of position, for the layout read through L2
+template <typename T, int FORM>
+__global__ void __launch_bounds__(256) rank_code8_kernel(const T* __restrict__ X, int64_t N, int64_t n_alloc, T H,
+                                                         T W, T X0, uint8_t* __restrict__ code) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_alloc) return;
+  if (i > N) {
+    code[i] = 0;
+    return;
+  }
+  const T x = X[i];
+  const T v = grid_value<T, FORM>(x, H, W, X0);
+  const T jf = std::floor(v);
+  const T c = cell_code<T, 7>(v, jf);
+  const T p = std::nextafter(x, -std::numeric_limits<T>::infinity());
+  const T vp = grid_value<T, FORM>(p, H, W, X0);
+  const T jp = std::floor(vp);
+  const int first = (jp == jf && cell_code<T, 7>(vp, jp) == c) ? 0 : 1;
+  code[i] = static_cast<uint8_t>((static_cast<int>(c) << 1) | first);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) pairs_kernel(const T* __restrict__ X, const int32_t* __restrict__ K, int64_t nK,
                                                     CachePair<T>* __restrict__ pairs) {
@@ -290,13 +311,16 @@ ds_status build_rankcode(ds_index* h, hipStream_t s) {
   h->rc_words = nW;
   if (hipMalloc(&h->rc_bits, size_t(nW) * 8) != hipSuccess || hipMalloc(&h->rc_base, size_t(nW) * 4) != hipSuccess ||
       hipMalloc(&h->rc_code, size_t(n_codes) * 2) != hipSuccess ||
-      hipMalloc(&h->rc_w16, size_t(nW) * sizeof(RcWord)) != hipSuccess)
+      hipMalloc(&h->rc_w16, size_t(nW) * sizeof(RcWord)) != hipSuccess ||
+      hipMalloc(&h->rc_code8, size_t(n_codes)) != hipSuccess)
     return DS_ERR_OOM;
   rank_bits_kernel<<<dim3((unsigned)((nW * 64 + 255) / 256)), dim3(256), 0, s>>>(h->K, h->nK, nW, h->rc_bits,
                                                                                     h->rc_base, h->rc_w16);
   DS_HIP_CHECK(hipGetLastError());
   rank_code_kernel<T, FORM><<<dim3((unsigned)((n_codes + 255) / 256)), dim3(256), 0, s>>>(
       static_cast<const T*>(h->X), h->N, n_codes, T(h->H), T(h->W), T(h->X0), h->rc_code);
+  rank_code8_kernel<T, FORM><<<dim3((unsigned)((n_codes + 255) / 256)), dim3(256), 0, s>>>(
+      static_cast<const T*>(h->X), h->N, n_codes, T(h->H), T(h->W), T(h->X0), h->rc_code8);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }
@@ -445,7 +469,9 @@ void free_layouts(ds_index* h) {
   if (h->rc_base) (void)hipFree(h->rc_base);
   if (h->rc_code) (void)hipFree(h->rc_code);
   if (h->rc_w16) (void)hipFree(h->rc_w16);
+  if (h->rc_code8) (void)hipFree(h->rc_code8);
   h->rc_w16 = nullptr;
+  h->rc_code8 = nullptr;
   if (h->pairs) (void)hipFree(h->pairs);
   h->rc_bits = nullptr;
   h->rc_base = nullptr;

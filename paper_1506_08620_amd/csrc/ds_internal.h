@@ -73,12 +73,14 @@ __device__ __forceinline__ int32_t direct_one(T z, const T* __restrict__ X, cons
 }
 
 // Position code of a value inside its grid cell: the fraction v - floor(v) in
-// units of 2^-15, capped at 2^15 - 1.  It is a non-decreasing function of v
-// within a cell, computed identically by the build and the search, so a
-// strict difference between the codes of z and of X_t orders z and X_t.
-template <typename T>
+// units of 2^-B, capped at 2^B - 1 (B = 15 for the 16-bit codes, 7 for the
+// 8-bit ones; one more bit of each code is the first-of-class flag).  It is a
+// non-decreasing function of v within a cell, computed identically by the
+// build and the search, so a strict difference between the codes of z and of
+// X_t orders z and X_t.
+template <typename T, int B = 15>
 __host__ __device__ __forceinline__ T cell_code(T v, T jf) {
-  return std::fmin(std::floor((v - jf) * T(32768)), T(32767));
+  return std::fmin(std::floor((v - jf) * T(1 << B)), T((1 << B) - 1));
 }
 
 // the cache-friendly pair of Sec. 4.8: (K_j, X_{K_j}) in one aligned load
@@ -120,6 +122,7 @@ struct DirectArgs {
   const uint32_t* rc_base;   // nW counts: #{i : f(X_i) < jmin + 64 w}
   const uint16_t* rc_code;   // N+1 codes (allocation padded to a multiple of 8)
   const RcWord* rc_w16;      // nW interleaved words (bits, base)
+  const uint8_t* rc_code8;   // N+1 8-bit codes (7-bit position, flag), for the L2 layout
   int32_t nW;
   int32_t pad_;
   // PAIRS layout
@@ -168,6 +171,7 @@ struct ds_index {
   uint32_t* rc_base = nullptr;
   uint16_t* rc_code = nullptr;
   ds::RcWord* rc_w16 = nullptr;
+  uint8_t* rc_code8 = nullptr;
   int64_t rc_words = 0;
   // PAIRS layout
   void* pairs = nullptr;

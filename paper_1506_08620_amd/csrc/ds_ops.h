@@ -91,12 +91,13 @@ struct DirectOp {
 // codes of z and X_t: a strict difference decides, equal codes decide when X_t
 // is the first float of its code class, and only the remaining case reads X_t.
 // The last two lines give -1 below X_0 (and for NaN) and N at or above X_N.
-template <typename T, int FORM, bool INTERLEAVED>
+template <typename T, int FORM, bool INTERLEAVED, typename CodeT = uint16_t>
 struct RankCodeOp {
+  static constexpr int kPosBits = sizeof(CodeT) * 8 - 1;
   const uint64_t* bits;
   const uint32_t* base;
   const RcWord* w16;  // INTERLEAVED: (bits, base) of a word in one 16-byte load
-  const uint16_t* code;
+  const CodeT* code;
   const T* Xg;  // X in global memory, for the rare undecided compare
   T H, W, X0, vlo, vhi, XN;
   int32_t jmin, N;
@@ -119,7 +120,7 @@ struct RankCodeOp {
     const int32_t t = static_cast<int32_t>(wbase) + __popcll(word & ((uint64_t(1) << b) - 1));
     const bool occupied = (word >> b) & 1u;
     const int32_t c = occupied ? code[t] : 0;  // only occupied cells need the code
-    const T cz = cell_code<T>(v, jf);
+    const T cz = cell_code<T, kPosBits>(v, jf);
     const T cx = static_cast<T>(c >> 1);
     const bool first = c & 1;
     int32_t i = t - 1;

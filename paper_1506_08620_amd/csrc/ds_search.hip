@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
                                   a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else if constexpr (STAGE == 5) {
-    RankCodeOp<T, FORM, true> op{nullptr, nullptr, a.rc_w16, a.rc_code, a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN,
-                                 a.jmin, a.N};
+    RankCodeOp<T, FORM, true, uint8_t> op{nullptr, nullptr, a.rc_w16, a.rc_code8, a.X, a.H, a.W, a.X0, a.vlo, a.vhi,
+                                          a.XN, a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else {
     PairsOp<T, FORM> op{a.pairs - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
@@ -247,6 +247,7 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
     a.rc_base = h->rc_base;
     a.rc_code = h->rc_code;
     a.rc_w16 = h->rc_w16;
+    a.rc_code8 = h->rc_code8;
     a.nW = static_cast<int32_t>(h->rc_words);
     a.pairs = static_cast<const CachePair<T>*>(h->pairs);
     a.z = static_cast<const T*>(z);
@@ -363,7 +364,7 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   if (t->block != 0 && (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)) return DS_ERR_ARG;
   if (t->unroll != 0 && t->unroll != 1 && t->unroll != 2 && t->unroll != 4) return DS_ERR_ARG;
   if (t->stage < 0 || t->stage > 5) return DS_ERR_ARG;
-  if (t->stage == 5 && !h->rc_w16) return DS_ERR_ARG;
+  if (t->stage == 5 && (!h->rc_w16 || !h->rc_code8)) return DS_ERR_ARG;
   if (t->stage == 1 && !h->staged) return DS_ERR_ARG;
   if (t->stage >= 3 && h->method != DS_METHOD_DIRECT) return DS_ERR_ARG;
   if (t->stage == 3 && (!h->rc_code || ds::rankcode_lds_bytes(h) > ds::kLdsBytesPerCU)) return DS_ERR_ARG;
