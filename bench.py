@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
-STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2", 5: "RANKCODE-L2"}
+STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2", 5: "RANKCODE-L2",
+               6: "NIBBLE-L2"}
 
 
 def measured_traffic(dtype: str, ns, stage_name: str):
@@ -258,7 +259,7 @@ def compare_methods(ds, cases, M, stream, reps):
         S = np.dtype(c["dt"]).itemsize
         tag = dict(N=c["n"], dtype="f32" if S == 4 else "f64")
         out = torch.empty_like(c["out"])
-        idx = ds.build(c["x"], layouts=("rankcode", "pairs"))
+        idx = ds.build(c["x"], layouts=("rankcode", "pairs", "nibble"))
         inf = idx.info()
         lay = {}
         for stage, name in STAGE_NAMES.items():
@@ -269,7 +270,7 @@ def compare_methods(ds, cases, M, stream, reps):
             ms = timed(idx, c, out)
             lay[name] = dict(gq_s=round(M / ms / 1e6, 2), same_as_direct=bool(torch.equal(out, c["out"])))
         res["direct_layouts"].append(dict(**tag, layouts=lay, rankcode_bytes=inf["rankcode_bytes"],
-                                          pairs_bytes=inf["pairs_bytes"]))
+                                          pairs_bytes=inf["pairs_bytes"], nibble_bytes=inf["nibble_bytes"]))
         idx.destroy()
         for key, kw in (("direct_fma", dict(form="fma")), ("bsearch_leadbit", dict(method="leadbit"))):
             idx = ds.build(c["x"], **kw)

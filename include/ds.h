@@ -123,9 +123,17 @@ typedef struct ds_build_opts {
  *             bytes and the codes have 8 bits (7 of position), so the
  *             layout of N = 2^21 still fits one XCD's 4 MB L2.
  *   PAIRS     the cache-friendly layout of Sec. 4.8: each cell stores the pair
- *             (K_j, X_{K_j}), so a query makes one gather instead of two. */
+ *             (K_j, X_{K_j}), so a query makes one gather instead of two.
+ *   NIBBLE    16-byte chunks of 24 grid cells: a 32-bit count of the X_i in
+ *             earlier cells and one 4-bit code per cell (0 = no X_i, else
+ *             7 bins of the position of the cell's X_i and the first-of-class
+ *             flag), so one 16-byte gather gives K_j and decides the
+ *             compare-and-fix except on a bin tie.  5.33 bits per cell: the
+ *             layout of N = 2^21 (about 4.2M cells) is 2.8 MB.  Read through
+ *             L2 (stage 6); the automatic choice above the LDS layouts. */
 #define DS_LAYOUT_RANKCODE 1
 #define DS_LAYOUT_PAIRS 2
+#define DS_LAYOUT_NIBBLE 4
 
 typedef struct ds_info_t {
   int32_t method;           /* method actually used (ds_method) */
@@ -147,6 +155,7 @@ typedef struct ds_info_t {
   int64_t rankcode_bytes;   /* bytes of the RANKCODE layout (0 if not built) */
   int64_t pairs_bytes;      /* bytes of the PAIRS layout (0 if not built) */
   double build_ms;          /* wall time of ds_build */
+  int64_t nibble_bytes;     /* bytes of the NIBBLE layout (0 if not built) */
 } ds_info_t;
 
 typedef struct ds_index* ds_handle;
@@ -158,7 +167,7 @@ typedef struct ds_tune {
   int32_t unroll;           /* 16-byte query vectors per thread per iteration: 1, 2 or 4; 0 = auto */
   int32_t stage;            /* 0 = auto; Direct: 1 = PLAIN in LDS, 2 = PLAIN through L2,
                                3 = RANKCODE in LDS, 4 = PAIRS through L2,
-                               5 = RANKCODE through L2; binary
+                               5 = RANKCODE through L2, 6 = NIBBLE through L2; binary
                                search: 1 = X in LDS, 2 = X through L2 */
   int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */
 } ds_tune;

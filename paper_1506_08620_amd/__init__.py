@@ -30,10 +30,10 @@ FORM_SUB, FORM_FMA = 0, 1
 HSTART_PHI, HSTART_HBAR = 0, 1
 METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, METHOD_AUTO = range(5)
 FALLBACK_NONE, FALLBACK_BSEARCH, FALLBACK_LEARNED = range(3)
-LAYOUT_RANKCODE, LAYOUT_PAIRS = 1, 2
+LAYOUT_RANKCODE, LAYOUT_PAIRS, LAYOUT_NIBBLE = 1, 2, 4
 # ds_tune.stage values of the Direct method
-STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2, STAGE_RANKCODE_L2 = 1, 2, 3, 4, 5
-_LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS}
+STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2, STAGE_RANKCODE_L2, STAGE_NIBBLE_L2 = 1, 2, 3, 4, 5, 6
+_LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS, "nibble": LAYOUT_NIBBLE}
 
 _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset": METHOD_BSEARCH_OFFSET,
             "learned": METHOD_LEARNED, "auto": METHOD_AUTO}
@@ -65,7 +65,8 @@ class Info(ctypes.Structure):
                 ("jmin", ctypes.c_int64), ("n_h_updates", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("model_bytes", ctypes.c_int64), ("max_err", ctypes.c_int64),
                 ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64),
-                ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
+                ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
+                ("nibble_bytes", ctypes.c_int64)]
 
 
 class Tune(ctypes.Structure):
@@ -242,7 +243,7 @@ def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart:
     """ds_build over the N+1 values of x (a strictly increasing GPU tensor).
 
     layouts: extra Direct layouts to build besides the automatic one
-    ("rankcode", "pairs"), so that set_tune(stage=...) can select them.
+    ("rankcode", "pairs", "nibble"), so that set_tune(stage=...) can select them.
     """
     _check_device(x, "x")
     if x.dim() != 1 or x.numel() < 2:

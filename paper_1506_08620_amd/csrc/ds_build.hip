@@ -215,6 +215,42 @@ __global__ void __launch_bounds__(256) rank_code8_kernel(const T* __restrict__ X
   code[i] = static_cast<uint8_t>((static_cast<int>(c) << 1) | first);
 }
 
+// NIBBLE chunks: one thread per 24 cells.  Cell e holds X_{K_e} exactly when
+// K_{e+1} > K_e (the last cell holds X_N); its nibble codes the bin of
+// X_{K_e} in the cell and, for f32, the first-of-class flag (NibCode).
+template <typename T, int FORM>
+__global__ void __launch_bounds__(256) nibble_kernel(const T* __restrict__ X, const int32_t* __restrict__ K, int64_t nK,
+                                                     int64_t n_chunks, T H, T W, T X0, NibChunk* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_chunks) return;
+  const int64_t e0 = k * kNibCells;
+  NibChunk ch{};
+  ch.base = static_cast<uint32_t>(K[e0]);  // e0 < nK for every chunk
+  for (int c = 0; c < kNibCells; ++c) {
+    const int64_t e = e0 + c;
+    bool occupied = false;
+    if (e < nK - 1)
+      occupied = K[e + 1] != K[e];
+    else if (e == nK - 1)
+      occupied = true;
+    if (!occupied) continue;
+    const T x = X[K[e]];
+    const T v = grid_value<T, FORM>(x, H, W, X0);
+    const T jf = std::floor(v);
+    const uint32_t b = static_cast<uint32_t>(cell_bin(v, jf));
+    uint32_t nib = 1u + b;
+    if constexpr (NibCode<T>::kFlag) {
+      const T p = std::nextafter(x, -std::numeric_limits<T>::infinity());
+      const T vp = grid_value<T, FORM>(p, H, W, X0);
+      const T jp = std::floor(vp);
+      const uint32_t first = (jp == jf && static_cast<uint32_t>(cell_bin(vp, jp)) == b) ? 0u : 1u;
+      nib = 1u + 2u * b + first;
+    }
+    ch.nib[c >> 3] |= nib << (4 * (c & 7));
+  }
+  out[k] = ch;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) pairs_kernel(const T* __restrict__ X, const int32_t* __restrict__ K, int64_t nK,
                                                     CachePair<T>* __restrict__ pairs) {
@@ -325,6 +361,20 @@ ds_status build_rankcode(ds_index* h, hipStream_t s) {
   return DS_OK;
 }
 
+template <typename T, int FORM>
+ds_status build_nibble(ds_index* h, hipStream_t s) {
+  const int64_t n = (h->nK + kNibCells - 1) / kNibCells;
+  if (hipMalloc(&h->nib, size_t(n) * sizeof(NibChunk)) != hipSuccess) {
+    h->nib = nullptr;
+    return DS_ERR_OOM;
+  }
+  h->nib_chunks = n;
+  nibble_kernel<T, FORM><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
+      static_cast<const T*>(h->X), h->K, h->nK, n, T(h->H), T(h->W), T(h->X0), h->nib);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
 template <typename T>
 ds_status build_pairs(ds_index* h, hipStream_t s) {
   if (hipMalloc(&h->pairs, size_t(h->nK) * sizeof(CachePair<T>)) != hipSuccess) {
@@ -338,18 +388,23 @@ ds_status build_pairs(ds_index* h, hipStream_t s) {
 }
 
 // Which layouts to build: the one the automatic launch will use (PLAIN in LDS
-// when it fits, else RANKCODE in LDS when it fits, else RANKCODE through L2,
-// which measured about twice as fast as PAIRS through L2 at N = 2^20..2^21),
-// plus whatever the caller asked for.
+// when it fits, else RANKCODE in LDS when it fits, else NIBBLE through L2: one
+// cache line of table per query, against about 1.5 for RANKCODE through L2
+// and 2 for PAIRS), plus whatever the caller asked for.
 template <typename T>
 ds_status build_layouts(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   h->staged = tables_fit_lds(h) ? 1 : 0;
   const int64_t nW = (h->nK + 63) / 64;
   h->rc_words = nW;
   const bool rc_fits = rankcode_lds_bytes(h) <= kLdsBytesPerCU;
-  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : 5);
+  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : 6);
   const bool want_rc = (o.extra_layouts & DS_LAYOUT_RANKCODE) || h->auto_stage == 3 || h->auto_stage == 5;
   const bool want_pairs = (o.extra_layouts & DS_LAYOUT_PAIRS) || h->auto_stage == 4;
+  const bool want_nib = (o.extra_layouts & DS_LAYOUT_NIBBLE) || h->auto_stage == 6;
+  if (want_nib) {
+    ds_status st = (h->form == DS_FORM_FMA) ? build_nibble<T, DS_FORM_FMA>(h, s) : build_nibble<T, DS_FORM_SUB>(h, s);
+    if (st != DS_OK) return st;
+  }
   if (want_rc) {
     ds_status st = (h->form == DS_FORM_FMA) ? build_rankcode<T, DS_FORM_FMA>(h, s) : build_rankcode<T, DS_FORM_SUB>(h, s);
     if (st != DS_OK) return st;
@@ -473,10 +528,13 @@ void free_layouts(ds_index* h) {
   h->rc_w16 = nullptr;
   h->rc_code8 = nullptr;
   if (h->pairs) (void)hipFree(h->pairs);
+  if (h->nib) (void)hipFree(h->nib);
   h->rc_bits = nullptr;
   h->rc_base = nullptr;
   h->rc_code = nullptr;
   h->pairs = nullptr;
+  h->nib = nullptr;
+  h->nib_chunks = 0;
 }
 
 void free_device(ds_index* h) {
@@ -564,6 +622,7 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   if (o.hstart != DS_HSTART_PHI && o.hstart != DS_HSTART_HBAR) return DS_ERR_ARG;
   if (o.fallback < DS_FALLBACK_NONE || o.fallback > DS_FALLBACK_LEARNED) return DS_ERR_ARG;
   if (o.table_cap_bytes < 0) return DS_ERR_ARG;
+  if (o.extra_layouts & ~(DS_LAYOUT_RANKCODE | DS_LAYOUT_PAIRS | DS_LAYOUT_NIBBLE)) return DS_ERR_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   ds_index* h = new (std::nothrow) ds_index();
   if (!h) return DS_ERR_OOM;
@@ -601,6 +660,7 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   in.x_bytes = h->nX * int64_t(dt == DS_F32 ? 4 : 8);
   in.rankcode_bytes = h->rc_code ? (h->rc_words * 12 + (h->N + 1) * 2) : 0;
   in.pairs_bytes = h->pairs ? h->nK * int64_t(dt == DS_F32 ? 8 : 16) : 0;
+  in.nibble_bytes = h->nib ? h->nib_chunks * int64_t(sizeof(ds::NibChunk)) : 0;
   in.build_ms = ms;
   ds::learned_fill_info(h, &in);
   *out = h;

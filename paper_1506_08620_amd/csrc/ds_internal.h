@@ -106,6 +106,38 @@ struct alignas(16) RcWord {
   uint32_t pad;
 };
 
+// NIBBLE layout: one 16-byte chunk per 24 grid cells, read with one gather.
+// base counts the X_i of earlier cells (it comes last, so that the first two
+// code words form an aligned 64-bit register pair); nibble c % 8 of
+// nib[c / 8] describes cell 24 k + c: 0 when it holds no X_i, else a code of
+// the position of its X_i inside the cell (NibCode).  The rank of a cell is
+// base plus the nonzero nibbles before it.
+constexpr int kNibCells = 24;
+struct alignas(16) NibChunk {
+  uint32_t nib[3];
+  uint32_t base;
+};
+
+// The 15 nonzero nibble values.  f32 cells hold few floats, so a code keeps
+// 7 bins of the position and the first-of-class flag (value 1 + 2 bin +
+// first): a query in the bin of X_t that is the first float of its bin is at
+// or above X_t.  f64 cells hold very many floats and the flag would almost
+// never be set, so all 15 values are bins (value 1 + bin).
+template <typename T>
+struct NibCode {
+  static constexpr bool kFlag = sizeof(T) == 4;
+  static constexpr int kBins = kFlag ? 7 : 15;
+};
+
+// Bin of a value inside its grid cell: kBins equal bins of the fraction
+// v - floor(v), capped at kBins - 1.  Non-decreasing in v within a cell and
+// computed identically by the build and the search, like cell_code.
+template <typename T>
+__host__ __device__ __forceinline__ T cell_bin(T v, T jf) {
+  constexpr int B = NibCode<T>::kBins;
+  return std::fmin(std::floor((v - jf) * T(B)), T(B - 1));
+}
+
 template <typename T>
 struct DirectArgs {
   const T* X;         // N+1 values (global)
@@ -127,6 +159,8 @@ struct DirectArgs {
   int32_t pad_;
   // PAIRS layout
   const CachePair<T>* pairs; // nK pairs, pairs[0] for cell jmin
+  // NIBBLE layout
+  const NibChunk* nib;       // ceil(nK / 24) chunks, chunk 0 starts at cell jmin
   const T* z;
   int32_t* out;
   int64_t M;
@@ -175,6 +209,9 @@ struct ds_index {
   int64_t rc_words = 0;
   // PAIRS layout
   void* pairs = nullptr;
+  // NIBBLE layout
+  ds::NibChunk* nib = nullptr;
+  int64_t nib_chunks = 0;
   int32_t auto_stage = 2;       // layout the automatic launch uses
   // binary search constants
   int32_t P = 0, F = 0, S = 0, J = 0;

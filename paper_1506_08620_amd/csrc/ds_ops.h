@@ -3,6 +3,9 @@
 // operators of every method and layout.
 #pragma once
 
+#include <algorithm>
+#include <type_traits>
+
 #include "ds_internal.h"
 
 namespace ds {
@@ -36,6 +39,69 @@ __device__ __forceinline__ void stage_bytes(unsigned char* __restrict__ dst, con
   }
 }
 
+// An operator with a Gathered type splits a query into three steps that
+// stream_queries runs over all of a lane's queries in turn, so that the loads
+// of each step are in flight together:
+//   g = gather(z)             the table load (plus what the next step needs
+//                             from z);
+//   i = decide(z, g, &t)      the result, unless t >= 0: then the result is
+//                             t - 1 + [z >= X_t] (the rare undecided compare,
+//                             always for an in-domain z).
+template <class Op, class = void>
+struct has_gather : std::false_type {};
+template <class Op>
+struct has_gather<Op, std::void_t<typename Op::Gathered>> : std::true_type {};
+
+// The VEC loop for an operator with a Gathered type: gather, decide and the
+// undecided compares each run over all 4U queries of a lane in turn, so the
+// loads of a step are in flight together.  A vector index past the end is
+// clamped to the last vector: every load is in bounds and unconditional
+// (which keeps the loop free of branches, so the compiler's waits cover only
+// the loads a step needs), and only the stores are guarded.  (Prefetching the
+// next iteration's queries measured no faster on MI355X and costs registers.)
+template <typename T, int U, class Op>
+__device__ __forceinline__ void stream_gathered(const vec4<T>* __restrict__ zv, ivec4* __restrict__ ov, int64_t nvec,
+                                                const Op& op) {
+  const int64_t B = blockDim.x;
+  const int64_t step = (int64_t)gridDim.x * B * U;
+  const int64_t last = nvec - 1;
+  for (int64_t base = (int64_t)blockIdx.x * B * U + threadIdx.x; base < nvec; base += step) {
+    vec4<T> q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = __builtin_nontemporal_load(zv + std::min<int64_t>(base + u * B, last));
+    typename Op::Gathered g[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int l = 0; l < 4; ++l) g[u][l] = op.gather(q[u][l]);
+    }
+    int32_t r[U][4], t[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int l = 0; l < 4; ++l) r[u][l] = op.decide(q[u][l], g[u][l], &t[u][l]);
+    }
+    T x[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        x[u][l] = T(0);
+        if (t[u][l] >= 0) x[u][l] = op.Xg[t[u][l]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (base + u * B < nvec) {
+        ivec4 o;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) o[l] = (t[u][l] >= 0) ? t[u][l] - 1 + (q[u][l] >= x[u][l] ? 1 : 0) : r[u][l];
+        __builtin_nontemporal_store(o, ov + base + u * B);
+      }
+    }
+  }
+}
+
 // Streams M queries through op.  VEC: z and out are aligned for 4-element
 // vector access; U vectors per lane per iteration keep several independent
 // gathers in flight.
@@ -47,24 +113,28 @@ __device__ __forceinline__ void stream_queries(const T* __restrict__ z, int32_t*
     const int64_t nvec = M >> 2;
     const vec4<T>* zv = reinterpret_cast<const vec4<T>*>(z);
     ivec4* ov = reinterpret_cast<ivec4*>(out);
-    const int64_t step = (int64_t)gridDim.x * blockDim.x * U;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x * U + threadIdx.x; base < nvec; base += step) {
-      vec4<T> q[U];
+    if constexpr (has_gather<Op>::value) {
+      stream_gathered<T, U>(zv, ov, nvec, op);
+    } else {
+      const int64_t step = (int64_t)gridDim.x * blockDim.x * U;
+      for (int64_t base = (int64_t)blockIdx.x * blockDim.x * U + threadIdx.x; base < nvec; base += step) {
+        vec4<T> q[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t v = base + (int64_t)u * blockDim.x;
-        if (v < nvec) q[u] = __builtin_nontemporal_load(zv + v);
-      }
+        for (int u = 0; u < U; ++u) {
+          const int64_t v = base + (int64_t)u * blockDim.x;
+          if (v < nvec) q[u] = __builtin_nontemporal_load(zv + v);
+        }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t v = base + (int64_t)u * blockDim.x;
-        if (v < nvec) {
-          ivec4 r;
-          r.x = op(q[u].x);
-          r.y = op(q[u].y);
-          r.z = op(q[u].z);
-          r.w = op(q[u].w);
-          __builtin_nontemporal_store(r, ov + v);
+        for (int u = 0; u < U; ++u) {
+          const int64_t v = base + (int64_t)u * blockDim.x;
+          if (v < nvec) {
+            ivec4 r;
+            r.x = op(q[u].x);
+            r.y = op(q[u].y);
+            r.z = op(q[u].z);
+            r.w = op(q[u].w);
+            __builtin_nontemporal_store(r, ov + v);
+          }
         }
       }
     }
@@ -133,6 +203,81 @@ struct RankCodeOp {
     }
     i = (z >= XN) ? N : i;
     return (z >= X0) ? i : -1;
+  }
+};
+
+// bit 4n + 3 set for each nonzero nibble n: the low three bits of a nibble
+// plus 7 carry into its top bit exactly when they are not all zero, and never
+// out of the nibble
+__device__ __forceinline__ uint32_t nonzero_nibbles32(uint32_t x) {
+  return (((x & 0x77777777u) + 0x77777777u) | x) & 0x88888888u;
+}
+
+// NIBBLE layout through L1/L2: the chunk of the query's cell is one 16-byte
+// gather holding the running count, the occupancy and the bin codes of 24
+// cells, so a query touches one cache line of the table (plus X_t when the
+// bins tie).  gather() also does all the floating-point work on z and packs
+// it into one word (cell in the chunk, bin of z, below X_0), so decide() is
+// integer-only.
+template <typename T, int FORM>
+struct NibbleOp {
+  struct Gathered {
+    uint4 q;
+    uint32_t p;
+  };
+  static constexpr uint32_t kBelow = 1u << 9;
+  const NibChunk* ch;
+  const T* Xg;
+  T H, W, X0, vlo, vhi, XN;
+  int32_t jmin, N;
+  __device__ __forceinline__ Gathered gather(T z) const {
+    const T v = grid_value<T, FORM>(z, H, W, X0);
+    const T jf = std::floor(std::fmin(std::fmax(v, vlo), vhi));
+    const uint32_t e = static_cast<uint32_t>(static_cast<int32_t>(jf) - jmin);
+    const uint32_t k = e / kNibCells;
+    Gathered g;
+    g.q = reinterpret_cast<const uint4*>(ch)[k];  // one dwordx4 gather
+    // the bin of z (clamped at 0 for z below X_0 and NaN, whose result is -1 anyway)
+    const uint32_t bz = static_cast<uint32_t>(std::fmax(cell_bin(v, jf), T(0)));
+    g.p = (e - k * kNibCells) | (bz << 5) | (z >= X0 ? 0u : kBelow);
+    return g;
+  }
+  __device__ __forceinline__ int32_t decide(T, const Gathered& g, int32_t* tie) const {
+    const uint32_t c = g.p & 31u, cz = (g.p >> 5) & 15u;
+    const uint32_t wi = c >> 3, sh = (c & 7u) << 2;
+    const uint32_t before = (1u << sh) - 1u;  // nibbles before c in its word
+    const uint32_t m0 = wi > 0 ? ~0u : before;
+    const uint32_t m1 = wi > 1 ? ~0u : (wi == 1 ? before : 0u);
+    const uint32_t m2 = wi == 2 ? before : 0u;
+    const uint32_t rank = __popc(nonzero_nibbles32(g.q.x) & m0) + __popc(nonzero_nibbles32(g.q.y) & m1) +
+                          __popc(nonzero_nibbles32(g.q.z) & m2);
+    const uint32_t w = wi == 0 ? g.q.x : (wi == 1 ? g.q.y : g.q.z);
+    const uint32_t nib = (w >> sh) & 15u;
+    const int32_t t = static_cast<int32_t>(g.q.w + rank);
+    bool up, eq;
+    if constexpr (NibCode<T>::kFlag) {
+      const uint32_t cx = (nib - 1) >> 1;
+      const bool first = (nib - 1) & 1u;
+      up = cz > cx || (cz == cx && first);
+      eq = cz == cx && !first;
+    } else {
+      const uint32_t cx = nib - 1;
+      up = cz > cx;
+      eq = cz == cx;
+    }
+    // z at or above X_N needs no case of its own: it lies in the last cell (or
+    // is clamped to it), which holds X_N = X_t, with a bin >= the bin of X_N,
+    // so the codes (or the compare with X_N) give t = N
+    const bool occupied = nib != 0;
+    const bool below = (g.p & kBelow) != 0;
+    *tie = (occupied && eq && !below) ? t : -1;
+    const int32_t i = (occupied && up) ? t : t - 1;
+    return below ? -1 : i;
+  }
+  __device__ __forceinline__ int32_t operator()(T z) const {
+    int32_t t;
+    const int32_t i = decide(z, gather(z), &t);
+    return (t >= 0) ? t - 1 + (z >= Xg[t] ? 1 : 0) : i;
   }
 };
 

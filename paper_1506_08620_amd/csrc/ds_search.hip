@@ -28,7 +28,7 @@ __host__ __device__ constexpr int64_t rankcode_offsets(int64_t nW, int64_t n_cod
 }
 
 // STAGE 1: PLAIN in LDS; 2: PLAIN through L1/L2; 3: RANKCODE in LDS;
-// 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2.
+// 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2; 6: NIBBLE through L1/L2.
 template <typename T, int FORM, int STAGE, int U, bool VEC>
 __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -62,6 +62,9 @@ __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
   } else if constexpr (STAGE == 5) {
     RankCodeOp<T, FORM, true, uint8_t> op{nullptr, nullptr, a.rc_w16, a.rc_code8, a.X, a.H, a.W, a.X0, a.vlo, a.vhi,
                                           a.XN, a.jmin, a.N};
+    stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+  } else if constexpr (STAGE == 6) {
+    NibbleOp<T, FORM> op{a.nib, a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else {
     PairsOp<T, FORM> op{a.pairs - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
@@ -129,6 +132,7 @@ void default_shape(const ds_index* h, int stage, int* block, int* unroll) {
     }
     case 4: *block = f32 ? 256 : 1024; *unroll = f32 ? 4 : 1; return;
     case 5: *block = 512; *unroll = 2; return;
+    case 6: *block = 512; *unroll = 2; return;
     default: *block = 512; *unroll = 2; return;
   }
 }
@@ -192,6 +196,9 @@ ds_status dispatch_direct(const DirectArgs<T>& a, const Shape& sh, bool vec, int
     case 5:
       return vec ? dispatch_direct_u<T, FORM, 5, true>(a, sh, 0, items, s)
                  : dispatch_direct_u<T, FORM, 5, false>(a, sh, 0, items, s);
+    case 6:
+      return vec ? dispatch_direct_u<T, FORM, 6, true>(a, sh, 0, items, s)
+                 : dispatch_direct_u<T, FORM, 6, false>(a, sh, 0, items, s);
     default:
       return vec ? dispatch_direct_u<T, FORM, 2, true>(a, sh, 0, items, s)
                  : dispatch_direct_u<T, FORM, 2, false>(a, sh, 0, items, s);
@@ -250,6 +257,7 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
     a.rc_code8 = h->rc_code8;
     a.nW = static_cast<int32_t>(h->rc_words);
     a.pairs = static_cast<const CachePair<T>*>(h->pairs);
+    a.nib = h->nib;
     a.z = static_cast<const T*>(z);
     a.out = out;
     a.M = M;
@@ -299,12 +307,13 @@ ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_de
   if (!h || !z_dev || !out_dev || M <= 0) return DS_ERR_ARG;
   if (h->method == DS_METHOD_LEARNED) return DS_ERR_UNSUPPORTED;
   const int64_t m = std::min<int64_t>(M, int64_t(1) << 24);
-  int stages[5];
+  int stages[6];
   int n_stages = 0;
   if (h->method == DS_METHOD_DIRECT) {
     if (h->staged) stages[n_stages++] = 1;
     if (h->rc_code && ds::rankcode_lds_bytes(h) <= ds::kLdsBytesPerCU) stages[n_stages++] = 3;
     if (h->rc_w16) stages[n_stages++] = 5;
+    if (h->nib) stages[n_stages++] = 6;
     if (h->pairs) stages[n_stages++] = 4;
     stages[n_stages++] = 2;
   } else {
@@ -363,7 +372,8 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   }
   if (t->block != 0 && (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)) return DS_ERR_ARG;
   if (t->unroll != 0 && t->unroll != 1 && t->unroll != 2 && t->unroll != 4) return DS_ERR_ARG;
-  if (t->stage < 0 || t->stage > 5) return DS_ERR_ARG;
+  if (t->stage < 0 || t->stage > 6) return DS_ERR_ARG;
+  if (t->stage == 6 && !h->nib) return DS_ERR_ARG;
   if (t->stage == 5 && (!h->rc_w16 || !h->rc_code8)) return DS_ERR_ARG;
   if (t->stage == 1 && !h->staged) return DS_ERR_ARG;
   if (t->stage >= 3 && h->method != DS_METHOD_DIRECT) return DS_ERR_ARG;

@@ -72,7 +72,7 @@ def test_sweep_tables_and_indices(ds, dtype, n, form):
     X = W.sweep_array(n, dtype)
     z = W.sweep_queries(1 << 20, dtype, stream=1)
     z = np.concatenate([z, X[:-1], W.prev_float(X[1:], dtype)[: 1 << 16], np.nextafter(X, np.dtype(dtype).type(2))])
-    idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs"))
+    idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs", "nibble"))
     _check_tables(idx, X, form)
     ref = oracle.search(X, z)
     z_d = _dev(z)
@@ -139,6 +139,8 @@ def _stages(idx):
         st.append(4)
     if inf["rankcode_bytes"]:
         st.append(5)
+    if inf["nibble_bytes"]:
+        st.append(6)
     return tuple(sorted(st))
 
 
@@ -149,7 +151,7 @@ def test_every_launch_shape_gives_the_same_answer(ds, dtype):
         z = W.sweep_queries((1 << 18) + 3, dtype, stream=2)
         ref = oracle.search(X, z)
         for method in ("direct", "leadbit"):
-            idx = ds.build(_dev(X), method=method, layouts=("rankcode", "pairs") if method == "direct" else ())
+            idx = ds.build(_dev(X), method=method, layouts=("rankcode", "pairs", "nibble") if method == "direct" else ())
             z_d = _dev(z)
             stages = _stages(idx)
             if method == "direct":
@@ -169,7 +171,7 @@ def test_autotune_keeps_results(ds):
         for n in (16, 65536, 1 << 20):
             X = W.sweep_array(n, dt)
             z_d = W.sweep_queries_torch(1 << 21, dt, DEV, stream=5)
-            idx = ds.build(_dev(X), layouts=("rankcode", "pairs"))
+            idx = ds.build(_dev(X), layouts=("rankcode", "pairs", "nibble"))
             ref = ds.search(idx, z_d).clone()
             best = idx.autotune(z_d)
             assert best["stage"] in _stages(idx)
@@ -205,7 +207,7 @@ def test_exhaustive_f32_domain_on_gpu(ds):
     ref = oracle.search(X, z)
     z_d = _dev(z)
     for form in ("sub", "fma"):
-        idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs"))
+        idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs", "nibble"))
         _check_tables(idx, X, form)
         for stage in _stages(idx):
             idx.set_tune(stage=stage)
@@ -224,7 +226,7 @@ def test_dense_neighbourhoods_all_layouts(ds, dtype):
     ref = oracle.search(X, z)
     z_d = _dev(z)
     for form in ("sub", "fma"):
-        idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs"))
+        idx = ds.build(_dev(X), form=form, layouts=("rankcode", "pairs", "nibble"))
         for stage in _stages(idx):
             idx.set_tune(stage=stage)
             _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
@@ -238,7 +240,7 @@ def test_fma_form_with_negative_first_cell(ds):
         X = W.gap_array(int(rng.integers(8, 3000)), np.float32, rng, x0=rng.uniform(-1e3, 1e3))
         t = oracle.build_direct(X, oracle.FORM_FMA)
         seen.add(t.jmin)
-        idx = ds.build(_dev(X), form="fma", layouts=("rankcode", "pairs"))
+        idx = ds.build(_dev(X), form="fma", layouts=("rankcode", "pairs", "nibble"))
         _check_tables(idx, X, "fma")
         z = np.concatenate([W.uniform_queries(X[0], X[-1], 5000, np.float32, rng), X,
                             W.prev_float(X, np.float32), np.nextafter(X, np.float32(np.inf)),
