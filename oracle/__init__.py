@@ -60,6 +60,14 @@ def _load():
             f.argtypes, f.restype = [vp, i64, i32, ct, ct, i64, i64, vp], i32
             f = getattr(lib, f"oracle_direct_{s}")
             f.argtypes, f.restype = [vp, i64, vp, i32, ct, ct, i64, i64, vp, i64, vp], None
+            f = getattr(lib, f"oracle_compute_hr_gap_{s}")
+            f.argtypes = [vp, i64, i64, i32, i32, ctypes.POINTER(ct), ctypes.POINTER(ct),
+                          ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+            f.restype = i32
+            f = getattr(lib, f"oracle_init_k_gap_{s}")
+            f.argtypes, f.restype = [vp, i64, i32, ct, ct, i64, i64, vp], i32
+            f = getattr(lib, f"oracle_direct_gap_{s}")
+            f.argtypes, f.restype = [vp, i64, i64, vp, i32, ct, ct, i64, i64, vp, i64, vp], None
         _lib = lib
     return _lib
 
@@ -108,6 +116,7 @@ class DirectTables:
     K: np.ndarray | None = None   # K[j - jmin] = K_j, j in [jmin, R]
     form: int = FORM_SUB
     dtype: np.dtype = np.dtype(np.float32)
+    q: int = 0                    # gap-q tables (Sec. 4.7); 0 for plain Direct
 
 
 def compute_hr(X: np.ndarray, form: int = FORM_SUB, hstart: int = HSTART_PHI) -> DirectTables:
@@ -151,4 +160,51 @@ def direct(X: np.ndarray, t: DirectTables, z: np.ndarray) -> np.ndarray:
     out = np.empty(z.size, np.int32)
     getattr(_load(), f"oracle_direct_{_suffix(X.dtype)}")(_ptr(X), X.size - 1, _ptr(t.K), t.form, t.H, t.W,
                                                            t.jmin, t.R, _ptr(z), z.size, _ptr(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The gap-q variant (Sec. 4.7): f(X_{i+q}) > f(X_i), K_j = max{i : f(X_i) <= j},
+# i = K_j - sum_{k<q} [z < X_{K_j - k}].
+
+def compute_hr_gap(X: np.ndarray, q: int, form: int = FORM_SUB, hstart: int = HSTART_PHI) -> DirectTables:
+    """ComputeHR under eq. (f-monotonic-n); status, H, W, R, jmin, n_updates (1 <= q <= N)."""
+    X = np.ascontiguousarray(X)
+    s = _suffix(X.dtype)
+    ct = ctypes.c_float if s == "f32" else ctypes.c_double
+    H, W = ct(), ct()
+    R, jmin, nu = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    st = getattr(_load(), f"oracle_compute_hr_gap_{s}")(_ptr(X), X.size - 1, q, form, hstart, ctypes.byref(H),
+                                                          ctypes.byref(W), ctypes.byref(R), ctypes.byref(jmin),
+                                                          ctypes.byref(nu))
+    if st != OK:
+        return DirectTables(st, form=form, dtype=X.dtype, q=q)
+    return DirectTables(OK, H.value, W.value, R.value, jmin.value, nu.value, None, form, X.dtype, q)
+
+
+def init_k_gap(X: np.ndarray, H: float, W: float, R: int, jmin: int, form: int = FORM_SUB):
+    """eq. (kgeneral): K[j - jmin] = max{i : f(X_i) <= j}; (status, K)."""
+    X = np.ascontiguousarray(X)
+    K = np.empty(R - jmin + 1, np.int32)
+    st = getattr(_load(), f"oracle_init_k_gap_{_suffix(X.dtype)}")(_ptr(X), X.size - 1, form, H, W, jmin, R, _ptr(K))
+    return st, K
+
+
+def build_direct_gap(X: np.ndarray, q: int, form: int = FORM_SUB, hstart: int = HSTART_PHI) -> DirectTables:
+    t = compute_hr_gap(X, q, form, hstart)
+    if t.status != OK:
+        return t
+    st, K = init_k_gap(X, t.H, t.W, t.R, t.jmin, form)
+    t.status = st
+    t.K = K
+    return t
+
+
+def direct_gap(X: np.ndarray, t: DirectTables, z: np.ndarray) -> np.ndarray:
+    """eq. (index2) with q compares (algorithm DirectGap2 for q = 2) on the oracle's own tables."""
+    X = np.ascontiguousarray(X)
+    z = np.ascontiguousarray(z, dtype=X.dtype)
+    out = np.empty(z.size, np.int32)
+    getattr(_load(), f"oracle_direct_gap_{_suffix(X.dtype)}")(_ptr(X), X.size - 1, t.q, _ptr(t.K), t.form, t.H, t.W,
+                                                               t.jmin, t.R, _ptr(z), z.size, _ptr(out))
     return out

@@ -23,6 +23,14 @@
  *                     to left as in algorithm InitK).
  *   oracle_direct_*   the Direct search (Sec. 4.2, algorithm Direct) on the
  *                     oracle's own tables; used only to pin the build.
+ *   oracle_compute_hr_gap_*, oracle_init_k_gap_*, oracle_direct_gap_*
+ *                     the relaxed variant of Sec. 4.7 ("Relaxing Limitations
+ *                     and Reducing Memory Usage"): the grid only has to
+ *                     satisfy f(X_{i+q}) > f(X_i) (eq. (f-monotonic-2) for
+ *                     q = 2, eq. (f-monotonic-n) in general), K_j is
+ *                     max{i : f(X_i) <= j} (eq. (kgeneral)), and the search
+ *                     subtracts the q indicators [z < X_{t-k}], k < q
+ *                     (eq. (index2), algorithm DirectGap2 for q = 2).
  *
  * Floating point: IEEE round-to-nearest-even, no contraction (the build file
  * passes -ffp-contract=off), denormals preserved, explicit fma() only in the
@@ -197,3 +205,110 @@
 
 DEFINE_ORACLE(float, f32, floorf, fmaf, nextafterf)
 DEFINE_ORACLE(double, f64, floor, fma, nextafter)
+
+/*
+ * The gap-q variant (Sec. 4.7), written once per precision like the above.
+ */
+#define DEFINE_ORACLE_GAP(T, S, FLOOR, FMA, NEXTUP)                              \
+                                                                                 \
+  /* ComputeHR with the condition of eq. (f-monotonic-n): the pairs checked   \
+   * are (X_{i-q}, X_i) instead of neighbours, and the starting point is       \
+   * Hbar = m(1 / min_i m(D_{i+q} - D_i)) (eq. (fcond11) in the rounded form of \
+   * eq. (minhnumeric)); everything else (start phi(Hbar), growth term P never \
+   * reset, passes repeated to a fixed point, overflow test) is as in          \
+   * oracle_compute_hr.  q = 1 is plain Direct's condition. */                 \
+  int oracle_compute_hr_gap_##S(const T* X, int64_t N, int64_t q, int form,     \
+                                int hstart, T* H_out, T* W_out, int64_t* R_out,  \
+                                int64_t* jmin_out, int64_t* n_updates_out) {     \
+    if (N < 1 || X == 0 || q < 1 || q > N) return OR_ERR_ARG;                    \
+    for (int64_t i = 0; i <= N; ++i)                                             \
+      if (!isfinite(X[i])) return OR_ERR_NONFINITE;                              \
+    for (int64_t i = 0; i < N; ++i)                                              \
+      if (!(X[i] < X[i + 1])) return OR_ERR_NOT_SORTED;                          \
+    const T X0 = X[0];                                                           \
+    T g = INFINITY;                                                              \
+    for (int64_t i = 0; i + q <= N; ++i) {                                       \
+      T Di = X[i] - X0, Dq = X[i + q] - X0;                                      \
+      if (!(Di < Dq)) return OR_ERR_INFEASIBLE;                                  \
+      T gap = Dq - Di; /* m(D_{i+q} - D_i) */                                    \
+      if (gap < g) g = gap;                                                      \
+    }                                                                            \
+    T one = 1;                                                                   \
+    T Hbar = one / g;                                                            \
+    if (isinf(Hbar)) return OR_ERR_INFEASIBLE;                                   \
+    T H = (hstart == OR_HSTART_HBAR) ? Hbar : NEXTUP(Hbar, (T)INFINITY);         \
+    T W = 0;                                                                     \
+    if (form == OR_FORM_FMA) W = H * X0;                                         \
+    if (FLOOR(grid_value_##S(form, H, W, X0, X[N])) >= (T)OR_TWO_POW_Q)          \
+      return OR_ERR_INFEASIBLE;                                                  \
+    T P = NEXTUP(H, (T)INFINITY) - H;                                            \
+    int64_t n_updates = 0;                                                       \
+    for (;;) {                                                                   \
+      int changed = 0;                                                           \
+      for (int64_t i = q; i <= N; ++i) {                                         \
+        while (FLOOR(grid_value_##S(form, H, W, X0, X[i - q])) ==                \
+               FLOOR(grid_value_##S(form, H, W, X0, X[i]))) {                    \
+          H = H + P;                                                             \
+          if (form == OR_FORM_FMA) W = H * X0;                                   \
+          if (FLOOR(grid_value_##S(form, H, W, X0, X[N])) >= (T)OR_TWO_POW_Q)    \
+            return OR_ERR_INFEASIBLE;                                            \
+          P = P + P;                                                             \
+          ++n_updates;                                                           \
+          changed = 1;                                                           \
+        }                                                                        \
+      }                                                                          \
+      if (!changed) break;                                                       \
+    }                                                                            \
+    *H_out = H;                                                                  \
+    *W_out = W;                                                                  \
+    *R_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[N]));              \
+    *jmin_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[0]));           \
+    *n_updates_out = n_updates;                                                  \
+    return OR_OK;                                                                \
+  }                                                                              \
+                                                                                 \
+  /* eq. (kgeneral): K_j = max{i : f(X_i) <= j} for j = jmin..R, by one scan  \
+   * of the non-decreasing sequence f(X_i); K[j - jmin] holds K_j. */           \
+  int oracle_init_k_gap_##S(const T* X, int64_t N, int form, T H, T W,           \
+                            int64_t jmin, int64_t R, int32_t* K) {               \
+    const T X0 = X[0];                                                           \
+    int64_t i = 0;                                                               \
+    for (int64_t j = jmin; j <= R; ++j) {                                        \
+      while (i + 1 <= N &&                                                       \
+             (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[i + 1])) <= j)      \
+        ++i;                                                                     \
+      if ((int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[i])) > j)              \
+        return OR_ERR_INFEASIBLE; /* only possible for j < f(X_0) */             \
+      K[j - jmin] = (int32_t)i;                                                  \
+    }                                                                            \
+    return OR_OK;                                                                \
+  }                                                                              \
+                                                                                 \
+  /* eq. (index2) for q compares: j = f(z) clamped to [jmin, R] in floating    \
+   * point, t = K_j, i = t - sum_{k<q} [z < X_{t-k}], where X_{t-k} for        \
+   * t - k < 0 is the left padding X_0 of the algorithm.  Below X_0 (and for   \
+   * NaN) the result is -1, as everywhere else in this file. */                 \
+  void oracle_direct_gap_##S(const T* X, int64_t N, int64_t q, const int32_t* K, \
+                             int form, T H, T W, int64_t jmin, int64_t R,        \
+                             const T* z, int64_t M, int32_t* out) {              \
+    (void)N;                                                                     \
+    for (int64_t k = 0; k < M; ++k) {                                            \
+      if (!(z[k] >= X[0])) {                                                     \
+        out[k] = -1;                                                             \
+        continue;                                                                \
+      }                                                                          \
+      T v = grid_value_##S(form, H, W, X[0], z[k]);                              \
+      if (!(v >= (T)jmin)) v = (T)jmin;                                          \
+      if (v > (T)R) v = (T)R;                                                    \
+      int64_t t = K[(int64_t)FLOOR(v) - jmin];                                   \
+      int64_t i = t;                                                             \
+      for (int64_t c = 0; c < q; ++c) {                                          \
+        T x = (t - c >= 0) ? X[t - c] : X[0];                                    \
+        if (z[k] < x) --i;                                                       \
+      }                                                                          \
+      out[k] = (int32_t)i;                                                       \
+    }                                                                            \
+  }
+
+DEFINE_ORACLE_GAP(float, f32, floorf, fmaf, nextafterf)
+DEFINE_ORACLE_GAP(double, f64, floor, fma, nextafter)
