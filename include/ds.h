@@ -73,7 +73,10 @@ typedef enum {
   DS_METHOD_BSEARCH_LEADBIT = 1,/* Sec. 3.2.1, padded leading-bit search */
   DS_METHOD_BSEARCH_OFFSET = 2, /* Sec. 3.3, offset-based search */
   DS_METHOD_LEARNED = 3,        /* learned monotone CDF + bounded search */
-  DS_METHOD_AUTO = 4            /* Direct when feasible and under the cap, else learned */
+  DS_METHOD_AUTO = 4,           /* Direct when feasible and under the cap, else learned */
+  DS_METHOD_DIRECT_GAP = 5      /* Sec. 4.7: grid with f(X_{i+q}) > f(X_i), K_j = max{i : f(X_i) <= j}
+                                   (eq. (kgeneral)), q compares per query (eq. (index2),
+                                   algorithm DirectGap2 for q = 2; ds_build_opts.gap_q) */
 } ds_method;
 
 typedef enum {
@@ -101,6 +104,9 @@ typedef struct ds_build_opts {
   int32_t extra_layouts;    /* Direct: also build these search layouts (bit mask of
                                DS_LAYOUT_*), beyond the one the automatic choice uses */
   int32_t learn_flags;      /* learned: bit mask of DS_LEARN_* */
+  int32_t gap_q;            /* DS_METHOD_DIRECT_GAP: q in 1..16 (q <= N), or 0 = the smallest q
+                               whose grid is feasible and whose table fits table_cap_bytes
+                               (the memory-budget choice of Sec. 4.7) */
 } ds_build_opts;
 
 /* learned: the router is trained and stored in FP32.  By default the search
@@ -156,6 +162,8 @@ typedef struct ds_info_t {
   int64_t pairs_bytes;      /* bytes of the PAIRS layout (0 if not built) */
   double build_ms;          /* wall time of ds_build */
   int64_t nibble_bytes;     /* bytes of the NIBBLE layout (0 if not built) */
+  int32_t gap_q;            /* DS_METHOD_DIRECT_GAP: the q in use; 0 otherwise */
+  int32_t pad_;
 } ds_info_t;
 
 typedef struct ds_index* ds_handle;
@@ -187,7 +195,9 @@ typedef struct ds_tune {
  * Build steps: validation and minimum rounded gap (Sec. 4.4.2, eq.
  *   (distinguishable-exact), eq. (minhnumeric)); H growth (Sec. 4.4.3,
  *   algorithm ComputeHR) with every pair re-verified under the final H; R;
- *   the table K (Sec. 4, eq. (indexdef)).
+ *   the table K (Sec. 4, eq. (indexdef)).  DS_METHOD_DIRECT_GAP (Sec. 4.7)
+ *   makes the same steps over the pairs (X_i, X_{i+q}) and fills K by eq.
+ *   (kgeneral); DS_ERR_ARG for gap_q outside 0..16 or above N.
  */
 ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opts* opts, hipStream_t s,
                    ds_handle* out);

@@ -28,7 +28,8 @@ F32, F64 = 0, 1
 OK, ERR_ARG, ERR_NOT_SORTED, ERR_NONFINITE, ERR_INFEASIBLE, ERR_TABLE_CAP, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = range(9)
 FORM_SUB, FORM_FMA = 0, 1
 HSTART_PHI, HSTART_HBAR = 0, 1
-METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, METHOD_AUTO = range(5)
+METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, METHOD_AUTO, METHOD_DIRECT_GAP = range(6)
+MAX_GAP_Q = 16
 FALLBACK_NONE, FALLBACK_BSEARCH, FALLBACK_LEARNED = range(3)
 LAYOUT_RANKCODE, LAYOUT_PAIRS, LAYOUT_NIBBLE = 1, 2, 4
 # ds_tune.stage values of the Direct method
@@ -36,7 +37,7 @@ STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2, STAGE_RANKC
 _LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS, "nibble": LAYOUT_NIBBLE}
 
 _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset": METHOD_BSEARCH_OFFSET,
-            "learned": METHOD_LEARNED, "auto": METHOD_AUTO}
+            "learned": METHOD_LEARNED, "auto": METHOD_AUTO, "direct_gap": METHOD_DIRECT_GAP}
 _FORMS = {"sub": FORM_SUB, "fma": FORM_FMA}
 _HSTARTS = {"phi": HSTART_PHI, "hbar": HSTART_HBAR}
 _FALLBACKS = {"none": FALLBACK_NONE, "bsearch": FALLBACK_BSEARCH, "learned": FALLBACK_LEARNED}
@@ -55,7 +56,7 @@ class BuildOpts(ctypes.Structure):
                 ("fallback", ctypes.c_int32), ("table_cap_bytes", ctypes.c_int64),
                 ("learn_epochs", ctypes.c_int32), ("learn_segments", ctypes.c_int32),
                 ("learn_rate", ctypes.c_float), ("learn_batch", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("extra_layouts", ctypes.c_int32), ("learn_flags", ctypes.c_int32)]
+                ("extra_layouts", ctypes.c_int32), ("learn_flags", ctypes.c_int32), ("gap_q", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -66,7 +67,7 @@ class Info(ctypes.Structure):
                 ("model_bytes", ctypes.c_int64), ("max_err", ctypes.c_int64),
                 ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64),
                 ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("nibble_bytes", ctypes.c_int64)]
+                ("nibble_bytes", ctypes.c_int64), ("gap_q", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class Tune(ctypes.Structure):
@@ -239,18 +240,20 @@ class Index:
 def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart: str = "phi",
           fallback: str = "none", table_cap_bytes: int = 0, learn_epochs: int = 0, learn_segments: int = 0,
           learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), learn_fp32_router: bool = False,
-          stream=None) -> Index:
+          gap_q: int = 0, stream=None) -> Index:
     """ds_build over the N+1 values of x (a strictly increasing GPU tensor).
 
     layouts: extra Direct layouts to build besides the automatic one
     ("rankcode", "pairs", "nibble"), so that set_tune(stage=...) can select them.
+    gap_q: method "direct_gap" (Sec. 4.7): compares per query, 1..16, or 0 for the
+    smallest q whose table fits table_cap_bytes.
     """
     _check_device(x, "x")
     if x.dim() != 1 or x.numel() < 2:
         raise ValueError("x must be 1-D with at least two values")
     opts = BuildOpts(_METHODS[method], _FORMS[form], _HSTARTS[hstart], _FALLBACKS[fallback], int(table_cap_bytes),
                      int(learn_epochs), int(learn_segments), float(learn_rate), int(learn_batch), int(seed),
-                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp32_router else 0)
+                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp32_router else 0, int(gap_q))
     h = ctypes.c_void_p()
     with torch.cuda.device(x.device):
         st = _lib.ds_build(x.data_ptr(), x.numel() - 1, _dtype_code(x), ctypes.byref(opts), _stream_handle(stream),

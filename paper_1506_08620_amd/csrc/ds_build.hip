@@ -62,8 +62,11 @@ T from_bits(unsigned long long b) {
 
 constexpr int kScanBlock = 256;
 
+// One pass over X: finiteness and order of neighbours, and the smallest
+// rounded q-gap m(D_{i+q} - D_i) (q = 1 for plain Direct; Sec. 4.7 for q > 1),
+// with a flag when some D_{i+q} <= D_i (no grid can then separate X_i and X_{i+q}).
 template <typename T>
-__global__ void __launch_bounds__(kScanBlock) mingap_kernel(const T* __restrict__ X, int64_t N,
+__global__ void __launch_bounds__(kScanBlock) mingap_kernel(const T* __restrict__ X, int64_t N, int64_t q,
                                                             BuildScratch* __restrict__ scr) {
   const T X0 = X[0];
   T gmin = std::numeric_limits<T>::infinity();
@@ -73,10 +76,12 @@ __global__ void __launch_bounds__(kScanBlock) mingap_kernel(const T* __restrict_
     const T a = X[i], b = X[i + 1];
     if (!std::isfinite(a) || !std::isfinite(b)) fl |= kFlagNonFinite;
     if (!(a < b)) fl |= kFlagNotSorted;
-    const T da = a - X0, db = b - X0;  // D_i = m(X_i - X_0)
-    if (!(da < db)) fl |= kFlagOffsetsNotIncreasing;
-    const T g = db - da;               // m(D_{i+1} - D_i)
-    gmin = std::fmin(gmin, g);
+    if (i + q <= N) {
+      const T da = a - X0, dq = X[i + q] - X0;  // D_i = m(X_i - X_0)
+      if (!(da < dq)) fl |= kFlagOffsetsNotIncreasing;
+      const T g = dq - da;                     // m(D_{i+q} - D_i)
+      gmin = std::fmin(gmin, g);
+    }
   }
   __shared__ T smin[kScanBlock];
   __shared__ uint32_t sfl[kScanBlock];
@@ -98,14 +103,16 @@ __global__ void __launch_bounds__(kScanBlock) mingap_kernel(const T* __restrict_
   }
 }
 
-// smallest i in [i_start, N] with floor(f(X_{i-1})) == floor(f(X_i)), eq. (cond2)
+// smallest i in [i_start, N] with floor(f(X_{i-q})) == floor(f(X_i)): eq. (cond2)
+// for q = 1, eq. (f-monotonic-n) for q > 1 (i_start >= q)
 template <typename T, int FORM>
-__global__ void __launch_bounds__(kScanBlock) verify_kernel(const T* __restrict__ X, int64_t N, int64_t i_start,
-                                                            T H, T W, T X0, BuildScratch* __restrict__ scr) {
+__global__ void __launch_bounds__(kScanBlock) verify_kernel(const T* __restrict__ X, int64_t N, int64_t q,
+                                                            int64_t i_start, T H, T W, T X0,
+                                                            BuildScratch* __restrict__ scr) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long first = ~0ull;
   for (int64_t i = i_start + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= N; i += stride) {
-    const T a = grid_floor<T, FORM>(X[i - 1], H, W, X0);
+    const T a = grid_floor<T, FORM>(X[i - q], H, W, X0);
     const T b = grid_floor<T, FORM>(X[i], H, W, X0);
     if (a == b) {
       first = static_cast<unsigned long long>(i);
@@ -142,6 +149,44 @@ __global__ void __launch_bounds__(kFillBlock) fill_kernel(const T* __restrict__ 
     const int64_t e = j - jmin;
     if (e >= 0 && e < nK) K[e] = static_cast<int32_t>(i0 + lo - 1);  // always true when f is monotone
   }
+}
+
+// K_j = max{ i : f(X_i) <= j } for j in [jmin, R] (eq. (kgeneral), Sec. 4.7);
+// K[e] holds K_{jmin+e}.  The workgroup of X_{i0..i0+255} owns the cells from
+// f(X_{i0}) up to the one before f(X_{i0+256}) (up to R for the last
+// workgroup), and finds each entry by a binary search over its cells in LDS.
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kFillBlock) fill_max_kernel(const T* __restrict__ X, int64_t N, T H, T W, T X0,
+                                                              int32_t jmin, int64_t R, int64_t nK,
+                                                              int32_t* __restrict__ K) {
+  __shared__ int32_t c[kFillBlock];  // c[t] = f(X_{i0+t})
+  __shared__ int64_t jnext;
+  const int64_t i0 = (int64_t)blockIdx.x * kFillBlock;
+  const int64_t i = i0 + threadIdx.x;
+  if (i <= N) c[threadIdx.x] = static_cast<int32_t>(grid_floor<T, FORM>(X[i], H, W, X0));
+  if (threadIdx.x == 0)
+    jnext = (i0 + kFillBlock <= N) ? static_cast<int64_t>(grid_floor<T, FORM>(X[i0 + kFillBlock], H, W, X0)) : R + 1;
+  __syncthreads();
+  const int nb = static_cast<int>(std::min<int64_t>(kFillBlock, N + 1 - i0));
+  for (int64_t j = (int64_t)c[0] + threadIdx.x; j < jnext; j += kFillBlock) {
+    int lo = 0, hi = nb - 1;  // largest t in [0, nb - 1] with c[t] <= j (c[0] <= j)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)c[mid] <= j)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int64_t e = j - jmin;
+    if (e >= 0 && e < nK) K[e] = static_cast<int32_t>(i0 + lo);  // always true when f is monotone
+  }
+}
+
+// Xp[0..count-1] = Xp[count]: the left padding of the gap-q search, copies of X_0
+template <typename T>
+__global__ void pad_left_kernel(T* __restrict__ Xp, int64_t count) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) Xp[k] = Xp[count];
 }
 
 // RANKCODE bitmap: one wave per 64 cells.  Cell e holds an X_i exactly when
@@ -279,9 +324,11 @@ T next_up(T x) {
   return std::nextafter(x, std::numeric_limits<T>::infinity());
 }
 
-// The host half of ComputeHR for one form; see the file comment.
+// The host half of ComputeHR for one form; see the file comment.  q = 1 is
+// plain Direct; q > 1 checks the pairs (X_{i-q}, X_i) of Sec. 4.7 instead of
+// neighbours, starting from the smallest rounded q-gap g.
 template <typename T, int FORM>
-ds_status compute_hr(ds_index* h, const T* X, BuildScratch* scr, hipStream_t s, T X0, T XN, T g) {
+ds_status compute_hr(ds_index* h, const T* X, int64_t q, BuildScratch* scr, hipStream_t s, T X0, T XN, T g) {
   const int64_t N = h->N;
   const T one = T(1);
   const T Hbar = one / g;  // eq. (minhnumeric), correctly rounded
@@ -295,11 +342,11 @@ ds_status compute_hr(ds_index* h, const T* X, BuildScratch* scr, hipStream_t s, 
   const int64_t vgrid = std::min<int64_t>(grid_for(N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
   for (;;) {
     bool changed = false;
-    int64_t i_start = 1;
+    int64_t i_start = q;
     while (i_start <= N) {
       const unsigned long long none = ~0ull;
       DS_HIP_CHECK(hipMemcpyAsync(&scr->first_bad, &none, sizeof(none), hipMemcpyHostToDevice, s));
-      verify_kernel<T, FORM><<<dim3((unsigned)vgrid), dim3(kScanBlock), 0, s>>>(X, N, i_start, H, W, X0, scr);
+      verify_kernel<T, FORM><<<dim3((unsigned)vgrid), dim3(kScanBlock), 0, s>>>(X, N, q, i_start, H, W, X0, scr);
       DS_HIP_CHECK(hipGetLastError());
       unsigned long long first = 0;
       DS_HIP_CHECK(hipMemcpyAsync(&first, &scr->first_bad, sizeof(first), hipMemcpyDeviceToHost, s));
@@ -307,7 +354,8 @@ ds_status compute_hr(ds_index* h, const T* X, BuildScratch* scr, hipStream_t s, 
       if (first == ~0ull) break;
       const int64_t i = static_cast<int64_t>(first);
       T pair[2];
-      DS_HIP_CHECK(hipMemcpyAsync(pair, X + (i - 1), 2 * sizeof(T), hipMemcpyDeviceToHost, s));
+      DS_HIP_CHECK(hipMemcpyAsync(&pair[0], X + (i - q), sizeof(T), hipMemcpyDeviceToHost, s));
+      DS_HIP_CHECK(hipMemcpyAsync(&pair[1], X + i, sizeof(T), hipMemcpyDeviceToHost, s));
       DS_HIP_CHECK(hipStreamSynchronize(s));
       while (grid_floor<T, FORM>(pair[0], H, W, X0) == grid_floor<T, FORM>(pair[1], H, W, X0)) {
         H = H + P;
@@ -431,7 +479,7 @@ ds_status build_direct(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   init.first_bad = ~0ull;
   DS_HIP_CHECK(hipMemcpyAsync(scr, &init, sizeof(init), hipMemcpyHostToDevice, s));
   const int64_t grid = std::min<int64_t>(grid_for(N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
-  mingap_kernel<T><<<dim3((unsigned)grid), dim3(kScanBlock), 0, s>>>(X, N, scr);
+  mingap_kernel<T><<<dim3((unsigned)grid), dim3(kScanBlock), 0, s>>>(X, N, 1, scr);
   DS_HIP_CHECK(hipGetLastError());
   BuildScratch got{};
   T ends[2];
@@ -443,8 +491,8 @@ ds_status build_direct(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   if (got.flags & kFlagNotSorted) return DS_ERR_NOT_SORTED;
   if (got.flags & kFlagOffsetsNotIncreasing) return DS_ERR_INFEASIBLE;
   const T g = from_bits<T>(got.min_gap_bits);
-  ds_status st = (h->form == DS_FORM_FMA) ? compute_hr<T, DS_FORM_FMA>(h, X, scr, s, ends[0], ends[1], g)
-                                          : compute_hr<T, DS_FORM_SUB>(h, X, scr, s, ends[0], ends[1], g);
+  ds_status st = (h->form == DS_FORM_FMA) ? compute_hr<T, DS_FORM_FMA>(h, X, 1, scr, s, ends[0], ends[1], g)
+                                          : compute_hr<T, DS_FORM_SUB>(h, X, 1, scr, s, ends[0], ends[1], g);
   if (st != DS_OK) return st;
   h->nK = h->R - h->jmin + 1;
   const int64_t cap = o.table_cap_bytes > 0 ? o.table_cap_bytes : kDefaultTableCap;
@@ -457,6 +505,89 @@ ds_status build_direct(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   if (st != DS_OK) return st;
   st = build_layouts<T>(h, o, s);
   if (st != DS_OK) return st;
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  return DS_OK;
+}
+
+// The gap-q variant (Sec. 4.7): the grid only has to satisfy
+// f(X_{i+q}) > f(X_i), K_j = max{i : f(X_i) <= j}, and the search makes q
+// compares.  X is stored after kMaxGapQ - 1 copies of X_0 (the left padding
+// the search reads for K_j < q - 1).  With o.gap_q = 0, q is the smallest
+// value in 1..min(16, N) whose grid is feasible and whose table fits the cap
+// (the memory-budget choice the section suggests).
+template <typename T>
+ds_status build_direct_gap(ds_index* h, const ds_build_opts& o, const void* X_dev, hipStream_t s) {
+  const int64_t N = h->N;
+  const int64_t pad = kMaxGapQ - 1;
+  if (hipMalloc(&h->X, size_t(N + 1 + pad) * sizeof(T)) != hipSuccess) {
+    h->X = nullptr;
+    return DS_ERR_OOM;
+  }
+  h->nX = N + 1 + pad;
+  h->x_off = pad;
+  T* Xp = static_cast<T*>(h->X);
+  const T* X = Xp + pad;
+  DS_HIP_CHECK(hipMemcpyAsync(Xp + pad, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
+  pad_left_kernel<T><<<dim3(1), dim3(64), 0, s>>>(Xp, pad);
+  DS_HIP_CHECK(hipGetLastError());
+  BuildScratch* scr = nullptr;
+  if (hipMalloc(&scr, sizeof(BuildScratch)) != hipSuccess) return DS_ERR_OOM;
+  struct Free {
+    BuildScratch* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{scr};
+  const int64_t cap = o.table_cap_bytes > 0 ? o.table_cap_bytes : kDefaultTableCap;
+  const int64_t q_lo = o.gap_q > 0 ? o.gap_q : 1;
+  const int64_t q_hi = o.gap_q > 0 ? o.gap_q : std::min<int64_t>(kMaxGapQ, N);
+  const int64_t grid = std::min<int64_t>(grid_for(N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
+  T ends[2];
+  DS_HIP_CHECK(hipMemcpyAsync(&ends[0], X, sizeof(T), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipMemcpyAsync(&ends[1], X + N, sizeof(T), hipMemcpyDeviceToHost, s));
+  ds_status st = DS_ERR_INFEASIBLE;
+  int64_t q = q_lo;
+  for (; q <= q_hi; ++q) {
+    BuildScratch init{};
+    init.min_gap_bits = ~0ull;
+    init.first_bad = ~0ull;
+    DS_HIP_CHECK(hipMemcpyAsync(scr, &init, sizeof(init), hipMemcpyHostToDevice, s));
+    mingap_kernel<T><<<dim3((unsigned)grid), dim3(kScanBlock), 0, s>>>(X, N, q, scr);
+    DS_HIP_CHECK(hipGetLastError());
+    BuildScratch got{};
+    DS_HIP_CHECK(hipMemcpyAsync(&got, scr, sizeof(got), hipMemcpyDeviceToHost, s));
+    DS_HIP_CHECK(hipStreamSynchronize(s));
+    if (got.flags & kFlagNonFinite) return DS_ERR_NONFINITE;
+    if (got.flags & kFlagNotSorted) return DS_ERR_NOT_SORTED;
+    if (got.flags & kFlagOffsetsNotIncreasing) {
+      st = DS_ERR_INFEASIBLE;
+      continue;
+    }
+    const T g = from_bits<T>(got.min_gap_bits);
+    st = (h->form == DS_FORM_FMA) ? compute_hr<T, DS_FORM_FMA>(h, X, q, scr, s, ends[0], ends[1], g)
+                                  : compute_hr<T, DS_FORM_SUB>(h, X, q, scr, s, ends[0], ends[1], g);
+    if (st != DS_OK) continue;
+    if ((h->R - h->jmin + 1) * int64_t(sizeof(int32_t)) > cap) {
+      st = DS_ERR_TABLE_CAP;
+      continue;
+    }
+    break;
+  }
+  if (st != DS_OK) return st;
+  h->gap_q = static_cast<int32_t>(q);
+  h->nK = h->R - h->jmin + 1;
+  if (hipMalloc(&h->K, size_t(h->nK) * sizeof(int32_t)) != hipSuccess) {
+    h->K = nullptr;
+    return DS_ERR_OOM;
+  }
+  const int64_t blocks = (N + 1 + kFillBlock - 1) / kFillBlock;
+  if (h->form == DS_FORM_FMA)
+    fill_max_kernel<T, DS_FORM_FMA><<<dim3((unsigned)blocks), dim3(kFillBlock), 0, s>>>(
+        X, N, T(h->H), T(h->W), T(h->X0), static_cast<int32_t>(h->jmin), h->R, h->nK, h->K);
+  else
+    fill_max_kernel<T, DS_FORM_SUB><<<dim3((unsigned)blocks), dim3(kFillBlock), 0, s>>>(
+        X, N, T(h->H), T(h->W), T(h->X0), static_cast<int32_t>(h->jmin), h->R, h->nK, h->K);
+  DS_HIP_CHECK(hipGetLastError());
+  h->staged = tables_fit_lds(h) ? 1 : 0;
+  h->auto_stage = h->staged ? 1 : 2;
   DS_HIP_CHECK(hipStreamSynchronize(s));
   return DS_OK;
 }
@@ -506,7 +637,7 @@ ds_status validate_only(ds_index* h, const void* X_dev, hipStream_t s) {
   init.min_gap_bits = ~0ull;
   DS_HIP_CHECK(hipMemcpyAsync(scr, &init, sizeof(init), hipMemcpyHostToDevice, s));
   const int64_t grid = std::min<int64_t>(grid_for(h->N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
-  mingap_kernel<T><<<dim3((unsigned)grid), dim3(kScanBlock), 0, s>>>(static_cast<const T*>(X_dev), h->N, scr);
+  mingap_kernel<T><<<dim3((unsigned)grid), dim3(kScanBlock), 0, s>>>(static_cast<const T*>(X_dev), h->N, 1, scr);
   DS_HIP_CHECK(hipGetLastError());
   BuildScratch got{};
   DS_HIP_CHECK(hipMemcpyAsync(&got, scr, sizeof(got), hipMemcpyDeviceToHost, s));
@@ -565,12 +696,18 @@ ds_status build_typed(ds_index* h, const void* X_dev, const ds_build_opts& o, hi
     if (st != DS_OK) return st;
     return learned_build(h, &o, s);
   }
-  // Direct (or AUTO: Direct first)
-  h->method = DS_METHOD_DIRECT;
-  if (hipMalloc(&h->X, size_t(N + 1) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
-  h->nX = N + 1;
-  DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
-  ds_status st = build_direct<T>(h, o, s);
+  ds_status st;
+  if (method == DS_METHOD_DIRECT_GAP) {
+    h->method = DS_METHOD_DIRECT_GAP;
+    st = build_direct_gap<T>(h, o, X_dev, s);
+  } else {
+    // Direct (or AUTO: Direct first)
+    h->method = DS_METHOD_DIRECT;
+    if (hipMalloc(&h->X, size_t(N + 1) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
+    h->nX = N + 1;
+    DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
+    st = build_direct<T>(h, o, s);
+  }
   if (st == DS_OK) return DS_OK;
   const bool can_fall = (st == DS_ERR_INFEASIBLE || st == DS_ERR_TABLE_CAP);
   int fb = o.fallback;
@@ -583,6 +720,17 @@ ds_status build_typed(ds_index* h, const void* X_dev, const ds_build_opts& o, hi
   h->nK = 0;
   h->H = h->W = 0;
   h->R = h->jmin = 0;
+  h->gap_q = 0;
+  if (h->x_off != 0) {  // the gap variant's padded copy: replace it by a plain one
+    (void)hipFree(h->X);
+    h->x_off = 0;
+    if (hipMalloc(&h->X, size_t(N + 1) * sizeof(T)) != hipSuccess) {
+      h->X = nullptr;
+      return DS_ERR_OOM;
+    }
+    h->nX = N + 1;
+    DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
+  }
   if (fb == DS_FALLBACK_BSEARCH) {
     (void)hipFree(h->X);
     h->X = nullptr;
@@ -617,7 +765,8 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   if (dt != DS_F32 && dt != DS_F64) return DS_ERR_ARG;
   ds_build_opts o{};
   if (opts) o = *opts;
-  if (o.method < DS_METHOD_DIRECT || o.method > DS_METHOD_AUTO) return DS_ERR_ARG;
+  if (o.method < DS_METHOD_DIRECT || o.method > DS_METHOD_DIRECT_GAP) return DS_ERR_ARG;
+  if (o.gap_q < 0 || o.gap_q > ds::kMaxGapQ || (o.method == DS_METHOD_DIRECT_GAP && o.gap_q > N)) return DS_ERR_ARG;
   if (o.form != DS_FORM_SUB && o.form != DS_FORM_FMA) return DS_ERR_ARG;
   if (o.hstart != DS_HSTART_PHI && o.hstart != DS_HSTART_HBAR) return DS_ERR_ARG;
   if (o.fallback < DS_FALLBACK_NONE || o.fallback > DS_FALLBACK_LEARNED) return DS_ERR_ARG;
@@ -647,8 +796,10 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   in.method = h->method;
   in.dtype = h->dt;
   in.form = h->form;
-  in.staged = (h->method == DS_METHOD_DIRECT) ? h->auto_stage : (ds::tables_fit_lds(h) ? 1 : 2);
-  if (h->method != DS_METHOD_DIRECT) h->staged = ds::tables_fit_lds(h) ? 1 : 0;
+  const bool direct_family = h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP;
+  in.staged = direct_family ? h->auto_stage : (ds::tables_fit_lds(h) ? 1 : 2);
+  if (!direct_family) h->staged = ds::tables_fit_lds(h) ? 1 : 0;
+  in.gap_q = h->gap_q;
   in.N = h->N;
   in.H = h->H;
   in.W = h->W;

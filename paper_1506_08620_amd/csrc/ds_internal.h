@@ -16,6 +16,7 @@ constexpr int kLdsBytesPerCU = 160 * 1024;     // gfx950 LDS per compute unit (a
 constexpr int64_t kL2BytesPerXcd = int64_t(4) << 20;  // MI355X L2 per XCD
 constexpr int64_t kDefaultTableCap = int64_t(4) << 30;
 constexpr double kTwoPowQ = 2147483648.0;       // Q = 31: grid indices are int32
+constexpr int kMaxGapQ = 16;                     // largest q of the gap-q variant
 
 #define DS_HIP_CHECK(expr)                                                              \
   do {                                                                                   \
@@ -156,7 +157,8 @@ struct DirectArgs {
   const RcWord* rc_w16;      // nW interleaved words (bits, base)
   const uint8_t* rc_code8;   // N+1 8-bit codes (7-bit position, flag), for the L2 layout
   int32_t nW;
-  int32_t pad_;
+  int32_t gap_q;             // gap-q variant: compares per query
+  int64_t x_off;             // index of X_0 in X (gap-q: the left padding)
   // PAIRS layout
   const CachePair<T>* pairs; // nK pairs, pairs[0] for cell jmin
   // NIBBLE layout
@@ -196,8 +198,11 @@ struct ds_index {
   int64_t R = 0, jmin = 0;
   int64_t n_updates = 0;
   // device memory
-  void* X = nullptr;            // N+1 values (Direct, offset, learned) or padded (leading-bit)
+  void* X = nullptr;            // N+1 values (Direct, offset, learned), padded on the right
+                                // (leading-bit) or on the left (gap-q: x_off copies of X_0)
   int64_t nX = 0;               // entries in X
+  int64_t x_off = 0;            // index of X_0 in X
+  int32_t gap_q = 0;            // gap-q variant: number of compares
   int32_t* K = nullptr;         // Direct table
   int64_t nK = 0;
   // RANKCODE layout (see ds.h)

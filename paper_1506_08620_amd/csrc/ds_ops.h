@@ -154,6 +154,33 @@ struct DirectOp {
   __device__ __forceinline__ int32_t operator()(T z) const { return direct_one<T, FORM>(z, X, Kb, H, W, X0, vlo, vhi); }
 };
 
+// The gap-q search of Sec. 4.7 (eq. (index2); algorithm DirectGap2 for
+// q = 2): t = K_j with K_j = max{i : f(X_i) <= j}, i = t - sum_{k<q}
+// [z < X_{t-k}].  Xt points at X_0 with at least Q - 1 copies of X_0 before
+// it, the left padding the algorithm needs for t < q - 1 (z >= X_0 there, so
+// those compares are false).  Q bounds q; the compares are predicated, and
+// independent, so their loads are in flight together.  NaN and z < X_0 give
+// -1; z >= X_N reaches K_R = N with every compare false.
+template <typename T, int FORM, int Q>
+struct GapOp {
+  const T* Xt;
+  const int32_t* Kb;  // points at K_0
+  T H, W, X0, vlo, vhi;
+  int32_t q;
+  __device__ __forceinline__ int32_t operator()(T z) const {
+    T v = grid_value<T, FORM>(z, H, W, X0);
+    v = std::fmin(std::fmax(v, vlo), vhi);
+    const int32_t j = static_cast<int32_t>(std::floor(v));
+    const int32_t t = Kb[j];
+    int32_t i = t;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (k < q) i -= (z < Xt[t - k]) ? 1 : 0;
+    }
+    return (z >= X0) ? i : -1;
+  }
+};
+
 // RANKCODE layout (see ds.h).  With e = f(z) - jmin, K_j is the running count
 // of the 64-cell word plus the popcount of the word's lower bits.  A cell
 // without an X_i gives i = K_j - 1 directly (every X_i before it is below z

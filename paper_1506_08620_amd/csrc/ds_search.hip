@@ -72,6 +72,25 @@ __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
   }
 }
 
+// gap-q (Sec. 4.7) on the PLAIN tables: STAGE 1 = padded X and K in LDS,
+// 2 = through L1/L2.  Q = 2 for q <= 2, 16 for larger q.
+template <typename T, int FORM, int STAGE, int U, bool VEC, int Q>
+__global__ void __launch_bounds__(1024) gap_search_kernel(DirectArgs<T> a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const T* X = a.X;
+  const int32_t* K = a.K;
+  if constexpr (STAGE == 1) {
+    const int64_t xb = round16(int64_t(a.nX) * sizeof(T));
+    stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.X), int64_t(a.nX) * sizeof(T));
+    stage_bytes(smem + xb, reinterpret_cast<const unsigned char*>(a.K), int64_t(a.nK) * 4);
+    __syncthreads();
+    X = reinterpret_cast<const T*>(smem);
+    K = reinterpret_cast<const int32_t*>(smem + xb);
+  }
+  GapOp<T, FORM, Q> op{X + a.x_off, K - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi, a.gap_q};
+  stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+}
+
 template <typename T, int KIND, int STAGE, int U, bool VEC>
 __global__ void __launch_bounds__(1024) bsearch_kernel(BsearchArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -96,7 +115,7 @@ int64_t lds_bytes_needed(const ds_index* h, int stage) {
     int64_t b = 0, c = 0;
     return rankcode_offsets(h->rc_words, round16((h->N + 1) * 2), &b, &c);
   }
-  if (h->method == DS_METHOD_DIRECT) return round16(h->nX * s) + h->nK * 4;
+  if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) return round16(h->nX * s) + h->nK * 4;
   if (h->method == DS_METHOD_BSEARCH_LEADBIT || h->method == DS_METHOD_BSEARCH_OFFSET) return round16(h->nX * s);
   return int64_t(1) << 40;
 }
@@ -142,13 +161,13 @@ Shape pick_shape(const ds_index* h, int64_t M) {
   const ds_tune& t = h->tune;
   if (h->tune_set && t.stage) {
     sh.stage = t.stage;
-  } else if (h->method == DS_METHOD_DIRECT) {
+  } else if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) {
     sh.stage = h->auto_stage;
   } else {
     sh.stage = h->staged ? 1 : 2;
   }
   int block = 512, unroll = 2;
-  if (h->method == DS_METHOD_DIRECT) default_shape(h, sh.stage, &block, &unroll);
+  if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) default_shape(h, sh.stage, &block, &unroll);
   sh.block = (h->tune_set && t.block) ? t.block : block;
   sh.unroll = (h->tune_set && t.unroll) ? t.unroll : unroll;
   sh.grid = (h->tune_set && t.grid) ? t.grid : 0;
@@ -205,6 +224,31 @@ ds_status dispatch_direct(const DirectArgs<T>& a, const Shape& sh, bool vec, int
   }
 }
 
+template <typename T, int FORM, int STAGE, bool VEC, int Q>
+ds_status dispatch_gap_u(const DirectArgs<T>& a, const Shape& sh, int lds, int64_t items, hipStream_t s) {
+  switch (sh.unroll) {
+    case 1: return launch(gap_search_kernel<T, FORM, STAGE, 1, VEC, Q>, a, sh, lds, items, s);
+    case 2: return launch(gap_search_kernel<T, FORM, STAGE, 2, VEC, Q>, a, sh, lds, items, s);
+    default: return launch(gap_search_kernel<T, FORM, STAGE, 4, VEC, Q>, a, sh, lds, items, s);
+  }
+}
+
+template <typename T, int FORM, int Q>
+ds_status dispatch_gap_q(const DirectArgs<T>& a, const Shape& sh, bool vec, int lds, hipStream_t s) {
+  const int64_t items = vec ? ((a.M >> 2) + sh.unroll - 1) / sh.unroll : a.M;
+  if (sh.stage == 1) {
+    return vec ? dispatch_gap_u<T, FORM, 1, true, Q>(a, sh, lds, items, s)
+               : dispatch_gap_u<T, FORM, 1, false, Q>(a, sh, lds, items, s);
+  }
+  return vec ? dispatch_gap_u<T, FORM, 2, true, Q>(a, sh, 0, items, s)
+             : dispatch_gap_u<T, FORM, 2, false, Q>(a, sh, 0, items, s);
+}
+
+template <typename T, int FORM>
+ds_status dispatch_gap(const DirectArgs<T>& a, const Shape& sh, bool vec, int lds, hipStream_t s) {
+  return (a.gap_q <= 2) ? dispatch_gap_q<T, FORM, 2>(a, sh, vec, lds, s) : dispatch_gap_q<T, FORM, kMaxGapQ>(a, sh, vec, lds, s);
+}
+
 template <typename T, int KIND, int STAGE, bool VEC>
 ds_status dispatch_bs_u(const BsearchArgs<T>& a, const Shape& sh, int lds, int64_t items, hipStream_t s) {
   switch (sh.unroll) {
@@ -236,7 +280,7 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
   const bool vec = ((reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T))) == 0) &&
                    ((reinterpret_cast<uintptr_t>(out) % 16) == 0);
   const int lds = (sh.stage == 1 || sh.stage == 3) ? static_cast<int>(lds_bytes_needed(h, sh.stage)) : 0;
-  if (h->method == DS_METHOD_DIRECT) {
+  if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) {
     DirectArgs<T> a{};
     a.X = static_cast<const T*>(h->X);
     a.K = h->K;
@@ -258,9 +302,14 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
     a.nW = static_cast<int32_t>(h->rc_words);
     a.pairs = static_cast<const CachePair<T>*>(h->pairs);
     a.nib = h->nib;
+    a.gap_q = h->gap_q;
+    a.x_off = h->x_off;
     a.z = static_cast<const T*>(z);
     a.out = out;
     a.M = M;
+    if (h->method == DS_METHOD_DIRECT_GAP)
+      return (h->form == DS_FORM_FMA) ? dispatch_gap<T, DS_FORM_FMA>(a, sh, vec, lds, s)
+                                      : dispatch_gap<T, DS_FORM_SUB>(a, sh, vec, lds, s);
     return (h->form == DS_FORM_FMA) ? dispatch_direct<T, DS_FORM_FMA>(a, sh, vec, lds, s)
                                     : dispatch_direct<T, DS_FORM_SUB>(a, sh, vec, lds, s);
   }
