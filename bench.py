@@ -254,7 +254,7 @@ def compare_methods(ds, cases, M, stream, reps):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    res = {"direct_layouts": [], "direct_fma": [], "bsearch_leadbit": []}
+    res = {"direct_layouts": [], "direct_fma": [], "direct_gap2": [], "direct_gap4": [], "bsearch_leadbit": []}
     for c in cases:
         S = np.dtype(c["dt"]).itemsize
         tag = dict(N=c["n"], dtype="f32" if S == 4 else "f64")
@@ -272,11 +272,14 @@ def compare_methods(ds, cases, M, stream, reps):
         res["direct_layouts"].append(dict(**tag, layouts=lay, rankcode_bytes=inf["rankcode_bytes"],
                                           pairs_bytes=inf["pairs_bytes"], nibble_bytes=inf["nibble_bytes"]))
         idx.destroy()
-        for key, kw in (("direct_fma", dict(form="fma")), ("bsearch_leadbit", dict(method="leadbit"))):
+        for key, kw in (("direct_fma", dict(form="fma")), ("direct_gap2", dict(method="direct_gap", gap_q=2)),
+                        ("direct_gap4", dict(method="direct_gap", gap_q=4)), ("bsearch_leadbit", dict(method="leadbit"))):
             idx = ds.build(c["x"], **kw)
+            inf = idx.info()
             ms = timed(idx, c, out)
             res[key].append(dict(**tag, gq_s=round(M / ms / 1e6, 2),
                                  hbm_frac=round(M * (S + 4) / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                 layout=STAGE_NAMES.get(inf["staged"], "?"), table_bytes=inf["table_bytes"],
                                  same_as_direct=bool(torch.equal(out, c["out"]))))
             idx.destroy()
         del out

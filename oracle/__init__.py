@@ -60,6 +60,10 @@ def _load():
             f.argtypes, f.restype = [vp, i64, i32, ct, ct, i64, i64, vp], i32
             f = getattr(lib, f"oracle_direct_{s}")
             f.argtypes, f.restype = [vp, i64, vp, i32, ct, ct, i64, i64, vp, i64, vp], None
+            f = getattr(lib, f"oracle_eytzinger_layout_{s}")
+            f.argtypes, f.restype = [vp, i64, i64, vp], i32
+            f = getattr(lib, f"oracle_eytzinger_search_{s}")
+            f.argtypes, f.restype = [vp, i64, i64, vp, i64, vp], None
             f = getattr(lib, f"oracle_compute_hr_gap_{s}")
             f.argtypes = [vp, i64, i64, i32, i32, ctypes.POINTER(ct), ctypes.POINTER(ct),
                           ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -207,4 +211,34 @@ def direct_gap(X: np.ndarray, t: DirectTables, z: np.ndarray) -> np.ndarray:
     out = np.empty(z.size, np.int32)
     getattr(_load(), f"oracle_direct_gap_{_suffix(X.dtype)}")(_ptr(X), X.size - 1, t.q, _ptr(t.K), t.form, t.H, t.W,
                                                                t.jmin, t.R, _ptr(z), z.size, _ptr(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The Eytzinger layout and its search (Sec. 3.4).
+
+def eytzinger_levels(N: int) -> int:
+    """Smallest L with 2^L - 1 >= N + 1 (room for X_0..X_N)."""
+    L = 1
+    while (1 << L) - 1 < N + 1:
+        L += 1
+    return L
+
+
+def eytzinger_layout(X: np.ndarray, L: int | None = None):
+    """(status, Y): Y[1 .. 2^L - 1] the padded X in breadth-first tree order, Y[0] unused."""
+    X = np.ascontiguousarray(X)
+    N = X.size - 1
+    L = eytzinger_levels(N) if L is None else L
+    Y = np.empty(1 << L, X.dtype)
+    st = getattr(_load(), f"oracle_eytzinger_layout_{_suffix(X.dtype)}")(_ptr(X), N, L, _ptr(Y))
+    return st, Y
+
+
+def eytzinger_search(Y: np.ndarray, N: int, L: int, z: np.ndarray) -> np.ndarray:
+    """The L-level descent over Y; i = #{k : X_k <= z} - 1 like every search here."""
+    Y = np.ascontiguousarray(Y)
+    z = np.ascontiguousarray(z, dtype=Y.dtype)
+    out = np.empty(z.size, np.int32)
+    getattr(_load(), f"oracle_eytzinger_search_{_suffix(Y.dtype)}")(_ptr(Y), N, L, _ptr(z), z.size, _ptr(out))
     return out

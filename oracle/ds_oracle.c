@@ -23,6 +23,11 @@
  *                     to left as in algorithm InitK).
  *   oracle_direct_*   the Direct search (Sec. 4.2, algorithm Direct) on the
  *                     oracle's own tables; used only to pin the build.
+ *   oracle_eytzinger_layout_*, oracle_eytzinger_search_*
+ *                     the cache-friendly binary search of Sec. 3.4: X padded
+ *                     with X_N to 2^L - 1 values and stored in breadth-first
+ *                     order of the complete search tree (the Eytzinger
+ *                     layout), searched by descending L levels.
  *   oracle_compute_hr_gap_*, oracle_init_k_gap_*, oracle_direct_gap_*
  *                     the relaxed variant of Sec. 4.7 ("Relaxing Limitations
  *                     and Reducing Memory Usage"): the grid only has to
@@ -312,3 +317,48 @@ DEFINE_ORACLE(double, f64, floor, fma, nextafter)
 
 DEFINE_ORACLE_GAP(float, f32, floorf, fmaf, nextafterf)
 DEFINE_ORACLE_GAP(double, f64, floor, fma, nextafter)
+
+/*
+ * Sec. 3.4, the Eytzinger layout: Y[1 .. 2^L - 1] holds the padded array
+ * P_0 .. P_{2^L - 2} (P_i = X_i for i <= N, X_N after) in breadth-first order
+ * of the complete binary search tree, node k having children 2k and 2k + 1
+ * (Y[0] is unused).  L is the smallest height with 2^L - 1 >= N + 1.
+ */
+#define DEFINE_ORACLE_EYT(T, S)                                                  \
+                                                                                 \
+  /* in-order walk of the tree: the n-th node visited receives P_n */          \
+  static void eyt_fill_##S(const T* X, int64_t N, int64_t nodes, int64_t k,     \
+                           int64_t* next, T* Y) {                                \
+    if (k > nodes) return;                                                       \
+    eyt_fill_##S(X, N, nodes, 2 * k, next, Y);                                   \
+    Y[k] = (*next <= N) ? X[*next] : X[N];                                       \
+    ++*next;                                                                     \
+    eyt_fill_##S(X, N, nodes, 2 * k + 1, next, Y);                               \
+  }                                                                              \
+                                                                                 \
+  int oracle_eytzinger_layout_##S(const T* X, int64_t N, int64_t L, T* Y) {      \
+    if (N < 1 || L < 1 || L > 40 || ((int64_t)1 << L) - 1 < N + 1) return OR_ERR_ARG; \
+    const int64_t nodes = ((int64_t)1 << L) - 1;                                 \
+    int64_t next = 0;                                                            \
+    Y[0] = X[0];                                                                 \
+    eyt_fill_##S(X, N, nodes, 1, &next, Y);                                      \
+    return OR_OK;                                                                \
+  }                                                                              \
+                                                                                 \
+  /* Descend L levels, k <- 2k + [z >= Y_k]; the leaf reached, k - 2^L, counts \
+   * the padded values <= z (each step to the right passes a node and its left \
+   * subtree).  i = min(count, N + 1) - 1: the pads equal X_N, so they only    \
+   * count for z >= X_N, where the result is N; NaN counts nothing: -1. */     \
+  void oracle_eytzinger_search_##S(const T* Y, int64_t N, int64_t L, const T* z, \
+                                   int64_t M, int32_t* out) {                    \
+    for (int64_t m = 0; m < M; ++m) {                                            \
+      int64_t k = 1;                                                             \
+      for (int64_t d = 0; d < L; ++d) k = 2 * k + (z[m] >= Y[k] ? 1 : 0);        \
+      int64_t c = k - ((int64_t)1 << L);                                         \
+      if (c > N + 1) c = N + 1;                                                  \
+      out[m] = (int32_t)(c - 1);                                                 \
+    }                                                                            \
+  }
+
+DEFINE_ORACLE_EYT(float, f32)
+DEFINE_ORACLE_EYT(double, f64)
