@@ -254,7 +254,8 @@ def compare_methods(ds, cases, M, stream, reps):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    res = {"direct_layouts": [], "direct_fma": [], "direct_gap2": [], "direct_gap4": [], "bsearch_leadbit": []}
+    res = {"direct_layouts": [], "direct_fma": [], "direct_gap2": [], "direct_gap4": [], "bsearch_leadbit": [],
+           "bsearch_eytzinger": []}
     for c in cases:
         S = np.dtype(c["dt"]).itemsize
         tag = dict(N=c["n"], dtype="f32" if S == 4 else "f64")
@@ -273,7 +274,8 @@ def compare_methods(ds, cases, M, stream, reps):
                                           pairs_bytes=inf["pairs_bytes"], nibble_bytes=inf["nibble_bytes"]))
         idx.destroy()
         for key, kw in (("direct_fma", dict(form="fma")), ("direct_gap2", dict(method="direct_gap", gap_q=2)),
-                        ("direct_gap4", dict(method="direct_gap", gap_q=4)), ("bsearch_leadbit", dict(method="leadbit"))):
+                        ("direct_gap4", dict(method="direct_gap", gap_q=4)), ("bsearch_leadbit", dict(method="leadbit")),
+                        ("bsearch_eytzinger", dict(method="eytzinger"))):
             idx = ds.build(c["x"], **kw)
             inf = idx.info()
             ms = timed(idx, c, out)

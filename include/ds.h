@@ -74,9 +74,13 @@ typedef enum {
   DS_METHOD_BSEARCH_OFFSET = 2, /* Sec. 3.3, offset-based search */
   DS_METHOD_LEARNED = 3,        /* learned monotone CDF + bounded search */
   DS_METHOD_AUTO = 4,           /* Direct when feasible and under the cap, else learned */
-  DS_METHOD_DIRECT_GAP = 5      /* Sec. 4.7: grid with f(X_{i+q}) > f(X_i), K_j = max{i : f(X_i) <= j}
+  DS_METHOD_DIRECT_GAP = 5,     /* Sec. 4.7: grid with f(X_{i+q}) > f(X_i), K_j = max{i : f(X_i) <= j}
                                    (eq. (kgeneral)), q compares per query (eq. (index2),
                                    algorithm DirectGap2 for q = 2; ds_build_opts.gap_q) */
+  DS_METHOD_BSEARCH_EYTZINGER = 6 /* Sec. 3.4: X padded with X_N to 2^L - 1 values in the
+                                   breadth-first order of the complete search tree (the
+                                   Eytzinger layout), L = ceil(log2(N + 2)) levels of descent;
+                                   the top levels (64 KiB) are staged in LDS */
 } ds_method;
 
 typedef enum {
@@ -176,7 +180,8 @@ typedef struct ds_tune {
   int32_t stage;            /* 0 = auto; Direct: 1 = PLAIN in LDS, 2 = PLAIN through L2,
                                3 = RANKCODE in LDS, 4 = PAIRS through L2,
                                5 = RANKCODE through L2, 6 = NIBBLE through L2; binary
-                               search: 1 = X in LDS, 2 = X through L2 */
+                               search: 1 = X in LDS, 2 = X through L2; Eytzinger: 1 = top
+                               levels in LDS, 2 = every level through L2 */
   int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */
 } ds_tune;
 

@@ -28,7 +28,8 @@ F32, F64 = 0, 1
 OK, ERR_ARG, ERR_NOT_SORTED, ERR_NONFINITE, ERR_INFEASIBLE, ERR_TABLE_CAP, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = range(9)
 FORM_SUB, FORM_FMA = 0, 1
 HSTART_PHI, HSTART_HBAR = 0, 1
-METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, METHOD_AUTO, METHOD_DIRECT_GAP = range(6)
+(METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, METHOD_AUTO, METHOD_DIRECT_GAP,
+ METHOD_BSEARCH_EYTZINGER) = range(7)
 MAX_GAP_Q = 16
 FALLBACK_NONE, FALLBACK_BSEARCH, FALLBACK_LEARNED = range(3)
 LAYOUT_RANKCODE, LAYOUT_PAIRS, LAYOUT_NIBBLE = 1, 2, 4
@@ -37,7 +38,8 @@ STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2, STAGE_RANKC
 _LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS, "nibble": LAYOUT_NIBBLE}
 
 _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset": METHOD_BSEARCH_OFFSET,
-            "learned": METHOD_LEARNED, "auto": METHOD_AUTO, "direct_gap": METHOD_DIRECT_GAP}
+            "learned": METHOD_LEARNED, "auto": METHOD_AUTO, "direct_gap": METHOD_DIRECT_GAP,
+            "eytzinger": METHOD_BSEARCH_EYTZINGER}
 _FORMS = {"sub": FORM_SUB, "fma": FORM_FMA}
 _HSTARTS = {"phi": HSTART_PHI, "hbar": HSTART_HBAR}
 _FALLBACKS = {"none": FALLBACK_NONE, "bsearch": FALLBACK_BSEARCH, "learned": FALLBACK_LEARNED}

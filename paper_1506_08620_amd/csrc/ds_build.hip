@@ -624,6 +624,43 @@ ds_status build_bsearch(ds_index* h, const void* X_dev, hipStream_t s) {
   return DS_OK;
 }
 
+// Eytzinger layout (Sec. 3.4): node b of the complete tree of L levels (depth
+// d = floor(log2 b), position p = b - 2^d in its level) is the in-order
+// element (2p + 1) 2^(L-1-d) - 1 of the padded array X_0..X_N, X_N, ...
+template <typename T>
+__global__ void eyt_layout_kernel(const T* __restrict__ X, int64_t N, int L, T* __restrict__ Y) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nodes = int64_t(1) << L;
+  if (b >= nodes) return;
+  if (b == 0) {
+    Y[0] = X[0];  // unused slot
+    return;
+  }
+  const int d = 63 - __clzll(static_cast<unsigned long long>(b));
+  const int64_t p = b - (int64_t(1) << d);
+  const int64_t idx = ((2 * p + 1) << (L - 1 - d)) - 1;
+  Y[b] = X[idx <= N ? idx : N];
+}
+
+template <typename T>
+ds_status build_eytzinger(ds_index* h, const void* X_dev, hipStream_t s) {
+  const int64_t N = h->N;
+  int L = 1;
+  while ((int64_t(1) << L) - 1 < N + 1) ++L;
+  const int64_t n = int64_t(1) << L;
+  if (hipMalloc(&h->X, size_t(n) * sizeof(T)) != hipSuccess) {
+    h->X = nullptr;
+    return DS_ERR_OOM;
+  }
+  h->nX = n;
+  h->eyt_L = L;
+  eyt_layout_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(static_cast<const T*>(X_dev), N, L,
+                                                                                static_cast<T*>(h->X));
+  DS_HIP_CHECK(hipGetLastError());
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  return DS_OK;
+}
+
 // the validation pass alone, for the binary-search methods
 template <typename T>
 ds_status validate_only(ds_index* h, const void* X_dev, hipStream_t s) {
@@ -686,6 +723,12 @@ ds_status build_typed(ds_index* h, const void* X_dev, const ds_build_opts& o, hi
     if (st != DS_OK) return st;
     h->method = method;
     return build_bsearch<T>(h, X_dev, s);
+  }
+  if (method == DS_METHOD_BSEARCH_EYTZINGER) {
+    ds_status st = validate_only<T>(h, X_dev, s);
+    if (st != DS_OK) return st;
+    h->method = method;
+    return build_eytzinger<T>(h, X_dev, s);
   }
   if (method == DS_METHOD_LEARNED) {
     h->method = DS_METHOD_LEARNED;
@@ -765,7 +808,7 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   if (dt != DS_F32 && dt != DS_F64) return DS_ERR_ARG;
   ds_build_opts o{};
   if (opts) o = *opts;
-  if (o.method < DS_METHOD_DIRECT || o.method > DS_METHOD_DIRECT_GAP) return DS_ERR_ARG;
+  if (o.method < DS_METHOD_DIRECT || o.method > DS_METHOD_BSEARCH_EYTZINGER) return DS_ERR_ARG;
   if (o.gap_q < 0 || o.gap_q > ds::kMaxGapQ || (o.method == DS_METHOD_DIRECT_GAP && o.gap_q > N)) return DS_ERR_ARG;
   if (o.form != DS_FORM_SUB && o.form != DS_FORM_FMA) return DS_ERR_ARG;
   if (o.hstart != DS_HSTART_PHI && o.hstart != DS_HSTART_HBAR) return DS_ERR_ARG;

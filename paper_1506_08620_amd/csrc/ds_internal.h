@@ -17,6 +17,15 @@ constexpr int64_t kL2BytesPerXcd = int64_t(4) << 20;  // MI355X L2 per XCD
 constexpr int64_t kDefaultTableCap = int64_t(4) << 30;
 constexpr double kTwoPowQ = 2147483648.0;       // Q = 31: grid indices are int32
 constexpr int kMaxGapQ = 16;                     // largest q of the gap-q variant
+constexpr int kEytLdsBytes = 64 * 1024;          // LDS for the top levels of the Eytzinger tree
+
+// levels of the Eytzinger tree whose nodes (plus the unused slot 0) fit kEytLdsBytes
+template <typename T>
+__host__ __device__ inline int eyt_lds_levels(int L) {
+  int t = 0;
+  while (t < L && (int64_t(2) << t) * int64_t(sizeof(T)) <= kEytLdsBytes) ++t;
+  return t;
+}
 
 #define DS_HIP_CHECK(expr)                                                              \
   do {                                                                                   \
@@ -203,6 +212,7 @@ struct ds_index {
   int64_t nX = 0;               // entries in X
   int64_t x_off = 0;            // index of X_0 in X
   int32_t gap_q = 0;            // gap-q variant: number of compares
+  int32_t eyt_L = 0;            // Eytzinger layout: levels (X holds 2^L values, X[0] unused)
   int32_t* K = nullptr;         // Direct table
   int64_t nK = 0;
   // RANKCODE layout (see ds.h)

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
 }
 
 // gap-q (Sec. 4.7) on the PLAIN tables: STAGE 1 = padded X and K in LDS,
-// 2 = through L1/L2.  Q = 2 for q <= 2, 16 for larger q.
+// 2 = through L1/L2.  Q = 2 for q <= 2, 4 for q <= 4, 16 for larger q.
 template <typename T, int FORM, int STAGE, int U, bool VEC, int Q>
 __global__ void __launch_bounds__(1024) gap_search_kernel(DirectArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -109,8 +109,108 @@ __global__ void __launch_bounds__(1024) bsearch_kernel(BsearchArgs<T> a) {
   }
 }
 
+template <typename T>
+struct EytArgs {
+  const T* Y;          // 2^L values, node k at Y[k] (Y[0] unused)
+  int32_t L;           // levels
+  int32_t lds_levels;  // levels staged in LDS (STAGE 1)
+  int32_t N;
+  int32_t pad_;
+  const T* z;
+  int32_t* out;
+  int64_t M;
+};
+
+// The descent of Sec. 3.4 for one query: k <- 2k + [z >= Y_k] for L levels,
+// the first `lt` from Yl (LDS), the rest from Yg.  The leaf k - 2^L counts the
+// padded values <= z; the pads equal X_N, so min(count, N + 1) - 1 is the
+// result everywhere (-1 below X_0 and for NaN, N at or above X_N).
+template <typename T>
+__device__ __forceinline__ int32_t eyt_one(T z, const T* Yl, const T* Yg, int lt, int L, int32_t N) {
+  uint32_t k = 1;
+  for (int d = 0; d < lt; ++d) k = 2 * k + (z >= Yl[k] ? 1u : 0u);
+  uint64_t kk = k;
+  for (int d = lt; d < L; ++d) kk = 2 * kk + (z >= Yg[kk] ? 1u : 0u);
+  const int64_t c = static_cast<int64_t>(kk - (uint64_t(1) << L));
+  return static_cast<int32_t>((c < int64_t(N) + 1 ? c : int64_t(N) + 1) - 1);
+}
+
+// STAGE 1: the top levels in LDS, the rest through L1/L2; 2: all through
+// L1/L2.  A lane descends its 4U queries in lockstep, so the gathers of one
+// level are in flight together; vector indices past the end are clamped to
+// the last vector and only the stores are guarded.
+template <typename T, int STAGE, int U, bool VEC>
+__global__ void __launch_bounds__(1024) eytzinger_kernel(EytArgs<T> a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const T* Yl = a.Y;
+  int lt = 0;
+  if constexpr (STAGE == 1) {
+    lt = a.lds_levels;
+    stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.Y), (int64_t(1) << lt) * int64_t(sizeof(T)));
+    __syncthreads();
+    Yl = reinterpret_cast<const T*>(smem);
+  }
+  const int L = a.L;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if constexpr (VEC) {
+    const int64_t nvec = a.M >> 2;
+    const vec4<T>* zv = reinterpret_cast<const vec4<T>*>(a.z);
+    ivec4* ov = reinterpret_cast<ivec4*>(a.out);
+    const int64_t B = blockDim.x;
+    const int64_t step = (int64_t)gridDim.x * B * U;
+    for (int64_t base = (int64_t)blockIdx.x * B * U + threadIdx.x; base < nvec; base += step) {
+      vec4<T> q[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u] = __builtin_nontemporal_load(zv + std::min<int64_t>(base + u * B, nvec - 1));
+      uint32_t k[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) k[u][l] = 1;
+      for (int d = 0; d < lt; ++d) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) k[u][l] = 2 * k[u][l] + (q[u][l] >= Yl[k[u][l]] ? 1u : 0u);
+      }
+      uint64_t kk[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) kk[u][l] = k[u][l];
+      for (int d = lt; d < L; ++d) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) kk[u][l] = 2 * kk[u][l] + (q[u][l] >= a.Y[kk[u][l]] ? 1u : 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (base + u * B < nvec) {
+          ivec4 o;
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            const int64_t c = static_cast<int64_t>(kk[u][l] - (uint64_t(1) << L));
+            o[l] = static_cast<int32_t>((c < int64_t(a.N) + 1 ? c : int64_t(a.N) + 1) - 1);
+          }
+          __builtin_nontemporal_store(o, ov + base + u * B);
+        }
+      }
+    }
+    const int64_t t = (nvec << 2) + gtid;
+    if (t < a.M) a.out[t] = eyt_one(a.z[t], Yl, a.Y, lt, L, a.N);
+  } else {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t m = gtid; m < a.M; m += step) a.out[m] = eyt_one(a.z[m], Yl, a.Y, lt, L, a.N);
+  }
+}
+
 int64_t lds_bytes_needed(const ds_index* h, int stage) {
   const int64_t s = (h->dt == DS_F32) ? 4 : 8;
+  if (h->method == DS_METHOD_BSEARCH_EYTZINGER) {
+    const int lt = (h->dt == DS_F32) ? eyt_lds_levels<float>(h->eyt_L) : eyt_lds_levels<double>(h->eyt_L);
+    return (int64_t(1) << lt) * s;
+  }
   if (h->method == DS_METHOD_DIRECT && stage == 3) {
     int64_t b = 0, c = 0;
     return rankcode_offsets(h->rc_words, round16((h->N + 1) * 2), &b, &c);
@@ -246,7 +346,9 @@ ds_status dispatch_gap_q(const DirectArgs<T>& a, const Shape& sh, bool vec, int 
 
 template <typename T, int FORM>
 ds_status dispatch_gap(const DirectArgs<T>& a, const Shape& sh, bool vec, int lds, hipStream_t s) {
-  return (a.gap_q <= 2) ? dispatch_gap_q<T, FORM, 2>(a, sh, vec, lds, s) : dispatch_gap_q<T, FORM, kMaxGapQ>(a, sh, vec, lds, s);
+  if (a.gap_q <= 2) return dispatch_gap_q<T, FORM, 2>(a, sh, vec, lds, s);
+  if (a.gap_q <= 4) return dispatch_gap_q<T, FORM, 4>(a, sh, vec, lds, s);
+  return dispatch_gap_q<T, FORM, kMaxGapQ>(a, sh, vec, lds, s);
 }
 
 template <typename T, int KIND, int STAGE, bool VEC>
@@ -267,6 +369,24 @@ ds_status dispatch_bs(const BsearchArgs<T>& a, const Shape& sh, bool vec, int ld
   }
   return vec ? dispatch_bs_u<T, KIND, 2, true>(a, sh, 0, items, s)
              : dispatch_bs_u<T, KIND, 2, false>(a, sh, 0, items, s);
+}
+
+template <typename T, int STAGE, bool VEC>
+ds_status dispatch_eyt_u(const EytArgs<T>& a, const Shape& sh, int lds, int64_t items, hipStream_t s) {
+  switch (sh.unroll) {
+    case 1: return launch(eytzinger_kernel<T, STAGE, 1, VEC>, a, sh, lds, items, s);
+    case 2: return launch(eytzinger_kernel<T, STAGE, 2, VEC>, a, sh, lds, items, s);
+    default: return launch(eytzinger_kernel<T, STAGE, 4, VEC>, a, sh, lds, items, s);
+  }
+}
+
+template <typename T>
+ds_status dispatch_eyt(const EytArgs<T>& a, const Shape& sh, bool vec, int lds, hipStream_t s) {
+  const int64_t items = vec ? ((a.M >> 2) + sh.unroll - 1) / sh.unroll : a.M;
+  if (sh.stage == 1) {
+    return vec ? dispatch_eyt_u<T, 1, true>(a, sh, lds, items, s) : dispatch_eyt_u<T, 1, false>(a, sh, lds, items, s);
+  }
+  return vec ? dispatch_eyt_u<T, 2, true>(a, sh, 0, items, s) : dispatch_eyt_u<T, 2, false>(a, sh, 0, items, s);
 }
 
 template <typename T>
@@ -312,6 +432,17 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
                                       : dispatch_gap<T, DS_FORM_SUB>(a, sh, vec, lds, s);
     return (h->form == DS_FORM_FMA) ? dispatch_direct<T, DS_FORM_FMA>(a, sh, vec, lds, s)
                                     : dispatch_direct<T, DS_FORM_SUB>(a, sh, vec, lds, s);
+  }
+  if (h->method == DS_METHOD_BSEARCH_EYTZINGER) {
+    EytArgs<T> e{};
+    e.Y = static_cast<const T*>(h->X);
+    e.L = h->eyt_L;
+    e.lds_levels = eyt_lds_levels<T>(h->eyt_L);
+    e.N = static_cast<int32_t>(h->N);
+    e.z = static_cast<const T*>(z);
+    e.out = out;
+    e.M = M;
+    return dispatch_eyt<T>(e, sh, vec, lds, s);
   }
   BsearchArgs<T> a{};
   a.X = static_cast<const T*>(h->X);
