@@ -41,6 +41,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "ds_device.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -247,6 +249,48 @@ ds_status ds_destroy(ds_handle h);
 
 /* ds_status_str: static English text for a status code. */
 const char* ds_status_str(ds_status st);
+
+/*
+ * ds_get_view: fills *view (host memory) with the Direct tables of h for the
+ * scalar-problem device API of ds_device.h (Sec. 2, scalar search problem).
+ * The device pointers stay valid until ds_destroy(h).  DS_ERR_UNSUPPORTED for
+ * a handle whose method is not DS_METHOD_DIRECT; DS_ERR_ARG for NULL.
+ */
+ds_status ds_get_view(ds_handle h, ds_view* view);
+
+/*
+ * ds_view_search: the vectorial problem solved through the scalar device
+ * API: one thread per query calls ds_find_f32 / ds_find_f64 on *view (the
+ * kernel is compiled against ds_device.h alone).  Same arguments and results
+ * as ds_search.  Asynchronous on s; DS_ERR_ARG for NULL pointers or M < 0.
+ */
+ds_status ds_view_search(const ds_view* view, const void* z_dev, int64_t M, int32_t* out_dev, hipStream_t s);
+
+/*
+ * ds_histogram: counts_dev[i + 1] += #{k < M : search(z_k) = i} for i in
+ * [-1, N], the count of samples per interval [X_i, X_{i+1}) plus one bin
+ * below X_0 (and NaN) and one at or above X_N (the second use case of
+ * Sec. 2).  counts_dev holds N + 2 uint64 counters that the caller
+ * initialises (so batches accumulate).  The search is fused into the counting
+ * kernel: the queries are read once and no index is written.  Bins are kept
+ * in LDS when they fit beside the tables, else counted with global atomics.
+ * Method DS_METHOD_DIRECT only (else DS_ERR_UNSUPPORTED); asynchronous on s.
+ */
+ds_status ds_histogram(ds_handle h, const void* z_dev, int64_t M, uint64_t* counts_dev, hipStream_t s);
+
+/*
+ * ds_interp_linear: y_dev[k] = piecewise-linear interpolation of the knots
+ * (X_i, Y_i) at z_k (the first use case of Sec. 2), computed in the handle's
+ * precision as
+ *     i = search(z_k);  y = Y_i + ((z_k - X_i) / (X_{i+1} - X_i)) * (Y_{i+1} - Y_i)
+ * for 0 <= i < N, with no contraction; y = Y_0 below X_0, Y_N at or above
+ * X_N, and NaN for a NaN query.  Y_dev holds N + 1 values of the handle's
+ * dtype, y_dev M values (may not overlap z_dev or Y_dev).  The search is fused
+ * into the kernel.  Method DS_METHOD_DIRECT only (else DS_ERR_UNSUPPORTED);
+ * asynchronous on s.
+ */
+ds_status ds_interp_linear(ds_handle h, const void* Y_dev, const void* z_dev, int64_t M, void* y_dev,
+                           hipStream_t s);
 
 /* ------------------------------------------------------------------------
  * The learned router's training and inference kernels, exposed for checking

@@ -49,7 +49,8 @@ METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_autotune", "ds_info", "ds_copy_table", "ds_destroy", "ds_status_str",
            "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_autotune", "ds_batch_report",
            "ds_batch_fallbacks",
-           "ds_learned_grad", "ds_learned_forward", "ds_learned_model")
+           "ds_learned_grad", "ds_learned_forward", "ds_learned_model",
+           "ds_get_view", "ds_view_search", "ds_histogram", "ds_interp_linear")
 N_ROUTER_PARAMS = 1153
 
 
@@ -70,6 +71,13 @@ class Info(ctypes.Structure):
                 ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64),
                 ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
                 ("nibble_bytes", ctypes.c_int64), ("gap_q", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class View(ctypes.Structure):
+    """ds_view of ds_device.h: the Direct tables for the scalar-problem device API."""
+    _fields_ = [("dtype", ctypes.c_int32), ("form", ctypes.c_int32), ("N", ctypes.c_int32), ("jmin", ctypes.c_int32),
+                ("R", ctypes.c_int32), ("pad_", ctypes.c_int32), ("H", ctypes.c_double), ("W", ctypes.c_double),
+                ("X0", ctypes.c_double), ("X", ctypes.c_void_p), ("K", ctypes.c_void_p)]
 
 
 class Tune(ctypes.Structure):
@@ -131,6 +139,14 @@ def _load_library():
     lib.ds_batch_autotune.restype = i32
     lib.ds_batch_report.argtypes = [ctypes.POINTER(BatchDesc), vp, vp, vp]
     lib.ds_batch_report.restype = i32
+    lib.ds_get_view.argtypes = [vp, ctypes.POINTER(View)]
+    lib.ds_get_view.restype = i32
+    lib.ds_view_search.argtypes = [ctypes.POINTER(View), vp, i64, vp, vp]
+    lib.ds_view_search.restype = i32
+    lib.ds_histogram.argtypes = [vp, vp, i64, vp, vp]
+    lib.ds_histogram.restype = i32
+    lib.ds_interp_linear.argtypes = [vp, vp, vp, i64, vp, vp]
+    lib.ds_interp_linear.restype = i32
     return lib
 
 
@@ -208,6 +224,47 @@ class Index:
             raise DsError(st, "ds_autotune")
         return {name: getattr(t, name) for name, _ in Tune._fields_}
 
+    def view(self) -> View:
+        """ds_get_view: the Direct tables as a ds_view (valid while this index lives)."""
+        v = View()
+        st = _lib.ds_get_view(self._h, ctypes.byref(v))
+        if st != OK:
+            raise DsError(st, "ds_get_view")
+        return v
+
+    def histogram(self, z: torch.Tensor, counts: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """ds_histogram: adds the number of queries per interval to counts (N + 2 int64,
+        bin i + 1 for result i; zeros if not given)."""
+        _check_device(z, "z")
+        if z.dtype != self.dtype or not z.is_contiguous():
+            raise ValueError("z must be a contiguous tensor of the index dtype")
+        n = self.info()["N"]
+        if counts is None:
+            counts = torch.zeros(n + 2, dtype=torch.int64, device=z.device)
+        if counts.dtype != torch.int64 or counts.numel() != n + 2 or not counts.is_contiguous():
+            raise ValueError("counts must be N + 2 contiguous int64")
+        st = _lib.ds_histogram(self._h, z.data_ptr(), z.numel(), counts.data_ptr(), _stream_handle(stream))
+        if st != OK:
+            raise DsError(st, "ds_histogram")
+        return counts
+
+    def interp_linear(self, Y: torch.Tensor, z: torch.Tensor, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+        """ds_interp_linear: piecewise-linear interpolation of the knots (X_i, Y_i) at z."""
+        _check_device(z, "z")
+        _check_device(Y, "Y")
+        if z.dtype != self.dtype or Y.dtype != self.dtype or not z.is_contiguous() or not Y.is_contiguous():
+            raise ValueError("Y and z must be contiguous tensors of the index dtype")
+        if Y.numel() != self.info()["N"] + 1:
+            raise ValueError("Y must hold N + 1 values")
+        if out is None:
+            out = torch.empty_like(z)
+        st = _lib.ds_interp_linear(self._h, Y.data_ptr(), z.data_ptr(), z.numel(), out.data_ptr(),
+                                   _stream_handle(stream))
+        if st != OK:
+            raise DsError(st, "ds_interp_linear")
+        return out
+
     def learned_model(self, stream=None):
         """(trained router parameters as a numpy float32 array, fallback count)."""
         import numpy as np
@@ -263,6 +320,17 @@ def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart:
     if st != OK:
         raise DsError(st, "ds_build")
     return Index(h.value, x.dtype, x.device)
+
+
+def view_search(view: View, z: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """ds_view_search: every query through the scalar device API of ds_device.h."""
+    _check_device(z, "z")
+    if out is None:
+        out = torch.empty(z.numel(), dtype=torch.int32, device=z.device)
+    st = _lib.ds_view_search(ctypes.byref(view), z.data_ptr(), z.numel(), out.data_ptr(), _stream_handle(stream))
+    if st != OK:
+        raise DsError(st, "ds_view_search")
+    return out
 
 
 def search(index: Index, z: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libds.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["ds_build.hip", "ds_search.hip", "ds_batched.hip", "ds_learned.hip"]
+SOURCES = ["ds_build.hip", "ds_search.hip", "ds_batched.hip", "ds_learned.hip", "ds_apps.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

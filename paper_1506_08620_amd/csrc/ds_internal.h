@@ -244,6 +244,7 @@ namespace ds {
 ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);
 bool tables_fit_lds(const ds_index* h);
 int64_t rankcode_lds_bytes(const ds_index* h);
+int64_t direct_lds_bytes(const ds_index* h, int stage);  // LDS bytes of a Direct layout staged by the search
 // implemented in ds_learned.hip
 ds_status learned_build(ds_index* h, const ds_build_opts* o, hipStream_t s);
 ds_status learned_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);

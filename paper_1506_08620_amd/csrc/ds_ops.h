@@ -16,6 +16,14 @@ using ivec4 = int __attribute__((ext_vector_type(4)));
 
 __host__ __device__ constexpr int64_t round16(int64_t b) { return (b + 15) & ~int64_t(15); }
 
+// LDS offsets of the RANKCODE layout staged as bits | counts | codes
+__host__ __device__ constexpr int64_t rankcode_offsets(int64_t nW, int64_t n_code_bytes, int64_t* base_off,
+                                                       int64_t* code_off) {
+  *base_off = round16(nW * 8);
+  *code_off = *base_off + round16(nW * 4);
+  return *code_off + round16(n_code_bytes);
+}
+
 // Copy n_bytes (multiple of 4) from global to LDS with 16-byte moves, four
 // loads in flight per lane before the stores.
 __device__ __forceinline__ void stage_bytes(unsigned char* __restrict__ dst, const unsigned char* __restrict__ src,

@@ -20,12 +20,6 @@ namespace ds {
 
 namespace {
 
-__host__ __device__ constexpr int64_t rankcode_offsets(int64_t nW, int64_t n_code_bytes, int64_t* base_off,
-                                                       int64_t* code_off) {
-  *base_off = round16(nW * 8);
-  *code_off = *base_off + round16(nW * 4);
-  return *code_off + round16(n_code_bytes);
-}
 
 // STAGE 1: PLAIN in LDS; 2: PLAIN through L1/L2; 3: RANKCODE in LDS;
 // 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2; 6: NIBBLE through L1/L2.
@@ -462,6 +456,7 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
 }  // namespace
 
 bool tables_fit_lds(const ds_index* h) { return lds_bytes_needed(h, 1) <= kLdsBytesPerCU; }
+int64_t direct_lds_bytes(const ds_index* h, int stage) { return lds_bytes_needed(h, stage); }
 int64_t rankcode_lds_bytes(const ds_index* h) { return lds_bytes_needed(h, 3); }
 
 ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s) {

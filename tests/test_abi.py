@@ -13,10 +13,19 @@ LIB = os.path.join(ROOT, "paper_1506_08620_amd", "libds.so")
 
 
 def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*[A-Za-z_][\w\s\*]*?\b(ds_\w+)\s*\(", text, flags=re.M)
-    return sorted(set(names))
+    """Every ds_* function the headers under include/ declare, except the static inline
+    device functions of the scalar-problem API (compiled into the caller, not exported)."""
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"#define.*?(?<!\\)\n", "\n", text, flags=re.S)
+        for m in re.finditer(r"^\s*([A-Za-z_][\w\s\*]*?)\b(ds_\w+)\s*\(", text, flags=re.M):
+            if "static" not in m.group(1):
+                names.add(m.group(2))
+    return sorted(names)
 
 
 def _lib():
