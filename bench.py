@@ -204,6 +204,7 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = compare_methods(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
+        extras["uses"] = bench_uses(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
     direct_f64_2p20 = next((r["gq_s"] for r in case_rows if r["N"] == 1 << 20 and r["dtype"] == "f64"), None)
     for c in cases:  # free the sweep's buffers first
         c["idx"].destroy()
@@ -286,6 +287,65 @@ def compare_methods(ds, cases, M, stream, reps):
             idx.destroy()
         del out
     return res
+
+
+def bench_uses(ds, cases, M, stream, reps):
+    """The uses of Sec. 2 on the sweep's arrays and queries: the fused histogram and
+    interpolation kernels against the same results built from ds_search plus torch ops
+    (not in the timed step)."""
+    import torch
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    rows = []
+    with torch.cuda.stream(stream):
+        for c in cases:
+            n, z, idx = c["n"], c["z"], c["idx"]
+            S = np.dtype(c["dt"]).itemsize
+            counts = torch.zeros(n + 2, dtype=torch.int64, device=z.device)
+            out = torch.empty_like(c["out"])
+            X = c["x"]
+            Y = torch.cumsum(torch.ones(n + 1, dtype=X.dtype, device=X.device), 0)
+            y = torch.empty_like(z)
+
+            def hist_fused():
+                counts.zero_()
+                idx.histogram(z, counts, stream=stream)
+
+            def hist_unfused():
+                ds.search(idx, z, out=out, stream=stream)
+                return torch.bincount(out.long() + 1, minlength=n + 2)
+
+            def interp_fused():
+                idx.interp_linear(Y, z, out=y, stream=stream)
+
+            def interp_unfused():
+                ds.search(idx, z, out=out, stream=stream)
+                i = out.long().clamp(0, n - 1)
+                x0, x1, y0, y1 = X[i], X[i + 1], Y[i], Y[i + 1]
+                r = y0 + ((z - x0) / (x1 - x0)) * (y1 - y0)
+                r = torch.where(out < 0, Y[0], torch.where(out >= n, Y[n], r))
+                return r
+
+            ms = {k: timed(f) for k, f in (("hist_fused", hist_fused), ("hist_unfused", hist_unfused),
+                                           ("interp_fused", interp_fused), ("interp_unfused", interp_unfused))}
+            hist_fused()
+            same_hist = bool(torch.equal(counts, hist_unfused()))
+            interp_fused()
+            rel = float(((y - interp_unfused()).abs().max() / Y.abs().max()).item())
+            rows.append(dict(N=n, dtype="f32" if S == 4 else "f64", layout=STAGE_NAMES[idx.info()["staged"]],
+                             **{f"{k}_gq_s": round(M / v / 1e6, 2) for k, v in ms.items()},
+                             hist_same_as_unfused=same_hist, interp_max_rel_diff_vs_unfused=rel))
+            del counts, out, Y, y
+    return rows
 
 
 def bench_learned(ds, W, dev, stream, reps, direct_ref):
