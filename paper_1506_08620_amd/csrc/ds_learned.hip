@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <random>
 #include <type_traits>
 #include <vector>
@@ -655,8 +656,50 @@ __device__ __forceinline__ int32_t finish_window(T z, int32_t L0, int32_t U, int
   return (z >= a.X0) ? i : -1;
 }
 
+// Values of X after X_N that the search may read (+inf): the block scan below
+// reads up to two 64-byte blocks from the block of a window's first index.
+constexpr int64_t kLearnScanPad = 32;
+
+template <typename T>
+using vec16b = T __attribute__((ext_vector_type(16 / sizeof(T))));
+
+// The end of the search of a window [L, L + n - 1], n <= E = 64 / sizeof(T)
+// values: instead of log2(n) more dependent probes, read the 64-byte block of
+// L (and the next one when the window, or the value after it, reaches it)
+// with independent 16-byte loads and count the values <= z.  With c such
+// values from the block start b0, X_{b0+c-1} <= z < X_{b0+c} has been read
+// whenever 1 <= c <= (values read) - 1: the index is then certain, whatever
+// the model predicted.  *certified tells whether that holds.
+template <typename T>
+__device__ __forceinline__ int32_t scan_window(T z, int32_t L, int32_t n, const T* __restrict__ X, bool* certified) {
+  constexpr int E = 64 / int(sizeof(T));
+  constexpr int V = 16 / int(sizeof(T));
+  const int32_t b0 = L & ~(E - 1);
+  const bool two = L + n >= b0 + E;
+  int32_t c = 0;
+  const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(X + b0);
+#pragma unroll
+  for (int v = 0; v < E / V; ++v) {
+    const vec16b<T> x = p[v];
+#pragma unroll
+    for (int e = 0; e < V; ++e) c += (x[e] <= z) ? 1 : 0;
+  }
+  if (two) {
+#pragma unroll
+    for (int v = E / V; v < 2 * E / V; ++v) {
+      const vec16b<T> x = p[v];
+#pragma unroll
+      for (int e = 0; e < V; ++e) c += (x[e] <= z) ? 1 : 0;
+    }
+  }
+  *certified = c >= 1 && c <= (two ? 2 * E : E) - 1;
+  return b0 + c - 1;
+}
+
 // One 64-query group per wave and iteration; the next group's queries are
-// loaded before this group is worked on.
+// loaded before this group is worked on.  A query bisects its window down to
+// one 64-byte block, then scans it (scan_window); a result the scan cannot
+// certify (never expected) takes a full binary search and is counted.
 template <typename T, bool F16>
 __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -668,6 +711,7 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
     load_router16(a.params, R);
   else
     load_router(a.params, R);
+  constexpr int32_t E = 64 / int32_t(sizeof(T));
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -681,13 +725,34 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
     const float y = a.identity ? u : route_pair<F16>(u, &R);
     int32_t L, U;
     query_window<T>(z, y, a, segs, &L, &U);
-    const int32_t L0 = L;
     int32_t n = U - L + 1;
-    while (n > 1) search_round<T>(z, a.X, L, n);
-    const int32_t i = finish_window<T>(z, L0, U, L, a);
+    while (n > E) search_round<T>(z, a.X, L, n);
+    bool certified;
+    int32_t i = scan_window<T>(z, L, n, a.X, &certified);
+    const bool inside = (z >= a.X0) && (z < a.XN);
+    if (inside && !certified) {
+      atomicAdd(a.fallbacks, 1ull);
+      int32_t lo = 0, nn = a.N;
+      while (nn > 1) {
+        const int32_t h = nn >> 1;
+        const bool c = z >= a.X[lo + h];
+        lo = c ? lo + h : lo;
+        nn = c ? nn - h : h;
+      }
+      i = lo;
+    }
+    i = (z >= a.XN) ? a.N : i;
+    i = (z >= a.X0) ? i : -1;
     if (base + lane < a.M) __builtin_nontemporal_store(i, a.out + base + lane);
     z = z_next;
   }
+}
+
+// Xp[from .. to - 1] = +inf
+template <typename T>
+__global__ void fill_inf_kernel(T* __restrict__ Xp, int64_t from, int64_t to) {
+  const int64_t k = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < to) Xp[k] = std::numeric_limits<T>::infinity();
 }
 
 template <typename T>
@@ -697,6 +762,23 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   h->learned = L;
   const int64_t N = h->N;
   const int64_t n = N + 1;
+  {
+    // the handle's copy of X gets kLearnScanPad values of +inf after X_N for the search's block scan
+    T* Xp = nullptr;
+    if (hipMalloc(&Xp, size_t(n + kLearnScanPad) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
+    if (hipMemcpyAsync(Xp, h->X, size_t(n) * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      (void)hipFree(Xp);
+      return DS_ERR_HIP;
+    }
+    fill_inf_kernel<T><<<dim3(1), dim3(64), 0, s>>>(Xp, n, n + kLearnScanPad);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipFree(Xp);
+      return DS_ERR_HIP;
+    }
+    (void)hipFree(h->X);
+    h->X = Xp;
+    h->nX = n + kLearnScanPad;
+  }
   const T* X = static_cast<const T*>(h->X);
   T ends[2];
   DS_HIP_CHECK(hipMemcpyAsync(&ends[0], X, sizeof(T), hipMemcpyDeviceToHost, s));
