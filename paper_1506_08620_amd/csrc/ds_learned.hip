@@ -283,10 +283,22 @@ __device__ __forceinline__ uint32_t mix32(uint64_t x) {
   return static_cast<uint32_t>(x);
 }
 
-// One training step, forward and backward, one sample per thread.  Sample j
-// of step `step` is key idx = mix(seed, step, j) mod n_keys (or, when idx_in
+// One training step, forward and backward, on the matrix cores.  Sample q of
+// the workgroup (q = 64 w + 32 p + n: wave w, pass p, lane n % 32) is key
+// idx = mix(seed, step, j) mod n_keys, j = 256 blockIdx.x + q (or, when idx_in
 // is given, idx_in[j] with its own target t_in[j] and feature u_in[j]).
-// Each workgroup writes its summed gradient to partial[blockIdx.x * kParams].
+// Lanes n and n + 32 carry the same sample and each holds half of its units:
+// unit out_row(r, h) in register r for lane half h, r = 0..15, which is where
+// v_mfma_f32_32x32x2f32 leaves row out_row(r, h) of its output.  The three
+// 32 x 32 contractions are:
+//   forward   a2 = W2 h1 + b2        (K = units; block r takes units out_row(r, 0/1),
+//                                    so h1 in the same registers is the B operand)
+//   backward  dh1 = W2^T da2          (the same K order, so da2 is the B operand as is)
+//   gradient  dW2 = da2^T h1          (K = the wave's 64 samples, after a transpose
+//                                    through LDS)
+// and the small gradients (W1, b1, b2, W3, b3) are sums over the LDS tiles.
+// The four waves' gradients are added in a fixed order and written to
+// partial[blockIdx.x * kParams]: deterministic.
 __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
     const float* __restrict__ params, const float* __restrict__ feat, int64_t n_keys, uint64_t seed, int64_t step,
     int32_t batch, const float* __restrict__ u_in, const float* __restrict__ t_in, float* __restrict__ partial,
@@ -302,102 +314,152 @@ __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
     partial += (int64_t)slot * gridDim.x * kParams;
     loss_partial += (int64_t)slot * gridDim.x;
   }
+  constexpr int kWaves = kTrainBlock / 64;
+  constexpr int kLd = kHid + 1;
   __shared__ float sp[kParams];
-  __shared__ float s_da2[kTrainBlock][kHid + 1];
-  __shared__ float s_h1[kTrainBlock][kHid + 1];
-  __shared__ float s_small[kTrainBlock][4];
-  const int tid = threadIdx.x;
+  __shared__ float tileA[kWaves][64][kLd];  // da2, then h2
+  __shared__ float tileB[kWaves][64][kLd];  // h1, then da1
+  __shared__ float svec[kWaves][64][3];     // dy, u, loss per sample
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, n = lane & 31, h = lane >> 5;
   for (int k = tid; k < kParams; k += kTrainBlock) sp[k] = params[k];
   __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * kTrainBlock + tid;
-  const bool valid = j < batch;
-  float u = 0.0f, t = 0.0f;
-  if (valid) {
-    if (u_in) {
-      u = u_in[j];
-      t = t_in[j];
-    } else {
-      const uint64_t key = seed * 0x9E3779B97F4A7C15ull + static_cast<uint64_t>(step) * 0x100000001B3ull +
-                           static_cast<uint64_t>(j);
-      const int64_t idx = static_cast<int64_t>(mix32(key) % static_cast<uint32_t>(n_keys));
-      u = feat[idx];
-      t = static_cast<float>(static_cast<double>(idx) / static_cast<double>(n_keys - 1));
-    }
-  }
-  // clamp(a) lies strictly inside (0, 1) exactly when a does, so the unit
-  // outputs alone give the derivative masks
-  float h1[kHid], h2[kHid];
+  float w2f[16], w2b[16];
 #pragma unroll
-  for (int k = 0; k < kHid; ++k) h1[k] = clamp01(std::fma(sp[oW1 + k], u, sp[oB1 + k]));
-  float y = sp[oB3];
-  for (int jj = 0; jj < kHid; ++jj) {
-    float acc = sp[oB2 + jj];
-#pragma unroll
-    for (int k = 0; k < kHid; ++k) acc = std::fma(sp[oW2 + jj * kHid + k], h1[k], acc);
-    h2[jj] = clamp01(acc);
-    y = std::fma(sp[oW3 + jj], h2[jj], y);
+  for (int r = 0; r < 16; ++r) {
+    const int u = out_row(r, h);
+    w2f[r] = sp[oW2 + n * kHid + u];  // A of the forward: W2[n][u]
+    w2b[r] = sp[oW2 + u * kHid + n];  // A of the backward: W2[u][n]
   }
+  float (*TA)[kLd] = tileA[w];
+  float (*TB)[kLd] = tileB[w];
   const float inv_b = 1.0f / static_cast<float>(batch);
-  const float dy = valid ? 2.0f * (y - t) * inv_b : 0.0f;
-  const float l = valid ? (y - t) * (y - t) * inv_b : 0.0f;
-  // backward
-  float dh1[kHid];
+  float st_h2[2][16], st_da1[2][16];
 #pragma unroll
-  for (int k = 0; k < kHid; ++k) dh1[k] = 0.0f;
-  for (int jj = 0; jj < kHid; ++jj) {
-    const float da2 = (h2[jj] > 0.0f && h2[jj] < 1.0f) ? dy * sp[oW3 + jj] : 0.0f;
-    s_da2[tid][jj] = da2;
+  for (int p = 0; p < 2; ++p) {
+    const int q = p * 32 + n;
+    const int64_t j = (int64_t)blockIdx.x * kTrainBlock + w * 64 + q;
+    const bool valid = j < batch;
+    float u = 0.0f, t = 0.0f;
+    if (valid) {
+      if (u_in) {
+        u = u_in[j];
+        t = t_in[j];
+      } else {
+        const uint64_t key = seed * 0x9E3779B97F4A7C15ull + static_cast<uint64_t>(step) * 0x100000001B3ull +
+                             static_cast<uint64_t>(j);
+        const int64_t idx = static_cast<int64_t>(mix32(key) % static_cast<uint32_t>(n_keys));
+        u = feat[idx];
+        t = static_cast<float>(static_cast<double>(idx) / static_cast<double>(n_keys - 1));
+      }
+    }
+    float h1[16];
+    floatx16 acc;
 #pragma unroll
-    for (int k = 0; k < kHid; ++k) dh1[k] = std::fma(da2, sp[oW2 + jj * kHid + k], dh1[k]);
+    for (int r = 0; r < 16; ++r) {
+      const int un = out_row(r, h);
+      h1[r] = clamp01(std::fma(sp[oW1 + un], u, sp[oB1 + un]));
+      acc[r] = sp[oB2 + un];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w2f[r], h1[r], acc, 0, 0, 0);
+    float part = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) part = std::fma(sp[oW3 + out_row(r, h)], clamp01(acc[r]), part);
+    const float y = (part + __shfl_xor(part, 32, 64)) + sp[oB3];  // the same sum in both lanes
+    const float dy = valid ? 2.0f * (y - t) * inv_b : 0.0f;
+    const float l = valid ? (y - t) * (y - t) * inv_b : 0.0f;
+    float da2[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int un = out_row(r, h);
+      const float h2 = clamp01(acc[r]);
+      st_h2[p][r] = h2;
+      // clamp(a) lies strictly inside (0, 1) exactly when a does, so the unit outputs give the masks
+      da2[r] = (h2 > 0.0f && h2 < 1.0f) ? dy * sp[oW3 + un] : 0.0f;
+      TA[q][un] = da2[r];
+      TB[q][un] = h1[r];
+    }
+    floatx16 d1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d1[r] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(w2b[r], da2[r], d1, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) st_da1[p][r] = (h1[r] > 0.0f && h1[r] < 1.0f) ? d1[r] : 0.0f;
+    if (h == 0) {
+      svec[w][q][0] = dy;
+      svec[w][q][1] = u;
+      svec[w][q][2] = l;
+    }
   }
+  __syncthreads();
+  // dW2[j][k] = sum_s da2[s][j] h1[s][k]: K = the wave's 64 samples, two per instruction
+  // (lane half h supplies sample 2i + h); db2 from the same reads
+  floatx16 g2;
 #pragma unroll
-  for (int k = 0; k < kHid; ++k) s_h1[tid][k] = h1[k];
+  for (int r = 0; r < 16; ++r) g2[r] = 0.0f;
+  float gb2 = 0.0f;
+#pragma unroll 8
+  for (int i = 0; i < 32; ++i) {
+    const float a = TA[2 * i + h][n];
+    gb2 += a;
+    g2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, TB[2 * i + h][n], g2, 0, 0, 0);
+  }
+  __syncthreads();
+  // phase 2: the tiles now hold h2 and da1
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      TA[p * 32 + n][out_row(r, h)] = st_h2[p][r];
+      TB[p * 32 + n][out_row(r, h)] = st_da1[p][r];
+    }
+  }
+  __syncthreads();
+  // lane (n, h): unit n over the samples s = 2i + h
+  float gw1 = 0.0f, gb1 = 0.0f, gw3 = 0.0f, gb3 = 0.0f, ls = 0.0f;
+  for (int i = 0; i < 32; ++i) {
+    const int s2 = 2 * i + h;
+    const float da1 = TB[s2][n], dy = svec[w][s2][0];
+    gw1 = std::fma(da1, svec[w][s2][1], gw1);
+    gb1 += da1;
+    gw3 = std::fma(dy, TA[s2][n], gw3);
+    gb3 += dy;
+    ls += svec[w][s2][2];
+  }
+  gw1 += __shfl_xor(gw1, 32, 64);
+  gb1 += __shfl_xor(gb1, 32, 64);
+  gw3 += __shfl_xor(gw3, 32, 64);
+  gb2 += __shfl_xor(gb2, 32, 64);
+  gb3 += __shfl_xor(gb3, 32, 64);
+  ls += __shfl_xor(ls, 32, 64);
+  __syncthreads();
+  // the four waves' gradients, added in wave order (tileA is free again)
+  float* red = &tileA[0][0][0];  // kWaves x (kParams + 1) floats
+  static_assert(kWaves * (kParams + 1) <= kWaves * 64 * kLd, "reduction fits the tile");
+  float* mine = red + w * (kParams + 1);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) mine[oW2 + out_row(r, h) * kHid + n] = g2[r];
+  if (h == 0) {
+    mine[oW1 + n] = gw1;
+    mine[oB1 + n] = gb1;
+    mine[oB2 + n] = gb2;
+    mine[oW3 + n] = gw3;
+    if (n == 0) {
+      mine[oB3] = gb3;
+      mine[kParams] = ls;
+    }
+  }
+  __syncthreads();
   float* out = partial + (int64_t)blockIdx.x * kParams;
-  __syncthreads();
-  // phase 1 (LDS holds da2 and h1 of every sample):
-  // dW2[jj][k] = sum_s da2[s][jj] h1[s][k] (1024 outputs, 4 per thread), db2
-  for (int o = tid; o < kHid * kHid; o += kTrainBlock) {
-    const int jj = o / kHid, k = o % kHid;
-    float g = 0.0f;
-    for (int s = 0; s < kTrainBlock; ++s) g = std::fma(s_da2[s][jj], s_h1[s][k], g);
-    out[oW2 + o] = g;
-  }
-  if (tid < kHid) {
-    float gb2 = 0.0f;
-    for (int s = 0; s < kTrainBlock; ++s) gb2 += s_da2[s][tid];
-    out[oB2 + tid] = gb2;
-  }
-  __syncthreads();
-  // phase 2 (the same LDS now holds da1 and h2): dW1, db1, dW3, db3 and the loss
+  for (int k = tid; k <= kParams; k += kTrainBlock) {
+    float v = red[k];
 #pragma unroll
-  for (int k = 0; k < kHid; ++k) s_da2[tid][k] = (h1[k] > 0.0f && h1[k] < 1.0f) ? dh1[k] : 0.0f;  // da1
-#pragma unroll
-  for (int k = 0; k < kHid; ++k) s_h1[tid][k] = h2[k];
-  s_small[tid][0] = dy;
-  s_small[tid][1] = u;
-  s_small[tid][2] = l;
-  __syncthreads();
-  if (tid < kHid) {
-    float gw1 = 0.0f, gb1 = 0.0f;
-    for (int s = 0; s < kTrainBlock; ++s) {
-      gw1 = std::fma(s_da2[s][tid], s_small[s][1], gw1);
-      gb1 += s_da2[s][tid];
-    }
-    out[oW1 + tid] = gw1;
-    out[oB1 + tid] = gb1;
-  } else if (tid < 2 * kHid) {
-    const int jj = tid - kHid;
-    float gw3 = 0.0f;
-    for (int s = 0; s < kTrainBlock; ++s) gw3 = std::fma(s_small[s][0], s_h1[s][jj], gw3);
-    out[oW3 + jj] = gw3;
-  } else if (tid == 2 * kHid) {
-    float gb3 = 0.0f, ls = 0.0f;
-    for (int s = 0; s < kTrainBlock; ++s) {
-      gb3 += s_small[s][0];
-      ls += s_small[s][2];
-    }
-    out[oB3] = gb3;
-    loss_partial[blockIdx.x] = ls;
+    for (int ww = 1; ww < kWaves; ++ww) v += red[ww * (kParams + 1) + k];
+    if (k < kParams)
+      out[k] = v;
+    else
+      loss_partial[blockIdx.x] = v;
   }
 }
 
