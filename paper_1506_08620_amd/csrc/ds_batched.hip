@@ -639,7 +639,7 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.tot = reinterpret_cast<PlanTotals*>(ws + L.totals);
   b.K = d->num_arrays;
   b.nseg = L.nseg;
-  b.steps = d->learn_steps > 0 ? d->learn_steps : 100;
+  b.steps = d->learn_steps > 0 ? d->learn_steps : 50;
   b.fp32_router = 0;
   b.seed = 0x1506ull;
   b.tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
