@@ -314,3 +314,41 @@ def test_graph_replay_matches_eager(ds):
         torch.cuda.synchronize()
         assert torch.equal(out, eager), r
         ds.search(idx, z_d[: 1000])  # eager work between replays
+
+
+def test_maximum_sizes_int64_query_offsets_and_large_n(ds):
+    """M = 2^31 + 4099 queries (offsets past int32 in the streaming loops, a ragged tail) on
+    an LDS-resident table, and N = 2^25 f64 (its NIBBLE table, 22 MB, spills past L2):
+    sampled against the oracle, including the last queries, plus the invariant on chunks."""
+    X = W.sweep_array(4096, np.float32)
+    xd = _dev(X)
+    M = (1 << 31) + 4099
+    g = torch.Generator(device=DEV)
+    g.manual_seed(77)
+    z = torch.rand(M, generator=g, device=DEV, dtype=torch.float32)
+    idx = ds.build(xd)
+    out = ds.search(idx, z)
+    pos = np.concatenate([np.random.default_rng(1).integers(0, M, 1 << 16), np.arange(M - 4200, M)])
+    pt = torch.from_numpy(pos).to(DEV)
+    zs = z[pt].cpu().numpy()
+    _assert_same(out[pt].cpu().numpy(), oracle.search(X, zs), zs)
+    for c0 in range(0, M, 1 << 28):  # invariant on every query, chunk by chunk
+        o = out[c0:c0 + (1 << 28)].long()
+        zz = z[c0:c0 + (1 << 28)]
+        assert int(o.min()) >= 0 and int(o.max()) <= X.size - 2
+        assert bool(torch.all(xd[o] <= zz)) and bool(torch.all(zz < xd[o + 1]))
+    del z, out, o, zz
+    torch.cuda.empty_cache()
+    n = 1 << 25
+    Xb = W.sweep_array(n, np.float64)
+    xb = _dev(Xb)
+    idx = ds.build(xb)
+    inf = idx.info()
+    assert inf["staged"] == 6 and inf["nibble_bytes"] > (16 << 20)
+    zb = W.sweep_queries_torch(1 << 26, np.float64, DEV)
+    ob = ds.search(idx, zb)
+    o = ob.long()
+    assert bool(torch.all(xb[o] <= zb)) and bool(torch.all(zb < xb[o + 1]))
+    pos = torch.from_numpy(np.random.default_rng(2).integers(0, 1 << 26, 1 << 16)).to(DEV)
+    zs = zb[pos].cpu().numpy()
+    _assert_same(ob[pos].cpu().numpy(), oracle.search(Xb, zs), zs)
