@@ -35,7 +35,7 @@ namespace ds {
 
 namespace {
 
-constexpr int kBuildBlock = 256;
+constexpr int kBuildBlock = 1024;
 constexpr int kPlanBlock = 1024;
 constexpr int kMaxGrowthRounds = 4096;
 
@@ -100,10 +100,20 @@ __device__ __forceinline__ T next_up_dev(T x) {
 
 // --------------------------------------------------------------------------
 // 1. per-array ComputeHR
+// R - jmin + 1 cells at this H exceed cap_cells (0 = no cap)
+template <typename T, int FORM>
+__device__ __forceinline__ bool over_cap(T H, T W, T X0, T XN, int64_t cap_cells) {
+  if (cap_cells <= 0) return false;
+  const int64_t cells = static_cast<int64_t>(grid_floor<T, FORM>(XN, H, W, X0)) -
+                        static_cast<int64_t>(grid_floor<T, FORM>(X0, H, W, X0)) + 1;
+  return cells > cap_cells;
+}
+
 template <typename T, int FORM>
 __global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __restrict__ x_off,
                                                                const int64_t* __restrict__ q_off,
-                                                               const T* __restrict__ Xp, ArrMeta<T>* __restrict__ meta) {
+                                                               const T* __restrict__ Xp, int64_t cap_cells,
+                                                               ArrMeta<T>* __restrict__ meta) {
   const int k = blockIdx.x;
   const int tid = threadIdx.x;
   __shared__ T s_min[kBuildBlock];
@@ -171,6 +181,8 @@ __global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __
     H = next_up_dev(Hbar);
     W = (FORM == DS_FORM_FMA) ? T(H * X0) : T(0);
     feasible = feasible && grid_floor<T, FORM>(XN, H, W, X0) < T(kTwoPowQ);
+    // a table already over the Direct cap only grows with H: not Direct, stop here
+    feasible = feasible && !over_cap<T, FORM>(H, W, X0, XN, cap_cells);
     P = next_up_dev(H) - H;
   }
   if (feasible) {
@@ -214,7 +226,7 @@ __global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __
         while (grid_floor<T, FORM>(a, h, ww, X0) == grid_floor<T, FORM>(b, h, ww, X0)) {
           h = h + P;
           if (FORM == DS_FORM_FMA) ww = h * X0;
-          if (!(grid_floor<T, FORM>(XN, h, ww, X0) < T(kTwoPowQ))) {
+          if (!(grid_floor<T, FORM>(XN, h, ww, X0) < T(kTwoPowQ)) || over_cap<T, FORM>(h, ww, X0, XN, cap_cells)) {
             st = 1;
             break;
           }
@@ -718,8 +730,9 @@ ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
   const int64_t wb = L.words_budget;
   const int64_t tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
   auto* meta = reinterpret_cast<ArrMeta<T>*>(ws + L.meta);
+  const int64_t cap_cells = d->direct_cap_bytes > 0 ? d->direct_cap_bytes / 4 : 0;
   build_hr_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(d->x_off_dev, d->q_off_dev,
-                                                                  static_cast<const T*>(d->X_dev), meta);
+                                                                  static_cast<const T*>(d->X_dev), cap_cells, meta);
   DS_HIP_CHECK(hipGetLastError());
   ds_status st = launch_plan<T>(d, L, ws, tile, s);
   if (st != DS_OK) return st;

@@ -565,7 +565,7 @@ __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, i
 template <typename T>
 __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, int64_t N,
                                                       const int32_t* __restrict__ first, SegFit* __restrict__ segs,
-                                                      const LearnMeta* __restrict__ lm,
+                                                      int32_t nseg, const LearnMeta* __restrict__ lm,
                                                       const PlanTotals* __restrict__ tot) {
   if (lm) {
     const int slot = blockIdx.y;
@@ -573,20 +573,20 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
     const LearnMeta L = lm[slot];
     X += L.x_off;
     N = L.N;
-    first += (int64_t)slot * (gridDim.x + 1);
-    segs += (int64_t)slot * gridDim.x;
+    first += (int64_t)slot * (nseg + 1);
+    segs += (int64_t)slot * nseg;
   }
-  const int s = blockIdx.x;
-  const int tid = threadIdx.x;
+  // one wave per segment, wave-level reductions in a fixed order
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= nseg) return;  // uniform across the wave
+  const int lane = threadIdx.x & 63;
   const int64_t a = first[s], b = first[s + 1];  // keys [a, b)
   const int64_t lo = std::max<int64_t>(0, std::min<int64_t>(a - 1, N - 1));
   const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(b - 1, N - 1));
-  __shared__ double sd[5][256];
-  __shared__ int32_t si[2][256];
   const int64_t c0 = (a < b) ? a : lo;
   const double zc = static_cast<double>(X[c0]);
   double n = 0, sz = 0, szz = 0, si_ = 0, siz = 0;
-  for (int64_t i = a + tid; i < b; i += 256) {
+  for (int64_t i = a + lane; i < b; i += 64) {
     const double dz = static_cast<double>(X[i]) - zc;
     const double di = static_cast<double>(i - lo);
     n += 1;
@@ -595,61 +595,46 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
     si_ += di;
     siz += di * dz;
   }
-  sd[0][tid] = n;
-  sd[1][tid] = sz;
-  sd[2][tid] = szz;
-  sd[3][tid] = si_;
-  sd[4][tid] = siz;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w)
-      for (int q = 0; q < 5; ++q) sd[q][tid] += sd[q][tid + w];
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    n += __shfl_xor(n, o, 64);
+    sz += __shfl_xor(sz, o, 64);
+    szz += __shfl_xor(szz, o, 64);
+    si_ += __shfl_xor(si_, o, 64);
+    siz += __shfl_xor(siz, o, 64);
   }
-  __shared__ SegFit s_fit;
-  if (tid == 0) {
-    const double cn = sd[0][0], cz = sd[1][0], czz = sd[2][0], ci = sd[3][0], ciz = sd[4][0];
-    double slope = 0, icpt = 0;
-    if (cn >= 2) {
-      const double var = czz - cz * cz / cn;
-      const double cov = ciz - ci * cz / cn;
-      slope = (var > 0) ? cov / var : 0.0;
-      if (!(slope > 0)) slope = 0;  // monotone prediction
-      icpt = (ci - slope * cz) / cn;
-    } else if (cn == 1) {
-      icpt = ci;
-    }
-    SegFit f{};
-    f.zc = zc;
-    f.a = static_cast<float>(slope);
-    f.b = static_cast<float>(icpt);
-    f.lo = static_cast<int32_t>(lo);
-    f.hi = static_cast<int32_t>(hi);
-    s_fit = f;
+  // every lane holds the same sums and computes the same fit
+  double slope = 0, icpt = 0;
+  if (n >= 2) {
+    const double var = szz - sz * sz / n;
+    const double cov = siz - si_ * sz / n;
+    slope = (var > 0) ? cov / var : 0.0;
+    if (!(slope > 0)) slope = 0;  // monotone prediction
+    icpt = (si_ - slope * sz) / n;
+  } else if (n == 1) {
+    icpt = si_;
   }
-  __syncthreads();
-  const SegFit f = s_fit;
+  SegFit f{};
+  f.zc = zc;
+  f.a = static_cast<float>(slope);
+  f.b = static_cast<float>(icpt);
+  f.lo = static_cast<int32_t>(lo);
+  f.hi = static_cast<int32_t>(hi);
   int32_t dmin = 1 << 30, dmax = -(1 << 30);
-  for (int64_t i = lo + tid; i <= hi + 1 && i <= N; i += 256) {
+  for (int64_t i = lo + lane; i <= hi + 1 && i <= N; i += 64) {
     const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, X[i]);
     dmin = std::min(dmin, d);
     dmax = std::max(dmax, d);
   }
-  si[0][tid] = dmin;
-  si[1][tid] = dmax;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) {
-      si[0][tid] = std::min(si[0][tid], si[0][tid + w]);
-      si[1][tid] = std::max(si[1][tid], si[1][tid + w]);
-    }
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dmin = std::min(dmin, __shfl_xor(dmin, o, 64));
+    dmax = std::max(dmax, __shfl_xor(dmax, o, 64));
   }
-  if (tid == 0) {
-    SegFit g = f;
-    g.dmin = si[0][0];
-    g.dmax = si[1][0];
-    segs[s] = g;
+  if (lane == 0) {
+    f.dmin = dmin;
+    f.dmax = dmax;
+    segs[s] = f;
   }
 }
 
@@ -938,7 +923,7 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
                                                                                    nullptr, nullptr);
   seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first,
                                                                                 nullptr, nullptr);
-  seg_fit_kernel<T><<<dim3(nseg), dim3(256), 0, s>>>(X, N, L->first, L->segs, nullptr, nullptr);
+  seg_fit_kernel<T><<<dim3((nseg + 3) / 4), dim3(256), 0, s>>>(X, N, L->first, L->segs, nseg, nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
   std::vector<SegFit> host(nseg);
   DS_HIP_CHECK(hipMemcpyAsync(host.data(), L->segs, size_t(nseg) * sizeof(SegFit), hipMemcpyDeviceToHost, s));
@@ -1181,8 +1166,9 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
     route_keys_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, 0, b.nseg, 0, b.route, nullptr,
                                                               b.lmeta, b.tot);
   seg_first_kernel<<<dim3(64, K), dim3(256), 0, s>>>(b.route, 0, b.nseg, b.first, b.lmeta, b.tot);
-  seg_fit_kernel<T><<<dim3(b.nseg, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, b.first,
-                                                            static_cast<SegFit*>(b.segs), b.lmeta, b.tot);
+  seg_fit_kernel<T><<<dim3((b.nseg + 3) / 4, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, b.first,
+                                                                      static_cast<SegFit*>(b.segs), b.nseg, b.lmeta,
+                                                                      b.tot);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }
