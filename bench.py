@@ -30,19 +30,28 @@ STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2", 
                6: "NIBBLE-L2"}
 
 
+# the files the sweep's kernels and their tables are built from: the counter summary
+# stays valid exactly while these are unchanged
+TRAFFIC_SOURCES = ("paper_1506_08620_amd/csrc/ds_search.hip", "paper_1506_08620_amd/csrc/ds_build.hip",
+                   "paper_1506_08620_amd/csrc/ds_ops.h", "paper_1506_08620_amd/csrc/ds_internal.h",
+                   "include/ds.h", "include/ds_device.h")
+
+
+def traffic_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(dtype: str, ns, stage_name: str):
     """HBM bytes per launch of the given sweep cases from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since the counters were taken."""
-    import glob
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "direct_sweep_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1506_08620_amd", "csrc", "*"))) + [
-            os.path.join(ROOT, "include", "ds.h")]:
-        h.update(open(p, "rb").read())
     vals, cases = {}, {}
     for line in open(path):
         if line.startswith("#") or not line.strip():
@@ -52,7 +61,7 @@ def measured_traffic(dtype: str, ns, stage_name: str):
             cases[(f[1], int(f[2]))] = (float(f[4]), float(f[6]))
         else:
             vals[f[0]] = f[1]
-    if vals.get("source_sha256") != h.hexdigest():
+    if vals.get("source_sha256") != traffic_sources_sha256():
         return None
     fs, ws = float(vals["fetch_scale"]), float(vals["write_scale"])
     got = [cases[(dtype, n)] for n in ns if (dtype, n) in cases]

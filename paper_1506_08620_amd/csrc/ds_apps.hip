@@ -2,8 +2,11 @@
 // the Direct search fused into the consuming kernel, and the scalar-problem
 // device API (ds_device.h):
 //   * ds_histogram      samples per interval: the index goes straight into
-//                       an LDS-private bin (or a global atomic), so queries
-//                       are read once and no index is written;
+//                       an LDS-private bin, so queries are read once and no
+//                       index is written (bins too many for LDS beside the
+//                       tables: up to four passes, each counting a range of
+//                       bins in all of LDS with the tables read through L2;
+//                       beyond that, one global atomic per sample);
 //   * ds_interp_linear  piecewise-linear interpolation: index, then the knots
 //                       X_i, X_{i+1}, Y_i, Y_{i+1}, then y, in one pass;
 //   * ds_get_view / ds_view_search  the tables as a plain view, searched by a
@@ -106,6 +109,29 @@ __global__ void __launch_bounds__(1024) hist_kernel(DirectArgs<T> a, int64_t bin
   }
 }
 
+// Histogram of the bins [b0, b0 + nbl) only, in LDS (all of it), with the
+// PLAIN tables read through L2: for arrays whose N + 2 bins fit neither
+// beside the staged tables nor in one LDS, a few such passes over the queries
+// (one launch each) beat one global atomic per sample.
+template <typename T, int FORM>
+__global__ void __launch_bounds__(1024) hist_range_kernel(DirectArgs<T> a, int64_t b0, int64_t nbl, bool vec,
+                                                          unsigned long long* __restrict__ counts) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  uint32_t* bins = reinterpret_cast<uint32_t*>(smem);
+  for (int64_t b = threadIdx.x; b < nbl; b += blockDim.x) bins[b] = 0;
+  __syncthreads();
+  const DirectOp<T, FORM> op{a.X, a.K - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
+  for_each_query<T>(a.z, a.M, vec, [&](int64_t, T z) {
+    const int64_t b = int64_t(op(z)) + 1 - b0;
+    if (b >= 0 && b < nbl) atomicAdd(&bins[b], 1u);
+  });
+  __syncthreads();
+  for (int64_t b = threadIdx.x; b < nbl; b += blockDim.x) {
+    const uint32_t c = bins[b];
+    if (c) atomicAdd(&counts[b0 + b], static_cast<unsigned long long>(c));
+  }
+}
+
 // Piecewise-linear interpolation in T, no contraction (the library is built
 // with -ffp-contract=off): the operation order is the one ds.h documents.
 template <typename T, int FORM, int STAGE>
@@ -201,12 +227,28 @@ ds_status launch_hist(const DirectArgs<T>& a, int64_t table_lds, int64_t bins_by
   return DS_OK;
 }
 
+constexpr int kHistMaxPasses = 4;
+
 template <typename T, int FORM, int STAGE>
 ds_status hist_stage(const ds_index* h, const DirectArgs<T>& a, bool vec, uint64_t* counts, hipStream_t s) {
   const int64_t table_lds = (STAGE == 6) ? 0 : round16(direct_lds_bytes(h, STAGE));
-  const int64_t bins_bytes = round16((h->N + 2) * 4);
+  const int64_t nb = h->N + 2;
+  const int64_t bins_bytes = round16(nb * 4);
   if (table_lds + bins_bytes <= kLdsBytesPerCU) return launch_hist<T, FORM, STAGE, true>(a, table_lds, bins_bytes, vec, counts, s);
-  return launch_hist<T, FORM, STAGE, false>(a, table_lds, 0, vec, counts, s);
+  const int64_t per_pass = kLdsBytesPerCU / 4;
+  const int64_t passes = (nb + per_pass - 1) / per_pass;
+  if (passes > kHistMaxPasses) return launch_hist<T, FORM, STAGE, false>(a, table_lds, 0, vec, counts, s);
+  auto k = hist_range_kernel<T, FORM>;
+  const int lds = static_cast<int>(std::min<int64_t>(nb, per_pass) * 4);
+  const int grid = persistent_grid(k, kAppBlock, lds, vec ? (a.M >> 2) : a.M);
+  if (grid < 0) return DS_ERR_HIP;
+  for (int64_t b0 = 0; b0 < nb; b0 += per_pass) {
+    const int64_t nbl = std::min<int64_t>(per_pass, nb - b0);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kAppBlock), lds, s, a, b0, nbl, vec,
+                       reinterpret_cast<unsigned long long*>(counts));
+    DS_HIP_CHECK(hipGetLastError());
+  }
+  return DS_OK;
 }
 
 template <typename T, int FORM, int STAGE>
