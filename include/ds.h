@@ -113,6 +113,14 @@ typedef struct ds_build_opts {
   int32_t gap_q;            /* DS_METHOD_DIRECT_GAP: q in 1..16 (q <= N), or 0 = the smallest q
                                whose grid is feasible and whose table fits table_cap_bytes
                                (the memory-budget choice of Sec. 4.7) */
+  int32_t refine_h;         /* Direct and direct_gap: 1 = when ComputeHR had to grow H, bisect
+                               between the last H that failed and the grown one (the
+                               refinement proposed at the end of Sec. 4.4.3): midpoint
+                               lo + (hi - lo) / 2 rounded in the dtype, each midpoint checked
+                               against the whole array, until the two ends are neighbouring
+                               floats.  Gives a feasible H whose predecessor float fails (not
+                               necessarily the smallest feasible H: feasibility is not
+                               monotone in H), hence a table no larger.  0 = keep the grown H */
 } ds_build_opts;
 
 /* learned: the router is trained and stored in FP32.  By default the search
@@ -169,7 +177,7 @@ typedef struct ds_info_t {
   double build_ms;          /* wall time of ds_build */
   int64_t nibble_bytes;     /* bytes of the NIBBLE layout (0 if not built) */
   int32_t gap_q;            /* DS_METHOD_DIRECT_GAP: the q in use; 0 otherwise */
-  int32_t pad_;
+  int32_t n_h_refine;       /* midpoints tested by the refinement of H (refine_h) */
 } ds_info_t;
 
 typedef struct ds_index* ds_handle;

@@ -54,7 +54,7 @@ def _load():
             f.argtypes, f.restype = [vp, i64, vp, i64, vp], None
             f = getattr(lib, f"oracle_compute_hr_{s}")
             f.argtypes = [vp, i64, i32, i32, ctypes.POINTER(ct), ctypes.POINTER(ct),
-                          ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+                          ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ct)]
             f.restype = i32
             f = getattr(lib, f"oracle_init_k_{s}")
             f.argtypes, f.restype = [vp, i64, i32, ct, ct, i64, i64, vp], i32
@@ -66,7 +66,11 @@ def _load():
             f.argtypes, f.restype = [vp, i64, i64, vp, i64, vp], None
             f = getattr(lib, f"oracle_compute_hr_gap_{s}")
             f.argtypes = [vp, i64, i64, i32, i32, ctypes.POINTER(ct), ctypes.POINTER(ct),
-                          ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+                          ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ct)]
+            f.restype = i32
+            f = getattr(lib, f"oracle_refine_h_{s}")
+            f.argtypes = [vp, i64, i64, i32, ct, ct, ctypes.POINTER(ct), ctypes.POINTER(ct),
+                          ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ct), ctypes.POINTER(i64)]
             f.restype = i32
             f = getattr(lib, f"oracle_init_k_gap_{s}")
             f.argtypes, f.restype = [vp, i64, i32, ct, ct, i64, i64, vp], i32
@@ -121,21 +125,54 @@ class DirectTables:
     form: int = FORM_SUB
     dtype: np.dtype = np.dtype(np.float32)
     q: int = 0                    # gap-q tables (Sec. 4.7); 0 for plain Direct
+    H_bad: float = 0.0            # last H the growth loop found infeasible (0 = none)
+    H_grown: float = float("nan")  # the H the growth loop ended with
+    H_lo: float = 0.0             # refined: the infeasible float just below H
+    n_refine: int = 0             # refined: midpoints tested by the bisection
 
 
-def compute_hr(X: np.ndarray, form: int = FORM_SUB, hstart: int = HSTART_PHI) -> DirectTables:
-    """ComputeHR (Sec. 4.4.3) in the chosen form; returns status, H, W, R, jmin, n_updates."""
+def refine_h(X: np.ndarray, q: int, form: int, Hlo: float, Hhi: float):
+    """Bisection of [Hlo (infeasible), Hhi (feasible)] (end of Sec. 4.4.3); q = 1 for plain
+    Direct.  Returns (status, H, W, R, jmin, final Hlo, steps)."""
     X = np.ascontiguousarray(X)
     s = _suffix(X.dtype)
     ct = ctypes.c_float if s == "f32" else ctypes.c_double
-    H, W = ct(), ct()
+    H, W, lo = ct(), ct(), ct()
+    R, jmin, steps = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    st = getattr(_load(), f"oracle_refine_h_{s}")(_ptr(X), X.size - 1, q, form, Hlo, Hhi, ctypes.byref(H),
+                                                    ctypes.byref(W), ctypes.byref(R), ctypes.byref(jmin),
+                                                    ctypes.byref(lo), ctypes.byref(steps))
+    return st, H.value, W.value, R.value, jmin.value, lo.value, steps.value
+
+
+def _refined(X: np.ndarray, t: DirectTables, q: int) -> DirectTables:
+    """t with H replaced by the bisection's result when the growth loop raised H."""
+    if t.status != OK or t.n_updates == 0:
+        return t
+    st, H, W, R, jmin, lo, steps = refine_h(X, q, t.form, t.H_bad, t.H_grown)
+    if st != OK:
+        raise RuntimeError(f"refine_h rejected its interval: status {st}")
+    t.H, t.W, t.R, t.jmin, t.H_lo, t.n_refine = H, W, R, jmin, lo, steps
+    return t
+
+
+def compute_hr(X: np.ndarray, form: int = FORM_SUB, hstart: int = HSTART_PHI,
+               refine: bool = False) -> DirectTables:
+    """ComputeHR (Sec. 4.4.3) in the chosen form; returns status, H, W, R, jmin, n_updates.
+    refine: bisect between the last infeasible H and the grown one (end of Sec. 4.4.3)."""
+    X = np.ascontiguousarray(X)
+    s = _suffix(X.dtype)
+    ct = ctypes.c_float if s == "f32" else ctypes.c_double
+    H, W, Hb = ct(), ct(), ct()
     R, jmin, nu = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     st = getattr(_load(), f"oracle_compute_hr_{s}")(_ptr(X), X.size - 1, form, hstart, ctypes.byref(H),
                                                       ctypes.byref(W), ctypes.byref(R), ctypes.byref(jmin),
-                                                      ctypes.byref(nu))
+                                                      ctypes.byref(nu), ctypes.byref(Hb))
     if st != OK:
         return DirectTables(st, form=form, dtype=X.dtype)
-    return DirectTables(OK, H.value, W.value, R.value, jmin.value, nu.value, None, form, X.dtype)
+    t = DirectTables(OK, H.value, W.value, R.value, jmin.value, nu.value, None, form, X.dtype,
+                     H_bad=Hb.value, H_grown=H.value)
+    return _refined(X, t, 1) if refine else t
 
 
 def init_k(X: np.ndarray, H: float, W: float, R: int, jmin: int, form: int = FORM_SUB):
@@ -147,8 +184,9 @@ def init_k(X: np.ndarray, H: float, W: float, R: int, jmin: int, form: int = FOR
     return st, K
 
 
-def build_direct(X: np.ndarray, form: int = FORM_SUB, hstart: int = HSTART_PHI) -> DirectTables:
-    t = compute_hr(X, form, hstart)
+def build_direct(X: np.ndarray, form: int = FORM_SUB, hstart: int = HSTART_PHI,
+                 refine: bool = False) -> DirectTables:
+    t = compute_hr(X, form, hstart, refine)
     if t.status != OK:
         return t
     st, K = init_k(X, t.H, t.W, t.R, t.jmin, form)
@@ -171,19 +209,22 @@ def direct(X: np.ndarray, t: DirectTables, z: np.ndarray) -> np.ndarray:
 # The gap-q variant (Sec. 4.7): f(X_{i+q}) > f(X_i), K_j = max{i : f(X_i) <= j},
 # i = K_j - sum_{k<q} [z < X_{K_j - k}].
 
-def compute_hr_gap(X: np.ndarray, q: int, form: int = FORM_SUB, hstart: int = HSTART_PHI) -> DirectTables:
+def compute_hr_gap(X: np.ndarray, q: int, form: int = FORM_SUB, hstart: int = HSTART_PHI,
+                   refine: bool = False) -> DirectTables:
     """ComputeHR under eq. (f-monotonic-n); status, H, W, R, jmin, n_updates (1 <= q <= N)."""
     X = np.ascontiguousarray(X)
     s = _suffix(X.dtype)
     ct = ctypes.c_float if s == "f32" else ctypes.c_double
-    H, W = ct(), ct()
+    H, W, Hb = ct(), ct(), ct()
     R, jmin, nu = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     st = getattr(_load(), f"oracle_compute_hr_gap_{s}")(_ptr(X), X.size - 1, q, form, hstart, ctypes.byref(H),
                                                           ctypes.byref(W), ctypes.byref(R), ctypes.byref(jmin),
-                                                          ctypes.byref(nu))
+                                                          ctypes.byref(nu), ctypes.byref(Hb))
     if st != OK:
         return DirectTables(st, form=form, dtype=X.dtype, q=q)
-    return DirectTables(OK, H.value, W.value, R.value, jmin.value, nu.value, None, form, X.dtype, q)
+    t = DirectTables(OK, H.value, W.value, R.value, jmin.value, nu.value, None, form, X.dtype, q,
+                     H_bad=Hb.value, H_grown=H.value)
+    return _refined(X, t, q) if refine else t
 
 
 def init_k_gap(X: np.ndarray, H: float, W: float, R: int, jmin: int, form: int = FORM_SUB):
@@ -194,8 +235,9 @@ def init_k_gap(X: np.ndarray, H: float, W: float, R: int, jmin: int, form: int =
     return st, K
 
 
-def build_direct_gap(X: np.ndarray, q: int, form: int = FORM_SUB, hstart: int = HSTART_PHI) -> DirectTables:
-    t = compute_hr_gap(X, q, form, hstart)
+def build_direct_gap(X: np.ndarray, q: int, form: int = FORM_SUB, hstart: int = HSTART_PHI,
+                     refine: bool = False) -> DirectTables:
+    t = compute_hr_gap(X, q, form, hstart, refine)
     if t.status != OK:
         return t
     st, K = init_k_gap(X, t.H, t.W, t.R, t.jmin, form)

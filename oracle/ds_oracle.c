@@ -28,6 +28,10 @@
  *                     with X_N to 2^L - 1 values and stored in breadth-first
  *                     order of the complete search tree (the Eytzinger
  *                     layout), searched by descending L levels.
+ *   oracle_refine_h_* the bisection of [last infeasible H, feasible H] that
+ *                     the end of Sec. 4.4.3 proposes (not used by the paper's
+ *                     own experiments); any q of the gap variant, q = 1 for
+ *                     plain Direct.
  *   oracle_compute_hr_gap_*, oracle_init_k_gap_*, oracle_direct_gap_*
  *                     the relaxed variant of Sec. 4.7 ("Relaxing Limitations
  *                     and Reducing Memory Usage"): the grid only has to
@@ -119,7 +123,8 @@
    * final H). */                                                                \
   int oracle_compute_hr_##S(const T* X, int64_t N, int form, int hstart,        \
                             T* H_out, T* W_out, int64_t* R_out,                  \
-                            int64_t* jmin_out, int64_t* n_updates_out) {         \
+                            int64_t* jmin_out, int64_t* n_updates_out,           \
+                            T* Hbad_out) {                                       \
     if (N < 1 || X == 0) return OR_ERR_ARG;                                      \
     for (int64_t i = 0; i <= N; ++i)                                             \
       if (!isfinite(X[i])) return OR_ERR_NONFINITE;                              \
@@ -144,12 +149,14 @@
       return OR_ERR_INFEASIBLE;                                                  \
     T P = NEXTUP(H, (T)INFINITY) - H;                                            \
     int64_t n_updates = 0;                                                       \
+    T Hbad = 0; /* last H seen to violate the condition; 0 = none */            \
     for (;;) {                                                                   \
       int changed = 0;                                                           \
       for (int64_t i = 1; i <= N; ++i) {                                         \
         /* eq. (cond2): floor(f(X_{i-1})) < floor(f(X_i)) must hold */           \
         while (FLOOR(grid_value_##S(form, H, W, X0, X[i - 1])) ==                \
                FLOOR(grid_value_##S(form, H, W, X0, X[i]))) {                    \
+          Hbad = H;                                                              \
           H = H + P;                                                             \
           if (form == OR_FORM_FMA) W = H * X0;                                   \
           if (FLOOR(grid_value_##S(form, H, W, X0, X[N])) >= (T)OR_TWO_POW_Q)    \
@@ -166,6 +173,7 @@
     *R_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[N]));              \
     *jmin_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[0]));           \
     *n_updates_out = n_updates;                                                  \
+    if (Hbad_out) *Hbad_out = Hbad;                                              \
     return OR_OK;                                                                \
   }                                                                              \
                                                                                  \
@@ -224,7 +232,8 @@ DEFINE_ORACLE(double, f64, floor, fma, nextafter)
    * oracle_compute_hr.  q = 1 is plain Direct's condition. */                 \
   int oracle_compute_hr_gap_##S(const T* X, int64_t N, int64_t q, int form,     \
                                 int hstart, T* H_out, T* W_out, int64_t* R_out,  \
-                                int64_t* jmin_out, int64_t* n_updates_out) {     \
+                                int64_t* jmin_out, int64_t* n_updates_out,       \
+                                T* Hbad_out) {                                   \
     if (N < 1 || X == 0 || q < 1 || q > N) return OR_ERR_ARG;                    \
     for (int64_t i = 0; i <= N; ++i)                                             \
       if (!isfinite(X[i])) return OR_ERR_NONFINITE;                              \
@@ -248,11 +257,13 @@ DEFINE_ORACLE(double, f64, floor, fma, nextafter)
       return OR_ERR_INFEASIBLE;                                                  \
     T P = NEXTUP(H, (T)INFINITY) - H;                                            \
     int64_t n_updates = 0;                                                       \
+    T Hbad = 0;                                                                  \
     for (;;) {                                                                   \
       int changed = 0;                                                           \
       for (int64_t i = q; i <= N; ++i) {                                         \
         while (FLOOR(grid_value_##S(form, H, W, X0, X[i - q])) ==                \
                FLOOR(grid_value_##S(form, H, W, X0, X[i]))) {                    \
+          Hbad = H;                                                              \
           H = H + P;                                                             \
           if (form == OR_FORM_FMA) W = H * X0;                                   \
           if (FLOOR(grid_value_##S(form, H, W, X0, X[N])) >= (T)OR_TWO_POW_Q)    \
@@ -269,6 +280,58 @@ DEFINE_ORACLE(double, f64, floor, fma, nextafter)
     *R_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[N]));              \
     *jmin_out = (int64_t)FLOOR(grid_value_##S(form, H, W, X0, X[0]));           \
     *n_updates_out = n_updates;                                                  \
+    if (Hbad_out) *Hbad_out = Hbad;                                              \
+    return OR_OK;                                                                \
+  }                                                                              \
+                                                                                 \
+  /* Feasibility of one H: no overflow (eq. (overflowexact)) and              \
+   * floor(f(X_{i-q})) < floor(f(X_i)) for every i in [q, N] (eq. (cond2) for \
+   * q = 1, eq. (f-monotonic-n) otherwise). */                                  \
+  static int feasible_##S(const T* X, int64_t N, int64_t q, int form, T H) {   \
+    const T X0 = X[0];                                                           \
+    const T W = (form == OR_FORM_FMA) ? H * X0 : 0;                              \
+    if (FLOOR(grid_value_##S(form, H, W, X0, X[N])) >= (T)OR_TWO_POW_Q)          \
+      return 0;                                                                  \
+    for (int64_t i = q; i <= N; ++i)                                             \
+      if (!(FLOOR(grid_value_##S(form, H, W, X0, X[i - q])) <                    \
+            FLOOR(grid_value_##S(form, H, W, X0, X[i]))))                        \
+        return 0;                                                                \
+    return 1;                                                                    \
+  }                                                                              \
+                                                                                 \
+  /* The refinement suggested at the end of Sec. 4.4.3: Hlo is known to be     \
+   * infeasible and Hhi feasible; bisect [Hlo, Hhi] with the midpoint          \
+   * Hlo + (Hhi - Hlo) / 2 rounded in the dtype, keeping an infeasible left    \
+   * end and a feasible right end, until no float lies strictly between them.  \
+   * Feasibility is not monotone in H, so the result is a feasible H whose     \
+   * predecessor float is infeasible, not necessarily the smallest feasible H. \
+   * Outputs the refined H with its W, R and jmin, the final left end and the  \
+   * number of midpoints tested. */                                             \
+  int oracle_refine_h_##S(const T* X, int64_t N, int64_t q, int form, T Hlo,    \
+                          T Hhi, T* H_out, T* W_out, int64_t* R_out,             \
+                          int64_t* jmin_out, T* Hlo_out, int64_t* steps_out) {   \
+    if (N < 1 || X == 0 || q < 1 || q > N || !(Hlo > 0) || !(Hlo < Hhi))         \
+      return OR_ERR_ARG;                                                         \
+    if (feasible_##S(X, N, q, form, Hlo) || !feasible_##S(X, N, q, form, Hhi))   \
+      return OR_ERR_ARG;                                                         \
+    int64_t steps = 0;                                                           \
+    for (;;) {                                                                   \
+      T mid = Hlo + (Hhi - Hlo) / 2;                                             \
+      if (!(Hlo < mid && mid < Hhi)) break;                                      \
+      ++steps;                                                                   \
+      if (feasible_##S(X, N, q, form, mid))                                      \
+        Hhi = mid;                                                               \
+      else                                                                       \
+        Hlo = mid;                                                               \
+    }                                                                            \
+    const T X0 = X[0];                                                           \
+    const T W = (form == OR_FORM_FMA) ? Hhi * X0 : 0;                            \
+    *H_out = Hhi;                                                                \
+    *W_out = W;                                                                  \
+    *R_out = (int64_t)FLOOR(grid_value_##S(form, Hhi, W, X0, X[N]));            \
+    *jmin_out = (int64_t)FLOOR(grid_value_##S(form, Hhi, W, X0, X[0]));         \
+    *Hlo_out = Hlo;                                                              \
+    *steps_out = steps;                                                          \
     return OR_OK;                                                                \
   }                                                                              \
                                                                                  \

@@ -59,7 +59,8 @@ class BuildOpts(ctypes.Structure):
                 ("fallback", ctypes.c_int32), ("table_cap_bytes", ctypes.c_int64),
                 ("learn_epochs", ctypes.c_int32), ("learn_segments", ctypes.c_int32),
                 ("learn_rate", ctypes.c_float), ("learn_batch", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("extra_layouts", ctypes.c_int32), ("learn_flags", ctypes.c_int32), ("gap_q", ctypes.c_int32)]
+                ("extra_layouts", ctypes.c_int32), ("learn_flags", ctypes.c_int32), ("gap_q", ctypes.c_int32),
+                ("refine_h", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -70,7 +71,7 @@ class Info(ctypes.Structure):
                 ("model_bytes", ctypes.c_int64), ("max_err", ctypes.c_int64),
                 ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64),
                 ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("nibble_bytes", ctypes.c_int64), ("gap_q", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("nibble_bytes", ctypes.c_int64), ("gap_q", ctypes.c_int32), ("n_h_refine", ctypes.c_int32)]
 
 
 class View(ctypes.Structure):
@@ -299,20 +300,23 @@ class Index:
 def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart: str = "phi",
           fallback: str = "none", table_cap_bytes: int = 0, learn_epochs: int = 0, learn_segments: int = 0,
           learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), learn_fp32_router: bool = False,
-          gap_q: int = 0, stream=None) -> Index:
+          gap_q: int = 0, refine_h: bool = False, stream=None) -> Index:
     """ds_build over the N+1 values of x (a strictly increasing GPU tensor).
 
     layouts: extra Direct layouts to build besides the automatic one
     ("rankcode", "pairs", "nibble"), so that set_tune(stage=...) can select them.
     gap_q: method "direct_gap" (Sec. 4.7): compares per query, 1..16, or 0 for the
     smallest q whose table fits table_cap_bytes.
+    refine_h: when ComputeHR had to grow H, bisect between the last failing H and the
+    grown one (end of Sec. 4.4.3); info()["n_h_refine"] counts the midpoints tested.
     """
     _check_device(x, "x")
     if x.dim() != 1 or x.numel() < 2:
         raise ValueError("x must be 1-D with at least two values")
     opts = BuildOpts(_METHODS[method], _FORMS[form], _HSTARTS[hstart], _FALLBACKS[fallback], int(table_cap_bytes),
                      int(learn_epochs), int(learn_segments), float(learn_rate), int(learn_batch), int(seed),
-                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp32_router else 0, int(gap_q))
+                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp32_router else 0, int(gap_q),
+                     1 if refine_h else 0)
     h = ctypes.c_void_p()
     with torch.cuda.device(x.device):
         st = _lib.ds_build(x.data_ptr(), x.numel() - 1, _dtype_code(x), ctypes.byref(opts), _stream_handle(stream),

@@ -8,6 +8,9 @@
 //      grid cells coincide under the current H, so the host applies the growth
 //      steps in exactly the order of the sequential algorithm.  Passes repeat
 //      until one changes nothing, so every pair holds under the final H.
+//      On request the interval between the last failing H and the grown one is
+//      then bisected (the refinement proposed at the end of Sec. 4.4.3), each
+//      midpoint checked by one verify pass over the whole array.
 //   c) the table K (Sec. 4, eq. (indexdef)): one workgroup per 256 consecutive
 //      X_i computes their cells, then fills the contiguous run of K entries
 //      that falls between its first and last cell, each entry found by a
@@ -339,25 +342,34 @@ ds_status compute_hr(ds_index* h, const T* X, int64_t q, BuildScratch* scr, hipS
   if (overflow(H, W)) return DS_ERR_INFEASIBLE;  // eq. (overflowexact)
   T P = next_up(H) - H;
   int64_t n_updates = 0;
+  T Hbad = T(0);  // last H seen to fail a pair; 0 = none
   const int64_t vgrid = std::min<int64_t>(grid_for(N, kScanBlock, 1 << 20), int64_t(num_cus()) * 8);
+  // smallest failing pair index >= i_start under (Hc, Wc), or -1
+  auto first_bad_from = [&](int64_t i_start, T Hc, T Wc, int64_t* first) -> ds_status {
+    const unsigned long long none = ~0ull;
+    DS_HIP_CHECK(hipMemcpyAsync(&scr->first_bad, &none, sizeof(none), hipMemcpyHostToDevice, s));
+    verify_kernel<T, FORM><<<dim3((unsigned)vgrid), dim3(kScanBlock), 0, s>>>(X, N, q, i_start, Hc, Wc, X0, scr);
+    DS_HIP_CHECK(hipGetLastError());
+    unsigned long long f = 0;
+    DS_HIP_CHECK(hipMemcpyAsync(&f, &scr->first_bad, sizeof(f), hipMemcpyDeviceToHost, s));
+    DS_HIP_CHECK(hipStreamSynchronize(s));
+    *first = (f == none) ? -1 : static_cast<int64_t>(f);
+    return DS_OK;
+  };
   for (;;) {
     bool changed = false;
     int64_t i_start = q;
     while (i_start <= N) {
-      const unsigned long long none = ~0ull;
-      DS_HIP_CHECK(hipMemcpyAsync(&scr->first_bad, &none, sizeof(none), hipMemcpyHostToDevice, s));
-      verify_kernel<T, FORM><<<dim3((unsigned)vgrid), dim3(kScanBlock), 0, s>>>(X, N, q, i_start, H, W, X0, scr);
-      DS_HIP_CHECK(hipGetLastError());
-      unsigned long long first = 0;
-      DS_HIP_CHECK(hipMemcpyAsync(&first, &scr->first_bad, sizeof(first), hipMemcpyDeviceToHost, s));
-      DS_HIP_CHECK(hipStreamSynchronize(s));
-      if (first == ~0ull) break;
-      const int64_t i = static_cast<int64_t>(first);
+      int64_t i = -1;
+      ds_status st = first_bad_from(i_start, H, W, &i);
+      if (st != DS_OK) return st;
+      if (i < 0) break;
       T pair[2];
       DS_HIP_CHECK(hipMemcpyAsync(&pair[0], X + (i - q), sizeof(T), hipMemcpyDeviceToHost, s));
       DS_HIP_CHECK(hipMemcpyAsync(&pair[1], X + i, sizeof(T), hipMemcpyDeviceToHost, s));
       DS_HIP_CHECK(hipStreamSynchronize(s));
       while (grid_floor<T, FORM>(pair[0], H, W, X0) == grid_floor<T, FORM>(pair[1], H, W, X0)) {
+        Hbad = H;
         H = H + P;
         if (FORM == DS_FORM_FMA) W = H * X0;
         if (overflow(H, W)) return DS_ERR_INFEASIBLE;
@@ -369,6 +381,31 @@ ds_status compute_hr(ds_index* h, const T* X, int64_t q, BuildScratch* scr, hipS
     }
     if (!changed) break;
   }
+  // The refinement at the end of Sec. 4.4.3: Hbad fails and H holds; keep that
+  // invariant while halving [Hbad, H] until the ends are neighbouring floats.
+  int32_t n_refine = 0;
+  if (h->refine_h && n_updates > 0) {
+    T lo = Hbad;
+    for (;;) {
+      const T mid = lo + (H - lo) / T(2);
+      if (!(lo < mid && mid < H)) break;
+      ++n_refine;
+      const T Wm = (FORM == DS_FORM_FMA) ? T(mid * X0) : T(0);
+      bool ok = !overflow(mid, Wm);
+      if (ok) {
+        int64_t i = -1;
+        ds_status st = first_bad_from(q, mid, Wm, &i);
+        if (st != DS_OK) return st;
+        ok = i < 0;
+      }
+      if (ok) {
+        H = mid;
+        W = Wm;
+      } else {
+        lo = mid;
+      }
+    }
+  }
   h->H = H;
   h->W = W;
   h->X0 = X0;
@@ -376,6 +413,7 @@ ds_status compute_hr(ds_index* h, const T* X, int64_t q, BuildScratch* scr, hipS
   h->R = static_cast<int64_t>(grid_floor<T, FORM>(XN, H, W, X0));
   h->jmin = static_cast<int64_t>(grid_floor<T, FORM>(X0, H, W, X0));
   h->n_updates = n_updates;
+  h->n_refine = n_refine;
   return DS_OK;
 }
 
@@ -812,6 +850,7 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   if (o.gap_q < 0 || o.gap_q > ds::kMaxGapQ || (o.method == DS_METHOD_DIRECT_GAP && o.gap_q > N)) return DS_ERR_ARG;
   if (o.form != DS_FORM_SUB && o.form != DS_FORM_FMA) return DS_ERR_ARG;
   if (o.hstart != DS_HSTART_PHI && o.hstart != DS_HSTART_HBAR) return DS_ERR_ARG;
+  if (o.refine_h != 0 && o.refine_h != 1) return DS_ERR_ARG;
   if (o.fallback < DS_FALLBACK_NONE || o.fallback > DS_FALLBACK_LEARNED) return DS_ERR_ARG;
   if (o.table_cap_bytes < 0) return DS_ERR_ARG;
   if (o.extra_layouts & ~(DS_LAYOUT_RANKCODE | DS_LAYOUT_PAIRS | DS_LAYOUT_NIBBLE)) return DS_ERR_ARG;
@@ -826,6 +865,7 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   h->N = N;
   h->form = o.form;
   h->hstart = o.hstart;
+  h->refine_h = o.refine_h;
   ds_status st = (dt == DS_F32) ? ds::build_typed<float>(h, X_dev, o, s) : ds::build_typed<double>(h, X_dev, o, s);
   if (st == DS_OK && hipStreamSynchronize(s) != hipSuccess) st = DS_ERR_HIP;
   if (st != DS_OK) {
@@ -850,6 +890,7 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   in.R = h->R;
   in.jmin = h->jmin;
   in.n_h_updates = h->n_updates;
+  in.n_h_refine = h->n_refine;
   in.table_bytes = h->nK * int64_t(sizeof(int32_t));
   in.x_bytes = h->nX * int64_t(dt == DS_F32 ? 4 : 8);
   in.rankcode_bytes = h->rc_code ? (h->rc_words * 12 + (h->N + 1) * 2) : 0;

@@ -206,6 +206,8 @@ struct ds_index {
   double H = 0, W = 0, X0 = 0, XN = 0;
   int64_t R = 0, jmin = 0;
   int64_t n_updates = 0;
+  int32_t refine_h = 0;   // bisect [last infeasible H, grown H] after growth
+  int32_t n_refine = 0;   // midpoints the bisection tested
   // device memory
   void* X = nullptr;            // N+1 values (Direct, offset, learned), padded on the right
                                 // (leading-bit) or on the left (gap-q: x_off copies of X_0)

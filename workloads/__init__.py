@@ -18,6 +18,9 @@ this project measures:
                        half uniform queries, half X_k (1 + U(-1e-12, 1e-12)).
 * ``batched_f32``      10,000 f32 arrays, N_k log-uniform in [8, 65536],
                        offset ~ U(-1e3, 1e3), gaps ~ U(0.5, 1.5), M_k = 64 N_k.
+* ``near_limit_array`` small arrays whose smallest gap is about one ulp of the
+                       largest key (the feasibility limit of Sec. 4.4), where
+                       the choice of H is sensitive to rounding.
 * ``batched_mixture``  256 f64 arrays, N_k log-uniform in [2^14, 2^20], each an
                        even mixture of uniform gaps, 8 Gaussian clusters and
                        lognormal tails.
@@ -72,6 +75,32 @@ def gap_array(n: int, dtype, rng: np.random.Generator, lo=0.5, hi=1.5, x0=0.0) -
     if not strictly_increasing(out):
         raise RuntimeError("generated array is not strictly increasing after rounding")
     return out
+
+
+def near_limit_array(dtype, rng: np.random.Generator, q: int = 1, n_fill: int = 0,
+                     offset: bool = False) -> np.ndarray:
+    """An array at the feasibility limit of Sec. 4.4 (smallest gap about one ulp of the
+    largest key): 2..12 consecutive floats ending at a power of two 2^e (e in [-3, 3]),
+    q + 1 points at 2^(e-s) (s in [2, 7]) spaced g = U(0.5, 1) times the spacing of the
+    run, and n_fill keys evenly spaced in between, each moved by up to a quarter of their
+    spacing.  X_0 = 0, or with offset a negative X_0 of up to the low points' magnitude."""
+    dt = _dtype(dtype)
+    e = int(rng.integers(-3, 4))
+    top = dt.type(2.0 ** e)
+    run = [top]
+    for _ in range(int(rng.integers(q + 1, 12))):
+        run.append(np.nextafter(run[-1], dt.type(0)))
+    u = np.spacing(run[-1])
+    low = dt.type(2.0 ** (e - int(rng.integers(2, 8))))
+    g = dt.type(u * rng.uniform(0.5, 1.0))
+    pts = [low]
+    for _ in range(q):
+        pts.append(dt.type(pts[-1] + g))
+    a, b = 2.0 * float(low), 0.5 * float(top)
+    step = (b - a) / max(n_fill, 1)
+    fill = (a + step * (np.arange(n_fill) + 0.5 + rng.uniform(-0.25, 0.25, n_fill))).astype(dt)
+    x0 = dt.type(-rng.uniform(0.0, 1.0) * float(low)) if offset else dt.type(0)
+    return np.unique(np.concatenate([[x0], pts, fill, run]).astype(dt))
 
 
 def uniform_queries(x0, xn, m: int, dtype, rng: np.random.Generator) -> np.ndarray:
