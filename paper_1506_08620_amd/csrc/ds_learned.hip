@@ -233,6 +233,16 @@ __device__ __forceinline__ float route_pair(float u_mine, const void* regs) {
   return half ? yb : ya;
 }
 
+// Segment coordinate of a key or query: three quarters of the network's output
+// plus a quarter of the feature itself.  The network places segments by key
+// count, which squeezes a sparse region of the key domain (a long tail) into a
+// few segments, although queries spread uniformly in z land mostly there; the
+// feature term keeps a share of the segments spread by the feature, which is
+// roughly logarithmic in z.  Both terms are non-decreasing in z and each
+// rounding is monotone, so the coordinate is non-decreasing in z.  Keys (build)
+// and queries (search) go through this same function.
+__device__ __forceinline__ float route_coord(float y_net, float u) { return 0.75f * y_net + 0.25f * u; }
+
 __device__ __forceinline__ int32_t segment_of(float y, int32_t nseg) {
   const float s = std::floor(std::fmin(std::fmax(y * static_cast<float>(nseg), 0.0f), static_cast<float>(nseg - 1)));
   return static_cast<int32_t>(s);
@@ -535,7 +545,7 @@ __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict
     const float u_mine = i < n ? feat[i] : 1.0f;
     const float y = identity ? u_mine : route_pair<F16>(u_mine, &R);
     if (i < n) {
-      route[i] = segment_of(y, nseg);
+      route[i] = segment_of(identity ? y : route_coord(y, u_mine), nseg);
       if (y_out) y_out[i] = y;
     }
   }
@@ -769,7 +779,7 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
   for (; base < a.M; base += stride) {
     const T z_next = load_z(base + stride + lane);
     const float u = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
-    const float y = a.identity ? u : route_pair<F16>(u, &R);
+    const float y = a.identity ? u : route_coord(route_pair<F16>(u, &R), u);
     int32_t L, U;
     query_window<T>(z, y, a, segs, &L, &U);
     int32_t n = U - L + 1;
@@ -1128,7 +1138,7 @@ __global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kerne
       const int64_t qn = q + step;
       const T z_next = qn < q1 ? __builtin_nontemporal_load(z + qn) : a.X0;
       const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
-      const float y = route_pair<F16>(u, &R);
+      const float y = route_coord(route_pair<F16>(u, &R), u);
       int32_t L, U;
       query_window<T>(zq, y, a, segs, &L, &U);
       const int32_t L0 = L;
