@@ -358,7 +358,8 @@ typedef struct ds_batch_desc {
   int64_t total_x;            /* x_off[K], as a host value */
   int64_t total_q;            /* q_off[K], as a host value */
   int32_t form;               /* ds_form */
-  int32_t tile;               /* queries per work item; 0 = auto (2^17) */
+  int32_t tile;               /* queries per work item; 0 = auto (2^17, or 2^14 when
+                                 learn_segments > 0) */
   int32_t block;              /* threads per search workgroup, 64..1024 step 64; 0 = auto (1024) */
   int32_t lds_bytes;          /* LDS budget per search workgroup; 0 = auto (159 KiB), -1 = never stage */
   int32_t qpt;                /* queries in flight per lane: 4, 8 or 16; 0 = auto (8) */

@@ -618,9 +618,18 @@ ds_status launch_search_qpt(const ds_batch_desc* d, const WsLayout& L, unsigned 
   }
 }
 
+// Queries per work item when none is set: 2^17, or 2^14 when learned models
+// are enabled, so that the workgroups of one XCD usually work on the same
+// learned array at once and share its keys in that XCD's L2 (each XCD takes a
+// contiguous range of the tile order).
+int64_t tile_of(const ds_batch_desc* d) {
+  if (d->tile > 0) return d->tile;
+  return d->learn_segments > 0 ? (int64_t(1) << 14) : (int64_t(1) << 17);
+}
+
 SearchShape shape_of(const ds_batch_desc* d) {
   SearchShape sh{};
-  sh.tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
+  sh.tile = tile_of(d);
   sh.lds_budget = d->lds_bytes < 0 ? 0 : (d->lds_bytes > 0 ? std::min(d->lds_bytes, kLdsBytesPerCU - 1024)
                                                             : kLdsBytesPerCU - 1024);
   sh.chunk = 4;
@@ -654,8 +663,9 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.steps = d->learn_steps > 0 ? d->learn_steps : 50;
   b.fp32_router = 0;
   b.seed = 0x1506ull;
-  b.tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
+  b.tile = tile_of(d);
   b.X = d->X_dev;
+  b.total_x = d->total_x;
   b.z = d->z_dev;
   b.out = d->out_dev;
   b.lmeta = reinterpret_cast<LearnMeta*>(ws + L.lmeta);
@@ -728,7 +738,7 @@ ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
   unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
   const WsLayout L = layout_of(d);
   const int64_t wb = L.words_budget;
-  const int64_t tile = d->tile > 0 ? d->tile : (int64_t(1) << 17);
+  const int64_t tile = tile_of(d);
   auto* meta = reinterpret_cast<ArrMeta<T>*>(ws + L.meta);
   const int64_t cap_cells = d->direct_cap_bytes > 0 ? d->direct_cap_bytes / 4 : 0;
   build_hr_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(d->x_off_dev, d->q_off_dev,

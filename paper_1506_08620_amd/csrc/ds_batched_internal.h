@@ -59,6 +59,7 @@ struct BatchLearned {
   int32_t fp32_router;
   uint64_t seed;
   int64_t tile;
+  int64_t total_x;         // values in the packed X (reads never pass its end)
   const void* X;
   const void* z;
   int32_t* out;

@@ -218,6 +218,92 @@ __device__ __forceinline__ void router16_y2(float ua, float ub, const RouterRegs
   *yb = router_tail16(acc_b, R);
 }
 
+// The FP16 router with its half-wave-uniform values (layer 1, b2, layer 3:
+// lanes of one half of a wave use the same 16 of each) read from LDS, and only
+// the lane's own row of W2 in registers.  The operations and their order are
+// those of router16_y2, so y is bit-identical; what changes is the register
+// footprint (about 30 fewer), which leaves the scheduler room to overlap the
+// window search's loads.
+struct RouterShared16 {
+  float w1[2][16], b1[2][16], w3[2][16], b2[2][16];
+  float b3;
+};
+
+// called by every thread of the workgroup (blockDim.x >= 64); a barrier must
+// follow before use
+__device__ void fill_router_shared16(const float* __restrict__ p, RouterShared16* S, half4* w2) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int half = t >> 5, i = t & 31;
+    if (i < 16) {
+      const int k = 8 * (i >> 2) + 4 * half + (i & 3);
+      S->w1[half][i] = p[oW1 + k];
+      S->b1[half][i] = p[oB1 + k];
+    } else {
+      const int r = i - 16;
+      const int j = out_row(r, half);
+      S->b2[half][r] = p[oB2 + j];
+      S->w3[half][r] = p[oW3 + j];
+    }
+    if (t == 0) S->b3 = p[oB3];
+  }
+  const int lane = t & 63, half = lane >> 5, m = lane & 31;
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w2[kb][c] = static_cast<_Float16>(p[oW2 + m * kHid + 8 * kb + 4 * half + c]);
+}
+
+__device__ __forceinline__ float router_tail16_shared(const floatx16& acc, const RouterShared16* S, int half) {
+  float part = 0.0f;
+  const float4* w3 = reinterpret_cast<const float4*>(S->w3[half]);
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const float4 w = w3[r4];
+    part = std::fma(w.x, clamp01(acc[4 * r4 + 0]), part);
+    part = std::fma(w.y, clamp01(acc[4 * r4 + 1]), part);
+    part = std::fma(w.z, clamp01(acc[4 * r4 + 2]), part);
+    part = std::fma(w.w, clamp01(acc[4 * r4 + 3]), part);
+  }
+  const float other = __shfl_xor(part, 32, 64);
+  return (part + other) + S->b3;
+}
+
+__device__ __forceinline__ float route_pair_shared16(float u_mine, const half4* w2, const RouterShared16* S) {
+  const int half = (threadIdx.x & 63) >> 5;
+  const float u_other = __shfl_xor(u_mine, 32, 64);
+  const float ua = half ? u_other : u_mine, ub = half ? u_mine : u_other;
+  floatx16 acc_a;
+  const float4* b2 = reinterpret_cast<const float4*>(S->b2[half]);
+#pragma unroll
+  for (int r4 = 0; r4 < 4; ++r4) {
+    const float4 v = b2[r4];
+    acc_a[4 * r4 + 0] = v.x;
+    acc_a[4 * r4 + 1] = v.y;
+    acc_a[4 * r4 + 2] = v.z;
+    acc_a[4 * r4 + 3] = v.w;
+  }
+  floatx16 acc_b = acc_a;
+  const float4* w1 = reinterpret_cast<const float4*>(S->w1[half]);
+  const float4* b1 = reinterpret_cast<const float4*>(S->b1[half]);
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    const float4 w = w1[kb], b = b1[kb];
+    const float wv[4] = {w.x, w.y, w.z, w.w}, bv[4] = {b.x, b.y, b.z, b.w};
+    half4 ha, hb;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      ha[c] = static_cast<_Float16>(clamp01(std::fma(wv[c], ua, bv[c])));
+      hb[c] = static_cast<_Float16>(clamp01(std::fma(wv[c], ub, bv[c])));
+    }
+    acc_a = __builtin_amdgcn_mfma_f32_32x32x8f16(w2[kb], ha, acc_a, 0, 0, 0);
+    acc_b = __builtin_amdgcn_mfma_f32_32x32x8f16(w2[kb], hb, acc_b, 0, 0, 0);
+  }
+  const float ya = router_tail16_shared(acc_a, S, half);
+  const float yb = router_tail16_shared(acc_b, S, half);
+  return half ? yb : ya;
+}
+
 // y for the query of this lane (lane l: query l of the 64-query group), with
 // the two 32-query passes of either router precision
 template <bool F16>
@@ -689,30 +775,6 @@ __device__ __forceinline__ void search_round(T z, const T* __restrict__ X, int32
   }
 }
 
-// Exact index of z from its window, with the out-of-domain conventions.  Only
-// a result at an end of the window has a side not proven by a probe; that side
-// is checked, and a failure (never expected) takes a full search and is counted.
-template <typename T>
-__device__ __forceinline__ int32_t finish_window(T z, int32_t L0, int32_t U, int32_t i, const LearnedArgs<T>& a) {
-  const bool inside = (z >= a.X0) && (z < a.XN);
-  bool ok = true;
-  if (inside && i == L0) ok = a.X[i] <= z;
-  if (inside && i == U) ok = ok && z < a.X[i + 1];
-  if (inside && !ok) {
-    atomicAdd(a.fallbacks, 1ull);
-    int32_t lo = 0, nn = a.N;
-    while (nn > 1) {
-      const int32_t h = nn >> 1;
-      const bool c = z >= a.X[lo + h];
-      lo = c ? lo + h : lo;
-      nn = c ? nn - h : h;
-    }
-    i = lo;
-  }
-  i = (z >= a.XN) ? a.N : i;
-  return (z >= a.X0) ? i : -1;
-}
-
 // Values of X after X_N that the search may read (+inf): the block scan below
 // reads up to two 64-byte blocks from the block of a window's first index.
 constexpr int64_t kLearnScanPad = 32;
@@ -753,6 +815,67 @@ __device__ __forceinline__ int32_t scan_window(T z, int32_t L, int32_t n, const 
   return b0 + c - 1;
 }
 
+// The block scan of scan_window for an array that sits inside a packed buffer
+// Xp of total_x values, starting at x_off, with no padding after X_N: the
+// blocks are 64-byte aligned in memory (the array itself need not be), and
+// values outside the array's [0, N] are masked by their index.  Blocks that
+// would start before Xp or end past its last value are read value by value,
+// inside the array only.  Certification as in scan_window, over the array's
+// values that were read.
+template <typename T>
+__device__ __forceinline__ int32_t scan_window_packed(T z, int32_t L, int32_t n, const T* __restrict__ Xp,
+                                                      int64_t x_off, int32_t N, int64_t total_x, bool* certified) {
+  constexpr int E = 64 / int(sizeof(T));
+  constexpr int V = 16 / int(sizeof(T));
+  const T* Xa = Xp + x_off;
+  const T* blk = reinterpret_cast<const T*>(reinterpret_cast<uintptr_t>(Xa + L) & ~uintptr_t(63));
+  const int64_t k0 = blk - Xa;                      // array index of the block's first value (may be < 0)
+  const bool two = int64_t(L) + n >= k0 + E;        // values L .. L + n reach the next block
+  const int nb = two ? 2 * E : E;
+  int32_t c = 0, valid = 0;
+  if (blk >= Xp && blk + nb <= Xp + total_x) {
+    const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(blk);
+#pragma unroll
+    for (int v = 0; v < 2 * E / V; ++v) {
+      if (v < nb / V) {
+        const vec16b<T> x = p[v];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const int64_t k = k0 + v * V + e;
+          const bool in = k >= 0 && k <= N;
+          c += (in && x[e] <= z) ? 1 : 0;
+          valid += in ? 1 : 0;
+        }
+      }
+    }
+  } else {
+    for (int t = 0; t < nb; ++t) {
+      const int64_t k = k0 + t;
+      if (k >= 0 && k <= N) {
+        c += (Xa[k] <= z) ? 1 : 0;
+        ++valid;
+      }
+    }
+  }
+  *certified = c >= 1 && c <= valid - 1;
+  return static_cast<int32_t>(std::max<int64_t>(k0, 0)) + c - 1;
+}
+
+// Index of z by the classic binary search over the whole array, for a query
+// whose window search could not certify its result (counted).
+template <typename T>
+__device__ int32_t full_search_counted(T z, const T* __restrict__ X, int32_t N, unsigned long long* fallbacks) {
+  atomicAdd(fallbacks, 1ull);
+  int32_t lo = 0, nn = N;
+  while (nn > 1) {
+    const int32_t h = nn >> 1;
+    const bool c = z >= X[lo + h];
+    lo = c ? lo + h : lo;
+    nn = c ? nn - h : h;
+  }
+  return lo;
+}
+
 // One 64-query group per wave and iteration; the next group's queries are
 // loaded before this group is worked on.  A query bisects its window down to
 // one 64-byte block, then scans it (scan_window); a result the scan cannot
@@ -760,14 +883,17 @@ __device__ __forceinline__ int32_t scan_window(T z, int32_t L, int32_t n, const 
 template <typename T, bool F16>
 __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ RouterShared16 S;
   stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.segs), int64_t(a.nseg) * sizeof(SegFit));
-  __syncthreads();
   const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
-  typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
+  // FP16 router: half-wave-uniform values in LDS, W2 rows in registers
+  half4 w2[4];
+  RouterRegs R;
   if constexpr (F16)
-    load_router16(a.params, R);
+    fill_router_shared16(a.params, &S, w2);
   else
     load_router(a.params, R);
+  __syncthreads();
   constexpr int32_t E = 64 / int32_t(sizeof(T));
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -779,25 +905,21 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
   for (; base < a.M; base += stride) {
     const T z_next = load_z(base + stride + lane);
     const float u = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
-    const float y = a.identity ? u : route_coord(route_pair<F16>(u, &R), u);
+    float y_net;
+    if constexpr (F16) {
+      asm volatile("" ::: "memory");  // keeps the LDS reads of the router inside the loop
+      y_net = route_pair_shared16(u, w2, &S);
+    } else {
+      y_net = route_pair<false>(u, &R);
+    }
+    const float y = a.identity ? u : route_coord(y_net, u);
     int32_t L, U;
     query_window<T>(z, y, a, segs, &L, &U);
     int32_t n = U - L + 1;
     while (n > E) search_round<T>(z, a.X, L, n);
     bool certified;
     int32_t i = scan_window<T>(z, L, n, a.X, &certified);
-    const bool inside = (z >= a.X0) && (z < a.XN);
-    if (inside && !certified) {
-      atomicAdd(a.fallbacks, 1ull);
-      int32_t lo = 0, nn = a.N;
-      while (nn > 1) {
-        const int32_t h = nn >> 1;
-        const bool c = z >= a.X[lo + h];
-        lo = c ? lo + h : lo;
-        nn = c ? nn - h : h;
-      }
-      i = lo;
-    }
+    if ((z >= a.X0) && (z < a.XN) && !certified) i = full_search_counted<T>(z, a.X, a.N, a.fallbacks);
     i = (z >= a.XN) ? a.N : i;
     i = (z >= a.X0) ? i : -1;
     if (base + lane < a.M) __builtin_nontemporal_store(i, a.out + base + lane);
@@ -1065,10 +1187,14 @@ __global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ par
   }
 }
 
-constexpr int kBatchLearnedBlock = 768;  // 170 registers per lane: the search state fits without spills
+// threads per workgroup: with the FP16 router's shared values in LDS the search
+// state takes about 124 registers (four waves per SIMD); the FP32 router keeps
+// its weights in registers (about 167, three waves per SIMD)
+template <bool F16>
+constexpr int batch_learned_block() { return F16 ? 1024 : 768; }
 
 template <typename T, bool F16>
-__global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kernel(BatchLearned b) {
+__global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_search_kernel(BatchLearned b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int64_t s_tile;
   __shared__ int32_t s_k;
@@ -1078,13 +1204,26 @@ __global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kerne
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
-  typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
+  __shared__ RouterShared16 S;  // FP16 router: half-wave-uniform values
+  half4 w2[4];
+  RouterRegs R;
+  constexpr int32_t E = 64 / int32_t(sizeof(T));
   int32_t cur = -1;
   for (;;) {
     if (threadIdx.x == 0) {
-      const int64_t li = atomicAdd(&b.tot->lqueue[queue], 1u);
-      const int64_t ch = 4;
-      const int64_t g = ((li / ch) * kNumQueues + queue) * ch + (li % ch);
+      // Each queue (one per XCD) owns a contiguous eighth of the tile order,
+      // so the workgroups of one XCD share the few arrays of their range in
+      // that XCD's L2; a queue whose range is done takes from the next ones.
+      int64_t g = total;
+      for (int t = 0; t < kNumQueues; ++t) {
+        const int qq = (queue + t) % kNumQueues;
+        const int64_t lo = total * qq / kNumQueues, hi = total * (qq + 1) / kNumQueues;
+        const int64_t li = atomicAdd(&b.tot->lqueue[qq], 1u);
+        if (lo + li < hi) {
+          g = lo + li;
+          break;
+        }
+      }
       int32_t k = -1;
       if (g < total) {
         int32_t lo = 0, hi = b.K - 1;
@@ -1111,11 +1250,11 @@ __global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kerne
     if (slot != cur) {
       stage_bytes(smem, static_cast<const unsigned char*>(b.segs) + (int64_t)slot * b.nseg * kSegFitBytes,
                   int64_t(b.nseg) * kSegFitBytes);
-      __syncthreads();
       if constexpr (F16)
-        load_router16(b.params + (int64_t)slot * kParams, R);
+        fill_router_shared16(b.params + (int64_t)slot * kParams, &S, w2);
       else
         load_router(b.params + (int64_t)slot * kParams, R);
+      __syncthreads();
       cur = slot;
     }
     const LearnMeta lm = b.lmeta[slot];
@@ -1138,13 +1277,23 @@ __global__ void __launch_bounds__(kBatchLearnedBlock) batch_learned_search_kerne
       const int64_t qn = q + step;
       const T z_next = qn < q1 ? __builtin_nontemporal_load(z + qn) : a.X0;
       const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
-      const float y = route_coord(route_pair<F16>(u, &R), u);
+      float y_net;
+      if constexpr (F16) {
+        asm volatile("" ::: "memory");  // keeps the LDS reads of the router inside the loop
+        y_net = route_pair_shared16(u, w2, &S);
+      } else {
+        y_net = route_pair<false>(u, &R);
+      }
+      const float y = route_coord(y_net, u);
       int32_t L, U;
       query_window<T>(zq, y, a, segs, &L, &U);
-      const int32_t L0 = L;
       int32_t n = U - L + 1;
-      while (n > 1) search_round<T>(zq, a.X, L, n);
-      const int32_t i = finish_window<T>(zq, L0, U, L, a);
+      while (n > E) search_round<T>(zq, a.X, L, n);
+      bool certified;
+      int32_t i = scan_window_packed<T>(zq, L, n, static_cast<const T*>(b.X), m.x_off, a.N, b.total_x, &certified);
+      if ((zq >= a.X0) && (zq < a.XN) && !certified) i = full_search_counted<T>(zq, a.X, a.N, a.fallbacks);
+      i = (zq >= a.XN) ? a.N : i;
+      i = (zq >= a.X0) ? i : -1;
       if (q < q1) __builtin_nontemporal_store(i, b.out + q);
       zq = z_next;
     }
@@ -1191,11 +1340,12 @@ ds_status batched_learned_search_typed(const BatchLearned& b, hipStream_t s) {
     DS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      lds));
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchLearnedBlock, lds) != hipSuccess || per_cu < 1)
+  const int block = b.fp32_router ? batch_learned_block<false>() : batch_learned_block<true>();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
   int grid = per_cu * num_cus();
   grid = std::max(kNumQueues, grid / kNumQueues * kNumQueues);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBatchLearnedBlock), lds, s, b);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, b);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }

@@ -271,6 +271,39 @@ def test_batched_learned_f32_and_shapes(ds):
     assert (meth == ds.METHOD_LEARNED).any() and (meth == ds.METHOD_DIRECT).any()
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batched_learned_block_scan_at_buffer_edges(ds, dtype):
+    """The learned search reads 64-byte blocks aligned in memory: arrays at unaligned offsets,
+    a packed buffer that itself starts off a 64-byte boundary (a view one value into a larger
+    tensor), and queries packed at both ends of every array, the last array's end being the
+    end of the buffer."""
+    rng = np.random.default_rng(31)
+    sizes = [5, 17, 300, 2500, 40, 9000, 3]
+    arrays = [W.gap_array(n, dtype, rng, x0=rng.uniform(-50, 50)) for n in sizes]
+    x_off = np.concatenate([[0], np.cumsum([a.size for a in arrays])]).astype(np.int64)
+    X = np.concatenate(arrays).astype(dtype)
+    zs = []
+    for a in arrays:
+        ends = np.concatenate([a[:12], a[-12:]])
+        zs.append(np.concatenate([ends, W.prev_float(ends, dtype), np.nextafter(ends, dtype(np.inf)),
+                                  W.uniform_queries(a[0], a[-1], 500, dtype, rng),
+                                  np.array([a[0] - 1, a[-1] + 1, np.nan], dtype)]).astype(dtype))
+    z = np.concatenate(zs)
+    q_off = np.concatenate([[0], np.cumsum([q.size for q in zs])]).astype(np.int64)
+    ref = _oracle_batch(x_off, X, q_off, z)
+    big = torch.zeros(X.size + 1, dtype=torch.float32 if dtype == np.float32 else torch.float64, device=DEV)
+    big[1:] = _dev(X)
+    Xv = big[1:]  # starts 4 or 8 bytes past an allocation boundary
+    for segs in (64, 1024):
+        bt = ds.Batch(_dev(x_off), Xv, _dev(q_off), _dev(z), learn_segments=segs, learn_steps=10,
+                      direct_cap_bytes=8)
+        out = bt.run().cpu().numpy()
+        meth, _ = bt.report()
+        assert np.all(meth == ds.METHOD_LEARNED)
+        _assert_same(out, ref)
+        assert bt.fallbacks() == 0
+
+
 def test_full_size_batched_learned_f64_sampled(ds):
     """256 mixture arrays, N_k log-uniform in [2^14, 2^20], 2^28 queries (70 % uniform, 20 % hits,
     10 % nextafter(X_i, -inf)); Direct where its table fits under 64 MB, the learned method elsewhere."""
