@@ -194,6 +194,35 @@ def test_graph_capture_replays(ds):
     _assert_same(eager.cpu().numpy(), _oracle_batch(b.x_off, b.X, b.q_off, b.z))
 
 
+def test_graph_capture_replays_learned(ds):
+    """A batch whose arrays take the learned method (device build, training steps, routing, fits
+    and search, all captured): every replay equals the eager run and the oracle."""
+    b = _mixture_batch((3000, 9000, 20000, 500), 20_000, 12)
+    bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z), learn_segments=512, learn_steps=8,
+                  direct_cap_bytes=64)
+    eager = bt.run().clone()
+    meth, _ = bt.report()
+    assert np.all(meth == ds.METHOD_LEARNED)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bt.run()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run()
+    for r in range(4):
+        bt.out.fill_(-9)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bt.out, eager), r
+        bt.run()  # eager work between replays
+        torch.cuda.synchronize()
+    _assert_same(eager.cpu().numpy(), _oracle_batch(b.x_off, b.X, b.q_off, b.z))
+    assert bt.fallbacks() == 0
+
+
 def test_full_size_batched_f32_sampled(ds):
     """10,000 arrays, N_k log-uniform in [8, 65536], M_k = 64 N_k (about 4.5e9 queries)."""
     b = W.batched_f32(with_queries=False)
