@@ -829,36 +829,32 @@ __device__ __forceinline__ int32_t scan_window_packed(T z, int32_t L, int32_t n,
   constexpr int V = 16 / int(sizeof(T));
   const T* Xa = Xp + x_off;
   const T* blk = reinterpret_cast<const T*>(reinterpret_cast<uintptr_t>(Xa + L) & ~uintptr_t(63));
-  const int64_t k0 = blk - Xa;                      // array index of the block's first value (may be < 0)
-  const bool two = int64_t(L) + n >= k0 + E;        // values L .. L + n reach the next block
-  const int nb = two ? 2 * E : E;
-  int32_t c = 0, valid = 0;
-  if (blk >= Xp && blk + nb <= Xp + total_x) {
+  const int32_t k0 = static_cast<int32_t>(blk - Xa);  // array index of the block's first value, > L - E
+  const bool two = L + n >= k0 + E;                   // values L .. L + n reach the next block
+  const int32_t e_lo = std::max(0, -k0);              // positions e_lo .. e_hi of the block(s) are in the array
+  const int32_t e_hi = std::min((two ? 2 * E : E) - 1, N - k0);
+  int32_t c = 0;
+  if (blk >= Xp && blk + (two ? 2 * E : E) <= Xp + total_x) {
     const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(blk);
 #pragma unroll
-    for (int v = 0; v < 2 * E / V; ++v) {
-      if (v < nb / V) {
+    for (int v = 0; v < E / V; ++v) {
+      const vec16b<T> x = p[v];
+#pragma unroll
+      for (int e = 0; e < V; ++e) c += (v * V + e >= e_lo && v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
+    }
+    if (two) {
+#pragma unroll
+      for (int v = E / V; v < 2 * E / V; ++v) {
         const vec16b<T> x = p[v];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-          const int64_t k = k0 + v * V + e;
-          const bool in = k >= 0 && k <= N;
-          c += (in && x[e] <= z) ? 1 : 0;
-          valid += in ? 1 : 0;
-        }
+        for (int e = 0; e < V; ++e) c += (v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
       }
     }
   } else {
-    for (int t = 0; t < nb; ++t) {
-      const int64_t k = k0 + t;
-      if (k >= 0 && k <= N) {
-        c += (Xa[k] <= z) ? 1 : 0;
-        ++valid;
-      }
-    }
+    for (int32_t e = e_lo; e <= e_hi; ++e) c += (Xa[k0 + e] <= z) ? 1 : 0;
   }
-  *certified = c >= 1 && c <= valid - 1;
-  return static_cast<int32_t>(std::max<int64_t>(k0, 0)) + c - 1;
+  *certified = c >= 1 && c <= e_hi - e_lo;
+  return k0 + e_lo + c - 1;
 }
 
 // Index of z by the classic binary search over the whole array, for a query
@@ -1198,12 +1194,11 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int64_t s_tile;
   __shared__ int32_t s_k;
+  __shared__ int32_t s_grp;  // next 64-query group of the current tile
   const ArrMeta<T>* meta = static_cast<const ArrMeta<T>*>(b.meta);
   const int queue = blockIdx.x % kNumQueues;
   const int64_t total = b.tot->total_tiles;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nwaves = blockDim.x >> 6;
   __shared__ RouterShared16 S;  // FP16 router: half-wave-uniform values
   half4 w2[4];
   RouterRegs R;
@@ -1238,6 +1233,7 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
       }
       s_tile = g;
       s_k = k;
+      s_grp = 0;
     }
     __syncthreads();
     const int64_t g = s_tile;
@@ -1268,14 +1264,24 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
     const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
     const int64_t q0 = m.q_off + (g - m.t_off) * b.tile;
     const int64_t q1 = std::min(m.q_end, q0 + b.tile);
+    const int32_t ngrp = static_cast<int32_t>((q1 - q0 + 63) >> 6);
     const T* z = static_cast<const T*>(b.z);
-    const int64_t step = int64_t(nwaves) * 64;
-    int64_t base = q0 + int64_t(wave) * 64;
-    T zq = (base + lane < q1) ? __builtin_nontemporal_load(z + base + lane) : a.X0;
-    for (; base < q1; base += step) {
-      const int64_t q = base + lane;
-      const int64_t qn = q + step;
-      const T z_next = qn < q1 ? __builtin_nontemporal_load(z + qn) : a.X0;
+    // waves claim the tile's 64-query groups one at a time, so they finish the
+    // tile within one group of each other; the next group is claimed and its
+    // queries loaded before the current one is worked on
+    auto claim = [&]() {
+      int32_t c = 0;
+      if (lane == 0) c = atomicAdd(&s_grp, 1);
+      return __shfl(c, 0, 64);
+    };
+    int32_t gi = claim();
+    T zq = (gi < ngrp && q0 + int64_t(gi) * 64 + lane < q1) ? __builtin_nontemporal_load(z + q0 + int64_t(gi) * 64 + lane)
+                                                           : a.X0;
+    while (gi < ngrp) {
+      const int64_t q = q0 + int64_t(gi) * 64 + lane;
+      const int32_t gn = claim();
+      const int64_t qn = q0 + int64_t(gn) * 64 + lane;
+      const T z_next = (gn < ngrp && qn < q1) ? __builtin_nontemporal_load(z + qn) : a.X0;
       const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
       float y_net;
       if constexpr (F16) {
@@ -1296,6 +1302,7 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
       i = (zq >= a.X0) ? i : -1;
       if (q < q1) __builtin_nontemporal_store(i, b.out + q);
       zq = z_next;
+      gi = gn;
     }
     __syncthreads();  // every wave is done with this array's tables before they may change
   }
