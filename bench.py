@@ -467,7 +467,7 @@ def bench_batched_learned(ds, W, dev, stream, reps):
                gq_s_end_to_end=round(total_q / ms / 1e6, 2),
                direct_arrays=int((meth == ds.METHOD_DIRECT).sum()),
                learned_arrays=int((meth == ds.METHOD_LEARNED).sum()), fallbacks=bt.fallbacks(),
-               note="end to end includes the device build and the training steps (50 by default) of every learned model")
+               note="end to end includes the device build and the training steps (10 by default) of every learned model")
     del z, bt
     torch.cuda.empty_cache()
     return res

@@ -366,7 +366,7 @@ typedef struct ds_batch_desc {
   int32_t learn_segments;     /* > 0: arrays where Direct is infeasible, over direct_cap_bytes or out of
                                  table room use the learned method with this many segments per array
                                  (the workspace must be sized with the same value); 0: binary search */
-  int32_t learn_steps;        /* learned: training steps (one batched launch each, 2048 samples per array); 0 = 50 */
+  int32_t learn_steps;        /* learned: training steps (one batched launch each, 2048 samples per array); 0 = 10 */
   int32_t reserved_;
   int64_t direct_cap_bytes;   /* per-array cap on the Direct table (4 bytes per grid cell); 0 = none */
 } ds_batch_desc;

@@ -277,9 +277,11 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
                                                           int64_t direct_cap_cells, LearnMeta* __restrict__ lmeta) {
   __shared__ int64_t s_w[kPlanBlock], s_c[kPlanBlock], s_t[kPlanBlock], s_l[kPlanBlock];
   __shared__ int64_t carry_w, carry_c, carry_t, carry_l;
+  __shared__ unsigned long long s_ltiles;
   const int tid = threadIdx.x;
   if (tid == 0) {
     carry_w = carry_c = carry_t = carry_l = 0;
+    s_ltiles = 0;
   }
   if (tid < kNumQueues) {
     tot->queue[tid] = 0;
@@ -355,6 +357,7 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
     }
     if (isl) {
       ArrMeta<T>& m = meta[k];
+      atomicAdd(&s_ltiles, static_cast<unsigned long long>(nt));
       const int32_t slot = static_cast<int32_t>(carry_l + s_l[tid] - 1);
       m.slot = slot;
       LearnMeta lm{};
@@ -385,6 +388,7 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
   if (tid == 0) {
     tile_off[K] = carry_t;
     tot->total_tiles = carry_t;
+    tot->learned_tiles = static_cast<int64_t>(s_ltiles);
     tot->words_used = carry_w;
     tot->n_learned = static_cast<int32_t>(carry_l);
   }
@@ -498,6 +502,7 @@ __global__ void __launch_bounds__(1024) batch_search_kernel(const ArrMeta<T>* __
   __shared__ int32_t s_k;
   const int queue = blockIdx.x % kNumQueues;
   const int64_t total = tot->total_tiles;
+  if (tot->learned_tiles == total) return;  // every tile belongs to a learned array
   int32_t cur = -1;
   bool staged = false;
   for (;;) {
@@ -660,7 +665,7 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.tot = reinterpret_cast<PlanTotals*>(ws + L.totals);
   b.K = d->num_arrays;
   b.nseg = L.nseg;
-  b.steps = d->learn_steps > 0 ? d->learn_steps : 50;
+  b.steps = d->learn_steps > 0 ? d->learn_steps : 10;
   b.fp32_router = 0;
   b.seed = 0x1506ull;
   b.tile = tile_of(d);

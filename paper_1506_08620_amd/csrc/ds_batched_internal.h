@@ -32,6 +32,7 @@ struct alignas(16) ArrMeta {
 
 struct PlanTotals {
   int64_t total_tiles;
+  int64_t learned_tiles;        // tiles of learned arrays (the rest are Direct / binary search)
   int64_t words_used;
   uint32_t queue[kNumQueues];   // Direct / binary-search tiles
   uint32_t lqueue[kNumQueues];  // learned tiles

@@ -657,7 +657,13 @@ __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, i
 }
 
 // least-squares line of index against z for the keys of one segment (f64
-// sums over centred z), then the key errors over [lo, hi + 1]
+// sums over centred z), then the key errors over [lo, hi + 1].  One wave per
+// segment, reductions in a fixed order: segments hold tens to hundreds of keys,
+// so a wave reads them in one or a few rounds of independent loads (groups of
+// 16 lanes per segment took twice as long: more dependent load rounds).
+constexpr int kFitLanes = 64;
+constexpr int kFitSegsPerBlock = 256 / kFitLanes;
+
 template <typename T>
 __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, int64_t N,
                                                       const int32_t* __restrict__ first, SegFit* __restrict__ segs,
@@ -672,17 +678,16 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
     first += (int64_t)slot * (nseg + 1);
     segs += (int64_t)slot * nseg;
   }
-  // one wave per segment, wave-level reductions in a fixed order
-  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (s >= nseg) return;  // uniform across the wave
-  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * kFitSegsPerBlock + (threadIdx.x / kFitLanes);
+  if (s >= nseg) return;  // uniform across the segment's lanes
+  const int lane = threadIdx.x % kFitLanes;
   const int64_t a = first[s], b = first[s + 1];  // keys [a, b)
   const int64_t lo = std::max<int64_t>(0, std::min<int64_t>(a - 1, N - 1));
   const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(b - 1, N - 1));
   const int64_t c0 = (a < b) ? a : lo;
   const double zc = static_cast<double>(X[c0]);
   double n = 0, sz = 0, szz = 0, si_ = 0, siz = 0;
-  for (int64_t i = a + lane; i < b; i += 64) {
+  for (int64_t i = a + lane; i < b; i += kFitLanes) {
     const double dz = static_cast<double>(X[i]) - zc;
     const double di = static_cast<double>(i - lo);
     n += 1;
@@ -692,14 +697,14 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
     siz += di * dz;
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    n += __shfl_xor(n, o, 64);
-    sz += __shfl_xor(sz, o, 64);
-    szz += __shfl_xor(szz, o, 64);
-    si_ += __shfl_xor(si_, o, 64);
-    siz += __shfl_xor(siz, o, 64);
+  for (int o = kFitLanes / 2; o > 0; o >>= 1) {
+    n += __shfl_xor(n, o, kFitLanes);
+    sz += __shfl_xor(sz, o, kFitLanes);
+    szz += __shfl_xor(szz, o, kFitLanes);
+    si_ += __shfl_xor(si_, o, kFitLanes);
+    siz += __shfl_xor(siz, o, kFitLanes);
   }
-  // every lane holds the same sums and computes the same fit
+  // every lane of the group holds the same sums and computes the same fit
   double slope = 0, icpt = 0;
   if (n >= 2) {
     const double var = szz - sz * sz / n;
@@ -717,15 +722,15 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
   f.lo = static_cast<int32_t>(lo);
   f.hi = static_cast<int32_t>(hi);
   int32_t dmin = 1 << 30, dmax = -(1 << 30);
-  for (int64_t i = lo + lane; i <= hi + 1 && i <= N; i += 64) {
+  for (int64_t i = lo + lane; i <= hi + 1 && i <= N; i += kFitLanes) {
     const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, X[i]);
     dmin = std::min(dmin, d);
     dmax = std::max(dmax, d);
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    dmin = std::min(dmin, __shfl_xor(dmin, o, 64));
-    dmax = std::max(dmax, __shfl_xor(dmax, o, 64));
+  for (int o = kFitLanes / 2; o > 0; o >>= 1) {
+    dmin = std::min(dmin, __shfl_xor(dmin, o, kFitLanes));
+    dmax = std::max(dmax, __shfl_xor(dmax, o, kFitLanes));
   }
   if (lane == 0) {
     f.dmin = dmin;
@@ -1051,7 +1056,8 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
                                                                                    nullptr, nullptr);
   seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first,
                                                                                 nullptr, nullptr);
-  seg_fit_kernel<T><<<dim3((nseg + 3) / 4), dim3(256), 0, s>>>(X, N, L->first, L->segs, nseg, nullptr, nullptr);
+  seg_fit_kernel<T><<<dim3((nseg + kFitSegsPerBlock - 1) / kFitSegsPerBlock), dim3(256), 0, s>>>(
+      X, N, L->first, L->segs, nseg, nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
   std::vector<SegFit> host(nseg);
   DS_HIP_CHECK(hipMemcpyAsync(host.data(), L->segs, size_t(nseg) * sizeof(SegFit), hipMemcpyDeviceToHost, s));
@@ -1198,6 +1204,7 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
   const ArrMeta<T>* meta = static_cast<const ArrMeta<T>*>(b.meta);
   const int queue = blockIdx.x % kNumQueues;
   const int64_t total = b.tot->total_tiles;
+  if (b.tot->learned_tiles == 0) return;  // no learned array
   const int lane = threadIdx.x & 63;
   __shared__ RouterShared16 S;  // FP16 router: half-wave-uniform values
   half4 w2[4];
@@ -1332,9 +1339,8 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
     route_keys_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, 0, b.nseg, 0, b.route, nullptr,
                                                               b.lmeta, b.tot);
   seg_first_kernel<<<dim3(64, K), dim3(256), 0, s>>>(b.route, 0, b.nseg, b.first, b.lmeta, b.tot);
-  seg_fit_kernel<T><<<dim3((b.nseg + 3) / 4, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, b.first,
-                                                                      static_cast<SegFit*>(b.segs), b.nseg, b.lmeta,
-                                                                      b.tot);
+  seg_fit_kernel<T><<<dim3((b.nseg + kFitSegsPerBlock - 1) / kFitSegsPerBlock, K), dim3(256), 0, s>>>(
+      static_cast<const T*>(b.X), 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }
