@@ -686,22 +686,35 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
   const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(b - 1, N - 1));
   const int64_t c0 = (a < b) ? a : lo;
   const double zc = static_cast<double>(X[c0]);
-  double n = 0, sz = 0, szz = 0, si_ = 0, siz = 0;
-  for (int64_t i = a + lane; i < b; i += kFitLanes) {
-    const double dz = static_cast<double>(X[i]) - zc;
-    const double di = static_cast<double>(i - lo);
-    n += 1;
-    sz += dz;
-    szz += dz * dz;
-    si_ += di;
-    siz += di * dz;
+  // n and the sum of (i - lo) over the keys [a, b) have closed forms
+  const double n = static_cast<double>(b - a);
+  const double si_ = static_cast<double>(b - a) * (static_cast<double>(a + b - 1) * 0.5 - static_cast<double>(lo));
+  const int64_t last = std::min(hi + 1, N);  // the error pass covers [lo, last]
+  // usual case: [lo, last] fits one value per lane, loaded once for both passes
+  const bool one_round = last - lo < kFitLanes;
+  T xr = T(0);
+  if (one_round && lo + lane <= last) xr = X[lo + lane];
+  double sz = 0, szz = 0, siz = 0;
+  if (one_round) {
+    const int64_t i = lo + lane;
+    if (i >= a && i < b) {
+      const double dz = static_cast<double>(xr) - zc;
+      sz = dz;
+      szz = dz * dz;
+      siz = static_cast<double>(i - lo) * dz;
+    }
+  } else {
+    for (int64_t i = a + lane; i < b; i += kFitLanes) {
+      const double dz = static_cast<double>(X[i]) - zc;
+      sz += dz;
+      szz += dz * dz;
+      siz += static_cast<double>(i - lo) * dz;
+    }
   }
 #pragma unroll
   for (int o = kFitLanes / 2; o > 0; o >>= 1) {
-    n += __shfl_xor(n, o, kFitLanes);
     sz += __shfl_xor(sz, o, kFitLanes);
     szz += __shfl_xor(szz, o, kFitLanes);
-    si_ += __shfl_xor(si_, o, kFitLanes);
     siz += __shfl_xor(siz, o, kFitLanes);
   }
   // every lane of the group holds the same sums and computes the same fit
@@ -722,10 +735,18 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
   f.lo = static_cast<int32_t>(lo);
   f.hi = static_cast<int32_t>(hi);
   int32_t dmin = 1 << 30, dmax = -(1 << 30);
-  for (int64_t i = lo + lane; i <= hi + 1 && i <= N; i += kFitLanes) {
-    const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, X[i]);
-    dmin = std::min(dmin, d);
-    dmax = std::max(dmax, d);
+  if (one_round) {
+    if (lo + lane <= last) {
+      const int32_t d = lane - seg_predict<T>(f, xr);
+      dmin = d;
+      dmax = d;
+    }
+  } else {
+    for (int64_t i = lo + lane; i <= last; i += kFitLanes) {
+      const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, X[i]);
+      dmin = std::min(dmin, d);
+      dmax = std::max(dmax, d);
+    }
   }
 #pragma unroll
   for (int o = kFitLanes / 2; o > 0; o >>= 1) {
