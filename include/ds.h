@@ -171,7 +171,8 @@ typedef struct ds_info_t {
   int64_t model_bytes;      /* bytes of the learned model (0 for other methods) */
   int64_t max_err;          /* learned: max position error over the keys */
   double mean_log2_window;  /* learned: mean log2 of the bounded-search window */
-  int64_t x_bytes;          /* bytes of the device copy of X (with padding) */
+  int64_t x_bytes;          /* bytes of the device copy of X (with padding; the learned
+                               method adds its array of every 64-byte block's first key) */
   int64_t rankcode_bytes;   /* bytes of the RANKCODE layout (0 if not built) */
   int64_t pairs_bytes;      /* bytes of the PAIRS layout (0 if not built) */
   double build_ms;          /* wall time of ds_build */

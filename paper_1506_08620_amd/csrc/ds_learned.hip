@@ -58,6 +58,8 @@ struct LearnedModel {
   int32_t* route = nullptr;     // segment of every key
   int32_t* first = nullptr;     // nseg + 1: first key of each segment
   SegFit* segs = nullptr;
+  void* samples = nullptr;      // S[j] = X_{E j} (single-array search)
+  int64_t nsamples = 0;
   unsigned long long* fallbacks = nullptr;
   int32_t nseg = 0;
   int32_t identity = 0;         // ablation: y = u
@@ -766,6 +768,7 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
 template <typename T>
 struct LearnedArgs {
   const T* X;
+  const T* S;  // samples X_{E j} (single-array search)
   const float* params;
   const SegFit* segs;
   unsigned long long* fallbacks;
@@ -801,44 +804,75 @@ __device__ __forceinline__ void search_round(T z, const T* __restrict__ X, int32
   }
 }
 
-// Values of X after X_N that the search may read (+inf): the block scan below
-// reads up to two 64-byte blocks from the block of a window's first index.
+// Values of X after X_N that the search may read (+inf): the block read by
+// the sample search can start at the block after the last one of X_N's.
 constexpr int64_t kLearnScanPad = 32;
 
 template <typename T>
 using vec16b = T __attribute__((ext_vector_type(16 / sizeof(T))));
 
-// The end of the search of a window [L, L + n - 1], n <= E = 64 / sizeof(T)
-// values: instead of log2(n) more dependent probes, read the 64-byte block of
-// L (and the next one when the window, or the value after it, reaches it)
-// with independent 16-byte loads and count the values <= z.  With c such
-// values from the block start b0, X_{b0+c-1} <= z < X_{b0+c} has been read
-// whenever 1 <= c <= (values read) - 1: the index is then certain, whatever
-// the model predicted.  *certified tells whether that holds.
+// The end of the search of a window [L, U] of a single array, through its
+// sample array S (S[j] = X_{E j}, E = 64 / sizeof(T) keys per 64-byte block of
+// X, +inf past the end): the samples jL + 1 .. jU + 1 of the window's blocks
+// (one or two 64-byte lines of S, which stays in L2: N bytes in f64) give the
+// block js of the answer, whose E values are then read as one line and
+// counted.  Instead of the dependent probes of a bisection into X and one or
+// two lines of X, a query reads one line of S and one line of X.  With c2
+// values <= z in block js, X_{E js + c2 - 1} <= z < X_{E js + c2} has been
+// read when 1 <= c2 <= E - 1, or when c2 = E and the sample js + 1 was read;
+// *certified tells whether that holds, whatever the model predicted.
 template <typename T>
-__device__ __forceinline__ int32_t scan_window(T z, int32_t L, int32_t n, const T* __restrict__ X, bool* certified) {
-  constexpr int E = 64 / int(sizeof(T));
+__device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, const T* __restrict__ X,
+                                                 const T* __restrict__ S, bool* certified) {
+  constexpr int E = 64 / int(sizeof(T));   // keys per 64-byte block of X
+  constexpr int SE = 64 / int(sizeof(T));  // samples per 64-byte line of S
   constexpr int V = 16 / int(sizeof(T));
-  const int32_t b0 = L & ~(E - 1);
-  const bool two = L + n >= b0 + E;
-  int32_t c = 0;
-  const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(X + b0);
+  int32_t jL = L / E, jU = U / E;
+  // narrow by bisection on the samples until jL + 1 .. jU + 1 lies in the two
+  // lines of S from the line of jL + 1 (only for windows of dozens of blocks)
+  while (jU + 1 > ((jL + 1) & ~(SE - 1)) + 2 * SE - 1) {
+    const int32_t m = jL + ((jU - jL + 1) >> 1);
+    const bool c = S[m] <= z;
+    jL = c ? m : jL;
+    jU = c ? jU : m - 1;
+  }
+  const int32_t s0 = (jL + 1) & ~(SE - 1);
+  const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
+  int32_t c1 = 0;
 #pragma unroll
-  for (int v = 0; v < E / V; ++v) {
+  for (int v = 0; v < SE / V; ++v) {
     const vec16b<T> x = p[v];
 #pragma unroll
-    for (int e = 0; e < V; ++e) c += (x[e] <= z) ? 1 : 0;
+    for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
   }
-  if (two) {
+  if (jU + 1 >= s0 + SE) {
 #pragma unroll
-    for (int v = E / V; v < 2 * E / V; ++v) {
+    for (int v = SE / V; v < 2 * SE / V; ++v) {
       const vec16b<T> x = p[v];
 #pragma unroll
-      for (int e = 0; e < V; ++e) c += (x[e] <= z) ? 1 : 0;
+      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
     }
   }
-  *certified = c >= 1 && c <= (two ? 2 * E : E) - 1;
-  return b0 + c - 1;
+  const int32_t js = jL + c1;
+  const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(X + int64_t(js) * E);
+  int32_t c2 = 0;
+#pragma unroll
+  for (int v = 0; v < E / V; ++v) {
+    const vec16b<T> x = q[v];
+#pragma unroll
+    for (int e = 0; e < V; ++e) c2 += (x[e] <= z) ? 1 : 0;
+  }
+  *certified = c2 >= 1 && (c2 <= E - 1 || js <= jU);
+  return js * E + c2 - 1;
+}
+
+// Samples of the single-array search: S[j] = X_{E j} for E j < nX (X padded
+// with +inf), +inf beyond.
+template <typename T>
+__global__ void samples_kernel(const T* __restrict__ X, int64_t nX, T* __restrict__ S, int64_t nS) {
+  constexpr int E = 64 / int(sizeof(T));
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nS) S[j] = (j * E < nX) ? X[j * E] : std::numeric_limits<T>::infinity();
 }
 
 // The block scan of scan_window for an array that sits inside a packed buffer
@@ -916,7 +950,6 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
   else
     load_router(a.params, R);
   __syncthreads();
-  constexpr int32_t E = 64 / int32_t(sizeof(T));
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -937,10 +970,8 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
     const float y = a.identity ? u : route_coord(y_net, u);
     int32_t L, U;
     query_window<T>(z, y, a, segs, &L, &U);
-    int32_t n = U - L + 1;
-    while (n > E) search_round<T>(z, a.X, L, n);
     bool certified;
-    int32_t i = scan_window<T>(z, L, n, a.X, &certified);
+    int32_t i = sample_search<T>(z, L, U, a.X, a.S, &certified);
     if ((z >= a.X0) && (z < a.XN) && !certified) i = full_search_counted<T>(z, a.X, a.N, a.fallbacks);
     i = (z >= a.XN) ? a.N : i;
     i = (z >= a.X0) ? i : -1;
@@ -979,6 +1010,15 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
     (void)hipFree(h->X);
     h->X = Xp;
     h->nX = n + kLearnScanPad;
+  }
+  {
+    // samples of every 64-byte block of X, plus two 64-byte lines of +inf
+    constexpr int64_t E = 64 / int64_t(sizeof(T));
+    L->nsamples = ((h->nX + E - 1) / E + 2 * E + E - 1) / E * E;
+    if (hipMalloc(&L->samples, size_t(L->nsamples) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
+    samples_kernel<T><<<dim3((unsigned)((L->nsamples + 255) / 256)), dim3(256), 0, s>>>(
+        static_cast<const T*>(h->X), h->nX, static_cast<T*>(L->samples), L->nsamples);
+    DS_HIP_CHECK(hipGetLastError());
   }
   const T* X = static_cast<const T*>(h->X);
   T ends[2];
@@ -1113,6 +1153,7 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   LearnedModel* L = h->learned;
   LearnedArgs<T> a{};
   a.X = static_cast<const T*>(h->X);
+  a.S = static_cast<const T*>(L->samples);
   a.params = L->params;
   a.segs = L->segs;
   a.fallbacks = L->fallbacks;
@@ -1162,7 +1203,7 @@ void learned_free(ds_index* h) {
   for (void* p : {static_cast<void*>(L->params), static_cast<void*>(L->adam_m), static_cast<void*>(L->adam_v),
                   static_cast<void*>(L->partial), static_cast<void*>(L->loss_partial), static_cast<void*>(L->feat),
                   static_cast<void*>(L->route), static_cast<void*>(L->first), static_cast<void*>(L->segs),
-                  static_cast<void*>(L->fallbacks)})
+                  static_cast<void*>(L->samples), static_cast<void*>(L->fallbacks)})
     if (p) (void)hipFree(p);
   delete L;
   h->learned = nullptr;
@@ -1400,6 +1441,7 @@ void learned_fill_info(const ds_index* h, ds_info_t* in) {
   const LearnedModel* L = h->learned;
   if (!L) return;
   in->model_bytes = int64_t(kParams) * 4 + int64_t(L->nseg) * int64_t(sizeof(SegFit));
+  in->x_bytes += L->nsamples * int64_t(h->dt == DS_F32 ? 4 : 8);  // the search's sample array
   in->max_err = L->max_err;
   in->mean_log2_window = L->mean_log2_window;
 }

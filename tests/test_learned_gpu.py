@@ -115,6 +115,24 @@ def test_learned_exact_on_clustered_arrays(ds, dt):
             assert inf["model_bytes"] == 1153 * 4 + segs * 32
 
 
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_learned_wide_windows_and_array_ends(ds, dt):
+    """Few segments over many keys give windows of thousands of keys (the search narrows them by
+    bisection on the samples of X's 64-byte blocks before reading one block); sizes around a
+    block multiple put the last window at the padded end of X."""
+    rng = np.random.default_rng(17)
+    for n, segs in ((200_000, 4), (200_000, 16), (8 * 1024 - 1, 64), (8 * 1024, 64), (16 * 1024 + 1, 64)):
+        X = _clustered(n, dt, n)
+        z = _queries(X, 50_000, rng)
+        ref = oracle.search(X, z)
+        for epochs in (5, -1):
+            idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=segs, seed=5)
+            _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
+            _, fb = idx.learned_model()
+            assert fb == 0
+            idx.destroy()
+
+
 def test_uniform_gaps_give_tight_windows(ds):
     """Closed form: X_i = i has a linear CDF, so every segment's fit is exact up to
     rounding and every window holds at most three candidates."""
