@@ -74,6 +74,7 @@ struct BatchLearned {
   int32_t* first;          // [K][nseg + 1]
   float* feat;             // [total_x]
   int32_t* route;          // [total_x]
+  void* samples;           // first value of every 64-byte block of X, then +inf
 };
 
 // implemented in ds_learned.hip

@@ -791,18 +791,6 @@ __device__ __forceinline__ void query_window(T z, float y, const LearnedArgs<T>&
   *U = std::min(std::max(*L, sg.lo + q + sg.dmax), sg.hi);
 }
 
-// One branch-free bisection step for the largest i in [L, L+n-1] with
-// X_i <= z (the path is bound by the issue rate of random gathers, so one
-// probe per step).  Accepted probes prove X_m <= z and rejected ones z < X_m.
-template <typename T>
-__device__ __forceinline__ void search_round(T z, const T* __restrict__ X, int32_t& L, int32_t& n) {
-  if (n > 1) {
-    const int32_t h = n >> 1;
-    const bool c = z >= X[L + h];
-    L = c ? L + h : L;
-    n = c ? n - h : h;
-  }
-}
 
 // Values of X after X_N that the search may read (+inf): the block read by
 // the sample search can start at the block after the last one of X_N's.
@@ -875,46 +863,73 @@ __global__ void samples_kernel(const T* __restrict__ X, int64_t nX, T* __restric
   if (j < nS) S[j] = (j * E < nX) ? X[j * E] : std::numeric_limits<T>::infinity();
 }
 
-// The block scan of scan_window for an array that sits inside a packed buffer
-// Xp of total_x values, starting at x_off, with no padding after X_N: the
-// blocks are 64-byte aligned in memory (the array itself need not be), and
-// values outside the array's [0, N] are masked by their index.  Blocks that
-// would start before Xp or end past its last value are read value by value,
-// inside the array only.  Certification as in scan_window, over the array's
-// values that were read.
+// The sample search for an array inside a packed buffer Xp of total_x values
+// (array values at x_off .. x_off + N, no padding between arrays): blocks and
+// samples are those of the whole buffer, S[J] = Xp[E J], and only samples
+// whose value belongs to the array are counted (blocks after the first one of
+// the array, up to the block holding X_N); the answer's block is scanned with
+// the values outside the array masked, read value by value where the buffer is
+// not 16-byte aligned or the block passes its end.  Certification as in
+// sample_search, over the array's own values.
 template <typename T>
-__device__ __forceinline__ int32_t scan_window_packed(T z, int32_t L, int32_t n, const T* __restrict__ Xp,
-                                                      int64_t x_off, int32_t N, int64_t total_x, bool* certified) {
+__device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t U, const T* __restrict__ Xp,
+                                                        const T* __restrict__ S, int64_t x_off, int32_t N,
+                                                        int64_t total_x, bool* certified) {
   constexpr int E = 64 / int(sizeof(T));
+  constexpr int SE = 64 / int(sizeof(T));
   constexpr int V = 16 / int(sizeof(T));
-  const T* Xa = Xp + x_off;
-  const T* blk = reinterpret_cast<const T*>(reinterpret_cast<uintptr_t>(Xa + L) & ~uintptr_t(63));
-  const int32_t k0 = static_cast<int32_t>(blk - Xa);  // array index of the block's first value, > L - E
-  const bool two = L + n >= k0 + E;                   // values L .. L + n reach the next block
-  const int32_t e_lo = std::max(0, -k0);              // positions e_lo .. e_hi of the block(s) are in the array
-  const int32_t e_hi = std::min((two ? 2 * E : E) - 1, N - k0);
-  int32_t c = 0;
-  if (blk >= Xp && blk + (two ? 2 * E : E) <= Xp + total_x) {
-    const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(blk);
+  const int64_t jlast = (x_off + N) / E;  // block holding X_N
+  int64_t jL = (x_off + L) / E, jU = (x_off + U) / E;
+  while (jU + 1 > ((jL + 1) & ~int64_t(SE - 1)) + 2 * SE - 1) {
+    const int64_t m = jL + ((jU - jL + 1) >> 1);  // jL < m <= jU: S[m] is a value of the array
+    const bool c = S[m] <= z;
+    jL = c ? m : jL;
+    jU = c ? jU : m - 1;
+  }
+  const int64_t jt = std::min(jU + 1, jlast);  // samples jL + 1 .. jt are counted
+  const int64_t s0 = (jL + 1) & ~int64_t(SE - 1);
+  const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
+  int32_t c1 = 0;
 #pragma unroll
-    for (int v = 0; v < E / V; ++v) {
+  for (int v = 0; v < SE / V; ++v) {
+    const vec16b<T> x = p[v];
+#pragma unroll
+    for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jt && x[e] <= z) ? 1 : 0;
+  }
+  if (jt >= s0 + SE) {
+#pragma unroll
+    for (int v = SE / V; v < 2 * SE / V; ++v) {
       const vec16b<T> x = p[v];
 #pragma unroll
-      for (int e = 0; e < V; ++e) c += (v * V + e >= e_lo && v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
+      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jt && x[e] <= z) ? 1 : 0;
     }
-    if (two) {
+  }
+  const int64_t js = jL + c1;
+  const int64_t k0 = js * E;  // buffer index of the block's first value
+  const int32_t e_lo = static_cast<int32_t>(std::max<int64_t>(0, x_off - k0));
+  const int32_t e_hi = static_cast<int32_t>(std::min<int64_t>(E - 1, x_off + N - k0));
+  int32_t c2 = 0;
+  if ((reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && k0 + E <= total_x) {
+    const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(Xp + k0);
 #pragma unroll
-      for (int v = E / V; v < 2 * E / V; ++v) {
-        const vec16b<T> x = p[v];
+    for (int v = 0; v < E / V; ++v) {
+      const vec16b<T> x = q[v];
 #pragma unroll
-        for (int e = 0; e < V; ++e) c += (v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
-      }
+      for (int e = 0; e < V; ++e) c2 += (v * V + e >= e_lo && v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
     }
   } else {
-    for (int32_t e = e_lo; e <= e_hi; ++e) c += (Xa[k0 + e] <= z) ? 1 : 0;
+    for (int32_t e = e_lo; e <= e_hi; ++e) c2 += (Xp[k0 + e] <= z) ? 1 : 0;
   }
-  *certified = c >= 1 && c <= e_hi - e_lo;
-  return k0 + e_lo + c - 1;
+  *certified = c2 >= 1 && (c2 <= e_hi - e_lo || js + 1 <= jt);
+  return static_cast<int32_t>(k0 + e_lo + c2 - 1 - x_off);
+}
+
+// Samples of the packed buffer: S[J] = Xp[E J] for E J < total_x, +inf beyond.
+template <typename T>
+__global__ void batch_samples_kernel(const T* __restrict__ Xp, int64_t total_x, T* __restrict__ S, int64_t nS) {
+  constexpr int E = 64 / int(sizeof(T));
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nS; j += (int64_t)gridDim.x * blockDim.x)
+    S[j] = (j * E < total_x) ? Xp[j * E] : std::numeric_limits<T>::infinity();
 }
 
 // Index of z by the classic binary search over the whole array, for a query
@@ -1271,7 +1286,6 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
   __shared__ RouterShared16 S;  // FP16 router: half-wave-uniform values
   half4 w2[4];
   RouterRegs R;
-  constexpr int32_t E = 64 / int32_t(sizeof(T));
   int32_t cur = -1;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -1362,10 +1376,9 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
       const float y = route_coord(y_net, u);
       int32_t L, U;
       query_window<T>(zq, y, a, segs, &L, &U);
-      int32_t n = U - L + 1;
-      while (n > E) search_round<T>(zq, a.X, L, n);
       bool certified;
-      int32_t i = scan_window_packed<T>(zq, L, n, static_cast<const T*>(b.X), m.x_off, a.N, b.total_x, &certified);
+      int32_t i = sample_search_packed<T>(zq, L, U, static_cast<const T*>(b.X), static_cast<const T*>(b.samples),
+                                          m.x_off, a.N, b.total_x, &certified);
       if ((zq >= a.X0) && (zq < a.XN) && !certified) i = full_search_counted<T>(zq, a.X, a.N, a.fallbacks);
       i = (zq >= a.XN) ? a.N : i;
       i = (zq >= a.X0) ? i : -1;
@@ -1380,6 +1393,12 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
 template <typename T>
 ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
   const int K = b.K;
+  {
+    constexpr int64_t E = 64 / int64_t(sizeof(T));
+    const int64_t nS = (b.total_x + E - 1) / E + 2 * E;  // fits the workspace's total_x + 512 bytes
+    batch_samples_kernel<T><<<dim3(1024), dim3(256), 0, s>>>(static_cast<const T*>(b.X), b.total_x,
+                                                             static_cast<T*>(b.samples), nS);
+  }
   init_params_kernel<<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, b.tot, b.seed);
   feature_kernel<T><<<dim3(64, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, 0, 0, 0, 0, b.feat, b.lmeta,
                                                        b.tot);
