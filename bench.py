@@ -146,11 +146,14 @@ def main():
     wall = time.perf_counter() - t0
 
     # per-launch kernel times with HIP events on the launch stream (separate pass)
+    # (steps back to back, as in the timed region, so that no case starts on an idle GPU)
     per = [[0.0, 0] for _ in cases]
-    for _ in range(args.steps):
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
+           for _ in range(args.steps)]
+    for ev in evs:
         step(ev)
-        torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    for ev in evs:
         for k, (a, b) in enumerate(ev):
             per[k][0] += a.elapsed_time(b)
             per[k][1] += 1
