@@ -149,8 +149,9 @@ typedef struct ds_build_opts {
  *             7 bins of the position of the cell's X_i and the first-of-class
  *             flag), so one 16-byte gather gives K_j and decides the
  *             compare-and-fix except on a bin tie.  5.33 bits per cell: the
- *             layout of N = 2^21 (about 4.2M cells) is 2.8 MB.  Read through
- *             L2 (stage 6); the automatic choice above the LDS layouts. */
+ *             layout of N = 2^21 (about 4.2M cells) is 2.8 MB.  Staged in
+ *             LDS (stage 7) while its chunks fit, for N up to about 120,000
+ *             above RANKCODE's limit; read through L2 (stage 6) beyond. */
 #define DS_LAYOUT_RANKCODE 1
 #define DS_LAYOUT_PAIRS 2
 #define DS_LAYOUT_NIBBLE 4
@@ -190,7 +191,8 @@ typedef struct ds_tune {
   int32_t unroll;           /* 16-byte query vectors per thread per iteration: 1, 2 or 4; 0 = auto */
   int32_t stage;            /* 0 = auto; Direct: 1 = PLAIN in LDS, 2 = PLAIN through L2,
                                3 = RANKCODE in LDS, 4 = PAIRS through L2,
-                               5 = RANKCODE through L2, 6 = NIBBLE through L2; binary
+                               5 = RANKCODE through L2, 6 = NIBBLE through L2,
+                               7 = NIBBLE in LDS; binary
                                search: 1 = X in LDS, 2 = X through L2; Eytzinger: 1 = top
                                levels in LDS, 2 = every level through L2 */
   int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */

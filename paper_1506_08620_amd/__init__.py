@@ -35,6 +35,7 @@ FALLBACK_NONE, FALLBACK_BSEARCH, FALLBACK_LEARNED = range(3)
 LAYOUT_RANKCODE, LAYOUT_PAIRS, LAYOUT_NIBBLE = 1, 2, 4
 # ds_tune.stage values of the Direct method
 STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2, STAGE_RANKCODE_L2, STAGE_NIBBLE_L2 = 1, 2, 3, 4, 5, 6
+STAGE_NIBBLE_LDS = 7
 _LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS, "nibble": LAYOUT_NIBBLE}
 
 _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset": METHOD_BSEARCH_OFFSET,

@@ -12,7 +12,9 @@
 //   * ds_get_view / ds_view_search  the tables as a plain view, searched by a
 //                       kernel built on ds_device.h alone.
 // The fused kernels use the layout the automatic search uses (PLAIN or
-// RANKCODE in LDS, NIBBLE through L2) through the same per-query operators.
+// RANKCODE in LDS, NIBBLE through L2) through the same per-query operators;
+// where the search stages NIBBLE in LDS they read it through L2, which leaves
+// the LDS to the histogram's bins.
 #include <algorithm>
 #include <mutex>
 
@@ -262,7 +264,8 @@ ds_status interp_stage(const ds_index* h, const DirectArgs<T>& a, bool vec, cons
   return DS_OK;
 }
 
-// the automatic layout of a Direct handle: 1 (PLAIN in LDS), 3 (RANKCODE in LDS) or 6 (NIBBLE)
+// the automatic layout of a Direct handle: 1 (PLAIN in LDS), 3 (RANKCODE in LDS) or 6 and 7 (NIBBLE,
+// read through L2)
 template <typename T, int FORM>
 ds_status hist_typed(const ds_index* h, const DirectArgs<T>& a, bool vec, uint64_t* counts, hipStream_t s) {
   switch (h->auto_stage) {
@@ -284,7 +287,8 @@ ds_status interp_typed(const ds_index* h, const DirectArgs<T>& a, bool vec, cons
 ds_status check_direct(ds_handle h) {
   if (!h) return DS_ERR_ARG;
   if (h->method != DS_METHOD_DIRECT) return DS_ERR_UNSUPPORTED;
-  const bool built = (h->auto_stage == 1) || (h->auto_stage == 3 && h->rc_code) || (h->auto_stage == 6 && h->nib);
+  const bool built = (h->auto_stage == 1) || (h->auto_stage == 3 && h->rc_code) ||
+                     ((h->auto_stage == 6 || h->auto_stage == 7) && h->nib);
   if (!built) return DS_ERR_UNSUPPORTED;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return DS_ERR_HIP;

@@ -449,7 +449,7 @@ ds_status build_rankcode(ds_index* h, hipStream_t s) {
 
 template <typename T, int FORM>
 ds_status build_nibble(ds_index* h, hipStream_t s) {
-  const int64_t n = (h->nK + kNibCells - 1) / kNibCells;
+  const int64_t n = nibble_chunks(h->nK);
   if (hipMalloc(&h->nib, size_t(n) * sizeof(NibChunk)) != hipSuccess) {
     h->nib = nullptr;
     return DS_ERR_OOM;
@@ -474,19 +474,21 @@ ds_status build_pairs(ds_index* h, hipStream_t s) {
 }
 
 // Which layouts to build: the one the automatic launch will use (PLAIN in LDS
-// when it fits, else RANKCODE in LDS when it fits, else NIBBLE through L2: one
-// cache line of table per query, against about 1.5 for RANKCODE through L2
-// and 2 for PAIRS), plus whatever the caller asked for.
+// when it fits, else RANKCODE in LDS when it fits, else NIBBLE in LDS when its
+// chunks fit, else NIBBLE through L2: one cache line of table per query,
+// against about 1.5 for RANKCODE through L2 and 2 for PAIRS), plus whatever
+// the caller asked for.
 template <typename T>
 ds_status build_layouts(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   h->staged = tables_fit_lds(h) ? 1 : 0;
   const int64_t nW = (h->nK + 63) / 64;
   h->rc_words = nW;
   const bool rc_fits = rankcode_lds_bytes(h) <= kLdsBytesPerCU;
-  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : 6);
+  const bool nib_fits = nibble_chunks(h->nK) * int64_t(sizeof(NibChunk)) <= kLdsBytesPerCU;
+  h->auto_stage = h->staged ? 1 : (rc_fits ? 3 : (nib_fits ? 7 : 6));
   const bool want_rc = (o.extra_layouts & DS_LAYOUT_RANKCODE) || h->auto_stage == 3 || h->auto_stage == 5;
   const bool want_pairs = (o.extra_layouts & DS_LAYOUT_PAIRS) || h->auto_stage == 4;
-  const bool want_nib = (o.extra_layouts & DS_LAYOUT_NIBBLE) || h->auto_stage == 6;
+  const bool want_nib = (o.extra_layouts & DS_LAYOUT_NIBBLE) || h->auto_stage == 6 || h->auto_stage == 7;
   if (want_nib) {
     ds_status st = (h->form == DS_FORM_FMA) ? build_nibble<T, DS_FORM_FMA>(h, s) : build_nibble<T, DS_FORM_SUB>(h, s);
     if (st != DS_OK) return st;

@@ -123,6 +123,8 @@ struct alignas(16) RcWord {
 // the position of its X_i inside the cell (NibCode).  The rank of a cell is
 // base plus the nonzero nibbles before it.
 constexpr int kNibCells = 24;
+// chunks of the NIBBLE layout for nK grid cells
+__host__ __device__ constexpr int64_t nibble_chunks(int64_t nK) { return (nK + kNibCells - 1) / kNibCells; }
 struct alignas(16) NibChunk {
   uint32_t nib[3];
   uint32_t base;
@@ -172,6 +174,7 @@ struct DirectArgs {
   const CachePair<T>* pairs; // nK pairs, pairs[0] for cell jmin
   // NIBBLE layout
   const NibChunk* nib;       // ceil(nK / 24) chunks, chunk 0 starts at cell jmin
+  int64_t nib_chunks;
   const T* z;
   int32_t* out;
   int64_t M;

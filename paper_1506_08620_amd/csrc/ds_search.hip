@@ -22,7 +22,8 @@ namespace {
 
 
 // STAGE 1: PLAIN in LDS; 2: PLAIN through L1/L2; 3: RANKCODE in LDS;
-// 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2; 6: NIBBLE through L1/L2.
+// 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2; 6: NIBBLE through L1/L2;
+// 7: NIBBLE in LDS.
 template <typename T, int FORM, int STAGE, int U, bool VEC>
 __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -57,8 +58,14 @@ __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
     RankCodeOp<T, FORM, true, uint8_t> op{nullptr, nullptr, a.rc_w16, a.rc_code8, a.X, a.H, a.W, a.X0, a.vlo, a.vhi,
                                           a.XN, a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
-  } else if constexpr (STAGE == 6) {
-    NibbleOp<T, FORM> op{a.nib, a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
+  } else if constexpr (STAGE == 6 || STAGE == 7) {
+    const NibChunk* nib = a.nib;
+    if constexpr (STAGE == 7) {
+      stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.nib), a.nib_chunks * int64_t(sizeof(NibChunk)));
+      __syncthreads();
+      nib = reinterpret_cast<const NibChunk*>(smem);
+    }
+    NibbleOp<T, FORM> op{nib, a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else {
     PairsOp<T, FORM> op{a.pairs - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
@@ -209,6 +216,7 @@ int64_t lds_bytes_needed(const ds_index* h, int stage) {
     int64_t b = 0, c = 0;
     return rankcode_offsets(h->rc_words, round16((h->N + 1) * 2), &b, &c);
   }
+  if (h->method == DS_METHOD_DIRECT && stage == 7) return nibble_chunks(h->nK) * int64_t(sizeof(NibChunk));
   if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) return round16(h->nX * s) + h->nK * 4;
   if (h->method == DS_METHOD_BSEARCH_LEADBIT || h->method == DS_METHOD_BSEARCH_OFFSET) return round16(h->nX * s);
   return int64_t(1) << 40;
@@ -246,6 +254,10 @@ void default_shape(const ds_index* h, int stage, int* block, int* unroll) {
     case 4: *block = f32 ? 256 : 1024; *unroll = f32 ? 4 : 1; return;
     case 5: *block = 512; *unroll = 2; return;
     case 6: *block = 512; *unroll = 2; return;
+    case 7:  // two workgroups per CU when the chunks take at most half the LDS
+      *block = 1024;
+      *unroll = lds_bytes_needed(h, 7) > kLdsBytesPerCU / 2 ? 2 : 1;
+      return;
     default: *block = 512; *unroll = 2; return;
   }
 }
@@ -312,6 +324,9 @@ ds_status dispatch_direct(const DirectArgs<T>& a, const Shape& sh, bool vec, int
     case 6:
       return vec ? dispatch_direct_u<T, FORM, 6, true>(a, sh, 0, items, s)
                  : dispatch_direct_u<T, FORM, 6, false>(a, sh, 0, items, s);
+    case 7:
+      return vec ? dispatch_direct_u<T, FORM, 7, true>(a, sh, lds, items, s)
+                 : dispatch_direct_u<T, FORM, 7, false>(a, sh, lds, items, s);
     default:
       return vec ? dispatch_direct_u<T, FORM, 2, true>(a, sh, 0, items, s)
                  : dispatch_direct_u<T, FORM, 2, false>(a, sh, 0, items, s);
@@ -393,7 +408,7 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
   const Shape sh = pick_shape(h, M);
   const bool vec = ((reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T))) == 0) &&
                    ((reinterpret_cast<uintptr_t>(out) % 16) == 0);
-  const int lds = (sh.stage == 1 || sh.stage == 3) ? static_cast<int>(lds_bytes_needed(h, sh.stage)) : 0;
+  const int lds = (sh.stage == 1 || sh.stage == 3 || sh.stage == 7) ? static_cast<int>(lds_bytes_needed(h, sh.stage)) : 0;
   if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) {
     DirectArgs<T> a{};
     a.X = static_cast<const T*>(h->X);
@@ -416,6 +431,7 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
     a.nW = static_cast<int32_t>(h->rc_words);
     a.pairs = static_cast<const CachePair<T>*>(h->pairs);
     a.nib = h->nib;
+    a.nib_chunks = h->nib_chunks;
     a.gap_q = h->gap_q;
     a.x_off = h->x_off;
     a.z = static_cast<const T*>(z);
@@ -482,13 +498,14 @@ ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_de
   if (!h || !z_dev || !out_dev || M <= 0) return DS_ERR_ARG;
   if (h->method == DS_METHOD_LEARNED) return DS_ERR_UNSUPPORTED;
   const int64_t m = std::min<int64_t>(M, int64_t(1) << 24);
-  int stages[6];
+  int stages[7];
   int n_stages = 0;
   if (h->method == DS_METHOD_DIRECT) {
     if (h->staged) stages[n_stages++] = 1;
     if (h->rc_code && ds::rankcode_lds_bytes(h) <= ds::kLdsBytesPerCU) stages[n_stages++] = 3;
     if (h->rc_w16) stages[n_stages++] = 5;
     if (h->nib) stages[n_stages++] = 6;
+    if (h->nib && ds::direct_lds_bytes(h, 7) <= ds::kLdsBytesPerCU) stages[n_stages++] = 7;
     if (h->pairs) stages[n_stages++] = 4;
     stages[n_stages++] = 2;
   } else {
@@ -547,8 +564,9 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   }
   if (t->block != 0 && (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)) return DS_ERR_ARG;
   if (t->unroll != 0 && t->unroll != 1 && t->unroll != 2 && t->unroll != 4) return DS_ERR_ARG;
-  if (t->stage < 0 || t->stage > 6) return DS_ERR_ARG;
-  if (t->stage == 6 && !h->nib) return DS_ERR_ARG;
+  if (t->stage < 0 || t->stage > 7) return DS_ERR_ARG;
+  if ((t->stage == 6 || t->stage == 7) && !h->nib) return DS_ERR_ARG;
+  if (t->stage == 7 && ds::direct_lds_bytes(h, 7) > ds::kLdsBytesPerCU) return DS_ERR_ARG;
   if (t->stage == 5 && (!h->rc_w16 || !h->rc_code8)) return DS_ERR_ARG;
   if (t->stage == 1 && !h->staged) return DS_ERR_ARG;
   if (t->stage >= 3 && h->method != DS_METHOD_DIRECT) return DS_ERR_ARG;

@@ -83,6 +83,33 @@ def test_sweep_tables_and_indices(ds, dtype, n, form):
     _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_mid_sizes_nibble_in_lds(ds, dtype):
+    """Between RANKCODE's LDS limit (about 65,000 keys) and NIBBLE's (about 120,000) the automatic
+    layout stages the NIBBLE chunks in LDS (stage 7); beyond, they are read through L2 (stage 6).
+    Every layout, both forms and the fused histogram agree with the oracle."""
+    from oracle import apps
+
+    for n, want in ((70_000, 7), (100_000, 7), (120_000, 7), (131_000, 6)):
+        X = W.sweep_array(n, dtype)
+        z = W.sweep_queries((1 << 19) + 5, dtype, stream=3)
+        z = np.concatenate([z, X[:-1], W.prev_float(X[1:], dtype), np.nextafter(X, np.dtype(dtype).type(2))])
+        ref = oracle.search(X, z)
+        for form in ("sub", "fma"):
+            idx = ds.build(_dev(X), form=form, layouts=("nibble",))
+            inf = idx.info()
+            assert inf["staged"] == want, (n, inf["staged"], inf["nibble_bytes"], inf["rankcode_bytes"])
+            assert (inf["nibble_bytes"] <= 160 * 1024) == (want == 7)
+            z_d = _dev(z)
+            _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
+            for stage in _stages(idx):
+                idx.set_tune(stage=stage)
+                _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
+            idx.clear_tune()
+            _assert_same(idx.histogram(z_d).cpu().numpy(), apps.histogram(X, z))
+            idx.destroy()
+
+
 def _invariant_on_device(X_d, z_d, out_d):
     """X_i <= z < X_{i+1} for every query (all queries in [X_0, X_N))."""
     n = X_d.numel() - 1
@@ -141,6 +168,8 @@ def _stages(idx):
         st.append(5)
     if inf["nibble_bytes"]:
         st.append(6)
+    if inf["nibble_bytes"] and inf["nibble_bytes"] <= 160 * 1024:
+        st.append(7)
     return tuple(sorted(st))
 
 
