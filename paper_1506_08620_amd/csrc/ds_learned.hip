@@ -805,7 +805,9 @@ using vec16b = T __attribute__((ext_vector_type(16 / sizeof(T))));
 // (one or two 64-byte lines of S, which stays in L2: N bytes in f64) give the
 // block js of the answer, whose E values are then read as one line and
 // counted.  Instead of the dependent probes of a bisection into X and one or
-// two lines of X, a query reads one line of S and one line of X.  With c2
+// two lines of X, a query reads one line of S and one line of X, and a window
+// inside one block reads that block alone (plus the next value when all of
+// the block's values are <= z).  With c2
 // values <= z in block js, X_{E js + c2 - 1} <= z < X_{E js + c2} has been
 // read when 1 <= c2 <= E - 1, or when c2 = E and the sample js + 1 was read;
 // *certified tells whether that holds, whatever the model predicted.
@@ -824,21 +826,25 @@ __device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, cons
     jL = c ? m : jL;
     jU = c ? jU : m - 1;
   }
-  const int32_t s0 = (jL + 1) & ~(SE - 1);
-  const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
+  // a window inside one block reads no samples: the block decides unless all
+  // of its values are <= z (then the next value, the first of the next block)
   int32_t c1 = 0;
+  if (jU > jL) {
+    const int32_t s0 = (jL + 1) & ~(SE - 1);
+    const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
 #pragma unroll
-  for (int v = 0; v < SE / V; ++v) {
-    const vec16b<T> x = p[v];
-#pragma unroll
-    for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
-  }
-  if (jU + 1 >= s0 + SE) {
-#pragma unroll
-    for (int v = SE / V; v < 2 * SE / V; ++v) {
+    for (int v = 0; v < SE / V; ++v) {
       const vec16b<T> x = p[v];
 #pragma unroll
-      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
+      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
+    }
+    if (jU + 1 >= s0 + SE) {
+#pragma unroll
+      for (int v = SE / V; v < 2 * SE / V; ++v) {
+        const vec16b<T> x = p[v];
+#pragma unroll
+        for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
+      }
     }
   }
   const int32_t js = jL + c1;
@@ -850,7 +856,9 @@ __device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, cons
 #pragma unroll
     for (int e = 0; e < V; ++e) c2 += (x[e] <= z) ? 1 : 0;
   }
-  *certified = c2 >= 1 && (c2 <= E - 1 || js <= jU);
+  bool upper = c2 <= E - 1 || (jU > jL && js <= jU);  // the value after the answer was read
+  if (c2 == E && jU == jL) upper = z < X[int64_t(js + 1) * E];
+  *certified = c2 >= 1 && upper;
   return js * E + c2 - 1;
 }
 
