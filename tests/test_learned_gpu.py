@@ -133,6 +133,22 @@ def test_learned_wide_windows_and_array_ends(ds, dt):
             idx.destroy()
 
 
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_learned_tiny_arrays(ds, dt):
+    """N from 1 to 33 (one block of X or a few; the padded tail of X and of the samples is read)."""
+    rng = np.random.default_rng(23)
+    for n in (1, 2, 3, 7, 8, 9, 15, 16, 17, 33):
+        X = W.gap_array(n, dt, rng, lo=0.1, hi=3.0, x0=rng.uniform(-5, 5))
+        z = _queries(X, 2000, rng)
+        ref = oracle.search(X, z)
+        for epochs in (3, -1):
+            idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=16, seed=2)
+            _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
+            _, fb = idx.learned_model()
+            assert fb == 0
+            idx.destroy()
+
+
 def test_uniform_gaps_give_tight_windows(ds):
     """Closed form: X_i = i has a linear CDF, so every segment's fit is exact up to
     rounding and every window holds at most three candidates."""
