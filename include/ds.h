@@ -151,7 +151,8 @@ typedef struct ds_build_opts {
  *             compare-and-fix except on a bin tie.  5.33 bits per cell: the
  *             layout of N = 2^21 (about 4.2M cells) is 2.8 MB.  Staged in
  *             LDS (stage 7) while its chunks fit, for N up to about 120,000
- *             above RANKCODE's limit; read through L2 (stage 6) beyond. */
+ *             above RANKCODE's limit; beyond, read through L2 with its first
+ *             156 KiB of chunks in each workgroup's LDS (stage 6). */
 #define DS_LAYOUT_RANKCODE 1
 #define DS_LAYOUT_PAIRS 2
 #define DS_LAYOUT_NIBBLE 4

@@ -123,6 +123,8 @@ struct alignas(16) RcWord {
 // the position of its X_i inside the cell (NibCode).  The rank of a cell is
 // base plus the nonzero nibbles before it.
 constexpr int kNibCells = 24;
+// NIBBLE chunks that a workgroup keeps in LDS when the layout is read through L2
+constexpr int64_t kNibPrefixChunks = (156 * 1024) / 16;
 // chunks of the NIBBLE layout for nK grid cells
 __host__ __device__ constexpr int64_t nibble_chunks(int64_t nK) { return (nK + kNibCells - 1) / kNibCells; }
 struct alignas(16) NibChunk {

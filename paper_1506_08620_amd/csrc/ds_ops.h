@@ -265,13 +265,18 @@ struct NibbleOp {
   const T* Xg;
   T H, W, X0, vlo, vhi, XN;
   int32_t jmin, N;
+  const uint4* pre = nullptr;  // the first n_pre chunks again, in LDS
+  uint32_t n_pre = 0;
   __device__ __forceinline__ Gathered gather(T z) const {
     const T v = grid_value<T, FORM>(z, H, W, X0);
     const T jf = std::floor(std::fmin(std::fmax(v, vlo), vhi));
     const uint32_t e = static_cast<uint32_t>(static_cast<int32_t>(jf) - jmin);
     const uint32_t k = e / kNibCells;
     Gathered g;
-    g.q = reinterpret_cast<const uint4*>(ch)[k];  // one dwordx4 gather
+    if (k < n_pre)
+      g.q = pre[k];  // an LDS read instead of an L2 access
+    else
+      g.q = reinterpret_cast<const uint4*>(ch)[k];  // one dwordx4 gather
     // the bin of z (clamped at 0 for z below X_0 and NaN, whose result is -1 anyway)
     const uint32_t bz = static_cast<uint32_t>(std::fmax(cell_bin(v, jf), T(0)));
     g.p = (e - k * kNibCells) | (bz << 5) | (z >= X0 ? 0u : kBelow);

@@ -59,13 +59,15 @@ __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
                                           a.XN, a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else if constexpr (STAGE == 6 || STAGE == 7) {
-    const NibChunk* nib = a.nib;
-    if constexpr (STAGE == 7) {
-      stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.nib), a.nib_chunks * int64_t(sizeof(NibChunk)));
-      __syncthreads();
-      nib = reinterpret_cast<const NibChunk*>(smem);
-    }
-    NibbleOp<T, FORM> op{nib, a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
+    // 7: every chunk in LDS; 6: the first kNibPrefixChunks in LDS, the rest
+    // through L2 (the L2's line rate bounds this layout, so every chunk served
+    // from LDS is an L2 access saved)
+    const int64_t n_pre = (STAGE == 7) ? a.nib_chunks : std::min<int64_t>(a.nib_chunks, kNibPrefixChunks);
+    stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.nib), n_pre * int64_t(sizeof(NibChunk)));
+    __syncthreads();
+    NibbleOp<T, FORM> op{a.nib, a.X, a.H, a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
+    op.pre = reinterpret_cast<const uint4*>(smem);
+    op.n_pre = static_cast<uint32_t>(n_pre);
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else {
     PairsOp<T, FORM> op{a.pairs - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi};
@@ -217,6 +219,8 @@ int64_t lds_bytes_needed(const ds_index* h, int stage) {
     return rankcode_offsets(h->rc_words, round16((h->N + 1) * 2), &b, &c);
   }
   if (h->method == DS_METHOD_DIRECT && stage == 7) return nibble_chunks(h->nK) * int64_t(sizeof(NibChunk));
+  if (h->method == DS_METHOD_DIRECT && stage == 6)
+    return std::min<int64_t>(nibble_chunks(h->nK), kNibPrefixChunks) * int64_t(sizeof(NibChunk));
   if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) return round16(h->nX * s) + h->nK * 4;
   if (h->method == DS_METHOD_BSEARCH_LEADBIT || h->method == DS_METHOD_BSEARCH_OFFSET) return round16(h->nX * s);
   return int64_t(1) << 40;
@@ -253,7 +257,7 @@ void default_shape(const ds_index* h, int stage, int* block, int* unroll) {
     }
     case 4: *block = f32 ? 256 : 1024; *unroll = f32 ? 4 : 1; return;
     case 5: *block = 512; *unroll = 2; return;
-    case 6: *block = 512; *unroll = 2; return;
+    case 6: *block = f32 ? 1024 : 512; *unroll = 2; return;  // one workgroup per CU (the LDS prefix)
     case 7:  // two workgroups per CU when the chunks take at most half the LDS
       *block = 1024;
       *unroll = lds_bytes_needed(h, 7) > kLdsBytesPerCU / 2 ? 2 : 1;
@@ -322,8 +326,8 @@ ds_status dispatch_direct(const DirectArgs<T>& a, const Shape& sh, bool vec, int
       return vec ? dispatch_direct_u<T, FORM, 5, true>(a, sh, 0, items, s)
                  : dispatch_direct_u<T, FORM, 5, false>(a, sh, 0, items, s);
     case 6:
-      return vec ? dispatch_direct_u<T, FORM, 6, true>(a, sh, 0, items, s)
-                 : dispatch_direct_u<T, FORM, 6, false>(a, sh, 0, items, s);
+      return vec ? dispatch_direct_u<T, FORM, 6, true>(a, sh, lds, items, s)
+                 : dispatch_direct_u<T, FORM, 6, false>(a, sh, lds, items, s);
     case 7:
       return vec ? dispatch_direct_u<T, FORM, 7, true>(a, sh, lds, items, s)
                  : dispatch_direct_u<T, FORM, 7, false>(a, sh, lds, items, s);
@@ -408,7 +412,9 @@ ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipS
   const Shape sh = pick_shape(h, M);
   const bool vec = ((reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T))) == 0) &&
                    ((reinterpret_cast<uintptr_t>(out) % 16) == 0);
-  const int lds = (sh.stage == 1 || sh.stage == 3 || sh.stage == 7) ? static_cast<int>(lds_bytes_needed(h, sh.stage)) : 0;
+  const int lds = (sh.stage == 1 || sh.stage == 3 || sh.stage == 6 || sh.stage == 7)
+                      ? static_cast<int>(lds_bytes_needed(h, sh.stage))
+                      : 0;
   if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) {
     DirectArgs<T> a{};
     a.X = static_cast<const T*>(h->X);
