@@ -475,9 +475,9 @@ ds_status build_pairs(ds_index* h, hipStream_t s) {
 
 // Which layouts to build: the one the automatic launch will use (PLAIN in LDS
 // when it fits, else RANKCODE in LDS when it fits, else NIBBLE in LDS when its
-// chunks fit, else NIBBLE through L2: one cache line of table per query,
-// against about 1.5 for RANKCODE through L2 and 2 for PAIRS), plus whatever
-// the caller asked for.
+// chunks fit, else NIBBLE through L2 with a prefix in LDS: one cache line of
+// table per query, against about 1.5 for RANKCODE through L2 and 2 for
+// PAIRS), plus whatever the caller asked for.
 template <typename T>
 ds_status build_layouts(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   h->staged = tables_fit_lds(h) ? 1 : 0;

@@ -7,7 +7,8 @@
 //     evict the tables from L2;
 //   * the tables (K and X for Direct, X for binary search) are copied into LDS
 //     by every workgroup when they fit in one workgroup's LDS (160 KiB),
-//     otherwise they are gathered through L1/L2;
+//     otherwise they are gathered through L1/L2 (the NIBBLE layout keeps its
+//     first 156 KiB in LDS even then);
 //   * the grid is persistent: as many workgroups as can be resident, each
 //     stepping through the query vectors with a grid-sized stride, so the LDS
 //     copy is paid once per workgroup.
@@ -22,8 +23,8 @@ namespace {
 
 
 // STAGE 1: PLAIN in LDS; 2: PLAIN through L1/L2; 3: RANKCODE in LDS;
-// 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2; 6: NIBBLE through L1/L2;
-// 7: NIBBLE in LDS.
+// 4: PAIRS through L1/L2; 5: RANKCODE through L1/L2; 6: NIBBLE through L1/L2
+// with its first chunks in LDS; 7: NIBBLE in LDS.
 template <typename T, int FORM, int STAGE, int U, bool VEC>
 __global__ void __launch_bounds__(1024) direct_search_kernel(DirectArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
