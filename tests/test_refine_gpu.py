@@ -72,6 +72,8 @@ def _stages(inf):
     for key, stage in (("pairs_bytes", 4), ("rankcode_bytes", 5), ("nibble_bytes", 6)):
         if inf[key]:
             st.append(stage)
+    if inf["nibble_bytes"] and inf["nibble_bytes"] <= 160 * 1024:
+        st.append(7)
     return st
 
 
