@@ -334,7 +334,7 @@ ds_status ds_learned_model(ds_handle h, float* params_host, int32_t capacity, ui
 
 /* ------------------------------------------------------------------------
  * Batched ragged search: K independent arrays, each with its own queries,
- * built and searched by a fixed sequence of four kernels with no host
+ * built and searched by a fixed sequence of kernels with no host
  * synchronisation and no allocation (capturable in a HIP graph).  Array k is
  * X_packed[x_off[k] .. x_off[k+1]) (N_k = x_off[k+1] - x_off[k] - 1 intervals)
  * and its queries are z_packed[q_off[k] .. q_off[k+1]); out_packed[q]

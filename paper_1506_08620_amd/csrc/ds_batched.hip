@@ -1,20 +1,23 @@
 // Batched ragged build + search: K independent arrays, each with its own
-// queries, handled by a fixed sequence of four kernels with no host
+// queries, handled by a fixed sequence of kernels with no host
 // synchronisation and no allocation, so the whole sequence can be captured in
 // a HIP graph and replayed.
 //
-//   1. build_hr    one workgroup per array: validation, minimum rounded gap,
-//                  and ComputeHR (Sec. 4.4.3) run entirely on the device: the
-//                  workgroup finds the first pair whose cells coincide, one
-//                  lane applies the growth steps of the sequential algorithm,
-//                  and the scan resumes after that pair; passes repeat until
-//                  one changes nothing.
+//   1. build       validation, minimum rounded gap and ComputeHR (Sec. 4.4.3)
+//                  entirely on the device: two passes over the packed keys in
+//                  fixed chunks (the minimum gap; the first pair whose cells
+//                  coincide at the starting H) with per-array atomics, then
+//                  one workgroup per array that needs growth applies the
+//                  growth steps of the sequential algorithm from that pair
+//                  and rescans until a pass changes nothing.
 //   2. plan        one workgroup: exclusive scans over the arrays of the table
 //                  words, codes and query tiles; arrays whose table would not
 //                  fit the workspace fall back to the offset binary search
 //                  (Sec. 3.3).  It also clears the tile queues.
-//   3. rankcode    one workgroup per Direct array: the RANKCODE layout (bitmap
-//                  of occupied cells, running counts, 16-bit position codes).
+//   3. rankcode    the RANKCODE layout of every Direct array (bitmap of
+//                  occupied cells, running counts, 16-bit position codes):
+//                  the occupancy words are cleared, then one pass over the
+//                  packed keys in the same chunks sets every key's entries.
 //   4. search      persistent workgroups pull query tiles from one queue per
 //                  XCD (tiles of an array go to the XCD that took its first
 //                  chunk, so that XCD's L2 holds the array's tables); when the
@@ -35,12 +38,11 @@ namespace ds {
 
 namespace {
 
-constexpr int kBuildBlock = 1024;
 constexpr int kPlanBlock = 1024;
 constexpr int kMaxGrowthRounds = 4096;
 
 struct WsLayout {
-  size_t meta, tile_off, totals, codes, bits, base, end;
+  size_t meta, chunk_first, tile_off, totals, codes, bits, base, end;
   // learned region (present when nseg > 0)
   size_t lmeta, params, adam_m, adam_v, partial, loss, segs, first, feat, route, samples;
   int64_t words_budget;
@@ -59,6 +61,7 @@ WsLayout ws_layout(int32_t K, int64_t total_x, int64_t words_budget, int32_t nse
     return at;
   };
   L.meta = take(size_t(K) * sizeof(ArrMeta<double>));
+  L.chunk_first = take(size_t((total_x + 4095) / 4096 + 1) * 4);
   L.tile_off = take(size_t(K + 1) * sizeof(int64_t));
   L.totals = take(sizeof(PlanTotals));
   L.codes_cap = total_x + int64_t(K) * 8 + 8;
@@ -102,7 +105,26 @@ __device__ __forceinline__ T next_up_dev(T x) {
 }
 
 // --------------------------------------------------------------------------
-// 1. per-array ComputeHR
+// 1. per-array ComputeHR (Sec. 4.4.2 - 4.4.3), in five launches.  The two
+//    passes over the keys run over the packed buffer in fixed chunks, so a
+//    2^20-key array is read by 256 workgroups at once instead of one:
+//   init       one thread per array: X_0, X_N, the accumulators, and the
+//              array of each chunk's first value
+//   gaps       one workgroup per 4096 packed values: validation flags and
+//              the minimum rounded gap of each array met, merged into the
+//              array's accumulators with atomics
+//   start      one thread per array: H = the float above 1 / min gap, W, and
+//              the start's feasibility
+//   first_bad  one workgroup per 4096 values: the first pair of each array
+//              whose cells coincide at the starting H (atomic minimum)
+//   finish     one workgroup per array: ComputeHR's growth from that pair
+//              on, for the arrays that have one; R, jmin, the table size
+constexpr int kScanBlock = 256;
+constexpr int64_t kScanChunk = 4096;  // packed values per scan workgroup (4096 is also the workspace's chunk size)
+constexpr int kScanSlots = 1024;      // arrays of a chunk accumulated in LDS before the global atomics
+constexpr int kFinishBlock = 256;
+constexpr int32_t kNoPair = 0x7fffffff;
+
 // R - jmin + 1 cells at this H exceed cap_cells (0 = no cap)
 template <typename T, int FORM>
 __device__ __forceinline__ bool over_cap(T H, T W, T X0, T XN, int64_t cap_cells) {
@@ -112,84 +134,324 @@ __device__ __forceinline__ bool over_cap(T H, T W, T X0, T XN, int64_t cap_cells
   return cells > cap_cells;
 }
 
-template <typename T, int FORM>
-__global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __restrict__ x_off,
+// bits of a float >= 0 as an unsigned integer of the same order (for atomicMin)
+__device__ __forceinline__ unsigned long long order_bits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ unsigned long long order_bits(double x) {
+  return static_cast<unsigned long long>(__double_as_longlong(x));
+}
+template <typename T>
+__device__ __forceinline__ T from_order_bits(unsigned long long b);
+template <>
+__device__ __forceinline__ float from_order_bits<float>(unsigned long long b) {
+  return __uint_as_float(static_cast<uint32_t>(b));
+}
+template <>
+__device__ __forceinline__ double from_order_bits<double>(unsigned long long b) {
+  return __longlong_as_double(static_cast<long long>(b));
+}
+
+// the array holding packed value g: the largest k in [lo, hi) with
+// x_off[k] <= g, given x_off[lo] <= g < x_off[hi] (empty arrays are skipped)
+__device__ __forceinline__ int32_t array_of(const int64_t* __restrict__ x_off, int32_t lo, int32_t hi, int64_t g) {
+  while (hi - lo > 1) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (x_off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kScanBlock) init_meta_kernel(const int64_t* __restrict__ x_off,
                                                                const int64_t* __restrict__ q_off,
-                                                               const T* __restrict__ Xp, int64_t cap_cells,
-                                                               ArrMeta<T>* __restrict__ meta) {
-  const int k = blockIdx.x;
-  const int tid = threadIdx.x;
-  __shared__ T s_min[kBuildBlock];
-  __shared__ uint32_t s_flags[kBuildBlock];
-  __shared__ int64_t s_first[kBuildBlock];
-  __shared__ T s_H, s_W;
-  __shared__ int s_state;  // 0 continue, 1 infeasible
+                                                               const T* __restrict__ Xp, int32_t K,
+                                                               ArrMeta<T>* __restrict__ meta,
+                                                               int32_t* __restrict__ chunk_first) {
+  const int32_t k = blockIdx.x * kScanBlock + threadIdx.x;
+  if (k >= K) return;
   const int64_t xo = x_off[k];
-  const int64_t n_vals = x_off[k + 1] - xo;
-  const int64_t N = n_vals - 1;
-  const T* X = Xp + xo;
+  const int64_t N = x_off[k + 1] - xo - 1;
+  // the chunks whose first value lies in this array (each chunk start lies in exactly one array)
+  for (int64_t c = (xo + kScanChunk - 1) / kScanChunk; c * kScanChunk < xo + N + 1; ++c)
+    chunk_first[c] = k;
   ArrMeta<T> m{};
   m.x_off = xo;
   m.q_off = q_off[k];
   m.q_end = q_off[k + 1];
   m.N = static_cast<int32_t>(N);
+  m.R = -1;
+  m.gbits = order_bits(std::numeric_limits<T>::infinity());
+  m.flags = 0;
+  m.first_bad = kNoPair;
   if (N <= 0) {
-    if (tid == 0) {
-      m.method = kBmTrivial;
-      m.X0 = (N == 0) ? X[0] : T(0);
-      meta[k] = m;
+    m.method = kBmTrivial;
+    m.X0 = (N == 0) ? Xp[xo] : T(0);
+  } else {
+    m.method = DS_METHOD_DIRECT;  // until the start kernel decides
+    m.X0 = Xp[xo];
+    m.XN = Xp[xo + N];
+  }
+  meta[k] = m;
+}
+
+template <typename T, bool VECLOAD>
+__device__ __forceinline__ void load_group(const T* __restrict__ X, int64_t g0, int64_t total_x,
+                                           T (&v)[16 / sizeof(T)]) {
+  constexpr int V = 16 / sizeof(T);
+  if (VECLOAD && g0 + V <= total_x) {
+    const uint4 q = *reinterpret_cast<const uint4*>(X + g0);
+    __builtin_memcpy(&v[0], &q, 16);
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[e] = (g0 + e < total_x) ? X[g0 + e] : T(0);
+  }
+}
+
+// The arrays met by this workgroup's chunk: k0 holds its first value, and
+// every array of the chunk lies in [k0, hi) with x_off[hi] past the chunk.
+struct ChunkArrays {
+  int32_t k0, hi;
+  bool one;  // the whole chunk lies in array k0
+};
+
+__device__ __forceinline__ ChunkArrays chunk_arrays(const int64_t* __restrict__ x_off, int32_t K,
+                                                    const int32_t* __restrict__ chunk_first, int64_t total_x) {
+  const int64_t c = blockIdx.x;
+  const int64_t c1 = std::min((c + 1) * kScanChunk, total_x);
+  const int64_t n_chunks = (total_x + kScanChunk - 1) / kScanChunk;
+  ChunkArrays a;
+  a.k0 = chunk_first[c];
+  a.one = x_off[a.k0 + 1] >= c1;
+  // the array holding the next chunk's first value ends past this chunk
+  a.hi = (c + 1 < n_chunks) ? std::min(chunk_first[c + 1] + 1, K) : K;
+  return a;
+}
+
+// Visits, in increasing g per lane, every pair (X[g], X[g+1]) of one array
+// with g in this workgroup's chunk: vis.begin(k) when a lane enters array k,
+// vis.pair(g, a, b) per pair, vis.end() when it leaves.  Lane t holds groups
+// of 16 bytes at t, t + 256, ... so each load of a wave is 1 KiB contiguous;
+// the loads are issued before the chunk's arrays are looked up.
+template <typename T, bool VECLOAD, class Vis>
+__device__ __forceinline__ ChunkArrays scan_pairs(const int64_t* __restrict__ x_off, int32_t K,
+                                                  const int32_t* __restrict__ chunk_first, const T* __restrict__ X,
+                                                  int64_t total_x, Vis& vis, unsigned long long* g_slots = nullptr,
+                                                  uint32_t* f_slots = nullptr) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int U = static_cast<int>(kScanChunk / (kScanBlock * V));
+  const int64_t c0 = int64_t(blockIdx.x) * kScanChunk;
+  const int64_t c1 = std::min(c0 + kScanChunk, total_x);
+  T v[U][V], nx[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t g0 = c0 + int64_t(u * kScanBlock + threadIdx.x) * V;
+    load_group<T, VECLOAD>(X, g0, total_x, v[u]);
+    nx[u] = (g0 + V < total_x) ? X[g0 + V] : T(0);
+  }
+  const ChunkArrays ca = chunk_arrays(x_off, K, chunk_first, total_x);
+  vis.prepare(ca, g_slots, f_slots);
+  int32_t k = ca.k0;
+  int64_t end = x_off[k + 1];  // one past array k's last value
+  vis.begin(k);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t g0 = c0 + int64_t(u * kScanBlock + threadIdx.x) * V;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const int64_t g = g0 + e;
+      if (g >= c1) continue;
+      if (g >= end) {
+        vis.end();
+        k = array_of(x_off, std::min(k + 1, ca.hi - 1), ca.hi, g);
+        end = x_off[k + 1];
+        vis.begin(k);
+      }
+      if (g + 1 < end) vis.pair(g, v[u][e], e + 1 < V ? v[u][e + 1] : nx[u]);
     }
-    return;
   }
-  const T X0 = X[0];
-  const T XN = X[N];
-  // validation and minimum rounded gap (Sec. 4.4.2)
-  T gmin = std::numeric_limits<T>::infinity();
-  uint32_t fl = 0;
-  for (int64_t i = tid; i < N; i += kBuildBlock) {
-    const T a = X[i], b = X[i + 1];
-    if (!std::isfinite(a) || !std::isfinite(b)) fl |= 1u;
-    if (!(a < b)) fl |= 2u;
-    const T da = a - X0, db = b - X0;
-    if (!(da < db)) fl |= 4u;
-    gmin = std::fmin(gmin, db - da);
-  }
-  s_min[tid] = gmin;
-  s_flags[tid] = fl;
-  __syncthreads();
-  for (int w = kBuildBlock / 2; w > 0; w >>= 1) {
-    if (tid < w) {
-      s_min[tid] = std::fmin(s_min[tid], s_min[tid + w]);
-      s_flags[tid] |= s_flags[tid + w];
+  return ca;
+}
+
+template <typename T>
+struct GapVis {
+  ArrMeta<T>* meta;
+  unsigned long long* s_g;  // per-array slots in LDS for a chunk of many arrays, else null
+  uint32_t* s_f;
+  int32_t k0;
+  int32_t k;
+  T x0, gmin;
+  uint32_t fl;
+  bool any;
+  // a chunk of several arrays (few enough for the slots) merges its lanes in LDS first
+  __device__ __forceinline__ void prepare(const ChunkArrays& ca, unsigned long long* g_slots, uint32_t* f_slots) {
+    s_g = nullptr;
+    if (ca.one || ca.hi - ca.k0 > kScanSlots) return;
+    s_g = g_slots;
+    s_f = f_slots;
+    k0 = ca.k0;
+    for (int j = threadIdx.x; j < ca.hi - ca.k0; j += kScanBlock) {
+      s_g[j] = ~0ull;  // untouched
+      s_f[j] = 0;
     }
     __syncthreads();
   }
-  const uint32_t flags = s_flags[0];
-  const T g = s_min[0];
-  m.X0 = X0;
-  m.XN = XN;
-  if (flags & 3u) {
-    if (tid == 0) {
-      m.method = kBmInvalid;
-      meta[k] = m;
+  __device__ __forceinline__ void begin(int32_t kk) {
+    k = kk;
+    x0 = meta[kk].X0;
+    gmin = std::numeric_limits<T>::infinity();
+    fl = 0;
+    any = false;
+  }
+  __device__ __forceinline__ void pair(int64_t, T a, T b) {
+    any = true;
+    if (!std::isfinite(a) || !std::isfinite(b)) fl |= 1u;
+    if (!(a < b)) fl |= 2u;
+    const T da = a - x0, db = b - x0;
+    if (!(da < db)) fl |= 4u;
+    gmin = std::fmin(gmin, db - da);
+  }
+  __device__ __forceinline__ void flush() const {
+    // a gap <= 0 or NaN comes with flag 2 or 4, which decides alone
+    const unsigned long long b = order_bits((gmin > T(0)) ? gmin : T(0));
+    if (s_g) {
+      atomicMin(&s_g[k - k0], b);
+      if (fl) atomicOr(&s_f[k - k0], fl);
+    } else {
+      atomicMin(&meta[k].gbits, b);
+      if (fl) atomicOr(&meta[k].flags, fl);
     }
+  }
+  __device__ __forceinline__ void end() const {
+    if (any) flush();
+  }
+};
+
+// validation flags (1: not finite, 2: not increasing, 4: X_i - X_0 not
+// increasing) and the minimum rounded gap min (X_{i+1} - X_0) - (X_i - X_0)
+template <typename T, bool VECLOAD>
+__global__ void __launch_bounds__(kScanBlock) gaps_kernel(const int64_t* __restrict__ x_off, int32_t K,
+                                                          const int32_t* __restrict__ chunk_first,
+                                                          const T* __restrict__ Xp, int64_t total_x,
+                                                          ArrMeta<T>* __restrict__ meta) {
+  __shared__ unsigned long long s_g[kScanSlots];
+  __shared__ uint32_t s_f[kScanSlots];
+  GapVis<T> vis{meta};
+  const ChunkArrays ca = scan_pairs<T, VECLOAD>(x_off, K, chunk_first, Xp, total_x, vis, s_g, s_f);
+  if (ca.one) {
+    // the whole chunk is one array: one atomic per wave
+    for (int off = 32; off > 0; off >>= 1) {
+      vis.gmin = std::fmin(vis.gmin, __shfl_xor(vis.gmin, off, 64));
+      vis.fl |= __shfl_xor(vis.fl, off, 64);
+      vis.any = vis.any | (__shfl_xor(static_cast<int>(vis.any), off, 64) != 0);
+    }
+    if ((threadIdx.x & 63) == 0 && vis.any) vis.flush();
+    return;
+  }
+  vis.end();
+  if (!vis.s_g) return;
+  __syncthreads();
+  for (int j = threadIdx.x; j < ca.hi - ca.k0; j += kScanBlock) {
+    if (s_g[j] == ~0ull) continue;
+    atomicMin(&meta[ca.k0 + j].gbits, s_g[j]);
+    if (s_f[j]) atomicOr(&meta[ca.k0 + j].flags, s_f[j]);
+  }
+}
+
+// H = the float above 1 / min gap (eq. minhnumeric), W, and whether that start
+// is feasible before any growth
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kScanBlock) start_kernel(int32_t K, int64_t cap_cells,
+                                                           ArrMeta<T>* __restrict__ meta) {
+  const int32_t k = blockIdx.x * kScanBlock + threadIdx.x;
+  if (k >= K) return;
+  ArrMeta<T>& m = meta[k];
+  if (m.method != DS_METHOD_DIRECT) return;  // no value or one value
+  const uint32_t flags = m.flags;
+  if (flags & 3u) {
+    m.method = kBmInvalid;
     return;
   }
   bool feasible = !(flags & 4u);
-  T H = 0, W = 0, P = 0;
-  int32_t n_updates = 0;
+  T H = 0, W = 0;
   if (feasible) {
+    const T g = from_order_bits<T>(m.gbits);
     const T Hbar = T(1) / g;  // correctly rounded division
     feasible = !std::isinf(Hbar);
     H = next_up_dev(Hbar);
-    W = (FORM == DS_FORM_FMA) ? T(H * X0) : T(0);
-    feasible = feasible && grid_floor<T, FORM>(XN, H, W, X0) < T(kTwoPowQ);
-    // a table already over the Direct cap only grows with H: not Direct, stop here
-    feasible = feasible && !over_cap<T, FORM>(H, W, X0, XN, cap_cells);
-    P = next_up_dev(H) - H;
+    W = (FORM == DS_FORM_FMA) ? T(H * m.X0) : T(0);
+    feasible = feasible && grid_floor<T, FORM>(m.XN, H, W, m.X0) < T(kTwoPowQ);
+    // a table already over the Direct cap only grows with H: not Direct
+    feasible = feasible && !over_cap<T, FORM>(H, W, m.X0, m.XN, cap_cells);
   }
   if (feasible) {
-    // growth passes (Sec. 4.4.3); every lane keeps H, W, P in step via LDS
+    m.H = H;
+    m.W = W;
+  } else {
+    m.method = DS_METHOD_BSEARCH_OFFSET;
+  }
+}
+
+template <typename T, int FORM>
+struct FirstBadVis {
+  ArrMeta<T>* meta;
+  int32_t k;
+  T H, W, x0;
+  int64_t base;
+  bool active;
+  __device__ __forceinline__ void prepare(const ChunkArrays&, unsigned long long*, uint32_t*) {}
+  __device__ __forceinline__ void begin(int32_t kk) {
+    k = kk;
+    const ArrMeta<T>& m = meta[kk];
+    active = m.method == DS_METHOD_DIRECT;
+    H = m.H;
+    W = m.W;
+    x0 = m.X0;
+    base = m.x_off;
+  }
+  __device__ __forceinline__ void pair(int64_t g, T a, T b) {
+    if (active && grid_floor<T, FORM>(a, H, W, x0) == grid_floor<T, FORM>(b, H, W, x0)) {
+      atomicMin(&meta[k].first_bad, static_cast<int32_t>(g + 1 - base));
+      active = false;  // later pairs of this lane come after this one
+    }
+  }
+  __device__ __forceinline__ void end() const {}
+};
+
+// the first i with floor(m(X_{i-1})) = floor(m(X_i)) at the starting H
+template <typename T, int FORM, bool VECLOAD>
+__global__ void __launch_bounds__(kScanBlock) first_bad_kernel(const int64_t* __restrict__ x_off, int32_t K,
+                                                               const int32_t* __restrict__ chunk_first,
+                                                               const T* __restrict__ Xp, int64_t total_x,
+                                                               ArrMeta<T>* __restrict__ meta) {
+  FirstBadVis<T, FORM> vis{meta};
+  (void)scan_pairs<T, VECLOAD>(x_off, K, chunk_first, Xp, total_x, vis);
+}
+
+// ComputeHR's growth (Sec. 4.4.3) from the first coinciding pair: one lane
+// applies the growth steps of the sequential algorithm to that pair, the
+// workgroup finds the next one after it, and a pass over the whole array
+// that changes nothing ends the search
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kFinishBlock) finish_kernel(const T* __restrict__ Xp, int64_t cap_cells,
+                                                              ArrMeta<T>* __restrict__ meta) {
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  __shared__ int64_t s_first[kFinishBlock];
+  __shared__ T s_H, s_W;
+  __shared__ int s_state;  // 0 continue, 1 infeasible
+  ArrMeta<T>& mref = meta[k];
+  if (mref.method != DS_METHOD_DIRECT) return;
+  const int64_t N = mref.N;
+  const T* X = Xp + mref.x_off;
+  const T X0 = mref.X0, XN = mref.XN;
+  T H = mref.H, W = mref.W;
+  T P = next_up_dev(H) - H;
+  int32_t n_updates = 0;
+  bool feasible = true;
+  int64_t bad = mref.first_bad;
+  if (bad <= N) {
     if (tid == 0) {
       s_H = H;
       s_W = W;
@@ -201,21 +463,23 @@ __global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __
     for (int round = 0; round < kMaxGrowthRounds; ++round) {
       H = s_H;
       W = s_W;
-      int64_t first = N + 1;
-      for (int64_t i = i_start + tid; i <= N; i += kBuildBlock) {
-        if (grid_floor<T, FORM>(X[i - 1], H, W, X0) == grid_floor<T, FORM>(X[i], H, W, X0)) {
-          first = i;
-          break;
+      if (round > 0) {
+        int64_t first = N + 1;
+        for (int64_t i = i_start + tid; i <= N; i += kFinishBlock) {
+          if (grid_floor<T, FORM>(X[i - 1], H, W, X0) == grid_floor<T, FORM>(X[i], H, W, X0)) {
+            first = i;
+            break;
+          }
         }
-      }
-      s_first[tid] = first;
-      __syncthreads();
-      for (int w = kBuildBlock / 2; w > 0; w >>= 1) {
-        if (tid < w) s_first[tid] = std::min(s_first[tid], s_first[tid + w]);
+        s_first[tid] = first;
+        __syncthreads();
+        for (int w = kFinishBlock / 2; w > 0; w >>= 1) {
+          if (tid < w) s_first[tid] = std::min(s_first[tid], s_first[tid + w]);
+          __syncthreads();
+        }
+        bad = s_first[0];
         __syncthreads();
       }
-      const int64_t bad = s_first[0];
-      __syncthreads();
       if (bad > N) {
         if (!changed) break;  // a whole pass without change: every pair holds
         changed = false;
@@ -254,213 +518,322 @@ __global__ void __launch_bounds__(kBuildBlock) build_hr_kernel(const int64_t* __
   }
   if (tid == 0) {
     if (feasible) {
-      m.H = H;
-      m.W = W;
-      m.R = static_cast<int32_t>(grid_floor<T, FORM>(XN, H, W, X0));
-      m.jmin = static_cast<int32_t>(grid_floor<T, FORM>(X0, H, W, X0));
-      const int64_t nK = int64_t(m.R) - m.jmin + 1;
+      mref.H = H;
+      mref.W = W;
+      mref.R = static_cast<int32_t>(grid_floor<T, FORM>(XN, H, W, X0));
+      mref.jmin = static_cast<int32_t>(grid_floor<T, FORM>(X0, H, W, X0));
+      const int64_t nK = int64_t(mref.R) - mref.jmin + 1;
       const int64_t nW = (nK + 63) / 64;
-      m.nW = static_cast<int32_t>((nW + 3) / 4 * 4);  // keeps every array's words 16-byte aligned
-      m.method = DS_METHOD_DIRECT;
-      m.n_updates = n_updates;
+      mref.nW = static_cast<int32_t>((nW + 3) / 4 * 4);  // keeps every array's words 16-byte aligned
+      mref.n_updates = n_updates;
     } else {
-      m.method = DS_METHOD_BSEARCH_OFFSET;
-      m.R = -1;
+      mref.method = DS_METHOD_BSEARCH_OFFSET;
+      mref.H = 0;
+      mref.W = 0;
     }
-    meta[k] = m;
   }
 }
 
+template <typename T, int FORM>
+ds_status launch_build(const ds_batch_desc* d, ArrMeta<T>* meta, int32_t* chunk_first, int64_t cap_cells,
+                       hipStream_t s) {
+  const int32_t K = d->num_arrays;
+  const T* X = static_cast<const T*>(d->X_dev);
+  const dim3 per_array((K + kScanBlock - 1) / kScanBlock);
+  init_meta_kernel<T><<<per_array, dim3(kScanBlock), 0, s>>>(d->x_off_dev, d->q_off_dev, X, K, meta, chunk_first);
+  DS_HIP_CHECK(hipGetLastError());
+  const dim3 chunks(static_cast<uint32_t>((d->total_x + kScanChunk - 1) / kScanChunk));
+  const bool vec = (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  if (chunks.x > 0) {
+    if (vec)
+      gaps_kernel<T, true><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X, d->total_x, meta);
+    else
+      gaps_kernel<T, false><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X, d->total_x, meta);
+    DS_HIP_CHECK(hipGetLastError());
+  }
+  start_kernel<T, FORM><<<per_array, dim3(kScanBlock), 0, s>>>(K, cap_cells, meta);
+  DS_HIP_CHECK(hipGetLastError());
+  if (chunks.x > 0) {
+    if (vec)
+      first_bad_kernel<T, FORM, true><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X,
+                                                                          d->total_x, meta);
+    else
+      first_bad_kernel<T, FORM, false><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X,
+                                                                           d->total_x, meta);
+    DS_HIP_CHECK(hipGetLastError());
+  }
+  finish_kernel<T, FORM><<<dim3(K), dim3(kFinishBlock), 0, s>>>(X, cap_cells, meta);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
+}
+
 // --------------------------------------------------------------------------
-// 2. plan: scans over arrays (one workgroup)
+// 2. plan: scans over arrays (one workgroup).  Lane t owns the arrays
+//    [t C, (t + 1) C), C = ceil(K / 1024): it sums them, one workgroup scan
+//    turns the lanes' sums into their first offsets, and the lane walks its
+//    arrays again to assign them; a second scan numbers the learned arrays.
+//    With tiles_only (a new tile size over arrays already built) only the
+//    query tiles are assigned again: methods, tables and slots stay.
+__device__ __forceinline__ void plan_scan3(int64_t* s_a, int64_t* s_b, int64_t* s_c, int tid) {
+  // inclusive Hillis-Steele scans of three lanes' values at once
+  for (int d = 1; d < kPlanBlock; d <<= 1) {
+    int64_t a = 0, b = 0, c = 0;
+    if (tid >= d) {
+      a = s_a[tid - d];
+      b = s_b[tid - d];
+      c = s_c[tid - d];
+    }
+    __syncthreads();
+    s_a[tid] += a;
+    s_b[tid] += b;
+    s_c[tid] += c;
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict__ meta, int32_t K,
                                                           int64_t* __restrict__ tile_off, PlanTotals* __restrict__ tot,
                                                           int64_t words_budget, int64_t tile, int32_t learn,
-                                                          int64_t direct_cap_cells, LearnMeta* __restrict__ lmeta) {
-  __shared__ int64_t s_w[kPlanBlock], s_c[kPlanBlock], s_t[kPlanBlock], s_l[kPlanBlock];
-  __shared__ int64_t carry_w, carry_c, carry_t, carry_l;
-  __shared__ unsigned long long s_ltiles;
+                                                          int64_t direct_cap_cells, LearnMeta* __restrict__ lmeta,
+                                                          int32_t tiles_only) {
+  __shared__ int64_t s_w[kPlanBlock], s_c[kPlanBlock], s_t[kPlanBlock];
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    carry_w = carry_c = carry_t = carry_l = 0;
-    s_ltiles = 0;
-  }
   if (tid < kNumQueues) {
     tot->queue[tid] = 0;
     tot->lqueue[tid] = 0;
   }
   if (tid == 0) tot->fallbacks = 0;
-  // Direct over the per-array table cap is treated like an infeasible array
-  for (int32_t k = tid; k < K; k += kPlanBlock) {
+  const int32_t per = (K + kPlanBlock - 1) / kPlanBlock;
+  const int32_t kb = static_cast<int32_t>(std::min<int64_t>(K, int64_t(tid) * per));
+  const int32_t ke = static_cast<int32_t>(std::min<int64_t>(K, int64_t(kb) + per));
+  // pass 1: Direct over the per-array table cap is treated like an infeasible
+  // array; the lane's table words, codes and tiles
+  int64_t sw = 0, sc = 0, st = 0;
+  for (int32_t k = kb; k < ke; ++k) {
     ArrMeta<T>& m = meta[k];
-    if (m.method == DS_METHOD_DIRECT && direct_cap_cells > 0 && int64_t(m.R) - m.jmin + 1 > direct_cap_cells)
-      m.method = DS_METHOD_BSEARCH_OFFSET;
-    if (learn && m.method == DS_METHOD_BSEARCH_OFFSET) m.method = DS_METHOD_LEARNED;
+    int32_t method = m.method;
+    if (!tiles_only) {
+      if (method == DS_METHOD_DIRECT && direct_cap_cells > 0 && int64_t(m.R) - m.jmin + 1 > direct_cap_cells)
+        method = DS_METHOD_BSEARCH_OFFSET;
+      if (learn && method == DS_METHOD_BSEARCH_OFFSET) method = DS_METHOD_LEARNED;
+      if (method != m.method) m.method = method;
+    }
+    if (method == DS_METHOD_DIRECT) {
+      sw += m.nW;
+      sc += (int64_t(m.N) + 1 + 7) / 8 * 8;
+    }
+    st += (m.q_end - m.q_off + tile - 1) / tile;
+  }
+  s_w[tid] = sw;
+  s_c[tid] = sc;
+  s_t[tid] = st;
+  __syncthreads();
+  plan_scan3(s_w, s_c, s_t, tid);
+  // pass 2: offsets; a table that does not fit the workspace falls back (its
+  // words still count in the offsets of the arrays after it)
+  int64_t w0 = s_w[tid] - sw, c0 = s_c[tid] - sc, t0 = s_t[tid] - st;
+  const int64_t words_total = s_w[kPlanBlock - 1], tiles_total = s_t[kPlanBlock - 1];
+  int64_t nl = 0, lt = 0;
+  for (int32_t k = kb; k < ke; ++k) {
+    ArrMeta<T>& m = meta[k];
+    const int64_t nt = (m.q_end - m.q_off + tile - 1) / tile;
+    m.t_off = t0;
+    tile_off[k] = t0;
+    t0 += nt;
+    if (m.method == DS_METHOD_DIRECT && !tiles_only) {
+      const int64_t nw = m.nW, nc = (int64_t(m.N) + 1 + 7) / 8 * 8;
+      if (w0 + nw > words_budget) {
+        m.method = learn ? DS_METHOD_LEARNED : DS_METHOD_BSEARCH_OFFSET;
+        m.w_off = 0;
+        m.c_off = 0;
+      } else {
+        m.w_off = w0;
+        m.c_off = c0;
+      }
+      w0 += nw;
+      c0 += nc;
+    }
+    if (m.method == DS_METHOD_LEARNED) {
+      ++nl;
+      lt += nt;
+    }
   }
   __syncthreads();
-  for (int32_t base = 0; base < K; base += kPlanBlock) {
-    const int32_t k = base + tid;
-    int64_t nw = 0, nc = 0, nt = 0;
-    if (k < K) {
-      const ArrMeta<T>& m = meta[k];
-      if (m.method == DS_METHOD_DIRECT) {
-        nw = m.nW;
-        nc = (int64_t(m.N) + 1 + 7) / 8 * 8;
-      }
-      nt = (m.q_end - m.q_off + tile - 1) / tile;
-    }
-    s_w[tid] = nw;
-    s_c[tid] = nc;
-    s_t[tid] = nt;
-    __syncthreads();
-    // inclusive Hillis-Steele scans
-    for (int d = 1; d < kPlanBlock; d <<= 1) {
-      int64_t aw = 0, ac = 0, at = 0;
-      if (tid >= d) {
-        aw = s_w[tid - d];
-        ac = s_c[tid - d];
-        at = s_t[tid - d];
-      }
-      __syncthreads();
-      s_w[tid] += aw;
-      s_c[tid] += ac;
-      s_t[tid] += at;
-      __syncthreads();
-    }
-    if (k < K) {
-      ArrMeta<T>& m = meta[k];
-      const int64_t w0 = carry_w + s_w[tid] - nw;
-      const int64_t c0 = carry_c + s_c[tid] - nc;
-      const int64_t t0 = carry_t + s_t[tid] - nt;
-      m.t_off = t0;
-      tile_off[k] = t0;
-      if (m.method == DS_METHOD_DIRECT) {
-        if (w0 + nw > words_budget) {
-          // the table does not fit the workspace
-          m.method = learn ? DS_METHOD_LEARNED : DS_METHOD_BSEARCH_OFFSET;
-          m.w_off = 0;
-          m.c_off = 0;
-        } else {
-          m.w_off = w0;
-          m.c_off = c0;
-        }
-      }
-    }
-    __syncthreads();
-    // learned arrays take consecutive model slots
-    const int64_t isl = (k < K && meta[k].method == DS_METHOD_LEARNED) ? 1 : 0;
-    s_l[tid] = isl;
-    __syncthreads();
-    for (int d = 1; d < kPlanBlock; d <<= 1) {
-      const int64_t a = tid >= d ? s_l[tid - d] : 0;
-      __syncthreads();
-      s_l[tid] += a;
-      __syncthreads();
-    }
-    if (isl) {
-      ArrMeta<T>& m = meta[k];
-      atomicAdd(&s_ltiles, static_cast<unsigned long long>(nt));
-      const int32_t slot = static_cast<int32_t>(carry_l + s_l[tid] - 1);
-      m.slot = slot;
-      LearnMeta lm{};
-      lm.X0 = static_cast<double>(m.X0);
-      lm.XN = static_cast<double>(m.XN);
-      const double range = lm.XN - lm.X0;
-      lm.delta = std::fmax(range * 0x1p-40, 1e-300);
-      const double d0 = lm.delta, d1 = range + lm.delta;
-      int64_t b0, b1;
-      __builtin_memcpy(&b0, &d0, 8);
-      __builtin_memcpy(&b1, &d1, 8);
-      lm.flo = static_cast<double>(b0);
-      lm.fscale = 1.0 / (static_cast<double>(b1) - lm.flo);
-      lm.x_off = m.x_off;
-      lm.N = m.N;
-      lm.k = k;
-      lmeta[slot] = lm;
-    }
-    __syncthreads();
-    if (tid == kPlanBlock - 1) {
-      carry_w += s_w[tid];
-      carry_c += s_c[tid];
-      carry_t += s_t[tid];
-      carry_l += s_l[tid];
-    }
-    __syncthreads();
+  s_w[tid] = nl;
+  s_t[tid] = lt;
+  s_c[tid] = 0;
+  __syncthreads();
+  plan_scan3(s_w, s_c, s_t, tid);
+  // pass 3: learned arrays take consecutive model slots
+  int32_t slot = static_cast<int32_t>(s_w[tid] - nl);
+  for (int32_t k = kb; k < ke && nl > 0 && !tiles_only; ++k) {
+    ArrMeta<T>& m = meta[k];
+    if (m.method != DS_METHOD_LEARNED) continue;
+    m.slot = slot;
+    LearnMeta lm{};
+    lm.X0 = static_cast<double>(m.X0);
+    lm.XN = static_cast<double>(m.XN);
+    const double range = lm.XN - lm.X0;
+    lm.delta = std::fmax(range * 0x1p-40, 1e-300);
+    const double d0 = lm.delta, d1 = range + lm.delta;
+    int64_t b0, b1;
+    __builtin_memcpy(&b0, &d0, 8);
+    __builtin_memcpy(&b1, &d1, 8);
+    lm.flo = static_cast<double>(b0);
+    lm.fscale = 1.0 / (static_cast<double>(b1) - lm.flo);
+    lm.x_off = m.x_off;
+    lm.N = m.N;
+    lm.k = k;
+    lmeta[slot] = lm;
+    ++slot;
   }
-  if (tid == 0) {
-    tile_off[K] = carry_t;
-    tot->total_tiles = carry_t;
-    tot->learned_tiles = static_cast<int64_t>(s_ltiles);
-    tot->words_used = carry_w;
-    tot->n_learned = static_cast<int32_t>(carry_l);
+  if (tid == kPlanBlock - 1) {
+    tile_off[K] = tiles_total;
+    tot->total_tiles = tiles_total;
+    tot->learned_tiles = s_t[kPlanBlock - 1];
+    if (!tiles_only) {
+      tot->words_used = words_total;
+      tot->n_learned = static_cast<int32_t>(s_w[kPlanBlock - 1]);
+    }
   }
 }
 
 // --------------------------------------------------------------------------
-// 3. per-array RANKCODE layout
-template <typename T, int FORM>
-__global__ void __launch_bounds__(kBuildBlock) rankcode_kernel(const T* __restrict__ Xp, ArrMeta<T>* __restrict__ meta,
-                                                               unsigned long long* __restrict__ bits,
-                                                               uint32_t* __restrict__ base,
-                                                               uint16_t* __restrict__ codes, int64_t words_budget) {
-  const int k = blockIdx.x;
-  const int tid = threadIdx.x;
-  const ArrMeta<T> m = meta[k];
-  if (m.method != DS_METHOD_DIRECT) return;
-  const T* X = Xp + m.x_off;
-  const int64_t N = m.N;
-  unsigned long long* wb = bits + m.w_off;
-  uint32_t* bb = base + m.w_off;
-  uint16_t* cb = codes + m.c_off;
-  const int64_t nK = int64_t(m.R) - m.jmin + 1;
-  const int64_t nWused = (nK + 63) / 64;
-  for (int64_t w = tid; w < m.nW; w += kBuildBlock) {
-    wb[w] = 0ull;
-    bb[w] = static_cast<uint32_t>(N + 1);  // padding words past the last cell
+// 3. RANKCODE layout of every Direct array (bitmap of occupied cells, running
+//    counts, 16-bit position codes), in two launches over the packed values
+//    like the build's scans: the pool's occupancy words are cleared, then
+//    each value sets its cell's bit, writes its code and the running count of
+//    the words whose first cell lies in (cell of X_{i-1}, cell of X_i].
+__global__ void __launch_bounds__(kScanBlock) zero_words_kernel(unsigned long long* __restrict__ bits,
+                                                                const PlanTotals* __restrict__ tot,
+                                                                int64_t words_budget) {
+  // the placed arrays' words lie in [0, words_used) (the count also holds
+  // arrays that did not fit, hence the budget)
+  const int64_t n = std::min(tot->words_used, words_budget);
+  const int64_t stride = int64_t(gridDim.x) * kScanBlock * 2;
+  for (int64_t w = (int64_t(blockIdx.x) * kScanBlock + threadIdx.x) * 2; w < n; w += stride) {
+    if (w + 1 < n)
+      *reinterpret_cast<uint4*>(bits + w) = make_uint4(0, 0, 0, 0);  // the pool is 256-byte aligned, w even
+    else
+      bits[w] = 0ull;
   }
-  const int64_t n_codes = (N + 1 + 7) / 8 * 8;
-  for (int64_t i = N + 1 + tid; i < n_codes; i += kBuildBlock) cb[i] = 0;
-  __syncthreads();
-  // Lanes of a wave hold consecutive i, so their cells (and words) are
-  // non-decreasing across the wave: a segmented OR over lanes that share a
-  // word leaves one atomic per word and wave instead of one per element.
-  const int lane = tid & 63;
-  for (int64_t i0 = 0; i0 <= N; i0 += kBuildBlock) {
-    const int64_t i = i0 + tid;
-    const bool valid = i <= N;
-    int64_t word = -1 - lane;  // distinct per invalid lane: never merges
-    unsigned long long bitv = 0;
-    if (valid) {
-      const T x = X[i];
-      const T v = grid_value<T, FORM>(x, m.H, m.W, m.X0);
-      const T jf = std::floor(v);
-      const int64_t e = static_cast<int64_t>(jf) - m.jmin;
-      const int64_t eprev =
-          (i == 0) ? -1 : static_cast<int64_t>(grid_floor<T, FORM>(X[i - 1], m.H, m.W, m.X0)) - m.jmin;
-      if (e >= 0 && e < nK) {
-        word = e >> 6;
-        bitv = 1ull << (e & 63);
+}
+
+template <typename T, int FORM, bool VECLOAD>
+__global__ void __launch_bounds__(kScanBlock) rankcode_kernel(const int64_t* __restrict__ x_off, int32_t K,
+                                                              const int32_t* __restrict__ chunk_first,
+                                                              const T* __restrict__ Xp, int64_t total_x,
+                                                              const ArrMeta<T>* __restrict__ meta,
+                                                              unsigned long long* __restrict__ bits,
+                                                              uint32_t* __restrict__ base,
+                                                              uint16_t* __restrict__ codes) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int U = static_cast<int>(kScanChunk / (kScanBlock * V));
+  const int64_t c0 = int64_t(blockIdx.x) * kScanChunk;
+  const int64_t c1 = std::min(c0 + kScanChunk, total_x);
+  const int lane = threadIdx.x & 63;
+  const ChunkArrays ca = chunk_arrays(x_off, K, chunk_first, total_x);
+  int32_t k = ca.k0;
+  ArrMeta<T> m = meta[k];
+  if (ca.one && m.method != DS_METHOD_DIRECT) return;  // a chunk of a learned or binary-search array
+  T v[U][V], pv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t g0 = c0 + int64_t(u * kScanBlock + threadIdx.x) * V;
+    load_group<T, VECLOAD>(Xp, g0, total_x, v[u]);
+    pv[u] = (g0 > 0 && g0 <= total_x) ? Xp[g0 - 1] : T(0);
+  }
+  int64_t end = x_off[k + 1];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t g0 = c0 + int64_t(u * kScanBlock + threadIdx.x) * V;
+    long long key = -1 - lane;  // global word of acc; distinct negatives never merge
+    unsigned long long acc = 0;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const int64_t g = g0 + e;
+      if (g >= c1) continue;
+      if (g >= end) {
+        k = array_of(x_off, std::min(k + 1, ca.hi - 1), ca.hi, g);
+        end = x_off[k + 1];
+        m = meta[k];
       }
-      // running counts: words whose first cell lies in (e_{i-1}, e_i] start at i
-      for (int64_t w = (eprev + 1 + 63) / 64; w <= e / 64 && w < nWused; ++w) bb[w] = static_cast<uint32_t>(i);
-      const T c = cell_code<T>(v, jf);
+      if (m.method != DS_METHOD_DIRECT) continue;
+      const int64_t i = g - m.x_off;
+      const int64_t nK = int64_t(m.R) - m.jmin + 1;
+      const int64_t nWused = (nK + 63) / 64;
+      uint32_t* bb = base + m.w_off;
+      uint16_t* cb = codes + m.c_off;
+      const T x = v[u][e];
+      const T gv = grid_value<T, FORM>(x, m.H, m.W, m.X0);
+      const T jf = std::floor(gv);
+      const int64_t cell = static_cast<int64_t>(jf) - m.jmin;
+      const T xp = (e > 0) ? v[u][e > 0 ? e - 1 : 0] : pv[u];
+      const int64_t cprev = (i == 0) ? -1 : static_cast<int64_t>(grid_floor<T, FORM>(xp, m.H, m.W, m.X0)) - m.jmin;
+      // running counts: words whose first cell lies in (cprev, cell] start at i
+      for (int64_t w = (cprev + 1 + 63) / 64; w <= cell / 64 && w < nWused; ++w) bb[w] = static_cast<uint32_t>(i);
+      const T c = cell_code<T>(gv, jf);
       const T p = std::nextafter(x, -std::numeric_limits<T>::infinity());
       const T vp = grid_value<T, FORM>(p, m.H, m.W, m.X0);
       const T jp = std::floor(vp);
       const int first = (jp == jf && cell_code<T>(vp, jp) == c) ? 0 : 1;
       cb[i] = static_cast<uint16_t>((static_cast<int>(c) << 1) | first);
+      if (i == m.N) {
+        for (int64_t w = nWused; w < m.nW; ++w) bb[w] = static_cast<uint32_t>(m.N + 1);  // padding words
+        for (int64_t j = m.N + 1; j < (int64_t(m.N) + 1 + 7) / 8 * 8; ++j) cb[j] = 0;
+      }
+      if (cell >= 0 && cell < nK) {
+        const long long word = m.w_off + (cell >> 6);
+        const unsigned long long bit = 1ull << (cell & 63);
+        if (word == key) {
+          acc |= bit;
+        } else {
+          if (key >= 0) atomicOr(&bits[key], acc);  // an earlier word of this lane's group
+          key = word;
+          acc = bit;
+        }
+      }
     }
+    // Lanes hold consecutive groups, so their words are non-decreasing across
+    // the wave: a segmented OR over lanes that share a word leaves one atomic
+    // per word and wave.
+#pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const unsigned long long ob = __shfl_down(bitv, off, 64);
-      const long long ow = __shfl_down(static_cast<long long>(word), off, 64);
-      if (lane + off < 64 && ow == word) bitv |= ob;
+      const unsigned long long ob = __shfl_down(acc, off, 64);
+      const long long ow = __shfl_down(key, off, 64);
+      if (lane + off < 64 && ow == key) acc |= ob;
     }
-    const long long wprev = __shfl_up(static_cast<long long>(word), 1, 64);
-    const bool head = (lane == 0) || (wprev != word);
-    if (valid && head && bitv) atomicOr(&wb[word], bitv);
+    const long long kprev = __shfl_up(key, 1, 64);
+    if (key >= 0 && (lane == 0 || kprev != key)) atomicOr(&bits[key], acc);
   }
-  (void)words_budget;
+}
+
+template <typename T, int FORM>
+ds_status launch_rankcode(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws, hipStream_t s) {
+  if (L.words_budget > 0) {
+    const int64_t blocks = std::min<int64_t>((L.words_budget + 2 * kScanBlock - 1) / (2 * kScanBlock), 4096);
+    zero_words_kernel<<<dim3(static_cast<uint32_t>(blocks)), dim3(kScanBlock), 0, s>>>(
+        reinterpret_cast<unsigned long long*>(ws + L.bits), reinterpret_cast<const PlanTotals*>(ws + L.totals),
+        L.words_budget);
+    DS_HIP_CHECK(hipGetLastError());
+  }
+  const dim3 chunks(static_cast<uint32_t>((d->total_x + kScanChunk - 1) / kScanChunk));
+  if (chunks.x == 0) return DS_OK;
+  const T* X = static_cast<const T*>(d->X_dev);
+  const auto* meta = reinterpret_cast<const ArrMeta<T>*>(ws + L.meta);
+  const auto* cf = reinterpret_cast<const int32_t*>(ws + L.chunk_first);
+  auto* bits = reinterpret_cast<unsigned long long*>(ws + L.bits);
+  auto* base = reinterpret_cast<uint32_t*>(ws + L.base);
+  auto* codes = reinterpret_cast<uint16_t*>(ws + L.codes);
+  if ((reinterpret_cast<uintptr_t>(X) & 15u) == 0)
+    rankcode_kernel<T, FORM, true><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, d->num_arrays, cf, X,
+                                                                       d->total_x, meta, bits, base, codes);
+  else
+    rankcode_kernel<T, FORM, false><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, d->num_arrays, cf, X,
+                                                                        d->total_x, meta, bits, base, codes);
+  DS_HIP_CHECK(hipGetLastError());
+  return DS_OK;
 }
 
 // --------------------------------------------------------------------------
@@ -651,12 +1024,13 @@ WsLayout layout_of(const ds_batch_desc* d) {
 }
 
 template <typename T>
-ds_status launch_plan(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws, int64_t tile, hipStream_t s) {
+ds_status launch_plan(const ds_batch_desc* d, const WsLayout& L, unsigned char* ws, int64_t tile, hipStream_t s,
+                      bool tiles_only = false) {
   const int64_t cap_cells = d->direct_cap_bytes > 0 ? d->direct_cap_bytes / 4 : 0;
   plan_kernel<T><<<dim3(1), dim3(kPlanBlock), 0, s>>>(
       reinterpret_cast<ArrMeta<T>*>(ws + L.meta), d->num_arrays, reinterpret_cast<int64_t*>(ws + L.tile_off),
       reinterpret_cast<PlanTotals*>(ws + L.totals), L.words_budget, tile, L.nseg > 0 ? 1 : 0, cap_cells,
-      L.nseg > 0 ? reinterpret_cast<LearnMeta*>(ws + L.lmeta) : nullptr);
+      L.nseg > 0 ? reinterpret_cast<LearnMeta*>(ws + L.lmeta) : nullptr, tiles_only ? 1 : 0);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }
@@ -715,7 +1089,7 @@ ds_status autotune_batched(ds_batch_desc* d, hipStream_t s) {
         const SearchShape sh = shape_of(&c);
         float total = 0;
         for (int r = 0; r < 2 && st == DS_OK; ++r) {
-          st = launch_plan<T>(&c, L, ws, sh.tile, s);  // re-plans the tiles and clears the queues
+          st = launch_plan<T>(&c, L, ws, sh.tile, s, true);  // re-plans the tiles and clears the queues
           if (st != DS_OK) break;
           if (hipEventRecord(e0, s) != hipSuccess) { st = DS_ERR_HIP; break; }
           st = launch_search_qpt<T, FORM>(&c, L, ws, sh, c.block, c.qpt, s);
@@ -743,22 +1117,17 @@ ds_status autotune_batched(ds_batch_desc* d, hipStream_t s) {
 
 template <typename T, int FORM>
 ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
-  const int32_t K = d->num_arrays;
   unsigned char* ws = static_cast<unsigned char*>(d->workspace_dev);
   const WsLayout L = layout_of(d);
-  const int64_t wb = L.words_budget;
   const int64_t tile = tile_of(d);
   auto* meta = reinterpret_cast<ArrMeta<T>*>(ws + L.meta);
   const int64_t cap_cells = d->direct_cap_bytes > 0 ? d->direct_cap_bytes / 4 : 0;
-  build_hr_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(d->x_off_dev, d->q_off_dev,
-                                                                  static_cast<const T*>(d->X_dev), cap_cells, meta);
-  DS_HIP_CHECK(hipGetLastError());
-  ds_status st = launch_plan<T>(d, L, ws, tile, s);
+  ds_status st = launch_build<T, FORM>(d, meta, reinterpret_cast<int32_t*>(ws + L.chunk_first), cap_cells, s);
   if (st != DS_OK) return st;
-  rankcode_kernel<T, FORM><<<dim3(K), dim3(kBuildBlock), 0, s>>>(
-      static_cast<const T*>(d->X_dev), meta, reinterpret_cast<unsigned long long*>(ws + L.bits),
-      reinterpret_cast<uint32_t*>(ws + L.base), reinterpret_cast<uint16_t*>(ws + L.codes), wb);
-  DS_HIP_CHECK(hipGetLastError());
+  st = launch_plan<T>(d, L, ws, tile, s);
+  if (st != DS_OK) return st;
+  st = launch_rankcode<T, FORM>(d, L, ws, s);
+  if (st != DS_OK) return st;
   if (L.nseg > 0) {
     st = batched_learned_build(learned_of(d, L, ws), d->dtype, s);
     if (st != DS_OK) return st;

@@ -28,6 +28,10 @@ struct alignas(16) ArrMeta {
   int32_t n_updates;
   int32_t slot;     // learned: index of the array's model
   int32_t pad;
+  // build accumulators, merged by atomics across the chunks of the array
+  unsigned long long gbits;  // bits of the minimum rounded gap (a float >= 0)
+  uint32_t flags;            // 1 not finite, 2 not increasing, 4 X_i - X_0 not increasing
+  int32_t first_bad;         // first i whose cell equals that of X_{i-1} at the starting H
 };
 
 struct PlanTotals {

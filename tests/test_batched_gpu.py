@@ -132,6 +132,113 @@ def test_edge_arrays(ds):
         _assert_same(got, ref)
 
 
+def _growth_batch(rng, dt):
+    """Arrays where ComputeHR grows H two or more times (at the feasibility limit, with and
+    without filler keys), mixed with empty, one-value, tiny, mid-sized, infeasible and
+    unsorted arrays in random order, so that the build's 4096-value scan chunks start and end
+    inside arrays, at their ends and among runs of tiny arrays."""
+    arrays = []
+    # four chosen by growth in the subtraction form, four in the FMA form, four in the FMA
+    # form with X_0 < 0 (growth there is rarer: bounded tries)
+    for form, offset in ((oracle.FORM_SUB, False), (oracle.FORM_FMA, False), (oracle.FORM_FMA, True)):
+        found = 0
+        for _ in range(40_000):
+            X = W.near_limit_array(dt, rng, n_fill=int(rng.integers(0, 6000)), offset=offset)
+            t = oracle.compute_hr(X, form)
+            if t.status == oracle.OK and t.n_updates >= 2 and t.R < (1 << 26):
+                arrays.append(X)
+                found += 1
+                if found == 4:
+                    break
+        assert found == 4
+    for _ in range(10):
+        arrays.append(np.array([], dt))
+        arrays.append(np.array([rng.uniform(-5, 5)], dt))
+        arrays.append(W.gap_array(int(rng.integers(1, 40)), dt, rng, x0=rng.uniform(-100, 100)))
+    for _ in range(6):
+        arrays.append(W.gap_array(int(rng.integers(3000, 20000)), dt, rng, x0=rng.uniform(-100, 100)))
+    arrays.append(np.array([-1e9, 0.0, 1.0], dt))   # infeasible
+    arrays.append(np.array([0.0, 2.0, 1.0], dt))    # not increasing
+    order = rng.permutation(len(arrays))
+    arrays = [arrays[i] for i in order]
+    zs = []
+    for a in arrays:
+        if a.size == 0:
+            zs.append(np.array([0.0, np.nan], dt))
+            continue
+        u = rng.uniform(float(a[0]) - 1, float(a[-1]) + 1, 2000).astype(dt)
+        zs.append(np.concatenate([u, a, W.prev_float(a, dt), np.array([np.nan, np.inf, -np.inf], dt)]).astype(dt))
+    x_off = np.concatenate([[0], np.cumsum([a.size for a in arrays])]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum([q.size for q in zs])]).astype(np.int64)
+    return arrays, W.Batch(np.dtype(dt), x_off, np.concatenate(arrays).astype(dt), q_off, np.concatenate(zs))
+
+
+@pytest.mark.parametrize("form", ["sub", "fma"])
+def test_batched_build_growth_and_chunk_edges(ds, form):
+    """Per array the device build's method and R equal the oracle's ComputeHR (H grown up to
+    the float of the sequential algorithm), and every result equals the oracle's search; the
+    same from an X pointer that is not 16-byte aligned (the build reads it with scalar loads)."""
+    rng = np.random.default_rng(21)
+    arrays, b = _growth_batch(rng, np.float32)
+    budget = 1 << 29
+    bt, out = _run(ds, b, form=form, table_budget_entries=budget)
+    meth, R = bt.report()
+    fm = oracle.FORM_SUB if form == "sub" else oracle.FORM_FMA
+    grown = 0
+    for k, a in enumerate(arrays):
+        if a.size <= 1:
+            assert meth[k] == -2, k
+            continue
+        if not np.all(a[1:] > a[:-1]):
+            assert meth[k] == -1, k
+            continue
+        t = oracle.compute_hr(a, fm)
+        if t.status == oracle.OK and t.R < (1 << 26):
+            assert meth[k] == ds.METHOD_DIRECT and R[k] == t.R, (k, a.size, meth[k], R[k], t.R)
+            grown += t.n_updates >= 2
+        elif t.status != oracle.OK:
+            assert meth[k] == ds.METHOD_BSEARCH_OFFSET, k
+    assert grown >= 8
+    ref = _oracle_batch(b.x_off, b.X, b.q_off, b.z)
+    bad = [k for k, a in enumerate(arrays) if a.size > 1 and not np.all(a[1:] > a[:-1])]
+    for k in bad:
+        assert np.all(out[b.q_off[k]:b.q_off[k + 1]] == -2)
+        ref[b.q_off[k]:b.q_off[k + 1]] = -2
+    _assert_same(out, ref)
+    # the same batch from a pointer 4 bytes past a 16-byte boundary
+    pad = torch.empty(b.X.size + 1, dtype=torch.float32, device=DEV)
+    pad[1:] = _dev(b.X)
+    Xu = pad[1:]
+    assert Xu.data_ptr() % 16 == 4
+    bt2 = ds.Batch(_dev(b.x_off), Xu, _dev(b.q_off), _dev(b.z), form=form, table_budget_entries=budget)
+    _assert_same(bt2.run().cpu().numpy(), out)
+    meth2, R2 = bt2.report()
+    assert np.array_equal(meth2, meth) and np.array_equal(R2, R)
+
+
+def test_many_tiny_arrays_per_chunk(ds):
+    """20,000 arrays of 0 to 12 values: the build's 4096-value chunks hold about 2,000 arrays
+    each in the first half (more than its 1,024 LDS slots: per-lane global atomics) and about
+    500 in the second (merged in LDS); every result equals the oracle's search."""
+    rng = np.random.default_rng(31)
+    f32 = np.float32
+    sizes = np.concatenate([rng.integers(0, 5, 10_000), rng.integers(3, 13, 10_000)])
+    arrays, zs = [], []
+    for n in sizes:
+        a = W.gap_array(int(n) - 1, f32, rng, x0=rng.uniform(-50, 50)) if n > 0 else np.array([], f32)
+        arrays.append(a)
+        lo, hi = (float(a[0]) - 1, float(a[-1]) + 1) if a.size else (-1.0, 1.0)
+        zs.append(np.concatenate([rng.uniform(lo, hi, 6).astype(f32), a]).astype(f32))
+    x_off = np.concatenate([[0], np.cumsum([a.size for a in arrays])]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum([q.size for q in zs])]).astype(np.int64)
+    b = W.Batch(np.dtype(f32), x_off, np.concatenate(arrays).astype(f32), q_off, np.concatenate(zs))
+    for form in ("sub", "fma"):
+        bt, out = _run(ds, b, form=form)
+        meth, _ = bt.report()
+        assert np.all(meth[sizes <= 1] == -2) and np.all(meth[sizes >= 2] == ds.METHOD_DIRECT)
+        _assert_same(out, _oracle_batch(x_off, b.X, q_off, b.z))
+
+
 def test_no_table_room_uses_binary_search(ds):
     b = W.batched_f32(num_arrays=50, n_lo=8, n_hi=20000, q_per_n=8, seed=9)
     bt, out = _run(ds, b, table_budget_entries=0)
@@ -169,6 +276,24 @@ def test_autotune_keeps_results(ds, tmp_path):
     bt2 = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z))
     assert bt2.autotune(cache=cache) == best  # served from the cache
     _assert_same(ref, _oracle_batch(b.x_off, b.X, b.q_off, b.z))
+
+
+def test_autotune_with_tables_out_of_room(ds):
+    """The autotuner re-plans the query tiles for each candidate shape; arrays that the first
+    plan moved to binary search for lack of table room keep their method and the others keep
+    their table offsets, so the output it leaves equals the oracle's."""
+    b = W.batched_f32(num_arrays=80, n_lo=8, n_hi=20000, q_per_n=8, seed=14)
+    ref = _oracle_batch(b.x_off, b.X, b.q_off, b.z)
+    bt = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(b.q_off), _dev(b.z),
+                  table_budget_entries=int(np.sum(np.diff(b.x_off))) // 2)
+    _assert_same(bt.run().cpu().numpy(), ref)
+    meth, _ = bt.report()
+    assert (meth == ds.METHOD_DIRECT).any() and (meth == ds.METHOD_BSEARCH_OFFSET).any()
+    bt.autotune()
+    _assert_same(bt.out.cpu().numpy(), ref)   # the last candidate's search
+    meth2, _ = bt.report()
+    assert np.array_equal(meth2, meth)
+    _assert_same(bt.run().cpu().numpy(), ref)
 
 
 def test_graph_capture_replays(ds):
