@@ -660,17 +660,26 @@ __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, i
 
 // least-squares line of index against z for the keys of one segment (f64
 // sums over centred z), then the key errors over [lo, hi + 1].  One wave per
-// segment, reductions in a fixed order: segments hold tens to hundreds of keys,
-// so a wave reads them in one or a few rounds of independent loads (groups of
-// 16 lanes per segment took twice as long: more dependent load rounds).
+// segment and one segment per workgroup, so that a wave retires as soon as its
+// segment is done (segment sizes are very uneven: clusters route thousands of
+// keys to one segment while half the segments stay empty).  Reductions run in
+// a fixed order (lane i holds lo + i, lo + i + 64, ... or, over a long
+// segment, a + i, a + i + 64, ...).  Up to 128 keys the values are loaded
+// once for both passes; longer segments loop with 8 loads per lane in flight.
+// (Four segments per 256-lane workgroup took 1.2x as long, sixteen per
+// workgroup with the long ones shared by all its waves 2x, and a workgroup of
+// 1024 lanes per segment over 8192 keys, in a second launch, added more than it
+// saved: the many short segments, not the few long ones, set the time.)
 constexpr int kFitLanes = 64;
-constexpr int kFitSegsPerBlock = 256 / kFitLanes;
+constexpr int kFitRounds = 2;
+constexpr int kFitUnroll = 8;
 
 template <typename T>
-__global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, int64_t N,
-                                                      const int32_t* __restrict__ first, SegFit* __restrict__ segs,
-                                                      int32_t nseg, const LearnMeta* __restrict__ lm,
-                                                      const PlanTotals* __restrict__ tot) {
+__global__ void __launch_bounds__(kFitLanes) seg_fit_kernel(const T* __restrict__ X, int64_t N,
+                                                            const int32_t* __restrict__ first,
+                                                            SegFit* __restrict__ segs, int32_t nseg,
+                                                            const LearnMeta* __restrict__ lm,
+                                                            const PlanTotals* __restrict__ tot) {
   if (lm) {
     const int slot = blockIdx.y;
     if (slot >= tot->n_learned) return;
@@ -680,38 +689,47 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
     first += (int64_t)slot * (nseg + 1);
     segs += (int64_t)slot * nseg;
   }
-  const int s = blockIdx.x * kFitSegsPerBlock + (threadIdx.x / kFitLanes);
-  if (s >= nseg) return;  // uniform across the segment's lanes
-  const int lane = threadIdx.x % kFitLanes;
+  const int s = blockIdx.x;
+  const int lane = threadIdx.x;
   const int64_t a = first[s], b = first[s + 1];  // keys [a, b)
   const int64_t lo = std::max<int64_t>(0, std::min<int64_t>(a - 1, N - 1));
   const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(b - 1, N - 1));
   const int64_t c0 = (a < b) ? a : lo;
+  const int64_t last = std::min(hi + 1, N);  // the error pass covers [lo, last]
+  const bool fast = last - lo < kFitLanes * kFitRounds;
+  T v[kFitRounds];
+#pragma unroll
+  for (int r = 0; r < kFitRounds; ++r) {
+    const int64_t i = lo + lane + kFitLanes * r;
+    v[r] = (fast && i <= last) ? X[i] : T(0);
+  }
   const double zc = static_cast<double>(X[c0]);
   // n and the sum of (i - lo) over the keys [a, b) have closed forms
   const double n = static_cast<double>(b - a);
-  const double si_ = static_cast<double>(b - a) * (static_cast<double>(a + b - 1) * 0.5 - static_cast<double>(lo));
-  const int64_t last = std::min(hi + 1, N);  // the error pass covers [lo, last]
-  // usual case: [lo, last] fits one value per lane, loaded once for both passes
-  const bool one_round = last - lo < kFitLanes;
-  T xr = T(0);
-  if (one_round && lo + lane <= last) xr = X[lo + lane];
+  const double si_ = n * (static_cast<double>(a + b - 1) * 0.5 - static_cast<double>(lo));
   double sz = 0, szz = 0, siz = 0;
-  if (one_round) {
-    const int64_t i = lo + lane;
-    if (i >= a && i < b) {
-      const double dz = static_cast<double>(xr) - zc;
-      sz = dz;
-      szz = dz * dz;
-      siz = static_cast<double>(i - lo) * dz;
+  auto add = [&](int64_t i, T x) {
+    const double dz = static_cast<double>(x) - zc;
+    sz += dz;
+    szz += dz * dz;
+    siz += static_cast<double>(i - lo) * dz;
+  };
+  if (fast) {
+#pragma unroll
+    for (int r = 0; r < kFitRounds; ++r) {
+      const int64_t i = lo + lane + kFitLanes * r;
+      if (i >= a && i < b) add(i, v[r]);
     }
   } else {
-    for (int64_t i = a + lane; i < b; i += kFitLanes) {
-      const double dz = static_cast<double>(X[i]) - zc;
-      sz += dz;
-      szz += dz * dz;
-      siz += static_cast<double>(i - lo) * dz;
+    int64_t i = a + lane;
+    for (; i + (kFitUnroll - 1) * kFitLanes < b; i += kFitUnroll * kFitLanes) {
+      T x[kFitUnroll];
+#pragma unroll
+      for (int u = 0; u < kFitUnroll; ++u) x[u] = X[i + u * kFitLanes];
+#pragma unroll
+      for (int u = 0; u < kFitUnroll; ++u) add(i + u * kFitLanes, x[u]);
     }
+    for (; i < b; i += kFitLanes) add(i, X[i]);
   }
 #pragma unroll
   for (int o = kFitLanes / 2; o > 0; o >>= 1) {
@@ -719,7 +737,7 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
     szz += __shfl_xor(szz, o, kFitLanes);
     siz += __shfl_xor(siz, o, kFitLanes);
   }
-  // every lane of the group holds the same sums and computes the same fit
+  // every lane holds the same sums and computes the same fit
   double slope = 0, icpt = 0;
   if (n >= 2) {
     const double var = szz - sz * sz / n;
@@ -737,18 +755,27 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
   f.lo = static_cast<int32_t>(lo);
   f.hi = static_cast<int32_t>(hi);
   int32_t dmin = 1 << 30, dmax = -(1 << 30);
-  if (one_round) {
-    if (lo + lane <= last) {
-      const int32_t d = lane - seg_predict<T>(f, xr);
-      dmin = d;
-      dmax = d;
+  auto err = [&](int64_t i, T x) {
+    const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, x);
+    dmin = std::min(dmin, d);
+    dmax = std::max(dmax, d);
+  };
+  if (fast) {
+#pragma unroll
+    for (int r = 0; r < kFitRounds; ++r) {
+      const int64_t i = lo + lane + kFitLanes * r;
+      if (i <= last) err(i, v[r]);
     }
   } else {
-    for (int64_t i = lo + lane; i <= last; i += kFitLanes) {
-      const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, X[i]);
-      dmin = std::min(dmin, d);
-      dmax = std::max(dmax, d);
+    int64_t i = lo + lane;
+    for (; i + (kFitUnroll - 1) * kFitLanes <= last; i += kFitUnroll * kFitLanes) {
+      T x[kFitUnroll];
+#pragma unroll
+      for (int u = 0; u < kFitUnroll; ++u) x[u] = X[i + u * kFitLanes];
+#pragma unroll
+      for (int u = 0; u < kFitUnroll; ++u) err(i + u * kFitLanes, x[u]);
     }
+    for (; i <= last; i += kFitLanes) err(i, X[i]);
   }
 #pragma unroll
   for (int o = kFitLanes / 2; o > 0; o >>= 1) {
@@ -761,6 +788,7 @@ __global__ void __launch_bounds__(256) seg_fit_kernel(const T* __restrict__ X, i
     segs[s] = f;
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // search
@@ -1140,8 +1168,7 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
                                                                                    nullptr, nullptr);
   seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first,
                                                                                 nullptr, nullptr);
-  seg_fit_kernel<T><<<dim3((nseg + kFitSegsPerBlock - 1) / kFitSegsPerBlock), dim3(256), 0, s>>>(
-      X, N, L->first, L->segs, nseg, nullptr, nullptr);
+  seg_fit_kernel<T><<<dim3(nseg), dim3(kFitLanes), 0, s>>>(X, N, L->first, L->segs, nseg, nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
   std::vector<SegFit> host(nseg);
   DS_HIP_CHECK(hipMemcpyAsync(host.data(), L->segs, size_t(nseg) * sizeof(SegFit), hipMemcpyDeviceToHost, s));
@@ -1428,7 +1455,7 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
     route_keys_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, 0, b.nseg, 0, b.route, nullptr,
                                                               b.lmeta, b.tot);
   seg_first_kernel<<<dim3(64, K), dim3(256), 0, s>>>(b.route, 0, b.nseg, b.first, b.lmeta, b.tot);
-  seg_fit_kernel<T><<<dim3((b.nseg + kFitSegsPerBlock - 1) / kFitSegsPerBlock, K), dim3(256), 0, s>>>(
+  seg_fit_kernel<T><<<dim3(b.nseg, K), dim3(kFitLanes), 0, s>>>(
       static_cast<const T*>(b.X), 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
