@@ -849,21 +849,38 @@ __device__ __forceinline__ void stage_values(T* __restrict__ dst, const T* __res
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+// The queries [q0, q1) of one tile in chunks of 64 QPT, each taken by a wave
+// from the LDS counter *next*: a wave that started late (the one that claims
+// the next tile) just takes fewer chunks.
 template <typename T, int QPT, class Op>
 __device__ __forceinline__ void run_tile(const T* __restrict__ z, int32_t* __restrict__ out, int64_t q0, int64_t q1,
-                                         const Op& op) {
-  const int64_t B = blockDim.x;
-  int64_t q = q0 + threadIdx.x;
-  for (; q + (QPT - 1) * B < q1; q += QPT * B) {
-    T v[QPT];
+                                         const Op& op, int32_t* next) {
+  constexpr int64_t kChunkQ = 64 * QPT;
+  const int lane = threadIdx.x & 63;
+  const int64_t nchunks = (q1 - q0 + kChunkQ - 1) / kChunkQ;
+  for (;;) {
+    int c = 0;
+    if (lane == 0) c = atomicAdd(next, 1);
+    c = __shfl(c, 0, 64);
+    if (c >= nchunks) break;
+    const int64_t q = q0 + int64_t(c) * kChunkQ + lane;
+    if (q0 + (int64_t(c) + 1) * kChunkQ <= q1) {
+      T v[QPT];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) v[u] = __builtin_nontemporal_load(z + q + u * B);
+      for (int u = 0; u < QPT; ++u) v[u] = __builtin_nontemporal_load(z + q + u * 64);
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) __builtin_nontemporal_store(op(v[u]), out + q + u * B);
+      for (int u = 0; u < QPT; ++u) __builtin_nontemporal_store(op(v[u]), out + q + u * 64);
+    } else {
+      for (int64_t r = q; r < q1; r += 64) out[r] = op(z[r]);
+    }
   }
-  for (; q < q1; q += B) out[q] = op(z[q]);
 }
 
+// Persistent workgroups pull tiles from their XCD's queue.  Wave 0 claims the
+// next tile (queue atomic, then the tile's array by a 64-way search of the
+// tile offsets) while the other waves start on the current one; the claim
+// and the tile's chunk counter are double-buffered in LDS, so one barrier per
+// tile separates them.
 template <typename T, int FORM, int QPT>
 __global__ void __launch_bounds__(1024) batch_search_kernel(const ArrMeta<T>* __restrict__ meta, int32_t K,
                                                             const int64_t* __restrict__ tile_off,
@@ -874,97 +891,87 @@ __global__ void __launch_bounds__(1024) batch_search_kernel(const ArrMeta<T>* __
                                                             const T* __restrict__ z, int32_t* __restrict__ out,
                                                             SearchShape sh) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int64_t s_tile;
-  __shared__ int32_t s_k;
+  __shared__ int64_t s_tile[2];
+  __shared__ int32_t s_k[2];
+  __shared__ int32_t s_next[2];
   const int queue = blockIdx.x % kNumQueues;
   const int64_t total = tot->total_tiles;
   if (tot->learned_tiles == total) return;  // every tile belongs to a learned array
+  auto claim = [&](int slot) {  // by wave 0
+    unsigned long long li = 0;
+    if (threadIdx.x == 0) li = atomicAdd(&tot->queue[queue], 1u);
+    li = __shfl(li, 0, 64);
+    const int64_t ch = sh.chunk;
+    const int64_t g = ((int64_t(li) / ch) * kNumQueues + queue) * ch + (int64_t(li) % ch);
+    // the last array whose first tile is <= g
+    const int32_t k = (g < total) ? wave_last_le(tile_off, K, g) : -1;
+    if (threadIdx.x == 0) {
+      s_tile[slot] = g;
+      s_k[slot] = k;
+    }
+  };
+  if (threadIdx.x < 64) claim(0);
+  if (threadIdx.x == 0) s_next[0] = 0;
+  __syncthreads();
   int32_t cur = -1;
   bool staged = false;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      const int64_t li = atomicAdd(&tot->queue[queue], 1u);
-      const int64_t ch = sh.chunk;
-      const int64_t g = ((li / ch) * kNumQueues + queue) * ch + (li % ch);
-      int32_t k = -1;
-      if (g < total) {
-        // last array whose first tile is <= g
-        int32_t lo = 0, hi = K - 1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi + 1) >> 1;
-          if (tile_off[mid] <= g)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        k = lo;
-      }
-      s_tile = g;
-      s_k = k;
-    }
-    __syncthreads();
-    const int64_t g = s_tile;
-    const int32_t k = s_k;
-    __syncthreads();  // s_tile is rewritten in the next round
+  for (int b = 0;; b ^= 1) {
+    const int64_t g = s_tile[b];
+    const int32_t k = s_k[b];
     if (g >= total) break;
     const ArrMeta<T>& m = meta[k];
     const int64_t q0 = m.q_off + (g - m.t_off) * sh.tile;
     const int64_t q1 = std::min(m.q_end, q0 + sh.tile);
     const int64_t N = m.N;
-    if (m.method == DS_METHOD_DIRECT) {
-      const int64_t nW = m.nW;
-      const int64_t code_bytes = round16((N + 1) * 2);
-      const int64_t base_off = round16(nW * 8);
-      const int64_t code_off = base_off + round16(nW * 4);
-      const bool fits = code_off + code_bytes <= sh.lds_budget;
-      if (k != cur) {
-        if (fits) {
-          __syncthreads();
+    // the tables of a new array go to LDS when they fit (every wave is past the
+    // previous tile's end barrier)
+    const int64_t nW = m.nW;
+    const int64_t base_off = round16(nW * 8);
+    const int64_t code_off = base_off + round16(nW * 4);
+    if (k != cur) {
+      if (m.method == DS_METHOD_DIRECT) {
+        staged = code_off + round16((N + 1) * 2) <= sh.lds_budget;
+        if (staged) {
           stage_bytes(smem, reinterpret_cast<const unsigned char*>(bits + m.w_off), nW * 8);
           stage_bytes(smem + base_off, reinterpret_cast<const unsigned char*>(base + m.w_off), nW * 4);
-          stage_bytes(smem + code_off, reinterpret_cast<const unsigned char*>(codes + m.c_off), code_bytes);
-          __syncthreads();
+          stage_bytes(smem + code_off, reinterpret_cast<const unsigned char*>(codes + m.c_off), round16((N + 1) * 2));
         }
-        cur = k;
-        staged = fits;
+      } else if (m.method == DS_METHOD_BSEARCH_OFFSET) {
+        staged = (N + 1) * int64_t(sizeof(T)) <= sh.lds_budget;
+        if (staged) stage_values(reinterpret_cast<T*>(smem), Xp + m.x_off, N + 1);
       }
+      cur = k;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) s_next[b ^ 1] = 0;
+    if (threadIdx.x < 64) claim(b ^ 1);
+    if (m.method == DS_METHOD_DIRECT) {
       const T vlo = T(m.jmin), vhi = T(m.R);
       if (staged) {
         RankCodeOp<T, FORM, false> op{reinterpret_cast<const uint64_t*>(smem),
                                       reinterpret_cast<const uint32_t*>(smem + base_off), nullptr,
                                       reinterpret_cast<const uint16_t*>(smem + code_off), Xp + m.x_off, m.H, m.W,
                                       m.X0, vlo, vhi, m.XN, m.jmin, m.N};
-        run_tile<T, QPT>(z, out, q0, q1, op);
+        run_tile<T, QPT>(z, out, q0, q1, op, &s_next[b]);
       } else {
         RankCodeOp<T, FORM, false> op{reinterpret_cast<const uint64_t*>(bits + m.w_off), base + m.w_off, nullptr,
                                       codes + m.c_off, Xp + m.x_off, m.H, m.W, m.X0, vlo, vhi, m.XN, m.jmin, m.N};
-        run_tile<T, QPT>(z, out, q0, q1, op);
+        run_tile<T, QPT>(z, out, q0, q1, op, &s_next[b]);
       }
-    } else if (m.method == DS_METHOD_LEARNED) {
-      continue;  // searched by the learned kernel
     } else if (m.method == DS_METHOD_BSEARCH_OFFSET) {
-      const bool fits = (N + 1) * int64_t(sizeof(T)) <= sh.lds_budget;
-      if (k != cur) {
-        if (fits) {
-          __syncthreads();
-          stage_values(reinterpret_cast<T*>(smem), Xp + m.x_off, N + 1);
-          __syncthreads();
-        }
-        cur = k;
-        staged = fits;
-      }
       const int32_t F = static_cast<int32_t>((N + 1) / 2);
       const int32_t S = static_cast<int32_t>(N + 1 - F);
       int32_t J = 0;
       while ((int64_t(1) << (J + 1)) <= N + 1) ++J;
       OffsetOp<T> op{staged ? reinterpret_cast<const T*>(smem) : Xp + m.x_off, F, S, J};
-      run_tile<T, QPT>(z, out, q0, q1, op);
-    } else {
+      run_tile<T, QPT>(z, out, q0, q1, op, &s_next[b]);
+    } else if (m.method != DS_METHOD_LEARNED) {  // learned tiles are searched by the learned kernel
       const int32_t fill = (m.method == kBmInvalid) ? -2 : -1;
       const bool one = (m.method == kBmTrivial && N == 0);
       const T x0 = m.X0;
       for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) out[q] = (one && z[q] >= x0) ? 0 : fill;
     }
+    __syncthreads();  // the tile is done and the next one claimed
   }
 }
 

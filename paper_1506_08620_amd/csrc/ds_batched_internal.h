@@ -81,6 +81,23 @@ struct BatchLearned {
   void* samples;           // first value of every 64-byte block of X, then +inf
 };
 
+// The largest k in [0, n) with off[k] <= g (off non-decreasing, off[0] <= g),
+// found by one whole wave with 64 probes per round: log64 n dependent loads
+// instead of log2 n.  Every lane of the wave must call it; all get the answer.
+__device__ __forceinline__ int32_t wave_last_le(const int64_t* __restrict__ off, int32_t n, int64_t g) {
+  const int lane = threadIdx.x & 63;
+  int32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int32_t stride = (hi - lo + 63) / 64;
+    const int64_t p = int64_t(lo) + int64_t(lane) * stride;
+    // the probes at or below the answer are a prefix of the lanes
+    const int c = __popcll(__ballot(p < hi && off[p] <= g));
+    lo += (c > 0 ? c - 1 : 0) * stride;
+    hi = (hi - lo < stride) ? hi : lo + stride;
+  }
+  return lo;
+}
+
 // implemented in ds_learned.hip
 ds_status batched_learned_build(const BatchLearned& b, int dtype, hipStream_t s);
 ds_status batched_learned_search(const BatchLearned& b, int dtype, hipStream_t s);

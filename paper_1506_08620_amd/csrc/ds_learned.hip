@@ -1323,35 +1323,30 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
   RouterRegs R;
   int32_t cur = -1;
   for (;;) {
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {  // wave 0 claims the next tile
       // Each queue (one per XCD) owns a contiguous eighth of the tile order,
       // so the workgroups of one XCD share the few arrays of their range in
       // that XCD's L2; a queue whose range is done takes from the next ones.
-      int64_t g = total;
-      for (int t = 0; t < kNumQueues; ++t) {
-        const int qq = (queue + t) % kNumQueues;
-        const int64_t lo = total * qq / kNumQueues, hi = total * (qq + 1) / kNumQueues;
-        const int64_t li = atomicAdd(&b.tot->lqueue[qq], 1u);
-        if (lo + li < hi) {
-          g = lo + li;
-          break;
+      long long gl = total;
+      if (threadIdx.x == 0) {
+        for (int t = 0; t < kNumQueues; ++t) {
+          const int qq = (queue + t) % kNumQueues;
+          const int64_t lo = total * qq / kNumQueues, hi = total * (qq + 1) / kNumQueues;
+          const int64_t li = atomicAdd(&b.tot->lqueue[qq], 1u);
+          if (lo + li < hi) {
+            gl = lo + li;
+            break;
+          }
         }
       }
-      int32_t k = -1;
-      if (g < total) {
-        int32_t lo = 0, hi = b.K - 1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi + 1) >> 1;
-          if (b.tile_off[mid] <= g)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        k = lo;
+      const int64_t g = __shfl(gl, 0, 64);
+      // the last array whose first tile is <= g
+      const int32_t k = (g < total) ? wave_last_le(b.tile_off, b.K, g) : -1;
+      if (threadIdx.x == 0) {
+        s_tile = g;
+        s_k = k;
+        s_grp = 0;
       }
-      s_tile = g;
-      s_k = k;
-      s_grp = 0;
     }
     __syncthreads();
     const int64_t g = s_tile;
