@@ -1310,9 +1310,11 @@ constexpr int batch_learned_block() { return F16 ? 1024 : 768; }
 template <typename T, bool F16>
 __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_search_kernel(BatchLearned b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int64_t s_tile;
-  __shared__ int32_t s_k;
-  __shared__ int32_t s_grp;  // next 64-query group of the current tile
+  // the current and the next tile (claimed by wave 0 while the others work),
+  // with their 64-query group counters
+  __shared__ int64_t s_tile[2];
+  __shared__ int32_t s_k[2];
+  __shared__ int32_t s_grp[2];
   const ArrMeta<T>* meta = static_cast<const ArrMeta<T>*>(b.meta);
   const int queue = blockIdx.x % kNumQueues;
   const int64_t total = b.tot->total_tiles;
@@ -1321,42 +1323,43 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
   __shared__ RouterShared16 S;  // FP16 router: half-wave-uniform values
   half4 w2[4];
   RouterRegs R;
-  int32_t cur = -1;
-  for (;;) {
-    if (threadIdx.x < 64) {  // wave 0 claims the next tile
-      // Each queue (one per XCD) owns a contiguous eighth of the tile order,
-      // so the workgroups of one XCD share the few arrays of their range in
-      // that XCD's L2; a queue whose range is done takes from the next ones.
-      long long gl = total;
-      if (threadIdx.x == 0) {
-        for (int t = 0; t < kNumQueues; ++t) {
-          const int qq = (queue + t) % kNumQueues;
-          const int64_t lo = total * qq / kNumQueues, hi = total * (qq + 1) / kNumQueues;
-          const int64_t li = atomicAdd(&b.tot->lqueue[qq], 1u);
-          if (lo + li < hi) {
-            gl = lo + li;
-            break;
-          }
+  auto claim_tile = [&](int slot) {  // by wave 0
+    // Each queue (one per XCD) owns a contiguous eighth of the tile order,
+    // so the workgroups of one XCD share the few arrays of their range in
+    // that XCD's L2; a queue whose range is done takes from the next ones.
+    long long gl = total;
+    if (threadIdx.x == 0) {
+      for (int t = 0; t < kNumQueues; ++t) {
+        const int qq = (queue + t) % kNumQueues;
+        const int64_t lo = total * qq / kNumQueues, hi = total * (qq + 1) / kNumQueues;
+        const int64_t li = atomicAdd(&b.tot->lqueue[qq], 1u);
+        if (lo + li < hi) {
+          gl = lo + li;
+          break;
         }
       }
-      const int64_t g = __shfl(gl, 0, 64);
-      // the last array whose first tile is <= g
-      const int32_t k = (g < total) ? wave_last_le(b.tile_off, b.K, g) : -1;
-      if (threadIdx.x == 0) {
-        s_tile = g;
-        s_k = k;
-        s_grp = 0;
-      }
     }
-    __syncthreads();
-    const int64_t g = s_tile;
-    const int32_t k = s_k;
-    __syncthreads();
+    const int64_t g = __shfl(gl, 0, 64);
+    // the last array whose first tile is <= g
+    const int32_t k = (g < total) ? wave_last_le(b.tile_off, b.K, g) : -1;
+    if (threadIdx.x == 0) {
+      s_tile[slot] = g;
+      s_k[slot] = k;
+    }
+  };
+  if (threadIdx.x < 64) claim_tile(0);
+  if (threadIdx.x == 0) s_grp[0] = 0;
+  __syncthreads();
+  int32_t cur = -1;
+  for (int bf = 0;; bf ^= 1) {
+    const int64_t g = s_tile[bf];
+    const int32_t k = s_k[bf];
     if (g >= total) break;
     const ArrMeta<T>& m = meta[k];
-    if (m.method != DS_METHOD_LEARNED) continue;
+    const bool learned = m.method == DS_METHOD_LEARNED;
     const int32_t slot = m.slot;
-    if (slot != cur) {
+    if (learned && slot != cur) {
+      // every wave is past the previous tile's end barrier
       stage_bytes(smem, static_cast<const unsigned char*>(b.segs) + (int64_t)slot * b.nseg * kSegFitBytes,
                   int64_t(b.nseg) * kSegFitBytes);
       if constexpr (F16)
@@ -1365,6 +1368,12 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
         load_router(b.params + (int64_t)slot * kParams, R);
       __syncthreads();
       cur = slot;
+    }
+    if (threadIdx.x == 0) s_grp[bf ^ 1] = 0;
+    if (threadIdx.x < 64) claim_tile(bf ^ 1);
+    if (!learned) {
+      __syncthreads();  // the next tile is claimed
+      continue;
     }
     const LearnMeta lm = b.lmeta[slot];
     LearnedArgs<T> a{};
@@ -1384,7 +1393,7 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
     // queries loaded before the current one is worked on
     auto claim = [&]() {
       int32_t c = 0;
-      if (lane == 0) c = atomicAdd(&s_grp, 1);
+      if (lane == 0) c = atomicAdd(&s_grp[bf], 1);
       return __shfl(c, 0, 64);
     };
     int32_t gi = claim();
@@ -1416,7 +1425,8 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
       zq = z_next;
       gi = gn;
     }
-    __syncthreads();  // every wave is done with this array's tables before they may change
+    __syncthreads();  // every wave is done with this array's tables before they may change, and the next tile
+                      // is claimed
   }
 }
 
