@@ -77,7 +77,6 @@ struct BatchLearned {
   void* segs;              // [K][nseg] segment fits
   int32_t* first;          // [K][nseg + 1]
   float* feat;             // [total_x]
-  int32_t* route;          // [total_x]
   void* samples;           // first value of every 64-byte block of X, then +inf
 };
 

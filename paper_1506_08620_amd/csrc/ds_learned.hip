@@ -610,17 +610,7 @@ template <bool F16>
 __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict__ params,
                                                          const float* __restrict__ feat, int64_t n,
                                                          int32_t nseg, int32_t identity, int32_t* __restrict__ route,
-                                                         float* __restrict__ y_out, const LearnMeta* __restrict__ lm,
-                                                         const PlanTotals* __restrict__ tot) {
-  if (lm) {
-    const int slot = blockIdx.y;
-    if (slot >= tot->n_learned) return;
-    const LearnMeta L = lm[slot];
-    params += (int64_t)slot * kParams;
-    feat += L.x_off;
-    route += L.x_off;
-    n = L.N + 1;
-  }
+                                                         float* __restrict__ y_out) {
   typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
   if constexpr (F16)
     load_router16(params, R);
@@ -641,20 +631,68 @@ __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict
 
 // first[s] = #{i : route_i < s} for s in [0, nseg]
 __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, int32_t nseg,
-                                 int32_t* __restrict__ first, const LearnMeta* __restrict__ lm,
-                                 const PlanTotals* __restrict__ tot) {
-  if (lm) {
-    const int slot = blockIdx.y;
-    if (slot >= tot->n_learned) return;
-    const LearnMeta L = lm[slot];
-    route += L.x_off;
-    first += (int64_t)slot * (nseg + 1);
-    n = L.N + 1;
-  }
+                                 int32_t* __restrict__ first) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t prev = (i == 0) ? -1 : route[i - 1];
     const int32_t cur = (i == n) ? nseg : route[i];
     for (int32_t s = prev + 1; s <= cur; ++s) first[s] = static_cast<int32_t>(i);
+  }
+}
+
+// The batched form of route_keys_kernel + seg_first_kernel in one pass, with
+// no per-key route array: each wave takes a contiguous range of at least 8
+// of the array's 64-key groups, and each key i routed to segment r with its
+// predecessor in segment p writes first[s] = i for s in (p, r]; the last key
+// also writes first[s] = n for s above its segment.  A lane's predecessor is
+// the lane before it or, for lane 0, the last key of the previous group (the
+// wave routes the group before its range first).  The next group's features
+// are loaded before the current group is routed.  Routing is the same code as
+// route_keys_kernel.  (Waves taking groups in lockstep, four at a time with
+// the predecessors passed through LDS, ran 1.1x slower than the two kernels.)
+template <bool F16>
+__global__ void __launch_bounds__(256) route_first_kernel(const float* __restrict__ params,
+                                                          const float* __restrict__ feat, int32_t nseg,
+                                                          int32_t* __restrict__ first,
+                                                          const LearnMeta* __restrict__ lm,
+                                                          const PlanTotals* __restrict__ tot) {
+  const int slot = blockIdx.y;
+  if (slot >= tot->n_learned) return;
+  const LearnMeta L = lm[slot];
+  params += (int64_t)slot * kParams;
+  feat += L.x_off;
+  first += (int64_t)slot * (nseg + 1);
+  const int64_t n = int64_t(L.N) + 1;  // keys
+  const int64_t ngroups = (n + 63) / 64;
+  const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
+  const int64_t per = std::max<int64_t>((ngroups + waves - 1) / waves, 8);
+  const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x / 64)) * per;
+  const int64_t g1 = std::min(ngroups, g0 + per);
+  if (g0 >= g1) return;  // uniform across the wave; no barrier below
+  typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
+  if constexpr (F16)
+    load_router16(params, R);
+  else
+    load_router(params, R);
+  const int lane = threadIdx.x & 63;
+  auto segment = [&](float u) { return segment_of(route_coord(route_pair<F16>(u, &R), u), nseg); };
+  auto feature_at = [&](int64_t i) { return i < n ? feat[i] : 1.0f; };
+  // the key before the range (group g0 - 1 is whole)
+  int32_t carry = -1;
+  if (g0 > 0) carry = __shfl(segment(feat[(g0 - 1) * 64 + lane]), 63, 64);
+  float u_next = feature_at(g0 * 64 + lane);
+  for (int64_t grp = g0; grp < g1; ++grp) {
+    const float u = u_next;
+    if (grp + 1 < g1) u_next = feature_at((grp + 1) * 64 + lane);
+    const int64_t i = grp * 64 + lane;
+    const int32_t r = segment(u);
+    int32_t p = __shfl_up(r, 1, 64);
+    if (lane == 0) p = carry;
+    if (i < n) {
+      for (int32_t sg = p + 1; sg <= r; ++sg) first[sg] = static_cast<int32_t>(i);
+      if (i == n - 1)
+        for (int32_t sg = r + 1; sg <= nseg; ++sg) first[sg] = static_cast<int32_t>(n);
+    }
+    carry = __shfl(r, 63, 64);  // used only when the group is whole
   }
 }
 
@@ -1161,13 +1199,11 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   // route the keys with the search-time router, then segments, fits and bounds
   if (L->f16)
     route_keys_kernel<true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
-                                                                                  L->identity, L->route, nullptr, nullptr, nullptr);
+                                                                                  L->identity, L->route, nullptr);
   else
     route_keys_kernel<false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
-                                                                                   L->identity, L->route, nullptr,
-                                                                                   nullptr, nullptr);
-  seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first,
-                                                                                nullptr, nullptr);
+                                                                                   L->identity, L->route, nullptr);
+  seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first);
   seg_fit_kernel<T><<<dim3(nseg), dim3(kFitLanes), 0, s>>>(X, N, L->first, L->segs, nseg, nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
   std::vector<SegFit> host(nseg);
@@ -1454,12 +1490,9 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
   }
   DS_HIP_CHECK(hipGetLastError());
   if (b.fp32_router)
-    route_keys_kernel<false><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, 0, b.nseg, 0, b.route, nullptr,
-                                                               b.lmeta, b.tot);
+    route_first_kernel<false><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, b.nseg, b.first, b.lmeta, b.tot);
   else
-    route_keys_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, 0, b.nseg, 0, b.route, nullptr,
-                                                              b.lmeta, b.tot);
-  seg_first_kernel<<<dim3(64, K), dim3(256), 0, s>>>(b.route, 0, b.nseg, b.first, b.lmeta, b.tot);
+    route_first_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, b.nseg, b.first, b.lmeta, b.tot);
   seg_fit_kernel<T><<<dim3(b.nseg, K), dim3(kFitLanes), 0, s>>>(
       static_cast<const T*>(b.X), 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot);
   DS_HIP_CHECK(hipGetLastError());
@@ -1540,10 +1573,10 @@ ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_
   if (hipMalloc(&route, size_t(n) * 4) != hipSuccess) return DS_ERR_OOM;
   if (fp16_router)
     ds::route_keys_kernel<true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0,
-                                                                                      route, y_dev, nullptr, nullptr);
+                                                                                      route, y_dev);
   else
     ds::route_keys_kernel<false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(params_dev, u_dev, n, 4096, 0,
-                                                                                       route, y_dev, nullptr, nullptr);
+                                                                                       route, y_dev);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(route);
