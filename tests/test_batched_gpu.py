@@ -239,6 +239,30 @@ def test_many_tiny_arrays_per_chunk(ds):
         _assert_same(out, _oracle_batch(x_off, b.X, q_off, b.z))
 
 
+@pytest.mark.parametrize("learn", [0, 64])
+def test_batches_without_keys_or_queries(ds, learn):
+    """Every array empty (no packed key at all: the build's chunked passes have nothing to
+    scan), and a batch with keys but no query; with and without learned models."""
+    f32 = np.float32
+    x_off = np.zeros(4, np.int64)
+    q_off = np.array([0, 3, 3, 5], np.int64)
+    z = np.array([0.0, np.nan, -1.0, 2.0, np.inf], f32)
+    bt = ds.Batch(_dev(x_off), torch.empty(0, dtype=torch.float32, device=DEV), _dev(q_off), _dev(z),
+                  learn_segments=learn)
+    assert np.all(bt.run().cpu().numpy() == -1)
+    meth, _ = bt.report()
+    assert np.all(meth == -2)
+    b = W.batched_f32(num_arrays=20, n_lo=8, n_hi=3000, q_per_n=1, seed=15)
+    q_none = np.zeros(21, np.int64)
+    bt2 = ds.Batch(_dev(b.x_off), _dev(b.X), _dev(q_none), torch.empty(0, dtype=torch.float32, device=DEV),
+                   learn_segments=learn)
+    assert bt2.run().numel() == 0
+    meth2, R2 = bt2.report()
+    assert np.all(meth2 == ds.METHOD_DIRECT)
+    for k in range(0, 20, 7):
+        assert R2[k] == oracle.compute_hr(b.array(k)).R
+
+
 def test_no_table_room_uses_binary_search(ds):
     b = W.batched_f32(num_arrays=50, n_lo=8, n_hi=20000, q_per_n=8, seed=9)
     bt, out = _run(ds, b, table_budget_entries=0)
