@@ -147,7 +147,7 @@ def main():
 
     # per-launch kernel times with HIP events on the launch stream (separate pass)
     # (steps back to back, as in the timed region, so that no case starts on an idle GPU)
-    per = [[0.0, 0] for _ in cases]
+    per = [[] for _ in cases]
     evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cases]
            for _ in range(args.steps)]
     for ev in evs:
@@ -155,22 +155,29 @@ def main():
     torch.cuda.synchronize()
     for ev in evs:
         for k, (a, b) in enumerate(ev):
-            per[k][0] += a.elapsed_time(b)
-            per[k][1] += 1
+            per[k].append(a.elapsed_time(b))
 
     total_q = M * len(cases) * args.steps
     value = total_q / wall / 1e9
     case_rows = []
     groups = {}
     for k, c in enumerate(cases):
-        ms = per[k][0] / per[k][1]
+        ms = float(np.mean(per[k]))
+        ms_med, ms_min = float(np.median(per[k])), float(np.min(per[k]))
         S = np.dtype(c["dt"]).itemsize
         bytes_per_launch = M * (S + 4)
         inf = c["idx"].info()
-        row = dict(N=c["n"], dtype="f32" if S == 4 else "f64", gq_s=round(M / ms / 1e6, 2),
+        dts = "f32" if S == 4 else "f64"
+        row = dict(N=c["n"], dtype=dts, gq_s=round(M / ms / 1e6, 2),
+                   gq_s_median=round(M / ms_med / 1e6, 2), gq_s_best=round(M / ms_min / 1e6, 2),
                    gbs=round(bytes_per_launch / ms / 1e6, 1), hbm_frac=round(bytes_per_launch / ms / 1e6 / HBM_PEAK_GBS, 4),
-                   kernel_ms=round(ms, 5), layout=STAGE_NAMES[inf["staged"]], R=inf["R"],
+                   kernel_ms=round(ms, 5), kernel_ms_median=round(ms_med, 5), kernel_ms_min=round(ms_min, 5),
+                   layout=STAGE_NAMES[inf["staged"]], R=inf["R"],
                    table_bytes=inf["table_bytes"], build_ns_per_elem=round(c["build_s"] * 1e9 / (c["n"] + 1), 2))
+        # HBM bytes this case's launch moved by the committed counters (FETCH_SIZE + WRITE_SIZE)
+        hbm = measured_traffic(dts, [c["n"]], row["layout"])
+        row["measured_hbm_bytes"] = None if hbm is None else int(hbm)
+        row["measured_hbm_gbs"] = None if hbm is None else round(hbm / ms / 1e6, 1)
         case_rows.append(row)
         key = (row["dtype"], row["layout"])
         g = groups.setdefault(key, [0.0, 0, 0, []])
@@ -210,14 +217,27 @@ def main():
         cpu = dict(value=round(sample * len(cases) / cpu_t / 1e9, 4), unit="Gqueries/s", cores=threads,
                    kind="oracle", sample=f"first {sample} queries of each of the {len(cases)} (N, dtype) cases, "
                                           f"classic binary search, {threads} OpenMP threads")
+        # one core, as the paper's single-core Classic figures
+        sample1 = max(1, sample // 16)
+        cpu_t1 = 0.0
+        for c in cases:
+            zs = c["z"][:sample1].cpu().numpy()
+            t1 = time.perf_counter()
+            oracle.search(c["X"], zs, nthreads=1)
+            cpu_t1 += time.perf_counter() - t1
+        cpu1 = dict(value=round(sample1 * len(cases) / cpu_t1 / 1e9, 4), unit="Gqueries/s", cores=1, kind="oracle",
+                    sample=f"first {sample1} queries of each of the {len(cases)} cases, classic binary search, "
+                           f"1 thread")
     except Exception as e:  # the CPU leg must not hide the GPU figure
         cpu = dict(value=None, unit="Gqueries/s", cores=0, kind="oracle", sample=f"failed: {e}")
+        cpu1 = None
 
     extras = {}
     if not args.no_extras:
         extras = compare_methods(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
         extras["uses"] = bench_uses(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
     direct_f64_2p20 = next((r["gq_s"] for r in case_rows if r["N"] == 1 << 20 and r["dtype"] == "f64"), None)
+    n_cases = len(cases)
     for c in cases:  # free the sweep's buffers first
         c["idx"].destroy()
     cases.clear()
@@ -243,9 +263,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"direct-sweep: N in {sizes} x {{f32, f64}}, gaps U(0.5,1.5) scaled to [0,1], "
                                f"M={M} uniform queries per case, subtraction form",
-                   "queries_per_step": M * len(cases)},
+                   "queries_per_step": M * n_cases},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
         "parity_sample_bit_exact": parity,
         "cases": case_rows,
         **extras,
