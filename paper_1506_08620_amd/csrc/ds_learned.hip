@@ -578,8 +578,17 @@ __global__ void __launch_bounds__(1024) adam_kernel(float* __restrict__ params, 
     partial += (int64_t)slot * n_parts * kParams;
   }
   for (int k = threadIdx.x; k < kParams; k += blockDim.x) {
+    // the parts in order, eight loads in flight at a time
     float g = 0.0f;
-    for (int b = 0; b < n_parts; ++b) g += partial[(int64_t)b * kParams + k];
+    int b = 0;
+    for (; b + 8 <= n_parts; b += 8) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = partial[(int64_t)(b + u) * kParams + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) g += x[u];
+    }
+    for (; b < n_parts; ++b) g += partial[(int64_t)b * kParams + k];
     if (grad_out) {
       grad_out[k] = g;
       continue;
