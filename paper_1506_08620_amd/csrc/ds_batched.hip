@@ -242,6 +242,12 @@ __device__ __forceinline__ ChunkArrays scan_pairs(const int64_t* __restrict__ x_
   constexpr int U = static_cast<int>(kScanChunk / (kScanBlock * V));
   const int64_t c0 = int64_t(blockIdx.x) * kScanChunk;
   const int64_t c1 = std::min(c0 + kScanChunk, total_x);
+  ChunkArrays ca;
+  if constexpr (Vis::kLookFirst) {
+    // a visitor that may skip the whole chunk looks before it loads
+    ca = chunk_arrays(x_off, K, chunk_first, total_x);
+    if (vis.skip(ca)) return ca;
+  }
   T v[U][V], nx[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -249,7 +255,7 @@ __device__ __forceinline__ ChunkArrays scan_pairs(const int64_t* __restrict__ x_
     load_group<T, VECLOAD>(X, g0, total_x, v[u]);
     nx[u] = (g0 + V < total_x) ? X[g0 + V] : T(0);
   }
-  const ChunkArrays ca = chunk_arrays(x_off, K, chunk_first, total_x);
+  if constexpr (!Vis::kLookFirst) ca = chunk_arrays(x_off, K, chunk_first, total_x);
   vis.prepare(ca, g_slots, f_slots);
   int32_t k = ca.k0;
   int64_t end = x_off[k + 1];  // one past array k's last value
@@ -275,6 +281,7 @@ __device__ __forceinline__ ChunkArrays scan_pairs(const int64_t* __restrict__ x_
 
 template <typename T>
 struct GapVis {
+  static constexpr bool kLookFirst = false;  // every chunk is scanned
   ArrMeta<T>* meta;
   unsigned long long* s_g;  // per-array slots in LDS for a chunk of many arrays, else null
   uint32_t* s_f;
@@ -399,6 +406,11 @@ struct FirstBadVis {
   T H, W, x0;
   int64_t base;
   bool active;
+  // a chunk inside one array that is not Direct at the starting H is skipped
+  static constexpr bool kLookFirst = true;
+  __device__ __forceinline__ bool skip(const ChunkArrays& ca) const {
+    return ca.one && meta[ca.k0].method != DS_METHOD_DIRECT;
+  }
   __device__ __forceinline__ void prepare(const ChunkArrays&, unsigned long long*, uint32_t*) {}
   __device__ __forceinline__ void begin(int32_t kk) {
     k = kk;
