@@ -39,6 +39,7 @@ namespace ds {
 namespace {
 
 constexpr int kPlanBlock = 1024;
+constexpr int64_t kScanChunk = 4096;  // packed values per workgroup of the build's passes over the keys
 constexpr int kMaxGrowthRounds = 4096;
 
 struct WsLayout {
@@ -61,7 +62,7 @@ WsLayout ws_layout(int32_t K, int64_t total_x, int64_t words_budget, int32_t nse
     return at;
   };
   L.meta = take(size_t(K) * sizeof(ArrMeta<double>));
-  L.chunk_first = take(size_t((total_x + 4095) / 4096 + 1) * 4);
+  L.chunk_first = take(size_t((total_x + kScanChunk - 1) / kScanChunk + 1) * 4);
   L.tile_off = take(size_t(K + 1) * sizeof(int64_t));
   L.totals = take(sizeof(PlanTotals));
   L.codes_cap = total_x + int64_t(K) * 8 + 8;
@@ -115,11 +116,11 @@ __device__ __forceinline__ T next_up_dev(T x) {
 //   start      one thread per array: H = the float above 1 / min gap, W, and
 //              the start's feasibility
 //   first_bad  one workgroup per 4096 values: the first pair of each array
-//              whose cells coincide at the starting H (atomic minimum)
+//              whose cells coincide at the starting H (atomic minimum);
+//              a chunk of an array that is not Direct there is skipped
 //   finish     one workgroup per array: ComputeHR's growth from that pair
 //              on, for the arrays that have one; R, jmin, the table size
 constexpr int kScanBlock = 256;
-constexpr int64_t kScanChunk = 4096;  // packed values per scan workgroup (4096 is also the workspace's chunk size)
 constexpr int kScanSlots = 1024;      // arrays of a chunk accumulated in LDS before the global atomics
 constexpr int kFinishBlock = 256;
 constexpr int32_t kNoPair = 0x7fffffff;
