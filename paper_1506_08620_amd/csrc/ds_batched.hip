@@ -621,21 +621,39 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
   const int32_t ke = static_cast<int32_t>(std::min<int64_t>(K, int64_t(kb) + per));
   // pass 1: Direct over the per-array table cap is treated like an infeasible
   // array; the lane's table words, codes and tiles
+  // (four arrays at a time, their fields loaded before any is used: the loop is bound by load latency)
+  constexpr int kPlanBatch = 4;
+  struct Fields {
+    int32_t method, R, jmin, nW, N;
+    int64_t q_off, q_end;
+  };
+  auto fields = [&](int32_t k0, Fields (&f)[kPlanBatch]) {
+#pragma unroll
+    for (int u = 0; u < kPlanBatch; ++u) {
+      const ArrMeta<T>& m = meta[std::min(k0 + u, ke - 1)];
+      f[u] = Fields{m.method, m.R, m.jmin, m.nW, m.N, m.q_off, m.q_end};
+    }
+  };
   int64_t sw = 0, sc = 0, st = 0;
-  for (int32_t k = kb; k < ke; ++k) {
-    ArrMeta<T>& m = meta[k];
-    int32_t method = m.method;
-    if (!tiles_only) {
-      if (method == DS_METHOD_DIRECT && direct_cap_cells > 0 && int64_t(m.R) - m.jmin + 1 > direct_cap_cells)
-        method = DS_METHOD_BSEARCH_OFFSET;
-      if (learn && method == DS_METHOD_BSEARCH_OFFSET) method = DS_METHOD_LEARNED;
-      if (method != m.method) m.method = method;
+  for (int32_t k0 = kb; k0 < ke; k0 += kPlanBatch) {
+    Fields f[kPlanBatch];
+    fields(k0, f);
+#pragma unroll
+    for (int u = 0; u < kPlanBatch; ++u) {
+      if (k0 + u >= ke) break;
+      int32_t method = f[u].method;
+      if (!tiles_only) {
+        if (method == DS_METHOD_DIRECT && direct_cap_cells > 0 && int64_t(f[u].R) - f[u].jmin + 1 > direct_cap_cells)
+          method = DS_METHOD_BSEARCH_OFFSET;
+        if (learn && method == DS_METHOD_BSEARCH_OFFSET) method = DS_METHOD_LEARNED;
+        if (method != f[u].method) meta[k0 + u].method = method;
+      }
+      if (method == DS_METHOD_DIRECT) {
+        sw += f[u].nW;
+        sc += (int64_t(f[u].N) + 1 + 7) / 8 * 8;
+      }
+      st += (f[u].q_end - f[u].q_off + tile - 1) / tile;
     }
-    if (method == DS_METHOD_DIRECT) {
-      sw += m.nW;
-      sc += (int64_t(m.N) + 1 + 7) / 8 * 8;
-    }
-    st += (m.q_end - m.q_off + tile - 1) / tile;
   }
   s_w[tid] = sw;
   s_c[tid] = sc;
@@ -647,28 +665,36 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
   int64_t w0 = s_w[tid] - sw, c0 = s_c[tid] - sc, t0 = s_t[tid] - st;
   const int64_t words_total = s_w[kPlanBlock - 1], tiles_total = s_t[kPlanBlock - 1];
   int64_t nl = 0, lt = 0;
-  for (int32_t k = kb; k < ke; ++k) {
-    ArrMeta<T>& m = meta[k];
-    const int64_t nt = (m.q_end - m.q_off + tile - 1) / tile;
-    m.t_off = t0;
-    tile_off[k] = t0;
-    t0 += nt;
-    if (m.method == DS_METHOD_DIRECT && !tiles_only) {
-      const int64_t nw = m.nW, nc = (int64_t(m.N) + 1 + 7) / 8 * 8;
-      if (w0 + nw > words_budget) {
-        m.method = learn ? DS_METHOD_LEARNED : DS_METHOD_BSEARCH_OFFSET;
-        m.w_off = 0;
-        m.c_off = 0;
-      } else {
-        m.w_off = w0;
-        m.c_off = c0;
+  for (int32_t k0 = kb; k0 < ke; k0 += kPlanBatch) {
+    Fields f[kPlanBatch];
+    fields(k0, f);  // the methods as pass 1 left them
+#pragma unroll
+    for (int u = 0; u < kPlanBatch; ++u) {
+      if (k0 + u >= ke) break;
+      ArrMeta<T>& m = meta[k0 + u];
+      int32_t method = f[u].method;
+      const int64_t nt = (f[u].q_end - f[u].q_off + tile - 1) / tile;
+      m.t_off = t0;
+      tile_off[k0 + u] = t0;
+      t0 += nt;
+      if (method == DS_METHOD_DIRECT && !tiles_only) {
+        const int64_t nw = f[u].nW, nc = (int64_t(f[u].N) + 1 + 7) / 8 * 8;
+        if (w0 + nw > words_budget) {
+          method = learn ? DS_METHOD_LEARNED : DS_METHOD_BSEARCH_OFFSET;
+          m.method = method;
+          m.w_off = 0;
+          m.c_off = 0;
+        } else {
+          m.w_off = w0;
+          m.c_off = c0;
+        }
+        w0 += nw;
+        c0 += nc;
       }
-      w0 += nw;
-      c0 += nc;
-    }
-    if (m.method == DS_METHOD_LEARNED) {
-      ++nl;
-      lt += nt;
+      if (method == DS_METHOD_LEARNED) {
+        ++nl;
+        lt += nt;
+      }
     }
   }
   __syncthreads();
