@@ -87,9 +87,10 @@ def test_sweep_tables_and_indices(ds, dtype, n, form):
 def test_mid_sizes_nibble_in_lds(ds, dtype):
     """Between RANKCODE's LDS limit (about 65,000 keys) and NIBBLE's (about 120,000) the automatic
     layout stages the NIBBLE chunks in LDS (stage 7); beyond, they are read through L2 (stage 6).
-    Every layout, both forms and the fused histogram agree with the oracle."""
+    Every layout, both forms and the fused histogram and interpolation agree with the oracle."""
     from oracle import apps
 
+    rng = np.random.default_rng(12)
     for n, want in ((70_000, 7), (100_000, 7), (120_000, 7), (131_000, 6)):
         X = W.sweep_array(n, dtype)
         z = W.sweep_queries((1 << 19) + 5, dtype, stream=3)
@@ -107,6 +108,10 @@ def test_mid_sizes_nibble_in_lds(ds, dtype):
                 _assert_same(ds.search(idx, z_d).cpu().numpy(), ref, z)
             idx.clear_tune()
             _assert_same(idx.histogram(z_d).cpu().numpy(), apps.histogram(X, z))
+            Y = np.cumsum(rng.normal(0, 1, X.size)).astype(dtype)
+            got = idx.interp_linear(_dev(Y), z_d).cpu().numpy()
+            want_y = apps.interp_linear(X, Y, z)
+            assert np.array_equal(got, want_y, equal_nan=True), (n, form)
             idx.destroy()
 
 
