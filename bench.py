@@ -91,7 +91,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1 "
+        print(json.dumps({"error": "this benchmark measures one GPU; run with --gpus 1 "
                                    "(the queries of a search shard across GPUs with no exchange; each GPU runs this measurement on its share)"}))
         sys.exit(2)
 
