@@ -659,7 +659,7 @@ __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, i
 // route_keys_kernel.  (Waves taking groups in lockstep, four at a time with
 // the predecessors passed through LDS, ran 1.1x slower than the two kernels.)
 template <bool F16>
-__global__ void __launch_bounds__(256) route_first_kernel(const float* __restrict__ params,
+__global__ void __launch_bounds__(256, F16 ? 4 : 1) route_first_kernel(const float* __restrict__ params,
                                                           const float* __restrict__ feat, int32_t nseg,
                                                           int32_t* __restrict__ first,
                                                           const LearnMeta* __restrict__ lm,
