@@ -7,10 +7,13 @@ M = 2^26 uniform queries per (N, dtype)).  One timed step searches every
 resident in HBM; the tables are built before timing, as the paper's harness
 sets each algorithm up before its clock starts (Sec. 6.1, algorithm TestHarness).
 
-Prints one JSON line: Gqueries/s over the step, the HBM-roofline fraction of
-the dominant search kernel (timed with HIP events on the launch stream), the
-CPU oracle timed on a bounded sample, and per-case figures for Direct,
-Direct-FMA and the branch-free binary search.
+Output: first the detail lines (one JSON object each, key "detail": the
+per-case figures, the other layouts and methods, the uses, the learned and the
+batched workloads), then, as the LAST line, one compact JSON object (under
+1.5 KB): Gqueries/s over the step, the roofline of the dominant search kernel
+(timed with HIP events on the launch stream), the CPU oracle timed on a bounded
+sample, and the ratios the targets are stated in.  --detail-json PATH also
+writes every detail object into one JSON file.
 """
 from __future__ import annotations
 
@@ -81,6 +84,7 @@ def parse():
     p.add_argument("--m", type=int, default=0, help="queries per case (default 2^26)")
     p.add_argument("--no-batched", action="store_true", help="skip the 10,000-array batched workload")
     p.add_argument("--no-learned", action="store_true", help="skip the learned method on the clustered array")
+    p.add_argument("--detail-json", type=str, default="", help="also write the detail objects to this file")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run a plain device copy of 2^26 int32 (256 MiB read + 256 MiB written), the "
                         "reference for scaling hardware traffic counters")
@@ -216,7 +220,7 @@ def main():
             parity = parity and bool(np.array_equal(got, ref))
         cpu = dict(value=round(sample * len(cases) / cpu_t / 1e9, 4), unit="Gqueries/s", cores=threads,
                    kind="oracle", sample=f"first {sample} queries of each of the {len(cases)} (N, dtype) cases, "
-                                          f"classic binary search, {threads} OpenMP threads")
+                                          f"classic binary search")
         # one core, as the paper's single-core Classic figures
         sample1 = max(1, sample // 16)
         cpu_t1 = 0.0
@@ -248,6 +252,34 @@ def main():
         extras["batched_f32"] = bench_batched(ds, W, dev, stream, reps=3)
         extras["batched_learned_f64_mixture"] = bench_batched_learned(ds, W, dev, stream, reps=2)
 
+    detail = {"cases": case_rows, "roofline_detail": roofline, "cpu_baseline_detail": cpu,
+              "cpu_baseline_1thread_detail": cpu1, **extras}
+    if args.detail_json:
+        with open(args.detail_json, "w") as f:
+            json.dump(detail, f, indent=1)
+    for k, v in detail.items():  # one line per object, each well under the 8 KB a log tail keeps
+        print(json.dumps({"detail": k, "value": v}))
+
+    # the targets, as ratios
+    def min_frac(dts):
+        fr = [r["hbm_frac"] for r in case_rows if r["dtype"] == dts and r["N"] <= 1 << 16]
+        return min(fr) if fr else None
+
+    targets = {"direct_min_hbm_frac_n_le_2p16": {"f32": min_frac("f32"), "f64": min_frac("f64"), "goal": 0.6}}
+    le = extras.get("learned_f64_clustered")
+    if le:
+        targets["learned_vs_direct_f64_2p20"] = {"ratio": le.get("learned_vs_direct"), "goal": 0.5,
+                                                 "learned_gq_s": le["learned"]["gq_s"],
+                                                 "no_network_gq_s": le["learned_no_network"]["gq_s"],
+                                                 "model_vs_table": float("%.3g" % le["model_vs_direct_table"])}
+    bf = extras.get("batched_f32")
+    if bf:
+        targets["batched_f32_gq_s"] = {"graph": bf["gq_s_graph_replay"], "eager": bf["gq_s_end_to_end"]}
+    bl = extras.get("batched_learned_f64_mixture")
+    if bl:
+        targets["batched_learned_f64_gq_s"] = bl["gq_s_end_to_end"]
+    keep = ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel", "avg_launch_ms", "bytes_per_launch",
+            "l2")
     line = {
         "metric": "Gqueries/s and %HBM peak: Direct vs learned vs binary search, FP32/FP64",
         "value": round(value, 2),
@@ -261,17 +293,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"direct-sweep: N in {sizes} x {{f32, f64}}, gaps U(0.5,1.5) scaled to [0,1], "
+        "config": {"workload": f"direct-sweep: N in {sizes} x {{f32,f64}}, U(0.5,1.5) gaps scaled to [0,1], "
                                f"M={M} uniform queries per case, subtraction form",
                    "queries_per_step": M * n_cases},
-        "roofline": roofline,
+        "roofline": {k: roofline[k] for k in keep if k in roofline},
         "cpu_baseline": cpu,
-        "cpu_baseline_1thread": cpu1,
+        "cpu_baseline_1thread": None if cpu1 is None else {k: cpu1[k] for k in ("value", "unit", "cores")},
         "parity_sample_bit_exact": parity,
-        "cases": case_rows,
-        **extras,
+        "targets": targets,
     }
-    print(json.dumps(line))
+    text = json.dumps(line, separators=(",", ":"))
+    if len(text) > 1500:  # never let the headline outgrow what a log tail keeps
+        line.pop("targets")
+        text = json.dumps(line, separators=(",", ":"))
+    print(text)
 
 
 def compare_methods(ds, cases, M, stream, reps):
@@ -454,13 +489,32 @@ def bench_batched(ds, W, dev, stream, reps):
     e.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(e) / reps
+    # the same build + search captured once in a HIP graph with the autotuned shape, timed over replays
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        bt.run()
+    stream.wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        g.replay()
+        a.record(stream)
+        for _ in range(reps):
+            g.replay()
+        e.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = a.elapsed_time(e) / reps
     total_q = int(b.q_off[-1])
     meth, _ = bt.report()
-    res = dict(arrays=b.num_arrays, total_x=int(b.x_off[-1]), total_q=total_q, ms_end_to_end=round(ms, 3),
-               gq_s_end_to_end=round(total_q / ms / 1e6, 2),
-               hbm_frac_streaming=round(total_q * 8 / ms / 1e6 / HBM_PEAK_GBS, 4),
+    res = dict(arrays=b.num_arrays, total_x=int(b.x_off[-1]), total_q=total_q,
+               ms_graph_replay=round(ms_graph, 3), gq_s_graph_replay=round(total_q / ms_graph / 1e6, 2),
+               ms_end_to_end=round(ms, 3), gq_s_end_to_end=round(total_q / ms / 1e6, 2),
+               hbm_frac_streaming=round(total_q * 8 / ms_graph / 1e6 / HBM_PEAK_GBS, 4),
                direct_arrays=int((meth == ds.METHOD_DIRECT).sum()), autotuned_shape=shape)
-    del z, bt
+    del g, z, bt
     torch.cuda.empty_cache()
     return res
 

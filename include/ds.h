@@ -181,6 +181,12 @@ typedef struct ds_info_t {
   int64_t nibble_bytes;     /* bytes of the NIBBLE layout (0 if not built) */
   int32_t gap_q;            /* DS_METHOD_DIRECT_GAP: the q in use; 0 otherwise */
   int32_t n_h_refine;       /* midpoints tested by the refinement of H (refine_h) */
+  uint64_t fallback_count;  /* learned: queries so far that fell outside their recorded
+                               window and took the full binary search (expected 0); 0 for
+                               other methods.  ds_info reads it from the device with a
+                               synchronous copy that orders only against the legacy
+                               default stream: synchronise the stream of the searches to
+                               be counted first. */
 } ds_info_t;
 
 typedef struct ds_index* ds_handle;
@@ -242,12 +248,17 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t);
 /* ds_autotune: times every launch shape the handle supports (each built
  * layout x block {256, 512, 1024} x vectors per lane {1, 2, 4}) on the first
  * min(M, 2^24) queries of z_dev with HIP events on s, and keeps the fastest
- * for later ds_search calls on h (as ds_set_tune would).  out_dev receives
- * scratch results.  Synchronises s.  *best (may be NULL) receives the choice.
- * Results of ds_search do not depend on the choice. */
+ * for later ds_search calls on h (as ds_set_tune would).  The candidates are
+ * launched without changing the handle; only the final choice is written
+ * into it, so, as for ds_set_tune, no other thread may search on h while
+ * that write happens.  out_dev receives scratch results.  Synchronises s.
+ * *best (may be NULL) receives the choice.  Results of ds_search do not
+ * depend on the choice. */
 ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_dev, hipStream_t s, ds_tune* best);
 
-/* ds_info: fills *info (host memory). */
+/* ds_info: fills *info (host memory).  For a learned handle it reads
+ * fallback_count from the device (a synchronous 8-byte copy); DS_ERR_HIP if
+ * that copy fails. */
 ds_status ds_info(ds_handle h, ds_info_t* info);
 
 /* ds_copy_table: copies the Direct table K (R - jmin + 1 int32 entries,

@@ -72,7 +72,8 @@ class Info(ctypes.Structure):
                 ("model_bytes", ctypes.c_int64), ("max_err", ctypes.c_int64),
                 ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64),
                 ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("nibble_bytes", ctypes.c_int64), ("gap_q", ctypes.c_int32), ("n_h_refine", ctypes.c_int32)]
+                ("nibble_bytes", ctypes.c_int64), ("gap_q", ctypes.c_int32), ("n_h_refine", ctypes.c_int32),
+                ("fallback_count", ctypes.c_uint64)]
 
 
 class View(ctypes.Structure):

@@ -604,7 +604,10 @@ ds_status build_direct_gap(ds_index* h, const ds_build_opts& o, const void* X_de
     const T g = from_bits<T>(got.min_gap_bits);
     st = (h->form == DS_FORM_FMA) ? compute_hr<T, DS_FORM_FMA>(h, X, q, scr, s, ends[0], ends[1], g)
                                   : compute_hr<T, DS_FORM_SUB>(h, X, q, scr, s, ends[0], ends[1], g);
-    if (st != DS_OK) continue;
+    // an infeasible grid (or one past the table cap) tries the next q; any other
+    // failure (a HIP call, an allocation) is returned as it is
+    if (st == DS_ERR_INFEASIBLE || st == DS_ERR_TABLE_CAP) continue;
+    if (st != DS_OK) return st;
     if ((h->R - h->jmin + 1) * int64_t(sizeof(int32_t)) > cap) {
       st = DS_ERR_TABLE_CAP;
       continue;
@@ -907,6 +910,8 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
 ds_status ds_info(ds_handle h, ds_info_t* info) {
   if (!h || !info) return DS_ERR_ARG;
   *info = h->info;
+  info->fallback_count = 0;
+  if (h->learned) return ds::learned_fallbacks(h, &info->fallback_count);
   return DS_OK;
 }
 

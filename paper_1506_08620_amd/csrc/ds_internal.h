@@ -248,7 +248,9 @@ struct ds_index {
 
 namespace ds {
 // implemented in ds_search.hip
-ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);
+// cand: a launch shape to use instead of the handle's (nullptr: the handle's)
+ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s,
+                        const ds_tune* cand = nullptr);
 bool tables_fit_lds(const ds_index* h);
 int64_t rankcode_lds_bytes(const ds_index* h);
 int64_t direct_lds_bytes(const ds_index* h, int stage);  // LDS bytes of a Direct layout staged by the search
@@ -257,5 +259,6 @@ ds_status learned_build(ds_index* h, const ds_build_opts* o, hipStream_t s);
 ds_status learned_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s);
 void learned_free(ds_index* h);
 void learned_fill_info(const ds_index* h, ds_info_t* in);
+ds_status learned_fallbacks(const ds_index* h, uint64_t* count);  // synchronous device read
 int num_cus();
 }  // namespace ds

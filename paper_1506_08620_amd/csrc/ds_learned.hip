@@ -1547,6 +1547,14 @@ void learned_fill_info(const ds_index* h, ds_info_t* in) {
   in->mean_log2_window = L->mean_log2_window;
 }
 
+ds_status learned_fallbacks(const ds_index* h, uint64_t* count) {
+  const LearnedModel* L = h->learned;
+  unsigned long long f = 0;
+  if (L && L->fallbacks) DS_HIP_CHECK(hipMemcpy(&f, L->fallbacks, 8, hipMemcpyDeviceToHost));
+  *count = f;
+  return DS_OK;
+}
+
 }  // namespace ds
 
 extern "C" {

@@ -267,10 +267,14 @@ void default_shape(const ds_index* h, int stage, int* block, int* unroll) {
   }
 }
 
-Shape pick_shape(const ds_index* h, int64_t M) {
+// The launch shape: the fields of *cand (the autotuner's candidate, which
+// never touches the handle) or else of the handle's fixed tune that are set,
+// the defaults for the rest.
+Shape pick_shape(const ds_index* h, int64_t M, const ds_tune* cand) {
   Shape sh{};
-  const ds_tune& t = h->tune;
-  if (h->tune_set && t.stage) {
+  const bool set = cand != nullptr || h->tune_set;
+  const ds_tune& t = cand ? *cand : h->tune;
+  if (set && t.stage) {
     sh.stage = t.stage;
   } else if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) {
     sh.stage = h->auto_stage;
@@ -279,9 +283,9 @@ Shape pick_shape(const ds_index* h, int64_t M) {
   }
   int block = 512, unroll = 2;
   if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) default_shape(h, sh.stage, &block, &unroll);
-  sh.block = (h->tune_set && t.block) ? t.block : block;
-  sh.unroll = (h->tune_set && t.unroll) ? t.unroll : unroll;
-  sh.grid = (h->tune_set && t.grid) ? t.grid : 0;
+  sh.block = (set && t.block) ? t.block : block;
+  sh.unroll = (set && t.unroll) ? t.unroll : unroll;
+  sh.grid = (set && t.grid) ? t.grid : 0;
   (void)M;
   return sh;
 }
@@ -409,8 +413,9 @@ T X_N(const ds_index* h) {
 }
 
 template <typename T>
-ds_status search_typed(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s) {
-  const Shape sh = pick_shape(h, M);
+ds_status search_typed(const ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s,
+                       const ds_tune* cand) {
+  const Shape sh = pick_shape(h, M, cand);
   const bool vec = ((reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T))) == 0) &&
                    ((reinterpret_cast<uintptr_t>(out) % 16) == 0);
   const int lds = (sh.stage == 1 || sh.stage == 3 || sh.stage == 6 || sh.stage == 7)
@@ -482,9 +487,10 @@ bool tables_fit_lds(const ds_index* h) { return lds_bytes_needed(h, 1) <= kLdsBy
 int64_t direct_lds_bytes(const ds_index* h, int stage) { return lds_bytes_needed(h, stage); }
 int64_t rankcode_lds_bytes(const ds_index* h) { return lds_bytes_needed(h, 3); }
 
-ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s) {
+ds_status launch_search(ds_index* h, const void* z, int64_t M, int32_t* out, hipStream_t s, const ds_tune* cand) {
   if (h->method == DS_METHOD_LEARNED) return learned_search(h, z, M, out, s);
-  return (h->dt == DS_F32) ? search_typed<float>(h, z, M, out, s) : search_typed<double>(h, z, M, out, s);
+  return (h->dt == DS_F32) ? search_typed<float>(h, z, M, out, s, cand)
+                           : search_typed<double>(h, z, M, out, s, cand);
 }
 
 }  // namespace ds
@@ -519,8 +525,6 @@ ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_de
     if (h->staged) stages[n_stages++] = 1;
     stages[n_stages++] = 2;
   }
-  const ds_tune saved = h->tune;
-  const bool saved_set = h->tune_set;
   hipEvent_t e0, e1;
   DS_HIP_CHECK(hipEventCreate(&e0));
   DS_HIP_CHECK(hipEventCreate(&e1));
@@ -532,13 +536,11 @@ ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_de
   for (int si = 0; si < n_stages && st == DS_OK; ++si) {
     for (int bi = 0; bi < 3 && st == DS_OK; ++bi) {
       for (int ui = 0; ui < 3 && st == DS_OK; ++ui) {
-        ds_tune cand{blocks[bi], unrolls[ui], stages[si], 0};
-        h->tune = cand;
-        h->tune_set = true;
-        st = ds::launch_search(h, z_dev, m, out_dev, s);  // warm-up
+        const ds_tune cand{blocks[bi], unrolls[ui], stages[si], 0};
+        st = ds::launch_search(h, z_dev, m, out_dev, s, &cand);  // warm-up
         if (st != DS_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { st = DS_ERR_HIP; break; }
-        for (int r = 0; r < 3 && st == DS_OK; ++r) st = ds::launch_search(h, z_dev, m, out_dev, s);
+        for (int r = 0; r < 3 && st == DS_OK; ++r) st = ds::launch_search(h, z_dev, m, out_dev, s, &cand);
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = DS_ERR_HIP; break; }
         float ms = 0;
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = DS_ERR_HIP; break; }
@@ -551,11 +553,8 @@ ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_de
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st != DS_OK) {
-    h->tune = saved;
-    h->tune_set = saved_set;
-    return st;
-  }
+  if (st != DS_OK) return st;
+  // the handle's tune is written once, with the choice (as ds_set_tune would)
   h->tune = best_t;
   h->tune_set = true;
   if (best) *best = best_t;

@@ -37,6 +37,7 @@ def _check_tables(idx, X, form, hstart=oracle.HSTART_PHI):
     assert inf["method_name"] == "direct"
     assert inf["H"] == t.H and inf["W"] == t.W and inf["R"] == t.R and inf["jmin"] == t.jmin
     assert inf["n_h_updates"] == t.n_updates
+    assert inf["fallback_count"] == 0 and inf["model_bytes"] == 0
     K = idx.table().cpu().numpy()
     assert np.array_equal(K, t.K)
     return t

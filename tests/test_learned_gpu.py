@@ -112,6 +112,8 @@ def test_learned_exact_on_clustered_arrays(ds, dt):
             _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
             _, fb = idx.learned_model()
             assert fb == 0
+            torch.cuda.synchronize()
+            assert idx.info()["fallback_count"] == 0
             assert inf["model_bytes"] == 1153 * 4 + segs * 32
 
 
@@ -202,5 +204,7 @@ def test_full_size_clustered_f64_sampled(ds):
     _assert_same(out[torch.from_numpy(pos).to(DEV)].cpu().numpy(), oracle.search(X, z[pos]))
     _, fb = idx.learned_model()
     assert fb == 0
+    torch.cuda.synchronize()
     inf = idx.info()
+    assert inf["fallback_count"] == 0
     assert inf["model_bytes"] < 200_000
