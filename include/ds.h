@@ -60,7 +60,9 @@ typedef enum {
   DS_ERR_TABLE_CAP = 5,    /* the Direct table would exceed the byte cap */
   DS_ERR_OOM = 6,          /* device allocation failed */
   DS_ERR_HIP = 7,          /* a HIP runtime call failed */
-  DS_ERR_UNSUPPORTED = 8   /* option combination not supported */
+  DS_ERR_UNSUPPORTED = 8,  /* option combination not supported */
+  DS_ERR_SCRATCH_CAP = 9   /* ds_search_batched_noalloc: the batch needs more workspace
+                              than the library's fixed scratch array holds */
 } ds_status;
 
 typedef enum { DS_FORM_SUB = 0, DS_FORM_FMA = 1 } ds_form;
@@ -402,6 +404,27 @@ size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t tab
  * live on the device and are not checked: they must be consistent with
  * total_x and total_q. */
 ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s);
+
+/* ds_search_batched_noalloc: ds_search_batched for callers that cannot
+ * allocate device memory or take a workspace (code under HIP graph capture
+ * that may not call hipMalloc, tight serving loops, harnesses that forbid
+ * allocation).  Same descriptor, results and errors as ds_search_batched,
+ * except that d->workspace_dev and d->workspace_bytes are ignored: the
+ * workspace is a fixed array of DS_NOALLOC_SCRATCH_BYTES of device memory
+ * inside the library, one per GPU, held from the library's load until the
+ * process ends.  The call allocates nothing (no hipMalloc, no hipFree); its
+ * first call on a device looks up that device's copy of the array.
+ * Limit: DS_ERR_SCRATCH_CAP when ds_batch_workspace_bytes(num_arrays,
+ * total_x, 0, learn_segments) exceeds DS_NOALLOC_SCRATCH_BYTES; the room
+ * left after the fixed part of the workspace holds Direct tables, and arrays
+ * whose table does not fit it use another method (results are identical).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on the
+ * same GPU (on two streams, or from two threads) race and give undefined
+ * results; calls ordered on one stream are safe.  The per-array report and
+ * fallback count of ds_batch_report / ds_batch_fallbacks are not available
+ * for these calls. */
+#define DS_NOALLOC_SCRATCH_BYTES (64u << 20)
+ds_status ds_search_batched_noalloc(const ds_batch_desc* d, hipStream_t s);
 
 /* Autotuner of the batched launch: runs ds_search_batched once, then times
  * the search phase (HIP events on s) for tile in {2^16 .. 2^20}, block in

@@ -25,7 +25,9 @@ LIB_PATH = os.path.join(_HERE, "libds.so")
 
 # ---- enums of ds.h --------------------------------------------------------
 F32, F64 = 0, 1
-OK, ERR_ARG, ERR_NOT_SORTED, ERR_NONFINITE, ERR_INFEASIBLE, ERR_TABLE_CAP, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED = range(9)
+(OK, ERR_ARG, ERR_NOT_SORTED, ERR_NONFINITE, ERR_INFEASIBLE, ERR_TABLE_CAP, ERR_OOM, ERR_HIP, ERR_UNSUPPORTED,
+ ERR_SCRATCH_CAP) = range(10)
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DS_NOALLOC_SCRATCH_BYTES
 FORM_SUB, FORM_FMA = 0, 1
 HSTART_PHI, HSTART_HBAR = 0, 1
 (METHOD_DIRECT, METHOD_BSEARCH_LEADBIT, METHOD_BSEARCH_OFFSET, METHOD_LEARNED, METHOD_AUTO, METHOD_DIRECT_GAP,
@@ -48,7 +50,8 @@ METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 
 # exported symbols of libds.so (every function ds.h declares)
 SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_autotune", "ds_info", "ds_copy_table", "ds_destroy", "ds_status_str",
-           "ds_batch_workspace_bytes", "ds_search_batched", "ds_batch_autotune", "ds_batch_report",
+           "ds_batch_workspace_bytes", "ds_search_batched", "ds_search_batched_noalloc", "ds_batch_autotune",
+           "ds_batch_report",
            "ds_batch_fallbacks",
            "ds_learned_grad", "ds_learned_forward", "ds_learned_model",
            "ds_get_view", "ds_view_search", "ds_histogram", "ds_interp_linear")
@@ -130,6 +133,8 @@ def _load_library():
     lib.ds_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.ds_search_batched.argtypes = [ctypes.POINTER(BatchDesc), vp]
     lib.ds_search_batched.restype = i32
+    lib.ds_search_batched_noalloc.argtypes = [ctypes.POINTER(BatchDesc), vp]
+    lib.ds_search_batched_noalloc.restype = i32
     lib.ds_learned_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     lib.ds_learned_grad.restype = i32
     lib.ds_learned_forward.argtypes = [vp, vp, i64, i32, vp, vp]
@@ -448,6 +453,24 @@ class Batch:
         if st != OK:
             raise DsError(st, "ds_search_batched")
         return self.out
+
+    def run_noalloc(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """The same build + search through ds_search_batched_noalloc: the library's fixed
+        per-GPU scratch array serves as the workspace (this object's is not used).  Results
+        go to out (int32, at least total_q entries), or to self.out."""
+        d = BatchDesc.from_buffer_copy(self.desc)
+        if out is None:
+            out = self.out
+        else:
+            _check_device(out, "out")
+            if out.dtype != torch.int32 or out.numel() < self.total_q or not out.is_contiguous():
+                raise ValueError("out must be a contiguous int32 tensor of at least total_q entries")
+            d.out_dev = out.data_ptr()
+        with torch.cuda.device(self.device):
+            st = _lib.ds_search_batched_noalloc(ctypes.byref(d), _stream_handle(stream))
+        if st != OK:
+            raise DsError(st, "ds_search_batched_noalloc")
+        return out
 
     def autotune(self, stream=None, cache: str | None = None) -> dict:
         """ds_batch_autotune; with cache (a JSON file path) the choice is stored under a key of

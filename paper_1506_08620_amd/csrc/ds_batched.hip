@@ -30,6 +30,7 @@
 // give -2 for all their queries.
 #include <algorithm>
 #include <limits>
+#include <mutex>
 
 #include "ds_batched_internal.h"
 #include "ds_ops.h"
@@ -1187,6 +1188,34 @@ ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// The fixed workspace of ds_search_batched_noalloc.  In host code the name
+// `scratch` stands for the symbol, not for device memory: the device address
+// of each GPU's copy is looked up once per device and kept in scratch_ptr.
+__device__ __align__(256) unsigned char scratch[DS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxScratchDevices] = {};
+
+// the current device's copy of the scratch array
+ds_status current_scratch(void** out) {
+  int dev = -1;
+  DS_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return DS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    DS_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return DS_ERR_HIP;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return DS_OK;
+}
+}  // namespace
+
 }  // namespace ds
 
 extern "C" {
@@ -1219,6 +1248,21 @@ ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s) {
   if (d->dtype == DS_F32)
     return d->form == DS_FORM_FMA ? ds::run_batched<float, DS_FORM_FMA>(d, s) : ds::run_batched<float, DS_FORM_SUB>(d, s);
   return d->form == DS_FORM_FMA ? ds::run_batched<double, DS_FORM_FMA>(d, s) : ds::run_batched<double, DS_FORM_SUB>(d, s);
+}
+
+ds_status ds_search_batched_noalloc(const ds_batch_desc* d, hipStream_t s) {
+  if (!d) return DS_ERR_ARG;
+  if (d->num_arrays < 0 || d->total_x < 0 || d->learn_segments < 0 || d->learn_segments > 8192) return DS_ERR_ARG;
+  const size_t need = ds_batch_workspace_bytes(d->num_arrays, d->total_x, 0, d->learn_segments);
+  if (need == 0) return DS_ERR_ARG;
+  if (need > size_t(DS_NOALLOC_SCRATCH_BYTES)) return DS_ERR_SCRATCH_CAP;
+  ds_batch_desc c = *d;
+  void* ws = nullptr;
+  const ds_status st = ds::current_scratch(&ws);
+  if (st != DS_OK) return st;
+  c.workspace_dev = ws;
+  c.workspace_bytes = DS_NOALLOC_SCRATCH_BYTES;
+  return ds_search_batched(&c, s);
 }
 
 ds_status ds_batch_autotune(ds_batch_desc* d, hipStream_t s) {

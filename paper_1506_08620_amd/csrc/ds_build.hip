@@ -940,6 +940,7 @@ const char* ds_status_str(ds_status st) {
     case DS_ERR_OOM: return "device allocation failed";
     case DS_ERR_HIP: return "HIP runtime error";
     case DS_ERR_UNSUPPORTED: return "unsupported option";
+    case DS_ERR_SCRATCH_CAP: return "the batch needs more workspace than the fixed scratch array holds";
   }
   return "unknown status";
 }

@@ -59,9 +59,9 @@ def test_status_strings():
     lib = _lib()
     lib.ds_status_str.restype = ctypes.c_char_p
     lib.ds_status_str.argtypes = [ctypes.c_int]
-    texts = [lib.ds_status_str(i).decode() for i in range(9)]
+    texts = [lib.ds_status_str(i).decode() for i in range(10)]
     assert texts[0] == "ok"
-    assert len(set(texts)) == 9
+    assert len(set(texts)) == 10
     assert "unknown" in lib.ds_status_str(99).decode()
 
 
