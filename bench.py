@@ -433,7 +433,8 @@ def bench_learned(ds, W, dev, stream, reps, direct_ref):
     res["direct_table_bytes_needed"] = float(4.0 * (X[-1] - X[0]) / gaps.min())
     ref_out = None
     for name, kw in (("learned", dict(method="learned")),
-                     ("learned_fp32_router", dict(method="learned", learn_fp32_router=True)),
+                     ("learned_eval_fp16_router", dict(method="learned", learn_router="fp16")),
+                     ("learned_eval_fp32_router", dict(method="learned", learn_router="fp32")),
                      ("learned_no_network", dict(method="learned", learn_epochs=-1)),
                      ("bsearch_leadbit", dict(method="leadbit"))):
         torch.cuda.synchronize()

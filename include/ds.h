@@ -125,12 +125,17 @@ typedef struct ds_build_opts {
                                monotone in H), hence a table no larger.  0 = keep the grown H */
 } ds_build_opts;
 
-/* learned: the router is trained and stored in FP32.  By default the search
- * (and the routing of the keys that defines the segments) evaluates its 32x32
- * layer on the matrix cores with FP16 inputs and FP32 accumulation; this flag
- * keeps FP32 inputs instead (4x the matrix-core time).  Either way routing is
- * monotone and results are exact. */
+/* learned: the router is trained and stored in FP32.  Its segment is a
+ * non-decreasing step function of the scalar feature with at most
+ * learn_segments steps; by default the build finds where each step lies by
+ * bisection with the FP32 network itself, and keys and queries are routed by a
+ * search of that step table -- the FP32 network's function, exactly.
+ * DS_LEARN_EVAL_ROUTER instead evaluates the network for every key and query
+ * on the matrix cores, with its 32x32 layer's inputs rounded to FP16 (FP32
+ * accumulation); DS_LEARN_FP32_ROUTER evaluates it per query with FP32 inputs.
+ * Routing is monotone in every mode and results are exact. */
 #define DS_LEARN_FP32_ROUTER 1
+#define DS_LEARN_EVAL_ROUTER 2
 
 /* Device layouts of the Direct tables (ds_tune.stage selects one):
  *   PLAIN     K (int32 per grid cell) and X, as in Sec. 4.
@@ -203,7 +208,10 @@ typedef struct ds_tune {
                                5 = RANKCODE through L2, 6 = NIBBLE through L2,
                                7 = NIBBLE in LDS; binary
                                search: 1 = X in LDS, 2 = X through L2; Eytzinger: 1 = top
-                               levels in LDS, 2 = every level through L2 */
+                               levels in LDS, 2 = every level through L2; learned: 1 = each
+                               lane reads its own lines of the sample array and of X, 2 =
+                               the lines are read cooperatively by four lanes each (unroll
+                               must be 0) */
   int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */
 } ds_tune;
 

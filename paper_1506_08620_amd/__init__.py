@@ -46,6 +46,8 @@ _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset"
 _FORMS = {"sub": FORM_SUB, "fma": FORM_FMA}
 _HSTARTS = {"phi": HSTART_PHI, "hbar": HSTART_HBAR}
 _FALLBACKS = {"none": FALLBACK_NONE, "bsearch": FALLBACK_BSEARCH, "learned": FALLBACK_LEARNED}
+LEARN_FP32_ROUTER, LEARN_EVAL_ROUTER = 1, 2
+_LEARN_ROUTERS = {"table": 0, "fp16": LEARN_EVAL_ROUTER, "fp32": LEARN_FP32_ROUTER}
 METHOD_NAMES = {v: k for k, v in _METHODS.items()}
 
 # exported symbols of libds.so (every function ds.h declares)
@@ -307,7 +309,7 @@ class Index:
 def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart: str = "phi",
           fallback: str = "none", table_cap_bytes: int = 0, learn_epochs: int = 0, learn_segments: int = 0,
           learn_rate: float = 0.0, learn_batch: int = 0, seed: int = 0, layouts=(), learn_fp32_router: bool = False,
-          gap_q: int = 0, refine_h: bool = False, stream=None) -> Index:
+          learn_router: str = "table", gap_q: int = 0, refine_h: bool = False, stream=None) -> Index:
     """ds_build over the N+1 values of x (a strictly increasing GPU tensor).
 
     layouts: extra Direct layouts to build besides the automatic one
@@ -316,13 +318,18 @@ def build(x: torch.Tensor, *, method: str = "direct", form: str = "sub", hstart:
     smallest q whose table fits table_cap_bytes.
     refine_h: when ComputeHR had to grow H, bisect between the last failing H and the
     grown one (end of Sec. 4.4.3); info()["n_h_refine"] counts the midpoints tested.
+    learn_router: how the learned method routes keys and queries: "table" (the FP32
+    network's exact step table, the default), "fp16" or "fp32" (the network evaluated per
+    query on the matrix cores, 32x32 layer with FP16 or FP32 inputs);
+    learn_fp32_router=True is "fp32".
     """
     _check_device(x, "x")
     if x.dim() != 1 or x.numel() < 2:
         raise ValueError("x must be 1-D with at least two values")
+    router = "fp32" if learn_fp32_router else learn_router
     opts = BuildOpts(_METHODS[method], _FORMS[form], _HSTARTS[hstart], _FALLBACKS[fallback], int(table_cap_bytes),
                      int(learn_epochs), int(learn_segments), float(learn_rate), int(learn_batch), int(seed),
-                     sum(_LAYOUTS[k] for k in set(layouts)), 1 if learn_fp32_router else 0, int(gap_q),
+                     sum(_LAYOUTS[k] for k in set(layouts)), _LEARN_ROUTERS[router], int(gap_q),
                      1 if refine_h else 0)
     h = ctypes.c_void_p()
     with torch.cuda.device(x.device):

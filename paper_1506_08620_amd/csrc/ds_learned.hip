@@ -58,12 +58,15 @@ struct LearnedModel {
   int32_t* route = nullptr;     // segment of every key
   int32_t* first = nullptr;     // nseg + 1: first key of each segment
   SegFit* segs = nullptr;
+  float* steps = nullptr;       // compiled router: nseg step positions (see router_steps_kernel)
+  uint32_t* grid = nullptr;     // compiled router: 2^log2g grid cells over u (grid_segment)
+  int32_t log2g = 0;
   void* samples = nullptr;      // S[j] = X_{E j} (single-array search)
   int64_t nsamples = 0;
   unsigned long long* fallbacks = nullptr;
   int32_t nseg = 0;
   int32_t identity = 0;         // ablation: y = u
-  int32_t f16 = 0;              // router's 32x32 layer with FP16 inputs
+  int32_t router = 0;           // kRouteTable, kRouteF16 or kRouteF32
   double delta = 0, flo = 0, fscale = 0;
   int64_t max_err = 0;
   double mean_log2_window = 0;
@@ -344,6 +347,66 @@ __device__ __forceinline__ int32_t seg_predict(const SegFit& sg, T z) {
   float p = std::fma(sg.a, d, sg.b);
   p = std::fmin(std::fmax(p, -2.0f), static_cast<float>(sg.hi - sg.lo + 2));
   return static_cast<int32_t>(std::floor(p));
+}
+
+// How keys and queries are routed to segments.  The network's segment is a
+// non-decreasing step function of the scalar f32 feature u with at most nseg
+// steps, so it is fully described by where each step lies:
+//   kRouteTable  (default) the FP32 network's steps, found once at build time
+//                by bisection over the f32 values of u with the network itself
+//                (router_steps_kernel); a key or query is then routed by a
+//                search of that table (table_segment) -- the same function as
+//                evaluating the FP32 network, at a fraction of the cost
+//   kRouteF16    the network evaluated per query on the matrix cores, 32x32
+//                layer with FP16 inputs and FP32 accumulation
+//   kRouteF32    the same with FP32 inputs
+// The identity router of the ablation (y = u) needs no table.
+constexpr int kRouteTable = 0, kRouteF16 = 1, kRouteF32 = 2;
+
+// The compiled router's segment of u: the largest t with steps[t] <= u, where
+// steps[0] = -inf and steps is non-decreasing (a branch-free bisection; the
+// probe index stays below nseg).
+__device__ __forceinline__ int32_t table_segment(float u, const float* steps, int32_t nseg) {
+  int32_t lo = 0, n = nseg;
+  while (n > 1) {
+    const int32_t half = n >> 1;
+    lo = (steps[lo + half] <= u) ? lo + half : lo;
+    n -= half;
+  }
+  return lo;
+}
+
+// A uniform grid over u speeds the table up: cell c of G = 2^k cells holds
+// u in [c 2^-k, (c + 1) 2^-k) (u = 1 falls in the last cell), and
+// grid[c] = s_lo | (s_hi - s_lo) << 16 with s_lo and s_hi the table segments of
+// the cell's lowest and highest u.  The segment of u is then found by the same
+// bisection restricted to [s_lo, s_hi] (steps[s_lo] <= u < steps[s_hi + 1]),
+// usually 0 to 3 probes instead of log2(nseg): the same result as
+// table_segment.  u * 2^k is exact, so the cell is exact.
+__device__ __forceinline__ int32_t grid_segment(float u, const float* steps, const uint32_t* grid, int32_t log2g) {
+  const int32_t g = 1 << log2g;
+  const int32_t c = std::min(static_cast<int32_t>(u * static_cast<float>(g)), g - 1);
+  const uint32_t e = grid[c];
+  int32_t lo = static_cast<int32_t>(e & 0xffffu), n = static_cast<int32_t>(e >> 16) + 1;
+  while (n > 1) {
+    const int32_t half = n >> 1;
+    lo = (steps[lo + half] <= u) ? lo + half : lo;
+    n -= half;
+  }
+  return lo;
+}
+
+// grid cells of the compiled router (one thread per cell), from its steps
+__global__ void router_grid_kernel(const float* __restrict__ steps, int32_t nseg, int32_t log2g,
+                                   uint32_t* __restrict__ grid) {
+  const int32_t g = 1 << log2g;
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g) return;
+  const float scale = std::ldexp(1.0f, -log2g);
+  const float u0 = static_cast<float>(c) * scale;
+  const float u1 = (c == g - 1) ? 1.0f : std::nextafter(static_cast<float>(c + 1) * scale, 0.0f);
+  const int32_t s0 = table_segment(u0, steps, nseg), s1 = table_segment(u1, steps, nseg);
+  grid[c] = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(s1 - s0) << 16);
 }
 
 // ---------------------------------------------------------------------------
@@ -638,6 +701,47 @@ __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict
   }
 }
 
+// Steps of the FP32 network's routing: lane t (1 <= t < nseg) finds the
+// smallest f32 u in [0, 1] whose segment segment_of(route_coord(y(u), u)) is
+// at least t, by bisection over the bit patterns of [0, 1] (ordered like the
+// values), 2.0f when no u reaches t; steps[0] = -inf.  Every lane of a wave
+// takes part in each evaluation of the network (the router works on 64 queries
+// at once), so the loop count is fixed and a converged lane only recomputes.
+// The network is non-decreasing in u, so each bisection finds its step; the
+// steps are then made non-decreasing (steps_monotone_kernel), so the table is a
+// non-decreasing step function even if a rounding were not monotone.
+__global__ void __launch_bounds__(256) router_steps_kernel(const float* __restrict__ params, int32_t nseg,
+                                                           float* __restrict__ steps) {
+  RouterRegs R;
+  load_router(params, R);
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t lo = 0, hi = 0x3f800001u;  // bit patterns of [0, 1], hi one past
+#pragma unroll 1
+  for (int it = 0; it < 31; ++it) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    const float u = __uint_as_float(mid);
+    const int32_t sg = segment_of(route_coord(route_pair<false>(u, &R), u), nseg);
+    if (lo < hi) {
+      if (sg >= t) hi = mid;
+      else lo = mid + 1;
+    }
+  }
+  if (t == 0) steps[0] = -std::numeric_limits<float>::infinity();
+  else if (t < nseg) steps[t] = lo <= 0x3f800000u ? __uint_as_float(lo) : 2.0f;
+}
+
+__global__ void steps_monotone_kernel(float* __restrict__ steps, int32_t nseg) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    for (int32_t t = 1; t < nseg; ++t) steps[t] = std::fmax(steps[t], steps[t - 1]);
+}
+
+// segment of every key through the compiled router
+__global__ void route_keys_table_kernel(const float* __restrict__ steps, const float* __restrict__ feat, int64_t n,
+                                        int32_t nseg, int32_t* __restrict__ route) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    route[i] = table_segment(feat[i], steps, nseg);
+}
+
 // first[s] = #{i : route_i < s} for s in [0, nseg]
 __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, int32_t nseg,
                                  int32_t* __restrict__ first) {
@@ -846,6 +950,9 @@ struct LearnedArgs {
   const T* S;  // samples X_{E j} (single-array search)
   const float* params;
   const SegFit* segs;
+  const float* steps;  // compiled router (kRouteTable)
+  const uint32_t* grid;
+  int32_t log2g;
   unsigned long long* fallbacks;
   const T* z;
   int32_t* out;
@@ -858,9 +965,8 @@ struct LearnedArgs {
 // Window of candidate indices for z from its segment: [q + dmin - 1, q + dmax]
 // relative to lo, kept inside [lo, hi].
 template <typename T>
-__device__ __forceinline__ void query_window(T z, float y, const LearnedArgs<T>& a, const SegFit* segs, int32_t* L,
-                                             int32_t* U) {
-  const SegFit sg = segs[segment_of(y, a.nseg)];
+__device__ __forceinline__ void query_window(T z, int32_t seg, const SegFit* segs, int32_t* L, int32_t* U) {
+  const SegFit sg = segs[seg];
   const int32_t q = seg_predict<T>(sg, z);
   *L = std::min(std::max(sg.lo, sg.lo + q + sg.dmin - 1), sg.hi);
   *U = std::min(std::max(*L, sg.lo + q + sg.dmax), sg.hi);
@@ -932,6 +1038,91 @@ __device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, cons
     for (int e = 0; e < V; ++e) c2 += (x[e] <= z) ? 1 : 0;
   }
   bool upper = c2 <= E - 1 || (jU > jL && js <= jU);  // the value after the answer was read
+  if (c2 == E && jU == jL) upper = z < X[int64_t(js + 1) * E];
+  *certified = c2 >= 1 && upper;
+  return js * E + c2 - 1;
+}
+
+// Sum of v over the four lanes of each quad (lanes 4k .. 4k + 3), in every
+// lane of the quad: two DPP quad permutations, [1,0,3,2] then [2,3,0,1].
+__device__ __forceinline__ int32_t quad_sum(int32_t v) {
+  v += __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  v += __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  return v;
+}
+
+// How many of the E values of block blk of X (values blk E .. blk E + E - 1)
+// are <= z, for the query of every lane.  All 64 lanes must call it with a
+// valid block.  The blocks are read cooperatively: in round r the four lanes
+// of quad k read 16 bytes each of the block of query 16 r + k, so each load
+// instruction touches 16 blocks (a lane reading its own block makes four
+// loads that each touch 64).  The quad's counts are summed by DPP; lane
+// 4 k + r keeps round r's sum, and one shuffle hands each query its count.
+template <typename T>
+__device__ __forceinline__ int32_t coop_block_count(const T* __restrict__ X, uint32_t blk, T z) {
+  constexpr int E = 64 / int(sizeof(T));
+  constexpr int V = 16 / int(sizeof(T));
+  const int lane = threadIdx.x & 63;
+  const int sub = lane & 3;
+  vec16b<T> x[4];
+  T zz[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {  // every load is issued before any value is used
+    const int src = 16 * r + (lane >> 2);
+    const uint32_t b = __shfl(blk, src, 64);
+    zz[r] = __shfl(z, src, 64);
+    x[r] = *reinterpret_cast<const vec16b<T>*>(X + int64_t(b) * E + sub * V);
+  }
+  int32_t mine = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int32_t c = 0;
+#pragma unroll
+    for (int e = 0; e < V; ++e) c += (x[r][e] <= zz[r]) ? 1 : 0;
+    c = quad_sum(c);
+    mine = (sub == r) ? c : mine;
+  }
+  return __shfl(mine, 4 * (lane & 15) + (lane >> 4), 64);
+}
+
+// sample_search with the block of X read cooperatively (coop_block_count);
+// the samples are read by each lane as there.  Same reads, result and
+// certification.  All 64 lanes must call it.
+template <typename T>
+__device__ __forceinline__ int32_t sample_search_coop(T z, int32_t L, int32_t U, const T* __restrict__ X,
+                                                      const T* __restrict__ S, bool* certified) {
+  constexpr int E = 64 / int(sizeof(T));
+  constexpr int SE = 64 / int(sizeof(T));
+  constexpr int V = 16 / int(sizeof(T));
+  int32_t jL = L / E, jU = U / E;
+  while (jU + 1 > ((jL + 1) & ~(SE - 1)) + 2 * SE - 1) {  // windows of dozens of blocks only
+    const int32_t m = jL + ((jU - jL + 1) >> 1);
+    const bool c = S[m] <= z;
+    jL = c ? m : jL;
+    jU = c ? jU : m - 1;
+  }
+  int32_t c1 = 0;
+  if (jU > jL) {
+    const int32_t s0 = (jL + 1) & ~(SE - 1);
+    const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
+#pragma unroll
+    for (int v = 0; v < SE / V; ++v) {
+      const vec16b<T> x = p[v];
+#pragma unroll
+      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
+    }
+    if (jU + 1 >= s0 + SE) {
+#pragma unroll
+      for (int v = SE / V; v < 2 * SE / V; ++v) {
+        const vec16b<T> x = p[v];
+#pragma unroll
+        for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
+      }
+    }
+  }
+  const int32_t js = jL + c1;
+  const int32_t c2 = coop_block_count<T>(X, static_cast<uint32_t>(js), z);
+  bool upper = c2 <= E - 1 || (jU > jL && js <= jU);
   if (c2 == E && jU == jL) upper = z < X[int64_t(js + 1) * E];
   *certified = c2 >= 1 && upper;
   return js * E + c2 - 1;
@@ -1031,45 +1222,70 @@ __device__ int32_t full_search_counted(T z, const T* __restrict__ X, int32_t N, 
 }
 
 // One 64-query group per wave and iteration; the next group's queries are
-// loaded before this group is worked on.  A query bisects its window down to
-// one 64-byte block, then scans it (scan_window); a result the scan cannot
-// certify (never expected) takes a full binary search and is counted.
-template <typename T, bool F16>
+// loaded before this group is worked on.  A query is routed to its segment
+// (the compiled router's grid and steps in LDS, or the network evaluated on
+// the matrix cores), takes its window from the segment's fit, finds the
+// 64-byte block of X that holds its answer from the samples of the window's
+// blocks, and counts that block's values <= z (COOP: four lanes read each
+// block together); a result that could not be certified (never expected)
+// takes a full binary search and is counted.
+template <typename T, int ROUTE, bool COOP>
 __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ RouterShared16 S;
-  stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.segs), int64_t(a.nseg) * sizeof(SegFit));
+  RouterShared16* Sp = nullptr;  // FP16 router's shared values (no static LDS in the other modes)
+  const int64_t seg_bytes = int64_t(a.nseg) * sizeof(SegFit);
+  stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.segs), seg_bytes);
   const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
+  const float* steps = reinterpret_cast<const float*>(smem + seg_bytes);
+  const uint32_t* grid = reinterpret_cast<const uint32_t*>(smem + seg_bytes + int64_t(a.nseg) * 4);
   // FP16 router: half-wave-uniform values in LDS, W2 rows in registers
   half4 w2[4];
   RouterRegs R;
-  if constexpr (F16)
-    fill_router_shared16(a.params, &S, w2);
-  else
+  if constexpr (ROUTE == kRouteTable) {
+    if (!a.identity) {
+      stage_bytes(smem + seg_bytes, reinterpret_cast<const unsigned char*>(a.steps), int64_t(a.nseg) * 4);
+      stage_bytes(smem + seg_bytes + int64_t(a.nseg) * 4, reinterpret_cast<const unsigned char*>(a.grid),
+                  (int64_t(4) << a.log2g));
+    }
+  } else if constexpr (ROUTE == kRouteF16) {
+    __shared__ RouterShared16 S;
+    Sp = &S;
+    fill_router_shared16(a.params, Sp, w2);
+  } else {
     load_router(a.params, R);
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t stride = waves * 64;
   int64_t base = wave * 64;
-  auto load_z = [&](int64_t q) { return q < a.M ? __builtin_nontemporal_load(a.z + q) : a.X0; };
+  // the load is unconditional (the index clamped to the last query; the lanes
+  // past M discard their result), so the compiler can leave the next group's
+  // load in flight: under a branch it could not count it and would wait for it
+  auto load_z = [&](int64_t q) { return __builtin_nontemporal_load(a.z + std::min(q, a.M - 1)); };
   T z = load_z(base + lane);
   for (; base < a.M; base += stride) {
     const T z_next = load_z(base + stride + lane);
     const float u = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
-    float y_net;
-    if constexpr (F16) {
-      asm volatile("" ::: "memory");  // keeps the LDS reads of the router inside the loop
-      y_net = route_pair_shared16(u, w2, &S);
+    int32_t seg;
+    if constexpr (ROUTE == kRouteTable) {
+      seg = a.identity ? segment_of(u, a.nseg) : grid_segment(u, steps, grid, a.log2g);
     } else {
-      y_net = route_pair<false>(u, &R);
+      float y_net;
+      if constexpr (ROUTE == kRouteF16) {
+        asm volatile("" ::: "memory");  // keeps the LDS reads of the router inside the loop
+        y_net = route_pair_shared16(u, w2, Sp);
+      } else {
+        y_net = route_pair<false>(u, &R);
+      }
+      seg = segment_of(a.identity ? u : route_coord(y_net, u), a.nseg);
     }
-    const float y = a.identity ? u : route_coord(y_net, u);
     int32_t L, U;
-    query_window<T>(z, y, a, segs, &L, &U);
+    query_window<T>(z, seg, segs, &L, &U);
     bool certified;
-    int32_t i = sample_search<T>(z, L, U, a.X, a.S, &certified);
+    int32_t i = COOP ? sample_search_coop<T>(z, L, U, a.X, a.S, &certified)
+                     : sample_search<T>(z, L, U, a.X, a.S, &certified);
     if ((z >= a.X0) && (z < a.XN) && !certified) i = full_search_counted<T>(z, a.X, a.N, a.fallbacks);
     i = (z >= a.XN) ? a.N : i;
     i = (z >= a.X0) ? i : -1;
@@ -1083,6 +1299,29 @@ template <typename T>
 __global__ void fill_inf_kernel(T* __restrict__ Xp, int64_t from, int64_t to) {
   const int64_t k = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < to) Xp[k] = std::numeric_limits<T>::infinity();
+}
+
+// Largest grid of the compiled router (cells) and the most segments of a
+// single-array model: its search stages the fits (32 bytes each), the steps
+// (4 bytes each) and the grid (4 bytes per cell) in one workgroup's LDS.
+constexpr int32_t kMaxLog2Grid = 12;
+constexpr int32_t kMaxLearnSegments = 4096;
+constexpr int64_t kLearnLdsBudget = 160 * 1024;
+
+// grid cells for nseg segments: as many cells as segments (rounded up to a
+// power of two), at most 4096, and fewer where the LDS budget requires
+int32_t grid_log2(int32_t nseg) {
+  int32_t k = 0;
+  while (k < kMaxLog2Grid && (1 << k) < nseg) ++k;
+  while (k > 0 && int64_t(nseg) * (int64_t(sizeof(SegFit)) + 4) + (int64_t(4) << k) > kLearnLdsBudget) --k;
+  return k;
+}
+
+// the network's parameters, the segment fits and, for the compiled router, its step table and grid
+int64_t learned_model_bytes(const LearnedModel* L) {
+  const bool table = L->router == kRouteTable && !L->identity;
+  return int64_t(kParams) * 4 + int64_t(L->nseg) * (int64_t(sizeof(SegFit)) + (table ? 4 : 0)) +
+         (table ? (int64_t(4) << L->log2g) : 0);
 }
 
 template <typename T>
@@ -1136,10 +1375,12 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
     L->fscale = 1.0 / (static_cast<double>(b1) - L->flo);
   }
   const int32_t nseg = o->learn_segments > 0 ? o->learn_segments : 4096;
-  if (nseg < 1 || nseg > 8192) return DS_ERR_ARG;
+  if (nseg < 1 || nseg > kMaxLearnSegments) return DS_ERR_ARG;
   L->nseg = nseg;
   L->identity = (o->learn_epochs < 0) ? 1 : 0;
-  L->f16 = (o->learn_flags & DS_LEARN_FP32_ROUTER) ? 0 : 1;
+  L->router = (o->learn_flags & DS_LEARN_FP32_ROUTER) ? kRouteF32
+             : (o->learn_flags & DS_LEARN_EVAL_ROUTER) ? kRouteF16
+                                                       : kRouteTable;
   const int32_t batch = o->learn_batch > 0 ? o->learn_batch : 8192;
   const int32_t epochs = o->learn_epochs > 0 ? o->learn_epochs : (o->learn_epochs == 0 ? 60 : 0);
   const float lr = o->learn_rate > 0 ? o->learn_rate : 2e-3f;
@@ -1151,6 +1392,8 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
       hipMalloc(&L->feat, size_t(n) * 4) != hipSuccess || hipMalloc(&L->route, size_t(n) * 4) != hipSuccess ||
       hipMalloc(&L->first, size_t(nseg + 1) * 4) != hipSuccess ||
       hipMalloc(&L->segs, size_t(nseg) * sizeof(SegFit)) != hipSuccess ||
+      hipMalloc(&L->steps, size_t(nseg) * 4) != hipSuccess ||
+      hipMalloc(&L->grid, size_t(4) << kMaxLog2Grid) != hipSuccess ||
       hipMalloc(&L->fallbacks, 8) != hipSuccess)
     return DS_ERR_OOM;
   // initial weights: layer-1 ramps spread over [0, 1], layer 2 averaging them,
@@ -1206,12 +1449,22 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
     L->final_loss = fl;
   }
   // route the keys with the search-time router, then segments, fits and bounds
-  if (L->f16)
+  if (L->router == kRouteTable && !L->identity) {
+    router_steps_kernel<<<dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s>>>(L->params, nseg, L->steps);
+    steps_monotone_kernel<<<1, 64, 0, s>>>(L->steps, nseg);
+    L->log2g = grid_log2(nseg);
+    router_grid_kernel<<<dim3((unsigned)(((1 << L->log2g) + 255) / 256)), dim3(256), 0, s>>>(L->steps, nseg, L->log2g,
+                                                                                          L->grid);
+    route_keys_table_kernel<<<dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s>>>(
+        L->steps, L->feat, n, nseg, L->route);
+  } else if (L->router == kRouteF16) {
     route_keys_kernel<true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
                                                                                   L->identity, L->route, nullptr);
-  else
+  } else {
+    // the FP32 network, or the identity router (routed by the same kernel)
     route_keys_kernel<false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(L->params, L->feat, n, nseg,
                                                                                    L->identity, L->route, nullptr);
+  }
   seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first);
   seg_fit_kernel<T><<<dim3(nseg), dim3(kFitLanes), 0, s>>>(X, N, L->first, L->segs, nseg, nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
@@ -1239,7 +1492,7 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   L->partial = nullptr;
   L->route = nullptr;
   L->first = nullptr;
-  h->info.model_bytes = int64_t(kParams) * 4 + int64_t(nseg) * int64_t(sizeof(SegFit));
+  h->info.model_bytes = learned_model_bytes(L);
   return DS_OK;
 }
 
@@ -1251,6 +1504,9 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   a.S = static_cast<const T*>(L->samples);
   a.params = L->params;
   a.segs = L->segs;
+  a.steps = L->steps;
+  a.grid = L->grid;
+  a.log2g = L->log2g;
   a.fallbacks = L->fallbacks;
   a.z = static_cast<const T*>(z);
   a.out = out;
@@ -1264,8 +1520,18 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   a.N = static_cast<int32_t>(h->N);
   a.nseg = L->nseg;
   a.identity = L->identity;
-  const int lds = static_cast<int>(int64_t(L->nseg) * sizeof(SegFit));
-  auto kern = L->f16 ? learned_search_kernel<T, true> : learned_search_kernel<T, false>;
+  const bool table = L->router == kRouteTable && !L->identity;
+  const int lds = static_cast<int>(int64_t(L->nseg) * (sizeof(SegFit) + (table ? 4 : 0)) +
+                                   (table ? (int64_t(4) << L->log2g) : 0));
+  // ds_tune.stage 1: each lane reads its own lines of S and X; else (0, 2) the
+  // lines are read cooperatively by the quads of the wave
+  const bool coop = !(h->tune_set && h->tune.stage == 1);
+  auto kern = L->router == kRouteTable ? (coop ? learned_search_kernel<T, kRouteTable, true>
+                                               : learned_search_kernel<T, kRouteTable, false>)
+              : L->router == kRouteF16 ? (coop ? learned_search_kernel<T, kRouteF16, true>
+                                               : learned_search_kernel<T, kRouteF16, false>)
+                                      : (coop ? learned_search_kernel<T, kRouteF32, true>
+                                              : learned_search_kernel<T, kRouteF32, false>);
   if (lds > 64 * 1024)
     DS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      lds));
@@ -1298,6 +1564,7 @@ void learned_free(ds_index* h) {
   for (void* p : {static_cast<void*>(L->params), static_cast<void*>(L->adam_m), static_cast<void*>(L->adam_v),
                   static_cast<void*>(L->partial), static_cast<void*>(L->loss_partial), static_cast<void*>(L->feat),
                   static_cast<void*>(L->route), static_cast<void*>(L->first), static_cast<void*>(L->segs),
+                  static_cast<void*>(L->steps), static_cast<void*>(L->grid),
                   static_cast<void*>(L->samples), static_cast<void*>(L->fallbacks)})
     if (p) (void)hipFree(p);
   delete L;
@@ -1459,7 +1726,7 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
       }
       const float y = route_coord(y_net, u);
       int32_t L, U;
-      query_window<T>(zq, y, a, segs, &L, &U);
+      query_window<T>(zq, segment_of(y, b.nseg), segs, &L, &U);
       bool certified;
       int32_t i = sample_search_packed<T>(zq, L, U, static_cast<const T*>(b.X), static_cast<const T*>(b.samples),
                                           m.x_off, a.N, b.total_x, &certified);
@@ -1541,7 +1808,7 @@ ds_status batched_learned_search(const BatchLearned& b, int dtype, hipStream_t s
 void learned_fill_info(const ds_index* h, ds_info_t* in) {
   const LearnedModel* L = h->learned;
   if (!L) return;
-  in->model_bytes = int64_t(kParams) * 4 + int64_t(L->nseg) * int64_t(sizeof(SegFit));
+  in->model_bytes = learned_model_bytes(L);
   in->x_bytes += L->nsamples * int64_t(h->dt == DS_F32 ? 4 : 8);  // the search's sample array
   in->max_err = L->max_err;
   in->mean_log2_window = L->mean_log2_window;

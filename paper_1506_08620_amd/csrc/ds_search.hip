@@ -571,6 +571,13 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   if (t->block != 0 && (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)) return DS_ERR_ARG;
   if (t->unroll != 0 && t->unroll != 1 && t->unroll != 2 && t->unroll != 4) return DS_ERR_ARG;
   if (t->stage < 0 || t->stage > 7) return DS_ERR_ARG;
+  if (h->method == DS_METHOD_LEARNED) {
+    // learned: stage 1 = each lane reads its own lines, 2 = the wave reads them cooperatively
+    if (t->stage > 2 || t->unroll != 0 || t->grid < 0) return DS_ERR_ARG;
+    h->tune = *t;
+    h->tune_set = true;
+    return DS_OK;
+  }
   if ((t->stage == 6 || t->stage == 7) && !h->nib) return DS_ERR_ARG;
   if (t->stage == 7 && ds::direct_lds_bytes(h, 7) > ds::kLdsBytesPerCU) return DS_ERR_ARG;
   if (t->stage == 5 && (!h->rc_w16 || !h->rc_code8)) return DS_ERR_ARG;

@@ -104,9 +104,10 @@ def test_learned_exact_on_clustered_arrays(ds, dt):
         X = _clustered(n, dt, n)
         z = _queries(X, 100_000, rng)
         ref = oracle.search(X, z)
-        for epochs, f32 in ((20, False), (20, True), (-1, False)):  # trained router (FP16 / FP32 layer), no network
+        # trained router (compiled step table; evaluated per query with FP16 / FP32 inputs), no network
+        for epochs, router in ((20, "table"), (20, "fp16"), (20, "fp32"), (-1, "table")):
             idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=segs, seed=3,
-                           learn_fp32_router=f32)
+                           learn_router=router)
             inf = idx.info()
             assert inf["method_name"] == "learned"
             _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
@@ -114,7 +115,10 @@ def test_learned_exact_on_clustered_arrays(ds, dt):
             assert fb == 0
             torch.cuda.synchronize()
             assert idx.info()["fallback_count"] == 0
-            assert inf["model_bytes"] == 1153 * 4 + segs * 32
+            table = router == "table" and epochs > 0
+            # fits (32 bytes each); the compiled router adds its steps (4 bytes per segment) and a grid of
+            # as many 4-byte cells as segments
+            assert inf["model_bytes"] == 1153 * 4 + segs * (40 if table else 32)
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
@@ -149,6 +153,26 @@ def test_learned_tiny_arrays(ds, dt):
             _, fb = idx.learned_model()
             assert fb == 0
             idx.destroy()
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_learned_read_modes_and_shapes(ds, dt):
+    """The search's launch choices (each lane reading its own lines, or the blocks of X read by
+    four lanes together; workgroup sizes) give the same exact indices, for the compiled router
+    and the identity router."""
+    rng = np.random.default_rng(29)
+    X = _clustered(30_000, dt, 30_000)
+    z = _queries(X, 70_001, rng)  # not a multiple of 64: the tail wave reads clamped queries
+    ref = oracle.search(X, z)
+    for epochs in (10, -1):
+        idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=1024, seed=4)
+        for stage in (1, 2):
+            for block in (256, 1024):
+                idx.set_tune(stage=stage, block=block)
+                _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
+        _, fb = idx.learned_model()
+        assert fb == 0
+        idx.destroy()
 
 
 def test_uniform_gaps_give_tight_windows(ds):
