@@ -288,3 +288,71 @@ def test_h_growth_reaches_a_valid_h_when_needed():
             z = _queries_for(X, rng, 2000)
             assert np.array_equal(oracle.direct(X, t, z), oracle.search(X, z))
     assert seen > 0
+
+
+
+def _rn32(v):
+    """A rational rounded to the nearest float32, ties to even (correct single rounding)."""
+    from fractions import Fraction
+    c = np.float32(float(v))
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - v)
+        key = (d, int(np.frombuffer(np.float32(cand).tobytes(), np.uint32)[0]) & 1)
+        if best is None or key < best[0]:
+            best = (key, cand)
+    return best[1]
+
+
+def _separated_f32(X, H, form):
+    """eq. (cond2) at H for every pair, evaluated independently in float32: the subtraction
+    form with numpy's correctly rounded float32 operations, the FMA form exactly (rationals,
+    one rounding), W = RN(H X_0) recomputed for H."""
+    from fractions import Fraction
+    H = np.float32(H)
+    if form == oracle.FORM_SUB:
+        f = np.floor(H * (X - X[0]))
+    else:
+        Wv = H * X[0]
+        f = np.array([np.floor(_rn32(Fraction(float(H)) * Fraction(float(x)) - Fraction(float(Wv)))) for x in X])
+    return bool(np.all(np.diff(f) > 0))
+
+
+def _start_h(X, dt):
+    """phi(Hbar) of Sec. 4.4.3 from its definition: Hbar = RN(1 / min RN(D_{i+1} - D_i)),
+    D_i = RN(X_i - X_0), all in the dtype; phi is the next float up."""
+    D = (X - X[0]).astype(dt)
+    g = np.min((D[1:] - D[:-1]).astype(dt))
+    hbar = (dt.type(1) / g).astype(dt)
+    return np.nextafter(hbar, dt.type(np.inf))
+
+
+@pytest.mark.parametrize("form", [oracle.FORM_SUB, oracle.FORM_FMA])
+def test_h_growth_visits_one_fixed_sequence(form):
+    """ComputeHR (Sec. 4.4.3) grows H by P, starting at one step of H (phi(H) - H), adding P
+    first and doubling it after, never resetting it between pairs, and re-checks every pair
+    until none moves.  So the values of H it can stand on form one fixed sequence
+    H_0 = phi(Hbar), H_(k+1) = RN(H_k + 2^k P_0), and it leaves H_k only when some pair still
+    shares a cell there: the result must be the first H_k at which every pair is separated,
+    after exactly k updates.  A reset of P per pair, or doubling before adding, stands on other
+    values and fails this on the near-limit arrays below (16 to 23 updates each).  Single
+    precision only: the two precisions share one definition in the oracle, and in double
+    precision the arrays whose cells coincide through rounding have R above 2^31."""
+    dt = np.dtype(np.float32)
+    rng = np.random.default_rng(1506 + form)
+    checked = 0
+    for a in range(1500 if form == oracle.FORM_SUB else 300):
+        X = W.near_limit_array(dt, rng, q=int(rng.integers(1, 4)), n_fill=int(rng.integers(0, 40)),
+                               offset=bool(a % 2))
+        t = oracle.compute_hr(X, form)
+        if t.status != oracle.OK or t.n_updates == 0:
+            continue
+        H, P = _start_h(X, dt), None
+        P = np.nextafter(H, dt.type(np.inf)) - H
+        for k in range(64):
+            if _separated_f32(X, H, form):
+                break
+            H, P = np.float32(H + P), np.float32(P + P)
+        assert (t.n_updates, t.H) == (k, float(H)), (a, t.n_updates, k, t.H, float(H))
+        checked += 1
+    assert checked >= (100 if form == oracle.FORM_SUB else 30), checked
