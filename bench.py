@@ -277,7 +277,8 @@ def main():
         targets["batched_f32_gq_s"] = {"graph": bf["gq_s_graph_replay"], "eager": bf["gq_s_end_to_end"]}
     bl = extras.get("batched_learned_f64_mixture")
     if bl:
-        targets["batched_learned_f64_gq_s"] = bl["gq_s_end_to_end"]
+        targets["batched_learned_f64_gq_s"] = {"trained": bl["gq_s_end_to_end"],
+                                               "no_network": bl["no_network"]["gq_s_end_to_end"]}
     keep = ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel", "avg_launch_ms", "bytes_per_launch",
             "l2")
     line = {
@@ -529,25 +530,36 @@ def bench_batched_learned(ds, W, dev, stream, reps):
 
     b = W.batched_mixture(with_queries=False)
     z = W.batched_mixture_queries_torch(b, dev)
-    bt = ds.Batch(torch.from_numpy(b.x_off).to(dev), torch.from_numpy(b.X).to(dev),
-                  torch.from_numpy(b.q_off).to(dev), z, learn_segments=4096, direct_cap_bytes=64 << 20)
-    bt.run(stream)
-    torch.cuda.synchronize()
-    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(reps):
-        bt.run(stream)
-    e.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(e) / reps
+    x_off, X, q_off = (torch.from_numpy(a).to(dev) for a in (b.x_off, b.X, b.q_off))
     total_q = int(b.q_off[-1])
-    meth, _ = bt.report()
-    res = dict(arrays=b.num_arrays, total_x=int(b.x_off[-1]), total_q=total_q, ms_end_to_end=round(ms, 3),
-               gq_s_end_to_end=round(total_q / ms / 1e6, 2),
-               direct_arrays=int((meth == ds.METHOD_DIRECT).sum()),
-               learned_arrays=int((meth == ds.METHOD_LEARNED).sum()), fallbacks=bt.fallbacks(),
-               note="end to end includes the device build and the training steps (10 by default) of every learned model")
-    del z, bt
+    res = dict(arrays=b.num_arrays, total_x=int(b.x_off[-1]), total_q=total_q,
+               note="end to end: device build, training of every learned model (10 steps, one launch), "
+                    "router compilation, fits and search")
+    ref = None
+    # the trained routers, and the same models with the router replaced by the feature (no network)
+    for name, steps in (("trained", 0), ("no_network", -1)):
+        bt = ds.Batch(x_off, X, q_off, z, learn_segments=4096, learn_steps=steps, direct_cap_bytes=64 << 20)
+        bt.run(stream)
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            bt.run(stream)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(e) / reps
+        meth, _ = bt.report()
+        row = dict(ms_end_to_end=round(ms, 3), gq_s_end_to_end=round(total_q / ms / 1e6, 2),
+                   direct_arrays=int((meth == ds.METHOD_DIRECT).sum()),
+                   learned_arrays=int((meth == ds.METHOD_LEARNED).sum()), fallbacks=bt.fallbacks())
+        if ref is None:
+            ref = bt.out.clone()
+            res.update(row)
+        else:
+            row["same_as_trained"] = bool(torch.equal(bt.out, ref))
+            res[name] = row
+        del bt
+    del z, ref
     torch.cuda.empty_cache()
     return res
 

@@ -364,8 +364,8 @@ ds_status ds_learned_model(ds_handle h, float* params_host, int32_t capacity, ui
  * device with ComputeHR of Sec. 4.4.3, searched through the RANKCODE layout)
  * is used whenever it is feasible, its table is under direct_cap_bytes and it
  * fits the workspace; every other array is searched with the learned method
- * when learn_segments > 0 (a model per array, all trained together: each
- * training step is one launch over all learned arrays) and with the offset
+ * when learn_segments > 0 (a model per array, all trained together in one
+ * launch, one workgroup per model running every step) and with the offset
  * binary search (Sec. 3.3) otherwise.  Results are identical either way.  Special arrays: N_k = -1 (no value) gives -1 for
  * all its queries; N_k = 0 (one value) gives -1 below X_0 and 0 otherwise; an
  * array that is not strictly increasing or holds NaN/inf gives -2.
@@ -388,10 +388,12 @@ typedef struct ds_batch_desc {
   int32_t block;              /* threads per search workgroup, 64..1024 step 64; 0 = auto (1024) */
   int32_t lds_bytes;          /* LDS budget per search workgroup; 0 = auto (159 KiB), -1 = never stage */
   int32_t qpt;                /* queries in flight per lane: 4, 8 or 16; 0 = auto (8) */
-  int32_t learn_segments;     /* > 0: arrays where Direct is infeasible, over direct_cap_bytes or out of
+  int32_t learn_segments;     /* 1..4096: arrays where Direct is infeasible, over direct_cap_bytes or out of
                                  table room use the learned method with this many segments per array
                                  (the workspace must be sized with the same value); 0: binary search */
-  int32_t learn_steps;        /* learned: training steps (one batched launch each, 2048 samples per array); 0 = 10 */
+  int32_t learn_steps;        /* learned: training steps of every model (2048 samples per array and step,
+                                 all steps of all models in one launch); 0 = 10; -1 = no network: the
+                                 segments split the feature evenly (the ablation of the router) */
   int32_t reserved_;
   int64_t direct_cap_bytes;   /* per-array cap on the Direct table (4 bytes per grid cell); 0 = none */
 } ds_batch_desc;

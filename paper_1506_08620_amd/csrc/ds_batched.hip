@@ -46,7 +46,7 @@ constexpr int kMaxGrowthRounds = 4096;
 struct WsLayout {
   size_t meta, chunk_first, tile_off, totals, codes, bits, base, end;
   // learned region (present when nseg > 0)
-  size_t lmeta, params, adam_m, adam_v, partial, loss, segs, first, feat, samples;
+  size_t lmeta, params, adam_m, adam_v, steps, grid, segs, first, feat, samples;
   int64_t words_budget;
   int64_t codes_cap;
   int32_t nseg;
@@ -75,8 +75,8 @@ WsLayout ws_layout(int32_t K, int64_t total_x, int64_t words_budget, int32_t nse
     L.params = take(size_t(K) * P);
     L.adam_m = take(size_t(K) * P);
     L.adam_v = take(size_t(K) * P);
-    L.partial = take(size_t(K) * kBatchLearnParts * P);
-    L.loss = take(size_t(K) * kBatchLearnParts * 4);
+    L.steps = take(size_t(K) * size_t(nseg) * 4);
+    L.grid = take(size_t(K) * (size_t(4) << batch_grid_log2(nseg)));
     L.segs = take(size_t(K) * size_t(nseg) * kSegFitBytes);
     L.first = take(size_t(K) * size_t(nseg + 1) * 4);
     L.feat = take(size_t(total_x) * 4);
@@ -1088,8 +1088,9 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.tot = reinterpret_cast<PlanTotals*>(ws + L.totals);
   b.K = d->num_arrays;
   b.nseg = L.nseg;
-  b.steps = d->learn_steps > 0 ? d->learn_steps : 10;
-  b.fp32_router = 0;
+  b.identity = d->learn_steps < 0 ? 1 : 0;
+  b.steps = d->learn_steps > 0 ? d->learn_steps : (d->learn_steps == 0 ? 10 : 0);
+  b.log2g = batch_grid_log2(L.nseg);
   b.seed = 0x1506ull;
   b.tile = tile_of(d);
   b.X = d->X_dev;
@@ -1100,8 +1101,8 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.params = reinterpret_cast<float*>(ws + L.params);
   b.adam_m = reinterpret_cast<float*>(ws + L.adam_m);
   b.adam_v = reinterpret_cast<float*>(ws + L.adam_v);
-  b.partial = reinterpret_cast<float*>(ws + L.partial);
-  b.loss = reinterpret_cast<float*>(ws + L.loss);
+  b.steps_tab = reinterpret_cast<float*>(ws + L.steps);
+  b.grid = reinterpret_cast<uint32_t*>(ws + L.grid);
   b.segs = ws + L.segs;
   b.first = reinterpret_cast<int32_t*>(ws + L.first);
   b.feat = reinterpret_cast<float*>(ws + L.feat);
@@ -1222,7 +1223,8 @@ extern "C" {
 
 size_t ds_batch_workspace_bytes(int32_t num_arrays, int64_t total_x, int64_t table_budget_entries,
                                 int32_t learn_segments) {
-  if (num_arrays < 0 || total_x < 0 || table_budget_entries < 0 || learn_segments < 0 || learn_segments > 8192)
+  if (num_arrays < 0 || total_x < 0 || table_budget_entries < 0 || learn_segments < 0 ||
+      learn_segments > ds::kBatchMaxSegments)
     return 0;
   // each array's words are rounded up to a multiple of 4, plus one partial word
   const int64_t words = table_budget_entries > 0 ? table_budget_entries / 64 + int64_t(num_arrays) * 4 + 16 : 0;
@@ -1241,7 +1243,8 @@ ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s) {
   if (d->block != 0 && (d->block < 64 || d->block > 1024 || d->block % 64)) return DS_ERR_ARG;
   if (d->qpt != 0 && d->qpt != 4 && d->qpt != 8 && d->qpt != 16) return DS_ERR_ARG;
   if (d->tile < 0) return DS_ERR_ARG;
-  if (d->learn_segments < 0 || d->learn_segments > 8192 || d->learn_steps < 0 || d->direct_cap_bytes < 0)
+  if (d->learn_segments < 0 || d->learn_segments > ds::kBatchMaxSegments || d->learn_steps < -1 ||
+      d->direct_cap_bytes < 0)
     return DS_ERR_ARG;
   if (d->workspace_bytes < ds_batch_workspace_bytes(d->num_arrays, d->total_x, 0, d->learn_segments))
     return DS_ERR_ARG;
@@ -1252,7 +1255,8 @@ ds_status ds_search_batched(const ds_batch_desc* d, hipStream_t s) {
 
 ds_status ds_search_batched_noalloc(const ds_batch_desc* d, hipStream_t s) {
   if (!d) return DS_ERR_ARG;
-  if (d->num_arrays < 0 || d->total_x < 0 || d->learn_segments < 0 || d->learn_segments > 8192) return DS_ERR_ARG;
+  if (d->num_arrays < 0 || d->total_x < 0 || d->learn_segments < 0 || d->learn_segments > ds::kBatchMaxSegments)
+    return DS_ERR_ARG;
   const size_t need = ds_batch_workspace_bytes(d->num_arrays, d->total_x, 0, d->learn_segments);
   if (need == 0) return DS_ERR_ARG;
   if (need > size_t(DS_NOALLOC_SCRATCH_BYTES)) return DS_ERR_SCRATCH_CAP;

@@ -12,7 +12,7 @@ constexpr int kNumQueues = 8;        // one tile queue per XCD
 constexpr int kRouterParams = 1153;  // 1 -> 32 -> 32 -> 1 router
 constexpr int kSegFitBytes = 32;
 constexpr int kBatchLearnSamples = 2048;  // training samples per array and step
-constexpr int kBatchLearnParts = kBatchLearnSamples / 256;
+constexpr int kBatchMaxSegments = 4096;   // the search stages a model's fits, steps and grid in LDS
 
 template <typename T>
 struct alignas(16) ArrMeta {
@@ -60,8 +60,10 @@ struct BatchLearned {
   PlanTotals* tot;
   int32_t K;
   int32_t nseg;
-  int32_t steps;
-  int32_t fp32_router;
+  int32_t steps;     // training steps (0 with the identity router)
+  int32_t identity;  // 1: no network, segments of the feature itself (the ablation)
+  int32_t log2g;     // cells of each model's router grid (2^log2g)
+  int32_t pad_;
   uint64_t seed;
   int64_t tile;
   int64_t total_x;         // values in the packed X (reads never pass its end)
@@ -72,8 +74,8 @@ struct BatchLearned {
   float* params;           // [K][kRouterParams]
   float* adam_m;
   float* adam_v;
-  float* partial;          // [K][kBatchLearnParts][kRouterParams]
-  float* loss;             // [K][kBatchLearnParts]
+  float* steps_tab;        // [K][nseg] compiled router steps
+  uint32_t* grid;          // [K][2^log2g] compiled router grid
   void* segs;              // [K][nseg] segment fits
   int32_t* first;          // [K][nseg + 1]
   float* feat;             // [total_x]
@@ -98,6 +100,7 @@ __device__ __forceinline__ int32_t wave_last_le(const int64_t* __restrict__ off,
 }
 
 // implemented in ds_learned.hip
+int32_t batch_grid_log2(int32_t nseg);  // grid cells of a batched model's compiled router (log2)
 ds_status batched_learned_build(const BatchLearned& b, int dtype, hipStream_t s);
 ds_status batched_learned_search(const BatchLearned& b, int dtype, hipStream_t s);
 

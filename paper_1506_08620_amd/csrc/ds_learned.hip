@@ -396,19 +396,6 @@ __device__ __forceinline__ int32_t grid_segment(float u, const float* steps, con
   return lo;
 }
 
-// grid cells of the compiled router (one thread per cell), from its steps
-__global__ void router_grid_kernel(const float* __restrict__ steps, int32_t nseg, int32_t log2g,
-                                   uint32_t* __restrict__ grid) {
-  const int32_t g = 1 << log2g;
-  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g) return;
-  const float scale = std::ldexp(1.0f, -log2g);
-  const float u0 = static_cast<float>(c) * scale;
-  const float u1 = (c == g - 1) ? 1.0f : std::nextafter(static_cast<float>(c + 1) * scale, 0.0f);
-  const int32_t s0 = table_segment(u0, steps, nseg), s1 = table_segment(u1, steps, nseg);
-  grid[c] = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(s1 - s0) << 16);
-}
-
 // ---------------------------------------------------------------------------
 // build kernels
 
@@ -444,22 +431,168 @@ __device__ __forceinline__ uint32_t mix32(uint64_t x) {
   return static_cast<uint32_t>(x);
 }
 
-// One training step, forward and backward, on the matrix cores.  Sample q of
-// the workgroup (q = 64 w + 32 p + n: wave w, pass p, lane n % 32) is key
-// idx = mix(seed, step, j) mod n_keys, j = 256 blockIdx.x + q (or, when idx_in
-// is given, idx_in[j] with its own target t_in[j] and feature u_in[j]).
-// Lanes n and n + 32 carry the same sample and each holds half of its units:
-// unit out_row(r, h) in register r for lane half h, r = 0..15, which is where
-// v_mfma_f32_32x32x2f32 leaves row out_row(r, h) of its output.  The three
-// 32 x 32 contractions are:
-//   forward   a2 = W2 h1 + b2        (K = units; block r takes units out_row(r, 0/1),
-//                                    so h1 in the same registers is the B operand)
-//   backward  dh1 = W2^T da2          (the same K order, so da2 is the B operand as is)
-//   gradient  dW2 = da2^T h1          (K = the wave's 64 samples, after a transpose
-//                                    through LDS)
-// and the small gradients (W1, b1, b2, W3, b3) are sums over the LDS tiles.
-// The four waves' gradients are added in a fixed order and written to
-// partial[blockIdx.x * kParams]: deterministic.
+constexpr int kLd = kHid + 1;  // padded row of the per-wave LDS tiles
+
+// Gradient sums of one wave (lane layout of the 32x32 MFMA tiles).
+struct GradAcc {
+  floatx16 g2;                         // dL/dW2, D[j][k] in the output layout
+  float gw1, gb1, gb2, gw3, gb3, ls;  // per lane: unit n = lane % 32, samples of half lane / 32
+};
+
+// Forward and backward pass of one wave over its 64 training samples, added
+// into acc.  sample(q, &u, &t) gives sample q's feature and target and whether
+// it exists.  The parameters are in LDS (sp); w2f / w2b hold the lane's row of
+// W2 and of its transpose; TA, TB, sv are the wave's own tiles.  Every wave of
+// the workgroup must call it together (it holds workgroup barriers).
+//   forward   h1 = clamp(W1 u + b1), a2 = W2 h1 + b2 (MFMA), y = W3 clamp(a2) + b3
+//   backward  dy = 2 (y - t) / batch, da2 = dy W3 [0 < h2 < 1], dW2 += da2 h1^T (MFMA
+//             over the 64 samples), da1 = W2^T da2 [0 < h1 < 1] (MFMA), dW1, db1, dW3,
+//             db3 as sums over the samples
+template <class Sample>
+__device__ __forceinline__ void wave_grad(const float* sp, const float (&w2f)[16], const float (&w2b)[16],
+                                          float (*TA)[kLd], float (*TB)[kLd], float (*sv)[3], float inv_b,
+                                          Sample sample, GradAcc& acc) {
+  const int lane = threadIdx.x & 63, n = lane & 31, h = lane >> 5;
+  float st_h2[2][16], st_da1[2][16];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int q = p * 32 + n;
+    float u = 0.0f, t = 0.0f;
+    const bool valid = sample(q, &u, &t);
+    float h1[16];
+    floatx16 acc2;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int un = out_row(r, h);
+      h1[r] = clamp01(std::fma(sp[oW1 + un], u, sp[oB1 + un]));
+      acc2[r] = sp[oB2 + un];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(w2f[r], h1[r], acc2, 0, 0, 0);
+    float part = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) part = std::fma(sp[oW3 + out_row(r, h)], clamp01(acc2[r]), part);
+    const float y = (part + __shfl_xor(part, 32, 64)) + sp[oB3];  // the same sum in both lanes
+    const float dy = valid ? 2.0f * (y - t) * inv_b : 0.0f;
+    const float l = valid ? (y - t) * (y - t) * inv_b : 0.0f;
+    float da2[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int un = out_row(r, h);
+      const float h2 = clamp01(acc2[r]);
+      st_h2[p][r] = h2;
+      // clamp(a) lies strictly inside (0, 1) exactly when a does, so the unit outputs give the masks
+      da2[r] = (h2 > 0.0f && h2 < 1.0f) ? dy * sp[oW3 + un] : 0.0f;
+      TA[q][un] = da2[r];
+      TB[q][un] = h1[r];
+    }
+    floatx16 d1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d1[r] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(w2b[r], da2[r], d1, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) st_da1[p][r] = (h1[r] > 0.0f && h1[r] < 1.0f) ? d1[r] : 0.0f;
+    if (h == 0) {
+      sv[q][0] = dy;
+      sv[q][1] = u;
+      sv[q][2] = l;
+    }
+  }
+  __syncthreads();
+  // dW2[j][k] += sum_s da2[s][j] h1[s][k]: K = the wave's 64 samples, two per instruction
+  // (lane half h supplies sample 2i + h); db2 from the same reads
+#pragma unroll 8
+  for (int i = 0; i < 32; ++i) {
+    const float a = TA[2 * i + h][n];
+    acc.gb2 += a;
+    acc.g2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, TB[2 * i + h][n], acc.g2, 0, 0, 0);
+  }
+  __syncthreads();
+  // phase 2: the tiles now hold h2 and da1
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      TA[p * 32 + n][out_row(r, h)] = st_h2[p][r];
+      TB[p * 32 + n][out_row(r, h)] = st_da1[p][r];
+    }
+  }
+  __syncthreads();
+  // lane (n, h): unit n over the samples s = 2i + h
+  for (int i = 0; i < 32; ++i) {
+    const int s2 = 2 * i + h;
+    const float da1 = TB[s2][n], dy = sv[s2][0];
+    acc.gw1 = std::fma(da1, sv[s2][1], acc.gw1);
+    acc.gb1 += da1;
+    acc.gw3 = std::fma(dy, TA[s2][n], acc.gw3);
+    acc.gb3 += dy;
+    acc.ls += sv[s2][2];
+  }
+  __syncthreads();
+}
+
+// The waves' gradients added in wave order into red[0 .. kParams] (kParams = the
+// loss); red is the workgroup's tile A, free once wave_grad returned.  The two
+// lane halves of each wave are combined first.  Ends with a barrier.
+template <int kWaves>
+__device__ __forceinline__ void reduce_waves(GradAcc& acc, float* red) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, n = lane & 31, h = lane >> 5;
+  acc.gw1 += __shfl_xor(acc.gw1, 32, 64);
+  acc.gb1 += __shfl_xor(acc.gb1, 32, 64);
+  acc.gw3 += __shfl_xor(acc.gw3, 32, 64);
+  acc.gb2 += __shfl_xor(acc.gb2, 32, 64);
+  acc.gb3 += __shfl_xor(acc.gb3, 32, 64);
+  acc.ls += __shfl_xor(acc.ls, 32, 64);
+  float* mine = red + w * (kParams + 1);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) mine[oW2 + out_row(r, h) * kHid + n] = acc.g2[r];
+  if (h == 0) {
+    mine[oW1 + n] = acc.gw1;
+    mine[oB1 + n] = acc.gb1;
+    mine[oB2 + n] = acc.gb2;
+    mine[oW3 + n] = acc.gw3;
+    if (n == 0) {
+      mine[oB3] = acc.gb3;
+      mine[kParams] = acc.ls;
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k <= kParams; k += kWaves * 64) {
+    float v = red[k];
+#pragma unroll
+    for (int ww = 1; ww < kWaves; ++ww) v += red[ww * (kParams + 1) + k];
+    red[k] = v;  // only thread k reads and writes column k
+  }
+  __syncthreads();
+}
+
+// the lane's rows of W2 (forward) and of its transpose (backward) from LDS
+__device__ __forceinline__ void load_w2_rows(const float* sp, float (&w2f)[16], float (&w2b)[16]) {
+  const int lane = threadIdx.x & 63, n = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int u = out_row(r, h);
+    w2f[r] = sp[oW2 + n * kHid + u];  // A of the forward: W2[n][u]
+    w2b[r] = sp[oW2 + u * kHid + n];  // A of the backward: W2[u][n]
+  }
+}
+
+// the training sample j of a step: a key drawn by a counter-based hash of
+// (seed, step, j), its feature and its target i / (n - 1)
+__device__ __forceinline__ void draw_sample(const float* feat, int64_t n_keys, uint64_t seed, int64_t step, int64_t j,
+                                            float* u, float* t) {
+  const uint64_t key = seed * 0x9E3779B97F4A7C15ull + static_cast<uint64_t>(step) * 0x100000001B3ull +
+                       static_cast<uint64_t>(j);
+  const int64_t idx = static_cast<int64_t>(mix32(key) % static_cast<uint32_t>(n_keys));
+  *u = feat[idx];
+  *t = static_cast<float>(static_cast<double>(idx) / static_cast<double>(n_keys - 1));
+}
+
+// One training step's gradient over a batch, split over workgroups of
+// kTrainBlock samples: each writes its sum (and its loss) to partial[part];
+// adam_kernel adds the parts in order.  Samples are given (u_in, t_in) or drawn
+// (draw_sample).  With lm, blockIdx.y is a model slot of the batched form.
 __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
     const float* __restrict__ params, const float* __restrict__ feat, int64_t n_keys, uint64_t seed, int64_t step,
     int32_t batch, const float* __restrict__ u_in, const float* __restrict__ t_in, float* __restrict__ partial,
@@ -476,152 +609,113 @@ __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
     loss_partial += (int64_t)slot * gridDim.x;
   }
   constexpr int kWaves = kTrainBlock / 64;
-  constexpr int kLd = kHid + 1;
   __shared__ float sp[kParams];
   __shared__ float tileA[kWaves][64][kLd];  // da2, then h2
   __shared__ float tileB[kWaves][64][kLd];  // h1, then da1
   __shared__ float svec[kWaves][64][3];     // dy, u, loss per sample
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, n = lane & 31, h = lane >> 5;
+  const int tid = threadIdx.x, w = tid >> 6;
   for (int k = tid; k < kParams; k += kTrainBlock) sp[k] = params[k];
   __syncthreads();
   float w2f[16], w2b[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int u = out_row(r, h);
-    w2f[r] = sp[oW2 + n * kHid + u];  // A of the forward: W2[n][u]
-    w2b[r] = sp[oW2 + u * kHid + n];  // A of the backward: W2[u][n]
-  }
-  float (*TA)[kLd] = tileA[w];
-  float (*TB)[kLd] = tileB[w];
-  const float inv_b = 1.0f / static_cast<float>(batch);
-  float st_h2[2][16], st_da1[2][16];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const int q = p * 32 + n;
+  load_w2_rows(sp, w2f, w2b);
+  GradAcc acc{};
+  auto sample = [&](int q, float* u, float* t) {
     const int64_t j = (int64_t)blockIdx.x * kTrainBlock + w * 64 + q;
-    const bool valid = j < batch;
-    float u = 0.0f, t = 0.0f;
-    if (valid) {
-      if (u_in) {
-        u = u_in[j];
-        t = t_in[j];
-      } else {
-        const uint64_t key = seed * 0x9E3779B97F4A7C15ull + static_cast<uint64_t>(step) * 0x100000001B3ull +
-                             static_cast<uint64_t>(j);
-        const int64_t idx = static_cast<int64_t>(mix32(key) % static_cast<uint32_t>(n_keys));
-        u = feat[idx];
-        t = static_cast<float>(static_cast<double>(idx) / static_cast<double>(n_keys - 1));
-      }
+    if (j >= batch) return false;
+    if (u_in) {
+      *u = u_in[j];
+      *t = t_in[j];
+    } else {
+      draw_sample(feat, n_keys, seed, step, j, u, t);
     }
-    float h1[16];
-    floatx16 acc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int un = out_row(r, h);
-      h1[r] = clamp01(std::fma(sp[oW1 + un], u, sp[oB1 + un]));
-      acc[r] = sp[oB2 + un];
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w2f[r], h1[r], acc, 0, 0, 0);
-    float part = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) part = std::fma(sp[oW3 + out_row(r, h)], clamp01(acc[r]), part);
-    const float y = (part + __shfl_xor(part, 32, 64)) + sp[oB3];  // the same sum in both lanes
-    const float dy = valid ? 2.0f * (y - t) * inv_b : 0.0f;
-    const float l = valid ? (y - t) * (y - t) * inv_b : 0.0f;
-    float da2[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int un = out_row(r, h);
-      const float h2 = clamp01(acc[r]);
-      st_h2[p][r] = h2;
-      // clamp(a) lies strictly inside (0, 1) exactly when a does, so the unit outputs give the masks
-      da2[r] = (h2 > 0.0f && h2 < 1.0f) ? dy * sp[oW3 + un] : 0.0f;
-      TA[q][un] = da2[r];
-      TB[q][un] = h1[r];
-    }
-    floatx16 d1;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) d1[r] = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) d1 = __builtin_amdgcn_mfma_f32_32x32x2f32(w2b[r], da2[r], d1, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) st_da1[p][r] = (h1[r] > 0.0f && h1[r] < 1.0f) ? d1[r] : 0.0f;
-    if (h == 0) {
-      svec[w][q][0] = dy;
-      svec[w][q][1] = u;
-      svec[w][q][2] = l;
-    }
-  }
-  __syncthreads();
-  // dW2[j][k] = sum_s da2[s][j] h1[s][k]: K = the wave's 64 samples, two per instruction
-  // (lane half h supplies sample 2i + h); db2 from the same reads
-  floatx16 g2;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) g2[r] = 0.0f;
-  float gb2 = 0.0f;
-#pragma unroll 8
-  for (int i = 0; i < 32; ++i) {
-    const float a = TA[2 * i + h][n];
-    gb2 += a;
-    g2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, TB[2 * i + h][n], g2, 0, 0, 0);
-  }
-  __syncthreads();
-  // phase 2: the tiles now hold h2 and da1
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      TA[p * 32 + n][out_row(r, h)] = st_h2[p][r];
-      TB[p * 32 + n][out_row(r, h)] = st_da1[p][r];
-    }
-  }
-  __syncthreads();
-  // lane (n, h): unit n over the samples s = 2i + h
-  float gw1 = 0.0f, gb1 = 0.0f, gw3 = 0.0f, gb3 = 0.0f, ls = 0.0f;
-  for (int i = 0; i < 32; ++i) {
-    const int s2 = 2 * i + h;
-    const float da1 = TB[s2][n], dy = svec[w][s2][0];
-    gw1 = std::fma(da1, svec[w][s2][1], gw1);
-    gb1 += da1;
-    gw3 = std::fma(dy, TA[s2][n], gw3);
-    gb3 += dy;
-    ls += svec[w][s2][2];
-  }
-  gw1 += __shfl_xor(gw1, 32, 64);
-  gb1 += __shfl_xor(gb1, 32, 64);
-  gw3 += __shfl_xor(gw3, 32, 64);
-  gb2 += __shfl_xor(gb2, 32, 64);
-  gb3 += __shfl_xor(gb3, 32, 64);
-  ls += __shfl_xor(ls, 32, 64);
-  __syncthreads();
-  // the four waves' gradients, added in wave order (tileA is free again)
+    return true;
+  };
+  wave_grad(sp, w2f, w2b, tileA[w], tileB[w], svec[w], 1.0f / static_cast<float>(batch), sample, acc);
   float* red = &tileA[0][0][0];  // kWaves x (kParams + 1) floats
   static_assert(kWaves * (kParams + 1) <= kWaves * 64 * kLd, "reduction fits the tile");
-  float* mine = red + w * (kParams + 1);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) mine[oW2 + out_row(r, h) * kHid + n] = g2[r];
-  if (h == 0) {
-    mine[oW1 + n] = gw1;
-    mine[oB1 + n] = gb1;
-    mine[oB2 + n] = gb2;
-    mine[oW3 + n] = gw3;
-    if (n == 0) {
-      mine[oB3] = gb3;
-      mine[kParams] = ls;
-    }
-  }
-  __syncthreads();
+  reduce_waves<kWaves>(acc, red);
   float* out = partial + (int64_t)blockIdx.x * kParams;
   for (int k = tid; k <= kParams; k += kTrainBlock) {
-    float v = red[k];
-#pragma unroll
-    for (int ww = 1; ww < kWaves; ++ww) v += red[ww * (kParams + 1) + k];
     if (k < kParams)
-      out[k] = v;
+      out[k] = red[k];
     else
-      loss_partial[blockIdx.x] = v;
+      loss_partial[blockIdx.x] = red[k];
   }
+}
+
+// Adam step of one parameter with its gradient g (step t >= 1), then the
+// projection of the weights onto w >= 0 that keeps the router monotone
+__device__ __forceinline__ float adam_update(int k, float p, float g, float* m, float* v, float lr, int64_t t) {
+  constexpr float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  const float mk = beta1 * m[k] + (1.0f - beta1) * g;
+  const float vk = beta2 * v[k] + (1.0f - beta2) * g * g;
+  m[k] = mk;
+  v[k] = vk;
+  const float bc1 = 1.0f - std::pow(beta1, static_cast<float>(t));
+  const float bc2 = 1.0f - std::pow(beta2, static_cast<float>(t));
+  p = p - lr * (mk / bc1) / (std::sqrt(vk / bc2) + eps);
+  const bool is_weight = (k < oB1) || (k >= oW2 && k < oB2) || (k >= oW3 && k < oB3);
+  return is_weight ? std::fmax(p, 0.0f) : p;
+}
+
+// step size of step st of steps: 2e-3 cosine-decayed to 5 % of it
+__host__ __device__ __forceinline__ float train_rate(float lr, int64_t st, int64_t steps) {
+  const float frac = static_cast<float>(st) / static_cast<float>(steps);
+  return lr * (0.05f + 0.95f * 0.5f * (1.0f + std::cos(3.14159265f * frac)));
+}
+
+// The whole training of the batched form in one launch: workgroup k trains the
+// model of learned slot k for every step (kBatchLearnSamples samples a step, in
+// kBatchTrainPasses passes of its kBatchTrainBlock lanes), sums the gradient of
+// its waves and passes in a fixed order, and applies the Adam step itself; the
+// parameters stay in LDS between steps.  No workgroup waits for another.
+constexpr int kBatchTrainBlock = 512;
+constexpr int kBatchTrainPasses = kBatchLearnSamples / kBatchTrainBlock;
+
+__global__ void __launch_bounds__(kBatchTrainBlock) batched_train_kernel(float* __restrict__ params,
+                                                                         float* __restrict__ adam_m,
+                                                                         float* __restrict__ adam_v,
+                                                                         const float* __restrict__ feat_all,
+                                                                         const LearnMeta* __restrict__ lm,
+                                                                         const PlanTotals* __restrict__ tot,
+                                                                         uint64_t seed0, int32_t steps, float lr) {
+  const int slot = blockIdx.x;
+  if (slot >= tot->n_learned) return;
+  constexpr int kWaves = kBatchTrainBlock / 64;
+  __shared__ float sp[kParams];
+  __shared__ float tileA[kWaves][64][kLd];
+  __shared__ float tileB[kWaves][64][kLd];
+  __shared__ float svec[kWaves][64][3];
+  static_assert(kWaves * (kParams + 1) <= kWaves * 64 * kLd, "reduction fits the tile");
+  const LearnMeta L = lm[slot];
+  const float* feat = feat_all + L.x_off;
+  const int64_t n_keys = int64_t(L.N) + 1;
+  const uint64_t seed = seed0 + 0x632BE59BD9B4E019ull * static_cast<uint64_t>(slot + 1);
+  float* p = params + (int64_t)slot * kParams;
+  float* m = adam_m + (int64_t)slot * kParams;
+  float* v = adam_v + (int64_t)slot * kParams;
+  const int tid = threadIdx.x, w = tid >> 6;
+  for (int k = tid; k < kParams; k += kBatchTrainBlock) sp[k] = p[k];
+  __syncthreads();
+  const float inv_b = 1.0f / static_cast<float>(kBatchLearnSamples);
+  for (int32_t st = 0; st < steps; ++st) {
+    float w2f[16], w2b[16];
+    load_w2_rows(sp, w2f, w2b);
+    GradAcc acc{};
+    for (int pass = 0; pass < kBatchTrainPasses; ++pass) {
+      auto sample = [&](int q, float* u, float* t) {
+        draw_sample(feat, n_keys, seed, st, int64_t(pass) * kBatchTrainBlock + w * 64 + q, u, t);
+        return true;
+      };
+      wave_grad(sp, w2f, w2b, tileA[w], tileB[w], svec[w], inv_b, sample, acc);
+    }
+    float* red = &tileA[0][0][0];
+    reduce_waves<kWaves>(acc, red);
+    const float lr_t = train_rate(lr, st, steps);
+    for (int k = tid; k < kParams; k += kBatchTrainBlock) sp[k] = adam_update(k, sp[k], red[k], m, v, lr_t, st + 1);
+    __syncthreads();
+  }
+  for (int k = tid; k < kParams; k += kBatchTrainBlock) p[k] = sp[k];
 }
 
 // Sums the per-workgroup gradients in a fixed order (deterministic), then,
@@ -629,8 +723,7 @@ __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
 // onto w >= 0.
 __global__ void __launch_bounds__(1024) adam_kernel(float* __restrict__ params, float* __restrict__ m,
                                                     float* __restrict__ v, const float* __restrict__ partial,
-                                                    int32_t n_parts, float lr, float beta1, float beta2, float eps,
-                                                    int64_t t, float* __restrict__ grad_out,
+                                                    int32_t n_parts, float lr, int64_t t, float* __restrict__ grad_out,
                                                     const PlanTotals* __restrict__ tot) {
   if (tot) {
     const int slot = blockIdx.x;
@@ -656,16 +749,7 @@ __global__ void __launch_bounds__(1024) adam_kernel(float* __restrict__ params, 
       grad_out[k] = g;
       continue;
     }
-    const float mk = beta1 * m[k] + (1.0f - beta1) * g;
-    const float vk = beta2 * v[k] + (1.0f - beta2) * g * g;
-    m[k] = mk;
-    v[k] = vk;
-    const float bc1 = 1.0f - std::pow(beta1, static_cast<float>(t));
-    const float bc2 = 1.0f - std::pow(beta2, static_cast<float>(t));
-    float p = params[k] - lr * (mk / bc1) / (std::sqrt(vk / bc2) + eps);
-    const bool is_weight = (k < oB1) || (k >= oW2 && k < oB2) || (k >= oW3 && k < oB3);
-    if (is_weight) p = std::fmax(p, 0.0f);
-    params[k] = p;
+    params[k] = adam_update(k, params[k], g, m, v, lr, t);
   }
 }
 
@@ -701,38 +785,134 @@ __global__ void __launch_bounds__(256) route_keys_kernel(const float* __restrict
   }
 }
 
-// Steps of the FP32 network's routing: lane t (1 <= t < nseg) finds the
-// smallest f32 u in [0, 1] whose segment segment_of(route_coord(y(u), u)) is
-// at least t, by bisection over the bit patterns of [0, 1] (ordered like the
-// values), 2.0f when no u reaches t; steps[0] = -inf.  Every lane of a wave
-// takes part in each evaluation of the network (the router works on 64 queries
-// at once), so the loop count is fixed and a converged lane only recomputes.
-// The network is non-decreasing in u, so each bisection finds its step; the
-// steps are then made non-decreasing (steps_monotone_kernel), so the table is a
-// non-decreasing step function even if a rounding were not monotone.
+// The FP32 network's segment of u, segment_of(route_coord(y(u), u)); every
+// lane of the wave must call it (the router works on 64 inputs at once).
+__device__ __forceinline__ int32_t net_segment(float u, const RouterRegs& R, int32_t nseg) {
+  return segment_of(route_coord(route_pair<false>(u, &R), u), nseg);
+}
+
+// Compiling the router, step 1: the network's segment at the 2^kp + 1 points
+// u_c = c 2^-kp, c = 0 .. 2^kp (exact floats), into probe[c].  With tot,
+// blockIdx.y is the model slot of the batched form.
+__global__ void __launch_bounds__(256) router_probe_kernel(const float* __restrict__ params, int32_t nseg,
+                                                           int32_t kp, int32_t* __restrict__ probe,
+                                                           const PlanTotals* __restrict__ tot) {
+  if (tot) {
+    if (int(blockIdx.y) >= tot->n_learned) return;
+    params += (int64_t)blockIdx.y * kParams;
+    probe += (int64_t)blockIdx.y * (nseg + 1);
+  }
+  RouterRegs R;
+  load_router(params, R);
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t np = (1 << kp) + 1;
+  const float u = std::ldexp(static_cast<float>(std::min(c, np - 1)), -kp);
+  const int32_t sg = net_segment(u, R, nseg);
+  if (c < np) probe[c] = sg;
+}
+
+// Step 2: lane t (1 <= t < nseg) finds the smallest f32 u in [0, 1] whose
+// segment is at least t (2.0f when no u reaches t; steps[0] = -inf).  The
+// probes bracket it: with c the first probe point whose segment is >= t, the
+// network is non-decreasing, so the answer lies in (u_(c-1), u_c], and a
+// bisection over the bit patterns of that interval (ordered like the values)
+// finds it -- the same value as a bisection over all of [0, 1], in 12 to 23
+// rounds instead of 31.  The wave evaluates the network while any of its lanes
+// is still bisecting.  The steps are then made non-decreasing
+// (router_table_kernel), so the table is a non-decreasing step function even
+// if some rounding were not monotone.
 __global__ void __launch_bounds__(256) router_steps_kernel(const float* __restrict__ params, int32_t nseg,
-                                                           float* __restrict__ steps) {
+                                                           int32_t kp, const int32_t* __restrict__ probe,
+                                                           float* __restrict__ steps,
+                                                           const PlanTotals* __restrict__ tot) {
+  if (tot) {
+    if (int(blockIdx.y) >= tot->n_learned) return;
+    params += (int64_t)blockIdx.y * kParams;
+    probe += (int64_t)blockIdx.y * (nseg + 1);
+    steps += (int64_t)blockIdx.y * nseg;
+  }
   RouterRegs R;
   load_router(params, R);
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t lo = 0, hi = 0x3f800001u;  // bit patterns of [0, 1], hi one past
-#pragma unroll 1
-  for (int it = 0; it < 31; ++it) {
+  const int32_t np = (1 << kp) + 1;
+  // c = #{probes < t}: the probe points are in order of u
+  int32_t c = 0, n = np;
+  while (n > 0) {
+    const int32_t half = n >> 1;
+    const bool below = probe[c + half] < t;
+    c = below ? c + half + 1 : c;
+    n = below ? n - half - 1 : half;
+  }
+  uint32_t lo = 1, hi = 0;  // an empty interval: nothing to bisect
+  float found = 2.0f;       // no u reaches t
+  if (c == 0) {
+    found = 0.0f;
+  } else if (c < np) {
+    lo = __float_as_uint(std::ldexp(static_cast<float>(c - 1), -kp)) + 1;
+    hi = __float_as_uint(std::ldexp(static_cast<float>(c), -kp));  // its segment is >= t
+  }
+  while (__ballot(lo < hi)) {
     const uint32_t mid = lo + ((hi - lo) >> 1);
-    const float u = __uint_as_float(mid);
-    const int32_t sg = segment_of(route_coord(route_pair<false>(u, &R), u), nseg);
+    const int32_t sg = net_segment(__uint_as_float(mid), R, nseg);
     if (lo < hi) {
       if (sg >= t) hi = mid;
       else lo = mid + 1;
     }
   }
+  if (c > 0 && c < np) found = __uint_as_float(lo);
   if (t == 0) steps[0] = -std::numeric_limits<float>::infinity();
-  else if (t < nseg) steps[t] = lo <= 0x3f800000u ? __uint_as_float(lo) : 2.0f;
+  else if (t < nseg) steps[t] = found;
 }
 
-__global__ void steps_monotone_kernel(float* __restrict__ steps, int32_t nseg) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    for (int32_t t = 1; t < nseg; ++t) steps[t] = std::fmax(steps[t], steps[t - 1]);
+// Step 3, one workgroup per model: the steps made non-decreasing (a prefix
+// maximum: each thread's run of steps, then a scan of the run maxima across the
+// workgroup), then the grid cells of grid_segment from them.
+constexpr int kTableBlock = 1024;
+
+__global__ void __launch_bounds__(kTableBlock) router_table_kernel(float* __restrict__ steps, int32_t nseg,
+                                                                   int32_t log2g, uint32_t* __restrict__ grid,
+                                                                   const PlanTotals* __restrict__ tot) {
+  if (tot) {
+    if (int(blockIdx.x) >= tot->n_learned) return;
+    steps += (int64_t)blockIdx.x * nseg;
+    grid += (int64_t)blockIdx.x << log2g;
+  }
+  __shared__ float st[kBatchMaxSegments];
+  __shared__ float wave_max[kTableBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int per = (nseg + kTableBlock - 1) / kTableBlock;
+  const int a = std::min(nseg, tid * per), b = std::min(nseg, a + per);
+  float run = -std::numeric_limits<float>::infinity();
+  for (int k = a; k < b; ++k) {
+    run = std::fmax(run, steps[k]);
+    st[k] = run;
+  }
+  // inclusive scan (max) of the run maxima over the wave, then over the waves
+  float x = run;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float y = __shfl_up(x, o, 64);
+    if (lane >= o) x = std::fmax(x, y);
+  }
+  if (lane == 63) wave_max[w] = x;
+  __syncthreads();
+  float before = -std::numeric_limits<float>::infinity();  // max of every earlier thread's run
+  for (int ww = 0; ww < w; ++ww) before = std::fmax(before, wave_max[ww]);
+  const float up = __shfl_up(x, 1, 64);
+  if (lane > 0) before = std::fmax(before, up);
+  for (int k = a; k < b; ++k) {
+    st[k] = std::fmax(st[k], before);
+    steps[k] = st[k];
+  }
+  __syncthreads();
+  const int32_t g = 1 << log2g;
+  const float scale = std::ldexp(1.0f, -log2g);
+  for (int32_t cc = tid; cc < g; cc += kTableBlock) {
+    const float u0 = static_cast<float>(cc) * scale;
+    const float u1 = (cc == g - 1) ? 1.0f : std::nextafter(static_cast<float>(cc + 1) * scale, 0.0f);
+    const int32_t s0 = table_segment(u0, st, nseg), s1 = table_segment(u1, st, nseg);
+    grid[cc] = static_cast<uint32_t>(s0) | (static_cast<uint32_t>(s1 - s0) << 16);
+  }
 }
 
 // segment of every key through the compiled router
@@ -762,8 +942,9 @@ __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, i
 // are loaded before the current group is routed.  Routing is the same code as
 // route_keys_kernel.  (Waves taking groups in lockstep, four at a time with
 // the predecessors passed through LDS, ran 1.1x slower than the two kernels.)
-template <bool F16>
-__global__ void __launch_bounds__(256, F16 ? 4 : 1) route_first_kernel(const float* __restrict__ params,
+template <bool IDENT>
+__global__ void __launch_bounds__(256) route_first_kernel(const float* __restrict__ steps_all,
+                                                          const uint32_t* __restrict__ grid_all, int32_t log2g,
                                                           const float* __restrict__ feat, int32_t nseg,
                                                           int32_t* __restrict__ first,
                                                           const LearnMeta* __restrict__ lm,
@@ -771,7 +952,8 @@ __global__ void __launch_bounds__(256, F16 ? 4 : 1) route_first_kernel(const flo
   const int slot = blockIdx.y;
   if (slot >= tot->n_learned) return;
   const LearnMeta L = lm[slot];
-  params += (int64_t)slot * kParams;
+  const float* steps = steps_all + (int64_t)slot * nseg;
+  const uint32_t* grid = grid_all + ((int64_t)slot << log2g);
   feat += L.x_off;
   first += (int64_t)slot * (nseg + 1);
   const int64_t n = int64_t(L.N) + 1;  // keys
@@ -781,13 +963,8 @@ __global__ void __launch_bounds__(256, F16 ? 4 : 1) route_first_kernel(const flo
   const int64_t g0 = (int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x / 64)) * per;
   const int64_t g1 = std::min(ngroups, g0 + per);
   if (g0 >= g1) return;  // uniform across the wave; no barrier below
-  typename std::conditional<F16, RouterRegs16, RouterRegs>::type R;
-  if constexpr (F16)
-    load_router16(params, R);
-  else
-    load_router(params, R);
   const int lane = threadIdx.x & 63;
-  auto segment = [&](float u) { return segment_of(route_coord(route_pair<F16>(u, &R), u), nseg); };
+  auto segment = [&](float u) { return IDENT ? segment_of(u, nseg) : grid_segment(u, steps, grid, log2g); };
   auto feature_at = [&](int64_t i) { return i < n ? feat[i] : 1.0f; };
   // the key before the range (group g0 - 1 is whole)
   int32_t carry = -1;
@@ -1058,19 +1235,25 @@ __device__ __forceinline__ int32_t quad_sum(int32_t v) {
 // instruction touches 16 blocks (a lane reading its own block makes four
 // loads that each touch 64).  The quad's counts are summed by DPP; lane
 // 4 k + r keeps round r's sum, and one shuffle hands each query its count.
-template <typename T>
-__device__ __forceinline__ int32_t coop_block_count(const T* __restrict__ X, uint32_t blk, T z) {
+// MASK: only the positions e_lo .. e_hi of the query's block count (the
+// block of a packed buffer holds values of neighbouring arrays).
+template <typename T, bool MASK = false>
+__device__ __forceinline__ int32_t coop_block_count(const T* __restrict__ X, uint64_t blk, T z, int32_t e_lo = 0,
+                                                    int32_t e_hi = 0) {
   constexpr int E = 64 / int(sizeof(T));
   constexpr int V = 16 / int(sizeof(T));
   const int lane = threadIdx.x & 63;
   const int sub = lane & 3;
+  const int32_t bounds = e_lo | (e_hi << 8);
   vec16b<T> x[4];
   T zz[4];
+  int32_t bd[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {  // every load is issued before any value is used
     const int src = 16 * r + (lane >> 2);
-    const uint32_t b = __shfl(blk, src, 64);
+    const uint64_t b = __shfl(blk, src, 64);
     zz[r] = __shfl(z, src, 64);
+    if constexpr (MASK) bd[r] = __shfl(bounds, src, 64);
     x[r] = *reinterpret_cast<const vec16b<T>*>(X + int64_t(b) * E + sub * V);
   }
   int32_t mine = 0;
@@ -1078,7 +1261,11 @@ __device__ __forceinline__ int32_t coop_block_count(const T* __restrict__ X, uin
   for (int r = 0; r < 4; ++r) {
     int32_t c = 0;
 #pragma unroll
-    for (int e = 0; e < V; ++e) c += (x[r][e] <= zz[r]) ? 1 : 0;
+    for (int e = 0; e < V; ++e) {
+      const int pos = sub * V + e;
+      const bool in = MASK ? (pos >= (bd[r] & 0xff) && pos <= (bd[r] >> 8)) : true;
+      c += (in && x[r][e] <= zz[r]) ? 1 : 0;
+    }
     c = quad_sum(c);
     mine = (sub == r) ? c : mine;
   }
@@ -1121,7 +1308,7 @@ __device__ __forceinline__ int32_t sample_search_coop(T z, int32_t L, int32_t U,
     }
   }
   const int32_t js = jL + c1;
-  const int32_t c2 = coop_block_count<T>(X, static_cast<uint32_t>(js), z);
+  const int32_t c2 = coop_block_count<T>(X, static_cast<uint64_t>(js), z);
   bool upper = c2 <= E - 1 || (jU > jL && js <= jU);
   if (c2 == E && jU == jL) upper = z < X[int64_t(js + 1) * E];
   *certified = c2 >= 1 && upper;
@@ -1143,9 +1330,11 @@ __global__ void samples_kernel(const T* __restrict__ X, int64_t nX, T* __restric
 // whose value belongs to the array are counted (blocks after the first one of
 // the array, up to the block holding X_N); the answer's block is scanned with
 // the values outside the array masked, read value by value where the buffer is
-// not 16-byte aligned or the block passes its end.  Certification as in
-// sample_search, over the array's own values.
-template <typename T>
+// not 16-byte aligned or the block passes its end (COOP: when no lane's
+// block passes the end of an aligned buffer, the wave reads the blocks
+// cooperatively, coop_block_count; every lane of the wave must then call it).
+// Certification as in sample_search, over the array's own values.
+template <typename T, bool COOP = false>
 __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t U, const T* __restrict__ Xp,
                                                         const T* __restrict__ S, int64_t x_off, int32_t N,
                                                         int64_t total_x, bool* certified) {
@@ -1183,7 +1372,10 @@ __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t 
   const int32_t e_lo = static_cast<int32_t>(std::max<int64_t>(0, x_off - k0));
   const int32_t e_hi = static_cast<int32_t>(std::min<int64_t>(E - 1, x_off + N - k0));
   int32_t c2 = 0;
-  if ((reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && k0 + E <= total_x) {
+  if (COOP && (reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && !__ballot(k0 + E > total_x)) {
+    // every lane's block lies inside the buffer: the wave reads them cooperatively
+    c2 = coop_block_count<T, true>(Xp, static_cast<uint64_t>(js), z, e_lo, e_hi);
+  } else if ((reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && k0 + E <= total_x) {
     const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(Xp + k0);
 #pragma unroll
     for (int v = 0; v < E / V; ++v) {
@@ -1308,12 +1500,19 @@ constexpr int32_t kMaxLog2Grid = 12;
 constexpr int32_t kMaxLearnSegments = 4096;
 constexpr int64_t kLearnLdsBudget = 160 * 1024;
 
+// probe points of the router compilation: 2^kp + 1 <= nseg + 1
+int32_t probe_log2(int32_t nseg) {
+  int32_t k = 0;
+  while ((2 << k) <= nseg) ++k;
+  return k;
+}
+
 // grid cells for nseg segments: as many cells as segments (rounded up to a
 // power of two), at most 4096, and fewer where the LDS budget requires
-int32_t grid_log2(int32_t nseg) {
+int32_t grid_log2(int32_t nseg, int64_t budget) {
   int32_t k = 0;
   while (k < kMaxLog2Grid && (1 << k) < nseg) ++k;
-  while (k > 0 && int64_t(nseg) * (int64_t(sizeof(SegFit)) + 4) + (int64_t(4) << k) > kLearnLdsBudget) --k;
+  while (k > 0 && int64_t(nseg) * (int64_t(sizeof(SegFit)) + 4) + (int64_t(4) << k) > budget) --k;
   return k;
 }
 
@@ -1434,10 +1633,8 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
     train_step_kernel<<<dim3(n_parts), dim3(kTrainBlock), 0, s>>>(L->params, L->feat, n, o->seed, st, batch, nullptr,
                                                                   nullptr, L->partial, L->loss_partial, nullptr,
                                                                   nullptr);
-    const float frac = static_cast<float>(st) / static_cast<float>(steps);
-    const float lr_t = lr * (0.05f + 0.95f * 0.5f * (1.0f + std::cos(3.14159265f * frac)));
-    adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(L->params, L->adam_m, L->adam_v, L->partial, n_parts, lr_t, 0.9f,
-                                               0.999f, 1e-8f, st + 1, nullptr, nullptr);
+    adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(L->params, L->adam_m, L->adam_v, L->partial, n_parts,
+                                               train_rate(lr, st, steps), st + 1, nullptr, nullptr);
   }
   DS_HIP_CHECK(hipGetLastError());
   if (steps > 0) {
@@ -1450,11 +1647,13 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   }
   // route the keys with the search-time router, then segments, fits and bounds
   if (L->router == kRouteTable && !L->identity) {
-    router_steps_kernel<<<dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s>>>(L->params, nseg, L->steps);
-    steps_monotone_kernel<<<1, 64, 0, s>>>(L->steps, nseg);
-    L->log2g = grid_log2(nseg);
-    router_grid_kernel<<<dim3((unsigned)(((1 << L->log2g) + 255) / 256)), dim3(256), 0, s>>>(L->steps, nseg, L->log2g,
-                                                                                          L->grid);
+    const int32_t kp = probe_log2(nseg);  // L->first (nseg + 1 entries) holds the probes until the fits
+    router_probe_kernel<<<dim3((unsigned)(((1 << kp) + 1 + 255) / 256)), dim3(256), 0, s>>>(L->params, nseg, kp,
+                                                                                         L->first, nullptr);
+    router_steps_kernel<<<dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s>>>(L->params, nseg, kp, L->first,
+                                                                                 L->steps, nullptr);
+    L->log2g = grid_log2(nseg, kLearnLdsBudget);
+    router_table_kernel<<<dim3(1), dim3(kTableBlock), 0, s>>>(L->steps, nseg, L->log2g, L->grid, nullptr);
     route_keys_table_kernel<<<dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s>>>(
         L->steps, L->feat, n, nseg, L->route);
   } else if (L->router == kRouteF16) {
@@ -1613,14 +1812,16 @@ __global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ par
   }
 }
 
-// threads per workgroup: with the FP16 router's shared values in LDS the search
-// state takes about 124 registers (four waves per SIMD); the FP32 router keeps
-// its weights in registers (about 167, three waves per SIMD)
-template <bool F16>
-constexpr int batch_learned_block() { return F16 ? 1024 : 768; }
+constexpr int kBatchLearnBlock = 1024;
 
-template <typename T, bool F16>
-__global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_search_kernel(BatchLearned b) {
+// LDS of the batched learned search: the current model's fits, router steps
+// and router grid
+int64_t batch_learned_lds(int32_t nseg, int32_t log2g) {
+  return int64_t(nseg) * (kSegFitBytes + 4) + (int64_t(4) << log2g);
+}
+
+template <typename T, bool IDENT>
+__global__ void __launch_bounds__(kBatchLearnBlock) batch_learned_search_kernel(BatchLearned b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // the current and the next tile (claimed by wave 0 while the others work),
   // with their 64-query group counters
@@ -1632,9 +1833,9 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
   const int64_t total = b.tot->total_tiles;
   if (b.tot->learned_tiles == 0) return;  // no learned array
   const int lane = threadIdx.x & 63;
-  __shared__ RouterShared16 S;  // FP16 router: half-wave-uniform values
-  half4 w2[4];
-  RouterRegs R;
+  const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
+  const float* steps = reinterpret_cast<const float*>(smem + int64_t(b.nseg) * kSegFitBytes);
+  const uint32_t* grid = reinterpret_cast<const uint32_t*>(smem + int64_t(b.nseg) * (kSegFitBytes + 4));
   auto claim_tile = [&](int slot) {  // by wave 0
     // Each queue (one per XCD) owns a contiguous eighth of the tile order,
     // so the workgroups of one XCD share the few arrays of their range in
@@ -1674,10 +1875,13 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
       // every wave is past the previous tile's end barrier
       stage_bytes(smem, static_cast<const unsigned char*>(b.segs) + (int64_t)slot * b.nseg * kSegFitBytes,
                   int64_t(b.nseg) * kSegFitBytes);
-      if constexpr (F16)
-        fill_router_shared16(b.params + (int64_t)slot * kParams, &S, w2);
-      else
-        load_router(b.params + (int64_t)slot * kParams, R);
+      if (!IDENT) {
+        stage_bytes(smem + int64_t(b.nseg) * kSegFitBytes,
+                    reinterpret_cast<const unsigned char*>(b.steps_tab + (int64_t)slot * b.nseg), int64_t(b.nseg) * 4);
+        stage_bytes(smem + int64_t(b.nseg) * (kSegFitBytes + 4),
+                    reinterpret_cast<const unsigned char*>(b.grid + ((int64_t)slot << b.log2g)),
+                    int64_t(4) << b.log2g);
+      }
       __syncthreads();
       cur = slot;
     }
@@ -1695,7 +1899,6 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
     a.XN = m.XN;
     a.N = m.N;
     a.nseg = b.nseg;
-    const SegFit* segs = reinterpret_cast<const SegFit*>(smem);
     const int64_t q0 = m.q_off + (g - m.t_off) * b.tile;
     const int64_t q1 = std::min(m.q_end, q0 + b.tile);
     const int32_t ngrp = static_cast<int32_t>((q1 - q0 + 63) >> 6);
@@ -1708,28 +1911,24 @@ __global__ void __launch_bounds__(batch_learned_block<F16>()) batch_learned_sear
       if (lane == 0) c = atomicAdd(&s_grp[bf], 1);
       return __shfl(c, 0, 64);
     };
+    // the query loads are unconditional (index clamped to the tile's last query,
+    // q1 > q0), so the next group's load stays in flight while this one is worked on
+    auto load_q = [&](int32_t grp) {
+      return __builtin_nontemporal_load(z + std::min(q0 + int64_t(grp) * 64 + lane, q1 - 1));
+    };
     int32_t gi = claim();
-    T zq = (gi < ngrp && q0 + int64_t(gi) * 64 + lane < q1) ? __builtin_nontemporal_load(z + q0 + int64_t(gi) * 64 + lane)
-                                                           : a.X0;
+    T zq = load_q(gi);
     while (gi < ngrp) {
       const int64_t q = q0 + int64_t(gi) * 64 + lane;
       const int32_t gn = claim();
-      const int64_t qn = q0 + int64_t(gn) * 64 + lane;
-      const T z_next = (gn < ngrp && qn < q1) ? __builtin_nontemporal_load(z + qn) : a.X0;
+      const T z_next = load_q(gn);
       const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
-      float y_net;
-      if constexpr (F16) {
-        asm volatile("" ::: "memory");  // keeps the LDS reads of the router inside the loop
-        y_net = route_pair_shared16(u, w2, &S);
-      } else {
-        y_net = route_pair<false>(u, &R);
-      }
-      const float y = route_coord(y_net, u);
+      const int32_t seg = IDENT ? segment_of(u, b.nseg) : grid_segment(u, steps, grid, b.log2g);
       int32_t L, U;
-      query_window<T>(zq, segment_of(y, b.nseg), segs, &L, &U);
+      query_window<T>(zq, seg, segs, &L, &U);
       bool certified;
-      int32_t i = sample_search_packed<T>(zq, L, U, static_cast<const T*>(b.X), static_cast<const T*>(b.samples),
-                                          m.x_off, a.N, b.total_x, &certified);
+      int32_t i = sample_search_packed<T, true>(zq, L, U, static_cast<const T*>(b.X),
+                                                static_cast<const T*>(b.samples), m.x_off, a.N, b.total_x, &certified);
       if ((zq >= a.X0) && (zq < a.XN) && !certified) i = full_search_counted<T>(zq, a.X, a.N, a.fallbacks);
       i = (zq >= a.XN) ? a.N : i;
       i = (zq >= a.X0) ? i : -1;
@@ -1751,24 +1950,30 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
     batch_samples_kernel<T><<<dim3(1024), dim3(256), 0, s>>>(static_cast<const T*>(b.X), b.total_x,
                                                              static_cast<T*>(b.samples), nS);
   }
-  init_params_kernel<<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, b.tot, b.seed);
+  if (!b.identity) init_params_kernel<<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, b.tot, b.seed);
   feature_kernel<T><<<dim3(64, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, 0, 0, 0, 0, b.feat, b.lmeta,
                                                        b.tot);
   DS_HIP_CHECK(hipGetLastError());
-  const float lr = 2e-3f;
-  for (int st = 0; st < b.steps; ++st) {
-    train_step_kernel<<<dim3(kBatchLearnParts, K), dim3(kTrainBlock), 0, s>>>(
-        b.params, b.feat, 0, b.seed, st, kBatchLearnSamples, nullptr, nullptr, b.partial, b.loss, b.lmeta, b.tot);
-    const float frac = static_cast<float>(st) / static_cast<float>(b.steps);
-    const float lr_t = lr * (0.05f + 0.95f * 0.5f * (1.0f + std::cos(3.14159265f * frac)));
-    adam_kernel<<<dim3(K), dim3(1024), 0, s>>>(b.params, b.adam_m, b.adam_v, b.partial, kBatchLearnParts, lr_t, 0.9f,
-                                               0.999f, 1e-8f, st + 1, nullptr, b.tot);
-  }
+  // every step of every model's training in one launch (one workgroup per model)
+  if (b.steps > 0)
+    batched_train_kernel<<<dim3(K), dim3(kBatchTrainBlock), 0, s>>>(b.params, b.adam_m, b.adam_v, b.feat, b.lmeta,
+                                                                    b.tot, b.seed, b.steps, 2e-3f);
   DS_HIP_CHECK(hipGetLastError());
-  if (b.fp32_router)
-    route_first_kernel<false><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, b.nseg, b.first, b.lmeta, b.tot);
-  else
-    route_first_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.params, b.feat, b.nseg, b.first, b.lmeta, b.tot);
+  if (b.identity) {
+    route_first_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.steps_tab, b.grid, b.log2g, b.feat, b.nseg, b.first,
+                                                               b.lmeta, b.tot);
+  } else {
+    // each trained network compiled to its step table and grid, then the keys routed through them
+    // (each model's entries of `first` hold its probes until the keys are routed)
+    const int32_t kp = probe_log2(b.nseg);
+    router_probe_kernel<<<dim3((unsigned)(((1 << kp) + 1 + 255) / 256), K), dim3(256), 0, s>>>(b.params, b.nseg, kp,
+                                                                                            b.first, b.tot);
+    router_steps_kernel<<<dim3((unsigned)((b.nseg + 255) / 256), K), dim3(256), 0, s>>>(b.params, b.nseg, kp, b.first,
+                                                                                      b.steps_tab, b.tot);
+    router_table_kernel<<<dim3(K), dim3(kTableBlock), 0, s>>>(b.steps_tab, b.nseg, b.log2g, b.grid, b.tot);
+    route_first_kernel<false><<<dim3(64, K), dim3(256), 0, s>>>(b.steps_tab, b.grid, b.log2g, b.feat, b.nseg, b.first,
+                                                                b.lmeta, b.tot);
+  }
   seg_fit_kernel<T><<<dim3(b.nseg, K), dim3(kFitLanes), 0, s>>>(
       static_cast<const T*>(b.X), 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot);
   DS_HIP_CHECK(hipGetLastError());
@@ -1777,13 +1982,13 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
 
 template <typename T>
 ds_status batched_learned_search_typed(const BatchLearned& b, hipStream_t s) {
-  auto kern = b.fp32_router ? batch_learned_search_kernel<T, false> : batch_learned_search_kernel<T, true>;
-  const int lds = b.nseg * kSegFitBytes;
+  auto kern = b.identity ? batch_learned_search_kernel<T, true> : batch_learned_search_kernel<T, false>;
+  const int lds = static_cast<int>(batch_learned_lds(b.nseg, b.log2g));
   if (lds > 64 * 1024)
     DS_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      lds));
   int per_cu = 0;
-  const int block = b.fp32_router ? batch_learned_block<false>() : batch_learned_block<true>();
+  const int block = kBatchLearnBlock;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1)
     per_cu = 1;
   int grid = per_cu * num_cus();
@@ -1795,8 +2000,12 @@ ds_status batched_learned_search_typed(const BatchLearned& b, hipStream_t s) {
 
 }  // namespace
 
+// the batched search kernel's own LDS (tile claims) is kept out of the budget
+int32_t batch_grid_log2(int32_t nseg) { return grid_log2(nseg, kLearnLdsBudget - 1024); }
+
 ds_status batched_learned_build(const BatchLearned& b, int dtype, hipStream_t s) {
-  if (b.nseg < 1 || b.nseg * kSegFitBytes > kLdsBytesPerCU) return DS_ERR_ARG;
+  if (b.nseg < 1 || b.nseg > kBatchMaxSegments || batch_learned_lds(b.nseg, b.log2g) > kLearnLdsBudget - 1024)
+    return DS_ERR_ARG;
   return dtype == DS_F32 ? batched_learned_build_typed<float>(b, s) : batched_learned_build_typed<double>(b, s);
 }
 
@@ -1839,8 +2048,8 @@ ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const flo
   }
   ds::train_step_kernel<<<dim3(n_parts), dim3(ds::kTrainBlock), 0, s>>>(params_dev, nullptr, 1, 0, 0, batch, u_dev,
                                                                         t_dev, partial, lp, nullptr, nullptr);
-  ds::adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(nullptr, nullptr, nullptr, partial, n_parts, 0, 0, 0, 0, 1,
-                                                 grad_dev, nullptr);
+  ds::adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(nullptr, nullptr, nullptr, partial, n_parts, 0, 1, grad_dev,
+                                                 nullptr);
   if (loss_dev) ds::sum_kernel<<<1, 64, 0, s>>>(lp, n_parts, loss_dev);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);

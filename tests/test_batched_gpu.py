@@ -421,6 +421,19 @@ def _mixture_batch(ns, m_each, seed):
     return W.Batch(np.dtype(np.float64), x_off, X, q_off, z)
 
 
+def test_batched_learned_no_network_exact(ds):
+    """The ablation of the batched router (learn_steps = -1: segments split the feature evenly,
+    no training) keeps the results of the trained models, exactly."""
+    b = _mixture_batch((500, 3000, 20000, 7), 30_000, 24)
+    ref = _oracle_batch(b.x_off, b.X, b.q_off, b.z)
+    for steps in (-1, 3):
+        bt, out = _run(ds, b, learn_segments=1024, learn_steps=steps, direct_cap_bytes=64)
+        meth, _ = bt.report()
+        assert np.all(meth[np.diff(b.x_off) > 1] == ds.METHOD_LEARNED)
+        _assert_same(out, ref)
+        assert bt.fallbacks() == 0
+
+
 def test_batched_learned_mixture_exact(ds):
     b = _mixture_batch((300, 2000, 9000, 40000, 70000, 5), 60_000, 21)
     bt, out = _run(ds, b, learn_segments=1024, learn_steps=60)
