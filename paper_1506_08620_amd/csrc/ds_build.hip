@@ -154,6 +154,156 @@ __global__ void __launch_bounds__(kFillBlock) fill_kernel(const T* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The whole Direct build of a small array in one workgroup and one launch, so
+// that ds_build makes one allocation and reads one result record: the copy of
+// X, validation and the smallest rounded gap (as mingap_kernel), ComputeHR
+// (Sec. 4.4.3) as compute_hr does it -- the start value, then passes that
+// find the first pair from i on whose cells coincide, grow H at that pair by
+// P (doubled after each step, never reset) and go on after it, until a pass
+// grows nothing -- then R, jmin and, when it fits kcap cells, the table K
+// (eq. (indexdef): i is written into the cells (f(X_{i-1}), f(X_i)]).  The
+// same floating-point operations in the same order as the multi-launch build,
+// so H, W, R, jmin and K are identical.
+constexpr int kSmallBlock = 1024;
+constexpr int64_t kSmallBuildMax = 65537;  // values (N + 1) of the one-workgroup build
+
+template <typename T>
+struct SmallResult {
+  T H, W, X0, XN;
+  int64_t R, jmin, n_updates;
+  int32_t status;   // ds_status
+  int32_t filled;   // K was written (R - jmin + 1 <= kcap)
+};
+
+template <typename T, int FORM>
+__global__ void __launch_bounds__(kSmallBlock) small_build_kernel(const T* __restrict__ Xin, int64_t N, int32_t hstart,
+                                                                  T* __restrict__ X, SmallResult<T>* __restrict__ res,
+                                                                  int32_t* __restrict__ K, int64_t kcap) {
+  const int tid = threadIdx.x;
+  __shared__ T s_min[kSmallBlock / 64];
+  __shared__ uint32_t s_fl[kSmallBlock / 64];
+  __shared__ unsigned long long s_first;
+  __shared__ T s_H, s_W;
+  __shared__ int32_t s_status;
+  for (int64_t i = tid; i <= N; i += kSmallBlock) X[i] = Xin[i];
+  __syncthreads();
+  const T X0 = X[0], XN = X[N];
+  // validation flags and the smallest rounded gap m(D_{i+1} - D_i)
+  T gmin = std::numeric_limits<T>::infinity();
+  uint32_t fl = 0;
+  for (int64_t i = tid; i < N; i += kSmallBlock) {
+    const T a = X[i], b = X[i + 1];
+    if (!std::isfinite(a) || !std::isfinite(b)) fl |= kFlagNonFinite;
+    if (!(a < b)) fl |= kFlagNotSorted;
+    const T da = a - X0, db = b - X0;
+    if (!(da < db)) fl |= kFlagOffsetsNotIncreasing;
+    gmin = std::fmin(gmin, db - da);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    gmin = std::fmin(gmin, __shfl_xor(gmin, o, 64));
+    fl |= __shfl_xor(fl, o, 64);
+  }
+  if ((tid & 63) == 0) {
+    s_min[tid >> 6] = gmin;
+    s_fl[tid >> 6] = fl;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    T g = std::numeric_limits<T>::infinity();
+    uint32_t f = 0;
+    for (int w = 0; w < kSmallBlock / 64; ++w) {
+      g = std::fmin(g, s_min[w]);
+      f |= s_fl[w];
+    }
+    int32_t st = DS_OK;
+    if (f & kFlagNonFinite) st = DS_ERR_NONFINITE;
+    else if (f & kFlagNotSorted) st = DS_ERR_NOT_SORTED;
+    else if (f & kFlagOffsetsNotIncreasing) st = DS_ERR_INFEASIBLE;
+    T H = 0, W = 0;
+    if (st == DS_OK) {
+      const T Hbar = T(1) / g;  // eq. (minhnumeric), correctly rounded
+      if (std::isinf(Hbar)) st = DS_ERR_INFEASIBLE;
+      H = (hstart == DS_HSTART_HBAR) ? Hbar : std::nextafter(Hbar, std::numeric_limits<T>::infinity());
+      W = (FORM == DS_FORM_FMA) ? T(H * X0) : T(0);
+      if (st == DS_OK && grid_floor<T, FORM>(XN, H, W, X0) >= T(kTwoPowQ)) st = DS_ERR_INFEASIBLE;
+    }
+    s_H = H;
+    s_W = W;
+    s_status = st;
+  }
+  __syncthreads();
+  T P = std::nextafter(s_H, std::numeric_limits<T>::infinity()) - s_H;  // used by thread 0 only
+  int64_t n_updates = 0;
+  for (;;) {  // passes until none grows H (the same for every thread: shared values)
+    if (s_status != DS_OK) break;
+    bool changed = false;
+    int64_t i_start = 1;
+    while (i_start <= N) {
+      if (tid == 0) s_first = ~0ull;
+      __syncthreads();
+      const T H = s_H, W = s_W;
+      for (int64_t i = i_start + tid; i <= N; i += kSmallBlock) {
+        if (grid_floor<T, FORM>(X[i - 1], H, W, X0) == grid_floor<T, FORM>(X[i], H, W, X0)) {
+          atomicMin(&s_first, static_cast<unsigned long long>(i));
+          break;  // later i of this thread are larger
+        }
+      }
+      __syncthreads();
+      const unsigned long long f = s_first;
+      if (f == ~0ull) break;
+      const int64_t i = static_cast<int64_t>(f);
+      if (tid == 0) {
+        T Hc = H, Wc = W;
+        const T a = X[i - 1], b = X[i];
+        while (grid_floor<T, FORM>(a, Hc, Wc, X0) == grid_floor<T, FORM>(b, Hc, Wc, X0)) {
+          Hc = Hc + P;
+          if (FORM == DS_FORM_FMA) Wc = Hc * X0;
+          if (grid_floor<T, FORM>(XN, Hc, Wc, X0) >= T(kTwoPowQ)) {  // eq. (overflowexact)
+            s_status = DS_ERR_INFEASIBLE;
+            break;
+          }
+          P = P + P;
+          ++n_updates;
+        }
+        s_H = Hc;
+        s_W = Wc;
+      }
+      changed = true;
+      __syncthreads();
+      if (s_status != DS_OK) break;
+      i_start = i + 1;
+    }
+    if (!changed) break;
+  }
+  __syncthreads();
+  const T H = s_H, W = s_W;
+  const int32_t st = s_status;
+  const int64_t R = st == DS_OK ? static_cast<int64_t>(grid_floor<T, FORM>(XN, H, W, X0)) : 0;
+  const int64_t jmin = st == DS_OK ? static_cast<int64_t>(grid_floor<T, FORM>(X0, H, W, X0)) : 0;
+  const bool fill = st == DS_OK && R - jmin + 1 <= kcap;
+  if (fill) {
+    for (int64_t i = tid; i <= N; i += kSmallBlock) {
+      const int64_t hi = static_cast<int64_t>(grid_floor<T, FORM>(X[i], H, W, X0));
+      const int64_t lo = (i == 0) ? jmin : static_cast<int64_t>(grid_floor<T, FORM>(X[i - 1], H, W, X0)) + 1;
+      for (int64_t j = lo; j <= hi; ++j) K[j - jmin] = static_cast<int32_t>(i);
+    }
+  }
+  if (tid == 0) {
+    SmallResult<T> r{};
+    r.H = H;
+    r.W = W;
+    r.X0 = X0;
+    r.XN = XN;
+    r.R = R;
+    r.jmin = jmin;
+    r.n_updates = n_updates;
+    r.status = st;
+    r.filled = fill ? 1 : 0;
+    *res = r;
+  }
+}
+
 // K_j = max{ i : f(X_i) <= j } for j in [jmin, R] (eq. (kgeneral), Sec. 4.7);
 // K[e] holds K_{jmin+e}.  The workgroup of X_{i0..i0+255} owns the cells from
 // f(X_{i0}) up to the one before f(X_{i0+256}) (up to R for the last
@@ -549,6 +699,59 @@ ds_status build_direct(ds_index* h, const ds_build_opts& o, hipStream_t s) {
   return DS_OK;
 }
 
+// Direct build of an array of at most kSmallBuildMax values: one allocation
+// holds the copy of X, the result record and room for a table of
+// max(4 (N + 1), 16384) cells; small_build_kernel does the rest, and the host
+// reads the record once.  A table larger than the room gets its own
+// allocation and the usual fill.
+template <typename T>
+ds_status build_direct_small(ds_index* h, const ds_build_opts& o, const void* X_dev, hipStream_t s) {
+  const int64_t N = h->N;
+  const int64_t cap = o.table_cap_bytes > 0 ? o.table_cap_bytes : kDefaultTableCap;
+  const int64_t kcap = std::min<int64_t>(std::max<int64_t>(4 * (N + 1), 16384), cap / int64_t(sizeof(int32_t)));
+  const size_t x_bytes = (size_t(N + 1) * sizeof(T) + 255) / 256 * 256;
+  const size_t r_bytes = (sizeof(SmallResult<T>) + 255) / 256 * 256;
+  unsigned char* arena = nullptr;
+  if (hipMalloc(&arena, x_bytes + r_bytes + size_t(kcap) * sizeof(int32_t)) != hipSuccess) return DS_ERR_OOM;
+  h->X = arena;
+  h->nX = N + 1;
+  auto* res = reinterpret_cast<SmallResult<T>*>(arena + x_bytes);
+  int32_t* Kin = reinterpret_cast<int32_t*>(arena + x_bytes + r_bytes);
+  if (h->form == DS_FORM_FMA)
+    small_build_kernel<T, DS_FORM_FMA><<<dim3(1), dim3(kSmallBlock), 0, s>>>(
+        static_cast<const T*>(X_dev), N, h->hstart, static_cast<T*>(h->X), res, Kin, kcap);
+  else
+    small_build_kernel<T, DS_FORM_SUB><<<dim3(1), dim3(kSmallBlock), 0, s>>>(
+        static_cast<const T*>(X_dev), N, h->hstart, static_cast<T*>(h->X), res, Kin, kcap);
+  DS_HIP_CHECK(hipGetLastError());
+  SmallResult<T> r{};
+  DS_HIP_CHECK(hipMemcpyAsync(&r, res, sizeof(r), hipMemcpyDeviceToHost, s));
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  if (r.status != DS_OK) return static_cast<ds_status>(r.status);
+  h->H = r.H;
+  h->W = r.W;
+  h->X0 = r.X0;
+  h->XN = r.XN;
+  h->R = r.R;
+  h->jmin = r.jmin;
+  h->n_updates = r.n_updates;
+  h->nK = h->R - h->jmin + 1;
+  if (h->nK * int64_t(sizeof(int32_t)) > cap) return DS_ERR_TABLE_CAP;
+  ds_status st = DS_OK;
+  if (r.filled) {
+    h->K = Kin;
+    h->k_in_x = true;  // freed with X
+  } else {
+    if (hipMalloc(&h->K, size_t(h->nK) * sizeof(int32_t)) != hipSuccess) {
+      h->K = nullptr;
+      return DS_ERR_OOM;
+    }
+    st = (h->form == DS_FORM_FMA) ? fill_table<T, DS_FORM_FMA>(h, s) : fill_table<T, DS_FORM_SUB>(h, s);
+    if (st != DS_OK) return st;
+  }
+  return build_layouts<T>(h, o, s);
+}
+
 // The gap-q variant (Sec. 4.7): the grid only has to satisfy
 // f(X_{i+q}) > f(X_i), K_j = max{i : f(X_i) <= j}, and the search makes q
 // compares.  X is stored after kMaxGapQ - 1 copies of X_0 (the left padding
@@ -750,9 +953,10 @@ void free_layouts(ds_index* h) {
 
 void free_device(ds_index* h) {
   if (h->X) (void)hipFree(h->X);
-  if (h->K) (void)hipFree(h->K);
+  if (h->K && !h->k_in_x) (void)hipFree(h->K);
   h->X = nullptr;
   h->K = nullptr;
+  h->k_in_x = false;
   free_layouts(h);
   learned_free(h);
 }
@@ -789,10 +993,14 @@ ds_status build_typed(ds_index* h, const void* X_dev, const ds_build_opts& o, hi
   } else {
     // Direct (or AUTO: Direct first)
     h->method = DS_METHOD_DIRECT;
-    if (hipMalloc(&h->X, size_t(N + 1) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
-    h->nX = N + 1;
-    DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
-    st = build_direct<T>(h, o, s);
+    if (N + 1 <= kSmallBuildMax && !o.refine_h) {
+      st = build_direct_small<T>(h, o, X_dev, s);
+    } else {
+      if (hipMalloc(&h->X, size_t(N + 1) * sizeof(T)) != hipSuccess) return DS_ERR_OOM;
+      h->nX = N + 1;
+      DS_HIP_CHECK(hipMemcpyAsync(h->X, X_dev, size_t(N + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
+      st = build_direct<T>(h, o, s);
+    }
   }
   if (st == DS_OK) return DS_OK;
   const bool can_fall = (st == DS_ERR_INFEASIBLE || st == DS_ERR_TABLE_CAP);
@@ -801,8 +1009,9 @@ ds_status build_typed(ds_index* h, const void* X_dev, const ds_build_opts& o, hi
   if (!can_fall || fb == DS_FALLBACK_NONE) return st;
   // fall back: drop the partial Direct state and build the replacement
   free_layouts(h);
-  if (h->K) (void)hipFree(h->K);
+  if (h->K && !h->k_in_x) (void)hipFree(h->K);
   h->K = nullptr;
+  h->k_in_x = false;
   h->nK = 0;
   h->H = h->W = 0;
   h->R = h->jmin = 0;

@@ -221,6 +221,7 @@ struct ds_index {
   int32_t gap_q = 0;            // gap-q variant: number of compares
   int32_t eyt_L = 0;            // Eytzinger layout: levels (X holds 2^L values, X[0] unused)
   int32_t* K = nullptr;         // Direct table
+  bool k_in_x = false;          // K lies inside the allocation of X (small builds)
   int64_t nK = 0;
   // RANKCODE layout (see ds.h)
   uint64_t* rc_bits = nullptr;

@@ -43,6 +43,15 @@ def _check_tables(idx, X, form, hstart=oracle.HSTART_PHI):
     return t
 
 
+def _queries(X, rng, m):
+    """Uniform queries over [X_0, X_N), every key, the float below every key, and a few
+    out-of-domain values."""
+    dt = X.dtype
+    zu = W.uniform_queries(X[0], X[-1], m, dt, rng)
+    extra = np.array([np.nan, -np.inf, np.inf, X[-1], W.prev_float(X[:1], dt)[0]], dt)
+    return np.concatenate([zu, X, W.prev_float(X, dt), extra]).astype(dt)
+
+
 def _assert_same(got, ref, z=None):
     if not np.array_equal(got, ref):
         bad = np.flatnonzero(got != ref)
@@ -302,6 +311,43 @@ def test_h_growth_matches_oracle(ds):
             idx = ds.build(_dev(X), form=form, hstart="hbar")
             _check_tables(idx, X, form, oracle.HSTART_HBAR)
     assert grown > 0
+
+
+@pytest.mark.parametrize("form", ["sub", "fma"])
+def test_small_build_growth_and_large_tables(ds, form):
+    """The one-launch build of arrays up to 65537 values: near-limit arrays where ComputeHR
+    grows H 16 to 23 times, offset or not, and arrays whose table exceeds the room kept
+    beside X (max(4 (N + 1), 16384) cells) and gets its own allocation: H, W, R, jmin, the
+    update count and K equal the oracle's, and so does every search."""
+    rng = np.random.default_rng(91)
+    grown = 0
+    for a in range(60):
+        X = W.near_limit_array(np.float32, rng, q=int(rng.integers(1, 4)), n_fill=int(rng.integers(0, 3000)),
+                               offset=bool(a % 2))
+        t = oracle.build_direct(X, FORMS[form])
+        if t.status != oracle.OK:
+            with pytest.raises(ds.DsError) as e:
+                ds.build(_dev(X), form=form)
+            assert e.value.status == t.status
+            continue
+        grown += t.n_updates > 0
+        idx = ds.build(_dev(X), form=form)
+        _check_tables(idx, X, form)
+        z = _queries(X, rng, 20_000)
+        _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), oracle.search(X, z), z)
+        idx.destroy()
+    assert grown >= 10
+    for n, spread in ((100, 1e-3), (3000, 1e-4), (65536, 1e-2)):
+        # one tiny gap among unit gaps: R is about N / spread, far beyond 4 (N + 1) cells
+        X = np.arange(n + 1, dtype=np.float64)
+        X[1] = spread
+        t = oracle.build_direct(X, FORMS[form])
+        assert t.status == oracle.OK and t.R - t.jmin + 1 > max(4 * (n + 1), 16384)
+        idx = ds.build(_dev(X), form=form)
+        _check_tables(idx, X, form)
+        z = _queries(X, rng, 20_000)
+        _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), oracle.search(X, z), z)
+        idx.destroy()
 
 
 def test_errors_and_fallback(ds):
