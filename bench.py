@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2", 5: "RANKCODE-L2",
-               6: "NIBBLE-L2", 7: "NIBBLE-LDS"}
+               6: "NIBBLE-L2", 7: "NIBBLE-LDS", 8: "GAPCODE-LDS"}
 
 
 # the files the sweep's kernels and their tables are built from: the counter summary

@@ -160,6 +160,14 @@ typedef struct ds_build_opts {
  *             LDS (stage 7) while its chunks fit, for N up to about 120,000
  *             above RANKCODE's limit; beyond, read through L2 with its first
  *             156 KiB of chunks in each workgroup's LDS (stage 6). */
+/*   GAPCODE   (gap-q variant, q <= 3) the grid holds at most q keys per cell:
+ *             per 32 cells a 64-bit word of 2-bit key counts and the count of
+ *             the keys in earlier cells, and the RANKCODE 16-bit code per key.
+ *             The first key of z's cell is the word's count plus its counts
+ *             below the cell; the cell's (at most 3) keys are compared with z
+ *             through their codes, reading X only on a tie.  About 2.4 bytes
+ *             per key, so gap-2 at N = 65536 fits one workgroup's LDS (stage 8);
+ *             built for every gap-q handle with q <= 3. */
 #define DS_LAYOUT_RANKCODE 1
 #define DS_LAYOUT_PAIRS 2
 #define DS_LAYOUT_NIBBLE 4
@@ -188,6 +196,7 @@ typedef struct ds_info_t {
   int64_t nibble_bytes;     /* bytes of the NIBBLE layout (0 if not built) */
   int32_t gap_q;            /* DS_METHOD_DIRECT_GAP: the q in use; 0 otherwise */
   int32_t n_h_refine;       /* midpoints tested by the refinement of H (refine_h) */
+  int64_t gapcode_bytes;    /* bytes of the GAPCODE layout of the gap-q variant (0 if not built) */
   uint64_t fallback_count;  /* learned: queries so far that fell outside their recorded
                                window and took the full binary search (expected 0); 0 for
                                other methods.  ds_info reads it from the device with a
@@ -206,7 +215,8 @@ typedef struct ds_tune {
   int32_t stage;            /* 0 = auto; Direct: 1 = PLAIN in LDS, 2 = PLAIN through L2,
                                3 = RANKCODE in LDS, 4 = PAIRS through L2,
                                5 = RANKCODE through L2, 6 = NIBBLE through L2,
-                               7 = NIBBLE in LDS; binary
+                               7 = NIBBLE in LDS; gap-q: 1 = PLAIN in LDS, 2 = PLAIN
+                               through L2, 8 = GAPCODE in LDS (q <= 3); binary
                                search: 1 = X in LDS, 2 = X through L2; Eytzinger: 1 = top
                                levels in LDS, 2 = every level through L2; learned: 1 = each
                                lane reads its own lines of the sample array and of X, 2 =

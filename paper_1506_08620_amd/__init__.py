@@ -38,6 +38,7 @@ LAYOUT_RANKCODE, LAYOUT_PAIRS, LAYOUT_NIBBLE = 1, 2, 4
 # ds_tune.stage values of the Direct method
 STAGE_PLAIN_LDS, STAGE_PLAIN_L2, STAGE_RANKCODE_LDS, STAGE_PAIRS_L2, STAGE_RANKCODE_L2, STAGE_NIBBLE_L2 = 1, 2, 3, 4, 5, 6
 STAGE_NIBBLE_LDS = 7
+STAGE_GAPCODE_LDS = 8
 _LAYOUTS = {"rankcode": LAYOUT_RANKCODE, "pairs": LAYOUT_PAIRS, "nibble": LAYOUT_NIBBLE}
 
 _METHODS = {"direct": METHOD_DIRECT, "leadbit": METHOD_BSEARCH_LEADBIT, "offset": METHOD_BSEARCH_OFFSET,
@@ -78,7 +79,7 @@ class Info(ctypes.Structure):
                 ("mean_log2_window", ctypes.c_double), ("x_bytes", ctypes.c_int64),
                 ("rankcode_bytes", ctypes.c_int64), ("pairs_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
                 ("nibble_bytes", ctypes.c_int64), ("gap_q", ctypes.c_int32), ("n_h_refine", ctypes.c_int32),
-                ("fallback_count", ctypes.c_uint64)]
+                ("gapcode_bytes", ctypes.c_int64), ("fallback_count", ctypes.c_uint64)]
 
 
 class View(ctypes.Structure):

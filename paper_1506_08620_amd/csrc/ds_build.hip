@@ -369,6 +369,25 @@ __global__ void __launch_bounds__(256) rank_bits_kernel(const int32_t* __restric
   }
 }
 
+// GAPCODE words (gap-q grid, q <= 3): 2-bit key counts of cells jmin + 32 w ..
+// jmin + 32 w + 31 (the count of cell e is K_e - K_(e-1), K_(jmin-1) = -1 with
+// K_j = max{i : f(X_i) <= j}) and the number of keys in earlier cells,
+// K_(jmin + 32 w - 1) + 1.
+__global__ void __launch_bounds__(256) gap_words_kernel(const int32_t* __restrict__ K, int64_t nK, int64_t nW,
+                                                        uint64_t* __restrict__ counts, uint32_t* __restrict__ base) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nW) return;
+  uint64_t m = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int64_t e = w * 32 + b;
+    if (e >= nK) break;
+    const int32_t c = K[e] - (e > 0 ? K[e - 1] : -1);
+    m |= static_cast<uint64_t>(c & 3) << (2 * b);
+  }
+  counts[w] = m;
+  base[w] = (w == 0) ? 0u : static_cast<uint32_t>(K[w * 32 - 1] + 1);
+}
+
 // RANKCODE codes: 15-bit position of X_i in its cell, and a flag set when no
 // smaller float shares the cell and the position code of X_i.
 template <typename T, int FORM>
@@ -832,8 +851,27 @@ ds_status build_direct_gap(ds_index* h, const ds_build_opts& o, const void* X_de
     fill_max_kernel<T, DS_FORM_SUB><<<dim3((unsigned)blocks), dim3(kFillBlock), 0, s>>>(
         X, N, T(h->H), T(h->W), T(h->X0), static_cast<int32_t>(h->jmin), h->R, h->nK, h->K);
   DS_HIP_CHECK(hipGetLastError());
+  if (q <= 3) {
+    // GAPCODE: count words and the keys' position codes (codes of the unpadded X)
+    const int64_t nW = (h->nK + 31) / 32;
+    const int64_t n_codes = ((N + 1) + 7) / 8 * 8;
+    if (hipMalloc(&h->gc_counts, size_t(nW) * 8) != hipSuccess || hipMalloc(&h->gc_base, size_t(nW) * 4) != hipSuccess ||
+        hipMalloc(&h->rc_code, size_t(n_codes) * 2) != hipSuccess)
+      return DS_ERR_OOM;
+    h->gc_words = nW;
+    gap_words_kernel<<<dim3((unsigned)((nW + 255) / 256)), dim3(256), 0, s>>>(h->K, h->nK, nW, h->gc_counts,
+                                                                               h->gc_base);
+    if (h->form == DS_FORM_FMA)
+      rank_code_kernel<T, DS_FORM_FMA><<<dim3((unsigned)((n_codes + 255) / 256)), dim3(256), 0, s>>>(
+          X, N, n_codes, T(h->H), T(h->W), T(h->X0), h->rc_code);
+    else
+      rank_code_kernel<T, DS_FORM_SUB><<<dim3((unsigned)((n_codes + 255) / 256)), dim3(256), 0, s>>>(
+          X, N, n_codes, T(h->H), T(h->W), T(h->X0), h->rc_code);
+    DS_HIP_CHECK(hipGetLastError());
+  }
   h->staged = tables_fit_lds(h) ? 1 : 0;
-  h->auto_stage = h->staged ? 1 : 2;
+  // PLAIN in LDS when it fits, else GAPCODE in LDS when it fits, else PLAIN through L2
+  h->auto_stage = h->staged ? 1 : ((h->gc_counts && direct_lds_bytes(h, 8) <= kLdsBytesPerCU) ? 8 : 2);
   DS_HIP_CHECK(hipStreamSynchronize(s));
   return DS_OK;
 }
@@ -943,6 +981,11 @@ void free_layouts(ds_index* h) {
   h->rc_code8 = nullptr;
   if (h->pairs) (void)hipFree(h->pairs);
   if (h->nib) (void)hipFree(h->nib);
+  if (h->gc_counts) (void)hipFree(h->gc_counts);
+  if (h->gc_base) (void)hipFree(h->gc_base);
+  h->gc_counts = nullptr;
+  h->gc_base = nullptr;
+  h->gc_words = 0;
   h->rc_bits = nullptr;
   h->rc_base = nullptr;
   h->rc_code = nullptr;
@@ -1107,7 +1150,8 @@ ds_status ds_build(const void* X_dev, int64_t N, ds_dtype dt, const ds_build_opt
   in.n_h_refine = h->n_refine;
   in.table_bytes = h->nK * int64_t(sizeof(int32_t));
   in.x_bytes = h->nX * int64_t(dt == DS_F32 ? 4 : 8);
-  in.rankcode_bytes = h->rc_code ? (h->rc_words * 12 + (h->N + 1) * 2) : 0;
+  in.rankcode_bytes = h->rc_bits ? (h->rc_words * 12 + (h->N + 1) * 2) : 0;
+  in.gapcode_bytes = h->gc_counts ? (h->gc_words * 12 + (h->N + 1) * 2) : 0;
   in.pairs_bytes = h->pairs ? h->nK * int64_t(dt == DS_F32 ? 8 : 16) : 0;
   in.nibble_bytes = h->nib ? h->nib_chunks * int64_t(sizeof(ds::NibChunk)) : 0;
   in.build_ms = ms;

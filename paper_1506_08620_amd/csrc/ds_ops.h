@@ -189,6 +189,50 @@ struct GapOp {
   }
 };
 
+// GAPCODE layout of the gap-q variant (Sec. 4.7) for q <= 3: the grid keeps
+// at most q keys per cell, so a cell is described by its key count (2 bits,
+// 32 cells per 64-bit word, with the count of the keys in earlier cells per
+// word) and each key by the RANKCODE position code.  With e = f(z) - jmin and
+// A the first key of cell e (the word's count plus its counts below e), keys
+// before A lie in earlier cells, so below z, and keys after the cell lie above
+// it: the result is A - 1 plus the number of the cell's keys at or below z,
+// each decided from the codes as in RankCodeOp (X read on an undecided tie).
+template <typename T, int FORM>
+struct GapCodeOp {
+  const uint64_t* counts;
+  const uint32_t* base;
+  const uint16_t* code;
+  const T* Xg;  // X_0 .. X_N in global memory
+  T H, W, X0, vlo, vhi, XN;
+  int32_t jmin, N;
+  __device__ __forceinline__ int32_t operator()(T z) const {
+    const T v = grid_value<T, FORM>(z, H, W, X0);
+    const T jf = std::floor(std::fmin(std::fmax(v, vlo), vhi));
+    const int32_t e = static_cast<int32_t>(jf) - jmin;
+    const uint64_t word = counts[e >> 5];
+    const uint32_t sh = (static_cast<uint32_t>(e) & 31u) << 1;
+    const uint64_t low = word & ((uint64_t(1) << sh) - 1);
+    const int32_t A = static_cast<int32_t>(base[e >> 5]) + __popcll(low & 0x5555555555555555ull) +
+                      2 * __popcll(low & 0xAAAAAAAAAAAAAAAAull);
+    const int32_t c = static_cast<int32_t>((word >> sh) & 3u);
+    const T cz = cell_code<T>(v, jf);
+    int32_t i = A - 1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k < c) {
+        const int32_t cx = code[A + k];
+        const T cxp = static_cast<T>(cx >> 1);
+        const bool first = cx & 1;
+        const bool up = cz > cxp || (cz == cxp && first);
+        const bool tie = cz == cxp && !first;
+        i += (up || (tie && z >= Xg[A + k])) ? 1 : 0;
+      }
+    }
+    i = (z >= XN) ? N : i;
+    return (z >= X0) ? i : -1;
+  }
+};
+
 // RANKCODE layout (see ds.h).  With e = f(z) - jmin, K_j is the running count
 // of the 64-cell word plus the popcount of the word's lower bits.  A cell
 // without an X_i gives i = K_j - 1 directly (every X_i before it is below z

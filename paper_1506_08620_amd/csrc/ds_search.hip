@@ -91,8 +91,23 @@ __global__ void __launch_bounds__(1024) gap_search_kernel(DirectArgs<T> a) {
     X = reinterpret_cast<const T*>(smem);
     K = reinterpret_cast<const int32_t*>(smem + xb);
   }
-  GapOp<T, FORM, Q> op{X + a.x_off, K - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi, a.gap_q};
-  stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+  if constexpr (STAGE == 8) {
+    // GAPCODE in LDS: the count words, their running counts and the key codes
+    int64_t base_off = 0, code_off = 0;
+    const int64_t code_bytes = round16(int64_t(a.N + 1) * 2);
+    rankcode_offsets(a.nW, code_bytes, &base_off, &code_off);
+    stage_bytes(smem, reinterpret_cast<const unsigned char*>(a.rc_bits), int64_t(a.nW) * 8);
+    stage_bytes(smem + base_off, reinterpret_cast<const unsigned char*>(a.rc_base), int64_t(a.nW) * 4);
+    stage_bytes(smem + code_off, reinterpret_cast<const unsigned char*>(a.rc_code), code_bytes);
+    __syncthreads();
+    GapCodeOp<T, FORM> op{reinterpret_cast<const uint64_t*>(smem), reinterpret_cast<const uint32_t*>(smem + base_off),
+                          reinterpret_cast<const uint16_t*>(smem + code_off), a.X + a.x_off, a.H, a.W, a.X0, a.vlo,
+                          a.vhi, a.XN, a.jmin, a.N};
+    stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+  } else {
+    GapOp<T, FORM, Q> op{X + a.x_off, K - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi, a.gap_q};
+    stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
+  }
 }
 
 template <typename T, int KIND, int STAGE, int U, bool VEC>
@@ -220,6 +235,10 @@ int64_t lds_bytes_needed(const ds_index* h, int stage) {
     return rankcode_offsets(h->rc_words, round16((h->N + 1) * 2), &b, &c);
   }
   if (h->method == DS_METHOD_DIRECT && stage == 7) return nibble_chunks(h->nK) * int64_t(sizeof(NibChunk));
+  if (h->method == DS_METHOD_DIRECT_GAP && stage == 8) {
+    int64_t b = 0, c = 0;
+    return rankcode_offsets(h->gc_words, round16((h->N + 1) * 2), &b, &c);
+  }
   if (h->method == DS_METHOD_DIRECT && stage == 6)
     return std::min<int64_t>(nibble_chunks(h->nK), kNibPrefixChunks) * int64_t(sizeof(NibChunk));
   if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) return round16(h->nX * s) + h->nK * 4;
@@ -252,6 +271,12 @@ void default_shape(const ds_index* h, int stage, int* block, int* unroll) {
     case 1: *block = 256; *unroll = f32 ? 4 : 2; return;
     case 3: {
       const bool one_wg_per_cu = lds_bytes_needed(h, 3) > kLdsBytesPerCU / 2;
+      *block = 1024;
+      *unroll = (one_wg_per_cu && f32) ? 4 : 1;
+      return;
+    }
+    case 8: {  // GAPCODE in LDS, as RANKCODE
+      const bool one_wg_per_cu = lds_bytes_needed(h, 8) > kLdsBytesPerCU / 2;
       *block = 1024;
       *unroll = (one_wg_per_cu && f32) ? 4 : 1;
       return;
@@ -354,6 +379,10 @@ ds_status dispatch_gap_u(const DirectArgs<T>& a, const Shape& sh, int lds, int64
 template <typename T, int FORM, int Q>
 ds_status dispatch_gap_q(const DirectArgs<T>& a, const Shape& sh, bool vec, int lds, hipStream_t s) {
   const int64_t items = vec ? ((a.M >> 2) + sh.unroll - 1) / sh.unroll : a.M;
+  if (sh.stage == 8) {  // GAPCODE (q <= 3): one instantiation serves every q
+    return vec ? dispatch_gap_u<T, FORM, 8, true, 2>(a, sh, lds, items, s)
+               : dispatch_gap_u<T, FORM, 8, false, 2>(a, sh, lds, items, s);
+  }
   if (sh.stage == 1) {
     return vec ? dispatch_gap_u<T, FORM, 1, true, Q>(a, sh, lds, items, s)
                : dispatch_gap_u<T, FORM, 1, false, Q>(a, sh, lds, items, s);
@@ -418,7 +447,7 @@ ds_status search_typed(const ds_index* h, const void* z, int64_t M, int32_t* out
   const Shape sh = pick_shape(h, M, cand);
   const bool vec = ((reinterpret_cast<uintptr_t>(z) % (4 * sizeof(T))) == 0) &&
                    ((reinterpret_cast<uintptr_t>(out) % 16) == 0);
-  const int lds = (sh.stage == 1 || sh.stage == 3 || sh.stage == 6 || sh.stage == 7)
+  const int lds = (sh.stage == 1 || sh.stage == 3 || sh.stage == 6 || sh.stage == 7 || sh.stage == 8)
                       ? static_cast<int>(lds_bytes_needed(h, sh.stage))
                       : 0;
   if (h->method == DS_METHOD_DIRECT || h->method == DS_METHOD_DIRECT_GAP) {
@@ -441,6 +470,11 @@ ds_status search_typed(const ds_index* h, const void* z, int64_t M, int32_t* out
     a.rc_w16 = h->rc_w16;
     a.rc_code8 = h->rc_code8;
     a.nW = static_cast<int32_t>(h->rc_words);
+    if (h->method == DS_METHOD_DIRECT_GAP) {  // the GAPCODE words take the RANKCODE fields
+      a.rc_bits = h->gc_counts;
+      a.rc_base = h->gc_base;
+      a.nW = static_cast<int32_t>(h->gc_words);
+    }
     a.pairs = static_cast<const CachePair<T>*>(h->pairs);
     a.nib = h->nib;
     a.nib_chunks = h->nib_chunks;
@@ -511,7 +545,7 @@ ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_de
   if (!h || !z_dev || !out_dev || M <= 0) return DS_ERR_ARG;
   if (h->method == DS_METHOD_LEARNED) return DS_ERR_UNSUPPORTED;
   const int64_t m = std::min<int64_t>(M, int64_t(1) << 24);
-  int stages[7];
+  int stages[8];
   int n_stages = 0;
   if (h->method == DS_METHOD_DIRECT) {
     if (h->staged) stages[n_stages++] = 1;
@@ -523,6 +557,7 @@ ds_status ds_autotune(ds_handle h, const void* z_dev, int64_t M, int32_t* out_de
     stages[n_stages++] = 2;
   } else {
     if (h->staged) stages[n_stages++] = 1;
+    if (h->gc_counts && ds::direct_lds_bytes(h, 8) <= ds::kLdsBytesPerCU) stages[n_stages++] = 8;
     stages[n_stages++] = 2;
   }
   hipEvent_t e0, e1;
@@ -570,7 +605,7 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   }
   if (t->block != 0 && (t->block < 64 || t->block > 1024 || (t->block % 64) != 0)) return DS_ERR_ARG;
   if (t->unroll != 0 && t->unroll != 1 && t->unroll != 2 && t->unroll != 4) return DS_ERR_ARG;
-  if (t->stage < 0 || t->stage > 7) return DS_ERR_ARG;
+  if (t->stage < 0 || t->stage > 8) return DS_ERR_ARG;
   if (h->method == DS_METHOD_LEARNED) {
     // learned: stage 1 = each lane reads its own lines, 2 = the wave reads them cooperatively
     if (t->stage > 2 || t->unroll != 0 || t->grid < 0) return DS_ERR_ARG;
@@ -582,7 +617,12 @@ ds_status ds_set_tune(ds_handle h, const ds_tune* t) {
   if (t->stage == 7 && ds::direct_lds_bytes(h, 7) > ds::kLdsBytesPerCU) return DS_ERR_ARG;
   if (t->stage == 5 && (!h->rc_w16 || !h->rc_code8)) return DS_ERR_ARG;
   if (t->stage == 1 && !h->staged) return DS_ERR_ARG;
-  if (t->stage >= 3 && h->method != DS_METHOD_DIRECT) return DS_ERR_ARG;
+  if (t->stage == 8) {  // GAPCODE: the gap-q variant with q <= 3
+    if (h->method != DS_METHOD_DIRECT_GAP || !h->gc_counts || ds::direct_lds_bytes(h, 8) > ds::kLdsBytesPerCU)
+      return DS_ERR_ARG;
+  } else if (t->stage >= 3 && h->method != DS_METHOD_DIRECT) {
+    return DS_ERR_ARG;
+  }
   if (t->stage == 3 && (!h->rc_code || ds::rankcode_lds_bytes(h) > ds::kLdsBytesPerCU)) return DS_ERR_ARG;
   if (t->stage == 4 && !h->pairs) return DS_ERR_ARG;
   if (t->grid < 0) return DS_ERR_ARG;

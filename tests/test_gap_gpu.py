@@ -58,7 +58,12 @@ def _check_tables(idx, X, q, form):
 
 
 def _stages(inf):
-    return (1, 2) if inf["staged"] == 1 else (2,)
+    """The layouts a handle can be searched through: PLAIN in LDS (when it fits) and through
+    L2, and GAPCODE in LDS (q <= 3, when it fits)."""
+    st = [1, 2] if inf["staged"] == 1 else [2]
+    if inf["gapcode_bytes"] and inf["gapcode_bytes"] <= 160 * 1024 - 64:
+        st.append(8)
+    return tuple(st)
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
@@ -78,6 +83,42 @@ def test_gap_tables_and_indices(ds, dtype, n):
                 idx.set_tune(stage=stage)
                 _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
             idx.destroy()
+
+
+@pytest.mark.parametrize("form", ["sub", "fma"])
+def test_gapcode_ties_on_twin_keys(ds, form):
+    """GAPCODE (stage 8) where the codes tie: "twin" arrays, pairs of consecutive floats about
+    one unit apart, which a q = 2 grid puts in one cell each (so the pair's position codes are
+    equal or adjacent and X decides); q = 3 too.  Every key, the floats next to every key and
+    out-of-domain values, against the oracle."""
+    rng = np.random.default_rng(44)
+    for a in range(12):
+        dt = np.dtype(np.float32 if a % 2 else np.float64)
+        n_pairs = int(rng.integers(3, 20_000))
+        base = (np.cumsum(rng.uniform(0.8, 1.2, n_pairs)) + rng.uniform(-500, 500)).astype(dt)
+        X = np.unique(np.concatenate([base, np.nextafter(base, dt.type(np.inf))]))
+        for q in (2, 3):
+            if oracle.build_direct_gap(X, q, FORMS[form]).status != oracle.OK:
+                continue
+            z = _queries(X, rng, m=20_000)
+            ref = oracle.search(X, z)
+            idx = ds.build(_dev(X), method="direct_gap", gap_q=q, form=form)
+            _check_tables(idx, X, q, form)
+            idx.set_tune(stage=8)
+            _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
+            idx.destroy()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_gapcode_keeps_gap2_on_chip_at_65536(ds, dtype):
+    """N = 65536, q = 2: the PLAIN table and X do not fit LDS but GAPCODE does, and the automatic
+    launch uses it; 2^22 sweep queries equal the oracle."""
+    X = W.sweep_array(65536, dtype)
+    idx = ds.build(_dev(X), method="direct_gap", gap_q=2)
+    inf = idx.info()
+    assert inf["staged"] == 8 and 0 < inf["gapcode_bytes"] <= 160 * 1024
+    z = W.sweep_queries(1 << 22, dtype)
+    _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), oracle.search(X, z), z)
 
 
 def test_gap_tiny_arrays_and_unaligned(ds):
@@ -103,7 +144,7 @@ def test_gap_launch_shapes(ds):
     z = _queries(X, np.random.default_rng(1), m=300_001)
     ref = oracle.search(X, z)
     idx = ds.build(_dev(X), method="direct_gap", gap_q=3)
-    for stage in (1, 2):
+    for stage in (1, 2, 8):
         for block in (64, 256, 1024):
             for unroll in (1, 2, 4):
                 idx.set_tune(block=block, unroll=unroll, stage=stage, grid=0 if block != 64 else 7)
