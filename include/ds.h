@@ -160,14 +160,15 @@ typedef struct ds_build_opts {
  *             LDS (stage 7) while its chunks fit, for N up to about 120,000
  *             above RANKCODE's limit; beyond, read through L2 with its first
  *             156 KiB of chunks in each workgroup's LDS (stage 6). */
-/*   GAPCODE   (gap-q variant, q <= 3) the grid holds at most q keys per cell:
- *             per 32 cells a 64-bit word of 2-bit key counts and the count of
- *             the keys in earlier cells, and the RANKCODE 16-bit code per key.
+/*   GAPCODE   (gap-q variant, q <= 15) the grid holds at most q keys per
+ *             cell: per 32 cells (q <= 3: 2-bit counts) or 16 cells (q <= 15:
+ *             4-bit counts) a 64-bit word of key counts and the count of the
+ *             keys in earlier cells, and the RANKCODE 16-bit code per key.
  *             The first key of z's cell is the word's count plus its counts
- *             below the cell; the cell's (at most 3) keys are compared with z
- *             through their codes, reading X only on a tie.  About 2.4 bytes
- *             per key, so gap-2 at N = 65536 fits one workgroup's LDS (stage 8);
- *             built for every gap-q handle with q <= 3. */
+ *             below the cell; the cell's (at most q) keys are compared with z
+ *             through their codes, reading X only on a tie.  About 2.2 to 2.4
+ *             bytes per key, so gap-q at N = 65536 fits one workgroup's LDS
+ *             (stage 8); built for every gap-q handle with q <= 15. */
 #define DS_LAYOUT_RANKCODE 1
 #define DS_LAYOUT_PAIRS 2
 #define DS_LAYOUT_NIBBLE 4
@@ -216,7 +217,7 @@ typedef struct ds_tune {
                                3 = RANKCODE in LDS, 4 = PAIRS through L2,
                                5 = RANKCODE through L2, 6 = NIBBLE through L2,
                                7 = NIBBLE in LDS; gap-q: 1 = PLAIN in LDS, 2 = PLAIN
-                               through L2, 8 = GAPCODE in LDS (q <= 3); binary
+                               through L2, 8 = GAPCODE in LDS (q <= 15); binary
                                search: 1 = X in LDS, 2 = X through L2; Eytzinger: 1 = top
                                levels in LDS, 2 = every level through L2; learned: 1 = each
                                lane reads its own lines of the sample array and of X, 2 =

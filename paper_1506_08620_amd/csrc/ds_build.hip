@@ -369,23 +369,25 @@ __global__ void __launch_bounds__(256) rank_bits_kernel(const int32_t* __restric
   }
 }
 
-// GAPCODE words (gap-q grid, q <= 3): 2-bit key counts of cells jmin + 32 w ..
-// jmin + 32 w + 31 (the count of cell e is K_e - K_(e-1), K_(jmin-1) = -1 with
-// K_j = max{i : f(X_i) <= j}) and the number of keys in earlier cells,
-// K_(jmin + 32 w - 1) + 1.
+// GAPCODE words (gap-q grid, q <= 15): CB-bit key counts of the L = 64 / CB
+// cells jmin + L w .. jmin + L w + L - 1 (the count of cell e is K_e - K_(e-1),
+// K_(jmin-1) = -1 with K_j = max{i : f(X_i) <= j}) and the number of keys in
+// earlier cells, K_(jmin + L w - 1) + 1.
 __global__ void __launch_bounds__(256) gap_words_kernel(const int32_t* __restrict__ K, int64_t nK, int64_t nW,
-                                                        uint64_t* __restrict__ counts, uint32_t* __restrict__ base) {
+                                                        int32_t cb, uint64_t* __restrict__ counts,
+                                                        uint32_t* __restrict__ base) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nW) return;
+  const int L = 64 / cb;
   uint64_t m = 0;
-  for (int b = 0; b < 32; ++b) {
-    const int64_t e = w * 32 + b;
+  for (int b = 0; b < L; ++b) {
+    const int64_t e = w * L + b;
     if (e >= nK) break;
     const int32_t c = K[e] - (e > 0 ? K[e - 1] : -1);
-    m |= static_cast<uint64_t>(c & 3) << (2 * b);
+    m |= static_cast<uint64_t>(c) << (cb * b);
   }
   counts[w] = m;
-  base[w] = (w == 0) ? 0u : static_cast<uint32_t>(K[w * 32 - 1] + 1);
+  base[w] = (w == 0) ? 0u : static_cast<uint32_t>(K[w * L - 1] + 1);
 }
 
 // RANKCODE codes: 15-bit position of X_i in its cell, and a flag set when no
@@ -851,16 +853,18 @@ ds_status build_direct_gap(ds_index* h, const ds_build_opts& o, const void* X_de
     fill_max_kernel<T, DS_FORM_SUB><<<dim3((unsigned)blocks), dim3(kFillBlock), 0, s>>>(
         X, N, T(h->H), T(h->W), T(h->X0), static_cast<int32_t>(h->jmin), h->R, h->nK, h->K);
   DS_HIP_CHECK(hipGetLastError());
-  if (q <= 3) {
+  if (q <= 15) {
     // GAPCODE: count words and the keys' position codes (codes of the unpadded X)
-    const int64_t nW = (h->nK + 31) / 32;
+    h->gc_bits = q <= 3 ? 2 : 4;
+    const int64_t cells = 64 / h->gc_bits;
+    const int64_t nW = (h->nK + cells - 1) / cells;
     const int64_t n_codes = ((N + 1) + 7) / 8 * 8;
     if (hipMalloc(&h->gc_counts, size_t(nW) * 8) != hipSuccess || hipMalloc(&h->gc_base, size_t(nW) * 4) != hipSuccess ||
         hipMalloc(&h->rc_code, size_t(n_codes) * 2) != hipSuccess)
       return DS_ERR_OOM;
     h->gc_words = nW;
-    gap_words_kernel<<<dim3((unsigned)((nW + 255) / 256)), dim3(256), 0, s>>>(h->K, h->nK, nW, h->gc_counts,
-                                                                               h->gc_base);
+    gap_words_kernel<<<dim3((unsigned)((nW + 255) / 256)), dim3(256), 0, s>>>(h->K, h->nK, nW, h->gc_bits,
+                                                                               h->gc_counts, h->gc_base);
     if (h->form == DS_FORM_FMA)
       rank_code_kernel<T, DS_FORM_FMA><<<dim3((unsigned)((n_codes + 255) / 256)), dim3(256), 0, s>>>(
           X, N, n_codes, T(h->H), T(h->W), T(h->X0), h->rc_code);
@@ -986,6 +990,7 @@ void free_layouts(ds_index* h) {
   h->gc_counts = nullptr;
   h->gc_base = nullptr;
   h->gc_words = 0;
+  h->gc_bits = 0;
   h->rc_bits = nullptr;
   h->rc_base = nullptr;
   h->rc_code = nullptr;

@@ -235,11 +235,13 @@ struct ds_index {
   // NIBBLE layout
   ds::NibChunk* nib = nullptr;
   int64_t nib_chunks = 0;
-  // GAPCODE layout of the gap-q variant (q <= 3): per 32 cells the 2-bit key
-  // counts and the count of keys in earlier cells; the codes are rc_code's
+  // GAPCODE layout of the gap-q variant (q <= 15): per 64 / gc_bits cells the
+  // key counts (gc_bits = 2 for q <= 3, else 4 bits each) and the count of
+  // keys in earlier cells; the codes are rc_code's
   uint64_t* gc_counts = nullptr;
   uint32_t* gc_base = nullptr;
   int64_t gc_words = 0;
+  int32_t gc_bits = 0;
   int32_t auto_stage = 2;       // layout the automatic launch uses
   // binary search constants
   int32_t P = 0, F = 0, S = 0, J = 0;

@@ -189,16 +189,30 @@ struct GapOp {
   }
 };
 
-// GAPCODE layout of the gap-q variant (Sec. 4.7) for q <= 3: the grid keeps
-// at most q keys per cell, so a cell is described by its key count (2 bits,
-// 32 cells per 64-bit word, with the count of the keys in earlier cells per
-// word) and each key by the RANKCODE position code.  With e = f(z) - jmin and
-// A the first key of cell e (the word's count plus its counts below e), keys
-// before A lie in earlier cells, so below z, and keys after the cell lie above
-// it: the result is A - 1 plus the number of the cell's keys at or below z,
-// each decided from the codes as in RankCodeOp (X read on an undecided tie).
-template <typename T, int FORM>
+// GAPCODE layout of the gap-q variant (Sec. 4.7) for q <= 15: the grid keeps
+// at most q keys per cell, so a cell is described by its key count (CB = 2
+// bits for q <= 3, 4 bits for q <= 15; 64 / CB cells per 64-bit word, with
+// the count of the keys in earlier cells per word) and each key by the
+// RANKCODE position code.  With e = f(z) - jmin and A the first key of cell e
+// (the word's count plus its counts below e), keys before A lie in earlier
+// cells, so below z, and keys after the cell lie above it: the result is
+// A - 1 plus the number of the cell's keys at or below z (at most QMAX), each
+// decided from the codes as in RankCodeOp (X read on an undecided tie).
+template <int CB>
+__device__ __forceinline__ int32_t sum_counts(uint64_t m) {
+  if constexpr (CB == 2) {
+    return __popcll(m & 0x5555555555555555ull) + 2 * __popcll(m & 0xAAAAAAAAAAAAAAAAull);
+  } else {
+    return __popcll(m & 0x1111111111111111ull) + 2 * __popcll(m & 0x2222222222222222ull) +
+           4 * __popcll(m & 0x4444444444444444ull) + 8 * __popcll(m & 0x8888888888888888ull);
+  }
+}
+
+template <typename T, int FORM, int CB, int QMAX>
 struct GapCodeOp {
+  static constexpr int kCells = 64 / CB;            // cells per word
+  static constexpr int kLog2Cells = CB == 2 ? 5 : 4;
+  static constexpr int kMask = (1 << CB) - 1;
   const uint64_t* counts;
   const uint32_t* base;
   const uint16_t* code;
@@ -209,16 +223,15 @@ struct GapCodeOp {
     const T v = grid_value<T, FORM>(z, H, W, X0);
     const T jf = std::floor(std::fmin(std::fmax(v, vlo), vhi));
     const int32_t e = static_cast<int32_t>(jf) - jmin;
-    const uint64_t word = counts[e >> 5];
-    const uint32_t sh = (static_cast<uint32_t>(e) & 31u) << 1;
+    const uint64_t word = counts[e >> kLog2Cells];
+    const uint32_t sh = (static_cast<uint32_t>(e) & (kCells - 1)) * CB;
     const uint64_t low = word & ((uint64_t(1) << sh) - 1);
-    const int32_t A = static_cast<int32_t>(base[e >> 5]) + __popcll(low & 0x5555555555555555ull) +
-                      2 * __popcll(low & 0xAAAAAAAAAAAAAAAAull);
-    const int32_t c = static_cast<int32_t>((word >> sh) & 3u);
+    const int32_t A = static_cast<int32_t>(base[e >> kLog2Cells]) + sum_counts<CB>(low);
+    const int32_t c = static_cast<int32_t>((word >> sh) & kMask);  // at most q <= QMAX
     const T cz = cell_code<T>(v, jf);
     int32_t i = A - 1;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < QMAX; ++k) {
       if (k < c) {
         const int32_t cx = code[A + k];
         const T cxp = static_cast<T>(cx >> 1);

@@ -100,9 +100,10 @@ __global__ void __launch_bounds__(1024) gap_search_kernel(DirectArgs<T> a) {
     stage_bytes(smem + base_off, reinterpret_cast<const unsigned char*>(a.rc_base), int64_t(a.nW) * 4);
     stage_bytes(smem + code_off, reinterpret_cast<const unsigned char*>(a.rc_code), code_bytes);
     __syncthreads();
-    GapCodeOp<T, FORM> op{reinterpret_cast<const uint64_t*>(smem), reinterpret_cast<const uint32_t*>(smem + base_off),
-                          reinterpret_cast<const uint16_t*>(smem + code_off), a.X + a.x_off, a.H, a.W, a.X0, a.vlo,
-                          a.vhi, a.XN, a.jmin, a.N};
+    GapCodeOp<T, FORM, (Q <= 3 ? 2 : 4), Q> op{reinterpret_cast<const uint64_t*>(smem),
+                                           reinterpret_cast<const uint32_t*>(smem + base_off),
+                                           reinterpret_cast<const uint16_t*>(smem + code_off), a.X + a.x_off, a.H,
+                                           a.W, a.X0, a.vlo, a.vhi, a.XN, a.jmin, a.N};
     stream_queries<T, U, VEC>(a.z, a.out, a.M, op);
   } else {
     GapOp<T, FORM, Q> op{X + a.x_off, K - a.jmin, a.H, a.W, a.X0, a.vlo, a.vhi, a.gap_q};
@@ -379,9 +380,19 @@ ds_status dispatch_gap_u(const DirectArgs<T>& a, const Shape& sh, int lds, int64
 template <typename T, int FORM, int Q>
 ds_status dispatch_gap_q(const DirectArgs<T>& a, const Shape& sh, bool vec, int lds, hipStream_t s) {
   const int64_t items = vec ? ((a.M >> 2) + sh.unroll - 1) / sh.unroll : a.M;
-  if (sh.stage == 8) {  // GAPCODE (q <= 3): one instantiation serves every q
-    return vec ? dispatch_gap_u<T, FORM, 8, true, 2>(a, sh, lds, items, s)
-               : dispatch_gap_u<T, FORM, 8, false, 2>(a, sh, lds, items, s);
+  if (sh.stage == 8) {  // GAPCODE: 2-bit counts for q <= 3, 4-bit counts for q <= 15
+    // the bound on the keys per cell: 3, 4, 8 or 15
+    if (a.gap_q <= 3)
+      return vec ? dispatch_gap_u<T, FORM, 8, true, 3>(a, sh, lds, items, s)
+                 : dispatch_gap_u<T, FORM, 8, false, 3>(a, sh, lds, items, s);
+    if (a.gap_q <= 4)
+      return vec ? dispatch_gap_u<T, FORM, 8, true, 4>(a, sh, lds, items, s)
+                 : dispatch_gap_u<T, FORM, 8, false, 4>(a, sh, lds, items, s);
+    if (a.gap_q <= 8)
+      return vec ? dispatch_gap_u<T, FORM, 8, true, 8>(a, sh, lds, items, s)
+                 : dispatch_gap_u<T, FORM, 8, false, 8>(a, sh, lds, items, s);
+    return vec ? dispatch_gap_u<T, FORM, 8, true, 15>(a, sh, lds, items, s)
+               : dispatch_gap_u<T, FORM, 8, false, 15>(a, sh, lds, items, s);
   }
   if (sh.stage == 1) {
     return vec ? dispatch_gap_u<T, FORM, 1, true, Q>(a, sh, lds, items, s)

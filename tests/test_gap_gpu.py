@@ -89,7 +89,7 @@ def test_gap_tables_and_indices(ds, dtype, n):
 def test_gapcode_ties_on_twin_keys(ds, form):
     """GAPCODE (stage 8) where the codes tie: "twin" arrays, pairs of consecutive floats about
     one unit apart, which a q = 2 grid puts in one cell each (so the pair's position codes are
-    equal or adjacent and X decides); q = 3 too.  Every key, the floats next to every key and
+    equal or adjacent and X decides); q = 3 (2-bit counts) and q = 4, 9 (4-bit counts) too.  Every key, the floats next to every key and
     out-of-domain values, against the oracle."""
     rng = np.random.default_rng(44)
     for a in range(12):
@@ -97,7 +97,7 @@ def test_gapcode_ties_on_twin_keys(ds, form):
         n_pairs = int(rng.integers(3, 20_000))
         base = (np.cumsum(rng.uniform(0.8, 1.2, n_pairs)) + rng.uniform(-500, 500)).astype(dt)
         X = np.unique(np.concatenate([base, np.nextafter(base, dt.type(np.inf))]))
-        for q in (2, 3):
+        for q in (2, 3, 4, 9):  # 2-bit and 4-bit cell counts
             if oracle.build_direct_gap(X, q, FORMS[form]).status != oracle.OK:
                 continue
             z = _queries(X, rng, m=20_000)
@@ -110,11 +110,12 @@ def test_gapcode_ties_on_twin_keys(ds, form):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_gapcode_keeps_gap2_on_chip_at_65536(ds, dtype):
-    """N = 65536, q = 2: the PLAIN table and X do not fit LDS but GAPCODE does, and the automatic
+@pytest.mark.parametrize("q", [2, 4, 15])
+def test_gapcode_keeps_gap_q_on_chip_at_65536(ds, dtype, q):
+    """N = 65536: the PLAIN table and X do not fit LDS but GAPCODE does, and the automatic
     launch uses it; 2^22 sweep queries equal the oracle."""
     X = W.sweep_array(65536, dtype)
-    idx = ds.build(_dev(X), method="direct_gap", gap_q=2)
+    idx = ds.build(_dev(X), method="direct_gap", gap_q=q)
     inf = idx.info()
     assert inf["staged"] == 8 and 0 < inf["gapcode_bytes"] <= 160 * 1024
     z = W.sweep_queries(1 << 22, dtype)
