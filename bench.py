@@ -29,15 +29,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+# L2 request ceiling: 8 XCDs x 16 L2 channels, each serving one (up to 128-byte) request per
+# clock, at 2.4 GHz (39.3 TB/s in 128-byte lines)
+L2_PEAK_GREQ_S = 8 * 16 * 2.4
 STAGE_NAMES = {1: "PLAIN-LDS", 2: "PLAIN-L2", 3: "RANKCODE-LDS", 4: "PAIRS-L2", 5: "RANKCODE-L2",
                6: "NIBBLE-L2", 7: "NIBBLE-LDS", 8: "GAPCODE-LDS"}
 
 
-# the files the sweep's kernels and their tables are built from: the counter summary
-# stays valid exactly while these are unchanged
+# the sources of the sweep's search kernels and of the tables they read: the counter
+# summaries stay valid exactly while these are unchanged
 TRAFFIC_SOURCES = ("paper_1506_08620_amd/csrc/ds_search.hip", "paper_1506_08620_amd/csrc/ds_build.hip",
-                   "paper_1506_08620_amd/csrc/ds_ops.h", "paper_1506_08620_amd/csrc/ds_internal.h",
-                   "include/ds.h", "include/ds_device.h")
+                   "paper_1506_08620_amd/csrc/ds_ops.h", "paper_1506_08620_amd/csrc/ds_internal.h")
 
 
 def traffic_sources_sha256() -> str:
@@ -47,6 +49,11 @@ def traffic_sources_sha256() -> str:
     for p in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, p), "rb").read())
     return h.hexdigest()
+
+
+def log(msg: str):
+    """A progress line on stderr (the result lines go to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(dtype: str, ns, stage_name: str):
@@ -71,6 +78,30 @@ def measured_traffic(dtype: str, ns, stage_name: str):
     if not got or len(got) != len(ns):
         return None
     return sum((f * fs + w * ws) * 1024.0 for f, w in got) / len(got)
+
+
+def measured_l2(dtype: str, ns):
+    """L2 requests, hits and misses per launch of the given sweep cases from the committed
+    rocprofv3 counter summary (TCC_REQ_sum, TCC_HIT_sum, TCC_MISS_sum), or None when the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "direct_sweep_l2_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals, cases = {}, {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "case":
+            cases[(f[1], int(f[2]))] = (float(f[4]), float(f[6]), float(f[8]))
+        else:
+            vals[f[0]] = f[1]
+    if vals.get("source_sha256") != traffic_sources_sha256():
+        return None
+    got = [cases[(dtype, n)] for n in ns if (dtype, n) in cases]
+    if not got or len(got) != len(ns):
+        return None
+    return tuple(sum(g[i] for g in got) / len(got) for i in range(3))
 
 
 def parse():
@@ -136,6 +167,7 @@ def main():
             cases.append(dict(n=n, dt=dt, X=X, x=x_d, z=z_d, out=out, idx=idx, build_s=float(np.median(times))))
 
     stream = torch.cuda.current_stream()
+    log(f"sweep: {len(cases)} cases built")
 
     def step(ev=None):
         for k, c in enumerate(cases):
@@ -208,7 +240,16 @@ def main():
                     kernel=kernel_name, cases=[f"{dom_key[0]} N={n}" for n in g[3]],
                     launches_per_step=g[1], bytes_per_launch=int(avg_bytes), avg_launch_ms=round(avg_ms, 5),
                     traffic_over_algorithmic=None if traffic is None else round(traffic / avg_bytes, 3))
+    # the second ceiling of the tables read through L2: requests per second against the L2's
+    # request rate, from the committed counters of the same launches
+    l2 = measured_l2(dom_key[0], g[3])
+    if l2 is not None:
+        req, hit, miss = l2
+        roofline["l2"] = dict(req_per_launch=int(req), achieved_greq_s=round(req / avg_ms / 1e6, 1),
+                              peak_greq_s=L2_PEAK_GREQ_S, frac=round(req / avg_ms / 1e6 / L2_PEAK_GREQ_S, 4),
+                              hit_rate=round(hit / req, 4), req_per_query=round(req / M, 3))
 
+    log(f"sweep: {args.steps} timed steps, {value:.1f} Gq/s")
     # CPU oracle on a bounded sample of the same workload
     cpu = None
     parity = True
@@ -243,10 +284,13 @@ def main():
         cpu = dict(value=None, unit="Gqueries/s", cores=0, kind="oracle", sample=f"failed: {e}")
         cpu1 = None
 
+    log("cpu baseline done")
     extras = {}
     if not args.no_extras:
         extras = compare_methods(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
+        log("other layouts and methods done")
         extras["uses"] = bench_uses(ds, cases, M, stream, reps=max(3, min(args.steps, 10)))
+        log("uses done")
     direct_f64_2p20 = next((r["gq_s"] for r in case_rows if r["N"] == 1 << 20 and r["dtype"] == "f64"), None)
     n_cases = len(cases)
     for c in cases:  # free the sweep's buffers first
@@ -255,9 +299,12 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_learned:
         extras["learned_f64_clustered"] = bench_learned(ds, W, dev, stream, reps=5, direct_ref=direct_f64_2p20)
+        log("learned done")
     if not args.no_batched:
         extras["batched_f32"] = bench_batched(ds, W, dev, stream, reps=3)
+        log("batched done")
         extras["batched_learned_f64_mixture"] = bench_batched_learned(ds, W, dev, stream, reps=2)
+        log("batched learned done")
 
     detail = {"cases": case_rows, "roofline_detail": roofline, "cpu_baseline_detail": cpu,
               "cpu_baseline_1thread_detail": cpu1, **extras}
@@ -301,8 +348,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"direct-sweep: N in {sizes} x {{f32,f64}}, U(0.5,1.5) gaps scaled to [0,1], "
-                               f"M={M} uniform queries per case, subtraction form",
+        "config": {"workload": f"direct-sweep N={sizes} f32+f64, U(0.5,1.5) gaps scaled to [0,1], "
+                               f"M={M} uniform queries per case",
                    "queries_per_step": M * n_cases},
         "roofline": {k: roofline[k] for k in keep if k in roofline},
         "cpu_baseline": cpu,
