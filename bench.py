@@ -298,7 +298,7 @@ def main():
     cases.clear()
     torch.cuda.empty_cache()
     if not args.no_learned:
-        extras["learned_f64_clustered"] = bench_learned(ds, W, dev, stream, reps=5, direct_ref=direct_f64_2p20)
+        extras["learned_f64_clustered"] = bench_learned(ds, W, dev, stream, reps=10, direct_ref=direct_f64_2p20)
         log("learned done")
     if not args.no_batched:
         extras["batched_f32"] = bench_batched(ds, W, dev, stream, reps=3)
@@ -497,7 +497,8 @@ def bench_learned(ds, W, dev, stream, reps, direct_ref):
         idx = ds.build(x_d, **kw)
         torch.cuda.synchronize()
         build_s = time.perf_counter() - t0
-        ds.search(idx, z_d, out=out, stream=stream)
+        for _ in range(reps):  # warm-up long enough for the clocks to settle after the build
+            ds.search(idx, z_d, out=out, stream=stream)
         a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         for _ in range(reps):

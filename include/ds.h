@@ -105,7 +105,7 @@ typedef struct ds_build_opts {
   /* learned method; 0 = default */
   int32_t learn_epochs;     /* passes over the (X_i, i) pairs (default 60); -1 = no
                                network: route by the feature alone (the ablation) */
-  int32_t learn_segments;   /* number of linear segments (default 4096) */
+  int32_t learn_segments;   /* number of linear segments, 1..4096 (default 2048) */
   float learn_rate;         /* Adam step size (default 2e-3) */
   int32_t learn_batch;      /* training pairs per step (default 8192) */
   uint64_t seed;            /* initialisation / sampling seed */

@@ -1160,25 +1160,28 @@ using vec16b = T __attribute__((ext_vector_type(16 / sizeof(T))));
 // The end of the search of a window [L, U] of a single array, through its
 // sample array S (S[j] = X_{E j}, E = 64 / sizeof(T) keys per 64-byte block of
 // X, +inf past the end): the samples jL + 1 .. jU + 1 of the window's blocks
-// (one or two 64-byte lines of S, which stays in L2: N bytes in f64) give the
-// block js of the answer, whose E values are then read as one line and
+// (64 bytes of S, which stays in L2: N bytes in f64) give the block js of the
+// answer, whose E values are then read as one line and
 // counted.  Instead of the dependent probes of a bisection into X and one or
 // two lines of X, a query reads one line of S and one line of X, and a window
 // inside one block reads that block alone (plus the next value when all of
-// the block's values are <= z).  With c2
-// values <= z in block js, X_{E js + c2 - 1} <= z < X_{E js + c2} has been
-// read when 1 <= c2 <= E - 1, or when c2 = E and the sample js + 1 was read;
-// *certified tells whether that holds, whatever the model predicted.
+// the block's values are <= z).
+//
+// sample_block returns js and the window's blocks [jL, jU] after narrowing.
+// The samples read are the 64 bytes from the 16-byte word of S that holds
+// sample jL + 1 (a window of up to SE - V + 1 blocks, 7 in f64 and 13 in f32;
+// longer windows are first narrowed by bisection on S), all issued before
+// any is used.  S is non-decreasing, so the samples <= z among them form a
+// prefix: with A of them, the samples jL + 1 .. jU + 1 that are <= z are
+// those before s0 + A, and no per-sample test of the window's ends is needed.
 template <typename T>
-__device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, const T* __restrict__ X,
-                                                 const T* __restrict__ S, bool* certified) {
+__device__ __forceinline__ int32_t sample_block(T z, int32_t L, int32_t U, const T* __restrict__ S, int32_t* jL_out,
+                                                int32_t* jU_out) {
   constexpr int E = 64 / int(sizeof(T));   // keys per 64-byte block of X
-  constexpr int SE = 64 / int(sizeof(T));  // samples per 64-byte line of S
-  constexpr int V = 16 / int(sizeof(T));
+  constexpr int SE = 64 / int(sizeof(T));  // samples per 64 bytes of S
+  constexpr int V = 16 / int(sizeof(T));   // samples per 16-byte word
   int32_t jL = L / E, jU = U / E;
-  // narrow by bisection on the samples until jL + 1 .. jU + 1 lies in the two
-  // lines of S from the line of jL + 1 (only for windows of dozens of blocks)
-  while (jU + 1 > ((jL + 1) & ~(SE - 1)) + 2 * SE - 1) {
+  while (jU + 1 > ((jL + 1) & ~(V - 1)) + SE - 1) {  // windows of more than SE - V + 1 blocks only
     const int32_t m = jL + ((jU - jL + 1) >> 1);
     const bool c = S[m] <= z;
     jL = c ? m : jL;
@@ -1188,24 +1191,46 @@ __device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, cons
   // of its values are <= z (then the next value, the first of the next block)
   int32_t c1 = 0;
   if (jU > jL) {
-    const int32_t s0 = (jL + 1) & ~(SE - 1);
+    const int32_t s0 = (jL + 1) & ~(V - 1);
     const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
+    vec16b<T> x[SE / V];
 #pragma unroll
-    for (int v = 0; v < SE / V; ++v) {
-      const vec16b<T> x = p[v];
+    for (int v = 0; v < SE / V; ++v) x[v] = p[v];
+    int32_t A = 0;
 #pragma unroll
-      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
-    }
-    if (jU + 1 >= s0 + SE) {
+    for (int v = 0; v < SE / V; ++v)
 #pragma unroll
-      for (int v = SE / V; v < 2 * SE / V; ++v) {
-        const vec16b<T> x = p[v];
-#pragma unroll
-        for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
-      }
-    }
+      for (int e = 0; e < V; ++e) A += (x[v][e] <= z) ? 1 : 0;
+    c1 = std::max(0, std::min(jU + 1, s0 + A - 1) - jL);
   }
-  const int32_t js = jL + c1;
+  *jL_out = jL;
+  *jU_out = jU;
+  return jL + c1;
+}
+
+// The result from the count c2 of values <= z in block js: with c2 values
+// <= z, X_{E js + c2 - 1} <= z < X_{E js + c2} has been read when
+// 1 <= c2 <= E - 1, or when c2 = E and the sample js + 1 was read (else it is
+// read here); *certified tells whether that holds, whatever the model
+// predicted.
+template <typename T>
+__device__ __forceinline__ int32_t block_result(T z, int32_t jL, int32_t jU, int32_t js, int32_t c2,
+                                                const T* __restrict__ X, bool* certified) {
+  constexpr int E = 64 / int(sizeof(T));
+  bool upper = c2 <= E - 1 || (jU > jL && js <= jU);  // the value after the answer was read
+  if (c2 == E && jU == jL) upper = z < X[int64_t(js + 1) * E];
+  *certified = c2 >= 1 && upper;
+  return js * E + c2 - 1;
+}
+
+// sample_block, then each lane reads its own block (four 16-byte loads).
+template <typename T>
+__device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, const T* __restrict__ X,
+                                                 const T* __restrict__ S, bool* certified) {
+  constexpr int E = 64 / int(sizeof(T));
+  constexpr int V = 16 / int(sizeof(T));
+  int32_t jL, jU;
+  const int32_t js = sample_block<T>(z, L, U, S, &jL, &jU);
   const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(X + int64_t(js) * E);
   int32_t c2 = 0;
 #pragma unroll
@@ -1214,10 +1239,7 @@ __device__ __forceinline__ int32_t sample_search(T z, int32_t L, int32_t U, cons
 #pragma unroll
     for (int e = 0; e < V; ++e) c2 += (x[e] <= z) ? 1 : 0;
   }
-  bool upper = c2 <= E - 1 || (jU > jL && js <= jU);  // the value after the answer was read
-  if (c2 == E && jU == jL) upper = z < X[int64_t(js + 1) * E];
-  *certified = c2 >= 1 && upper;
-  return js * E + c2 - 1;
+  return block_result<T>(z, jL, jU, js, c2, X, certified);
 }
 
 // Sum of v over the four lanes of each quad (lanes 4k .. 4k + 3), in every
@@ -1228,91 +1250,89 @@ __device__ __forceinline__ int32_t quad_sum(int32_t v) {
   return v;
 }
 
+// Value of lane r of each quad (lanes 4k .. 4k + 3), in every lane of the
+// quad: a DPP quad permutation [r, r, r, r] per 32-bit word.  r must be a
+// constant after unrolling.
+__device__ __forceinline__ int32_t quad_bcast32(int32_t v, int r) {
+  switch (r) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);
+  }
+}
+
+template <typename U>
+__device__ __forceinline__ U quad_bcast(U v, int r) {
+  static_assert(sizeof(U) % 4 == 0, "32-bit words");
+  int32_t w[sizeof(U) / 4];
+  __builtin_memcpy(w, &v, sizeof(U));
+#pragma unroll
+  for (int i = 0; i < int(sizeof(U) / 4); ++i) w[i] = quad_bcast32(w[i], r);
+  __builtin_memcpy(&v, w, sizeof(U));
+  return v;
+}
+
 // How many of the E values of block blk of X (values blk E .. blk E + E - 1)
-// are <= z, for the query of every lane.  All 64 lanes must call it with a
-// valid block.  The blocks are read cooperatively: in round r the four lanes
-// of quad k read 16 bytes each of the block of query 16 r + k, so each load
-// instruction touches 16 blocks (a lane reading its own block makes four
-// loads that each touch 64).  The quad's counts are summed by DPP; lane
-// 4 k + r keeps round r's sum, and one shuffle hands each query its count.
+// are <= z, for the query of every lane.  All 64 lanes must take part with a
+// valid block.  The blocks are read cooperatively, inside each quad: in round
+// r the four lanes of a quad read 16 bytes each of the block of the quad's
+// lane r (its block and z broadcast by DPP), so each load instruction touches
+// 16 blocks (a lane reading its own block makes four loads that each touch
+// 64).  The quad's counts are summed by DPP and lane r keeps round r's sum.
+// coop_issue issues the four loads; coop_count counts once they are needed,
+// so the caller can issue other loads in between.
 // MASK: only the positions e_lo .. e_hi of the query's block count (the
 // block of a packed buffer holds values of neighbouring arrays).
-template <typename T, bool MASK = false>
-__device__ __forceinline__ int32_t coop_block_count(const T* __restrict__ X, uint64_t blk, T z, int32_t e_lo = 0,
-                                                    int32_t e_hi = 0) {
-  constexpr int E = 64 / int(sizeof(T));
-  constexpr int V = 16 / int(sizeof(T));
-  const int lane = threadIdx.x & 63;
-  const int sub = lane & 3;
-  const int32_t bounds = e_lo | (e_hi << 8);
+template <typename T, bool MASK>
+struct CoopBlock {
   vec16b<T> x[4];
   T zz[4];
   int32_t bd[4];
+};
+
+template <typename T, bool MASK, typename I>
+__device__ __forceinline__ void coop_issue(const T* __restrict__ X, I blk, T z, int32_t e_lo, int32_t e_hi,
+                                           CoopBlock<T, MASK>& c) {
+  constexpr int E = 64 / int(sizeof(T));
+  constexpr int V = 16 / int(sizeof(T));
+  const int sub = threadIdx.x & 3;
+  const int32_t bounds = e_lo | (e_hi << 8);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {  // every load is issued before any value is used
-    const int src = 16 * r + (lane >> 2);
-    const uint64_t b = __shfl(blk, src, 64);
-    zz[r] = __shfl(z, src, 64);
-    if constexpr (MASK) bd[r] = __shfl(bounds, src, 64);
-    x[r] = *reinterpret_cast<const vec16b<T>*>(X + int64_t(b) * E + sub * V);
+    const I b = quad_bcast(blk, r);
+    c.zz[r] = quad_bcast(z, r);
+    if constexpr (MASK) c.bd[r] = quad_bcast32(bounds, r);
+    c.x[r] = *reinterpret_cast<const vec16b<T>*>(X + int64_t(b) * E + sub * V);
   }
+}
+
+template <typename T, bool MASK>
+__device__ __forceinline__ int32_t coop_count(const CoopBlock<T, MASK>& c) {
+  constexpr int V = 16 / int(sizeof(T));
+  const int sub = threadIdx.x & 3;
   int32_t mine = 0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    int32_t c = 0;
+    int32_t n = 0;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       const int pos = sub * V + e;
-      const bool in = MASK ? (pos >= (bd[r] & 0xff) && pos <= (bd[r] >> 8)) : true;
-      c += (in && x[r][e] <= zz[r]) ? 1 : 0;
+      const bool in = MASK ? (pos >= (c.bd[r] & 0xff) && pos <= (c.bd[r] >> 8)) : true;
+      n += (in && c.x[r][e] <= c.zz[r]) ? 1 : 0;
     }
-    c = quad_sum(c);
-    mine = (sub == r) ? c : mine;
+    n = quad_sum(n);
+    mine = (sub == r) ? n : mine;
   }
-  return __shfl(mine, 4 * (lane & 15) + (lane >> 4), 64);
+  return mine;
 }
 
-// sample_search with the block of X read cooperatively (coop_block_count);
-// the samples are read by each lane as there.  Same reads, result and
-// certification.  All 64 lanes must call it.
-template <typename T>
-__device__ __forceinline__ int32_t sample_search_coop(T z, int32_t L, int32_t U, const T* __restrict__ X,
-                                                      const T* __restrict__ S, bool* certified) {
-  constexpr int E = 64 / int(sizeof(T));
-  constexpr int SE = 64 / int(sizeof(T));
-  constexpr int V = 16 / int(sizeof(T));
-  int32_t jL = L / E, jU = U / E;
-  while (jU + 1 > ((jL + 1) & ~(SE - 1)) + 2 * SE - 1) {  // windows of dozens of blocks only
-    const int32_t m = jL + ((jU - jL + 1) >> 1);
-    const bool c = S[m] <= z;
-    jL = c ? m : jL;
-    jU = c ? jU : m - 1;
-  }
-  int32_t c1 = 0;
-  if (jU > jL) {
-    const int32_t s0 = (jL + 1) & ~(SE - 1);
-    const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
-#pragma unroll
-    for (int v = 0; v < SE / V; ++v) {
-      const vec16b<T> x = p[v];
-#pragma unroll
-      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
-    }
-    if (jU + 1 >= s0 + SE) {
-#pragma unroll
-      for (int v = SE / V; v < 2 * SE / V; ++v) {
-        const vec16b<T> x = p[v];
-#pragma unroll
-        for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jU + 1 && x[e] <= z) ? 1 : 0;
-      }
-    }
-  }
-  const int32_t js = jL + c1;
-  const int32_t c2 = coop_block_count<T>(X, static_cast<uint64_t>(js), z);
-  bool upper = c2 <= E - 1 || (jU > jL && js <= jU);
-  if (c2 == E && jU == jL) upper = z < X[int64_t(js + 1) * E];
-  *certified = c2 >= 1 && upper;
-  return js * E + c2 - 1;
+template <typename T, bool MASK = false, typename I>
+__device__ __forceinline__ int32_t coop_block_count(const T* __restrict__ X, I blk, T z, int32_t e_lo = 0,
+                                                    int32_t e_hi = 0) {
+  CoopBlock<T, MASK> c;
+  coop_issue<T, MASK>(X, blk, z, e_lo, e_hi, c);
+  return coop_count<T, MASK>(c);
 }
 
 // Samples of the single-array search: S[j] = X_{E j} for E j < nX (X padded
@@ -1374,7 +1394,7 @@ __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t 
   int32_t c2 = 0;
   if (COOP && (reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && !__ballot(k0 + E > total_x)) {
     // every lane's block lies inside the buffer: the wave reads them cooperatively
-    c2 = coop_block_count<T, true>(Xp, static_cast<uint64_t>(js), z, e_lo, e_hi);
+    c2 = coop_block_count<T, true>(Xp, js, z, e_lo, e_hi);
   } else if ((reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && k0 + E <= total_x) {
     const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(Xp + k0);
 #pragma unroll
@@ -1458,7 +1478,11 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
   auto load_z = [&](int64_t q) { return __builtin_nontemporal_load(a.z + std::min(q, a.M - 1)); };
   T z = load_z(base + lane);
   for (; base < a.M; base += stride) {
-    const T z_next = load_z(base + stride + lane);
+    // the per-lane read loads the next group at once; the cooperative one
+    // after its block loads, so that waiting for the samples does not
+    // wait for the next group (loads complete in order)
+    T z_next;
+    if constexpr (!COOP) z_next = load_z(base + stride + lane);
     const float u = feature(static_cast<double>(z), a.X0d, a.delta, a.flo, a.fscale);
     int32_t seg;
     if constexpr (ROUTE == kRouteTable) {
@@ -1476,8 +1500,17 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
     int32_t L, U;
     query_window<T>(z, seg, segs, &L, &U);
     bool certified;
-    int32_t i = COOP ? sample_search_coop<T>(z, L, U, a.X, a.S, &certified)
-                     : sample_search<T>(z, L, U, a.X, a.S, &certified);
+    int32_t i;
+    if constexpr (COOP) {
+      int32_t jL, jU;
+      const int32_t js = sample_block<T>(z, L, U, a.S, &jL, &jU);
+      CoopBlock<T, false> cb;
+      coop_issue<T, false>(a.X, js, z, 0, 0, cb);
+      z_next = load_z(base + stride + lane);
+      i = block_result<T>(z, jL, jU, js, coop_count<T, false>(cb), a.X, &certified);
+    } else {
+      i = sample_search<T>(z, L, U, a.X, a.S, &certified);
+    }
     if ((z >= a.X0) && (z < a.XN) && !certified) i = full_search_counted<T>(z, a.X, a.N, a.fallbacks);
     i = (z >= a.XN) ? a.N : i;
     i = (z >= a.X0) ? i : -1;
@@ -1498,6 +1531,9 @@ __global__ void fill_inf_kernel(T* __restrict__ Xp, int64_t from, int64_t to) {
 // (4 bytes each) and the grid (4 bytes per cell) in one workgroup's LDS.
 constexpr int32_t kMaxLog2Grid = 12;
 constexpr int32_t kMaxLearnSegments = 4096;
+// 2048 segments (64 KiB of fits, 8 KiB of steps, 8 KiB of grid) leave room
+// for two 1024-thread workgroups per CU
+constexpr int32_t kDefaultLearnSegments = 2048;
 constexpr int64_t kLearnLdsBudget = 160 * 1024;
 
 // probe points of the router compilation: 2^kp + 1 <= nseg + 1
@@ -1573,7 +1609,7 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
     L->flo = static_cast<double>(b0);
     L->fscale = 1.0 / (static_cast<double>(b1) - L->flo);
   }
-  const int32_t nseg = o->learn_segments > 0 ? o->learn_segments : 4096;
+  const int32_t nseg = o->learn_segments > 0 ? o->learn_segments : kDefaultLearnSegments;
   if (nseg < 1 || nseg > kMaxLearnSegments) return DS_ERR_ARG;
   L->nseg = nseg;
   L->identity = (o->learn_epochs < 0) ? 1 : 0;
@@ -1737,8 +1773,12 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   const int block = (h->tune_set && h->tune.block) ? h->tune.block : 1024;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  // eight workgroups per resident slot, each restaging the tables: measured
+  // 5-10 % faster than one persistent workgroup per slot on the clustered f64
+  // array (the waves of a CU then start their groups at different times
+  // rather than all routing, then all waiting on memory, together)
   const int64_t need = (M + block - 1) / block;
-  int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * num_cus())));
+  int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(8) * per_cu * num_cus())));
   if (h->tune_set && h->tune.grid) grid = h->tune.grid;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a);
   DS_HIP_CHECK(hipGetLastError());
