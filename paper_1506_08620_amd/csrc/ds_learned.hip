@@ -1348,45 +1348,46 @@ __global__ void samples_kernel(const T* __restrict__ X, int64_t nX, T* __restric
 // (array values at x_off .. x_off + N, no padding between arrays): blocks and
 // samples are those of the whole buffer, S[J] = Xp[E J], and only samples
 // whose value belongs to the array are counted (blocks after the first one of
-// the array, up to the block holding X_N); the answer's block is scanned with
-// the values outside the array masked, read value by value where the buffer is
-// not 16-byte aligned or the block passes its end (COOP: when no lane's
-// block passes the end of an aligned buffer, the wave reads the blocks
-// cooperatively, coop_block_count; every lane of the wave must then call it).
+// the array, up to the block holding X_N); the samples read are the 64 bytes
+// from the 16-byte word of sample jL + 1, as in sample_block.  The answer's
+// block is scanned with the values outside the array masked, read value by
+// value where the buffer is not 16-byte aligned or the block passes its end
+// (COOP: when no lane's block passes the end of an aligned buffer, the wave
+// reads the blocks cooperatively, coop_issue / coop_count; every lane of the
+// wave must then take part).  between() is called once, by the whole wave
+// together, after the block's loads are issued where they are cooperative
+// (before them otherwise): the caller's next loads then do not hold up this
+// count.
 // Certification as in sample_search, over the array's own values.
-template <typename T, bool COOP = false>
+template <typename T, bool COOP, typename F>
 __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t U, const T* __restrict__ Xp,
                                                         const T* __restrict__ S, int64_t x_off, int32_t N,
-                                                        int64_t total_x, bool* certified) {
+                                                        int64_t total_x, bool* certified, F&& between) {
   constexpr int E = 64 / int(sizeof(T));
   constexpr int SE = 64 / int(sizeof(T));
   constexpr int V = 16 / int(sizeof(T));
   const int64_t jlast = (x_off + N) / E;  // block holding X_N
   int64_t jL = (x_off + L) / E, jU = (x_off + U) / E;
-  while (jU + 1 > ((jL + 1) & ~int64_t(SE - 1)) + 2 * SE - 1) {
+  while (jU + 1 > ((jL + 1) & ~int64_t(V - 1)) + SE - 1) {
     const int64_t m = jL + ((jU - jL + 1) >> 1);  // jL < m <= jU: S[m] is a value of the array
     const bool c = S[m] <= z;
     jL = c ? m : jL;
     jU = c ? jU : m - 1;
   }
   const int64_t jt = std::min(jU + 1, jlast);  // samples jL + 1 .. jt are counted
-  const int64_t s0 = (jL + 1) & ~int64_t(SE - 1);
+  const int64_t s0 = (jL + 1) & ~int64_t(V - 1);
   const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
+  vec16b<T> xs[SE / V];
+#pragma unroll
+  for (int v = 0; v < SE / V; ++v) xs[v] = p[v];
+  // sample s0 + i counts when jL < s0 + i <= jt, i.e. (s0 - jL - 1) + i in [0, jt - jL)
+  const int32_t d = static_cast<int32_t>(s0 - jL - 1);
+  const uint32_t span = static_cast<uint32_t>(jt - jL);
   int32_t c1 = 0;
 #pragma unroll
-  for (int v = 0; v < SE / V; ++v) {
-    const vec16b<T> x = p[v];
+  for (int v = 0; v < SE / V; ++v)
 #pragma unroll
-    for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e > jL && s0 + v * V + e <= jt && x[e] <= z) ? 1 : 0;
-  }
-  if (jt >= s0 + SE) {
-#pragma unroll
-    for (int v = SE / V; v < 2 * SE / V; ++v) {
-      const vec16b<T> x = p[v];
-#pragma unroll
-      for (int e = 0; e < V; ++e) c1 += (s0 + v * V + e <= jt && x[e] <= z) ? 1 : 0;
-    }
-  }
+    for (int e = 0; e < V; ++e) c1 += (static_cast<uint32_t>(d + v * V + e) < span && xs[v][e] <= z) ? 1 : 0;
   const int64_t js = jL + c1;
   const int64_t k0 = js * E;  // buffer index of the block's first value
   const int32_t e_lo = static_cast<int32_t>(std::max<int64_t>(0, x_off - k0));
@@ -1394,17 +1395,23 @@ __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t 
   int32_t c2 = 0;
   if (COOP && (reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && !__ballot(k0 + E > total_x)) {
     // every lane's block lies inside the buffer: the wave reads them cooperatively
-    c2 = coop_block_count<T, true>(Xp, js, z, e_lo, e_hi);
-  } else if ((reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && k0 + E <= total_x) {
-    const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(Xp + k0);
-#pragma unroll
-    for (int v = 0; v < E / V; ++v) {
-      const vec16b<T> x = q[v];
-#pragma unroll
-      for (int e = 0; e < V; ++e) c2 += (v * V + e >= e_lo && v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
-    }
+    CoopBlock<T, true> cb;
+    coop_issue<T, true>(Xp, js, z, e_lo, e_hi, cb);
+    between();
+    c2 = coop_count<T, true>(cb);
   } else {
-    for (int32_t e = e_lo; e <= e_hi; ++e) c2 += (Xp[k0 + e] <= z) ? 1 : 0;
+    between();  // by the whole wave, before the lanes part
+    if ((reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && k0 + E <= total_x) {
+      const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(Xp + k0);
+#pragma unroll
+      for (int v = 0; v < E / V; ++v) {
+        const vec16b<T> x = q[v];
+#pragma unroll
+        for (int e = 0; e < V; ++e) c2 += (v * V + e >= e_lo && v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
+      }
+    } else {
+      for (int32_t e = e_lo; e <= e_hi; ++e) c2 += (Xp[k0 + e] <= z) ? 1 : 0;
+    }
   }
   *certified = c2 >= 1 && (c2 <= e_hi - e_lo || js + 1 <= jt);
   return static_cast<int32_t>(k0 + e_lo + c2 - 1 - x_off);
@@ -1960,15 +1967,23 @@ __global__ void __launch_bounds__(kBatchLearnBlock) batch_learned_search_kernel(
     T zq = load_q(gi);
     while (gi < ngrp) {
       const int64_t q = q0 + int64_t(gi) * 64 + lane;
-      const int32_t gn = claim();
-      const T z_next = load_q(gn);
+      // the next group is claimed and its queries loaded once this group's
+      // block loads are in flight (loads complete in order: issued earlier,
+      // they would hold up the wait for the samples)
+      int32_t gn;
+      T z_next;
+      auto next = [&]() {
+        gn = claim();
+        z_next = load_q(gn);
+      };
       const float u = feature(static_cast<double>(zq), lm.X0, lm.delta, lm.flo, lm.fscale);
       const int32_t seg = IDENT ? segment_of(u, b.nseg) : grid_segment(u, steps, grid, b.log2g);
       int32_t L, U;
       query_window<T>(zq, seg, segs, &L, &U);
       bool certified;
       int32_t i = sample_search_packed<T, true>(zq, L, U, static_cast<const T*>(b.X),
-                                                static_cast<const T*>(b.samples), m.x_off, a.N, b.total_x, &certified);
+                                                static_cast<const T*>(b.samples), m.x_off, a.N, b.total_x, &certified,
+                                                next);
       if ((zq >= a.X0) && (zq < a.XN) && !certified) i = full_search_counted<T>(zq, a.X, a.N, a.fallbacks);
       i = (zq >= a.XN) ? a.N : i;
       i = (zq >= a.X0) ? i : -1;
