@@ -220,10 +220,12 @@ typedef struct ds_tune {
                                through L2, 8 = GAPCODE in LDS (q <= 15); binary
                                search: 1 = X in LDS, 2 = X through L2; Eytzinger: 1 = top
                                levels in LDS, 2 = every level through L2; learned: 1 = each
-                               lane reads its own lines of the sample array and of X, 2 =
-                               the lines are read cooperatively by four lanes each (unroll
-                               must be 0) */
-  int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity) */
+                               lane reads its own 64 bytes of the sample array and its own
+                               block of X, 2 = the same samples, the blocks of X read
+                               cooperatively by the four lanes of each quad (unroll must
+                               be 0) */
+  int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity; the
+                               learned search: eight workgroups per resident slot) */
 } ds_tune;
 
 /*
@@ -356,6 +358,21 @@ ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const flo
  * Synchronises s.  Allocates temporary device memory. */
 ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_t n, int32_t fp16_router, float* y_dev,
                              hipStream_t s);
+
+/* Segments of the f32 features u_dev[k] (k < n, each in [0, 1]) by a learned
+ * handle's router, into seg_dev[k] (device, n int32):
+ *   mode 0: as its search routes queries (for the compiled router: the grid
+ *           cell, then the steps between the cell's first and last);
+ *   mode 1: the network evaluated in FP32 (for the ablation, u itself):
+ *           segment_of(3/4 y(u) + 1/4 u);
+ *   mode 2: as its build routed the keys (for the compiled router: a binary
+ *           search of the whole step table).
+ * For the default compiled router the three agree on every f32 feature:
+ * the step table holds, for every segment k >= 1, the smallest f32 u whose
+ * FP32 network segment is >= k.  For checking.  DS_ERR_ARG if h is not a
+ * learned handle or mode is not 0..2.  Synchronises s. */
+ds_status ds_learned_route(ds_handle h, const float* u_dev, int64_t n, int32_t mode, int32_t* seg_dev,
+                           hipStream_t s);
 
 /* Trained parameters of a learned handle (params_host: capacity >= 1153
  * floats, or NULL) and the number of queries so far that fell outside their

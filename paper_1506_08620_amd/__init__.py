@@ -56,7 +56,7 @@ SYMBOLS = ("ds_build", "ds_search", "ds_set_tune", "ds_autotune", "ds_info", "ds
            "ds_batch_workspace_bytes", "ds_search_batched", "ds_search_batched_noalloc", "ds_batch_autotune",
            "ds_batch_report",
            "ds_batch_fallbacks",
-           "ds_learned_grad", "ds_learned_forward", "ds_learned_model",
+           "ds_learned_grad", "ds_learned_forward", "ds_learned_model", "ds_learned_route",
            "ds_get_view", "ds_view_search", "ds_histogram", "ds_interp_linear")
 N_ROUTER_PARAMS = 1153
 
@@ -144,6 +144,8 @@ def _load_library():
     lib.ds_learned_forward.restype = i32
     lib.ds_learned_model.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_uint64), vp]
     lib.ds_learned_model.restype = i32
+    lib.ds_learned_route.argtypes = [vp, vp, i64, i32, vp, vp]
+    lib.ds_learned_route.restype = i32
     lib.ds_batch_fallbacks.argtypes = [ctypes.POINTER(BatchDesc), ctypes.POINTER(ctypes.c_uint64), vp]
     lib.ds_batch_fallbacks.restype = i32
     lib.ds_batch_autotune.argtypes = [ctypes.POINTER(BatchDesc), vp]
@@ -286,6 +288,20 @@ class Index:
         if st != OK:
             raise DsError(st, "ds_learned_model")
         return p, int(fb.value)
+
+    def learned_route(self, u, mode: int = 0, stream=None):
+        """Segments of the f32 features u (device tensor) by the handle's router:
+        mode 0 as the search routes queries, 1 the network evaluated in FP32,
+        2 as the build routed the keys."""
+        u = u.contiguous()
+        if u.dtype != torch.float32 or not u.is_cuda:
+            raise ValueError("u must be a float32 device tensor")
+        seg = torch.empty(u.numel(), dtype=torch.int32, device=u.device)
+        st = _lib.ds_learned_route(self._h, u.data_ptr(), u.numel(), int(mode), seg.data_ptr(),
+                                   _stream_handle(stream))
+        if st != OK:
+            raise DsError(st, "ds_learned_route")
+        return seg
 
     def clear_tune(self):
         st = _lib.ds_set_tune(self._h, None)

@@ -922,6 +922,14 @@ __global__ void route_keys_table_kernel(const float* __restrict__ steps, const f
     route[i] = table_segment(feat[i], steps, nseg);
 }
 
+// the queries' routing of the compiled router (grid_segment), for checking
+__global__ void route_query_table_kernel(const float* __restrict__ steps, const uint32_t* __restrict__ grid,
+                                         int32_t log2g, const float* __restrict__ feat, int64_t n,
+                                         int32_t* __restrict__ route) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    route[i] = grid_segment(feat[i], steps, grid, log2g);
+}
+
 // first[s] = #{i : route_i < s} for s in [0, nseg]
 __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, int32_t nseg,
                                  int32_t* __restrict__ first) {
@@ -2129,6 +2137,33 @@ ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(route);
   return e == hipSuccess ? DS_OK : DS_ERR_HIP;
+}
+
+ds_status ds_learned_route(ds_handle h, const float* u_dev, int64_t n, int32_t mode, int32_t* seg_dev,
+                           hipStream_t s) {
+  if (!h || !h->learned || !u_dev || !seg_dev || n < 0 || mode < 0 || mode > 2) return DS_ERR_ARG;
+  if (n == 0) return DS_OK;
+  const ds::LearnedModel* L = h->learned;
+  const bool table = L->router == ds::kRouteTable && !L->identity;
+  const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 1 << 16));
+  if (mode == 1 || !table) {
+    // the network evaluated (FP16 inputs for a handle with the FP16-input router, unless mode 1)
+    if (mode != 1 && L->router == ds::kRouteF16)
+      ds::route_keys_kernel<true><<<dim3(blocks), dim3(256), 0, s>>>(L->params, u_dev, n, L->nseg, L->identity,
+                                                                     seg_dev, nullptr);
+    else
+      ds::route_keys_kernel<false><<<dim3(blocks), dim3(256), 0, s>>>(L->params, u_dev, n, L->nseg, L->identity,
+                                                                      seg_dev, nullptr);
+  } else if (mode == 0) {
+    ds::route_query_table_kernel<<<dim3(std::min(blocks, 4096u)), dim3(256), 0, s>>>(L->steps, L->grid, L->log2g,
+                                                                                     u_dev, n, seg_dev);
+  } else {
+    ds::route_keys_table_kernel<<<dim3(std::min(blocks, 4096u)), dim3(256), 0, s>>>(L->steps, u_dev, n, L->nseg,
+                                                                                     seg_dev);
+  }
+  DS_HIP_CHECK(hipGetLastError());
+  DS_HIP_CHECK(hipStreamSynchronize(s));
+  return DS_OK;
 }
 
 ds_status ds_learned_model(ds_handle h, float* params_host, int32_t capacity, uint64_t* fallbacks_host,

@@ -121,6 +121,44 @@ def test_learned_exact_on_clustered_arrays(ds, dt):
             assert inf["model_bytes"] == 1153 * 4 + segs * (40 if table else 32)
 
 
+def test_compiled_router_is_the_fp32_network(ds):
+    """The step table routes every f32 feature exactly as the FP32 network evaluated on it does:
+    on random features, on a grid, and on both sides of every step of the network, each found by
+    bisection over f32 bit patterns with the evaluated network (mode 1), for the search's routing
+    (mode 0, grid then steps) and the build's (mode 2, the whole table)."""
+    rng = np.random.default_rng(11)
+    one = int(np.float32(1.0).view(np.uint32))
+    for dt, n, segs in ((np.float64, 200_000, 2048), (np.float32, 30_000, 512), (np.float64, 5_000, 4096)):
+        X = _clustered(n, dt, 17)
+        idx = ds.build(_dev(X), method="learned", learn_epochs=20, learn_segments=segs, seed=9)
+        u = np.concatenate([rng.uniform(0, 1, 1 << 20), np.linspace(0, 1, 65537), [0.0, 1.0]]).astype(np.float32)
+        ud = _dev(u)
+        net = idx.learned_route(ud, 1).cpu().numpy()
+        assert np.all(net >= 0) and np.all(net < segs)
+        for mode in (0, 2):
+            assert np.array_equal(idx.learned_route(ud, mode).cpu().numpy(), net), (dt, n, mode)
+        # brackets where the network's segment changes on a grid of bit patterns, then bisection
+        bits = np.unique(np.linspace(0, one, 1 << 20).astype(np.int64))
+        sg = idx.learned_route(_dev(bits.astype(np.uint32).view(np.float32)), 1).cpu().numpy()
+        assert np.all(np.diff(sg) >= 0)  # the network's segment is non-decreasing in u
+        ch = np.flatnonzero(np.diff(sg))
+        lo, hi = bits[ch], bits[ch + 1]
+        s_lo = sg[ch]
+        while np.any(hi - lo > 1):
+            mid = lo + (hi - lo) // 2
+            sm = idx.learned_route(_dev(mid.astype(np.uint32).view(np.float32)), 1).cpu().numpy()
+            same = sm == s_lo
+            lo = np.where(same, mid, lo)
+            hi = np.where(same, hi, mid)
+        edge = np.concatenate([lo, hi]).astype(np.uint32).view(np.float32)
+        ed = _dev(edge)
+        ref = idx.learned_route(ed, 1).cpu().numpy()
+        assert np.all(ref[: lo.size] < ref[lo.size:])  # a step between each pair of neighbouring floats
+        for mode in (0, 2):
+            assert np.array_equal(idx.learned_route(ed, mode).cpu().numpy(), ref), (dt, n, mode)
+        idx.destroy()
+
+
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_learned_wide_windows_and_array_ends(ds, dt):
     """Few segments over many keys give windows of thousands of keys (the search narrows them by
