@@ -593,7 +593,7 @@ def bench_batched_learned(ds, W, dev, stream, reps):
     ref = None
     # the trained routers, and the same models with the router replaced by the feature (no network)
     for name, steps in (("trained", 0), ("no_network", -1)):
-        bt = ds.Batch(x_off, X, q_off, z, learn_segments=4096, learn_steps=steps, direct_cap_bytes=64 << 20)
+        bt = ds.Batch(x_off, X, q_off, z, learn_segments=2048, learn_steps=steps, direct_cap_bytes=64 << 20)
         bt.run(stream)
         torch.cuda.synchronize()
         a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -225,7 +225,7 @@ typedef struct ds_tune {
                                cooperatively by the four lanes of each quad (unroll must
                                be 0) */
   int32_t grid;             /* workgroups; 0 = auto (persistent: resident capacity; the
-                               learned search: eight workgroups per resident slot) */
+                               learned search: six workgroups per resident slot) */
 } ds_tune;
 
 /*

@@ -1788,12 +1788,12 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   const int block = (h->tune_set && h->tune.block) ? h->tune.block : 1024;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-  // eight workgroups per resident slot, each restaging the tables: measured
+  // six workgroups per resident slot, each restaging the tables: measured
   // 5-10 % faster than one persistent workgroup per slot on the clustered f64
   // array (the waves of a CU then start their groups at different times
   // rather than all routing, then all waiting on memory, together)
   const int64_t need = (M + block - 1) / block;
-  int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(8) * per_cu * num_cus())));
+  int grid = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(6) * per_cu * num_cus())));
   if (h->tune_set && h->tune.grid) grid = h->tune.grid;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, a);
   DS_HIP_CHECK(hipGetLastError());
