@@ -1176,10 +1176,11 @@ using vec16b = T __attribute__((ext_vector_type(16 / sizeof(T))));
 // the block's values are <= z).
 //
 // sample_block returns js and the window's blocks [jL, jU] after narrowing.
-// The samples read are the 64 bytes from the 16-byte word of S that holds
-// sample jL + 1 (a window of up to SE - V + 1 blocks, 7 in f64 and 13 in f32;
-// longer windows are first narrowed by bisection on S), all issued before
-// any is used.  S is non-decreasing, so the samples <= z among them form a
+// The samples read are 64 bytes of S: the aligned line that holds sample
+// jL + 1 when it holds sample jU + 1 too, else the 64 bytes from the 16-byte
+// word of sample jL + 1 (a window of up to SE - V + 1 blocks, 7 in f64 and 13
+// in f32; longer windows are first narrowed by bisection on S), all issued
+// before any is used.  S is non-decreasing, so the samples <= z among them form a
 // prefix: with A of them, the samples jL + 1 .. jU + 1 that are <= z are
 // those before s0 + A, and no per-sample test of the window's ends is needed.
 template <typename T>
@@ -1199,7 +1200,10 @@ __device__ __forceinline__ int32_t sample_block(T z, int32_t L, int32_t U, const
   // of its values are <= z (then the next value, the first of the next block)
   int32_t c1 = 0;
   if (jU > jL) {
-    const int32_t s0 = (jL + 1) & ~(V - 1);
+    // the 64-byte-aligned line of sample jL + 1 when it holds jU + 1 too (one
+    // request to L2), else the 64 bytes from jL + 1's 16-byte word (two)
+    const int32_t s64 = (jL + 1) & ~(SE - 1);
+    const int32_t s0 = (jU + 1 <= s64 + SE - 1) ? s64 : ((jL + 1) & ~(V - 1));
     const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
     vec16b<T> x[SE / V];
 #pragma unroll
@@ -1383,7 +1387,10 @@ __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t 
     jU = c ? jU : m - 1;
   }
   const int64_t jt = std::min(jU + 1, jlast);  // samples jL + 1 .. jt are counted
-  const int64_t s0 = (jL + 1) & ~int64_t(V - 1);
+  // the 64-byte-aligned line of sample jL + 1 when it holds jt too, else the
+  // 64 bytes from jL + 1's 16-byte word
+  const int64_t s64 = (jL + 1) & ~int64_t(SE - 1);
+  const int64_t s0 = (jt <= s64 + SE - 1) ? s64 : ((jL + 1) & ~int64_t(V - 1));
   const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
   vec16b<T> xs[SE / V];
 #pragma unroll
