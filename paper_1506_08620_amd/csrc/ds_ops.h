@@ -60,40 +60,51 @@ struct has_gather : std::false_type {};
 template <class Op>
 struct has_gather<Op, std::void_t<typename Op::Gathered>> : std::true_type {};
 
+// Vectors of W queries and W results: a lane loads and stores W consecutive
+// values with one 16-byte (f32: 4 values) or 16-byte (f64: 2 values) access,
+// so one load instruction of a wave covers 1 KiB of contiguous queries and the
+// L1 asks the L2 for whole lines (a 32-byte f64 vector per lane would split
+// into two 16-byte loads of which each touches every line at half of it,
+// doubling the requests of the query stream).
+template <typename T, int W>
+using vecw = T __attribute__((ext_vector_type(W)));
+template <int W>
+using ivecw = int __attribute__((ext_vector_type(W)));
+
 // The VEC loop for an operator with a Gathered type: gather, decide and the
-// undecided compares each run over all 4U queries of a lane in turn, so the
+// undecided compares each run over all U W queries of a lane in turn, so the
 // loads of a step are in flight together.  A vector index past the end is
 // clamped to the last vector: every load is in bounds and unconditional
 // (which keeps the loop free of branches, so the compiler's waits cover only
 // the loads a step needs), and only the stores are guarded.  (Prefetching the
 // next iteration's queries measured no faster on MI355X and costs registers.)
-template <typename T, int U, class Op>
-__device__ __forceinline__ void stream_gathered(const vec4<T>* __restrict__ zv, ivec4* __restrict__ ov, int64_t nvec,
-                                                const Op& op) {
+template <typename T, int W, int U, class Op>
+__device__ __forceinline__ void stream_gathered(const vecw<T, W>* __restrict__ zv, ivecw<W>* __restrict__ ov,
+                                                int64_t nvec, const Op& op) {
   const int64_t B = blockDim.x;
   const int64_t step = (int64_t)gridDim.x * B * U;
   const int64_t last = nvec - 1;
   for (int64_t base = (int64_t)blockIdx.x * B * U + threadIdx.x; base < nvec; base += step) {
-    vec4<T> q[U];
+    vecw<T, W> q[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) q[u] = __builtin_nontemporal_load(zv + std::min<int64_t>(base + u * B, last));
-    typename Op::Gathered g[U][4];
+    typename Op::Gathered g[U][W];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int l = 0; l < 4; ++l) g[u][l] = op.gather(q[u][l]);
+      for (int l = 0; l < W; ++l) g[u][l] = op.gather(q[u][l]);
     }
-    int32_t r[U][4], t[U][4];
+    int32_t r[U][W], t[U][W];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int l = 0; l < 4; ++l) r[u][l] = op.decide(q[u][l], g[u][l], &t[u][l]);
+      for (int l = 0; l < W; ++l) r[u][l] = op.decide(q[u][l], g[u][l], &t[u][l]);
     }
-    T x[U][4];
+    T x[U][W];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
+      for (int l = 0; l < W; ++l) {
         x[u][l] = T(0);
         if (t[u][l] >= 0) x[u][l] = op.Xg[t[u][l]];
       }
@@ -101,52 +112,52 @@ __device__ __forceinline__ void stream_gathered(const vec4<T>* __restrict__ zv, 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (base + u * B < nvec) {
-        ivec4 o;
+        ivecw<W> o;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) o[l] = (t[u][l] >= 0) ? t[u][l] - 1 + (q[u][l] >= x[u][l] ? 1 : 0) : r[u][l];
+        for (int l = 0; l < W; ++l) o[l] = (t[u][l] >= 0) ? t[u][l] - 1 + (q[u][l] >= x[u][l] ? 1 : 0) : r[u][l];
         __builtin_nontemporal_store(o, ov + base + u * B);
       }
     }
   }
 }
 
-// Streams M queries through op.  VEC: z and out are aligned for 4-element
-// vector access; U vectors per lane per iteration keep several independent
-// gathers in flight.
+// Streams M queries through op.  VEC: z is aligned for 4-element vectors and
+// out for 16 bytes; a lane handles 4U queries per iteration (f32: U vectors of
+// 4, f64: 2U vectors of 2), so several independent gathers are in flight.
 template <typename T, int U, bool VEC, class Op>
 __device__ __forceinline__ void stream_queries(const T* __restrict__ z, int32_t* __restrict__ out, int64_t M,
                                                const Op& op) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if constexpr (VEC) {
-    const int64_t nvec = M >> 2;
-    const vec4<T>* zv = reinterpret_cast<const vec4<T>*>(z);
-    ivec4* ov = reinterpret_cast<ivec4*>(out);
+    constexpr int W = 16 / int(sizeof(T));  // values per 16-byte vector
+    constexpr int UV = 4 * U / W;           // vectors per lane and iteration
+    const int64_t nvec = M / W;
+    const vecw<T, W>* zv = reinterpret_cast<const vecw<T, W>*>(z);
+    ivecw<W>* ov = reinterpret_cast<ivecw<W>*>(out);
     if constexpr (has_gather<Op>::value) {
-      stream_gathered<T, U>(zv, ov, nvec, op);
+      stream_gathered<T, W, UV>(zv, ov, nvec, op);
     } else {
-      const int64_t step = (int64_t)gridDim.x * blockDim.x * U;
-      for (int64_t base = (int64_t)blockIdx.x * blockDim.x * U + threadIdx.x; base < nvec; base += step) {
-        vec4<T> q[U];
+      const int64_t step = (int64_t)gridDim.x * blockDim.x * UV;
+      for (int64_t base = (int64_t)blockIdx.x * blockDim.x * UV + threadIdx.x; base < nvec; base += step) {
+        vecw<T, W> q[UV];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UV; ++u) {
           const int64_t v = base + (int64_t)u * blockDim.x;
           if (v < nvec) q[u] = __builtin_nontemporal_load(zv + v);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UV; ++u) {
           const int64_t v = base + (int64_t)u * blockDim.x;
           if (v < nvec) {
-            ivec4 r;
-            r.x = op(q[u].x);
-            r.y = op(q[u].y);
-            r.z = op(q[u].z);
-            r.w = op(q[u].w);
+            ivecw<W> r;
+#pragma unroll
+            for (int l = 0; l < W; ++l) r[l] = op(q[u][l]);
             __builtin_nontemporal_store(r, ov + v);
           }
         }
       }
     }
-    const int64_t t = (nvec << 2) + gtid;
+    const int64_t t = nvec * W + gtid;
     if (t < M) out[t] = op(z[t]);
   } else {
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
