@@ -58,23 +58,23 @@ __device__ __forceinline__ void with_direct_op(const DirectArgs<T>& a, unsigned 
   }
 }
 
-// Calls f(k, z_k) for every query: 4-element vector loads when z is aligned
-// (grid-stride over vectors, then the tail), scalar loads otherwise.
+// Calls f(k, z_k) for every query: 16-byte vector loads (4 f32 or 2 f64
+// values, so a wave's load covers 1 KiB of contiguous queries) when z is
+// aligned (grid-stride over vectors, then the tail), scalar loads otherwise.
 template <typename T, class F>
 __device__ __forceinline__ void for_each_query(const T* __restrict__ z, int64_t M, bool vec, F f) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   if (vec) {
-    const int64_t nvec = M >> 2;
-    const vec4<T>* zv = reinterpret_cast<const vec4<T>*>(z);
+    constexpr int W = 16 / int(sizeof(T));
+    const int64_t nvec = M / W;
+    const vecw<T, W>* zv = reinterpret_cast<const vecw<T, W>*>(z);
     for (int64_t v = gtid; v < nvec; v += step) {
-      const vec4<T> q = __builtin_nontemporal_load(zv + v);
-      f(4 * v, q.x);
-      f(4 * v + 1, q.y);
-      f(4 * v + 2, q.z);
-      f(4 * v + 3, q.w);
+      const vecw<T, W> q = __builtin_nontemporal_load(zv + v);
+#pragma unroll
+      for (int l = 0; l < W; ++l) f(W * v + l, q[l]);
     }
-    const int64_t t = (nvec << 2) + gtid;
+    const int64_t t = nvec * W + gtid;
     if (t < M) f(t, z[t]);
   } else {
     for (int64_t k = gtid; k < M; k += step) f(k, z[k]);

@@ -173,43 +173,47 @@ __global__ void __launch_bounds__(1024) eytzinger_kernel(EytArgs<T> a) {
   const int L = a.L;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if constexpr (VEC) {
-    const int64_t nvec = a.M >> 2;
-    const vec4<T>* zv = reinterpret_cast<const vec4<T>*>(a.z);
-    ivec4* ov = reinterpret_cast<ivec4*>(a.out);
+    // 16-byte vectors (4 f32 or 2 f64 queries) so each load of a wave covers
+    // 1 KiB of contiguous queries; 4U queries per lane and iteration either way
+    constexpr int W = 16 / int(sizeof(T));
+    constexpr int UV = 4 * U / W;
+    const int64_t nvec = a.M / W;
+    const vecw<T, W>* zv = reinterpret_cast<const vecw<T, W>*>(a.z);
+    ivecw<W>* ov = reinterpret_cast<ivecw<W>*>(a.out);
     const int64_t B = blockDim.x;
-    const int64_t step = (int64_t)gridDim.x * B * U;
-    for (int64_t base = (int64_t)blockIdx.x * B * U + threadIdx.x; base < nvec; base += step) {
-      vec4<T> q[U];
+    const int64_t step = (int64_t)gridDim.x * B * UV;
+    for (int64_t base = (int64_t)blockIdx.x * B * UV + threadIdx.x; base < nvec; base += step) {
+      vecw<T, W> q[UV];
 #pragma unroll
-      for (int u = 0; u < U; ++u) q[u] = __builtin_nontemporal_load(zv + std::min<int64_t>(base + u * B, nvec - 1));
-      uint32_t k[U][4];
+      for (int u = 0; u < UV; ++u) q[u] = __builtin_nontemporal_load(zv + std::min<int64_t>(base + u * B, nvec - 1));
+      uint32_t k[UV][W];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < UV; ++u)
 #pragma unroll
-        for (int l = 0; l < 4; ++l) k[u][l] = 1;
+        for (int l = 0; l < W; ++l) k[u][l] = 1;
       for (int d = 0; d < lt; ++d) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < UV; ++u)
 #pragma unroll
-          for (int l = 0; l < 4; ++l) k[u][l] = 2 * k[u][l] + (q[u][l] >= Yl[k[u][l]] ? 1u : 0u);
+          for (int l = 0; l < W; ++l) k[u][l] = 2 * k[u][l] + (q[u][l] >= Yl[k[u][l]] ? 1u : 0u);
       }
-      uint64_t kk[U][4];
+      uint64_t kk[UV][W];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
+      for (int u = 0; u < UV; ++u)
 #pragma unroll
-        for (int l = 0; l < 4; ++l) kk[u][l] = k[u][l];
+        for (int l = 0; l < W; ++l) kk[u][l] = k[u][l];
       for (int d = lt; d < L; ++d) {
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < UV; ++u)
 #pragma unroll
-          for (int l = 0; l < 4; ++l) kk[u][l] = 2 * kk[u][l] + (q[u][l] >= a.Y[kk[u][l]] ? 1u : 0u);
+          for (int l = 0; l < W; ++l) kk[u][l] = 2 * kk[u][l] + (q[u][l] >= a.Y[kk[u][l]] ? 1u : 0u);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UV; ++u) {
         if (base + u * B < nvec) {
-          ivec4 o;
+          ivecw<W> o;
 #pragma unroll
-          for (int l = 0; l < 4; ++l) {
+          for (int l = 0; l < W; ++l) {
             const int64_t c = static_cast<int64_t>(kk[u][l] - (uint64_t(1) << L));
             o[l] = static_cast<int32_t>((c < int64_t(a.N) + 1 ? c : int64_t(a.N) + 1) - 1);
           }
@@ -217,7 +221,7 @@ __global__ void __launch_bounds__(1024) eytzinger_kernel(EytArgs<T> a) {
         }
       }
     }
-    const int64_t t = (nvec << 2) + gtid;
+    const int64_t t = nvec * W + gtid;
     if (t < a.M) a.out[t] = eyt_one(a.z[t], Yl, a.Y, lt, L, a.N);
   } else {
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
