@@ -1169,11 +1169,11 @@ using vec16b = T __attribute__((ext_vector_type(16 / sizeof(T))));
 // sample array S (S[j] = X_{E j}, E = 64 / sizeof(T) keys per 64-byte block of
 // X, +inf past the end): the samples jL + 1 .. jU + 1 of the window's blocks
 // (64 bytes of S, which stays in L2: N bytes in f64) give the block js of the
-// answer, whose E values are then read as one line and
-// counted.  Instead of the dependent probes of a bisection into X and one or
-// two lines of X, a query reads one line of S and one line of X, and a window
-// inside one block reads that block alone (plus the next value when all of
-// the block's values are <= z).
+// answer, whose E values are then read as one 64-byte block and counted.
+// Instead of the dependent probes of a bisection into X and one or two lines
+// of X, a query reads 64 bytes of S and one block of X, and a window inside
+// one block reads that block alone (plus the next value when all of the
+// block's values are <= z).
 //
 // sample_block returns js and the window's blocks [jL, jU] after narrowing.
 // The samples read are 64 bytes of S: the aligned line that holds sample
@@ -1780,8 +1780,8 @@ ds_status learned_search_typed(ds_index* h, const void* z, int64_t M, int32_t* o
   const bool table = L->router == kRouteTable && !L->identity;
   const int lds = static_cast<int>(int64_t(L->nseg) * (sizeof(SegFit) + (table ? 4 : 0)) +
                                    (table ? (int64_t(4) << L->log2g) : 0));
-  // ds_tune.stage 1: each lane reads its own lines of S and X; else (0, 2) the
-  // lines are read cooperatively by the quads of the wave
+  // ds_tune.stage 1: each lane reads its own samples and block of X; else (0,
+  // 2) the same samples, and the blocks of X read cooperatively by the quads
   const bool coop = !(h->tune_set && h->tune.stage == 1);
   auto kern = L->router == kRouteTable ? (coop ? learned_search_kernel<T, kRouteTable, true>
                                                : learned_search_kernel<T, kRouteTable, false>)
