@@ -361,12 +361,14 @@ ds_status ds_learned_forward(const float* params_dev, const float* u_dev, int64_
 
 /* Segments of the f32 features u_dev[k] (k < n, each in [0, 1]) by a learned
  * handle's router, into seg_dev[k] (device, n int32):
- *   mode 0: as its search routes queries (for the compiled router: the grid
+ *   mode 0: for the compiled router, as its search routes queries (the grid
  *           cell, then the steps between the cell's first and last);
  *   mode 1: the network evaluated in FP32 (for the ablation, u itself):
- *           segment_of(3/4 y(u) + 1/4 u);
+ *           segment of 3/4 y(u) + 1/4 u;
  *   mode 2: as its build routed the keys (for the compiled router: a binary
  *           search of the whole step table).
+ * For a handle whose router is evaluated per query, modes 0 and 2 evaluate
+ * it as the build did for the keys (FP16 inputs for DS_LEARN_EVAL_ROUTER).
  * For the default compiled router the three agree on every f32 feature:
  * the step table holds, for every segment k >= 1, the smallest f32 u whose
  * FP32 network segment is >= k.  For checking.  DS_ERR_ARG if h is not a
