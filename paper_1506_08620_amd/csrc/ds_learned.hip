@@ -1299,39 +1299,41 @@ __device__ __forceinline__ U quad_bcast(U v, int r) {
 template <typename T, bool MASK>
 struct CoopBlock {
   vec16b<T> x[4];
-  T zz[4];
-  int32_t bd[4];
+  int32_t bounds;  // MASK: e_lo | e_hi << 8 of this lane's query
 };
 
 template <typename T, bool MASK, typename I>
-__device__ __forceinline__ void coop_issue(const T* __restrict__ X, I blk, T z, int32_t e_lo, int32_t e_hi,
+__device__ __forceinline__ void coop_issue(const T* __restrict__ X, I blk, int32_t e_lo, int32_t e_hi,
                                            CoopBlock<T, MASK>& c) {
   constexpr int E = 64 / int(sizeof(T));
   constexpr int V = 16 / int(sizeof(T));
   const int sub = threadIdx.x & 3;
-  const int32_t bounds = e_lo | (e_hi << 8);
+  if constexpr (MASK) c.bounds = e_lo | (e_hi << 8);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {  // every load is issued before any value is used
     const I b = quad_bcast(blk, r);
-    c.zz[r] = quad_bcast(z, r);
-    if constexpr (MASK) c.bd[r] = quad_bcast32(bounds, r);
     c.x[r] = *reinterpret_cast<const vec16b<T>*>(X + int64_t(b) * E + sub * V);
   }
 }
 
+// z (and the bounds) of round r's query are broadcast again here rather than
+// held from coop_issue, which keeps fewer registers live while the loads are
+// in flight.
 template <typename T, bool MASK>
-__device__ __forceinline__ int32_t coop_count(const CoopBlock<T, MASK>& c) {
+__device__ __forceinline__ int32_t coop_count(const CoopBlock<T, MASK>& c, T z) {
   constexpr int V = 16 / int(sizeof(T));
   const int sub = threadIdx.x & 3;
   int32_t mine = 0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
+    const T zr = quad_bcast(z, r);
+    const int32_t bd = MASK ? quad_bcast32(c.bounds, r) : 0;
     int32_t n = 0;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       const int pos = sub * V + e;
-      const bool in = MASK ? (pos >= (c.bd[r] & 0xff) && pos <= (c.bd[r] >> 8)) : true;
-      n += (in && c.x[r][e] <= c.zz[r]) ? 1 : 0;
+      const bool in = MASK ? (pos >= (bd & 0xff) && pos <= (bd >> 8)) : true;
+      n += (in && c.x[r][e] <= zr) ? 1 : 0;
     }
     n = quad_sum(n);
     mine = (sub == r) ? n : mine;
@@ -1343,8 +1345,8 @@ template <typename T, bool MASK = false, typename I>
 __device__ __forceinline__ int32_t coop_block_count(const T* __restrict__ X, I blk, T z, int32_t e_lo = 0,
                                                     int32_t e_hi = 0) {
   CoopBlock<T, MASK> c;
-  coop_issue<T, MASK>(X, blk, z, e_lo, e_hi, c);
-  return coop_count<T, MASK>(c);
+  coop_issue<T, MASK>(X, blk, e_lo, e_hi, c);
+  return coop_count<T, MASK>(c, z);
 }
 
 // Samples of the single-array search: S[j] = X_{E j} for E j < nX (X padded
@@ -1371,53 +1373,81 @@ __global__ void samples_kernel(const T* __restrict__ X, int64_t nX, T* __restric
 // (before them otherwise): the caller's next loads then do not hold up this
 // count.
 // Certification as in sample_search, over the array's own values.
+// The array's place in the packed buffer, the same for every lane of a tile:
+// its values start at Xb[xr] (Xb = Xp + E xb, the start of the block that
+// holds its first value, xr < E), its samples are Sb[j] = S[xb + j], and
+// blocks j with E j + E <= lim lie inside the buffer.  Block indices below
+// are relative to xb, so they fit 32 bits.
+template <typename T>
+struct PackedArray {
+  const T* Xb;
+  const T* Sb;
+  int32_t xr, N;
+  int32_t lim;  // total_x - E xb, capped at INT32_MAX
+};
+
+template <typename T>
+__device__ __forceinline__ PackedArray<T> packed_array(const T* Xp, const T* S, int64_t x_off, int32_t N,
+                                                       int64_t total_x) {
+  constexpr int64_t E = 64 / int64_t(sizeof(T));
+  const int64_t xb = x_off / E;
+  PackedArray<T> pa;
+  pa.Xb = Xp + xb * E;
+  pa.Sb = S + xb;
+  pa.xr = static_cast<int32_t>(x_off - xb * E);
+  pa.N = N;
+  pa.lim = static_cast<int32_t>(std::min<int64_t>(total_x - xb * E, INT32_MAX));
+  return pa;
+}
+
 template <typename T, bool COOP, typename F>
-__device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t U, const T* __restrict__ Xp,
-                                                        const T* __restrict__ S, int64_t x_off, int32_t N,
-                                                        int64_t total_x, bool* certified, F&& between) {
+__device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t U, const PackedArray<T>& pa,
+                                                        bool* certified, F&& between) {
   constexpr int E = 64 / int(sizeof(T));
   constexpr int SE = 64 / int(sizeof(T));
   constexpr int V = 16 / int(sizeof(T));
-  const int64_t jlast = (x_off + N) / E;  // block holding X_N
-  int64_t jL = (x_off + L) / E, jU = (x_off + U) / E;
-  while (jU + 1 > ((jL + 1) & ~int64_t(V - 1)) + SE - 1) {
-    const int64_t m = jL + ((jU - jL + 1) >> 1);  // jL < m <= jU: S[m] is a value of the array
+  const T* __restrict__ S = pa.Sb;
+  const int32_t jlast = (pa.xr + pa.N) / E;  // block holding X_N
+  int32_t jL = (pa.xr + L) / E, jU = (pa.xr + U) / E;
+  while (jU + 1 > ((jL + 1) & ~(V - 1)) + SE - 1) {
+    const int32_t m = jL + ((jU - jL + 1) >> 1);  // jL < m <= jU: S[m] is a value of the array
     const bool c = S[m] <= z;
     jL = c ? m : jL;
     jU = c ? jU : m - 1;
   }
-  const int64_t jt = std::min(jU + 1, jlast);  // samples jL + 1 .. jt are counted
+  const int32_t jt = std::min(jU + 1, jlast);  // samples jL + 1 .. jt are counted
   // the 64-byte-aligned line of sample jL + 1 when it holds jt too, else the
   // 64 bytes from jL + 1's 16-byte word
-  const int64_t s64 = (jL + 1) & ~int64_t(SE - 1);
-  const int64_t s0 = (jt <= s64 + SE - 1) ? s64 : ((jL + 1) & ~int64_t(V - 1));
+  const int32_t s64 = (jL + 1) & ~(SE - 1);
+  const int32_t s0 = (jt <= s64 + SE - 1) ? s64 : ((jL + 1) & ~(V - 1));
   const vec16b<T>* p = reinterpret_cast<const vec16b<T>*>(S + s0);
   vec16b<T> xs[SE / V];
 #pragma unroll
   for (int v = 0; v < SE / V; ++v) xs[v] = p[v];
   // sample s0 + i counts when jL < s0 + i <= jt, i.e. (s0 - jL - 1) + i in [0, jt - jL)
-  const int32_t d = static_cast<int32_t>(s0 - jL - 1);
+  const int32_t d = s0 - jL - 1;
   const uint32_t span = static_cast<uint32_t>(jt - jL);
   int32_t c1 = 0;
 #pragma unroll
   for (int v = 0; v < SE / V; ++v)
 #pragma unroll
     for (int e = 0; e < V; ++e) c1 += (static_cast<uint32_t>(d + v * V + e) < span && xs[v][e] <= z) ? 1 : 0;
-  const int64_t js = jL + c1;
-  const int64_t k0 = js * E;  // buffer index of the block's first value
-  const int32_t e_lo = static_cast<int32_t>(std::max<int64_t>(0, x_off - k0));
-  const int32_t e_hi = static_cast<int32_t>(std::min<int64_t>(E - 1, x_off + N - k0));
+  const int32_t js = jL + c1;
+  const int32_t k0 = js * E;  // the block's first value, relative to Xb
+  const int32_t e_lo = std::max(0, pa.xr - k0);
+  const int32_t e_hi = std::min(E - 1, pa.xr + pa.N - k0);
+  const bool aligned = (reinterpret_cast<uintptr_t>(pa.Xb) & 15) == 0;
   int32_t c2 = 0;
-  if (COOP && (reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && !__ballot(k0 + E > total_x)) {
+  if (COOP && aligned && !__ballot(k0 + E > pa.lim)) {
     // every lane's block lies inside the buffer: the wave reads them cooperatively
     CoopBlock<T, true> cb;
-    coop_issue<T, true>(Xp, js, z, e_lo, e_hi, cb);
+    coop_issue<T, true>(pa.Xb, js, e_lo, e_hi, cb);
     between();
-    c2 = coop_count<T, true>(cb);
+    c2 = coop_count<T, true>(cb, z);
   } else {
     between();  // by the whole wave, before the lanes part
-    if ((reinterpret_cast<uintptr_t>(Xp) & 15) == 0 && k0 + E <= total_x) {
-      const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(Xp + k0);
+    if (aligned && k0 + E <= pa.lim) {
+      const vec16b<T>* q = reinterpret_cast<const vec16b<T>*>(pa.Xb + k0);
 #pragma unroll
       for (int v = 0; v < E / V; ++v) {
         const vec16b<T> x = q[v];
@@ -1425,11 +1455,11 @@ __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t 
         for (int e = 0; e < V; ++e) c2 += (v * V + e >= e_lo && v * V + e <= e_hi && x[e] <= z) ? 1 : 0;
       }
     } else {
-      for (int32_t e = e_lo; e <= e_hi; ++e) c2 += (Xp[k0 + e] <= z) ? 1 : 0;
+      for (int32_t e = e_lo; e <= e_hi; ++e) c2 += (pa.Xb[k0 + e] <= z) ? 1 : 0;
     }
   }
   *certified = c2 >= 1 && (c2 <= e_hi - e_lo || js + 1 <= jt);
-  return static_cast<int32_t>(k0 + e_lo + c2 - 1 - x_off);
+  return k0 + e_lo + c2 - 1 - pa.xr;
 }
 
 // Samples of the packed buffer: S[J] = Xp[E J] for E J < total_x, +inf beyond.
@@ -1527,9 +1557,9 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
       int32_t jL, jU;
       const int32_t js = sample_block<T>(z, L, U, a.S, &jL, &jU);
       CoopBlock<T, false> cb;
-      coop_issue<T, false>(a.X, js, z, 0, 0, cb);
+      coop_issue<T, false>(a.X, js, 0, 0, cb);
       z_next = load_z(base + stride + lane);
-      i = block_result<T>(z, jL, jU, js, coop_count<T, false>(cb), a.X, &certified);
+      i = block_result<T>(z, jL, jU, js, coop_count<T, false>(cb, z), a.X, &certified);
     } else {
       i = sample_search<T>(z, L, U, a.X, a.S, &certified);
     }
@@ -1882,8 +1912,17 @@ int64_t batch_learned_lds(int32_t nseg, int32_t log2g) {
   return int64_t(nseg) * (kSegFitBytes + 4) + (int64_t(4) << log2g);
 }
 
+// A value equal in every lane of the wave, as a scalar (both 32-bit halves
+// through readfirstlane).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint64_t u = static_cast<uint64_t>(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+  return static_cast<int64_t>((uint64_t(hi) << 32) | lo);
+}
+
 template <typename T, bool IDENT>
-__global__ void __launch_bounds__(kBatchLearnBlock) batch_learned_search_kernel(BatchLearned b) {
+__global__ void __launch_bounds__(kBatchLearnBlock, 8) batch_learned_search_kernel(BatchLearned b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // the current and the next tile (claimed by wave 0 while the others work),
   // with their 64-query group counters
@@ -1927,8 +1966,11 @@ __global__ void __launch_bounds__(kBatchLearnBlock) batch_learned_search_kernel(
   __syncthreads();
   int32_t cur = -1;
   for (int bf = 0;; bf ^= 1) {
-    const int64_t g = s_tile[bf];
-    const int32_t k = s_k[bf];
+    // the tile and its array are the same for the whole workgroup: read from
+    // LDS into scalar registers, so the array's metadata is loaded once into
+    // scalar registers too instead of into every lane's vector registers
+    const int64_t g = uniform64(s_tile[bf]);
+    const int32_t k = __builtin_amdgcn_readfirstlane(s_k[bf]);
     if (g >= total) break;
     const ArrMeta<T>& m = meta[k];
     const bool learned = m.method == DS_METHOD_LEARNED;
@@ -1961,6 +2003,8 @@ __global__ void __launch_bounds__(kBatchLearnBlock) batch_learned_search_kernel(
     a.XN = m.XN;
     a.N = m.N;
     a.nseg = b.nseg;
+    const PackedArray<T> pa = packed_array<T>(static_cast<const T*>(b.X), static_cast<const T*>(b.samples), m.x_off,
+                                              m.N, b.total_x);
     const int64_t q0 = m.q_off + (g - m.t_off) * b.tile;
     const int64_t q1 = std::min(m.q_end, q0 + b.tile);
     const int32_t ngrp = static_cast<int32_t>((q1 - q0 + 63) >> 6);
@@ -1996,9 +2040,7 @@ __global__ void __launch_bounds__(kBatchLearnBlock) batch_learned_search_kernel(
       int32_t L, U;
       query_window<T>(zq, seg, segs, &L, &U);
       bool certified;
-      int32_t i = sample_search_packed<T, true>(zq, L, U, static_cast<const T*>(b.X),
-                                                static_cast<const T*>(b.samples), m.x_off, a.N, b.total_x, &certified,
-                                                next);
+      int32_t i = sample_search_packed<T, true>(zq, L, U, pa, &certified, next);
       if ((zq >= a.X0) && (zq < a.XN) && !certified) i = full_search_counted<T>(zq, a.X, a.N, a.fallbacks);
       i = (zq >= a.XN) ? a.N : i;
       i = (zq >= a.X0) ? i : -1;
@@ -2071,7 +2113,15 @@ ds_status batched_learned_search_typed(const BatchLearned& b, hipStream_t s) {
 }  // namespace
 
 // the batched search kernel's own LDS (tile claims) is kept out of the budget
-int32_t batch_grid_log2(int32_t nseg) { return grid_log2(nseg, kLearnLdsBudget - 1024); }
+// The batched search's grid: small enough that two workgroups fit one CU's LDS
+// (fits, steps, grid and about 1 KiB of static LDS each) when the fits and
+// steps leave room for a grid of at least 64 cells, else as large as one
+// workgroup allows.
+int32_t batch_grid_log2(int32_t nseg) {
+  const int64_t half = kLearnLdsBudget / 2 - 1024;
+  if (int64_t(nseg) * (int64_t(sizeof(SegFit)) + 4) + (int64_t(4) << 6) <= half) return grid_log2(nseg, half);
+  return grid_log2(nseg, kLearnLdsBudget - 1024);
+}
 
 ds_status batched_learned_build(const BatchLearned& b, int dtype, hipStream_t s) {
   if (b.nseg < 1 || b.nseg > kBatchMaxSegments || batch_learned_lds(b.nseg, b.log2g) > kLearnLdsBudget - 1024)
