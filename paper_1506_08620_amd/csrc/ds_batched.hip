@@ -616,7 +616,10 @@ __global__ void __launch_bounds__(kPlanBlock) plan_kernel(ArrMeta<T>* __restrict
     tot->queue[tid] = 0;
     tot->lqueue[tid] = 0;
   }
-  if (tid == 0) tot->fallbacks = 0;
+  if (tid == 0) {
+    tot->fallbacks = 0;
+    tot->long_segs = 0;
+  }
   const int32_t per = (K + kPlanBlock - 1) / kPlanBlock;
   const int32_t kb = static_cast<int32_t>(std::min<int64_t>(K, int64_t(tid) * per));
   const int32_t ke = static_cast<int32_t>(std::min<int64_t>(K, int64_t(kb) + per));

@@ -41,7 +41,7 @@ struct PlanTotals {
   uint32_t queue[kNumQueues];   // Direct / binary-search tiles
   uint32_t lqueue[kNumQueues];  // learned tiles
   int32_t n_learned;
-  int32_t pad;
+  uint32_t long_segs;  // long segments queued by the learned fit (batched learned build)
   unsigned long long fallbacks;  // learned queries that left their window
 };
 

@@ -940,28 +940,62 @@ __global__ void seg_first_kernel(const int32_t* __restrict__ route, int64_t n, i
   }
 }
 
+// Copy n 32-bit words from global memory to LDS with 4-byte moves, four
+// loads in flight per lane.  The router's step table and grid sit after nseg
+// entries, so their addresses are 4-byte but, for nseg not a multiple of 4,
+// not 16-byte aligned (stage_bytes needs 16).
+__device__ __forceinline__ void stage_words(void* dst, const void* src, int64_t n) {
+  const uint32_t* s = static_cast<const uint32_t*>(src);
+  uint32_t* d = static_cast<uint32_t*>(dst);
+  const int64_t B = blockDim.x;
+  int64_t k = threadIdx.x;
+  for (; k + 3 * B < n; k += 4 * B) {
+    const uint32_t w0 = s[k], w1 = s[k + B], w2 = s[k + 2 * B], w3 = s[k + 3 * B];
+    d[k] = w0;
+    d[k + B] = w1;
+    d[k + 2 * B] = w2;
+    d[k + 3 * B] = w3;
+  }
+  for (; k < n; k += B) d[k] = s[k];
+}
+
 // The batched form of route_keys_kernel + seg_first_kernel in one pass, with
 // no per-key route array: each wave takes a contiguous range of at least 8
 // of the array's 64-key groups, and each key i routed to segment r with its
 // predecessor in segment p writes first[s] = i for s in (p, r]; the last key
 // also writes first[s] = n for s above its segment.  A lane's predecessor is
 // the lane before it or, for lane 0, the last key of the previous group (the
-// wave routes the group before its range first).  The next group's features
-// are loaded before the current group is routed.  Routing is the same code as
-// route_keys_kernel.  (Waves taking groups in lockstep, four at a time with
-// the predecessors passed through LDS, ran 1.1x slower than the two kernels.)
+// wave routes the key before its range first).  The features of the next
+// kRouteGroups groups are loaded before the current ones are routed, so each
+// lane keeps up to 2 kRouteGroups loads in flight.  The compiled router's step
+// table and grid are staged in LDS first (a few dozen KiB at most), and each
+// model's keys are shared by kRouteBlocks workgroups of 1024 lanes.  Routing
+// is the same function as route_keys_table_kernel's.
+constexpr int kRouteBlock = 1024;
+constexpr int kRouteBlocks = 8;
+constexpr int kRouteGroups = 4;
+
+// dynamic LDS of route_first_kernel<false>: the step table, then the grid
+int64_t route_first_lds(int32_t nseg, int32_t log2g) { return int64_t(nseg) * 4 + (int64_t(4) << log2g); }
+
 template <bool IDENT>
-__global__ void __launch_bounds__(256) route_first_kernel(const float* __restrict__ steps_all,
-                                                          const uint32_t* __restrict__ grid_all, int32_t log2g,
-                                                          const float* __restrict__ feat, int32_t nseg,
-                                                          int32_t* __restrict__ first,
-                                                          const LearnMeta* __restrict__ lm,
-                                                          const PlanTotals* __restrict__ tot) {
+__global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* __restrict__ steps_all,
+                                                                  const uint32_t* __restrict__ grid_all, int32_t log2g,
+                                                                  const float* __restrict__ feat, int32_t nseg,
+                                                                  int32_t* __restrict__ first,
+                                                                  const LearnMeta* __restrict__ lm,
+                                                                  const PlanTotals* __restrict__ tot) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char rlds[];
   const int slot = blockIdx.y;
-  if (slot >= tot->n_learned) return;
+  if (slot >= tot->n_learned) return;  // uniform across the workgroup
+  const float* steps = reinterpret_cast<const float*>(rlds);
+  const uint32_t* grid = reinterpret_cast<const uint32_t*>(rlds + int64_t(nseg) * 4);
+  if (!IDENT) {
+    stage_words(rlds, steps_all + (int64_t)slot * nseg, nseg);
+    stage_words(rlds + int64_t(nseg) * 4, grid_all + ((int64_t)slot << log2g), int64_t(1) << log2g);
+    __syncthreads();
+  }
   const LearnMeta L = lm[slot];
-  const float* steps = steps_all + (int64_t)slot * nseg;
-  const uint32_t* grid = grid_all + ((int64_t)slot << log2g);
   feat += L.x_off;
   first += (int64_t)slot * (nseg + 1);
   const int64_t n = int64_t(L.N) + 1;  // keys
@@ -974,113 +1008,157 @@ __global__ void __launch_bounds__(256) route_first_kernel(const float* __restric
   const int lane = threadIdx.x & 63;
   auto segment = [&](float u) { return IDENT ? segment_of(u, nseg) : grid_segment(u, steps, grid, log2g); };
   auto feature_at = [&](int64_t i) { return i < n ? feat[i] : 1.0f; };
-  // the key before the range (group g0 - 1 is whole)
-  int32_t carry = -1;
-  if (g0 > 0) carry = __shfl(segment(feat[(g0 - 1) * 64 + lane]), 63, 64);
-  float u_next = feature_at(g0 * 64 + lane);
-  for (int64_t grp = g0; grp < g1; ++grp) {
-    const float u = u_next;
-    if (grp + 1 < g1) u_next = feature_at((grp + 1) * 64 + lane);
-    const int64_t i = grp * 64 + lane;
-    const int32_t r = segment(u);
-    int32_t p = __shfl_up(r, 1, 64);
-    if (lane == 0) p = carry;
-    if (i < n) {
-      for (int32_t sg = p + 1; sg <= r; ++sg) first[sg] = static_cast<int32_t>(i);
-      if (i == n - 1)
-        for (int32_t sg = r + 1; sg <= nseg; ++sg) first[sg] = static_cast<int32_t>(n);
+  // the key before the range
+  int32_t carry = (g0 > 0) ? segment(feat[g0 * 64 - 1]) : -1;
+  float un[kRouteGroups];
+#pragma unroll
+  for (int k = 0; k < kRouteGroups; ++k) un[k] = feature_at((g0 + k) * 64 + lane);
+  for (int64_t grp = g0; grp < g1; grp += kRouteGroups) {
+    float u[kRouteGroups];
+#pragma unroll
+    for (int k = 0; k < kRouteGroups; ++k) u[k] = un[k];
+    if (grp + kRouteGroups < g1) {
+#pragma unroll
+      for (int k = 0; k < kRouteGroups; ++k) un[k] = feature_at((grp + kRouteGroups + k) * 64 + lane);
     }
-    carry = __shfl(r, 63, 64);  // used only when the group is whole
+#pragma unroll
+    for (int k = 0; k < kRouteGroups; ++k) {
+      if (grp + k >= g1) break;  // uniform across the wave
+      const int64_t i = (grp + k) * 64 + lane;
+      const int32_t r = segment(u[k]);
+      int32_t p = __shfl_up(r, 1, 64);
+      if (lane == 0) p = carry;
+      if (i < n) {
+        for (int32_t sg = p + 1; sg <= r; ++sg) first[sg] = static_cast<int32_t>(i);
+        if (i == n - 1)
+          for (int32_t sg = r + 1; sg <= nseg; ++sg) first[sg] = static_cast<int32_t>(n);
+      }
+      carry = __shfl(r, 63, 64);  // used only when the group is whole
+    }
   }
 }
 
 // least-squares line of index against z for the keys of one segment (f64
-// sums over centred z), then the key errors over [lo, hi + 1].  One wave per
-// segment and one segment per workgroup, so that a wave retires as soon as its
-// segment is done (segment sizes are very uneven: clusters route thousands of
-// keys to one segment while half the segments stay empty).  Reductions run in
-// a fixed order (lane i holds lo + i, lo + i + 64, ... or, over a long
-// segment, a + i, a + i + 64, ...).  Up to 128 keys the values are loaded
-// once for both passes; longer segments loop with 8 loads per lane in flight.
-// (Four segments per 256-lane workgroup took 1.2x as long, sixteen per
-// workgroup with the long ones shared by all its waves 2x, and a workgroup of
-// 1024 lanes per segment over 8192 keys, in a second launch, added more than it
-// saved: the many short segments, not the few long ones, set the time.)
+// sums over centred z), then the key errors over [lo, hi + 1].
+//
+// seg_fit_kernel: one wave per kFitSegs consecutive segments and one wave per
+// workgroup, so that a wave retires as soon as its segments are done.  The
+// wave reads the kFitSegs + 1 boundaries in one load; a short segment's keys
+// (fit range up to 128) are loaded once for both passes, longer ones loop with
+// 8 loads per lane in flight.  The kernel is bound by instruction issue (half
+// the segments are empty or hold one key), so a segment's butterflies span
+// only the lanes that hold its keys, and one key needs no sums.  (Four
+// segments per wave, their loads issued together, took 1.06x as long.)  In the
+// batched form, a segment whose fit range exceeds kLongKeys keys is queued for
+// seg_fit_long_kernel instead, which gives it a workgroup of kLongBlock lanes:
+// segment sizes are very uneven (clusters route tens of thousands of keys to
+// one segment), and a single wave walking such a segment set the whole
+// launch's time (374 us against 221 + 163 for the two kernels, for 2048
+// segments of each of the 256 mixture arrays).  Reductions run in a fixed
+// order (with L lanes, lane t holds a + t, a + t + L, ...; a butterfly over
+// the wave, then the waves in order), so the fits do not depend on timing.
 constexpr int kFitLanes = 64;
 constexpr int kFitRounds = 2;
 constexpr int kFitUnroll = 8;
+constexpr int kFitSegs = 1;
+constexpr int kLongKeys = 2048;
+constexpr int kLongBlock = 1024;
+
+// a queued long segment: model slot and segment
+struct LongSeg {
+  int32_t slot, s;
+};
+
+// the keys [a, b) of a segment and the range [lo, last] of its error pass
+struct FitSpan {
+  int64_t a, b, lo, hi, last;
+  bool fast;  // last - lo < kFitLanes * kFitRounds: values loaded once
+};
+
+__device__ __forceinline__ FitSpan fit_span(int64_t a, int64_t b, int64_t N) {
+  FitSpan sp;
+  sp.a = a;
+  sp.b = b;
+  sp.lo = std::max<int64_t>(0, std::min<int64_t>(a - 1, N - 1));
+  sp.hi = std::max<int64_t>(sp.lo, std::min<int64_t>(b - 1, N - 1));
+  sp.last = std::min(sp.hi + 1, N);
+  sp.fast = sp.last - sp.lo < kFitLanes * kFitRounds;
+  return sp;
+}
+
+struct FitSums {
+  double sz, szz, siz;
+};
 
 template <typename T>
-__global__ void __launch_bounds__(kFitLanes) seg_fit_kernel(const T* __restrict__ X, int64_t N,
-                                                            const int32_t* __restrict__ first,
-                                                            SegFit* __restrict__ segs, int32_t nseg,
-                                                            const LearnMeta* __restrict__ lm,
-                                                            const PlanTotals* __restrict__ tot) {
-  if (lm) {
-    const int slot = blockIdx.y;
-    if (slot >= tot->n_learned) return;
-    const LearnMeta L = lm[slot];
-    X += L.x_off;
-    N = L.N;
-    first += (int64_t)slot * (nseg + 1);
-    segs += (int64_t)slot * nseg;
+__device__ __forceinline__ void add_key(FitSums& s, int64_t i, T x, int64_t lo, double zc) {
+  const double dz = static_cast<double>(x) - zc;
+  s.sz += dz;
+  s.szz += dz * dz;
+  s.siz += static_cast<double>(i - lo) * dz;
+}
+
+// the sums over keys [from, to) taken by lane t of L lanes, in rounds of
+// kFitUnroll loads issued together (the last round's loads predicated, so a
+// remainder costs one round trip, not one per key)
+template <typename T, int L>
+__device__ __forceinline__ void add_keys(const T* __restrict__ X, int64_t from, int64_t to, int64_t lo, double zc,
+                                         int t, FitSums& s) {
+  for (int64_t i = from + t; i < to; i += kFitUnroll * L) {
+    T x[kFitUnroll];
+#pragma unroll
+    for (int u = 0; u < kFitUnroll; ++u) x[u] = (i + u * L < to) ? X[i + u * L] : T(0);
+#pragma unroll
+    for (int u = 0; u < kFitUnroll; ++u)
+      if (i + u * L < to) add_key(s, i + u * L, x[u], lo, zc);
   }
-  const int s = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int64_t a = first[s], b = first[s + 1];  // keys [a, b)
-  const int64_t lo = std::max<int64_t>(0, std::min<int64_t>(a - 1, N - 1));
-  const int64_t hi = std::max<int64_t>(lo, std::min<int64_t>(b - 1, N - 1));
-  const int64_t c0 = (a < b) ? a : lo;
-  const int64_t last = std::min(hi + 1, N);  // the error pass covers [lo, last]
-  const bool fast = last - lo < kFitLanes * kFitRounds;
-  T v[kFitRounds];
-#pragma unroll
-  for (int r = 0; r < kFitRounds; ++r) {
-    const int64_t i = lo + lane + kFitLanes * r;
-    v[r] = (fast && i <= last) ? X[i] : T(0);
+}
+
+// The butterfly width for values held by lanes [0, cnt) (lanes above hold the
+// reduction's identity): the levels o = top, top / 2, ..., 1 cover lanes
+// [0, 2 top), and the levels above would only combine identities (adding an
+// exact zero, or taking the min / max with the empty bound).
+__device__ __forceinline__ int butterfly_top(int64_t cnt) {
+  int top = 0;  // covers one lane
+  while (top < kFitLanes / 2 && (top ? 2 * int64_t(top) : 1) < cnt) top = top ? 2 * top : 1;
+  return top;
+}
+
+__device__ __forceinline__ double lane0(double x) {
+  uint64_t b;
+  __builtin_memcpy(&b, &x, 8);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+  b = (uint64_t(hi) << 32) | lo;
+  __builtin_memcpy(&x, &b, 8);
+  return x;
+}
+
+// the sums over lanes [0, 2 top), then lane 0's in every lane (the whole wave
+// must be active)
+__device__ __forceinline__ void wave_sum(FitSums& s, int top = kFitLanes / 2) {
+  for (int o = top; o > 0; o >>= 1) {
+    s.sz += __shfl_xor(s.sz, o, kFitLanes);
+    s.szz += __shfl_xor(s.szz, o, kFitLanes);
+    s.siz += __shfl_xor(s.siz, o, kFitLanes);
   }
-  const double zc = static_cast<double>(X[c0]);
-  // n and the sum of (i - lo) over the keys [a, b) have closed forms
-  const double n = static_cast<double>(b - a);
-  const double si_ = n * (static_cast<double>(a + b - 1) * 0.5 - static_cast<double>(lo));
-  double sz = 0, szz = 0, siz = 0;
-  auto add = [&](int64_t i, T x) {
-    const double dz = static_cast<double>(x) - zc;
-    sz += dz;
-    szz += dz * dz;
-    siz += static_cast<double>(i - lo) * dz;
-  };
-  if (fast) {
-#pragma unroll
-    for (int r = 0; r < kFitRounds; ++r) {
-      const int64_t i = lo + lane + kFitLanes * r;
-      if (i >= a && i < b) add(i, v[r]);
-    }
-  } else {
-    int64_t i = a + lane;
-    for (; i + (kFitUnroll - 1) * kFitLanes < b; i += kFitUnroll * kFitLanes) {
-      T x[kFitUnroll];
-#pragma unroll
-      for (int u = 0; u < kFitUnroll; ++u) x[u] = X[i + u * kFitLanes];
-#pragma unroll
-      for (int u = 0; u < kFitUnroll; ++u) add(i + u * kFitLanes, x[u]);
-    }
-    for (; i < b; i += kFitLanes) add(i, X[i]);
-  }
-#pragma unroll
-  for (int o = kFitLanes / 2; o > 0; o >>= 1) {
-    sz += __shfl_xor(sz, o, kFitLanes);
-    szz += __shfl_xor(szz, o, kFitLanes);
-    siz += __shfl_xor(siz, o, kFitLanes);
-  }
-  // every lane holds the same sums and computes the same fit
+  s.sz = lane0(s.sz);
+  s.szz = lane0(s.szz);
+  s.siz = lane0(s.siz);
+}
+
+// the line of the sums (every lane holds the same sums and computes the same
+// fit); n and the sum of (i - lo) over the keys [a, b) have closed forms
+__device__ __forceinline__ SegFit line_fit(const FitSpan& sp, double zc, const FitSums& s) {
+  const double n = static_cast<double>(sp.b - sp.a);
+  const double si_ = n * (static_cast<double>(sp.a + sp.b - 1) * 0.5 - static_cast<double>(sp.lo));
   double slope = 0, icpt = 0;
   if (n >= 2) {
-    const double var = szz - sz * sz / n;
-    const double cov = siz - si_ * sz / n;
+    const double var = s.szz - s.sz * s.sz / n;
+    const double cov = s.siz - si_ * s.sz / n;
     slope = (var > 0) ? cov / var : 0.0;
     if (!(slope > 0)) slope = 0;  // monotone prediction
-    icpt = (si_ - slope * sz) / n;
+    icpt = (si_ - slope * s.sz) / n;
   } else if (n == 1) {
     icpt = si_;
   }
@@ -1088,40 +1166,190 @@ __global__ void __launch_bounds__(kFitLanes) seg_fit_kernel(const T* __restrict_
   f.zc = zc;
   f.a = static_cast<float>(slope);
   f.b = static_cast<float>(icpt);
-  f.lo = static_cast<int32_t>(lo);
-  f.hi = static_cast<int32_t>(hi);
-  int32_t dmin = 1 << 30, dmax = -(1 << 30);
-  auto err = [&](int64_t i, T x) {
-    const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, x);
-    dmin = std::min(dmin, d);
-    dmax = std::max(dmax, d);
-  };
-  if (fast) {
+  f.lo = static_cast<int32_t>(sp.lo);
+  f.hi = static_cast<int32_t>(sp.hi);
+  return f;
+}
+
+template <typename T>
+__device__ __forceinline__ void err_key(const SegFit& f, int64_t i, T x, int64_t lo, int32_t& dmin, int32_t& dmax) {
+  const int32_t d = static_cast<int32_t>(i - lo) - seg_predict<T>(f, x);
+  dmin = std::min(dmin, d);
+  dmax = std::max(dmax, d);
+}
+
+// the error bounds over keys [lo, last] taken by lane t of L lanes, in rounds
+// as add_keys
+template <typename T, int L>
+__device__ __forceinline__ void err_keys(const T* __restrict__ X, int64_t lo, int64_t last, const SegFit& f, int t,
+                                         int32_t& dmin, int32_t& dmax) {
+  for (int64_t i = lo + t; i <= last; i += kFitUnroll * L) {
+    T x[kFitUnroll];
 #pragma unroll
-    for (int r = 0; r < kFitRounds; ++r) {
-      const int64_t i = lo + lane + kFitLanes * r;
-      if (i <= last) err(i, v[r]);
-    }
-  } else {
-    int64_t i = lo + lane;
-    for (; i + (kFitUnroll - 1) * kFitLanes <= last; i += kFitUnroll * kFitLanes) {
-      T x[kFitUnroll];
+    for (int u = 0; u < kFitUnroll; ++u) x[u] = (i + u * L <= last) ? X[i + u * L] : T(0);
 #pragma unroll
-      for (int u = 0; u < kFitUnroll; ++u) x[u] = X[i + u * kFitLanes];
-#pragma unroll
-      for (int u = 0; u < kFitUnroll; ++u) err(i + u * kFitLanes, x[u]);
-    }
-    for (; i <= last; i += kFitLanes) err(i, X[i]);
+    for (int u = 0; u < kFitUnroll; ++u)
+      if (i + u * L <= last) err_key(f, i + u * L, x[u], lo, dmin, dmax);
   }
-#pragma unroll
-  for (int o = kFitLanes / 2; o > 0; o >>= 1) {
+}
+
+__device__ __forceinline__ void wave_minmax(int32_t& dmin, int32_t& dmax, int top = kFitLanes / 2) {
+  for (int o = top; o > 0; o >>= 1) {
     dmin = std::min(dmin, __shfl_xor(dmin, o, kFitLanes));
     dmax = std::max(dmax, __shfl_xor(dmax, o, kFitLanes));
   }
-  if (lane == 0) {
-    f.dmin = dmin;
-    f.dmax = dmax;
-    segs[s] = f;
+  dmin = __builtin_amdgcn_readfirstlane(dmin);
+  dmax = __builtin_amdgcn_readfirstlane(dmax);
+}
+
+// the fit and error bounds of one segment by one wave, from its span, its
+// values v[r] = X[lo + lane + 64 r] when sp.fast, and its centre zc = X[a]
+// (X[lo] when empty)
+template <typename T>
+__device__ __forceinline__ SegFit fit_one(const T* __restrict__ X, const FitSpan& sp, const T (&v)[kFitRounds],
+                                          double zc, int lane) {
+  // a segment's keys sit in lanes [0, cnt) when sp.fast and cnt <= 64
+  const int top = sp.fast ? butterfly_top(sp.last - sp.lo + 1) : kFitLanes / 2;
+  FitSums s{0, 0, 0};
+  if (sp.b - sp.a >= 2) {  // one key gives zero sums (its centre is itself)
+    if (sp.fast) {
+#pragma unroll
+      for (int r = 0; r < kFitRounds; ++r) {
+        const int64_t i = sp.lo + lane + kFitLanes * r;
+        if (i >= sp.a && i < sp.b) add_key(s, i, v[r], sp.lo, zc);
+      }
+    } else {
+      add_keys<T, kFitLanes>(X, sp.a, sp.b, sp.lo, zc, lane, s);
+    }
+    wave_sum(s, top);
+  }
+  SegFit f = line_fit(sp, zc, s);
+  int32_t dmin = 1 << 30, dmax = -(1 << 30);
+  if (sp.fast) {
+#pragma unroll
+    for (int r = 0; r < kFitRounds; ++r) {
+      const int64_t i = sp.lo + lane + kFitLanes * r;
+      if (i <= sp.last) err_key(f, i, v[r], sp.lo, dmin, dmax);
+    }
+  } else {
+    err_keys<T, kFitLanes>(X, sp.lo, sp.last, f, lane, dmin, dmax);
+  }
+  wave_minmax(dmin, dmax, top);
+  f.dmin = dmin;
+  f.dmax = dmax;
+  return f;
+}
+
+// segments [kFitSegs x, kFitSegs (x + 1)) of the model, x = blockIdx.x; with
+// long_list (batched form), the long ones are queued there (count in
+// tot->long_segs) for seg_fit_long_kernel
+template <typename T>
+__global__ void __launch_bounds__(kFitLanes, 8) seg_fit_kernel(const T* __restrict__ X, int64_t N,
+                                                               const int32_t* __restrict__ first,
+                                                               SegFit* __restrict__ segs, int32_t nseg,
+                                                               const LearnMeta* __restrict__ lm,
+                                                               PlanTotals* __restrict__ tot,
+                                                               LongSeg* __restrict__ long_list) {
+  const int slot = blockIdx.y;
+  if (lm) {
+    if (slot >= tot->n_learned) return;
+    const LearnMeta L = lm[slot];
+    X += L.x_off;
+    N = L.N;
+    first += (int64_t)slot * (nseg + 1);
+    segs += (int64_t)slot * nseg;
+  }
+  const int32_t s0 = static_cast<int32_t>(blockIdx.x) * kFitSegs;
+  const int lane = threadIdx.x;
+  // first[s0 .. s0 + kFitSegs] (clamped to first[nseg]) in one load
+  const int32_t fl = first[std::min(s0 + std::min(lane, kFitSegs), nseg)];
+  FitSpan sp[kFitSegs];
+  T v[kFitSegs][kFitRounds];
+  double zc[kFitSegs];
+#pragma unroll
+  for (int k = 0; k < kFitSegs; ++k) {
+    const int64_t a = __builtin_amdgcn_readfirstlane(__shfl(fl, k, kFitLanes));
+    const int64_t b = __builtin_amdgcn_readfirstlane(__shfl(fl, k + 1, kFitLanes));
+    sp[k] = fit_span(a, b, N);
+    const bool live = s0 + k < nseg;
+#pragma unroll
+    for (int r = 0; r < kFitRounds; ++r) {
+      const int64_t i = sp[k].lo + lane + kFitLanes * r;
+      v[k][r] = (live && sp[k].fast && i <= sp[k].last) ? X[i] : T(0);
+    }
+    zc[k] = live ? static_cast<double>(X[(a < b) ? a : sp[k].lo]) : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kFitSegs; ++k) {
+    if (s0 + k >= nseg) break;  // uniform across the wave
+    if (long_list && sp[k].last - sp[k].lo + 1 > kLongKeys) {
+      if (lane == 0) long_list[atomicAdd(&tot->long_segs, 1u)] = LongSeg{slot, s0 + k};
+      continue;
+    }
+    const SegFit f = fit_one<T>(X, sp[k], v[k], zc[k], lane);
+    if (lane == 0) segs[s0 + k] = f;
+  }
+}
+
+int32_t fit_blocks(int32_t nseg) { return (nseg + kFitSegs - 1) / kFitSegs; }
+
+// The queued long segments, one workgroup of kLongBlock lanes at a time each
+// (workgroup x takes entries x, x + gridDim.x, ...).  A long segment holds at
+// least kLongKeys - 1 keys of its own, so the queue has at most
+// total_x / (kLongKeys - 1) entries.
+template <typename T>
+__global__ void __launch_bounds__(kLongBlock) seg_fit_long_kernel(const T* __restrict__ X,
+                                                                  const int32_t* __restrict__ first_all,
+                                                                  SegFit* __restrict__ segs_all, int32_t nseg,
+                                                                  const LearnMeta* __restrict__ lm,
+                                                                  const PlanTotals* __restrict__ tot,
+                                                                  const LongSeg* __restrict__ list) {
+  constexpr int kW = kLongBlock / 64;
+  __shared__ double red[3][kW];
+  __shared__ int32_t redi[2][kW];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t count = tot->long_segs;
+  for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {  // uniform across the workgroup
+    const LongSeg ls = list[e];
+    const LearnMeta L = lm[ls.slot];
+    const T* Xa = X + L.x_off;
+    const int32_t* first = first_all + (int64_t)ls.slot * (nseg + 1);
+    const FitSpan sp = fit_span(first[ls.s], first[ls.s + 1], L.N);
+    const double zc = static_cast<double>(Xa[(sp.a < sp.b) ? sp.a : sp.lo]);
+    FitSums s{0, 0, 0};
+    add_keys<T, kLongBlock>(Xa, sp.a, sp.b, sp.lo, zc, tid, s);
+    wave_sum(s);
+    if (lane == 0) {
+      red[0][w] = s.sz;
+      red[1][w] = s.szz;
+      red[2][w] = s.siz;
+    }
+    __syncthreads();
+    FitSums t{0, 0, 0};
+    for (int ww = 0; ww < kW; ++ww) {
+      t.sz += red[0][ww];
+      t.szz += red[1][ww];
+      t.siz += red[2][ww];
+    }
+    SegFit f = line_fit(sp, zc, t);
+    int32_t dmin = 1 << 30, dmax = -(1 << 30);
+    err_keys<T, kLongBlock>(Xa, sp.lo, sp.last, f, tid, dmin, dmax);
+    wave_minmax(dmin, dmax);
+    if (lane == 0) {
+      redi[0][w] = dmin;
+      redi[1][w] = dmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int ww = 0; ww < kW; ++ww) {
+        dmin = std::min(dmin, redi[0][ww]);
+        dmax = std::max(dmax, redi[1][ww]);
+      }
+      f.dmin = dmin;
+      f.dmax = dmax;
+      segs_all[(int64_t)ls.slot * nseg + ls.s] = f;
+    }
+    __syncthreads();  // red and redi are reused by the next entry
   }
 }
 
@@ -1408,7 +1636,9 @@ __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t 
   constexpr int V = 16 / int(sizeof(T));
   const T* __restrict__ S = pa.Sb;
   const int32_t jlast = (pa.xr + pa.N) / E;  // block holding X_N
-  int32_t jL = (pa.xr + L) / E, jU = (pa.xr + U) / E;
+  // 0 <= L <= U: the divisions are shifts
+  int32_t jL = static_cast<int32_t>(static_cast<uint32_t>(pa.xr + L) / E);
+  int32_t jU = static_cast<int32_t>(static_cast<uint32_t>(pa.xr + U) / E);
   while (jU + 1 > ((jL + 1) & ~(V - 1)) + SE - 1) {
     const int32_t m = jL + ((jU - jL + 1) >> 1);  // jL < m <= jU: S[m] is a value of the array
     const bool c = S[m] <= z;
@@ -1507,9 +1737,8 @@ __global__ void __launch_bounds__(1024) learned_search_kernel(LearnedArgs<T> a) 
   RouterRegs R;
   if constexpr (ROUTE == kRouteTable) {
     if (!a.identity) {
-      stage_bytes(smem + seg_bytes, reinterpret_cast<const unsigned char*>(a.steps), int64_t(a.nseg) * 4);
-      stage_bytes(smem + seg_bytes + int64_t(a.nseg) * 4, reinterpret_cast<const unsigned char*>(a.grid),
-                  (int64_t(4) << a.log2g));
+      stage_words(smem + seg_bytes, a.steps, a.nseg);
+      stage_words(smem + seg_bytes + int64_t(a.nseg) * 4, a.grid, int64_t(1) << a.log2g);
     }
   } else if constexpr (ROUTE == kRouteF16) {
     __shared__ RouterShared16 S;
@@ -1753,7 +1982,8 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
                                                                                    L->identity, L->route, nullptr);
   }
   seg_first_kernel<<<dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s>>>(L->route, n, nseg, L->first);
-  seg_fit_kernel<T><<<dim3(nseg), dim3(kFitLanes), 0, s>>>(X, N, L->first, L->segs, nseg, nullptr, nullptr);
+  seg_fit_kernel<T><<<dim3(fit_blocks(nseg)), dim3(kFitLanes), 0, s>>>(X, N, L->first, L->segs, nseg, nullptr,
+                                                                         nullptr, nullptr);
   DS_HIP_CHECK(hipGetLastError());
   std::vector<SegFit> host(nseg);
   DS_HIP_CHECK(hipMemcpyAsync(host.data(), L->segs, size_t(nseg) * sizeof(SegFit), hipMemcpyDeviceToHost, s));
@@ -1980,11 +2210,9 @@ __global__ void __launch_bounds__(kBatchLearnBlock, 8) batch_learned_search_kern
       stage_bytes(smem, static_cast<const unsigned char*>(b.segs) + (int64_t)slot * b.nseg * kSegFitBytes,
                   int64_t(b.nseg) * kSegFitBytes);
       if (!IDENT) {
-        stage_bytes(smem + int64_t(b.nseg) * kSegFitBytes,
-                    reinterpret_cast<const unsigned char*>(b.steps_tab + (int64_t)slot * b.nseg), int64_t(b.nseg) * 4);
-        stage_bytes(smem + int64_t(b.nseg) * (kSegFitBytes + 4),
-                    reinterpret_cast<const unsigned char*>(b.grid + ((int64_t)slot << b.log2g)),
-                    int64_t(4) << b.log2g);
+        stage_words(smem + int64_t(b.nseg) * kSegFitBytes, b.steps_tab + (int64_t)slot * b.nseg, b.nseg);
+        stage_words(smem + int64_t(b.nseg) * (kSegFitBytes + 4), b.grid + ((int64_t)slot << b.log2g),
+                    int64_t(1) << b.log2g);
       }
       __syncthreads();
       cur = slot;
@@ -2072,8 +2300,8 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
                                                                     b.tot, b.seed, b.steps, 2e-3f);
   DS_HIP_CHECK(hipGetLastError());
   if (b.identity) {
-    route_first_kernel<true><<<dim3(64, K), dim3(256), 0, s>>>(b.steps_tab, b.grid, b.log2g, b.feat, b.nseg, b.first,
-                                                               b.lmeta, b.tot);
+    route_first_kernel<true><<<dim3(kRouteBlocks, K), dim3(kRouteBlock), 0, s>>>(b.steps_tab, b.grid, b.log2g, b.feat,
+                                                                                b.nseg, b.first, b.lmeta, b.tot);
   } else {
     // each trained network compiled to its step table and grid, then the keys routed through them
     // (each model's entries of `first` hold its probes until the keys are routed)
@@ -2083,11 +2311,15 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
     router_steps_kernel<<<dim3((unsigned)((b.nseg + 255) / 256), K), dim3(256), 0, s>>>(b.params, b.nseg, kp, b.first,
                                                                                       b.steps_tab, b.tot);
     router_table_kernel<<<dim3(K), dim3(kTableBlock), 0, s>>>(b.steps_tab, b.nseg, b.log2g, b.grid, b.tot);
-    route_first_kernel<false><<<dim3(64, K), dim3(256), 0, s>>>(b.steps_tab, b.grid, b.log2g, b.feat, b.nseg, b.first,
-                                                                b.lmeta, b.tot);
+    route_first_kernel<false><<<dim3(kRouteBlocks, K), dim3(kRouteBlock), route_first_lds(b.nseg, b.log2g), s>>>(
+        b.steps_tab, b.grid, b.log2g, b.feat, b.nseg, b.first, b.lmeta, b.tot);
   }
-  seg_fit_kernel<T><<<dim3(b.nseg, K), dim3(kFitLanes), 0, s>>>(
-      static_cast<const T*>(b.X), 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot);
+  // the feature buffer is free once the keys are routed: it holds the queue of long segments
+  LongSeg* long_list = reinterpret_cast<LongSeg*>(b.feat);
+  seg_fit_kernel<T><<<dim3(fit_blocks(b.nseg), K), dim3(kFitLanes), 0, s>>>(
+      static_cast<const T*>(b.X), 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot, long_list);
+  seg_fit_long_kernel<T><<<dim3(static_cast<unsigned>(2 * num_cus())), dim3(kLongBlock), 0, s>>>(
+      static_cast<const T*>(b.X), b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot, long_list);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }

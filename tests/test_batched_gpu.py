@@ -495,6 +495,33 @@ def test_batched_learned_block_scan_at_buffer_edges(ds, dtype):
         assert bt.fallbacks() == 0
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batched_learned_segment_counts_off_four(ds, dtype):
+    """Segment counts that are not multiples of 4 (1, 3, 5, 37, 1023): each model's step table
+    and grid then start off a 16-byte boundary in the workspace and in LDS, and the fit kernel's
+    last group of segments is partial.  Exact results without fallback, trained and without
+    network."""
+    rng = np.random.default_rng(37)
+    sizes = [9, 700, 5000, 20_000, 64]
+    arrays = [W.gap_array(n, dtype, rng, x0=rng.uniform(-50, 50)) for n in sizes]
+    x_off = np.concatenate([[0], np.cumsum([a.size for a in arrays])]).astype(np.int64)
+    X = np.concatenate(arrays).astype(dtype)
+    zs = [np.concatenate([a[:8], W.prev_float(a[-8:], dtype), W.uniform_queries(a[0], a[-1], 3000, dtype, rng)])
+          .astype(dtype) for a in arrays]
+    z = np.concatenate(zs)
+    q_off = np.concatenate([[0], np.cumsum([q.size for q in zs])]).astype(np.int64)
+    ref = _oracle_batch(x_off, X, q_off, z)
+    for segs in (1, 3, 5, 37, 1023):
+        for steps in (6, -1):
+            bt = ds.Batch(_dev(x_off), _dev(X), _dev(q_off), _dev(z), learn_segments=segs, learn_steps=steps,
+                          direct_cap_bytes=8)
+            out = bt.run().cpu().numpy()
+            meth, _ = bt.report()
+            assert np.all(meth == ds.METHOD_LEARNED)
+            _assert_same(out, ref)
+            assert bt.fallbacks() == 0
+
+
 def test_full_size_batched_learned_f64_sampled(ds):
     """256 mixture arrays, N_k log-uniform in [2^14, 2^20], 2^28 queries (70 % uniform, 20 % hits,
     10 % nextafter(X_i, -inf)); Direct where its table fits under 64 MB, the learned method elsewhere."""

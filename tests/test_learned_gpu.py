@@ -178,6 +178,24 @@ def test_learned_wide_windows_and_array_ends(ds, dt):
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_learned_segment_counts_off_four(ds, dt):
+    """Segment counts that are not multiples of 4 (1, 3, 5, 37, 1023) place the compiled router's
+    grid, after the step table, off a 16-byte boundary in LDS: exact results without fallback,
+    trained and without network."""
+    rng = np.random.default_rng(19)
+    X = _clustered(20_000, dt, 20_000)
+    z = _queries(X, 40_000, rng)
+    ref = oracle.search(X, z)
+    for segs in (1, 3, 5, 37, 1023):
+        for epochs in (5, -1):
+            idx = ds.build(_dev(X), method="learned", learn_epochs=epochs, learn_segments=segs, seed=8)
+            _assert_same(ds.search(idx, _dev(z)).cpu().numpy(), ref, z)
+            _, fb = idx.learned_model()
+            assert fb == 0
+            idx.destroy()
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_learned_tiny_arrays(ds, dt):
     """N from 1 to 33 (one block of X or a few; the padded tail of X and of the samples is read)."""
     rng = np.random.default_rng(23)
