@@ -46,7 +46,7 @@ constexpr int kMaxGrowthRounds = 4096;
 struct WsLayout {
   size_t meta, chunk_first, tile_off, totals, codes, bits, base, end;
   // learned region (present when nseg > 0)
-  size_t lmeta, params, adam_m, adam_v, steps, grid, segs, first, feat, samples;
+  size_t lmeta, params, adam_m, adam_v, steps, grid, segs, first, longs, samples;
   int64_t words_budget;
   int64_t codes_cap;
   int32_t nseg;
@@ -79,7 +79,7 @@ WsLayout ws_layout(int32_t K, int64_t total_x, int64_t words_budget, int32_t nse
     L.grid = take(size_t(K) * (size_t(4) << batch_grid_log2(nseg)));
     L.segs = take(size_t(K) * size_t(nseg) * kSegFitBytes);
     L.first = take(size_t(K) * size_t(nseg + 1) * 4);
-    L.feat = take(size_t(total_x) * 4);
+    L.longs = take(size_t(total_x / (kFitLongKeys - 1) + 1) * sizeof(LongSeg));
     // first value of every 64-byte block of the packed X (total_x / 8 values of
     // 8 bytes in f64, total_x / 16 of 4 bytes in f32) and two lines of +inf
     L.samples = take(size_t(total_x) + 512);
@@ -1108,7 +1108,7 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.grid = reinterpret_cast<uint32_t*>(ws + L.grid);
   b.segs = ws + L.segs;
   b.first = reinterpret_cast<int32_t*>(ws + L.first);
-  b.feat = reinterpret_cast<float*>(ws + L.feat);
+  b.longs = reinterpret_cast<LongSeg*>(ws + L.longs);
   b.samples = ws + L.samples;
   return b;
 }

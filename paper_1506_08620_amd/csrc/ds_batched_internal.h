@@ -53,6 +53,15 @@ struct alignas(16) LearnMeta {
   int32_t k;   // array index
 };
 
+// A segment whose fit range holds more than kFitLongKeys keys is fitted by a
+// whole workgroup (seg_fit_long_kernel); the build queues it as (model slot,
+// segment).  Such a segment holds at least kFitLongKeys - 1 keys of its own,
+// so a batch of total_x keys queues at most total_x / (kFitLongKeys - 1).
+constexpr int kFitLongKeys = 2048;
+struct LongSeg {
+  int32_t slot, s;
+};
+
 // device pointers of the batched learned method inside the workspace
 struct BatchLearned {
   const void* meta;        // ArrMeta<T>[K]
@@ -78,7 +87,7 @@ struct BatchLearned {
   uint32_t* grid;          // [K][2^log2g] compiled router grid
   void* segs;              // [K][nseg] segment fits
   int32_t* first;          // [K][nseg + 1]
-  float* feat;             // [total_x]
+  LongSeg* longs;          // queue of long segments, total_x / (kFitLongKeys - 1) + 1 entries
   void* samples;           // first value of every 64-byte block of X, then +inf
 };
 

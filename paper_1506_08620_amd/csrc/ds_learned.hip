@@ -399,25 +399,13 @@ __device__ __forceinline__ int32_t grid_segment(float u, const float* steps, con
 // ---------------------------------------------------------------------------
 // build kernels
 
-// Kernels below serve one array, or, when lm is given, every learned array of
-// a batch at once: blockIdx.y (blockIdx.x for the Adam step) selects the
-// model slot, and lm[slot] gives the array's keys and feature constants.
+// Kernels below serve one array, or, when given the batch's totals (and its
+// LearnMeta), every learned array of a batch at once: blockIdx.y (blockIdx.x
+// for the one-workgroup kernels) selects the model slot, and lm[slot] gives the
+// array's keys and feature constants.
 template <typename T>
 __global__ void feature_kernel(const T* __restrict__ X, int64_t n, double X0, double delta, double flo, double fscale,
-                               float* __restrict__ u, const LearnMeta* __restrict__ lm,
-                               const PlanTotals* __restrict__ tot) {
-  if (lm) {
-    const int slot = blockIdx.y;
-    if (slot >= tot->n_learned) return;
-    const LearnMeta L = lm[slot];
-    X += L.x_off;
-    u += L.x_off;
-    n = L.N + 1;
-    X0 = L.X0;
-    delta = L.delta;
-    flo = L.flo;
-    fscale = L.fscale;
-  }
+                               float* __restrict__ u) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     u[i] = feature(static_cast<double>(X[i]), X0, delta, flo, fscale);
 }
@@ -580,34 +568,31 @@ __device__ __forceinline__ void load_w2_rows(const float* sp, float (&w2f)[16], 
 
 // the training sample j of a step: a key drawn by a counter-based hash of
 // (seed, step, j), its feature and its target i / (n - 1)
-__device__ __forceinline__ void draw_sample(const float* feat, int64_t n_keys, uint64_t seed, int64_t step, int64_t j,
-                                            float* u, float* t) {
+__device__ __forceinline__ int64_t draw_index(int64_t n_keys, uint64_t seed, int64_t step, int64_t j) {
   const uint64_t key = seed * 0x9E3779B97F4A7C15ull + static_cast<uint64_t>(step) * 0x100000001B3ull +
                        static_cast<uint64_t>(j);
-  const int64_t idx = static_cast<int64_t>(mix32(key) % static_cast<uint32_t>(n_keys));
+  return static_cast<int64_t>(mix32(key) % static_cast<uint32_t>(n_keys));
+}
+
+__device__ __forceinline__ float key_target(int64_t idx, int64_t n_keys) {
+  return static_cast<float>(static_cast<double>(idx) / static_cast<double>(n_keys - 1));
+}
+
+__device__ __forceinline__ void draw_sample(const float* feat, int64_t n_keys, uint64_t seed, int64_t step, int64_t j,
+                                            float* u, float* t) {
+  const int64_t idx = draw_index(n_keys, seed, step, j);
   *u = feat[idx];
-  *t = static_cast<float>(static_cast<double>(idx) / static_cast<double>(n_keys - 1));
+  *t = key_target(idx, n_keys);
 }
 
 // One training step's gradient over a batch, split over workgroups of
 // kTrainBlock samples: each writes its sum (and its loss) to partial[part];
 // adam_kernel adds the parts in order.  Samples are given (u_in, t_in) or drawn
-// (draw_sample).  With lm, blockIdx.y is a model slot of the batched form.
+// (draw_sample).
 __global__ void __launch_bounds__(kTrainBlock) train_step_kernel(
     const float* __restrict__ params, const float* __restrict__ feat, int64_t n_keys, uint64_t seed, int64_t step,
     int32_t batch, const float* __restrict__ u_in, const float* __restrict__ t_in, float* __restrict__ partial,
-    float* __restrict__ loss_partial, const LearnMeta* __restrict__ lm, const PlanTotals* __restrict__ tot) {
-  if (lm) {
-    const int slot = blockIdx.y;
-    if (slot >= tot->n_learned) return;
-    const LearnMeta L = lm[slot];
-    params += (int64_t)slot * kParams;
-    feat += L.x_off;
-    n_keys = L.N + 1;
-    seed += 0x632BE59BD9B4E019ull * static_cast<uint64_t>(slot + 1);
-    partial += (int64_t)slot * gridDim.x * kParams;
-    loss_partial += (int64_t)slot * gridDim.x;
-  }
+    float* __restrict__ loss_partial) {
   constexpr int kWaves = kTrainBlock / 64;
   __shared__ float sp[kParams];
   __shared__ float tileA[kWaves][64][kLd];  // da2, then h2
@@ -668,14 +653,17 @@ __host__ __device__ __forceinline__ float train_rate(float lr, int64_t st, int64
 // model of learned slot k for every step (kBatchLearnSamples samples a step, in
 // kBatchTrainPasses passes of its kBatchTrainBlock lanes), sums the gradient of
 // its waves and passes in a fixed order, and applies the Adam step itself; the
-// parameters stay in LDS between steps.  No workgroup waits for another.
+// parameters stay in LDS between steps.  No workgroup waits for another.  The
+// feature of each drawn key is computed from the key (the same function as
+// feature_kernel's).
 constexpr int kBatchTrainBlock = 512;
 constexpr int kBatchTrainPasses = kBatchLearnSamples / kBatchTrainBlock;
 
+template <typename T>
 __global__ void __launch_bounds__(kBatchTrainBlock) batched_train_kernel(float* __restrict__ params,
                                                                          float* __restrict__ adam_m,
                                                                          float* __restrict__ adam_v,
-                                                                         const float* __restrict__ feat_all,
+                                                                         const T* __restrict__ X,
                                                                          const LearnMeta* __restrict__ lm,
                                                                          const PlanTotals* __restrict__ tot,
                                                                          uint64_t seed0, int32_t steps, float lr) {
@@ -688,7 +676,7 @@ __global__ void __launch_bounds__(kBatchTrainBlock) batched_train_kernel(float* 
   __shared__ float svec[kWaves][64][3];
   static_assert(kWaves * (kParams + 1) <= kWaves * 64 * kLd, "reduction fits the tile");
   const LearnMeta L = lm[slot];
-  const float* feat = feat_all + L.x_off;
+  const T* Xa = X + L.x_off;
   const int64_t n_keys = int64_t(L.N) + 1;
   const uint64_t seed = seed0 + 0x632BE59BD9B4E019ull * static_cast<uint64_t>(slot + 1);
   float* p = params + (int64_t)slot * kParams;
@@ -704,7 +692,9 @@ __global__ void __launch_bounds__(kBatchTrainBlock) batched_train_kernel(float* 
     GradAcc acc{};
     for (int pass = 0; pass < kBatchTrainPasses; ++pass) {
       auto sample = [&](int q, float* u, float* t) {
-        draw_sample(feat, n_keys, seed, st, int64_t(pass) * kBatchTrainBlock + w * 64 + q, u, t);
+        const int64_t idx = draw_index(n_keys, seed, st, int64_t(pass) * kBatchTrainBlock + w * 64 + q);
+        *u = feature(static_cast<double>(Xa[idx]), L.X0, L.delta, L.flo, L.fscale);
+        *t = key_target(idx, n_keys);
         return true;
       };
       wave_grad(sp, w2f, w2b, tileA[w], tileB[w], svec[w], inv_b, sample, acc);
@@ -723,16 +713,7 @@ __global__ void __launch_bounds__(kBatchTrainBlock) batched_train_kernel(float* 
 // onto w >= 0.
 __global__ void __launch_bounds__(1024) adam_kernel(float* __restrict__ params, float* __restrict__ m,
                                                     float* __restrict__ v, const float* __restrict__ partial,
-                                                    int32_t n_parts, float lr, int64_t t, float* __restrict__ grad_out,
-                                                    const PlanTotals* __restrict__ tot) {
-  if (tot) {
-    const int slot = blockIdx.x;
-    if (slot >= tot->n_learned) return;
-    params += (int64_t)slot * kParams;
-    m += (int64_t)slot * kParams;
-    v += (int64_t)slot * kParams;
-    partial += (int64_t)slot * n_parts * kParams;
-  }
+                                                    int32_t n_parts, float lr, int64_t t, float* __restrict__ grad_out) {
   for (int k = threadIdx.x; k < kParams; k += blockDim.x) {
     // the parts in order, eight loads in flight at a time
     float g = 0.0f;
@@ -959,15 +940,16 @@ __device__ __forceinline__ void stage_words(void* dst, const void* src, int64_t 
   for (; k < n; k += B) d[k] = s[k];
 }
 
-// The batched form of route_keys_kernel + seg_first_kernel in one pass, with
-// no per-key route array: each wave takes a contiguous range of at least 8
+// The batched form of feature_kernel + route_keys_kernel + seg_first_kernel in
+// one pass, with no per-key feature or route array: each wave takes a contiguous range of at least 8
 // of the array's 64-key groups, and each key i routed to segment r with its
 // predecessor in segment p writes first[s] = i for s in (p, r]; the last key
 // also writes first[s] = n for s above its segment.  A lane's predecessor is
 // the lane before it or, for lane 0, the last key of the previous group (the
-// wave routes the key before its range first).  The features of the next
+// wave routes the key before its range first).  The keys of the next
 // kRouteGroups groups are loaded before the current ones are routed, so each
-// lane keeps up to 2 kRouteGroups loads in flight.  The compiled router's step
+// lane keeps up to 2 kRouteGroups loads in flight; each key's feature is
+// computed as feature_kernel computes it.  The compiled router's step
 // table and grid are staged in LDS first (a few dozen KiB at most), and each
 // model's keys are shared by kRouteBlocks workgroups of 1024 lanes.  Routing
 // is the same function as route_keys_table_kernel's.
@@ -978,10 +960,10 @@ constexpr int kRouteGroups = 4;
 // dynamic LDS of route_first_kernel<false>: the step table, then the grid
 int64_t route_first_lds(int32_t nseg, int32_t log2g) { return int64_t(nseg) * 4 + (int64_t(4) << log2g); }
 
-template <bool IDENT>
+template <bool IDENT, typename T>
 __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* __restrict__ steps_all,
                                                                   const uint32_t* __restrict__ grid_all, int32_t log2g,
-                                                                  const float* __restrict__ feat, int32_t nseg,
+                                                                  const T* __restrict__ X, int32_t nseg,
                                                                   int32_t* __restrict__ first,
                                                                   const LearnMeta* __restrict__ lm,
                                                                   const PlanTotals* __restrict__ tot) {
@@ -996,7 +978,7 @@ __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* _
     __syncthreads();
   }
   const LearnMeta L = lm[slot];
-  feat += L.x_off;
+  X += L.x_off;
   first += (int64_t)slot * (nseg + 1);
   const int64_t n = int64_t(L.N) + 1;  // keys
   const int64_t ngroups = (n + 63) / 64;
@@ -1007,25 +989,26 @@ __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* _
   if (g0 >= g1) return;  // uniform across the wave; no barrier below
   const int lane = threadIdx.x & 63;
   auto segment = [&](float u) { return IDENT ? segment_of(u, nseg) : grid_segment(u, steps, grid, log2g); };
-  auto feature_at = [&](int64_t i) { return i < n ? feat[i] : 1.0f; };
+  auto feat = [&](T x) { return feature(static_cast<double>(x), L.X0, L.delta, L.flo, L.fscale); };
+  auto key_at = [&](int64_t i) { return X[std::min(i, n - 1)]; };  // lanes past the last key read it again
   // the key before the range
-  int32_t carry = (g0 > 0) ? segment(feat[g0 * 64 - 1]) : -1;
-  float un[kRouteGroups];
+  int32_t carry = (g0 > 0) ? segment(feat(X[g0 * 64 - 1])) : -1;
+  T xn[kRouteGroups];
 #pragma unroll
-  for (int k = 0; k < kRouteGroups; ++k) un[k] = feature_at((g0 + k) * 64 + lane);
+  for (int k = 0; k < kRouteGroups; ++k) xn[k] = key_at((g0 + k) * 64 + lane);
   for (int64_t grp = g0; grp < g1; grp += kRouteGroups) {
-    float u[kRouteGroups];
+    T x[kRouteGroups];
 #pragma unroll
-    for (int k = 0; k < kRouteGroups; ++k) u[k] = un[k];
+    for (int k = 0; k < kRouteGroups; ++k) x[k] = xn[k];
     if (grp + kRouteGroups < g1) {
 #pragma unroll
-      for (int k = 0; k < kRouteGroups; ++k) un[k] = feature_at((grp + kRouteGroups + k) * 64 + lane);
+      for (int k = 0; k < kRouteGroups; ++k) xn[k] = key_at((grp + kRouteGroups + k) * 64 + lane);
     }
 #pragma unroll
     for (int k = 0; k < kRouteGroups; ++k) {
       if (grp + k >= g1) break;  // uniform across the wave
       const int64_t i = (grp + k) * 64 + lane;
-      const int32_t r = segment(u[k]);
+      const int32_t r = segment(feat(x[k]));
       int32_t p = __shfl_up(r, 1, 64);
       if (lane == 0) p = carry;
       if (i < n) {
@@ -1049,7 +1032,7 @@ __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* _
 // the segments are empty or hold one key), so a segment's butterflies span
 // only the lanes that hold its keys, and one key needs no sums.  (Four
 // segments per wave, their loads issued together, took 1.06x as long.)  In the
-// batched form, a segment whose fit range exceeds kLongKeys keys is queued for
+// batched form, a segment whose fit range exceeds kFitLongKeys keys is queued for
 // seg_fit_long_kernel instead, which gives it a workgroup of kLongBlock lanes:
 // segment sizes are very uneven (clusters route tens of thousands of keys to
 // one segment), and a single wave walking such a segment set the whole
@@ -1061,13 +1044,7 @@ constexpr int kFitLanes = 64;
 constexpr int kFitRounds = 2;
 constexpr int kFitUnroll = 8;
 constexpr int kFitSegs = 1;
-constexpr int kLongKeys = 2048;
 constexpr int kLongBlock = 1024;
-
-// a queued long segment: model slot and segment
-struct LongSeg {
-  int32_t slot, s;
-};
 
 // the keys [a, b) of a segment and the range [lo, last] of its error pass
 struct FitSpan {
@@ -1282,7 +1259,7 @@ __global__ void __launch_bounds__(kFitLanes, 8) seg_fit_kernel(const T* __restri
 #pragma unroll
   for (int k = 0; k < kFitSegs; ++k) {
     if (s0 + k >= nseg) break;  // uniform across the wave
-    if (long_list && sp[k].last - sp[k].lo + 1 > kLongKeys) {
+    if (long_list && sp[k].last - sp[k].lo + 1 > kFitLongKeys) {
       if (lane == 0) long_list[atomicAdd(&tot->long_segs, 1u)] = LongSeg{slot, s0 + k};
       continue;
     }
@@ -1294,9 +1271,7 @@ __global__ void __launch_bounds__(kFitLanes, 8) seg_fit_kernel(const T* __restri
 int32_t fit_blocks(int32_t nseg) { return (nseg + kFitSegs - 1) / kFitSegs; }
 
 // The queued long segments, one workgroup of kLongBlock lanes at a time each
-// (workgroup x takes entries x, x + gridDim.x, ...).  A long segment holds at
-// least kLongKeys - 1 keys of its own, so the queue has at most
-// total_x / (kLongKeys - 1) entries.
+// (workgroup x takes entries x, x + gridDim.x, ...).
 template <typename T>
 __global__ void __launch_bounds__(kLongBlock) seg_fit_long_kernel(const T* __restrict__ X,
                                                                   const int32_t* __restrict__ first_all,
@@ -1941,17 +1916,15 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
   const unsigned long long zero = 0;
   DS_HIP_CHECK(hipMemcpyAsync(L->fallbacks, &zero, 8, hipMemcpyHostToDevice, s));
   feature_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, n, static_cast<double>(ends[0]),
-                                                                             L->delta, L->flo, L->fscale, L->feat,
-                                                                             nullptr, nullptr);
+                                                                             L->delta, L->flo, L->fscale, L->feat);
   DS_HIP_CHECK(hipGetLastError());
   // training: epochs passes of n / batch steps, cosine-decayed step size
   const int64_t steps = L->identity ? 0 : std::max<int64_t>(1, int64_t(epochs) * ((n + batch - 1) / batch));
   for (int64_t st = 0; st < steps; ++st) {
     train_step_kernel<<<dim3(n_parts), dim3(kTrainBlock), 0, s>>>(L->params, L->feat, n, o->seed, st, batch, nullptr,
-                                                                  nullptr, L->partial, L->loss_partial, nullptr,
-                                                                  nullptr);
+                                                                  nullptr, L->partial, L->loss_partial);
     adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(L->params, L->adam_m, L->adam_v, L->partial, n_parts,
-                                               train_rate(lr, st, steps), st + 1, nullptr, nullptr);
+                                               train_rate(lr, st, steps), st + 1, nullptr);
   }
   DS_HIP_CHECK(hipGetLastError());
   if (steps > 0) {
@@ -2290,18 +2263,16 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
     batch_samples_kernel<T><<<dim3(1024), dim3(256), 0, s>>>(static_cast<const T*>(b.X), b.total_x,
                                                              static_cast<T*>(b.samples), nS);
   }
+  const T* X = static_cast<const T*>(b.X);
   if (!b.identity) init_params_kernel<<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, b.tot, b.seed);
-  feature_kernel<T><<<dim3(64, K), dim3(256), 0, s>>>(static_cast<const T*>(b.X), 0, 0, 0, 0, 0, b.feat, b.lmeta,
-                                                       b.tot);
-  DS_HIP_CHECK(hipGetLastError());
   // every step of every model's training in one launch (one workgroup per model)
   if (b.steps > 0)
-    batched_train_kernel<<<dim3(K), dim3(kBatchTrainBlock), 0, s>>>(b.params, b.adam_m, b.adam_v, b.feat, b.lmeta,
-                                                                    b.tot, b.seed, b.steps, 2e-3f);
+    batched_train_kernel<T><<<dim3(K), dim3(kBatchTrainBlock), 0, s>>>(b.params, b.adam_m, b.adam_v, X, b.lmeta,
+                                                                       b.tot, b.seed, b.steps, 2e-3f);
   DS_HIP_CHECK(hipGetLastError());
   if (b.identity) {
-    route_first_kernel<true><<<dim3(kRouteBlocks, K), dim3(kRouteBlock), 0, s>>>(b.steps_tab, b.grid, b.log2g, b.feat,
-                                                                                b.nseg, b.first, b.lmeta, b.tot);
+    route_first_kernel<true, T><<<dim3(kRouteBlocks, K), dim3(kRouteBlock), 0, s>>>(b.steps_tab, b.grid, b.log2g, X,
+                                                                                   b.nseg, b.first, b.lmeta, b.tot);
   } else {
     // each trained network compiled to its step table and grid, then the keys routed through them
     // (each model's entries of `first` hold its probes until the keys are routed)
@@ -2311,15 +2282,13 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
     router_steps_kernel<<<dim3((unsigned)((b.nseg + 255) / 256), K), dim3(256), 0, s>>>(b.params, b.nseg, kp, b.first,
                                                                                       b.steps_tab, b.tot);
     router_table_kernel<<<dim3(K), dim3(kTableBlock), 0, s>>>(b.steps_tab, b.nseg, b.log2g, b.grid, b.tot);
-    route_first_kernel<false><<<dim3(kRouteBlocks, K), dim3(kRouteBlock), route_first_lds(b.nseg, b.log2g), s>>>(
-        b.steps_tab, b.grid, b.log2g, b.feat, b.nseg, b.first, b.lmeta, b.tot);
+    route_first_kernel<false, T><<<dim3(kRouteBlocks, K), dim3(kRouteBlock), route_first_lds(b.nseg, b.log2g), s>>>(
+        b.steps_tab, b.grid, b.log2g, X, b.nseg, b.first, b.lmeta, b.tot);
   }
-  // the feature buffer is free once the keys are routed: it holds the queue of long segments
-  LongSeg* long_list = reinterpret_cast<LongSeg*>(b.feat);
   seg_fit_kernel<T><<<dim3(fit_blocks(b.nseg), K), dim3(kFitLanes), 0, s>>>(
-      static_cast<const T*>(b.X), 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot, long_list);
+      X, 0, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot, b.longs);
   seg_fit_long_kernel<T><<<dim3(static_cast<unsigned>(2 * num_cus())), dim3(kLongBlock), 0, s>>>(
-      static_cast<const T*>(b.X), b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot, long_list);
+      X, b.first, static_cast<SegFit*>(b.segs), b.nseg, b.lmeta, b.tot, b.longs);
   DS_HIP_CHECK(hipGetLastError());
   return DS_OK;
 }
@@ -2399,9 +2368,8 @@ ds_status ds_learned_grad(const float* params_dev, const float* u_dev, const flo
     return DS_ERR_OOM;
   }
   ds::train_step_kernel<<<dim3(n_parts), dim3(ds::kTrainBlock), 0, s>>>(params_dev, nullptr, 1, 0, 0, batch, u_dev,
-                                                                        t_dev, partial, lp, nullptr, nullptr);
-  ds::adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(nullptr, nullptr, nullptr, partial, n_parts, 0, 1, grad_dev,
-                                                 nullptr);
+                                                                        t_dev, partial, lp);
+  ds::adam_kernel<<<dim3(1), dim3(1024), 0, s>>>(nullptr, nullptr, nullptr, partial, n_parts, 0, 1, grad_dev);
   if (loss_dev) ds::sum_kernel<<<1, 64, 0, s>>>(lp, n_parts, loss_dev);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
