@@ -686,15 +686,33 @@ __global__ void __launch_bounds__(kBatchTrainBlock) batched_train_kernel(float* 
   for (int k = tid; k < kParams; k += kBatchTrainBlock) sp[k] = p[k];
   __syncthreads();
   const float inv_b = 1.0f / static_cast<float>(kBatchLearnSamples);
+  // The draws do not depend on the parameters: the keys of the next pass
+  // (lane sample q = 32 p + lane % 32, p = 0, 1) are loaded while this one is
+  // worked on, so the key reads do not wait between the passes' barriers.
+  const int n32 = tid & 31;
+  int64_t idx_next[2];
+  T key_next[2];
+  auto fetch = [&](int32_t st, int pass) {
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      idx_next[pp] = draw_index(n_keys, seed, st, int64_t(pass) * kBatchTrainBlock + w * 64 + 32 * pp + n32);
+      key_next[pp] = Xa[idx_next[pp]];
+    }
+  };
+  if (steps > 0) fetch(0, 0);
   for (int32_t st = 0; st < steps; ++st) {
     float w2f[16], w2b[16];
     load_w2_rows(sp, w2f, w2b);
     GradAcc acc{};
     for (int pass = 0; pass < kBatchTrainPasses; ++pass) {
+      const int64_t idx[2] = {idx_next[0], idx_next[1]};
+      const T key[2] = {key_next[0], key_next[1]};
+      if (pass + 1 < kBatchTrainPasses) fetch(st, pass + 1);
+      else if (st + 1 < steps) fetch(st + 1, 0);
       auto sample = [&](int q, float* u, float* t) {
-        const int64_t idx = draw_index(n_keys, seed, st, int64_t(pass) * kBatchTrainBlock + w * 64 + q);
-        *u = feature(static_cast<double>(Xa[idx]), L.X0, L.delta, L.flo, L.fscale);
-        *t = key_target(idx, n_keys);
+        const int pp = q >= 32 ? 1 : 0;
+        *u = feature(static_cast<double>(key[pp]), L.X0, L.delta, L.flo, L.fscale);
+        *t = key_target(idx[pp], n_keys);
         return true;
       };
       wave_grad(sp, w2f, w2b, tileA[w], tileB[w], svec[w], inv_b, sample, acc);
