@@ -57,7 +57,7 @@ struct alignas(16) LearnMeta {
 // whole workgroup (seg_fit_long_kernel); the build queues it as (model slot,
 // segment).  Such a segment holds at least kFitLongKeys - 1 keys of its own,
 // so a batch of total_x keys queues at most total_x / (kFitLongKeys - 1).
-constexpr int kFitLongKeys = 2048;
+constexpr int kFitLongKeys = 8192;
 struct LongSeg {
   int32_t slot, s;
 };

@@ -1054,8 +1054,9 @@ __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* _
 // seg_fit_long_kernel instead, which gives it a workgroup of kLongBlock lanes:
 // segment sizes are very uneven (clusters route tens of thousands of keys to
 // one segment), and a single wave walking such a segment set the whole
-// launch's time (374 us against 221 + 163 for the two kernels, for 2048
-// segments of each of the 256 mixture arrays).  Reductions run in a fixed
+// launch's time (for 2048 segments of each of the 256 mixture arrays: 374 us
+// with no queue, 249 + 70 us for the two kernels at 8192 keys, 221 + 165 at
+// 2048, 277 + 52 at 16384).  Reductions run in a fixed
 // order (with L lanes, lane t holds a + t, a + t + L, ...; a butterfly over
 // the wave, then the waves in order), so the fits do not depend on timing.
 constexpr int kFitLanes = 64;
