@@ -239,7 +239,7 @@ template <typename T, bool VECLOAD, class Vis>
 __device__ __forceinline__ ChunkArrays scan_pairs(const int64_t* __restrict__ x_off, int32_t K,
                                                   const int32_t* __restrict__ chunk_first, const T* __restrict__ X,
                                                   int64_t total_x, Vis& vis, unsigned long long* g_slots = nullptr,
-                                                  uint32_t* f_slots = nullptr) {
+                                                  uint32_t* f_slots = nullptr, T* __restrict__ samples = nullptr) {
   constexpr int V = 16 / sizeof(T);
   constexpr int U = static_cast<int>(kScanChunk / (kScanBlock * V));
   const int64_t c0 = int64_t(blockIdx.x) * kScanChunk;
@@ -256,6 +256,16 @@ __device__ __forceinline__ ChunkArrays scan_pairs(const int64_t* __restrict__ x_
     const int64_t g0 = c0 + int64_t(u * kScanBlock + threadIdx.x) * V;
     load_group<T, VECLOAD>(X, g0, total_x, v[u]);
     nx[u] = (g0 + V < total_x) ? X[g0 + V] : T(0);
+  }
+  if (samples) {
+    // the first value of each 64-byte block of the packed buffer (the learned
+    // search's samples): the lane whose group starts the block holds it
+    constexpr int64_t E = 64 / sizeof(T);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t g0 = c0 + int64_t(u * kScanBlock + threadIdx.x) * V;
+      if (g0 % E == 0 && g0 < c1) samples[g0 / E] = v[u][0];
+    }
   }
   if constexpr (!Vis::kLookFirst) ca = chunk_arrays(x_off, K, chunk_first, total_x);
   vis.prepare(ca, g_slots, f_slots);
@@ -342,11 +352,18 @@ template <typename T, bool VECLOAD>
 __global__ void __launch_bounds__(kScanBlock) gaps_kernel(const int64_t* __restrict__ x_off, int32_t K,
                                                           const int32_t* __restrict__ chunk_first,
                                                           const T* __restrict__ Xp, int64_t total_x,
-                                                          ArrMeta<T>* __restrict__ meta) {
+                                                          ArrMeta<T>* __restrict__ meta, T* __restrict__ samples) {
   __shared__ unsigned long long s_g[kScanSlots];
   __shared__ uint32_t s_f[kScanSlots];
+  if (samples && blockIdx.x == gridDim.x - 1) {
+    // after the last block's sample: two blocks' worth of +inf, which the
+    // learned search may read past the buffer's end
+    constexpr int64_t E = 64 / sizeof(T);
+    const int64_t n_full = (total_x + E - 1) / E;
+    if (threadIdx.x < 2 * E) samples[n_full + threadIdx.x] = std::numeric_limits<T>::infinity();
+  }
   GapVis<T> vis{meta};
-  const ChunkArrays ca = scan_pairs<T, VECLOAD>(x_off, K, chunk_first, Xp, total_x, vis, s_g, s_f);
+  const ChunkArrays ca = scan_pairs<T, VECLOAD>(x_off, K, chunk_first, Xp, total_x, vis, s_g, s_f, samples);
   if (ca.one) {
     // the whole chunk is one array: one atomic per wave
     for (int off = 32; off > 0; off >>= 1) {
@@ -547,9 +564,11 @@ __global__ void __launch_bounds__(kFinishBlock) finish_kernel(const T* __restric
   }
 }
 
+// samples: where the learned search's samples go (the first value of each
+// 64-byte block of the packed keys, then 2 x 64 / sizeof(T) of +inf), or null
 template <typename T, int FORM>
 ds_status launch_build(const ds_batch_desc* d, ArrMeta<T>* meta, int32_t* chunk_first, int64_t cap_cells,
-                       hipStream_t s) {
+                       T* samples, hipStream_t s) {
   const int32_t K = d->num_arrays;
   const T* X = static_cast<const T*>(d->X_dev);
   const dim3 per_array((K + kScanBlock - 1) / kScanBlock);
@@ -559,9 +578,11 @@ ds_status launch_build(const ds_batch_desc* d, ArrMeta<T>* meta, int32_t* chunk_
   const bool vec = (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
   if (chunks.x > 0) {
     if (vec)
-      gaps_kernel<T, true><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X, d->total_x, meta);
+      gaps_kernel<T, true><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X, d->total_x, meta,
+                                                               samples);
     else
-      gaps_kernel<T, false><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X, d->total_x, meta);
+      gaps_kernel<T, false><<<chunks, dim3(kScanBlock), 0, s>>>(d->x_off_dev, K, chunk_first, X, d->total_x, meta,
+                                                                samples);
     DS_HIP_CHECK(hipGetLastError());
   }
   start_kernel<T, FORM><<<per_array, dim3(kScanBlock), 0, s>>>(K, cap_cells, meta);
@@ -1171,7 +1192,8 @@ ds_status run_batched(const ds_batch_desc* d, hipStream_t s) {
   const int64_t tile = tile_of(d);
   auto* meta = reinterpret_cast<ArrMeta<T>*>(ws + L.meta);
   const int64_t cap_cells = d->direct_cap_bytes > 0 ? d->direct_cap_bytes / 4 : 0;
-  ds_status st = launch_build<T, FORM>(d, meta, reinterpret_cast<int32_t*>(ws + L.chunk_first), cap_cells, s);
+  ds_status st = launch_build<T, FORM>(d, meta, reinterpret_cast<int32_t*>(ws + L.chunk_first), cap_cells,
+                                       L.nseg > 0 ? reinterpret_cast<T*>(ws + L.samples) : nullptr, s);
   if (st != DS_OK) return st;
   st = launch_plan<T>(d, L, ws, tile, s);
   if (st != DS_OK) return st;

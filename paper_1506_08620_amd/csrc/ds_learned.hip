@@ -1686,14 +1686,6 @@ __device__ __forceinline__ int32_t sample_search_packed(T z, int32_t L, int32_t 
   return k0 + e_lo + c2 - 1 - pa.xr;
 }
 
-// Samples of the packed buffer: S[J] = Xp[E J] for E J < total_x, +inf beyond.
-template <typename T>
-__global__ void batch_samples_kernel(const T* __restrict__ Xp, int64_t total_x, T* __restrict__ S, int64_t nS) {
-  constexpr int E = 64 / int(sizeof(T));
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nS; j += (int64_t)gridDim.x * blockDim.x)
-    S[j] = (j * E < total_x) ? Xp[j * E] : std::numeric_limits<T>::infinity();
-}
-
 // Index of z by the classic binary search over the whole array, for a query
 // whose window search could not certify its result (counted).
 template <typename T>
@@ -2276,12 +2268,7 @@ __global__ void __launch_bounds__(kBatchLearnBlock, 8) batch_learned_search_kern
 template <typename T>
 ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
   const int K = b.K;
-  {
-    constexpr int64_t E = 64 / int64_t(sizeof(T));
-    const int64_t nS = (b.total_x + E - 1) / E + 2 * E;  // fits the workspace's total_x + 512 bytes
-    batch_samples_kernel<T><<<dim3(1024), dim3(256), 0, s>>>(static_cast<const T*>(b.X), b.total_x,
-                                                             static_cast<T*>(b.samples), nS);
-  }
+  // the samples were written by the build's pass over the keys (gaps_kernel)
   const T* X = static_cast<const T*>(b.X);
   if (!b.identity) init_params_kernel<<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, b.tot, b.seed);
   // every step of every model's training in one launch (one workgroup per model)
