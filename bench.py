@@ -588,7 +588,7 @@ def bench_batched_learned(ds, W, dev, stream, reps):
     x_off, X, q_off = (torch.from_numpy(a).to(dev) for a in (b.x_off, b.X, b.q_off))
     total_q = int(b.q_off[-1])
     res = dict(arrays=b.num_arrays, total_x=int(b.x_off[-1]), total_q=total_q,
-               note="end to end: device build, training of every learned model (10 steps, one launch), "
+               note="end to end: device build, training of every learned model (2 steps, one launch), "
                     "router compilation, fits and search")
     ref = None
     # the trained routers, and the same models with the router replaced by the feature (no network)

@@ -422,8 +422,9 @@ typedef struct ds_batch_desc {
                                  table room use the learned method with this many segments per array
                                  (the workspace must be sized with the same value); 0: binary search */
   int32_t learn_steps;        /* learned: training steps of every model (2048 samples per array and step,
-                                 all steps of all models in one launch); 0 = 10; -1 = no network: the
-                                 segments split the feature evenly (the ablation of the router) */
+                                 all steps of all models in one launch), from the keys' quantile CDF as
+                                 the starting network; 0 = 2; -1 = no network: the segments split the
+                                 feature evenly (the ablation of the router) */
   int32_t reserved_;
   int64_t direct_cap_bytes;   /* per-array cap on the Direct table (4 bytes per grid cell); 0 = none */
 } ds_batch_desc;

@@ -1113,7 +1113,7 @@ BatchLearned learned_of(const ds_batch_desc* d, const WsLayout& L, unsigned char
   b.K = d->num_arrays;
   b.nseg = L.nseg;
   b.identity = d->learn_steps < 0 ? 1 : 0;
-  b.steps = d->learn_steps > 0 ? d->learn_steps : (d->learn_steps == 0 ? 10 : 0);
+  b.steps = d->learn_steps > 0 ? d->learn_steps : (d->learn_steps == 0 ? kBatchLearnStepsDefault : 0);
   b.log2g = batch_grid_log2(L.nseg);
   b.seed = 0x1506ull;
   b.tile = tile_of(d);

@@ -12,6 +12,11 @@ constexpr int kNumQueues = 8;        // one tile queue per XCD
 constexpr int kRouterParams = 1153;  // 1 -> 32 -> 32 -> 1 router
 constexpr int kSegFitBytes = 32;
 constexpr int kBatchLearnSamples = 2048;  // training samples per array and step
+// Training steps of a batched model when none are asked for.  From the quantile
+// starting point (init_params_kernel) more steps do not narrow the windows:
+// on the 256-array mixture the search takes the same time after 1 to 40
+// steps, and each step costs about 44 us for 256 models.
+constexpr int kBatchLearnStepsDefault = 2;
 constexpr int kBatchMaxSegments = 4096;   // the search stages a model's fits, steps and grid in LDS
 
 template <typename T>

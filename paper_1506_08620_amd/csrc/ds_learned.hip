@@ -24,7 +24,6 @@
 #include <chrono>
 #include <cmath>
 #include <limits>
-#include <random>
 #include <type_traits>
 #include <vector>
 
@@ -1826,6 +1825,56 @@ int64_t learned_model_bytes(const LearnedModel* L) {
          (table ? (int64_t(4) << L->log2g) : 0);
 }
 
+// The starting point of a model: the network is set to the piecewise-linear
+// CDF of the array's keys at their 32-quantiles.  With u_k the feature of the
+// key at position k N / 32 (k = 0 .. 32), layer-1 unit k rises from 0 to 1
+// over [u_k, u_(k+1)], layer 2 passes the units through (identity), and the
+// output averages them, so y(u_k) = k / 32.  Tight clusters of keys get ramps
+// (and so segments) of their own from the start, which training from a
+// generic starting point (ramps spread evenly over u) does not achieve in the
+// steps the build can afford.  Every weight is >= 0: the network is monotone.
+// Adam's moments start at zero.  One workgroup of 64 lanes per model: the
+// single array's (lm null), or learned slot blockIdx.x of a batch.
+template <typename T>
+__global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ params, float* __restrict__ m,
+                                                         float* __restrict__ v, const T* __restrict__ X, int64_t N,
+                                                         double X0, double delta, double flo, double fscale,
+                                                         const LearnMeta* __restrict__ lm,
+                                                         const PlanTotals* __restrict__ tot) {
+  if (lm) {
+    const int slot = blockIdx.x;
+    if (slot >= tot->n_learned) return;
+    const LearnMeta L = lm[slot];
+    X += L.x_off;
+    N = L.N;
+    X0 = L.X0;
+    delta = L.delta;
+    flo = L.flo;
+    fscale = L.fscale;
+    params += (int64_t)slot * kParams;
+    m += (int64_t)slot * kParams;
+    v += (int64_t)slot * kParams;
+  }
+  const int t = threadIdx.x;
+  // the quantile features, u_t for lane t <= kHid
+  const int64_t pos = (int64_t(std::min(t, kHid)) * N + kHid / 2) / kHid;
+  const float u = feature(static_cast<double>(X[pos]), X0, delta, flo, fscale);
+  const float u_next = __shfl_down(u, 1, 64);
+  if (t < kHid) {
+    const float w = 1.0f / std::fmax(u_next - u, 0x1p-24f);
+    params[oW1 + t] = w;
+    params[oB1 + t] = -u * w;
+    for (int k = 0; k < kHid; ++k) params[oW2 + t * kHid + k] = (k == t) ? 1.0f : 0.0f;
+    params[oB2 + t] = 0.0f;
+    params[oW3 + t] = 1.0f / kHid;
+  }
+  if (t == 0) params[oB3] = 0.0f;
+  for (int k = t; k < kParams; k += blockDim.x) {
+    m[k] = 0.0f;
+    v[k] = 0.0f;
+  }
+}
+
 template <typename T>
 ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s) {
   LearnedModel* L = new (std::nothrow) LearnedModel();
@@ -1898,32 +1947,11 @@ ds_status learned_build_typed(ds_index* h, const ds_build_opts* o, hipStream_t s
       hipMalloc(&L->grid, size_t(4) << kMaxLog2Grid) != hipSuccess ||
       hipMalloc(&L->fallbacks, 8) != hipSuccess)
     return DS_ERR_OOM;
-  // initial weights: layer-1 ramps spread over [0, 1], layer 2 averaging them,
-  // output the mean of layer 2 (so y(u) starts as a smooth increasing curve)
-  std::vector<float> p0(kParams, 0.0f);
-  std::mt19937_64 rng(o->seed ^ 0x5EEDull);
-  std::uniform_real_distribution<float> U(0.0f, 1.0f);
-  for (int k = 0; k < kHid; ++k) {
-    const float c = (k + 0.5f) / kHid;
-    const float w = 4.0f + 4.0f * U(rng);
-    p0[oW1 + k] = w;
-    p0[oB1 + k] = 0.5f - w * c;
-  }
-  for (int j = 0; j < kHid; ++j) {
-    float sum = 0.0f;
-    for (int k = 0; k < kHid; ++k) {
-      const float w = (0.5f + U(rng)) / kHid;
-      p0[oW2 + j * kHid + k] = w;
-      sum += w;
-    }
-    p0[oB2 + j] = 0.5f - 0.5f * sum;
-    p0[oW3 + j] = 1.0f / kHid;
-  }
-  p0[oB3] = 0.0f;
-  DS_HIP_CHECK(hipMemcpyAsync(L->params, p0.data(), kParams * 4, hipMemcpyHostToDevice, s));
-  std::vector<float> zeros(kParams, 0.0f);
-  DS_HIP_CHECK(hipMemcpyAsync(L->adam_m, zeros.data(), kParams * 4, hipMemcpyHostToDevice, s));
-  DS_HIP_CHECK(hipMemcpyAsync(L->adam_v, zeros.data(), kParams * 4, hipMemcpyHostToDevice, s));
+  // the starting point: the keys' piecewise-linear CDF at their 32-quantiles
+  init_params_kernel<T><<<dim3(1), dim3(64), 0, s>>>(L->params, L->adam_m, L->adam_v, X, n - 1,
+                                                     static_cast<double>(ends[0]), L->delta, L->flo, L->fscale,
+                                                     nullptr, nullptr);
+  DS_HIP_CHECK(hipGetLastError());
   const unsigned long long zero = 0;
   DS_HIP_CHECK(hipMemcpyAsync(L->fallbacks, &zero, 8, hipMemcpyHostToDevice, s));
   feature_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(X, n, static_cast<double>(ends[0]),
@@ -2084,40 +2112,6 @@ void learned_free(ds_index* h) {
 
 namespace {
 
-__device__ __forceinline__ float unit_hash(uint64_t seed, uint64_t a, uint64_t b) {
-  return static_cast<float>(mix32(seed * 0x9E3779B97F4A7C15ull + a * 0xBF58476D1CE4E5B9ull + b) >> 8) *
-         (1.0f / 16777216.0f);
-}
-
-// the same starting point as the single-array build: layer-1 ramps spread over
-// [0, 1], layer 2 averaging them, the output averaging layer 2
-__global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ params, float* __restrict__ m,
-                                                         float* __restrict__ v, const PlanTotals* __restrict__ tot,
-                                                         uint64_t seed) {
-  const int slot = blockIdx.x;
-  if (slot >= tot->n_learned) return;
-  float* p = params + (int64_t)slot * kParams;
-  const int t = threadIdx.x;
-  if (t < kHid) {
-    const float w = 4.0f + 4.0f * unit_hash(seed, slot, t);
-    p[oW1 + t] = w;
-    p[oB1 + t] = 0.5f - w * (t + 0.5f) / kHid;
-    float sum = 0.0f;
-    for (int k = 0; k < kHid; ++k) {
-      const float w2 = (0.5f + unit_hash(seed, slot, 1000 + t * kHid + k)) / kHid;
-      p[oW2 + t * kHid + k] = w2;
-      sum += w2;
-    }
-    p[oB2 + t] = 0.5f - 0.5f * sum;
-    p[oW3 + t] = 1.0f / kHid;
-  }
-  if (t == 0) p[oB3] = 0.0f;
-  for (int k = t; k < kParams; k += blockDim.x) {
-    m[(int64_t)slot * kParams + k] = 0.0f;
-    v[(int64_t)slot * kParams + k] = 0.0f;
-  }
-}
-
 constexpr int kBatchLearnBlock = 1024;
 
 // LDS of the batched learned search: the current model's fits, router steps
@@ -2270,7 +2264,9 @@ ds_status batched_learned_build_typed(const BatchLearned& b, hipStream_t s) {
   const int K = b.K;
   // the samples were written by the build's pass over the keys (gaps_kernel)
   const T* X = static_cast<const T*>(b.X);
-  if (!b.identity) init_params_kernel<<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, b.tot, b.seed);
+  if (!b.identity)
+    init_params_kernel<T><<<dim3(K), dim3(64), 0, s>>>(b.params, b.adam_m, b.adam_v, X, 0, 0, 0, 0, 0, b.lmeta,
+                                                       b.tot);
   // every step of every model's training in one launch (one workgroup per model)
   if (b.steps > 0)
     batched_train_kernel<T><<<dim3(K), dim3(kBatchTrainBlock), 0, s>>>(b.params, b.adam_m, b.adam_v, X, b.lmeta,
