@@ -303,7 +303,7 @@ def main():
     if not args.no_batched:
         extras["batched_f32"] = bench_batched(ds, W, dev, stream, reps=3)
         log("batched done")
-        extras["batched_learned_f64_mixture"] = bench_batched_learned(ds, W, dev, stream, reps=2)
+        extras["batched_learned_f64_mixture"] = bench_batched_learned(ds, W, dev, stream, reps=5)
         log("batched learned done")
 
     detail = {"cases": case_rows, "roofline_detail": roofline, "cpu_baseline_detail": cpu,
@@ -594,7 +594,8 @@ def bench_batched_learned(ds, W, dev, stream, reps):
     # the trained routers, and the same models with the router replaced by the feature (no network)
     for name, steps in (("trained", 0), ("no_network", -1)):
         bt = ds.Batch(x_off, X, q_off, z, learn_segments=2048, learn_steps=steps, direct_cap_bytes=64 << 20)
-        bt.run(stream)
+        for _ in range(2):
+            bt.run(stream)
         torch.cuda.synchronize()
         a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
