@@ -1061,7 +1061,10 @@ __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* _
 constexpr int kFitLanes = 64;
 constexpr int kFitRounds = 2;
 constexpr int kFitUnroll = 8;
-constexpr int kFitSegs = 1;
+constexpr int kFitSegs = 4;                                     // segments per wave
+constexpr int kFitGroupLanes = kFitLanes / kFitSegs;           // lanes per short segment
+constexpr int kFitGroupRounds = 4;                             // keys per lane of a short segment
+constexpr int kFitGroupKeys = kFitGroupLanes * kFitGroupRounds;  // a short segment's fit range, at most
 constexpr int kLongBlock = 1024;
 
 // the keys [a, b) of a segment and the range [lo, last] of its error pass
@@ -1235,9 +1238,54 @@ __device__ __forceinline__ SegFit fit_one(const T* __restrict__ X, const FitSpan
   return f;
 }
 
-// segments [kFitSegs x, kFitSegs (x + 1)) of the model, x = blockIdx.x; with
-// long_list (batched form), the long ones are queued there (count in
-// tot->long_segs) for seg_fit_long_kernel
+// The fit and error bounds of a short segment (fit range of at most
+// kFitGroupKeys keys) by the kFitGroupLanes lanes of one group of a wave: the
+// same sums, line and bounds as fit_one, with the butterflies inside the group,
+// so the groups of a wave fit their segments with the same instructions.
+// Every lane of the group holds the result; live = false gives an unused one.
+template <typename T>
+__device__ __forceinline__ SegFit fit_grouped(const T* __restrict__ X, const FitSpan& sp, bool live, int gl) {
+  T v[kFitGroupRounds];
+#pragma unroll
+  for (int r = 0; r < kFitGroupRounds; ++r) {
+    const int64_t i = sp.lo + gl + kFitGroupLanes * r;
+    v[r] = (live && i <= sp.last) ? X[i] : T(0);
+  }
+  const double zc = live ? static_cast<double>(X[(sp.a < sp.b) ? sp.a : sp.lo]) : 0.0;
+  FitSums s{0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < kFitGroupRounds; ++r) {
+    const int64_t i = sp.lo + gl + kFitGroupLanes * r;
+    if (live && i >= sp.a && i < sp.b) add_key(s, i, v[r], sp.lo, zc);
+  }
+#pragma unroll
+  for (int o = kFitGroupLanes / 2; o > 0; o >>= 1) {
+    s.sz += __shfl_xor(s.sz, o, kFitGroupLanes);
+    s.szz += __shfl_xor(s.szz, o, kFitGroupLanes);
+    s.siz += __shfl_xor(s.siz, o, kFitGroupLanes);
+  }
+  SegFit f = line_fit(sp, zc, s);
+  int32_t dmin = 1 << 30, dmax = -(1 << 30);
+#pragma unroll
+  for (int r = 0; r < kFitGroupRounds; ++r) {
+    const int64_t i = sp.lo + gl + kFitGroupLanes * r;
+    if (live && i <= sp.last) err_key(f, i, v[r], sp.lo, dmin, dmax);
+  }
+#pragma unroll
+  for (int o = kFitGroupLanes / 2; o > 0; o >>= 1) {
+    dmin = std::min(dmin, __shfl_xor(dmin, o, kFitGroupLanes));
+    dmax = std::max(dmax, __shfl_xor(dmax, o, kFitGroupLanes));
+  }
+  f.dmin = dmin;
+  f.dmax = dmax;
+  return f;
+}
+
+// segments [kFitSegs x, kFitSegs (x + 1)) of the model, x = blockIdx.x: the
+// short ones by lane groups, kFitSegs at once (group q takes segment
+// kFitSegs x + q), then each longer one by the whole wave; with long_list
+// (batched form), the long ones are queued there (count in tot->long_segs)
+// for seg_fit_long_kernel
 template <typename T>
 __global__ void __launch_bounds__(kFitLanes, 8) seg_fit_kernel(const T* __restrict__ X, int64_t N,
                                                                const int32_t* __restrict__ first,
@@ -1245,6 +1293,7 @@ __global__ void __launch_bounds__(kFitLanes, 8) seg_fit_kernel(const T* __restri
                                                                const LearnMeta* __restrict__ lm,
                                                                PlanTotals* __restrict__ tot,
                                                                LongSeg* __restrict__ long_list) {
+  static_assert(kFitSegs * kFitGroupLanes == kFitLanes, "one lane group per segment of the wave");
   const int slot = blockIdx.y;
   if (lm) {
     if (slot >= tot->n_learned) return;
@@ -1258,30 +1307,34 @@ __global__ void __launch_bounds__(kFitLanes, 8) seg_fit_kernel(const T* __restri
   const int lane = threadIdx.x;
   // first[s0 .. s0 + kFitSegs] (clamped to first[nseg]) in one load
   const int32_t fl = first[std::min(s0 + std::min(lane, kFitSegs), nseg)];
-  FitSpan sp[kFitSegs];
-  T v[kFitSegs][kFitRounds];
-  double zc[kFitSegs];
-#pragma unroll
-  for (int k = 0; k < kFitSegs; ++k) {
-    const int64_t a = __builtin_amdgcn_readfirstlane(__shfl(fl, k, kFitLanes));
-    const int64_t b = __builtin_amdgcn_readfirstlane(__shfl(fl, k + 1, kFitLanes));
-    sp[k] = fit_span(a, b, N);
-    const bool live = s0 + k < nseg;
-#pragma unroll
-    for (int r = 0; r < kFitRounds; ++r) {
-      const int64_t i = sp[k].lo + lane + kFitLanes * r;
-      v[k][r] = (live && sp[k].fast && i <= sp[k].last) ? X[i] : T(0);
+  {
+    const int q = lane / kFitGroupLanes, gl = lane % kFitGroupLanes;
+    const FitSpan sp = fit_span(__shfl(fl, q, kFitLanes), __shfl(fl, q + 1, kFitLanes), N);
+    const bool mine = s0 + q < nseg && sp.last - sp.lo < kFitGroupKeys;
+    if (__ballot(mine)) {  // the whole wave takes part in the groups' butterflies
+      const SegFit f = fit_grouped<T>(X, sp, mine, gl);
+      if (mine && gl == 0) segs[s0 + q] = f;
     }
-    zc[k] = live ? static_cast<double>(X[(a < b) ? a : sp[k].lo]) : 0.0;
   }
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < kFitSegs; ++k) {
     if (s0 + k >= nseg) break;  // uniform across the wave
-    if (long_list && sp[k].last - sp[k].lo + 1 > kFitLongKeys) {
+    const int64_t a = __builtin_amdgcn_readfirstlane(__shfl(fl, k, kFitLanes));
+    const int64_t b = __builtin_amdgcn_readfirstlane(__shfl(fl, k + 1, kFitLanes));
+    const FitSpan sp = fit_span(a, b, N);
+    if (sp.last - sp.lo < kFitGroupKeys) continue;  // fitted by its group
+    if (long_list && sp.last - sp.lo + 1 > kFitLongKeys) {
       if (lane == 0) long_list[atomicAdd(&tot->long_segs, 1u)] = LongSeg{slot, s0 + k};
       continue;
     }
-    const SegFit f = fit_one<T>(X, sp[k], v[k], zc[k], lane);
+    T v[kFitRounds];
+#pragma unroll
+    for (int r = 0; r < kFitRounds; ++r) {
+      const int64_t i = sp.lo + lane + kFitLanes * r;
+      v[r] = (sp.fast && i <= sp.last) ? X[i] : T(0);
+    }
+    const double zc = static_cast<double>(X[(a < b) ? a : sp.lo]);
+    const SegFit f = fit_one<T>(X, sp, v, zc, lane);
     if (lane == 0) segs[s0 + k] = f;
   }
 }
