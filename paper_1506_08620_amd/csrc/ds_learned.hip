@@ -1287,7 +1287,7 @@ __device__ __forceinline__ SegFit fit_grouped(const T* __restrict__ X, const Fit
 // (batched form), the long ones are queued there (count in tot->long_segs)
 // for seg_fit_long_kernel
 template <typename T>
-__global__ void __launch_bounds__(kFitLanes, 8) seg_fit_kernel(const T* __restrict__ X, int64_t N,
+__global__ void __launch_bounds__(kFitLanes, 7) seg_fit_kernel(const T* __restrict__ X, int64_t N,
                                                                const int32_t* __restrict__ first,
                                                                SegFit* __restrict__ segs, int32_t nseg,
                                                                const LearnMeta* __restrict__ lm,
