@@ -103,12 +103,14 @@ typedef struct ds_build_opts {
   int32_t fallback;         /* ds_fallback */
   int64_t table_cap_bytes;  /* 0 = 4 GiB; the Direct table may not exceed it */
   /* learned method; 0 = default */
-  int32_t learn_epochs;     /* passes over the (X_i, i) pairs (default 60); -1 = no
-                               network: route by the feature alone (the ablation) */
+  int32_t learn_epochs;     /* passes over the (X_i, i) pairs (default 60), starting from
+                               the network set to the keys' piecewise-linear CDF at their
+                               32-quantiles; -1 = no network: route by the feature alone
+                               (the ablation) */
   int32_t learn_segments;   /* number of linear segments, 1..4096 (default 2048) */
   float learn_rate;         /* Adam step size (default 2e-3) */
   int32_t learn_batch;      /* training pairs per step (default 8192) */
-  uint64_t seed;            /* initialisation / sampling seed */
+  uint64_t seed;            /* training sample draws */
   int32_t extra_layouts;    /* Direct: also build these search layouts (bit mask of
                                DS_LAYOUT_*), beyond the one the automatic choice uses */
   int32_t learn_flags;      /* learned: bit mask of DS_LEARN_* */
