@@ -966,7 +966,12 @@ __device__ __forceinline__ void stage_words(void* dst, const void* src, int64_t 
 // wave routes the key before its range first).  The keys of the next
 // kRouteGroups groups are loaded before the current ones are routed, so each
 // lane keeps up to 2 kRouteGroups loads in flight; each key's feature is
-// computed as feature_kernel computes it.  The compiled router's step
+// computed as feature_kernel computes it.  With the compiled router the keys'
+// order is used: a key's table segment (the last step <= its feature) is
+// non-decreasing along the sorted keys, so a group's keys lie between the
+// segment carried from the key before it and that of its last key, found by
+// galloping up the steps from the carried one (one LDS read when the group
+// crosses no step); only a group that crosses steps searches them per lane.  The compiled router's step
 // table and grid are staged in LDS first (a few dozen KiB at most), and each
 // model's keys are shared by kRouteBlocks workgroups of 1024 lanes.  Routing
 // is the same function as route_keys_table_kernel's.
@@ -1007,6 +1012,16 @@ __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* _
   const int lane = threadIdx.x & 63;
   auto segment = [&](float u) { return IDENT ? segment_of(u, nseg) : grid_segment(u, steps, grid, log2g); };
   auto feat = [&](T x) { return feature(static_cast<double>(x), L.X0, L.delta, L.flo, L.fscale); };
+  // the last step <= u among steps [lo, hi] (steps[lo] <= u)
+  auto last_step_le = [&](float u, int32_t lo, int32_t hi) {
+    int32_t cnt = hi - lo + 1;
+    while (cnt > 1) {
+      const int32_t half = cnt >> 1;
+      lo = (steps[lo + half] <= u) ? lo + half : lo;
+      cnt -= half;
+    }
+    return lo;
+  };
   auto key_at = [&](int64_t i) { return X[std::min(i, n - 1)]; };  // lanes past the last key read it again
   // the key before the range
   int32_t carry = (g0 > 0) ? segment(feat(X[g0 * 64 - 1])) : -1;
@@ -1025,7 +1040,27 @@ __global__ void __launch_bounds__(kRouteBlock) route_first_kernel(const float* _
     for (int k = 0; k < kRouteGroups; ++k) {
       if (grp + k >= g1) break;  // uniform across the wave
       const int64_t i = (grp + k) * 64 + lane;
-      const int32_t r = segment(feat(x[k]));
+      const float u = feat(x[k]);
+      int32_t r;
+      if (IDENT) {
+        r = segment_of(u, nseg);
+      } else {
+        // lanes past the array's last key hold that key, so lane 63 holds the group's largest
+        const float u_last = __shfl(u, 63, 64);
+        const int32_t r_lo = std::max(carry, 0);  // steps[0] = -inf
+        int32_t hi = r_lo, step = 1;
+        while (hi + 1 < nseg && steps[hi + 1] <= u_last) {  // gallop: the same steps in every lane
+          const int32_t probe = std::min(hi + step, nseg - 1);
+          if (steps[probe] <= u_last) {
+            hi = probe;
+            step *= 2;
+          } else {
+            hi = last_step_le(u_last, hi, probe - 1);
+            break;
+          }
+        }
+        r = (hi == r_lo) ? r_lo : last_step_le(u, r_lo, hi);
+      }
       int32_t p = __shfl_up(r, 1, 64);
       if (lane == 0) p = carry;
       if (i < n) {
