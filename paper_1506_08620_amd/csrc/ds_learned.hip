@@ -1913,22 +1913,30 @@ int64_t learned_model_bytes(const LearnedModel* L) {
          (table ? (int64_t(4) << L->log2g) : 0);
 }
 
-// The starting point of a model: the network is set to the piecewise-linear
-// CDF of the array's keys at their 32-quantiles.  With u_k the feature of the
-// key at position k N / 32 (k = 0 .. 32), layer-1 unit k rises from 0 to 1
-// over [u_k, u_(k+1)], layer 2 passes the units through (identity), and the
-// output averages them, so y(u_k) = k / 32.  Tight clusters of keys get ramps
-// (and so segments) of their own from the start, which training from a
-// generic starting point (ramps spread evenly over u) does not achieve in the
-// steps the build can afford.  Every weight is >= 0: the network is monotone.
-// Adam's moments start at zero.  One workgroup of 64 lanes per model: the
-// single array's (lm null), or learned slot blockIdx.x of a batch.
+// The starting point of a model: the network is set to a piecewise-linear CDF
+// of the array's keys.  With u_q the feature of the key at position q N / 64
+// (q = 0 .. 64), layer-1 unit k rises from 0 to 1 over [u_2k, u_2k+2], the
+// k-th 32-quantile interval.  Layer 2 then spends its units where that is
+// least linear: the kInitSplit intervals whose median feature u_2k+1 lies
+// farthest from the middle of the interval are split there (two units, one
+// rising over each half, each weighted 1/64 in the output), and one more unit
+// sums the ramps of all the other intervals (weighted by their share).  So
+// y(u_2k) = k / 32 and, in a split interval, y(u_2k+1) = (2k + 1) / 64: a tight
+// cluster of keys gets ramps (and so segments) of its own from the start,
+// which training from a generic starting point (ramps spread evenly over u)
+// does not achieve in the steps the build can afford.  Every weight is >= 0:
+// the network is monotone.  Adam's moments start at zero.  One workgroup of 64
+// lanes per model: the single array's (lm null), or learned slot blockIdx.x of
+// a batch.
+constexpr int kInitSplit = 15;  // (kHid - 1) / 2: two layer-2 units per split, one for the rest
+
 template <typename T>
 __global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ params, float* __restrict__ m,
                                                          float* __restrict__ v, const T* __restrict__ X, int64_t N,
                                                          double X0, double delta, double flo, double fscale,
                                                          const LearnMeta* __restrict__ lm,
                                                          const PlanTotals* __restrict__ tot) {
+  static_assert(2 * kInitSplit + 1 <= kHid, "layer-2 units");
   if (lm) {
     const int slot = blockIdx.x;
     if (slot >= tot->n_learned) return;
@@ -1944,22 +1952,57 @@ __global__ void __launch_bounds__(64) init_params_kernel(float* __restrict__ par
     v += (int64_t)slot * kParams;
   }
   const int t = threadIdx.x;
-  // the quantile features, u_t for lane t <= kHid
-  const int64_t pos = (int64_t(std::min(t, kHid)) * N + kHid / 2) / kHid;
-  const float u = feature(static_cast<double>(X[pos]), X0, delta, flo, fscale);
-  const float u_next = __shfl_down(u, 1, 64);
+  auto feat = [&](int64_t pos) { return feature(static_cast<double>(X[pos]), X0, delta, flo, fscale); };
+  // u_q for lane q < 64, and u_64 (the last key) in every lane
+  const float uq = feat((int64_t(t) * N + 32) / 64);
+  const float u_end = feat(N);
+  // interval k = lane t < kHid: its ends and median
+  const int k = t & (kHid - 1);
+  const float lo = __shfl(uq, 2 * k, 64), mid = __shfl(uq, 2 * k + 1, 64);
+  const float hi = (k + 1 < kHid) ? __shfl(uq, 2 * k + 2, 64) : u_end;
+  const float w1 = 1.0f / std::fmax(hi - lo, 0x1p-24f);
+  const float b1 = -lo * w1;
+  // where the median sits in the ramp, as layer 1 computes it
+  const float tm = clamp01(std::fma(w1, mid, b1));
+  const bool can_split = tm > 0x1p-20f && tm < 1.0f - 0x1p-20f;
+  const float score = can_split ? std::fabs(tm - 0.5f) : -1.0f;
+  // rank of the score among the intervals (ties by interval index)
+  int rank = 0;
+  for (int j2 = 0; j2 < kHid; ++j2) {
+    const float sj = __shfl(score, j2, 64);
+    rank += (sj > score || (sj == score && j2 < k)) ? 1 : 0;
+  }
+  const bool split = t < kHid && can_split && rank < kInitSplit;
+  const uint64_t split_mask = __ballot(split);
+  const int n_split = __popcll(split_mask);
+  const int n_rest = kHid - n_split;
   if (t < kHid) {
-    const float w = 1.0f / std::fmax(u_next - u, 0x1p-24f);
-    params[oW1 + t] = w;
-    params[oB1 + t] = -u * w;
-    for (int k = 0; k < kHid; ++k) params[oW2 + t * kHid + k] = (k == t) ? 1.0f : 0.0f;
+    params[oW1 + t] = w1;
+    params[oB1 + t] = b1;
+    for (int j2 = 0; j2 < kHid; ++j2) params[oW2 + j2 * kHid + t] = 0.0f;
     params[oB2 + t] = 0.0f;
-    params[oW3 + t] = 1.0f / kHid;
+    params[oW3 + t] = 0.0f;
+  }
+  __syncthreads();
+  if (t < kHid) {
+    if (split) {
+      // the r-th split interval drives units 1 + 2r (its first half) and 2 + 2r (its second)
+      const int r = __popcll(split_mask & ((uint64_t(1) << t) - 1));
+      const int j1 = 1 + 2 * r, j2 = 2 + 2 * r;
+      params[oW2 + j1 * kHid + t] = 1.0f / tm;
+      params[oW2 + j2 * kHid + t] = 1.0f / (1.0f - tm);
+      params[oB2 + j2] = -tm / (1.0f - tm);
+      params[oW3 + j1] = 1.0f / (2 * kHid);
+      params[oW3 + j2] = 1.0f / (2 * kHid);
+    } else {
+      params[oW2 + 0 * kHid + t] = 1.0f / static_cast<float>(n_rest);  // unit 0 sums the rest
+    }
+    if (t == 0) params[oW3 + 0] = static_cast<float>(n_rest) / kHid;
   }
   if (t == 0) params[oB3] = 0.0f;
-  for (int k = t; k < kParams; k += blockDim.x) {
-    m[k] = 0.0f;
-    v[k] = 0.0f;
+  for (int q = t; q < kParams; q += blockDim.x) {
+    m[q] = 0.0f;
+    v[q] = 0.0f;
   }
 }
 
