@@ -104,8 +104,9 @@ typedef struct ds_build_opts {
   int64_t table_cap_bytes;  /* 0 = 4 GiB; the Direct table may not exceed it */
   /* learned method; 0 = default */
   int32_t learn_epochs;     /* passes over the (X_i, i) pairs (default 60), starting from
-                               the network set to the keys' piecewise-linear CDF at their
-                               32-quantiles; -1 = no network: route by the feature alone
+                               the network set to a piecewise-linear CDF of the keys (their
+                               32-quantiles, the 15 least linear intervals split at their
+                               medians); -1 = no network: route by the feature alone
                                (the ablation) */
   int32_t learn_segments;   /* number of linear segments, 1..4096 (default 2048) */
   float learn_rate;         /* Adam step size (default 2e-3) */
